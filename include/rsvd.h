@@ -1,0 +1,199 @@
+/*
+ * rsvd.h -- C ABI of librsvd.so: randomized range finder and truncated SVD
+ * (PCA by SVD) of a tall-skinny, column-centred matrix on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method is the one compared in "Tutorial: Complexity analysis of
+ * Singular Value Decomposition and its variants" (Li, Wang, Cai; arXiv
+ * 1906.12085):
+ *   - Randomized PCA (Sec. 3.1.2): G standard normal (n x l), H = A G,
+ *     power iterations H = A (A^T H), QR of H -> Q, T = A^T Q, SVD of T,
+ *     U~ = Q W;
+ *   - truncated SVD through A^T A (Sec. 2.3, Sec. 3.1.3): eig(A^T A) -> V,
+ *     lambda; s_i = sqrt(lambda_i) (Eq. LambdaSigma); u_i = A v_i / s_i;
+ *   - the number of principal components K from the cumulative explained
+ *     variance threshold t (Sec. 2.4), with the denominator ||A||_F^2
+ *     (Eq. sumeigen).
+ *
+ * Conventions for every entry point (Sec. 1 "Notations"/"Assumptions"):
+ *   - A is m x n, real, m >= n, rows are examples, columns are features (the
+ *     caller centres the columns; the library does not).
+ *   - Matrices are ROW-MAJOR with an explicit leading dimension (elements
+ *     between the starts of consecutive rows), ld >= number of columns.
+ *   - Every matrix/vector pointer is a DEVICE pointer (hipMalloc'd or a
+ *     torch tensor's storage) on the plan's device, unless stated otherwise.
+ *     The caller owns all buffers it passes; the library never frees them.
+ *   - Element type of A, U, V is the plan's dtype (double for RSVD_F64,
+ *     float for RSVD_F32).  Singular values S and all FP64 buffers are double.
+ *   - Singular values are returned in descending order.  Each pair (u_i, v_i)
+ *     is signed so that the lowest-index entry of v_i whose magnitude is
+ *     within 0.1% of the largest magnitude of v_i is positive.
+ *   - Calls are stream-ordered on the plan's stream and asynchronous: results
+ *     are valid after that stream has synchronised.  Argument errors are
+ *     detected synchronously on the host before anything is launched.
+ *     Numerical outcomes (breakdown, non-finite input, threshold not reached)
+ *     are written to a device status word read by rsvd_plan_status().
+ *   - A plan is not thread-safe: calls that use one plan must not overlap.
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsvd_plan_s* rsvd_plan_t;
+
+typedef enum {
+  RSVD_F64 = 0, /* A, U, V double; products on FP64 matrix cores */
+  RSVD_F32 = 1  /* A, U, V float; products on FP32 matrix cores with FP32
+                   accumulation inside a row block; Gram matrices, Cholesky
+                   factors, the small SVD and the eigensolver in FP64 */
+} rsvd_dtype;
+
+typedef enum {
+  RSVD_OK = 0,
+  RSVD_WARN_THRESHOLD = 1,   /* the k computed lambda_i capture < t ||A||_F^2: K = k */
+  RSVD_WARN_ZERO_MATRIX = 2, /* ||A||_F = 0: K = 0, outputs are zero */
+  RSVD_ERR_ARG = -1,         /* null pointer, bad k/p/q/t, bad leading dimension */
+  RSVD_ERR_SHAPE = -2,       /* m < n, n < 1, or sizes above the plan's maxima */
+  RSVD_ERR_NOMEM = -3,       /* device allocation failed */
+  RSVD_ERR_DEVICE = -4,      /* a HIP runtime call or kernel launch failed */
+  RSVD_ERR_BREAKDOWN = -5,   /* non-positive pivot in a Cholesky factorisation
+                                (the sketch has numerical rank < l) */
+  RSVD_ERR_NONFINITE = -6,   /* A contains NaN or Inf (||A||_F^2 not finite) */
+  RSVD_ERR_NOCONV = -7       /* a Jacobi iteration hit its sweep limit */
+} rsvd_status;
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* rsvd_status_string(int32_t status);
+
+/* ---------------------------------------------------------------- plans --
+ * rsvd_plan_create: allocate the device workspace for problems up to
+ * m_max x n_max with sketch width l = k + p <= l_max (Sec. 3.2.2 lists what a
+ * Randomized PCA solve keeps: the l-column sketch and basis, the n x l
+ * projection, the small SVD factors).  With want_gram != 0 the plan is also
+ * sized for gram_eig_solve on n_max x n_max (Sec. 3.2.3: A^T A and V).
+ *   plan      out: the new plan (NULL on failure)
+ *   dtype     RSVD_F64 or RSVD_F32
+ *   seed      seeds the Gaussian sketch G of rsvd_solve (Philox4x32-10 +
+ *             Box-Muller, see rsvd_gaussian_fill)
+ *   stream    hipStream_t to order all work on; NULL = the null stream
+ * Errors: RSVD_ERR_ARG (plan NULL, bad dtype, l_max < 1), RSVD_ERR_SHAPE
+ * (m_max < n_max or n_max < 1), RSVD_ERR_NOMEM, RSVD_ERR_DEVICE. */
+int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_t l_max,
+                         int32_t dtype, int32_t want_gram, uint64_t seed, void* stream);
+
+/* Free the workspace (synchronises the plan's stream first). NULL is a no-op. */
+int32_t rsvd_plan_destroy(rsvd_plan_t plan);
+
+/* Synchronise the plan's stream and return the status word written by the
+ * last solve's kernels (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN,
+ * RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV); resets it to RSVD_OK. */
+int32_t rsvd_plan_status(rsvd_plan_t plan);
+
+/* Synchronise and copy diagnostics of the last solve to host memory `out`
+ * (up to `count` doubles): [0] ||A||_F^2, [1] captured fraction
+ * sum_{i<=K} s_i^2 / ||A||_F^2, [2] Jacobi sweeps of the small SVD or of the
+ * eigensolver, [3] largest off-diagonal measure left by that Jacobi, [4] K.
+ * Returns the number of values written. */
+int32_t rsvd_plan_diag(rsvd_plan_t plan, double* out, int32_t count);
+
+/* ------------------------------------------------------------- solvers --
+ * rsvd_solve: Randomized PCA (Sec. 3.1.2) of A (m x n, lda) with target rank
+ * k, oversampling p (sketch width l = min(k + p, n)) and q power iterations;
+ * each product with A or A^T is followed by an orthonormalisation
+ * (CholeskyQR2 for the m x l basis), and K is chosen by threshold t in (0, 1]
+ * over the k computed values (Sec. 2.4).
+ *   U  (m x k, ldu >= k)  left singular vectors U~ = Q W (first k columns)
+ *   S  (k, double)        singular values, descending
+ *   V  (n x k, ldv >= k)  right singular vectors (the principal axes)
+ *   K  (1 int32, device)  number of components meeting t (K <= k)
+ * The sketch G is drawn from the plan's seed: repeated calls on one plan use
+ * the same G.  Errors (synchronous): RSVD_ERR_ARG (a NULL pointer, k < 1,
+ * k > n, p < 0, q < 0, t outside (0, 1], lda < n, ldu < k, ldv < k),
+ * RSVD_ERR_SHAPE (m < n, or m, n, l above the plan's maxima). */
+int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                   int32_t k, int32_t p, int32_t q, double t,
+                   void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
+
+/* Same as rsvd_solve with the sketch G supplied: `omega` is a device FP64
+ * row-major n x l matrix, l = min(k + p, n) (it is rounded to the plan's
+ * dtype before use).  For parity tests and for callers with their own G. */
+int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                         int32_t k, int32_t p, int32_t q, double t, const double* omega,
+                         void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
+
+/* gram_eig_solve: truncated SVD through A^T A (Sec. 2.3, Sec. 3.1.3):
+ * G = A^T A, eigen-decomposition G = V diag(lambda) V^T (Jacobi, FP64),
+ * s_i = sqrt(max(lambda_i, 0)), and u_i = A v_i / s_i for the first `ucols`
+ * columns (0 = skip U; n = all, as the paper does).  A column whose s_i is
+ * not above max(m, n) * 2^-52 * s_1 is returned as zero.  K is chosen by t
+ * over all n values.  The plan must have been created with want_gram.
+ *   U  (m x ucols, ldu >= ucols; may be NULL when ucols == 0)
+ *   S  (n, double), V (n x n, ldv >= n), K (1 int32, device)
+ * Errors: as rsvd_solve, plus RSVD_ERR_ARG for ucols outside [0, n] and
+ * RSVD_ERR_SHAPE when the plan was not sized for the A^T A route. */
+int32_t gram_eig_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                       double t, int32_t ucols, void* U, int64_t ldu, double* S,
+                       void* V, int64_t ldv, int32_t* K);
+
+/* ------------------------------------------------------- stage entry points
+ * The steps of the two solvers, exposed one by one so each can be checked on
+ * its own.  They use the plan's stream and workspace (sizes must fit the
+ * plan) and the plan's dtype for A/X/Y/Q; G, Z, R, T and eigen/singular
+ * factors are FP64.
+ *
+ * rsvd_gaussian_fill: G (rows x cols, FP64, row-major, ld = cols) from
+ * Philox4x32-10 (Salmon et al., SC 2011) and Box-Muller: element
+ * e = i*cols + j uses counter (e/2 low word, e/2 high word, 0, 0), key
+ * (seed low, seed high); the four words give u1 = ((x0>>5)*2^26 + (x1>>6)
+ * + 0.5)*2^-53, u2 likewise from (x2, x3); even e takes
+ * sqrt(-2 ln u1) cos(2 pi u2), odd e the sine (Sec. 3.1.2 step 1). */
+int32_t rsvd_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G, void* stream);
+
+/* rsvd_gemm_nn: Y (m x c, ldy) = A (m x n, lda) X (n x c, ldx), the products
+ * H = A G and A (A^T H) of Sec. 3.1.2.  When Gram != NULL it also writes
+ * Gram (c x c, FP64) = Y^T Y accumulated in FP64, and when fro2 != NULL the
+ * FP64 sum of a_ij^2 (Eq. sumeigen).  c <= plan l_max unless the plan was
+ * sized for the A^T A route (then c <= n_max). */
+int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                     const void* X, int64_t ldx, int32_t c, void* Y, int64_t ldy,
+                     double* Gram, double* fro2);
+
+/* rsvd_gemm_tn: Z (n x c, FP64, ld = c) = A^T (n x m) Q (m x c, ldq), the
+ * product T = A^T Q of Sec. 3.1.2 (and A^T H of the power iterations); the
+ * sum over the m rows is split into row blocks whose partial sums are added
+ * in a fixed order (deterministic). */
+int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                     const void* Q, int64_t ldq, int32_t c, double* Z);
+
+/* rsvd_cholqr2: orthonormal basis of Y (m x c, ldy) by CholeskyQR2 -- stands
+ * in for "QR decomposition on H" (Sec. 3.1.2 step 4): W = Y^T Y (FP64),
+ * R1 = chol(W), Q1 = Y R1^-1, R2 = chol(Q1^T Q1), Q = Q1 R2^-1, R = R2 R1.
+ * Writes Q (m x c, ldq, plan dtype) and R (c x c, FP64 upper triangular,
+ * positive diagonal, ld = c), Y = Q R.  A non-positive pivot sets the status
+ * word to RSVD_ERR_BREAKDOWN. */
+int32_t rsvd_cholqr2(rsvd_plan_t plan, const void* Y, int64_t m, int32_t c, int64_t ldy,
+                     void* Q, int64_t ldq, double* R);
+
+/* rsvd_small_svd: thin SVD of an FP64 matrix T (r x c, r >= c, ld = c) on the
+ * device -- "SVD on T = V~ S~ W^T" (Sec. 3.1.2 step 6): CholeskyQR2 of T,
+ * then one-sided Jacobi on the c x c factor.  Writes Vt (r x c, ld = c),
+ * S (c, descending) and W (c x c, ld = c), sign rule applied. */
+int32_t rsvd_small_svd(rsvd_plan_t plan, const double* T, int64_t r, int32_t c,
+                       double* Vt, double* S, double* W);
+
+/* rsvd_sym_eig: eigen-decomposition of a symmetric FP64 matrix G (n x n,
+ * ld = n) -- "eigen-decomposition on A^T A" (Sec. 3.1.3 step 2) -- by
+ * one-sided Jacobi on G with the rotations accumulated: lam (n, descending),
+ * V (n x n, ld = n, columns = eigenvectors, sign rule applied).  Needs a plan
+ * sized for the A^T A route. */
+int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, double* V);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSVD_H */

@@ -137,6 +137,30 @@ double orc_fro2(int64_t m, int64_t n, const double* A, int64_t lda) {
   return s;
 }
 
+/* w[c] = sum_{i=r0}^{m-1} v[i*ldv] * X[i*ldx + c] for c in [c0, c1): the row
+ * sum is split into ORC_CHUNKS fixed chunks added in chunk order. */
+static int orc_weighted_colsum(int64_t r0, int64_t m, const double* v, int64_t ldv,
+                               const double* X, int64_t ldx, int64_t c0, int64_t c1, double* w) {
+  const int64_t rows = m - r0, width = c1 - c0;
+  for (int64_t c = c0; c < c1; ++c) w[c] = 0.0;
+  if (rows <= 0 || width <= 0) return ORC_OK;
+  const int64_t nch = rows < ORC_CHUNKS ? rows : ORC_CHUNKS;
+  double* part = (double*)calloc((size_t)(nch * width), sizeof(double));
+  if (!part) return ORC_ERR_NOMEM;
+#pragma omp parallel for schedule(static)
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    double* P = part + ch * width;
+    for (int64_t i = r0 + rows * ch / nch; i < r0 + rows * (ch + 1) / nch; ++i) {
+      const double vi = v[i * ldv];
+      for (int64_t c = c0; c < c1; ++c) P[c - c0] += vi * X[i * ldx + c];
+    }
+  }
+  for (int64_t ch = 0; ch < nch; ++ch)
+    for (int64_t c = c0; c < c1; ++c) w[c] += part[ch * width + c - c0];
+  free(part);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Thin QR by Householder reflections (Golub & Van Loan, Matrix Computations,
  * 4th ed., Alg. 5.2.1 with backward accumulation of Q).  X (m x n, m >= n) is
@@ -170,10 +194,8 @@ int orc_qr_householder(int64_t m, int64_t n, const double* X, int64_t ldx,
     beta[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
     if (beta[j] == 0.0) continue;  /* x already a multiple of e_1 (or zero) */
     /* W[j:, j:] -= beta v (v^T W[j:, j:]) ; two passes over the rows */
-    for (int64_t c = j; c < n; ++c) w[c] = 0.0;
-    for (int64_t i = j; i < m; ++i) {
-      const double v = vs[i * n + j];
-      for (int64_t c = j; c < n; ++c) w[c] += v * W[i * n + c];
+    if (orc_weighted_colsum(j, m, vs + j, n, W, n, j, n, w) != ORC_OK) {
+      free(W); free(vs); free(beta); free(w); return ORC_ERR_NOMEM;
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = j; i < m; ++i) {
@@ -187,10 +209,8 @@ int orc_qr_householder(int64_t m, int64_t n, const double* X, int64_t ldx,
     for (int64_t c = 0; c < n; ++c) Q[i * ldq + c] = (i == c) ? 1.0 : 0.0;
   for (int64_t j = n - 1; j >= 0; --j) {
     if (beta[j] == 0.0) continue;
-    for (int64_t c = 0; c < n; ++c) w[c] = 0.0;
-    for (int64_t i = j; i < m; ++i) {
-      const double v = vs[i * n + j];
-      for (int64_t c = 0; c < n; ++c) w[c] += v * Q[i * ldq + c];
+    if (orc_weighted_colsum(j, m, vs + j, n, Q, ldq, 0, n, w) != ORC_OK) {
+      free(W); free(vs); free(beta); free(w); return ORC_ERR_NOMEM;
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = j; i < m; ++i) {

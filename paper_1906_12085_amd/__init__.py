@@ -1,0 +1,269 @@
+"""Python binding of librsvd.so (include/rsvd.h): randomized range finder and
+truncated SVD (PCA by SVD) of a tall-skinny centred matrix on an MI355X.
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+librsvd.so.  Tensors are torch tensors on the GPU (torch supplies device
+memory and streams); the functions below pass their data pointers, sizes and
+row strides to the C entry points of the same names.  If librsvd.so has not
+been built this module raises on first use -- there is no fallback path.
+
+Quick use::
+
+    plan = Plan(m_max, n_max, l_max, torch.float32, want_gram=True)
+    U, S, V, K = plan.solve(A, k=64, p=16, q=2, t=0.95)
+    U, S, V, K = plan.gram_eig(A, t=0.95)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsvd.so")
+
+RSVD_F64, RSVD_F32 = 0, 1
+STATUS = {
+    0: "RSVD_OK", 1: "RSVD_WARN_THRESHOLD", 2: "RSVD_WARN_ZERO_MATRIX",
+    -1: "RSVD_ERR_ARG", -2: "RSVD_ERR_SHAPE", -3: "RSVD_ERR_NOMEM", -4: "RSVD_ERR_DEVICE",
+    -5: "RSVD_ERR_BREAKDOWN", -6: "RSVD_ERR_NONFINITE", -7: "RSVD_ERR_NOCONV",
+}
+RSVD_OK, RSVD_WARN_THRESHOLD, RSVD_WARN_ZERO_MATRIX = 0, 1, 2
+RSVD_ERR_ARG, RSVD_ERR_SHAPE, RSVD_ERR_NOMEM, RSVD_ERR_DEVICE = -1, -2, -3, -4
+RSVD_ERR_BREAKDOWN, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = -5, -6, -7
+
+EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_plan_status",
+           "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
+           "rsvd_gaussian_fill", "rsvd_gemm_nn", "rsvd_gemm_tn", "rsvd_cholqr2",
+           "rsvd_small_svd", "rsvd_sym_eig"]
+
+
+class RSVDError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librsvd.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() "
+                          "(there is no CPU fallback for the GPU path)")
+    lib = ctypes.CDLL(path)
+    i32, i64, u64, dbl, vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                              ctypes.c_void_p)
+    sig = {
+        "rsvd_status_string": (ctypes.c_char_p, [i32]),
+        "rsvd_plan_create": (i32, [ctypes.POINTER(vp), i64, i64, i32, i32, i32, u64, vp]),
+        "rsvd_plan_destroy": (i32, [vp]),
+        "rsvd_plan_status": (i32, [vp]),
+        "rsvd_plan_diag": (i32, [vp, vp, i32]),
+        "rsvd_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp]),
+        "rsvd_solve_omega": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
+                                   vp, i64, vp, vp, i64, vp]),
+        "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
+        "rsvd_gaussian_fill": (i32, [u64, i64, i64, vp, vp]),
+        "rsvd_gemm_nn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp, i64, vp, vp]),
+        "rsvd_gemm_tn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp]),
+        "rsvd_cholqr2": (i32, [vp, vp, i64, i32, i64, vp, i64, vp]),
+        "rsvd_small_svd": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+        "rsvd_sym_eig": (i32, [vp, vp, i64, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _ld(t) -> int:
+    """Row stride of a row-major 2-D tensor (elements between rows)."""
+    assert t.dim() == 2 and t.stride(1) == 1, "matrices must be row-major with unit column stride"
+    return t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise RSVDError(rc, where)
+    return rc
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ---------------------------------------------------------------- C names --
+def rsvd_status_string(code: int) -> str:
+    return load_library().rsvd_status_string(code).decode()
+
+
+def rsvd_plan_create(m_max: int, n_max: int, l_max: int, dtype: int, want_gram: bool = False,
+                     seed: int = 0, stream=None) -> int:
+    h = ctypes.c_void_p()
+    rc = load_library().rsvd_plan_create(ctypes.byref(h), m_max, n_max, l_max, dtype,
+                                         int(bool(want_gram)), seed, _stream_ptr(stream))
+    _check(rc, "rsvd_plan_create")
+    return h.value
+
+
+def rsvd_plan_destroy(plan: int) -> int:
+    return _check(load_library().rsvd_plan_destroy(plan), "rsvd_plan_destroy")
+
+
+def rsvd_plan_status(plan: int) -> int:
+    return load_library().rsvd_plan_status(plan)
+
+
+def rsvd_plan_diag(plan: int, count: int = 8):
+    buf = (ctypes.c_double * count)()
+    nc = _check(load_library().rsvd_plan_diag(plan, buf, count), "rsvd_plan_diag")
+    return list(buf[:nc])
+
+
+def rsvd_solve(plan: int, A, k: int, p: int, q: int, t: float, U, S, V, K) -> int:
+    m, n = A.shape
+    return _check(load_library().rsvd_solve(plan, _ptr(A), m, n, _ld(A), k, p, q, float(t),
+                                            _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V), _ptr(K)),
+                  "rsvd_solve")
+
+
+def rsvd_solve_omega(plan: int, A, k: int, p: int, q: int, t: float, omega, U, S, V, K) -> int:
+    m, n = A.shape
+    assert omega.is_contiguous() and omega.dtype.is_floating_point and omega.element_size() == 8
+    return _check(load_library().rsvd_solve_omega(plan, _ptr(A), m, n, _ld(A), k, p, q, float(t),
+                                                  _ptr(omega), _ptr(U), _ld(U), _ptr(S), _ptr(V),
+                                                  _ld(V), _ptr(K)), "rsvd_solve_omega")
+
+
+def gram_eig_solve(plan: int, A, t: float, ucols: int, U, S, V, K) -> int:
+    m, n = A.shape
+    ldu = _ld(U) if U is not None else 0
+    return _check(load_library().gram_eig_solve(plan, _ptr(A), m, n, _ld(A), float(t), ucols,
+                                                _ptr(U), ldu, _ptr(S), _ptr(V), _ld(V), _ptr(K)),
+                  "gram_eig_solve")
+
+
+def rsvd_gaussian_fill(seed: int, G, stream=None) -> int:
+    rows, cols = G.shape
+    assert G.is_contiguous() and G.element_size() == 8
+    return _check(load_library().rsvd_gaussian_fill(seed, rows, cols, _ptr(G), _stream_ptr(stream)),
+                  "rsvd_gaussian_fill")
+
+
+def rsvd_gemm_nn(plan: int, A, X, Y, Gram=None, fro2=None) -> int:
+    m, n = A.shape
+    c = X.shape[1]
+    return _check(load_library().rsvd_gemm_nn(plan, _ptr(A), m, n, _ld(A), _ptr(X), _ld(X), c,
+                                              _ptr(Y), _ld(Y), _ptr(Gram), _ptr(fro2)),
+                  "rsvd_gemm_nn")
+
+
+def rsvd_gemm_tn(plan: int, A, Q, Z) -> int:
+    m, n = A.shape
+    c = Q.shape[1]
+    assert Z.is_contiguous() and tuple(Z.shape) == (n, c)
+    return _check(load_library().rsvd_gemm_tn(plan, _ptr(A), m, n, _ld(A), _ptr(Q), _ld(Q), c,
+                                              _ptr(Z)), "rsvd_gemm_tn")
+
+
+def rsvd_cholqr2(plan: int, Y, Q, R) -> int:
+    m, c = Y.shape
+    assert R.is_contiguous()
+    return _check(load_library().rsvd_cholqr2(plan, _ptr(Y), m, c, _ld(Y), _ptr(Q), _ld(Q),
+                                              _ptr(R)), "rsvd_cholqr2")
+
+
+def rsvd_small_svd(plan: int, T, Vt, S, W) -> int:
+    r, c = T.shape
+    assert T.is_contiguous() and Vt.is_contiguous() and W.is_contiguous()
+    return _check(load_library().rsvd_small_svd(plan, _ptr(T), r, c, _ptr(Vt), _ptr(S), _ptr(W)),
+                  "rsvd_small_svd")
+
+
+def rsvd_sym_eig(plan: int, G, lam, V) -> int:
+    n = G.shape[0]
+    assert G.is_contiguous() and V.is_contiguous()
+    return _check(load_library().rsvd_sym_eig(plan, _ptr(G), n, _ptr(lam), _ptr(V)),
+                  "rsvd_sym_eig")
+
+
+# ------------------------------------------------------- convenience class --
+class Result(NamedTuple):
+    U: object
+    S: object
+    V: object
+    K: int
+    status: int
+
+
+class Plan:
+    """Owns an rsvd plan; allocates outputs as torch tensors on the device."""
+
+    def __init__(self, m_max: int, n_max: int, l_max: int, dtype, want_gram: bool = False,
+                 seed: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.dtype = dtype
+        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[dtype]
+        self.handle = rsvd_plan_create(m_max, n_max, l_max, code, want_gram, seed, stream)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if self.handle:
+            rsvd_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self, shape, dtype=None):
+        return self.torch.empty(shape, dtype=dtype or self.dtype, device=self.device)
+
+    def status(self) -> int:
+        return rsvd_plan_status(self.handle)
+
+    def diag(self):
+        return rsvd_plan_diag(self.handle)
+
+    def solve(self, A, k: int, p: int, q: int, t: float, omega=None, sync: bool = True):
+        m, n = A.shape
+        torch = self.torch
+        U = self._out((m, k)); V = self._out((n, k))
+        S = self._out((k,), torch.float64); K = self._out((1,), torch.int32)
+        if omega is None:
+            rsvd_solve(self.handle, A, k, p, q, t, U, S, V, K)
+        else:
+            rsvd_solve_omega(self.handle, A, k, p, q, t, omega, U, S, V, K)
+        if not sync:
+            return Result(U, S, V, K, 0)
+        st = self.status()
+        return Result(U, S, V, int(K.item()), st)
+
+    def gram_eig(self, A, t: float, ucols: Optional[int] = None, sync: bool = True):
+        m, n = A.shape
+        torch = self.torch
+        uc = n if ucols is None else ucols
+        U = self._out((m, uc)) if uc > 0 else None
+        S = self._out((n,), torch.float64); V = self._out((n, n)); K = self._out((1,), torch.int32)
+        gram_eig_solve(self.handle, A, t, uc, U, S, V, K)
+        if not sync:
+            return Result(U, S, V, K, 0)
+        st = self.status()
+        return Result(U, S, V, int(K.item()), st)

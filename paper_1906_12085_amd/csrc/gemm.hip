@@ -1,0 +1,354 @@
+// gemm.hip -- the passes over A: Y = A X (tall-skinny, row-major) and the
+// split-m partial products of A^T Q, on the gfx950 matrix cores.
+//
+// These are the "m n l" products of Randomized PCA (paper Sec. 3.1.2, steps
+// 2, 3 and 5: H = A G, A (A^T H), T = A^T Q) and of the truncated SVD
+// (Sec. 3.1.3: A^T A and u_i = A v_i / s_i).  Every product is a
+// contraction, so all of them run on 16x16x4 matrix-core instructions
+// (fp32 or fp64).
+#include "rsvd_internal.h"
+
+namespace rsvd {
+
+namespace {
+
+template <typename T> struct Vec16;          // 16-byte vector of T
+template <> struct Vec16<float> { typedef f32x4 type; };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+constexpr int kNNThreads = 256;              // 4 waves
+constexpr int kNNBK = 32;                    // k-chunk staged in LDS
+
+// ---------------------------------------------------------------------------
+// Y = A X.  Block = 4 waves; wave w owns rows [row0 + 16*MR*w, +16*MR), the
+// block owns 16*NT columns of Y (one column tile).  A goes straight from HBM
+// into registers: within a slab of 4*VW columns of A, lane (r = l%16,
+// g = l/16) loads the VW consecutive elements A[row r][slab + VW*g .. +VW-1]
+// with one 16-byte load, and matrix-core step t uses element t -- so step t
+// contracts over k = slab + VW*g + t (a permutation of the slab, matched on
+// the X side).  The X chunk (kNNBK x 16*NT) is staged transposed in LDS so a
+// lane reads its VW operands with one 16-byte LDS load.
+template <typename T, int NT, int MR, bool VEC>
+__global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
+    const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, const T* __restrict__ X,
+    int64_t ldx, int c, T* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part,
+    int ncol_tiles) {
+  typedef Mfma<T> M;
+  typedef typename M::acc_t acc_t;
+  typedef typename Vec16<T>::type vec_t;
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int SLAB = 4 * VW;
+  constexpr int NS = kNNBK / SLAB;
+  constexpr int BC = 16 * NT;
+  constexpr int XLD = kNNBK + VW;            // padded, keeps 16-byte alignment
+  __shared__ __attribute__((aligned(16))) T Xt[BC * XLD];
+  __shared__ double red[kNNThreads / 64];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int64_t rb = blockIdx.x / ncol_tiles;
+  const int ct = blockIdx.x % ncol_tiles;
+  const int64_t row0 = rb * (64 * MR) + (int64_t)wave * 16 * MR;
+  const int col0 = ct * BC;
+  const bool do_ss = (fro2_part != nullptr) && ct == 0;
+
+  acc_t acc[MR][NT];
+#pragma unroll
+  for (int r = 0; r < MR; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[r][j] = acc_t{0, 0, 0, 0};
+  double ss = 0.0;
+
+  for (int64_t k0 = 0; k0 < n; k0 += kNNBK) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kNNBK * BC; idx += kNNThreads) {
+      const int kk = idx / BC, col = idx - kk * BC;
+      const int64_t k = k0 + kk;
+      const int cc = col0 + col;
+      Xt[col * XLD + kk] = (k < n && cc < c) ? X[k * ldx + cc] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int64_t kb = k0 + s * SLAB + g * VW;
+      T a[MR][VW];
+#pragma unroll
+      for (int r = 0; r < MR; ++r) {
+        const int64_t row = row0 + 16 * r + lr;
+        if (VEC && row < m && kb + VW <= n) {
+          const vec_t v = *reinterpret_cast<const vec_t*>(A + row * lda + kb);
+#pragma unroll
+          for (int t = 0; t < VW; ++t) a[r][t] = v[t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < VW; ++t)
+            a[r][t] = (row < m && kb + t < n) ? A[row * lda + kb + t] : T(0);
+        }
+        if (do_ss) {
+#pragma unroll
+          for (int t = 0; t < VW; ++t) ss += (double)a[r][t] * (double)a[r][t];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const vec_t b = *reinterpret_cast<const vec_t*>(&Xt[(16 * j + lr) * XLD + s * SLAB + g * VW]);
+#pragma unroll
+        for (int t = 0; t < VW; ++t)
+#pragma unroll
+          for (int r = 0; r < MR; ++r) acc[r][j] = M::run(a[r][t], b[t], acc[r][j]);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < MR; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = col0 + 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + 16 * r + M::row(lane, e);
+        if (row < m && col < c) Y[row * ldy + col] = acc[r][j][e];
+      }
+    }
+
+  if (do_ss) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kNNThreads / 64; ++w) t += red[w];
+      fro2_part[blockIdx.x / ncol_tiles] = t;
+    }
+  }
+}
+
+template <typename T, int NT, int MR>
+hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
+                       int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
+  const int ncol_tiles = (c + 16 * NT - 1) / (16 * NT);
+  const int64_t nrow_blocks = (m + 64 * MR - 1) / (64 * MR);
+  if (nparts) *nparts = (int)nrow_blocks;
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((lda * sizeof(T)) % 16 == 0);
+  dim3 grid((unsigned)(nrow_blocks * ncol_tiles));
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_nn<T, NT, MR, true>), grid, dim3(kNNThreads), 0, s, A, m, n, lda,
+                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, NT, MR, false>), grid, dim3(kNNThreads), 0, s, A, m, n, lda,
+                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Split-m partials of Z = A^T Q.  Block = WAVES waves over rows [rs, re) of A;
+// wave w owns 16*VW consecutive columns of A (rows of Z), the block covers
+// 16*NT columns of Q.  Lane (x = l%16, g = l/16) loads A[r + g][i_w + VW*x
+// .. +VW-1] (one 16-byte load when VW*sizeof(T) = 16) and Q[r + g][j0 + 16j + x];
+// matrix-core step t produces the Z rows i_w + VW*x' + t, x' = 0..15.
+// C is the compute type (double gives exact products of float data).
+template <typename T, typename C, int VW, int NT, int WAVES, bool VEC>
+__global__ __launch_bounds__(WAVES * 64) void k_gemm_tn_partial(
+    const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, const T* __restrict__ Q,
+    int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split) {
+  typedef Mfma<C> M;
+  typedef typename M::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t split = blockIdx.x;
+  const int64_t rs = split * rows_per_split;
+  const int64_t re = (rs + rows_per_split < m) ? rs + rows_per_split : m;
+  const int64_t iw = (int64_t)blockIdx.y * (WAVES * 16 * VW) + (int64_t)wave * 16 * VW;
+  const int64_t ia = iw + VW * x;            // this lane's first A column
+  const int j0 = blockIdx.z * 16 * NT;
+  const bool full_i = (ia + VW <= n);
+
+  acc_t acc[VW][NT];
+#pragma unroll
+  for (int t = 0; t < VW; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[t][j] = acc_t{0, 0, 0, 0};
+
+  for (int64_t r = rs; r < re; r += 4) {
+    const int64_t row = r + g;
+    const bool rok = row < re;
+    C a[VW];
+    bool loaded = false;
+    if constexpr (VEC && VW * sizeof(T) == 16) {
+      if (rok && full_i) {
+        const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(A + row * lda + ia);
+#pragma unroll
+        for (int t = 0; t < VW; ++t) a[t] = (C)v[t];
+        loaded = true;
+      }
+    }
+    if (!loaded) {
+#pragma unroll
+      for (int t = 0; t < VW; ++t) a[t] = (rok && ia + t < n) ? (C)A[row * lda + ia + t] : C(0);
+    }
+    C b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = j0 + 16 * j + x;
+      b[j] = (rok && col < c) ? (C)Q[row * ldq + col] : C(0);
+    }
+#pragma unroll
+    for (int t = 0; t < VW; ++t)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[t][j] = M::run(a[t], b[j], acc[t][j]);
+  }
+
+  double* Ps = P + split * n * (int64_t)c;
+#pragma unroll
+  for (int t = 0; t < VW; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = j0 + 16 * j + x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = iw + VW * M::row(lane, e) + t;
+        if (i < n && col < c) Ps[i * c + col] = (double)acc[t][j][e];
+      }
+    }
+}
+
+// Row-split count: aim at ~256 blocks in total (one per compute unit) and at
+// least 64 rows per split.
+int64_t tn_splits(int64_t m, int64_t tiles) {
+  int64_t s = 256 / (tiles > 0 ? tiles : 1);
+  if (s < 1) s = 1;
+  const int64_t by_rows = (m + 63) / 64;
+  if (s > by_rows) s = by_rows;
+  return s < 1 ? 1 : s;
+}
+
+template <typename T, typename C, int VW, int NT, int WAVES>
+hipError_t tn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q, int64_t ldq,
+                       int c, double* P, int64_t max_split, int* nsplit, hipStream_t s) {
+  const int64_t itiles = (n + WAVES * 16 * VW - 1) / (WAVES * 16 * VW);
+  const int64_t jtiles = (c + 16 * NT - 1) / (16 * NT);
+  int64_t splits = tn_splits(m, itiles * jtiles);
+  if (splits > max_split) splits = max_split;
+  int64_t rps = (m + splits - 1) / splits;
+  rps = (rps + 15) / 16 * 16;
+  splits = (m + rps - 1) / rps;
+  if (splits < 1) splits = 1;
+  *nsplit = (int)splits;
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((lda * sizeof(T)) % 16 == 0);
+  dim3 grid((unsigned)splits, (unsigned)itiles, (unsigned)jtiles);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_tn_partial<T, C, VW, NT, WAVES, true>), grid, dim3(WAVES * 64), 0, s,
+                       A, m, n, lda, Q, ldq, c, P, rps);
+  else
+    hipLaunchKernelGGL((k_gemm_tn_partial<T, C, VW, NT, WAVES, false>), grid, dim3(WAVES * 64), 0,
+                       s, A, m, n, lda, Q, ldq, c, P, rps);
+  return hipGetLastError();
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ P, int nsplit, int64_t rows,
+                                  int64_t cols, double* __restrict__ Z, int64_t ldz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = rows * cols;
+  if (idx >= total) return;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += P[(int64_t)k * total + idx];
+  const int64_t i = idx / cols, j = idx - i * cols;
+  Z[i * ldz + j] = s;
+}
+
+__global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double* out) {
+  // fixed order: 256 strided lanes, then a fixed tree
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += parts[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
+                          int c, T* Y, int64_t ldy, double* fro2_part, int* nparts,
+                          hipStream_t s) {
+  if (m <= 0 || c <= 0) { if (nparts) *nparts = 0; return hipSuccess; }
+  // the number of 16-column tiles a block covers: all of c up to 128 columns
+  const int nt = (c + 15) / 16;
+  switch (nt > 8 ? 8 : nt) {
+    case 1: return nn_dispatch<T, 1, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 2: return nn_dispatch<T, 2, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 3: return nn_dispatch<T, 3, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 4: return nn_dispatch<T, 4, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 5: return nn_dispatch<T, 5, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 6: return nn_dispatch<T, 6, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    case 7: return nn_dispatch<T, 7, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+    default: return nn_dispatch<T, 8, 2>(A, m, n, lda, X, ldx, c, Y, ldy, fro2_part, nparts, s);
+  }
+}
+
+int64_t tn_max_split(int64_t m, int64_t n, int c) {
+  (void)n; (void)c;
+  return tn_splits(m, 1);
+}
+
+template <typename T, typename C>
+hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q,
+                                  int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                                  hipStream_t s) {
+  if (m <= 0 || n <= 0 || c <= 0) { *nsplit = 0; return hipSuccess; }
+  const int nt = (c + 15) / 16;
+  constexpr bool exact = sizeof(C) > sizeof(T);       // fp64 Gram of fp32 data
+  constexpr int VW = exact ? 1 : 16 / sizeof(T);
+  constexpr int WAVES = exact ? 4 : 8;
+#define RSVD_TN(NT_) return tn_dispatch<T, C, VW, NT_, WAVES>(A, m, n, lda, Q, ldq, c, P, max_split, nsplit, s)
+  switch (nt > 8 ? 8 : nt) {
+    case 1: RSVD_TN(1);
+    case 2: RSVD_TN(2);
+    case 3: RSVD_TN(3);
+    case 4: RSVD_TN(4);
+    case 5: RSVD_TN(5);
+    case 6: RSVD_TN(6);
+    case 7: RSVD_TN(7);
+    default: RSVD_TN(8);
+  }
+#undef RSVD_TN
+}
+
+hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,
+                                  double* Z, int64_t ldz, hipStream_t s) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     P, nsplit, rows, cols, Z, ldz);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_scalar(const double* parts, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(256), 0, s, parts, n, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm_nn<float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                          int64_t, int, float*, int64_t, double*, int*,
+                                          hipStream_t);
+template hipError_t launch_gemm_nn<double>(const double*, int64_t, int64_t, int64_t,
+                                           const double*, int64_t, int, double*, int64_t, double*,
+                                           int*, hipStream_t);
+template hipError_t launch_gemm_tn_partial<float, float>(const float*, int64_t, int64_t, int64_t,
+                                                         const float*, int64_t, int, double*,
+                                                         int64_t, int*, hipStream_t);
+template hipError_t launch_gemm_tn_partial<float, double>(const float*, int64_t, int64_t, int64_t,
+                                                          const float*, int64_t, int, double*,
+                                                          int64_t, int*, hipStream_t);
+template hipError_t launch_gemm_tn_partial<double, double>(const double*, int64_t, int64_t,
+                                                           int64_t, const double*, int64_t, int,
+                                                           double*, int64_t, int*, hipStream_t);
+
+}  // namespace rsvd

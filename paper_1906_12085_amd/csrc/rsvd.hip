@@ -1,0 +1,550 @@
+// rsvd.hip -- the C ABI of librsvd.so (declared in include/rsvd.h): plans,
+// argument validation and the stream-ordered sequence of kernels for
+// Randomized PCA (paper Sec. 3.1.2) and the truncated SVD through A^T A
+// (Sec. 2.3 / 3.1.3).  No host synchronisation happens inside a solve.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "rsvd_internal.h"
+
+using namespace rsvd;
+
+namespace {
+
+// Largest sketch width l supported: the l x l Cholesky / inverse and the
+// one-sided Jacobi SVD keep two l x l FP64 matrices in one block's LDS.
+constexpr int kMaxL = 96;
+constexpr int kDiagWords = 8;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct rsvd_plan_s {
+  int device = 0;
+  int dtype = RSVD_F64;
+  int64_t m_max = 0, n_max = 0;
+  int l_max = 0;
+  bool gram = false;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  int64_t max_split = 1;
+
+  char* base = nullptr;   // one device allocation, carved below
+  size_t bytes = 0;
+
+  // rSVD workspace
+  double* omega = nullptr;   // n x l   FP64 sketch
+  void* Xs = nullptr;        // n x cmax (T) right operand of A X
+  void* Y = nullptr;         // m x l (T) sketch / power-iteration iterate
+  void* Q1 = nullptr;        // m x l (T) first CholeskyQR factor (Q = Q1 R2^-1)
+  double* part = nullptr;    // split-m partials
+  double* fro2_part = nullptr;
+  double* scal = nullptr;    // [0] = ||A||_F^2
+  double *Wg = nullptr, *R1 = nullptr, *R1inv = nullptr, *R2 = nullptr, *R2inv = nullptr;
+  void* RinvT = nullptr;     // l x l (T)
+  double *R1s = nullptr, *R1invs = nullptr, *R2s = nullptr, *R2invs = nullptr;
+  void* RinvTs = nullptr;    // l x l (T) of the FP64 n x l orthonormalisations
+  double *Zd = nullptr, *Z2 = nullptr, *Z1 = nullptr, *Zq = nullptr;   // n x l
+  double *Rt = nullptr, *Uo = nullptr, *Jm = nullptr, *Su = nullptr, *Vt = nullptr;
+  double *Wk = nullptr, *Mk = nullptr;
+  void* MkT = nullptr;       // l x l (T)
+  int32_t* status = nullptr;
+  double* diag = nullptr;
+  int32_t* flags = nullptr;
+  // A^T A route
+  double *Gd = nullptr, *Xe = nullptr, *Je = nullptr, *lam = nullptr, *Se = nullptr,
+         *Vd = nullptr;
+};
+
+namespace {
+
+#define RSVD_CHECK(expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return RSVD_ERR_DEVICE;          \
+  } while (0)
+
+size_t elem_size(int dtype) { return dtype == RSVD_F64 ? sizeof(double) : sizeof(float); }
+
+// Carve the workspace; with base == nullptr it only counts bytes.
+size_t carve(rsvd_plan_s* p, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return ptr;
+  };
+  const size_t es = elem_size(p->dtype);
+  const int64_t n = p->n_max, m = p->m_max, l = p->l_max;
+  const int64_t cmax = p->gram ? (n > l ? n : l) : l;
+  p->omega = (double*)take(n * l * 8);
+  p->Xs = take(n * cmax * es);
+  p->Y = take(m * l * es);
+  p->Q1 = take(m * l * es);
+  p->part = (double*)take(p->max_split * n * cmax * 8);
+  p->fro2_part = (double*)take(((m + 127) / 128 + 1) * 8);
+  p->scal = (double*)take(64);
+  p->Wg = (double*)take(l * l * 8);
+  p->R1 = (double*)take(l * l * 8);
+  p->R1inv = (double*)take(l * l * 8);
+  p->R2 = (double*)take(l * l * 8);
+  p->R2inv = (double*)take(l * l * 8);
+  p->RinvT = take(l * l * es);
+  p->R1s = (double*)take(l * l * 8);
+  p->R1invs = (double*)take(l * l * 8);
+  p->R2s = (double*)take(l * l * 8);
+  p->R2invs = (double*)take(l * l * 8);
+  p->RinvTs = take(l * l * 8);
+  p->Zd = (double*)take(n * l * 8);
+  p->Z2 = (double*)take(n * l * 8);
+  p->Z1 = (double*)take(n * l * 8);
+  p->Zq = (double*)take(n * l * 8);
+  p->Rt = (double*)take(l * l * 8);
+  p->Uo = (double*)take(l * l * 8);
+  p->Jm = (double*)take(l * l * 8);
+  p->Su = (double*)take(l * 8);
+  p->Vt = (double*)take(n * l * 8);
+  p->Wk = (double*)take(l * l * 8);
+  p->Mk = (double*)take(l * l * 8);
+  p->MkT = take(l * l * es);
+  p->status = (int32_t*)take(64);
+  p->diag = (double*)take(kDiagWords * 8);
+  p->flags = (int32_t*)take(jacobi_eig_flag_words() * 4);
+  if (p->gram) {
+    p->Gd = (double*)take(n * n * 8);
+    p->Xe = (double*)take(n * n * 8);
+    p->Je = (double*)take(n * n * 8);
+    p->lam = (double*)take(n * 8);
+    p->Se = (double*)take(n * 8);
+    p->Vd = (double*)take(n * n * 8);
+  }
+  return off;
+}
+
+__global__ void k_reset(int32_t* status, double* diag, int nd) {
+  if (threadIdx.x == 0) *status = RSVD_OK;
+  if ((int)threadIdx.x < nd) diag[threadIdx.x] = 0.0;
+}
+
+__global__ void k_trace(const double* G, int64_t n, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += G[i * n + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// X = G (a symmetric matrix is its own column-major copy), J = I.
+__global__ void k_init_eig(const double* G, int64_t n, double* X, double* J) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx - i * n;
+  X[idx] = 0.5 * (G[i * n + j] + G[j * n + i]);
+  J[idx] = (i == j) ? 1.0 : 0.0;
+}
+
+hipError_t reset(rsvd_plan_s* p) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, p->stream, p->status, p->diag, kDiagWords);
+  return hipGetLastError();
+}
+
+template <typename T>
+struct Path {
+  rsvd_plan_s* p;
+  hipStream_t s;
+  explicit Path(rsvd_plan_s* plan) : p(plan), s(plan->stream) {}
+
+  // Wout (c x c) = Y^T Y with exact FP64 products, fixed-order reduction.
+  hipError_t gram(const T* Y, int64_t m, int c, int64_t ldy, double* Wout) {
+    int ns = 0;
+    hipError_t e = launch_gemm_tn_partial<T, double>(Y, m, c, ldy, Y, ldy, c, p->part, p->max_split,
+                                                     &ns, s);
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(p->part, ns, c, c, Wout, c, s);
+  }
+
+  // Z (n x c, FP64) = A^T Q.
+  hipError_t tn(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q, int64_t ldq, int c,
+                double* Z) {
+    int ns = 0;
+    hipError_t e = launch_gemm_tn_partial<T, T>(A, m, n, lda, Q, ldq, c, p->part, p->max_split,
+                                                &ns, s);
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(p->part, ns, n, c, Z, c, s);
+  }
+
+  // CholeskyQR2 of Y (m x c): Q1 = Y R1^-1 (type T), R2 = chol(Q1^T Q1); the
+  // orthonormal basis is Q = Q1 R2^-1 (kept implicit: R2inv).
+  hipError_t cqr2(const T* Y, int64_t m, int c, int64_t ldy, T* Q1, int64_t ldq, double* R1,
+                  double* R1inv, double* R2, double* R2inv, T* RinvT) {
+    hipError_t e;
+    if ((e = gram(Y, m, c, ldy, p->Wg)) != hipSuccess) return e;
+    if ((e = launch_chol_inv<T>(p->Wg, c, R1, R1inv, RinvT, p->status, s)) != hipSuccess) return e;
+    if ((e = launch_gemm_nn<T>(Y, m, c, ldy, RinvT, c, c, Q1, ldq, nullptr, nullptr, s)) != hipSuccess)
+      return e;
+    if ((e = gram(Q1, m, c, ldq, p->Wg)) != hipSuccess) return e;
+    return launch_chol_inv<T>(p->Wg, c, R2, R2inv, RinvT, p->status, s);
+  }
+};
+
+// Orthonormalise an FP64 n x c matrix Zin: Zout = Q (explicit), R2s R1s = R.
+hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, double* Zout) {
+  Path<double> d(p);
+  hipError_t e = d.cqr2(Zin, n, c, c, p->Z1, c, p->R1s, p->R1invs, p->R2s, p->R2invs,
+                        (double*)p->RinvTs);
+  if (e != hipSuccess) return e;
+  return launch_gemm_nn<double>(p->Z1, n, c, c, (const double*)p->RinvTs, c, c, Zout, c, nullptr,
+                                nullptr, p->stream);
+}
+
+// Thin SVD of the FP64 matrix Tm (r x c): Tm = Qt R (CholeskyQR2), one-sided
+// Jacobi R J = Uo diag(Su), so Tm = (Qt Uo) diag(Su) J^T: V~ = Qt Uo, W = J.
+// Leaves V~ unsorted in p->Vt, the values in p->Su and J in p->Jm.
+hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c) {
+  hipError_t e;
+  if ((e = cqr2_small(p, Tm, r, c, p->Zq)) != hipSuccess) return e;
+  if ((e = launch_small_gemm<double>(p->R2s, p->R1s, c, c, c, p->Rt, nullptr, p->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_jacobi_svd_small(p->Rt, c, p->Uo, p->Su, p->Jm, p->diag, p->status, p->stream)) !=
+      hipSuccess)
+    return e;
+  return launch_small_gemm<double>(p->Zq, p->Uo, r, c, c, p->Vt, nullptr, p->stream);
+}
+
+template <typename T>
+int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, int k, int pov,
+                 int q, double t, const double* omega, T* U, int64_t ldu, double* S, T* V,
+                 int64_t ldv, int32_t* K) {
+  const int l = (int)((k + pov < n) ? k + pov : n);
+  hipStream_t s = p->stream;
+  Path<T> P(p);
+  T* Xs = (T*)p->Xs;
+  T* Y = (T*)p->Y;
+  T* Q1 = (T*)p->Q1;
+  RSVD_CHECK(reset(p));
+  // step 1: the Gaussian sketch matrix G (n x l)
+  if (!omega) {
+    RSVD_CHECK(launch_gaussian_fill(p->seed, n, l, p->omega, s));
+    omega = p->omega;
+  }
+  RSVD_CHECK(launch_cast_from_f64<T>(omega, n, l, l, Xs, l, s));
+  // step 2: H = A G, with ||A||_F^2 (Eq. sumeigen) from the same pass
+  int np = 0;
+  RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Y, l, p->fro2_part, &np, s));
+  RSVD_CHECK(launch_reduce_scalar(p->fro2_part, np, p->scal, s));
+  RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  // step 3: power iterations H = A (A^T H), orthonormalised after each product
+  for (int it = 0; it < q; ++it) {
+    RSVD_CHECK(P.tn(A, m, n, lda, Q1, l, l, p->Zd));
+    RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));  // A^T Q
+    RSVD_CHECK(cqr2_small(p, p->Z2, n, l, p->Zq));
+    RSVD_CHECK(launch_cast_from_f64<T>(p->Zq, n, l, l, Xs, l, s));
+    RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Y, l, nullptr, nullptr, s));
+    RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  }
+  // step 5: T = A^T Q
+  RSVD_CHECK(P.tn(A, m, n, lda, Q1, l, l, p->Zd));
+  RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));
+  // step 6: T = V~ S~ W^T
+  RSVD_CHECK(small_svd_unsorted(p, p->Z2, n, l));
+  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Su, l, p->Vt, n, l, 1, p->Jm, k, S, V, ldv, nullptr,
+                                         p->Wk, s));
+  // step 7: U~ = Q W = Q1 (R2^-1 W), first k columns
+  RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s));
+  RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, l, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
+  // K by the explained-variance criterion (Sec. 2.4)
+  RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
+  return RSVD_OK;
+}
+
+template <typename T>
+int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, double t,
+                 int ucols, T* U, int64_t ldu, double* S, T* V, int64_t ldv, int32_t* K) {
+  hipStream_t s = p->stream;
+  Path<T> P(p);
+  RSVD_CHECK(reset(p));
+  // step 1: A^T A (Eq. AB), and its trace = ||A||_F^2 (Eq. sumeigen)
+  RSVD_CHECK(P.tn(A, m, n, lda, A, lda, (int)n, p->Gd));
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, p->Gd, n, p->scal);
+  RSVD_CHECK(hipGetLastError());
+  // step 2: eigen-decomposition (Jacobi, FP64)
+  hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, p->Gd, n,
+                     p->Xe, p->Je);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->status, s));
+  // step 3: s_i = sqrt(lambda_i) (Eq. LambdaSigma), sorted, sign rule
+  RSVD_CHECK(launch_sqrt_clamp(p->lam, (int)n, p->Se, s));
+  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Se, (int)n, p->Je, n, 1, n, nullptr, (int)n, S, V,
+                                         ldv, p->Vd, nullptr, s));
+  // step 4: u_i = A v_i / s_i
+  if (ucols > 0) {
+    const double floor_rel = (double)(m > n ? m : n) * 2.220446049250313e-16;
+    RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, ucols, n, S, floor_rel, (T*)p->Xs, ucols, s));
+    RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, (const T*)p->Xs, ucols, ucols, U, ldu, nullptr,
+                                 nullptr, s));
+  }
+  RSVD_CHECK(launch_select_k(S, (int)n, p->scal, t, K, p->diag, p->status, s));
+  return RSVD_OK;
+}
+
+bool bad_t(double t) { return !(t > 0.0 && t <= 1.0); }
+
+int32_t check_common(rsvd_plan_s* p, const void* A, int64_t m, int64_t n, int64_t lda) {
+  if (!p || !A) return RSVD_ERR_ARG;
+  if (n < 1 || m < n) return RSVD_ERR_SHAPE;
+  if (m > p->m_max || n > p->n_max) return RSVD_ERR_SHAPE;
+  if (lda < n) return RSVD_ERR_ARG;
+  return RSVD_OK;
+}
+
+int32_t check_rsvd(rsvd_plan_s* p, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,
+                   int32_t pov, int32_t q, double t, const void* U, int64_t ldu, const void* S,
+                   const void* V, int64_t ldv, const void* K) {
+  int32_t rc = check_common(p, A, m, n, lda);
+  if (rc != RSVD_OK) return rc;
+  if (!U || !S || !V || !K) return RSVD_ERR_ARG;
+  if (k < 1 || k > n || pov < 0 || q < 0 || bad_t(t)) return RSVD_ERR_ARG;
+  if (ldu < k || ldv < k) return RSVD_ERR_ARG;
+  const int64_t l = (k + (int64_t)pov < n) ? k + (int64_t)pov : n;
+  if (l > p->l_max) return RSVD_ERR_SHAPE;
+  return RSVD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* rsvd_status_string(int32_t st) {
+  switch (st) {
+    case RSVD_OK: return "RSVD_OK";
+    case RSVD_WARN_THRESHOLD: return "RSVD_WARN_THRESHOLD";
+    case RSVD_WARN_ZERO_MATRIX: return "RSVD_WARN_ZERO_MATRIX";
+    case RSVD_ERR_ARG: return "RSVD_ERR_ARG";
+    case RSVD_ERR_SHAPE: return "RSVD_ERR_SHAPE";
+    case RSVD_ERR_NOMEM: return "RSVD_ERR_NOMEM";
+    case RSVD_ERR_DEVICE: return "RSVD_ERR_DEVICE";
+    case RSVD_ERR_BREAKDOWN: return "RSVD_ERR_BREAKDOWN";
+    case RSVD_ERR_NONFINITE: return "RSVD_ERR_NONFINITE";
+    case RSVD_ERR_NOCONV: return "RSVD_ERR_NOCONV";
+    default: return "RSVD_UNKNOWN_STATUS";
+  }
+}
+
+int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_t l_max,
+                         int32_t dtype, int32_t want_gram, uint64_t seed, void* stream) {
+  if (!plan) return RSVD_ERR_ARG;
+  *plan = nullptr;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
+  if (l_max < 1) return RSVD_ERR_ARG;
+  if (n_max < 1 || m_max < n_max) return RSVD_ERR_SHAPE;
+  if (l_max > kMaxL) return RSVD_ERR_SHAPE;
+  rsvd_plan_s* p = new (std::nothrow) rsvd_plan_s();
+  if (!p) return RSVD_ERR_NOMEM;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RSVD_ERR_DEVICE; }
+  p->dtype = dtype;
+  p->m_max = m_max;
+  p->n_max = n_max;
+  p->l_max = (int)((l_max < n_max) ? l_max : n_max);
+  p->gram = want_gram != 0;
+  p->seed = seed;
+  p->stream = (hipStream_t)stream;
+  p->max_split = tn_max_split(m_max, n_max, p->l_max);
+  p->bytes = carve(p, nullptr);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, p->bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return RSVD_ERR_NOMEM;
+  }
+  p->base = (char*)mem;
+  carve(p, p->base);
+  if (hipMemsetAsync(p->base, 0, p->bytes, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    (void)hipFree(mem);
+    delete p;
+    return RSVD_ERR_DEVICE;
+  }
+  *plan = p;
+  return RSVD_OK;
+}
+
+int32_t rsvd_plan_destroy(rsvd_plan_t plan) {
+  if (!plan) return RSVD_OK;
+  int32_t rc = RSVD_OK;
+  if (hipSetDevice(plan->device) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  if (plan->base && hipFree(plan->base) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  delete plan;
+  return rc;
+}
+
+int32_t rsvd_plan_status(rsvd_plan_t plan) {
+  if (!plan) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return RSVD_ERR_DEVICE;
+  int32_t st = 0;
+  if (hipMemcpy(&st, plan->status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return RSVD_ERR_DEVICE;
+  const int32_t zero = 0;
+  if (hipMemcpy(plan->status, &zero, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return RSVD_ERR_DEVICE;
+  return st;
+}
+
+int32_t rsvd_plan_diag(rsvd_plan_t plan, double* out, int32_t count) {
+  if (!plan || !out || count < 0) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return RSVD_ERR_DEVICE;
+  const int32_t nc = count < kDiagWords ? count : kDiagWords;
+  if (nc > 0 && hipMemcpy(out, plan->diag, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return RSVD_ERR_DEVICE;
+  return nc;
+}
+
+int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                         int32_t k, int32_t p, int32_t q, double t, const double* omega, void* U,
+                         int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K) {
+  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (plan->dtype == RSVD_F64)
+    return rsvd_run<double>(plan, (const double*)A, m, n, lda, k, p, q, t, omega, (double*)U, ldu,
+                            S, (double*)V, ldv, K);
+  return rsvd_run<float>(plan, (const float*)A, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
+                         (float*)V, ldv, K);
+}
+
+int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,
+                   int32_t p, int32_t q, double t, void* U, int64_t ldu, double* S, void* V,
+                   int64_t ldv, int32_t* K) {
+  return rsvd_solve_omega(plan, A, m, n, lda, k, p, q, t, nullptr, U, ldu, S, V, ldv, K);
+}
+
+int32_t gram_eig_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                       double t, int32_t ucols, void* U, int64_t ldu, double* S, void* V,
+                       int64_t ldv, int32_t* K) {
+  int32_t rc = check_common(plan, A, m, n, lda);
+  if (rc != RSVD_OK) return rc;
+  if (!plan->gram) return RSVD_ERR_SHAPE;
+  if (!S || !V || !K || bad_t(t) || ucols < 0 || ucols > n || ldv < n) return RSVD_ERR_ARG;
+  if (ucols > 0 && (!U || ldu < ucols)) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (plan->dtype == RSVD_F64)
+    return gram_run<double>(plan, (const double*)A, m, n, lda, t, ucols, (double*)U, ldu, S,
+                            (double*)V, ldv, K);
+  return gram_run<float>(plan, (const float*)A, m, n, lda, t, ucols, (float*)U, ldu, S, (float*)V,
+                         ldv, K);
+}
+
+int32_t rsvd_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G, void* stream) {
+  if (!G || rows < 0 || cols < 0) return RSVD_ERR_ARG;
+  RSVD_CHECK(launch_gaussian_fill(seed, rows, cols, G, (hipStream_t)stream));
+  return RSVD_OK;
+}
+
+int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                     const void* X, int64_t ldx, int32_t c, void* Y, int64_t ldy, double* Gram,
+                     double* fro2) {
+  if (!plan || !A || !X || !Y) return RSVD_ERR_ARG;
+  if (m < 1 || n < 1 || c < 1 || lda < n || ldx < c || ldy < c) return RSVD_ERR_ARG;
+  const int64_t cmax = plan->gram ? (plan->n_max > plan->l_max ? plan->n_max : plan->l_max)
+                                  : plan->l_max;
+  if (m > plan->m_max || c > cmax || (Gram && c > plan->l_max)) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipStream_t s = plan->stream;
+  int np = 0;
+  if (plan->dtype == RSVD_F64) {
+    RSVD_CHECK(launch_gemm_nn<double>((const double*)A, m, n, lda, (const double*)X, ldx, c,
+                                      (double*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
+    if (Gram) RSVD_CHECK(Path<double>(plan).gram((const double*)Y, m, c, ldy, Gram));
+  } else {
+    RSVD_CHECK(launch_gemm_nn<float>((const float*)A, m, n, lda, (const float*)X, ldx, c,
+                                     (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
+    if (Gram) RSVD_CHECK(Path<float>(plan).gram((const float*)Y, m, c, ldy, Gram));
+  }
+  if (fro2) RSVD_CHECK(launch_reduce_scalar(plan->fro2_part, np, fro2, s));
+  return RSVD_OK;
+}
+
+int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                     const void* Q, int64_t ldq, int32_t c, double* Z) {
+  if (!plan || !A || !Q || !Z) return RSVD_ERR_ARG;
+  if (m < 1 || n < 1 || c < 1 || lda < n || ldq < c) return RSVD_ERR_ARG;
+  const int64_t cmax = plan->gram ? (plan->n_max > plan->l_max ? plan->n_max : plan->l_max)
+                                  : plan->l_max;
+  if (m > plan->m_max || n > plan->n_max || c > cmax) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (plan->dtype == RSVD_F64)
+    RSVD_CHECK(Path<double>(plan).tn((const double*)A, m, n, lda, (const double*)Q, ldq, c, Z));
+  else
+    RSVD_CHECK(Path<float>(plan).tn((const float*)A, m, n, lda, (const float*)Q, ldq, c, Z));
+  return RSVD_OK;
+}
+
+int32_t rsvd_cholqr2(rsvd_plan_t plan, const void* Y, int64_t m, int32_t c, int64_t ldy, void* Q,
+                     int64_t ldq, double* R) {
+  if (!plan || !Y || !Q || !R) return RSVD_ERR_ARG;
+  if (c < 1 || m < c || ldy < c || ldq < c) return RSVD_ERR_ARG;
+  if (m > plan->m_max || c > plan->l_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipStream_t s = plan->stream;
+  RSVD_CHECK(reset(plan));
+  if (plan->dtype == RSVD_F64) {
+    Path<double> P(plan);
+    RSVD_CHECK(P.cqr2((const double*)Y, m, c, ldy, (double*)plan->Q1, c, plan->R1, plan->R1inv,
+                      plan->R2, plan->R2inv, (double*)plan->RinvT));
+    RSVD_CHECK(launch_gemm_nn<double>((const double*)plan->Q1, m, c, c,
+                                      (const double*)plan->RinvT, c, c, (double*)Q, ldq, nullptr,
+                                      nullptr, s));
+  } else {
+    Path<float> P(plan);
+    RSVD_CHECK(P.cqr2((const float*)Y, m, c, ldy, (float*)plan->Q1, c, plan->R1, plan->R1inv,
+                      plan->R2, plan->R2inv, (float*)plan->RinvT));
+    RSVD_CHECK(launch_gemm_nn<float>((const float*)plan->Q1, m, c, c, (const float*)plan->RinvT,
+                                     c, c, (float*)Q, ldq, nullptr, nullptr, s));
+  }
+  RSVD_CHECK(launch_small_gemm<double>(plan->R2, plan->R1, c, c, c, R, nullptr, s));
+  return RSVD_OK;
+}
+
+int32_t rsvd_small_svd(rsvd_plan_t plan, const double* T, int64_t r, int32_t c, double* Vt,
+                       double* S, double* W) {
+  if (!plan || !T || !Vt || !S || !W) return RSVD_ERR_ARG;
+  if (c < 1 || r < c) return RSVD_ERR_ARG;
+  if (r > plan->n_max || c > plan->l_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  RSVD_CHECK(reset(plan));
+  RSVD_CHECK(small_svd_unsorted(plan, T, r, c));
+  RSVD_CHECK(launch_sort_sign_scatter<double>(plan->Su, c, plan->Vt, r, c, 1, plan->Jm, c, S,
+                                              nullptr, 0, Vt, W, plan->stream));
+  return RSVD_OK;
+}
+
+int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, double* V) {
+  if (!plan || !G || !lam || !V) return RSVD_ERR_ARG;
+  if (n < 1) return RSVD_ERR_ARG;
+  if (!plan->gram || n > plan->n_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipStream_t s = plan->stream;
+  RSVD_CHECK(reset(plan));
+  hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, G, n,
+                     plan->Xe, plan->Je);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(launch_jacobi_eig(plan->Xe, plan->Je, n, plan->lam, plan->diag, plan->flags,
+                               plan->status, s));
+  RSVD_CHECK(launch_sort_sign_scatter<double>(plan->lam, (int)n, plan->Je, n, 1, n, nullptr,
+                                              (int)n, lam, nullptr, 0, V, nullptr, s));
+  return RSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// rsvd_internal.h -- shared declarations of the HIP kernels behind librsvd.so.
+// Target: gfx950 (CDNA4), wave64.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rsvd.h"
+
+namespace rsvd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// 16x16x4 matrix-core products.  For both, lane l supplies a = Aop[l%16][l/16]
+// and b = Bop[l/16][l%16]; the 16x16 result is spread over the wave as four
+// values per lane.  Row of value e held by lane l (column is always l%16):
+//   fp32: 4*(l/16) + e        fp64: (l/16) + 4*e
+template <typename C> struct Mfma;
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (host functions; every one returns hipSuccess or the launch error).
+
+// Y (m x c) = A (m x n) X (n x c), all row-major; T = float or double.
+// fro2_part != nullptr: per-block partial sums of a_ij^2 (FP64), count
+// returned through *nparts.
+template <typename T>
+hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
+                          int c, T* Y, int64_t ldy, double* fro2_part, int* nparts,
+                          hipStream_t s);
+
+// Partials P[s] (n x c, FP64) of A^T Q over row splits; C = compute type of
+// the matrix-core product (double gives an exact-product FP64 Gram for float
+// data).  *nsplit returns the number of partial matrices written.
+template <typename T, typename C>
+hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q,
+                                  int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                                  hipStream_t s);
+
+// Z (rows x cols) = sum over s < nsplit of P[s] (each rows x cols), fixed order.
+hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,
+                                  double* Z, int64_t ldz, hipStream_t s);
+// out[0] = sum of parts[0..n) in order (single block).
+hipError_t launch_reduce_scalar(const double* parts, int n, double* out, hipStream_t s);
+
+// Largest number of row splits launch_gemm_tn_partial uses for (m, n, c).
+int64_t tn_max_split(int64_t m, int64_t n, int c);
+
+// ---- small FP64 kernels (small.hip) ----
+hipError_t launch_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_cast_from_f64(const double* src, int64_t rows, int64_t cols, int64_t lds,
+                                T* dst, int64_t ldd, hipStream_t s);
+template <typename T>
+hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t lds,
+                              double* dst, int64_t ldd, hipStream_t s);
+
+// Cholesky of the symmetric c x c matrix W (ld = c): R upper with W = R^T R,
+// Rinv = R^-1 (upper), both ld = c.  Rinv also written, rounded, to RinvT
+// (type T, ld = c) when RinvT != nullptr.  Non-positive pivot -> status word
+// = RSVD_ERR_BREAKDOWN, R = 0 and Rinv = identity (so later kernels stay finite).
+template <typename T>
+hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
+                           int32_t* status, hipStream_t s);
+
+// C (r x c2) = A (r x c1) B (c1 x c2), FP64, all ld = their column counts.
+// Optional rounded copy CT (type T, ld = c2).
+template <typename T>
+hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1, int c2,
+                             double* C, T* CT, hipStream_t s);
+
+// One-sided Jacobi SVD of a c x c FP64 matrix M (ld = c), in one workgroup:
+// M J = Uo diag(S) with J orthogonal; writes Uo (c x c), S (c), J (c x c),
+// all unsorted; sweeps used and final off-diagonal measure to diag[0..1].
+hipError_t launch_jacobi_svd_small(const double* M, int c, double* Uo, double* S, double* J,
+                                   double* diag, int32_t* status, hipStream_t s);
+
+// One-sided Jacobi on the columns of a symmetric n x n FP64 matrix (its
+// eigen-decomposition): X <- X J until the columns are orthogonal; then
+// lambda_i = ||x_i|| and the eigenvectors are the columns of J.
+hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
+                             int32_t* flags, int32_t* status, hipStream_t s);
+
+// Sort (descending by key), apply the sign rule, and scatter the first kout
+// singular triplets: S_out[i] = key-sorted S, Vout (r x kout, type T, ldv)
+// and/or Vd_out (r x kout, FP64) from the columns of Vsrc (r x c, FP64),
+// Wout (c x kout, FP64) from the columns of Wsrc (c x c, row-major), the
+// vector pair flipped together.
+// Element i of source column col is Vsrc[i * vrs + col * vcs].
+template <typename T>
+hipError_t launch_sort_sign_scatter(const double* S, int c, const double* Vsrc, int64_t r,
+                                    int64_t vrs, int64_t vcs, const double* Wsrc, int kout,
+                                    double* S_out, T* Vout, int64_t ldv, double* Vd_out,
+                                    double* Wout, hipStream_t s);
+
+// K by the explained-variance criterion over S[0..k), denominator *fro2;
+// writes *K (device int32), diag[0] = fro2, diag[1] = captured fraction,
+// diag[4] = K, and RSVD_WARN_* / RSVD_ERR_NONFINITE into *status.
+hipError_t launch_select_k(const double* S, int k, const double* fro2, double t, int32_t* K,
+                           double* diag, int32_t* status, hipStream_t s);
+
+// Scale the columns of V (n x cols, FP64) by 1/S[j] into X (type T), with a
+// zero column when S[j] <= floor_rel * S[0].
+template <typename T>
+hipError_t launch_scale_cols_inv(const double* V, int64_t n, int cols, int64_t ldv,
+                                 const double* S, double floor_rel, T* X, int64_t ldx,
+                                 hipStream_t s);
+
+// S[i] = sqrt(max(lam[i], 0)).
+hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s);
+// p[0..n) = v (a kernel, so the fill can be captured in a graph).
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
+// Number of int32 words launch_jacobi_eig needs in `flags`.
+int jacobi_eig_flag_words();
+
+}  // namespace rsvd

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI (no GPU needed): librsvd.so loads, exports
+every function include/rsvd.h declares, and rejects bad arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "rsvd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1906_12085_amd as pk
+    if not os.path.exists(pk.LIB_PATH):
+        pytest.fail("librsvd.so is not built (run __graft_entry__.build())")
+    return pk.load_library()
+
+
+def test_header_parses_all_entry_points():
+    names = declared_functions()
+    assert "rsvd_solve" in names and "gram_eig_solve" in names and len(names) >= 14
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_1906_12085_amd as pk
+    names = declared_functions()
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in rsvd.h but not exported"
+    assert sorted(pk.EXPORTS) == names
+
+
+def test_status_strings(lib):
+    import paper_1906_12085_amd as pk
+    for code, name in pk.STATUS.items():
+        assert pk.rsvd_status_string(code) == name
+    assert pk.rsvd_status_string(12345) == "RSVD_UNKNOWN_STATUS"
+
+
+def test_plan_create_validates_before_device_calls(lib):
+    h = ctypes.c_void_p()
+    f = lib.rsvd_plan_create
+    assert f(None, 100, 10, 8, 0, 0, 0, None) == -1                       # NULL out-pointer
+    assert f(ctypes.byref(h), 100, 10, 8, 7, 0, 0, None) == -1            # bad dtype
+    assert f(ctypes.byref(h), 100, 10, 0, 0, 0, 0, None) == -1            # l_max < 1
+    assert f(ctypes.byref(h), 5, 10, 8, 0, 0, 0, None) == -2              # m_max < n_max
+    assert f(ctypes.byref(h), 100, 0, 8, 0, 0, 0, None) == -2             # n_max < 1
+    assert f(ctypes.byref(h), 1000, 200, 97, 1, 0, 0, None) == -2         # l_max above 96
+    assert h.value is None
+
+
+def test_solvers_reject_null_plan(lib):
+    a = ctypes.c_void_p(16)
+    assert lib.rsvd_solve(None, a, 100, 10, 10, 2, 2, 1, 0.9, a, 2, a, a, 2, a) == -1
+    assert lib.gram_eig_solve(None, a, 100, 10, 10, 0.9, 0, None, 0, a, a, 10, a) == -1
+    assert lib.rsvd_gemm_nn(None, a, 10, 10, 10, a, 4, 4, a, 4, None, None) == -1
+    assert lib.rsvd_plan_status(None) == -1
+    assert lib.rsvd_plan_destroy(None) == 0
+    assert lib.rsvd_gaussian_fill(1, 4, 4, None, None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import paper_1906_12085_amd as pk
+    saved = pk._lib
+    try:
+        pk._lib = None
+        with pytest.raises(ImportError):
+            pk.load_library(str(tmp_path / "missing.so"))
+    finally:
+        pk._lib = saved

@@ -1,0 +1,87 @@
+"""End-to-end parity of gram_eig_solve (truncated SVD through A^T A, paper
+Sec. 2.3 / 3.1.3) against the oracle on the same stored A.
+
+The A^T A route resolves s_i only to about u * s_1^2 / s_i (absolute), so the
+relative singular-value gate (1e-10 FP64, 1e-4 FP32) applies to the values the
+criterion keeps (i <= K) and, for the rest, the bound |s^2 - s_o^2| <=
+c n u s_1^2 is checked; vectors are compared where the spectrum separates
+them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import EPS64, align_columns, announce, dev, host, rounded, sign_rule_holds
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1906_12085_amd as rs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def plans():
+    out = {dt: rs.Plan(30000, 260, 32, dt, want_gram=True, seed=1) for dt in (torch.float64, torch.float32)}
+    yield out
+    for p in out.values():
+        p.close()
+
+
+def test_config1_fp64_gram_route(plans):
+    announce("gram config1 fp64 2000x200")
+    A0 = synth.config1(1)
+    m, n = A0.shape
+    res = plans[torch.float64].gram_eig(dev(A0, torch.float64), 0.95)
+    ref = oracle.gram_eig(A0, 0.95)
+    S, V, U = host(res.S), host(res.V), host(res.U)
+    assert res.status == rs.RSVD_OK and res.K == ref.K == 10
+    K = res.K
+    assert np.max(np.abs(S[:K] - ref.S[:K]) / ref.S[:K]) <= 1e-10
+    assert np.max(np.abs(S ** 2 - ref.S ** 2)) <= 50 * n * EPS64 * ref.S[0] ** 2
+    assert np.abs(align_columns(V[:, :K], ref.V[:, :K]) - ref.V[:, :K]).max() <= 1e-9
+    assert np.abs(align_columns(U[:, :K], ref.U[:, :K]) - ref.U[:, :K]).max() <= 1e-9
+    assert sign_rule_holds(V)
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 50 * n * EPS64
+    # Eq. AV on the formed columns
+    good = S > max(m, n) * EPS64 * S[0]
+    assert np.linalg.norm(A0 @ V[:, good] - U[:, good] * S[good]) <= 1e-9 * np.linalg.norm(A0)
+
+
+@pytest.mark.parametrize("m,n,ucols", [(20000, 96, 96), (4099, 131, 40), (300, 257, 0), (64, 64, 64)])
+def test_fp32_gram_route(plans, m, n, ucols):
+    announce(f"gram fp32 m={m} n={n} ucols={ucols}")
+    rng = np.random.default_rng(m + n)
+    # well-conditioned, separated spectrum (as the 1e6 x 512 noisy workload is)
+    sigma = np.linspace(2.0, 1.0, n)
+    A0 = rounded(synth.haar(rng, m, n, centre=True) @ np.diag(sigma) @ synth.haar(rng, n, n).T,
+                 torch.float32)
+    res = plans[torch.float32].gram_eig(dev(A0, torch.float32), 0.9, ucols=ucols)
+    ref = oracle.gram_eig(A0, 0.9, ucols=ucols)
+    S, V = host(res.S), host(res.V)
+    assert res.status == rs.RSVD_OK and res.K == ref.K
+    assert np.max(np.abs(S - ref.S) / ref.S) <= 1e-4
+    # eigenvectors: every relative eigenvalue gap is >= 1/n here, and the FP32
+    # Gram perturbs A^T A by ~1e-6 relative, so each vector moves < 1e-3
+    err = np.abs(align_columns(V, ref.V) - ref.V).max(axis=0)
+    assert np.all(err <= 1e-3)
+    assert sign_rule_holds(V)
+    if ucols:
+        U = host(res.U)
+        assert U.shape == (m, ucols)
+        assert np.abs(U.T @ U - np.eye(ucols)).max() <= 1e-3
+        assert oracle.principal_angle_max(ref.U[:, :ucols], U) <= 1e-3
+    else:
+        assert res.U is None
+
+
+def test_gram_zero_and_nonfinite(plans):
+    announce("gram status words")
+    plan = plans[torch.float64]
+    res = plan.gram_eig(torch.zeros(50, 10, dtype=torch.float64, device="cuda"), 0.9)
+    assert res.status == rs.RSVD_WARN_ZERO_MATRIX and res.K == 0
+    assert np.all(host(res.S) == 0) and np.all(host(res.U) == 0)
+    A = torch.randn(50, 10, dtype=torch.float64, device="cuda")
+    A[1, 1] = float("inf")
+    res = plan.gram_eig(A, 0.9)
+    assert res.status in (rs.RSVD_ERR_NONFINITE,)

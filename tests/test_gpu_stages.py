@@ -1,0 +1,177 @@
+"""Per-stage parity of the HIP path against the oracle, through the C ABI.
+
+Bounds follow from the arithmetic: a length-n dot product in precision u has
+error at most about n*u*sum|a_k b_k| (standard rounding analysis), so each
+product is compared element by element against that bound computed from the
+absolute values of the same operands.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import EPS64, U32, align_columns, announce, dev, host, rounded, sign_rule_holds
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1906_12085_amd as rs  # noqa: E402
+
+DTYPES = {"f64": torch.float64, "f32": torch.float32}
+
+
+def unit(dt):
+    return EPS64 if dt == torch.float64 else U32
+
+
+@pytest.fixture(scope="module")
+def plans():
+    out = {}
+    for name, dt in DTYPES.items():
+        out[name] = rs.Plan(6000, 300, 96, dt, want_gram=True, seed=7)
+    yield out
+    for p in out.values():
+        p.close()
+
+
+def test_gaussian_fill_matches_published_definition():
+    for seed, rows, cols in [(101, 200, 30), (5, 3, 5), (2**40 + 3, 512, 80)]:
+        announce(f"gaussian_fill seed={seed} {rows}x{cols}")
+        G = torch.empty(rows, cols, dtype=torch.float64, device="cuda")
+        rs.rsvd_gaussian_fill(seed, G)
+        torch.cuda.synchronize()
+        ref = synth.gaussian_omega(seed, rows, cols)
+        got = host(G)
+        # same Philox words and uniforms; only libm's last bits may differ
+        assert np.max(np.abs(got - ref) / (1.0 + np.abs(ref))) <= 8 * EPS64
+
+
+NN_CASES = [
+    (1037, 203, 30, 0),    # ragged rows, odd n (scalar loads)
+    (1037, 200, 80, 0),    # 16-byte loads, tail row block
+    (300, 64, 17, 4),      # padded leading dimension, c not a multiple of 16
+    (5000, 256, 96, 0),
+    (777, 150, 200, 0),    # c > 128: several column tiles
+]
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("m,n,c,pad", NN_CASES)
+def test_gemm_nn_parity(plans, name, m, n, c, pad):
+    dt = DTYPES[name]
+    announce(f"gemm_nn {name} m={m} n={n} c={c} pad={pad}")
+    rng = np.random.default_rng(m + n + c)
+    A0 = rounded(rng.standard_normal((m, n)), dt)
+    X0 = rounded(rng.standard_normal((n, c)), dt)
+    Abig = dev(np.pad(A0, ((0, 0), (0, pad))), dt)
+    A = Abig[:, :n]
+    X = dev(X0, dt)
+    Y = torch.empty(m, c, dtype=dt, device="cuda")
+    want_gram = c <= 96
+    Gm = torch.empty(c, c, dtype=torch.float64, device="cuda") if want_gram else None
+    f2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    rs.rsvd_gemm_nn(plans[name].handle, A, X, Y, Gram=Gm, fro2=f2)
+    torch.cuda.synchronize()
+    Yref = oracle.gemm_nn(A0, X0)
+    bound = 2.0 * n * unit(dt) * (np.abs(A0) @ np.abs(X0)) + 1e-300
+    Yg = host(Y)
+    assert np.all(np.abs(Yg - Yref) <= bound)
+    f2ref = oracle.fro2(A0)
+    assert abs(host(f2)[0] - f2ref) <= 2 * m * n * EPS64 * f2ref
+    if want_gram:
+        # FP64 Gram of the stored (rounded) Y, exact products
+        Gref = oracle.gemm_tn(Yg, Yg)
+        gb = 2.0 * m * EPS64 * (np.abs(Yg).T @ np.abs(Yg))
+        assert np.all(np.abs(host(Gm) - Gref) <= gb)
+
+
+TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100, 97, 96)]
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("m,n,c", TN_CASES)
+def test_gemm_tn_parity(plans, name, m, n, c):
+    dt = DTYPES[name]
+    announce(f"gemm_tn {name} m={m} n={n} c={c}")
+    rng = np.random.default_rng(3 * m + n + c)
+    A0 = rounded(rng.standard_normal((m, n)), dt)
+    Q0 = rounded(rng.standard_normal((m, c)), dt)
+    Z = torch.empty(n, c, dtype=torch.float64, device="cuda")
+    rs.rsvd_gemm_tn(plans[name].handle, dev(A0, dt), dev(Q0, dt), Z)
+    torch.cuda.synchronize()
+    Zref = oracle.gemm_tn(A0, Q0)
+    # partial sums over at most m rows in the product precision, then FP64
+    bound = 2.0 * m * unit(dt) * (np.abs(A0).T @ np.abs(Q0)) + 1e-300
+    assert np.all(np.abs(host(Z) - Zref) <= bound)
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("m,c,kappa", [(2000, 30, 1e2), (5000, 80, 1e3), (333, 17, 10.0)])
+def test_cholqr2_parity(plans, name, m, c, kappa):
+    dt = DTYPES[name]
+    announce(f"cholqr2 {name} m={m} c={c} kappa={kappa}")
+    rng = np.random.default_rng(m + c)
+    Y0 = synth.haar(rng, m, c) @ np.diag(np.logspace(0, -np.log10(kappa), c)) @ synth.haar(rng, c, c).T
+    Y0 = rounded(Y0, dt)
+    Q = torch.empty(m, c, dtype=dt, device="cuda")
+    R = torch.empty(c, c, dtype=torch.float64, device="cuda")
+    p = plans[name]
+    rs.rsvd_cholqr2(p.handle, dev(Y0, dt), Q, R)
+    assert p.status() == rs.RSVD_OK
+    Qg, Rg = host(Q), host(R)
+    u = unit(dt)
+    # orthonormality and reconstruction at the working precision
+    assert np.abs(Qg.T @ Qg - np.eye(c)).max() <= 50 * c * u
+    assert np.linalg.norm(Qg @ Rg - Y0) <= 50 * c * u * np.linalg.norm(Y0)
+    # same factors as the oracle's Householder QR (unique with R_jj > 0)
+    Qo, Ro = oracle.qr(Y0)
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0)
+    assert np.abs(Rg - Ro).max() <= 50 * c * u * kappa * np.abs(Ro).max()
+    assert np.abs(Qg - Qo).max() <= 50 * c * u * kappa
+
+
+@pytest.mark.parametrize("r,c", [(300, 40), (200, 31), (96, 96), (250, 1)])
+def test_small_svd_parity(plans, r, c):
+    announce(f"small_svd r={r} c={c}")
+    rng = np.random.default_rng(r * c)
+    T0 = synth.haar(rng, r, c) @ np.diag(np.logspace(0, -6, c)) @ synth.haar(rng, c, c).T
+    Vt = torch.empty(r, c, dtype=torch.float64, device="cuda")
+    S = torch.empty(c, dtype=torch.float64, device="cuda")
+    W = torch.empty(c, c, dtype=torch.float64, device="cuda")
+    p = plans["f64"]
+    rs.rsvd_small_svd(p.handle, dev(T0, torch.float64), Vt, S, W)
+    assert p.status() == rs.RSVD_OK
+    Uo, so, Vo = oracle.svd(T0)
+    oracle.sign_convention(Uo, Vo)
+    Sg, Vg, Wg = host(S), host(Vt), host(W)
+    assert np.all(np.diff(Sg) <= 0)
+    kappa = so[0] / so[-1]
+    assert np.max(np.abs(Sg - so) / so) <= 100 * c * EPS64 * kappa
+    # separated values: columns match up to sign; the sign rule is applied
+    assert np.abs(align_columns(Vg, Uo) - Uo).max() <= 1e-9
+    assert np.abs(align_columns(Wg, Vo) - Vo).max() <= 1e-9
+    assert sign_rule_holds(Vg)
+    assert np.linalg.norm((Vg * Sg) @ Wg.T - T0) <= 100 * c * EPS64 * np.linalg.norm(T0)
+
+
+@pytest.mark.parametrize("n", [2, 7, 64, 200, 257])
+def test_sym_eig_parity(plans, n):
+    announce(f"sym_eig n={n}")
+    rng = np.random.default_rng(n)
+    Qh = synth.haar(rng, n, n)
+    lam_true = np.linspace(3.0, 0.5, n) ** 2
+    G0 = (Qh * lam_true) @ Qh.T
+    G0 = 0.5 * (G0 + G0.T)
+    lam = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    p = plans["f64"]
+    rs.rsvd_sym_eig(p.handle, dev(G0, torch.float64), lam, V)
+    assert p.status() == rs.RSVD_OK
+    lo, Vo, _ = oracle.eig_sym(G0)
+    oracle.sign_convention(None, Vo)
+    lg, Vg = host(lam), host(V)
+    assert np.abs(lg - lo).max() <= 50 * n * EPS64 * lo[0]
+    gap = np.min(np.abs(np.diff(lo))) / lo[0]
+    assert np.abs(align_columns(Vg, Vo) - Vo).max() <= 100 * n * EPS64 / gap
+    assert sign_rule_holds(Vg)
+    assert np.abs(Vg.T @ Vg - np.eye(n)).max() <= 50 * n * EPS64

@@ -81,8 +81,11 @@ const char* rsvd_status_string(int32_t status);
  *   seed      seeds the Gaussian sketch G of rsvd_solve (Philox4x32-10 +
  *             Box-Muller, see rsvd_gaussian_fill)
  *   stream    hipStream_t to order all work on; NULL = the null stream
+ * Limits: l_max <= 96 (the l x l factors live in one workgroup's LDS); with
+ * want_gram, n_max <= 1120 (the eigensolver keeps column blocks in LDS).
  * Errors: RSVD_ERR_ARG (plan NULL, bad dtype, l_max < 1), RSVD_ERR_SHAPE
- * (m_max < n_max or n_max < 1), RSVD_ERR_NOMEM, RSVD_ERR_DEVICE. */
+ * (m_max < n_max, n_max < 1, or a limit above exceeded), RSVD_ERR_NOMEM,
+ * RSVD_ERR_DEVICE. */
 int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_t l_max,
                          int32_t dtype, int32_t want_gram, uint64_t seed, void* stream);
 

@@ -27,7 +27,9 @@ constexpr int kNNBK = 32;                    // k-chunk staged in LDS
 // with one 16-byte load, and matrix-core step t uses element t -- so step t
 // contracts over k = slab + VW*g + t (a permutation of the slab, matched on
 // the X side).  The X chunk (kNNBK x 16*NT) is staged transposed in LDS so a
-// lane reads its VW operands with one 16-byte LDS load.
+// lane reads its VW operands with one 16-byte LDS load.  Chunk c+1 of A and
+// of X is loaded into registers while chunk c is multiplied; X chunks
+// alternate between two LDS buffers (one barrier per chunk).
 template <typename T, int NT, int MR, bool VEC>
 __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
     const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, const T* __restrict__ X,
@@ -41,7 +43,8 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
   constexpr int NS = kNNBK / SLAB;
   constexpr int BC = 16 * NT;
   constexpr int XLD = kNNBK + VW;            // padded, keeps 16-byte alignment
-  __shared__ __attribute__((aligned(16))) T Xt[BC * XLD];
+  constexpr int XE = (kNNBK * BC + kNNThreads - 1) / kNNThreads;
+  __shared__ __attribute__((aligned(16))) T Xt[2][BC * XLD];
   __shared__ double red[kNNThreads / 64];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -51,6 +54,7 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
   const int64_t row0 = rb * (64 * MR) + (int64_t)wave * 16 * MR;
   const int col0 = ct * BC;
   const bool do_ss = (fro2_part != nullptr) && ct == 0;
+  const int nch = (int)((n + kNNBK - 1) / kNNBK);
 
   acc_t acc[MR][NT];
 #pragma unroll
@@ -59,45 +63,83 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
     for (int j = 0; j < NT; ++j) acc[r][j] = acc_t{0, 0, 0, 0};
   double ss = 0.0;
 
-  for (int64_t k0 = 0; k0 < n; k0 += kNNBK) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kNNBK * BC; idx += kNNThreads) {
+  auto load_x = [&](int ch, T(&xr)[XE]) {
+    const int64_t k0 = (int64_t)ch * kNNBK;
+#pragma unroll
+    for (int u = 0; u < XE; ++u) {
+      const int idx = threadIdx.x + u * kNNThreads;
       const int kk = idx / BC, col = idx - kk * BC;
       const int64_t k = k0 + kk;
       const int cc = col0 + col;
-      Xt[col * XLD + kk] = (k < n && cc < c) ? X[k * ldx + cc] : T(0);
+      xr[u] = (idx < kNNBK * BC && k < n && cc < c) ? X[k * ldx + cc] : T(0);
     }
-    __syncthreads();
+  };
+  auto store_x = [&](int buf, const T(&xr)[XE]) {
+#pragma unroll
+    for (int u = 0; u < XE; ++u) {
+      const int idx = threadIdx.x + u * kNNThreads;
+      const int kk = idx / BC, col = idx - kk * BC;
+      if (idx < kNNBK * BC) Xt[buf][col * XLD + kk] = xr[u];
+    }
+  };
+  auto load_a = [&](int ch, T(&a)[NS][MR][VW]) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int64_t kb = k0 + s * SLAB + g * VW;
-      T a[MR][VW];
+      const int64_t kb = (int64_t)ch * kNNBK + s * SLAB + g * VW;
 #pragma unroll
       for (int r = 0; r < MR; ++r) {
         const int64_t row = row0 + 16 * r + lr;
         if (VEC && row < m && kb + VW <= n) {
           const vec_t v = *reinterpret_cast<const vec_t*>(A + row * lda + kb);
 #pragma unroll
-          for (int t = 0; t < VW; ++t) a[r][t] = v[t];
+          for (int t = 0; t < VW; ++t) a[s][r][t] = v[t];
         } else {
 #pragma unroll
           for (int t = 0; t < VW; ++t)
-            a[r][t] = (row < m && kb + t < n) ? A[row * lda + kb + t] : T(0);
+            a[s][r][t] = (row < m && kb + t < n) ? A[row * lda + kb + t] : T(0);
         }
-        if (do_ss) {
+      }
+    }
+  };
+  auto compute = [&](int buf, const T(&a)[NS][MR][VW]) {
 #pragma unroll
-          for (int t = 0; t < VW; ++t) ss += (double)a[r][t] * (double)a[r][t];
-        }
+    for (int s = 0; s < NS; ++s) {
+      if (do_ss) {
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+          for (int t = 0; t < VW; ++t) ss += (double)a[s][r][t] * (double)a[s][r][t];
       }
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        const vec_t b = *reinterpret_cast<const vec_t*>(&Xt[(16 * j + lr) * XLD + s * SLAB + g * VW]);
+        const vec_t b =
+            *reinterpret_cast<const vec_t*>(&Xt[buf][(16 * j + lr) * XLD + s * SLAB + g * VW]);
 #pragma unroll
         for (int t = 0; t < VW; ++t)
 #pragma unroll
-          for (int r = 0; r < MR; ++r) acc[r][j] = M::run(a[r][t], b[t], acc[r][j]);
+          for (int r = 0; r < MR; ++r) acc[r][j] = M::run(a[s][r][t], b[t], acc[r][j]);
       }
     }
+  };
+
+  T xr[XE];
+  T a0[NS][MR][VW], a1[NS][MR][VW];
+  load_x(0, xr);
+  load_a(0, a0);
+  store_x(0, xr);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ch += 2) {
+    const bool has1 = ch + 1 < nch;
+    if (has1) { load_x(ch + 1, xr); load_a(ch + 1, a1); }
+    compute(0, a0);
+    if (has1) store_x(1, xr);
+    __syncthreads();
+    if (!has1) break;
+    const bool has2 = ch + 2 < nch;
+    if (has2) { load_x(ch + 2, xr); load_a(ch + 2, a0); }
+    compute(1, a1);
+    if (has2) store_x(0, xr);
+    __syncthreads();
   }
 
 #pragma unroll
@@ -154,6 +196,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm_tn_partial(
     int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split) {
   typedef Mfma<C> M;
   typedef typename M::acc_t acc_t;
+  constexpr int U = 4;                       // 4-row groups per register set
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x = lane & 15, g = lane >> 4;
   const int64_t split = blockIdx.x;
@@ -170,33 +213,55 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm_tn_partial(
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = acc_t{0, 0, 0, 0};
 
-  for (int64_t r = rs; r < re; r += 4) {
-    const int64_t row = r + g;
-    const bool rok = row < re;
-    C a[VW];
-    bool loaded = false;
-    if constexpr (VEC && VW * sizeof(T) == 16) {
-      if (rok && full_i) {
-        const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(A + row * lda + ia);
+  // rows [r, r + 16): lane (x, g) takes rows r + 4u + g, u < U
+  auto load = [&](int64_t r, T(&a)[U][VW], T(&b)[U][NT]) {
 #pragma unroll
-        for (int t = 0; t < VW; ++t) a[t] = (C)v[t];
-        loaded = true;
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = r + 4 * u + g;
+      const bool rok = row < re;
+      bool loaded = false;
+      if constexpr (VEC && VW * sizeof(T) == 16) {
+        if (rok && full_i) {
+          const typename Vec16<T>::type v =
+              *reinterpret_cast<const typename Vec16<T>::type*>(A + row * lda + ia);
+#pragma unroll
+          for (int t = 0; t < VW; ++t) a[u][t] = v[t];
+          loaded = true;
+        }
+      }
+      if (!loaded) {
+#pragma unroll
+        for (int t = 0; t < VW; ++t) a[u][t] = (rok && ia + t < n) ? A[row * lda + ia + t] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int col = j0 + 16 * j + x;
+        b[u][j] = (rok && col < c) ? Q[row * ldq + col] : T(0);
       }
     }
-    if (!loaded) {
+  };
+  auto compute = [&](const T(&a)[U][VW], const T(&b)[U][NT]) {
 #pragma unroll
-      for (int t = 0; t < VW; ++t) a[t] = (rok && ia + t < n) ? (C)A[row * lda + ia + t] : C(0);
-    }
-    C b[NT];
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int col = j0 + 16 * j + x;
-      b[j] = (rok && col < c) ? (C)Q[row * ldq + col] : C(0);
-    }
+      for (int t = 0; t < VW; ++t)
 #pragma unroll
-    for (int t = 0; t < VW; ++t)
-#pragma unroll
-      for (int j = 0; j < NT; ++j) acc[t][j] = M::run(a[t], b[j], acc[t][j]);
+        for (int j = 0; j < NT; ++j) acc[t][j] = M::run((C)a[u][t], (C)b[u][j], acc[t][j]);
+  };
+
+  T a0[U][VW], b0[U][NT], a1[U][VW], b1[U][NT];
+  int64_t r = rs;
+  load(r, a0, b0);
+  while (true) {
+    const bool has1 = r + 4 * U < re;
+    if (has1) load(r + 4 * U, a1, b1);
+    compute(a0, b0);
+    if (!has1) break;
+    const bool has2 = r + 8 * U < re;
+    if (has2) load(r + 8 * U, a0, b0);
+    compute(a1, b1);
+    if (!has2) break;
+    r += 8 * U;
   }
 
   double* Ps = P + split * n * (int64_t)c;
@@ -246,13 +311,143 @@ hipError_t tn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// FP64 Gram matrix W = Y^T Y of a tall m x c panel (c <= 16*NT), the first
+// step of each CholeskyQR pass.  Every product of two stored values is exact
+// in FP64 (and for fp32 data the sum is accumulated in FP64), so the Gram
+// keeps the accuracy CholeskyQR needs.  Wave w of a block takes the row
+// groups w, w + WAVES, ... (4 rows each) of the block's row range; lane
+// (x, g) loads Y[r + g][16 J + x] for every column tile J, and the FP64
+// matrix core accumulates the upper-triangle tile pairs (I <= J) only.  The
+// waves' sums are added in LDS in wave order and the block writes its
+// symmetric partial P[block] (c x c).
+constexpr int kGramWaves = 8;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64(const T* __restrict__ Y, int64_t m,
+                                                            int c, int64_t ldy,
+                                                            double* __restrict__ P,
+                                                            int64_t rows_per_block) {
+  typedef Mfma<double> M;
+  constexpr int NP = NT * (NT + 1) / 2;
+  constexpr int U = 2;                       // 4-row groups per register set
+  constexpr int64_t STEP = (int64_t)4 * kGramWaves * U;
+  extern __shared__ double red[];            // c x c
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t rs = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = (rs + rows_per_block < m) ? rs + rows_per_block : m;
+  f64x4 acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = f64x4{0, 0, 0, 0};
+  bool colok[NT];
+#pragma unroll
+  for (int J = 0; J < NT; ++J) colok[J] = (16 * J + x) < c;
+
+  // row group u of the set starting at r0: rows r0 + 4*kGramWaves*u + g
+  auto load = [&](int64_t r0, T(&y)[U][NT]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = r0 + (int64_t)4 * kGramWaves * u + g;
+      const bool rok = row < re;
+#pragma unroll
+      for (int J = 0; J < NT; ++J) y[u][J] = (rok && colok[J]) ? Y[row * ldy + 16 * J + x] : T(0);
+    }
+  };
+  auto compute = [&](const T(&y)[U][NT]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double yd[NT];
+#pragma unroll
+      for (int J = 0; J < NT; ++J) yd[J] = (double)y[u][J];
+      int idx = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+          acc[idx] = M::run(yd[I], yd[J], acc[idx]);
+          ++idx;
+        }
+    }
+  };
+
+  T y0[U][NT], y1[U][NT];
+  int64_t r = rs + 4 * wave;
+  load(r, y0);
+  while (r < re) {
+    const bool has1 = r + STEP < re;
+    if (has1) load(r + STEP, y1);
+    compute(y0);
+    if (!has1) break;
+    const bool has2 = r + 2 * STEP < re;
+    if (has2) load(r + 2 * STEP, y0);
+    compute(y1);
+    if (!has2) break;
+    r += 2 * STEP;
+  }
+  // fixed-order reduction of the waves' tiles in LDS
+  for (int w = 0; w < kGramWaves; ++w) {
+    if (wave == w) {
+      int idx = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = 16 * I + M::row(lane, e), j = 16 * J + x;
+            if (i < c && j < c) {
+              const double v = acc[idx][e];
+              red[i * c + j] = (w == 0) ? v : red[i * c + j] + v;
+            }
+          }
+          ++idx;
+        }
+    }
+    __syncthreads();
+  }
+  // symmetric partial: the upper tiles hold W[i][j] for tile(i) <= tile(j)
+  double* Pb = P + (int64_t)blockIdx.x * c * c;
+  for (int idx = threadIdx.x; idx < c * c; idx += kGramWaves * 64) {
+    const int i = idx / c, j = idx - i * c;
+    Pb[idx] = ((i >> 4) <= (j >> 4)) ? red[i * c + j] : red[j * c + i];
+  }
+}
+
+template <typename T, int NT>
+hipError_t gram_dispatch(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
+                         int* nsplit, hipStream_t s) {
+  int64_t blocks = (m + 255) / 256;          // at least 256 rows per block
+  if (blocks > max_split) blocks = max_split;
+  if (blocks < 1) blocks = 1;
+  int64_t rpb = (m + blocks - 1) / blocks;
+  rpb = (rpb + 3) / 4 * 4;
+  blocks = (m + rpb - 1) / rpb;
+  *nsplit = (int)blocks;
+  const size_t shmem = (size_t)c * c * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gram_f64<T, NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gram_f64<T, NT>), dim3((unsigned)blocks), dim3(kGramWaves * 64), shmem, s,
+                     Y, m, c, ldy, P, rpb);
+  return hipGetLastError();
+}
+
 __global__ void k_reduce_partials(const double* __restrict__ P, int nsplit, int64_t rows,
                                   int64_t cols, double* __restrict__ Z, int64_t ldz) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = rows * cols;
   if (idx >= total) return;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += P[(int64_t)k * total + idx];
+  int k = 0;
+  for (; k + 8 <= nsplit; k += 8) {          // eight loads in flight, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)(k + u) * total + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; k < nsplit; ++k) s += P[(int64_t)k * total + idx];
   const int64_t i = idx / cols, j = idx - i * cols;
   Z[i * ldz + j] = s;
 }
@@ -321,6 +516,21 @@ hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda,
 #undef RSVD_TN
 }
 
+template <typename T>
+hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
+                           int* nsplit, hipStream_t s) {
+  if (m <= 0 || c <= 0) { *nsplit = 0; return hipSuccess; }
+  switch ((c + 15) / 16) {
+    case 1: return gram_dispatch<T, 1>(Y, m, c, ldy, P, max_split, nsplit, s);
+    case 2: return gram_dispatch<T, 2>(Y, m, c, ldy, P, max_split, nsplit, s);
+    case 3: return gram_dispatch<T, 3>(Y, m, c, ldy, P, max_split, nsplit, s);
+    case 4: return gram_dispatch<T, 4>(Y, m, c, ldy, P, max_split, nsplit, s);
+    case 5: return gram_dispatch<T, 5>(Y, m, c, ldy, P, max_split, nsplit, s);
+    case 6: return gram_dispatch<T, 6>(Y, m, c, ldy, P, max_split, nsplit, s);
+    default: return hipErrorInvalidValue;   // c <= 96 (the plan's l limit)
+  }
+}
+
 hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,
                                   double* Z, int64_t ldz, hipStream_t s) {
   const int64_t total = rows * cols;
@@ -341,6 +551,10 @@ template hipError_t launch_gemm_nn<float>(const float*, int64_t, int64_t, int64_
 template hipError_t launch_gemm_nn<double>(const double*, int64_t, int64_t, int64_t,
                                            const double*, int64_t, int, double*, int64_t, double*,
                                            int*, hipStream_t);
+template hipError_t launch_gram_f64<float>(const float*, int64_t, int, int64_t, double*, int64_t,
+                                           int*, hipStream_t);
+template hipError_t launch_gram_f64<double>(const double*, int64_t, int, int64_t, double*, int64_t,
+                                            int*, hipStream_t);
 template hipError_t launch_gemm_tn_partial<float, float>(const float*, int64_t, int64_t, int64_t,
                                                          const float*, int64_t, int, double*,
                                                          int64_t, int*, hipStream_t);

@@ -166,8 +166,7 @@ struct Path {
   // Wout (c x c) = Y^T Y with exact FP64 products, fixed-order reduction.
   hipError_t gram(const T* Y, int64_t m, int c, int64_t ldy, double* Wout) {
     int ns = 0;
-    hipError_t e = launch_gemm_tn_partial<T, double>(Y, m, c, ldy, Y, ldy, c, p->part, p->max_split,
-                                                     &ns, s);
+    hipError_t e = launch_gram_f64<T>(Y, m, c, ldy, p->part, p->max_split, &ns, s);
     if (e != hipSuccess) return e;
     return launch_reduce_partials(p->part, ns, c, c, Wout, c, s);
   }
@@ -206,18 +205,21 @@ hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, doubl
                                 nullptr, p->stream);
 }
 
-// Thin SVD of the FP64 matrix Tm (r x c): Tm = Qt R (CholeskyQR2), one-sided
-// Jacobi R J = Uo diag(Su), so Tm = (Qt Uo) diag(Su) J^T: V~ = Qt Uo, W = J.
-// Leaves V~ unsorted in p->Vt, the values in p->Su and J in p->Jm.
+// Thin SVD of the FP64 matrix Tm (r x c): Tm = Qt R (CholeskyQR2), then
+// one-sided Jacobi on R^T (QR-preconditioned Jacobi in the manner of Drmac &
+// Veselic, SIAM J. Matrix Anal. Appl. 2008: the columns of R^T are already
+// close to orthogonal, so few sweeps are needed): R^T J = Uo diag(Su), so
+// R = J diag(Su) Uo^T and Tm = (Qt J) diag(Su) Uo^T: V~ = Qt J, W = Uo.
+// Leaves V~ unsorted in p->Vt, the values in p->Su and W in p->Uo.
 hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c) {
   hipError_t e;
   if ((e = cqr2_small(p, Tm, r, c, p->Zq)) != hipSuccess) return e;
   if ((e = launch_small_gemm<double>(p->R2s, p->R1s, c, c, c, p->Rt, nullptr, p->stream)) != hipSuccess)
     return e;
-  if ((e = launch_jacobi_svd_small(p->Rt, c, p->Uo, p->Su, p->Jm, p->diag, p->status, p->stream)) !=
-      hipSuccess)
+  if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, p->diag, p->status,
+                                   p->stream)) != hipSuccess)
     return e;
-  return launch_small_gemm<double>(p->Zq, p->Uo, r, c, c, p->Vt, nullptr, p->stream);
+  return launch_small_gemm<double>(p->Zq, p->Jm, r, c, c, p->Vt, nullptr, p->stream);
 }
 
 template <typename T>
@@ -256,7 +258,7 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));
   // step 6: T = V~ S~ W^T
   RSVD_CHECK(small_svd_unsorted(p, p->Z2, n, l));
-  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Su, l, p->Vt, n, l, 1, p->Jm, k, S, V, ldv, nullptr,
+  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Su, l, p->Vt, n, l, 1, p->Uo, k, S, V, ldv, nullptr,
                                          p->Wk, s));
   // step 7: U~ = Q W = Q1 (R2^-1 W), first k columns
   RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s));
@@ -348,6 +350,7 @@ int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_
   if (l_max < 1) return RSVD_ERR_ARG;
   if (n_max < 1 || m_max < n_max) return RSVD_ERR_SHAPE;
   if (l_max > kMaxL) return RSVD_ERR_SHAPE;
+  if (want_gram && n_max > jacobi_eig_max_n()) return RSVD_ERR_SHAPE;
   rsvd_plan_s* p = new (std::nothrow) rsvd_plan_s();
   if (!p) return RSVD_ERR_NOMEM;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RSVD_ERR_DEVICE; }
@@ -525,7 +528,7 @@ int32_t rsvd_small_svd(rsvd_plan_t plan, const double* T, int64_t r, int32_t c, 
   if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
   RSVD_CHECK(reset(plan));
   RSVD_CHECK(small_svd_unsorted(plan, T, r, c));
-  RSVD_CHECK(launch_sort_sign_scatter<double>(plan->Su, c, plan->Vt, r, c, 1, plan->Jm, c, S,
+  RSVD_CHECK(launch_sort_sign_scatter<double>(plan->Su, c, plan->Vt, r, c, 1, plan->Uo, c, S,
                                               nullptr, 0, Vt, W, plan->stream));
   return RSVD_OK;
 }

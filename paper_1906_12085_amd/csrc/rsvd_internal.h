@@ -52,6 +52,12 @@ hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda,
                                   int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
                                   hipStream_t s);
 
+// Symmetric partial Gram matrices P[s] (c x c, FP64) of a tall m x c panel Y,
+// accumulated in FP64 from exact products (c <= 96).
+template <typename T>
+hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
+                           int* nsplit, hipStream_t s);
+
 // Z (rows x cols) = sum over s < nsplit of P[s] (each rows x cols), fixed order.
 hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,
                                   double* Z, int64_t ldz, hipStream_t s);
@@ -85,11 +91,12 @@ template <typename T>
 hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1, int c2,
                              double* C, T* CT, hipStream_t s);
 
-// One-sided Jacobi SVD of a c x c FP64 matrix M (ld = c), in one workgroup:
-// M J = Uo diag(S) with J orthogonal; writes Uo (c x c), S (c), J (c x c),
-// all unsorted; sweeps used and final off-diagonal measure to diag[0..1].
-hipError_t launch_jacobi_svd_small(const double* M, int c, double* Uo, double* S, double* J,
-                                   double* diag, int32_t* status, hipStream_t s);
+// One-sided Jacobi SVD of a c x c FP64 matrix M (ld = c, c <= 96), in one
+// workgroup, on M itself or (transpose != 0) on M^T =: N:  N J = Uo diag(S)
+// with J orthogonal; writes Uo (c x c), S (c), J (c x c), all unsorted;
+// sweeps used and final off-diagonal measure to diag[2..3].
+hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
+                                   double* J, double* diag, int32_t* status, hipStream_t s);
 
 // One-sided Jacobi on the columns of a symmetric n x n FP64 matrix (its
 // eigen-decomposition): X <- X J until the columns are orthogonal; then
@@ -128,5 +135,7 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
 // Number of int32 words launch_jacobi_eig needs in `flags`.
 int jacobi_eig_flag_words();
+// Largest n the Jacobi eigensolver supports (columns in LDS, blocks resident).
+int64_t jacobi_eig_max_n();
 
 }  // namespace rsvd

@@ -17,6 +17,23 @@ constexpr double kEps = 2.220446049250313e-16;
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code) { atomicMin(status, code); }
 __device__ __forceinline__ void set_warning(int32_t* status, int32_t code) { atomicCAS(status, 0, code); }
 
+// Copy `count` doubles from global memory into LDS with the whole block; each
+// thread issues eight independent loads before its eight LDS stores, so the
+// memory latency is paid once per eight elements rather than per element.
+__device__ __forceinline__ void stage_to_lds(double* dst, const double* __restrict__ src,
+                                             int count) {
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * step < count; i += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[i + u * step];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[i + u * step] = v[u];
+  }
+  for (; i < count; i += step) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC 2011): ten rounds; each
 // multiplies words 0 and 2 by the two round constants and mixes the high
@@ -64,12 +81,18 @@ __global__ void k_cast(const S* __restrict__ src, int64_t rows, int64_t cols, in
 
 // ---------------------------------------------------------------------------
 // Cholesky W = R^T R (R upper, positive diagonal) and Rinv = R^-1, one block,
-// both c x c matrices in LDS (row stride c + 1).  Right-looking elimination
-// with one barrier per step: at step j every thread updates the trailing
-// entries (i, i2), j < i <= i2, with W[j][i] W[j][i2] / W[j][j], which needs
-// only the (already final) row j.  The inverse solves R X = I from the last
-// row up in the same way (B <- B - R[i][k] B[k][:] / R[k][k]).
-constexpr int kCholThreads = 256;
+// both c x c (c <= 96) in LDS.  Phase 1, symmetric Gaussian elimination
+// without pivoting (stable for a positive definite W): step j subtracts
+// (a_ij / a_jj) times row j from every row i > j, leaving D L^T (W = L D L^T)
+// in the upper triangle; scaling row i by 1/sqrt(d_i) gives R.  Phase 2, R X
+// = I by right-looking back substitution: step k (from the last row up)
+// subtracts R[i][k] X[k][:] from the rows i < k (X[k][:] = B[k][:] / R[k][k]
+// is final), which keeps Rinv accurate relative to the computed R.  In both
+// phases the columns that change at a step are assigned one per thread slot
+// with a fixed stride of rows, and each step ends with one barrier.
+constexpr int kCholThreads = 1024;
+constexpr int kCholMaxC = 96;
+constexpr int kCholRows = 10;                // rows per thread per step: ceil(96 / (1024/96))
 
 template <typename T>
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ W, int c,
@@ -79,33 +102,43 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
                                                            int32_t* __restrict__ status) {
   extern __shared__ double sm[];
   const int ld = c + 1;
-  double* L = sm;             // c x c, upper triangle used
-  double* B = sm + c * ld;    // c x c
-  double* dg = sm + 2 * c * ld;  // sqrt of the pivots
-  __shared__ int bad;
+  double* L = sm;                            // c x c (ld), becomes R
+  double* B = sm + (size_t)c * ld;           // c x c (ld), becomes R^-1 * diag(R)
+  __shared__ double dg[kCholMaxC];
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
   for (int idx = tid; idx < c * c; idx += kCholThreads) {
     const int i = idx / c, j = idx - i * c;
     L[i * ld + j] = 0.5 * (W[i * c + j] + W[j * c + i]);
     B[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  const int rpp = kCholThreads / c;          // rows per pass, >= 10 for c <= 96
+  const int a = tid % c, r0 = tid / c;       // column slot, first row offset
+  const bool active = r0 < rpp;
+  bool bad = false;
   for (int j = 0; j < c; ++j) {
     const double d = L[j * ld + j];
-    if (!(d > 0.0)) {           // also catches NaN
-      if (tid == 0) bad = 1;
-      break;
-    }
-    const double inv_d = 1.0 / d;
-    const int nt = c - 1 - j;   // trailing size
-    for (int idx = tid; idx < nt * nt; idx += kCholThreads) {
-      const int i = j + 1 + idx / nt, i2 = j + 1 + idx % nt;
-      if (i2 >= i) L[i * ld + i2] -= L[j * ld + i] * L[j * ld + i2] * inv_d;
+    if (!(d > 0.0)) { bad = true; break; }   // uniform: every thread reads the same d
+    const int col = j + 1 + a;               // columns j+1..c-1 change
+    if (active && col < c) {
+      const double pr = L[j * ld + col] / d;
+      // all reads first, then all writes: the LDS latency is paid once per step.
+      // Multiplier a_ij / a_jj from the (updated) upper entry a_ji of row j.
+      double x[kCholRows], f[kCholRows];
+#pragma unroll
+      for (int u = 0; u < kCholRows; ++u) {
+        const int i = j + 1 + r0 + u * rpp;
+        x[u] = (i <= col) ? L[i * ld + col] : 0.0;
+        f[u] = (i <= col) ? L[j * ld + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCholRows; ++u) {
+        const int i = j + 1 + r0 + u * rpp;
+        if (i <= col) L[i * ld + col] = x[u] - f[u] * pr;
+      }
     }
     __syncthreads();
   }
-  __syncthreads();
   if (bad) {
     // R = 0 (no factor), Rinv = I keeps the later products finite
     for (int idx = tid; idx < c * c; idx += kCholThreads) {
@@ -118,32 +151,37 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
   }
-  // R[i][j] = L[i][j] / sqrt(L[i][i]) for j >= i (pivots read before any write)
   for (int i = tid; i < c; i += kCholThreads) dg[i] = sqrt(L[i * ld + i]);
   __syncthreads();
   for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, j = idx - i * c;
-    L[i * ld + j] = (j >= i) ? L[i * ld + j] / dg[i] : 0.0;
+    const int i = idx / c, k = idx - i * c;
+    const double v = (k >= i) ? L[i * ld + k] / dg[i] : 0.0;
+    L[i * ld + k] = v;                       // each entry rewritten by its own reader
+    R[idx] = v;
   }
   __syncthreads();
-  for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, j = idx - i * c;
-    R[idx] = L[i * ld + j];
-  }
-  // back substitution for X = R^-1, rows from the bottom: after step k, row k
-  // of B divided by R[k][k] is row k of X.
   for (int k = c - 1; k >= 1; --k) {
-    const double rkk = L[k * ld + k];
-    const int w = c - k;        // columns j >= k
-    for (int idx = tid; idx < k * w; idx += kCholThreads) {
-      const int i = idx / w, j = k + idx % w;
-      B[i * ld + j] -= L[i * ld + k] * B[k * ld + j] / rkk;
+    const int col = k + a;                   // columns k..c-1 of the rows above k change
+    if (active && col < c) {
+      const double xk = B[k * ld + col] / L[k * ld + k];
+      double x[kCholRows], f[kCholRows];
+#pragma unroll
+      for (int u = 0; u < kCholRows; ++u) {
+        const int i = r0 + u * rpp;
+        x[u] = (i < k) ? B[i * ld + col] : 0.0;
+        f[u] = (i < k) ? L[i * ld + k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCholRows; ++u) {
+        const int i = r0 + u * rpp;
+        if (i < k) B[i * ld + col] = x[u] - f[u] * xk;
+      }
     }
     __syncthreads();
   }
   for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, j = idx - i * c;
-    const double v = (j >= i) ? B[i * ld + j] / L[i * ld + i] : 0.0;
+    const int i = idx / c, k = idx - i * c;
+    const double v = (k >= i) ? B[i * ld + k] / L[i * ld + i] : 0.0;
     Rinv[idx] = v;
     if (RinvT) RinvT[idx] = (T)v;
   }
@@ -188,30 +226,67 @@ __device__ __forceinline__ void jacobi_cs(double alpha, double beta, double gamm
   *sn = *cs * t;
 }
 
-// One-sided Jacobi SVD of a c x c matrix in one block, both the matrix and
-// the accumulated rotations J held column-major in LDS.  A group of G lanes
-// (G | 64) owns one column pair per step.
-constexpr int kJsThreads = 1024;
+// Sum over the G consecutive lanes of this lane's group (G = 16, 32 or 64,
+// groups aligned to G).  Within a 16-lane row: quad_perm swaps (lanes l^1,
+// l^2) and row rotations by 4 and 8 (DPP), then every lane takes lane
+// (l & 16)'s value (ds_swizzle) so all lanes of the row hold the same bits;
+// larger groups add the partner row / half-wave symmetrically.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int PAT>
+__device__ __forceinline__ double swizzle(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PAT);
+  return __hiloint2double(hi, lo);
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 16 || G == 32 || G == 64, "group of 16, 32 or 64 lanes");
+  v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1): quad sum
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x128>(v);   // row_ror:8: row sum (association differs by quad)
+  v = swizzle<0x0010>(v);   // broadcast lane (l & 16): identical bits in the row
+  if (G >= 32) v += swizzle<0x401F>(v);   // xor 16
+  if (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
+// M and of the accumulated rotations J held column-major in LDS.  Each group
+// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
+// pair's entries in registers (6 rows per lane), reduces the three inner
+// products with group_sum, rotates and writes back.  With transpose != 0 the
+// kernel works on M^T (the rows of Min are its columns).
+constexpr int kJsG = 16;
+constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
 constexpr int kJsMaxSweeps = 60;
 
-__global__ __launch_bounds__(kJsThreads) void k_jacobi_svd_small(
-    const double* __restrict__ Min, int c, double* __restrict__ Uo, double* __restrict__ S,
-    double* __restrict__ Jout, double* __restrict__ diag, int32_t* __restrict__ status, int G) {
+__global__ __launch_bounds__(768) void k_jacobi_svd_small(
+    const double* __restrict__ Min, int c, int transpose, double* __restrict__ Uo,
+    double* __restrict__ S, double* __restrict__ Jout, double* __restrict__ diag,
+    int32_t* __restrict__ status) {
   extern __shared__ double sm[];
   const int npad = c + (c & 1);
   double* Mc = sm;                   // column j at Mc + j*c
   double* Jc = sm + (size_t)npad * c;
   __shared__ int rotated;
   __shared__ double offmax;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < c * c; idx += kJsThreads) {
-    const int i = idx / c, j = idx - i * c;   // Min row-major (i, j) -> column j
-    Mc[j * c + i] = Min[idx];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int idx = tid; idx < c * c; idx += nthr) {
+    const int i = idx / c, j = idx - i * c;   // Min row-major (i, j)
+    const double v = Min[idx];
+    if (transpose) Mc[i * c + j] = v;        // column i of M^T is row i of Min
+    else Mc[j * c + i] = v;
     Jc[j * c + i] = (i == j) ? 1.0 : 0.0;
   }
   const int npairs = npad / 2;
-  const int grp = tid / G, gl = tid % G;
-  const double tol = kEps * sqrt((double)c);
+  const int grp = tid / kJsG, gl = tid % kJsG;
+  const double tol = kEps * (double)c;
   int sweep = 0;
   bool converged = false;
   double last_off = 0.0;
@@ -220,43 +295,50 @@ __global__ __launch_bounds__(kJsThreads) void k_jacobi_svd_small(
     if (tid == 0) { rotated = 0; offmax = 0.0; }
     __syncthreads();
     for (int s = 0; s < npad - 1; ++s) {
-      for (int pk = grp; pk < npairs; pk += kJsThreads / G) {
-        int p, q;
-        rr_pair(s, pk, npad, &p, &q);
-        if (q >= c) continue;           // the padding index of odd c
+      int p = 0, q = c;
+      if (grp < npairs) rr_pair(s, grp, npad, &p, &q);
+      if (grp < npairs && q < c) {           // uniform within the 16-lane group
         double* xp = Mc + (size_t)p * c;
         double* xq = Mc + (size_t)q * c;
+        double a[kJsRows], b[kJsRows];
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < c; i += G) {
-          const double a = xp[i], b = xq[i];
-          al += a * a; be += b * b; ga += a * b;
+#pragma unroll
+        for (int u = 0; u < kJsRows; ++u) {
+          const int i = gl + kJsG * u;
+          a[u] = (i < c) ? xp[i] : 0.0;
+          b[u] = (i < c) ? xq[i] : 0.0;
+          al += a[u] * a[u]; be += b[u] * b[u]; ga += a[u] * b[u];
         }
-        for (int off = G / 2; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off);
-          be += __shfl_xor(be, off);
-          ga += __shfl_xor(ga, off);
-        }
+        al = group_sum<kJsG>(al);
+        be = group_sum<kJsG>(be);
+        ga = group_sum<kJsG>(ga);
         const double scale = sqrt(al) * sqrt(be);
-        const double rel = scale > 0.0 ? fabs(ga) / scale : 0.0;
-        if (ga != 0.0 && rel > tol) {
+        if (ga != 0.0 && fabs(ga) > tol * scale) {
           double cs, sn;
           jacobi_cs(al, be, ga, &cs, &sn);
-          for (int i = gl; i < c; i += G) {
-            const double a = xp[i], b = xq[i];
-            xp[i] = cs * a - sn * b;
-            xq[i] = sn * a + cs * b;
-          }
           double* jp = Jc + (size_t)p * c;
           double* jq = Jc + (size_t)q * c;
-          for (int i = gl; i < c; i += G) {
-            const double a = jp[i], b = jq[i];
-            jp[i] = cs * a - sn * b;
-            jq[i] = sn * a + cs * b;
+          double ja[kJsRows], jb[kJsRows];   // all reads before any write
+#pragma unroll
+          for (int u = 0; u < kJsRows; ++u) {
+            const int i = gl + kJsG * u;
+            ja[u] = (i < c) ? jp[i] : 0.0;
+            jb[u] = (i < c) ? jq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kJsRows; ++u) {
+            const int i = gl + kJsG * u;
+            if (i < c) {
+              xp[i] = cs * a[u] - sn * b[u];
+              xq[i] = sn * a[u] + cs * b[u];
+              jp[i] = cs * ja[u] - sn * jb[u];
+              jq[i] = sn * ja[u] + cs * jb[u];
+            }
           }
           if (gl == 0) {
             rotated = 1;
-            // benign race: any writer's value is a valid lower bound
-            if (rel > offmax) offmax = rel;
+            const double rel = fabs(ga) / scale;
+            if (rel > offmax) offmax = rel;   // diagnostic only (benign race)
           }
         }
       }
@@ -269,11 +351,11 @@ __global__ __launch_bounds__(kJsThreads) void k_jacobi_svd_small(
     if (done) { converged = true; break; }
   }
   // singular values = column norms, Uo = normalised columns
-  for (int j = tid / 64; j < c; j += kJsThreads / 64) {
+  for (int j = tid / 64; j < c; j += nthr / 64) {
     const int lane = tid & 63;
     double s2 = 0.0;
     for (int i = lane; i < c; i += 64) s2 += Mc[(size_t)j * c + i] * Mc[(size_t)j * c + i];
-    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+    s2 = group_sum<64>(s2);
     const double nrm = sqrt(s2);
     if (lane == 0) S[j] = nrm;
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
@@ -291,24 +373,31 @@ __global__ __launch_bounds__(kJsThreads) void k_jacobi_svd_small(
 
 // ---------------------------------------------------------------------------
 // Jacobi eigensolver of the A^T A route: one-sided Jacobi on the columns of
-// the symmetric matrix X (column j at X + j*n), rotations accumulated in J.
-// Every wave owns one column pair per step; the steps of a sweep are
-// separated by a grid barrier (cooperative launch, all blocks resident).
-// The barrier spin is bounded: on timeout the kernel records an error and
-// every block leaves.
-constexpr int kJeThreads = 256;
+// the symmetric matrix X (column j at X + j*n, X J orthogonalised until
+// X J = W diag(lambda)), rotations accumulated in J.  Block form: the n
+// columns are cut into blocks of b; each workgroup takes one pair of blocks
+// per step (round-robin over the blocks), copies their 2b columns of X and J
+// into LDS, performs one inner sweep over all column pairs of the 2b (b
+// disjoint pairs per round, tpp lanes per pair), and writes them back.  The
+// steps of a sweep are separated by a grid barrier (cooperative launch); the
+// sweep loop ends when a sweep rotates nothing.  The barrier spin is
+// bounded: on timeout the kernel records an error and every block leaves.
 constexpr int kJeMaxSweeps = 40;
 constexpr long kSpinLimit = 1L << 22;
 
+
+// All threads of every block call this; thread 0 publishes the block's
+// global writes (agent-scope release after the workgroup barrier) and
+// acquires the others' before the block continues.
 __device__ __forceinline__ bool grid_barrier(int32_t* counter, int32_t* abort_flag, int target) {
-  __threadfence();
-  __syncthreads();
   __shared__ int ok;
+  __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           ++spins > kSpinLimit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -317,72 +406,119 @@ __device__ __forceinline__ bool grid_barrier(int32_t* counter, int32_t* abort_fl
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __threadfence();
   }
   __syncthreads();
-  __threadfence();
   return ok != 0;
 }
 
 // flags[0] = barrier counter, flags[1] = abort flag, flags[2 + sweep] =
-// rotations counted in that sweep (all zeroed by the host before launch).
-__global__ __launch_bounds__(kJeThreads) void k_jacobi_eig(double* __restrict__ X,
-                                                           double* __restrict__ J, int64_t n,
-                                                           double* __restrict__ lam,
-                                                           double* __restrict__ diag,
-                                                           int32_t* __restrict__ flags,
-                                                           int32_t* __restrict__ status) {
-  const int lane = threadIdx.x & 63;
-  const int wpb = kJeThreads / 64;
-  const int gwave = blockIdx.x * wpb + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * wpb;
-  const int npad = (int)(n + (n & 1));
-  const int npairs = npad / 2;
-  const double tol = kEps * sqrt((double)n);
+// rotations counted in that sweep (all zeroed before launch).  TPP lanes own
+// one column pair in a round; each keeps RPT rows of the two X columns and
+// the two J columns in registers while it rotates them.
+template <int TPP, int RPT>
+__global__ __launch_bounds__(256) void k_jacobi_eig(double* __restrict__ X, double* __restrict__ J, int64_t n, int b,
+                             int nbp, double* __restrict__ lam, double* __restrict__ diag,
+                             int32_t* __restrict__ flags, int32_t* __restrict__ status) {
+  extern __shared__ double sm[];
+  const int m2 = 2 * b;
+  const int ni = (int)n;
+  double* Xl = sm;
+  double* Jl = sm + (size_t)m2 * ni;
+  __shared__ int rot_local;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int pk = tid / TPP, tl = tid % TPP;
+  const double tol = kEps * (double)n;
   int32_t* counter = flags;
   int32_t* abort_flag = flags + 1;
-  int bar = 0;
-  int sweep = 0;
+  int bar = 0, sweep = 0, sweep_rot = 0;
   bool converged = false, aborted = false;
   while (sweep < kJeMaxSweeps && !aborted) {
-    int local = 0;
-    for (int s = 0; s < npad - 1 && !aborted; ++s) {
-      for (int pk = gwave; pk < npairs; pk += nwaves) {
-        int p, q;
-        rr_pair(s, pk, npad, &p, &q);
-        if (q >= n) continue;
-        double* xp = X + (int64_t)p * n;
-        double* xq = X + (int64_t)q * n;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int64_t i = lane; i < n; i += 64) {
-          const double a = xp[i], b = xq[i];
-          al += a * a; be += b * b; ga += a * b;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off);
-          be += __shfl_xor(be, off);
-          ga += __shfl_xor(ga, off);
-        }
-        const double scale = sqrt(al) * sqrt(be);
-        if (ga != 0.0 && scale > 0.0 && fabs(ga) > tol * scale) {
-          double cs, sn;
-          jacobi_cs(al, be, ga, &cs, &sn);
-          for (int64_t i = lane; i < n; i += 64) {
-            const double a = xp[i], b = xq[i];
-            xp[i] = cs * a - sn * b;
-            xq[i] = sn * a + cs * b;
+    sweep_rot = 0;
+    for (int s = 0; s < nbp - 1 && !aborted; ++s) {
+      int I, Jb;
+      rr_pair(s, blockIdx.x, nbp, &I, &Jb);
+      {
+        // the 2b columns of X and J, sixteen independent loads in flight per thread
+        const int tot = m2 * ni;
+        for (int e0 = tid; e0 < tot; e0 += 8 * nthr) {
+          double vx[8], vj[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * nthr;
+            vx[u] = 0.0; vj[u] = 0.0;
+            if (e < tot) {
+              const int lc = e / ni, i = e - lc * ni;
+              const int64_t gc = (lc < b) ? (int64_t)I * b + lc : (int64_t)Jb * b + (lc - b);
+              if (gc < n) { vx[u] = X[gc * n + i]; vj[u] = J[gc * n + i]; }
+            }
           }
-          double* jp = J + (int64_t)p * n;
-          double* jq = J + (int64_t)q * n;
-          for (int64_t i = lane; i < n; i += 64) {
-            const double a = jp[i], b = jq[i];
-            jp[i] = cs * a - sn * b;
-            jq[i] = sn * a + cs * b;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * nthr;
+            if (e < tot) { Xl[e] = vx[u]; Jl[e] = vj[u]; }
           }
-          ++local;
         }
       }
-      if (s == npad - 2 && lane == 0 && local > 0)
-        __hip_atomic_fetch_add(&flags[2 + sweep], local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) rot_local = 0;
+      __syncthreads();
+      for (int r = 0; r < m2 - 1; ++r) {
+        if (pk < b) {                        // uniform within the TPP-lane group
+          int p, q;
+          rr_pair(r, pk, m2, &p, &q);
+          double* xp = Xl + (size_t)p * ni;
+          double* xq = Xl + (size_t)q * ni;
+          double a[RPT], c2[RPT];
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int i = tl + TPP * u;
+            a[u] = (i < ni) ? xp[i] : 0.0;
+            c2[u] = (i < ni) ? xq[i] : 0.0;
+            al += a[u] * a[u]; be += c2[u] * c2[u]; ga += a[u] * c2[u];
+          }
+          al = group_sum<TPP>(al);
+          be = group_sum<TPP>(be);
+          ga = group_sum<TPP>(ga);
+          const double scale = sqrt(al) * sqrt(be);
+          if (ga != 0.0 && scale > 0.0 && fabs(ga) > tol * scale) {
+            double cs, sn;
+            jacobi_cs(al, be, ga, &cs, &sn);
+            double* jp = Jl + (size_t)p * ni;
+            double* jq = Jl + (size_t)q * ni;
+            double ja[RPT], jb[RPT];         // all reads before any write
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+              const int i = tl + TPP * u;
+              ja[u] = (i < ni) ? jp[i] : 0.0;
+              jb[u] = (i < ni) ? jq[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+              const int i = tl + TPP * u;
+              if (i < ni) {
+                xp[i] = cs * a[u] - sn * c2[u];
+                xq[i] = sn * a[u] + cs * c2[u];
+                jp[i] = cs * ja[u] - sn * jb[u];
+                jq[i] = sn * ja[u] + cs * jb[u];
+              }
+            }
+            if (tl == 0) atomicAdd(&rot_local, 1);
+          }
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < m2 * ni; e += nthr) {
+        const int lc = e / ni, i = e - lc * ni;
+        const int64_t gc = (lc < b) ? (int64_t)I * b + lc : (int64_t)Jb * b + (lc - b);
+        if (gc < n) { X[gc * n + i] = Xl[e]; J[gc * n + i] = Jl[e]; }
+      }
+      if (tid == 0) {
+        sweep_rot += rot_local;
+        if (s == nbp - 2 && sweep_rot > 0)
+          __hip_atomic_fetch_add(&flags[2 + sweep], sweep_rot, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
       ++bar;
       if (!grid_barrier(counter, abort_flag, bar * (int)gridDim.x)) aborted = true;
     }
@@ -392,21 +528,25 @@ __global__ __launch_bounds__(kJeThreads) void k_jacobi_eig(double* __restrict__ 
     if (rot == 0) { converged = true; break; }
   }
   if (aborted) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(status, RSVD_ERR_DEVICE);
+    if (blockIdx.x == 0 && tid == 0) set_error(status, RSVD_ERR_DEVICE);
     return;
   }
-  // lambda_j = |column j of X J| (X J = W diag(lambda) for a PSD matrix)
-  for (int64_t j = gwave; j < n; j += nwaves) {
-    double s2 = 0.0;
-    for (int64_t i = lane; i < n; i += 64) s2 += X[j * n + i] * X[j * n + i];
-    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
-    // sign from the Rayleigh quotient j^T X j keeps a negative eigenvalue negative
-    double rq = 0.0;
-    for (int64_t i = lane; i < n; i += 64) rq += J[j * n + i] * X[j * n + i];
-    for (int off = 32; off > 0; off >>= 1) rq += __shfl_xor(rq, off);
+  // lambda_j = |column j of X J| (= lambda_j w_j for a PSD matrix), signed by
+  // the Rayleigh quotient j_j^T X_j; one wave per column
+  const int lane = tid & 63;
+  const int wpb = nthr / 64;
+  for (int64_t j = (int64_t)blockIdx.x * wpb + tid / 64; j < n; j += (int64_t)gridDim.x * wpb) {
+    double s2 = 0.0, rq = 0.0;
+    for (int64_t i = lane; i < n; i += 64) {
+      const double x = X[j * n + i];
+      s2 += x * x;
+      rq += J[j * n + i] * x;
+    }
+    s2 = group_sum<64>(s2);
+    rq = group_sum<64>(rq);
     if (lane == 0) lam[j] = rq < 0.0 ? -sqrt(s2) : sqrt(s2);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     diag[2] = (double)sweep;
     if (!converged) set_error(status, RSVD_ERR_NOCONV);
   }
@@ -423,15 +563,17 @@ __global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
                                     double* __restrict__ S_out, T* __restrict__ Vout,
                                     int64_t ldv, double* __restrict__ Vd_out,
                                     double* __restrict__ Wout) {
-  extern __shared__ int perm[];
+  extern __shared__ double Sl[];              // c keys, then c ints
+  int* perm = reinterpret_cast<int*>(Sl + c);
   const int tid = threadIdx.x;
+  stage_to_lds(Sl, S, c);
   for (int i = tid; i < c; i += blockDim.x) perm[i] = i;   // NaN keys may leave slots unranked
   __syncthreads();
   for (int i = tid; i < c; i += blockDim.x) {
-    const double si = S[i];
+    const double si = Sl[i];
     int rank = 0;
     for (int j = 0; j < c; ++j) {
-      const double sj = S[j];
+      const double sj = Sl[j];
       rank += (sj > si) || (sj == si && j < i);
     }
     perm[rank] = i;
@@ -452,7 +594,7 @@ __global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
       first = o < first ? o : first;
     }
     const double sg = (first < r && Vsrc[first * vrs + src * vcs] < 0.0) ? -1.0 : 1.0;
-    if (lane == 0) S_out[kk] = S[src];
+    if (lane == 0) S_out[kk] = Sl[src];
     for (int64_t i = lane; i < r; i += 64) {
       const double v = sg * Vsrc[i * vrs + src * vcs];
       if (Vout) Vout[i * ldv + kk] = (T)v;
@@ -468,7 +610,10 @@ __global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
 __global__ void k_select_k(const double* __restrict__ S, int k, const double* __restrict__ fro2,
                            double t, int32_t* __restrict__ K, double* __restrict__ diag,
                            int32_t* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  extern __shared__ double Sl[];
+  stage_to_lds(Sl, S, k);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double f2 = fro2[0];
   diag[0] = f2;
   if (!isfinite(f2)) {
@@ -487,7 +632,7 @@ __global__ void k_select_k(const double* __restrict__ S, int k, const double* __
   int kk = k;
   bool hit = false;
   for (int i = 0; i < k; ++i) {
-    cum += S[i] * S[i];
+    cum += Sl[i] * Sl[i];
     if (cum >= t * f2) { kk = i + 1; hit = true; break; }
   }
   *K = kk;
@@ -553,7 +698,8 @@ hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t 
 template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
                            int32_t* status, hipStream_t s) {
-  const size_t shmem = (2 * (size_t)c * (c + 1) + c) * sizeof(double);
+  if (c < 1 || c > kCholMaxC) return hipErrorInvalidValue;
+  const size_t shmem = 2 * (size_t)c * (c + 1) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
@@ -571,45 +717,63 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_svd_small(const double* M, int c, double* Uo, double* S, double* J,
-                                   double* diag, int32_t* status, hipStream_t s) {
+hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
+                                   double* J, double* diag, int32_t* status, hipStream_t s) {
+  if (c < 1 || c > kJsG * kJsRows) return hipErrorInvalidValue;
   const int npad = c + (c & 1);
   const size_t shmem = 2 * (size_t)npad * c * sizeof(double);
-  // lanes per column pair: the largest power of two with npairs * G <= threads, at most 64
-  int G = 64;
-  while (G > 1 && (npad / 2) * G > kJsThreads) G >>= 1;
+  const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
   hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_svd_small,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi_svd_small, dim3(1), dim3(kJsThreads), shmem, s, M, c, Uo, S, J, diag,
-                     status, G);
+  hipLaunchKernelGGL(k_jacobi_svd_small, dim3(1), dim3(threads), shmem, s, M, c, transpose, Uo, S,
+                     J, diag, status);
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
+template <int TPP, int RPT>
+hipError_t jacobi_eig_launch(double* X, double* J, int64_t n, int b, double* lam, double* diag,
                              int32_t* flags, int32_t* status, hipStream_t s) {
-  const int npairs = (int)((n + 1) / 2);
+  const int64_t nb = (n + b - 1) / b;
+  const int nbp = (int)((nb + (nb & 1)) < 2 ? 2 : nb + (nb & 1));
+  const int threads = b * TPP;               // 256 for every instantiation used
+  if (threads > 256) return hipErrorInvalidValue;
+  const int blocks = nbp / 2;
+  const size_t shmem = (size_t)4 * b * n * sizeof(double);
+  const void* fn = (const void*)k_jacobi_eig<TPP, RPT>;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   int ncu = 0;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jacobi_eig, kJeThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jacobi_eig<TPP, RPT>, threads, shmem);
   if (e != hipSuccess) return e;
-  const int wpb = kJeThreads / 64;
-  int blocks = (npairs + wpb - 1) / wpb;
-  const int resident = ncu * (per_cu > 0 ? per_cu : 1);
-  if (blocks > resident) blocks = resident;
-  if (blocks < 1) blocks = 1;
+  if (blocks > ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flags, 2 + kJeMaxSweeps, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  void* args[] = {&X, &J, &n, &lam, &diag, &flags, &status};
-  return hipLaunchCooperativeKernel((const void*)k_jacobi_eig, dim3(blocks), dim3(kJeThreads), args,
-                                    0, s);
+  int bb = b, nn = nbp;
+  void* args[] = {&X, &J, &n, &bb, &nn, &lam, &diag, &flags, &status};
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, shmem, s);
 }
+
+hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
+                             int32_t* flags, int32_t* status, hipStream_t s) {
+  // blocks of b = 8 columns (32 lanes per pair) up to n = 512, b = 4 (64
+  // lanes) up to n = 1024: the 2b columns of X and J fit in LDS and every
+  // lane holds at most 16 rows of a column
+  if (n < 1 || n > jacobi_eig_max_n()) return hipErrorInvalidValue;
+  if (n <= 128) return jacobi_eig_launch<32, 4>(X, J, n, 8, lam, diag, flags, status, s);
+  if (n <= 256) return jacobi_eig_launch<32, 8>(X, J, n, 8, lam, diag, flags, status, s);
+  if (n <= 512) return jacobi_eig_launch<32, 16>(X, J, n, 8, lam, diag, flags, status, s);
+  return jacobi_eig_launch<64, 16>(X, J, n, 4, lam, diag, flags, status, s);
+}
+
+int64_t jacobi_eig_max_n() { return 1024; }
 
 int jacobi_eig_flag_words() { return 2 + kJeMaxSweeps; }
 
@@ -618,14 +782,16 @@ hipError_t launch_sort_sign_scatter(const double* S, int c, const double* Vsrc, 
                                     int64_t vrs, int64_t vcs, const double* Wsrc, int kout,
                                     double* S_out, T* Vout, int64_t ldv, double* Vd_out,
                                     double* Wout, hipStream_t s) {
-  hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3(1), dim3(1024), (size_t)c * sizeof(int), s, S,
+  hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3(1), dim3(1024),
+                     (size_t)c * (sizeof(double) + sizeof(int)), s, S,
                      c, Vsrc, r, vrs, vcs, Wsrc, kout, S_out, Vout, ldv, Vd_out, Wout);
   return hipGetLastError();
 }
 
 hipError_t launch_select_k(const double* S, int k, const double* fro2, double t, int32_t* K,
                            double* diag, int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_k, dim3(1), dim3(64), 0, s, S, k, fro2, t, K, diag, status);
+  hipLaunchKernelGGL(k_select_k, dim3(1), dim3(256), (size_t)k * sizeof(double), s, S, k, fro2, t,
+                     K, diag, status);
   return hipGetLastError();
 }
 

@@ -1,0 +1,97 @@
+"""Parity at the full benchmark size: A = 1,000,000 x 512 FP32 (sigma_i = 1/i
+plus N(0, 1e-3) noise, columns centred), in the launch configuration bench.py
+times (rsvd_solve with the plan's seeded sketch, gram_eig_solve with all 512
+columns of U).
+
+Randomized PCA: the oracle runs the whole solve on the same stored A (read
+back to FP64) with the same sketch (the published Philox/Box-Muller
+definition, rounded to FP32 as the GPU uses it); gate: relative singular-value
+error <= 1e-4, largest principal angle of the top-k U and V subspaces
+<= 1e-3 rad, K equal.
+
+A^T A route: the oracle forms A^T A and its Jacobi eigen-decomposition; all
+512 singular values are gated at 1e-4 relative (the spectrum is well
+conditioned, s in [0.97, 1.42]); eigenvector columns are compared where the
+eigenvalue gap separates them, and U is checked on 64 sampled rows against
+u_i = A v_i / s_i evaluated by the oracle's own V and s.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+import paper_1906_12085_amd as rs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def workload():
+    c = synth.CONFIG2
+    m, n = c["m"], c["n"]
+    announce(f"fullsize: generating A {m}x{n} fp32")
+    A = synth.spiked_noisy_torch(c["seed"], m, n, synth.config2_sigma(n), c["noise_std"],
+                                 torch.device("cuda", 0), torch.float32)
+    torch.cuda.synchronize()
+    A64 = A.double().cpu().numpy()
+    yield c, A, A64
+    del A
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_rsvd_vs_oracle(workload):
+    c, A, A64 = workload
+    m, n, k, p, q, t = c["m"], c["n"], c["k"], c["p"], c["q"], c["t"]
+    l = k + p
+    announce("fullsize: rsvd_solve on GPU")
+    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=c["omega_seed"])
+    res = plan.solve(A, k, p, q, t)
+    plan.close()
+    assert res.status == rs.RSVD_WARN_THRESHOLD      # K = k: 0.95 is not reached in 64 values
+    G = synth.gaussian_omega(c["omega_seed"], n, l).astype(np.float32).astype(np.float64)
+    announce("fullsize: oracle rsvd (tens of seconds)")
+    ref = oracle.rsvd(A64, G, k, p, q, t)
+    S, U, V = host(res.S), host(res.U), host(res.V)
+    assert np.max(np.abs(S - ref.S) / ref.S) <= 1e-4
+    assert oracle.principal_angle_max(ref.V, V) <= 1e-3
+    assert oracle.principal_angle_max(ref.U, U) <= 1e-3
+    assert res.K == ref.K == k and ref.status == oracle.WARN_THRESHOLD
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_gram_route_vs_oracle(workload):
+    c, A, A64 = workload
+    m, n, t = c["m"], c["n"], c["t"]
+    announce("fullsize: gram_eig_solve on GPU")
+    plan = rs.Plan(m, n, 8, torch.float32, want_gram=True, seed=1)
+    res = plan.gram_eig(A, t)
+    plan.close()
+    assert res.status == rs.RSVD_OK
+    announce("fullsize: oracle A^T A and Jacobi eigensolver")
+    Gm = oracle.gemm_tn(A64, A64)
+    lam, Vo, _ = oracle.eig_sym(Gm)
+    oracle.sign_convention(None, Vo)
+    So = np.sqrt(np.maximum(lam, 0.0))
+    Kref, _ = oracle.select_k(So, oracle.fro2(A64), t)
+    S, V = host(res.S), host(res.V)
+    assert np.max(np.abs(S - So) / So) <= 1e-4
+    assert res.K == Kref
+    # vectors whose eigenvalue is separated from its neighbours by > 1e-3
+    # relative: the FP32 Gram perturbs A^T A by ~1e-6 relative
+    lam_g = So ** 2
+    gap = np.minimum(np.abs(np.diff(lam_g, prepend=np.inf)), np.abs(np.diff(lam_g, append=-np.inf)))
+    sep = gap / lam_g[0] > 1e-3
+    assert sep.sum() >= 2
+    err = np.abs(np.sum(V[:, sep] * Vo[:, sep], axis=0))
+    assert np.all(err >= 1 - 1e-6)
+    # U on sampled rows: u_i = A v_i / s_i with the oracle's V and s
+    rows = np.random.default_rng(5).choice(m, 64, replace=False)
+    Uo_rows = (A64[rows] @ Vo) / So
+    Ug_rows = host(res.U[torch.as_tensor(rows, device=res.U.device)])
+    d = np.sign(np.sum(V * Vo, axis=0))
+    d[d == 0] = 1.0
+    sel = np.where(sep)[0]
+    assert np.max(np.abs(Ug_rows[:, sel] * d[sel] - Uo_rows[:, sel])) <= 1e-4

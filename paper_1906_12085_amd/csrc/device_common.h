@@ -1,0 +1,150 @@
+// device_common.h -- device helpers shared by the FP64 kernels of librsvd:
+// status words, LDS staging, the round-robin pairing and rotation of the
+// Jacobi methods, cross-lane sums, and bounded inter-workgroup waits.
+#pragma once
+
+#include <math.h>
+
+#include "rsvd_internal.h"
+
+namespace rsvd {
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+// Errors win over warnings; among errors the most negative code wins.
+__device__ __forceinline__ void set_error(int32_t* status, int32_t code) { atomicMin(status, code); }
+__device__ __forceinline__ void set_warning(int32_t* status, int32_t code) { atomicCAS(status, 0, code); }
+
+// Copy `count` doubles from global memory into LDS with the whole block; each
+// thread issues eight independent loads before its eight LDS stores, so the
+// memory latency is paid once per eight elements rather than per element.
+__device__ __forceinline__ void stage_to_lds(double* dst, const double* __restrict__ src,
+                                             int count) {
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * step < count; i += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[i + u * step];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[i + u * step] = v[u];
+  }
+  for (; i < count; i += step) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Round-robin ("circle") pairing of npad (even) indices: in step s, pair 0 is
+// (npad-1, s) and pair k > 0 is ((s+k) mod (npad-1), (s-k) mod (npad-1)); the
+// npad-1 steps meet every pair exactly once, and the pairs of one step are
+// disjoint, so their rotations commute.
+__device__ __forceinline__ void rr_pair(int s, int k, int npad, int* p, int* q) {
+  int a, b;
+  const int h = npad - 1;
+  if (k == 0) { a = h; b = s; }
+  else { a = (s + k) % h; b = (s - k + h) % h; }
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+// One-sided (Hestenes) Jacobi rotation that orthogonalises columns x, y with
+// alpha = |x|^2, beta = |y|^2, gamma = x.y:  zeta = (beta - alpha)/(2 gamma),
+// t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), cs = 1/sqrt(1+t^2), sn = cs t;
+// x' = cs x - sn y, y' = sn x + cs y.
+__device__ __forceinline__ void jacobi_cs(double alpha, double beta, double gamma, double* cs,
+                                          double* sn) {
+  const double zeta = (beta - alpha) / (2.0 * gamma);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  *cs = 1.0 / sqrt(1.0 + t * t);
+  *sn = *cs * t;
+}
+
+// Sum over the G consecutive lanes of this lane's group (G = 16, 32 or 64,
+// groups aligned to G).  Within a 16-lane row: quad_perm swaps (lanes l^1,
+// l^2) and row rotations by 4 and 8 (DPP), then every lane takes lane
+// (l & 16)'s value (ds_swizzle) so all lanes of the row hold the same bits;
+// larger groups add the partner row / half-wave symmetrically.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int PAT>
+__device__ __forceinline__ double swizzle(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PAT);
+  return __hiloint2double(hi, lo);
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 16 || G == 32 || G == 64, "group of 16, 32 or 64 lanes");
+  v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1): quad sum
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x128>(v);   // row_ror:8: row sum (association differs by quad)
+  v = swizzle<0x0010>(v);   // broadcast lane (l & 16): identical bits in the row
+  if (G >= 32) v += swizzle<0x401F>(v);   // xor 16
+  if (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
+// M and of the accumulated rotations J held column-major in LDS.  Each group
+// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
+// pair's entries in registers (6 rows per lane), reduces the three inner
+// products with group_sum, rotates and writes back.  With transpose != 0 the
+// ---------------------------------------------------------------------------
+// Waits between workgroups of one cooperative launch.  Spins are bounded:
+// on timeout (or when another workgroup already gave up) the abort flag is
+// raised and the wait reports failure, so that every workgroup leaves.
+constexpr long kSpinLimit = 1L << 22;
+
+// Thread 0 only: spin until *word >= target (agent scope, relaxed loads).
+__device__ __forceinline__ bool spin_geq(int32_t* word, int target, int32_t* abort_flag) {
+  long spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+        ++spins > kSpinLimit) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Agent-scope release / acquire fences (one direction each: the release
+// writes back this XCD's L2, the acquire invalidates it).
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Loads and stores of data handed between workgroups: agent-scope relaxed
+// atomics, i.e. accesses made at the agent's coherence point, so the release
+// fence that publishes them finds little to write back.
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All threads of the block call this.  The block's global writes are
+// published (workgroup barrier, then a release fence by thread 0) before
+// *counter is incremented; thread 0 then waits for *counter >= target and
+// acquires, so the block sees the writes of everyone it waited for.
+__device__ __forceinline__ bool arrive_and_wait(int32_t* counter, int target, int32_t* abort_flag) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    fence_release();
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = spin_geq(counter, target, abort_flag) ? 1 : 0;
+    fence_acquire();
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+}  // namespace
+}  // namespace rsvd

@@ -56,7 +56,7 @@ struct rsvd_plan_s {
   double* diag = nullptr;
   int32_t* flags = nullptr;
   // A^T A route
-  double *Gd = nullptr, *Xe = nullptr, *Je = nullptr, *lam = nullptr, *Se = nullptr,
+  double *Gd = nullptr, *Xe = nullptr, *Je = nullptr, *Es = nullptr, *lam = nullptr, *Se = nullptr,
          *Vd = nullptr;
 };
 
@@ -121,6 +121,7 @@ size_t carve(rsvd_plan_s* p, char* base) {
     p->lam = (double*)take(n * 8);
     p->Se = (double*)take(n * 8);
     p->Vd = (double*)take(n * n * 8);
+    p->Es = (double*)take(jacobi_eig_scratch_doubles(n) * 8);
   }
   return off;
 }
@@ -282,7 +283,7 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, p->Gd, n,
                      p->Xe, p->Je);
   RSVD_CHECK(hipGetLastError());
-  RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->status, s));
+  RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->Es, p->status, s));
   // step 3: s_i = sqrt(lambda_i) (Eq. LambdaSigma), sorted, sign rule
   RSVD_CHECK(launch_sqrt_clamp(p->lam, (int)n, p->Se, s));
   RSVD_CHECK(launch_sort_sign_scatter<T>(p->Se, (int)n, p->Je, n, 1, n, nullptr, (int)n, S, V,
@@ -544,7 +545,7 @@ int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, 
                      plan->Xe, plan->Je);
   RSVD_CHECK(hipGetLastError());
   RSVD_CHECK(launch_jacobi_eig(plan->Xe, plan->Je, n, plan->lam, plan->diag, plan->flags,
-                               plan->status, s));
+                               plan->Es, plan->status, s));
   RSVD_CHECK(launch_sort_sign_scatter<double>(plan->lam, (int)n, plan->Je, n, 1, n, nullptr,
                                               (int)n, lam, nullptr, 0, V, nullptr, s));
   return RSVD_OK;

@@ -98,11 +98,18 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
                                    double* J, double* diag, int32_t* status, hipStream_t s);
 
-// One-sided Jacobi on the columns of a symmetric n x n FP64 matrix (its
-// eigen-decomposition): X <- X J until the columns are orthogonal; then
-// lambda_i = ||x_i|| and the eigenvectors are the columns of J.
+// Eigen-decomposition of a symmetric n x n FP64 matrix by one-sided block
+// Jacobi on its columns: on entry X = G and J = I (column j at X + j*n);
+// X <- X R, J <- J R until the columns of X are orthogonal; then lambda_j =
+// +-||x_j|| (sign of the Rayleigh quotient j_j^T x_j) and the eigenvectors
+// are the columns of J (unsorted).  `flags` holds jacobi_eig_flag_words()
+// int32 words and `scratch` jacobi_eig_scratch_doubles(n) doubles; sweeps
+// used go to diag[2].  inner_sweeps < 0 selects the default.
 hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
-                             int32_t* flags, int32_t* status, hipStream_t s);
+                             int32_t* flags, double* scratch, int32_t* status, hipStream_t s,
+                             int inner_sweeps = -1);
+// Doubles of scratch launch_jacobi_eig needs for matrices up to n.
+int64_t jacobi_eig_scratch_doubles(int64_t n);
 
 // Sort (descending by key), apply the sign rule, and scatter the first kout
 // singular triplets: S_out[i] = key-sorted S, Vout (r x kout, type T, ldv)
@@ -135,7 +142,7 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
 // Number of int32 words launch_jacobi_eig needs in `flags`.
 int jacobi_eig_flag_words();
-// Largest n the Jacobi eigensolver supports (columns in LDS, blocks resident).
+// Largest n the Jacobi eigensolver supports (every workgroup resident).
 int64_t jacobi_eig_max_n();
 
 }  // namespace rsvd

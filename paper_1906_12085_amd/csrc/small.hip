@@ -1,38 +1,12 @@
 // small.hip -- the FP64 work on n x l, l x l and n x n matrices between the
 // passes over A: the Gaussian sketch, Cholesky factors and their inverses
 // (CholeskyQR2), small products, the one-sided Jacobi SVD of the l x l
-// factor, the Jacobi eigensolver of the A^T A route, the sign rule and the
-// explained-variance criterion.
-#include <math.h>
-
-#include "rsvd_internal.h"
+// factor, the sign rule and the explained-variance criterion.
+#include "device_common.h"
 
 namespace rsvd {
 
 namespace {
-
-constexpr double kEps = 2.220446049250313e-16;
-
-// Errors win over warnings; among errors the most negative code wins.
-__device__ __forceinline__ void set_error(int32_t* status, int32_t code) { atomicMin(status, code); }
-__device__ __forceinline__ void set_warning(int32_t* status, int32_t code) { atomicCAS(status, 0, code); }
-
-// Copy `count` doubles from global memory into LDS with the whole block; each
-// thread issues eight independent loads before its eight LDS stores, so the
-// memory latency is paid once per eight elements rather than per element.
-__device__ __forceinline__ void stage_to_lds(double* dst, const double* __restrict__ src,
-                                             int count) {
-  const int step = blockDim.x;
-  int i = threadIdx.x;
-  for (; i + 7 * step < count; i += 8 * step) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[i + u * step];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) dst[i + u * step] = v[u];
-  }
-  for (; i < count; i += step) dst[i] = src[i];
-}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC 2011): ten rounds; each
@@ -200,67 +174,6 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   if (CT) CT[idx] = (T)s;
 }
 
-// ---------------------------------------------------------------------------
-// Round-robin ("circle") pairing of npad (even) indices: in step s, pair 0 is
-// (npad-1, s) and pair k > 0 is ((s+k) mod (npad-1), (s-k) mod (npad-1)); the
-// npad-1 steps meet every pair exactly once, and the pairs of one step are
-// disjoint, so their rotations commute.
-__device__ __forceinline__ void rr_pair(int s, int k, int npad, int* p, int* q) {
-  int a, b;
-  const int h = npad - 1;
-  if (k == 0) { a = h; b = s; }
-  else { a = (s + k) % h; b = (s - k + h) % h; }
-  *p = a < b ? a : b;
-  *q = a < b ? b : a;
-}
-
-// One-sided (Hestenes) Jacobi rotation that orthogonalises columns x, y with
-// alpha = |x|^2, beta = |y|^2, gamma = x.y:  zeta = (beta - alpha)/(2 gamma),
-// t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), cs = 1/sqrt(1+t^2), sn = cs t;
-// x' = cs x - sn y, y' = sn x + cs y.
-__device__ __forceinline__ void jacobi_cs(double alpha, double beta, double gamma, double* cs,
-                                          double* sn) {
-  const double zeta = (beta - alpha) / (2.0 * gamma);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  *cs = 1.0 / sqrt(1.0 + t * t);
-  *sn = *cs * t;
-}
-
-// Sum over the G consecutive lanes of this lane's group (G = 16, 32 or 64,
-// groups aligned to G).  Within a 16-lane row: quad_perm swaps (lanes l^1,
-// l^2) and row rotations by 4 and 8 (DPP), then every lane takes lane
-// (l & 16)'s value (ds_swizzle) so all lanes of the row hold the same bits;
-// larger groups add the partner row / half-wave symmetrically.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int PAT>
-__device__ __forceinline__ double swizzle(double v) {
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PAT);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PAT);
-  return __hiloint2double(hi, lo);
-}
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-  static_assert(G == 16 || G == 32 || G == 64, "group of 16, 32 or 64 lanes");
-  v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
-  v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1): quad sum
-  v += dpp_mov<0x124>(v);   // row_ror:4
-  v += dpp_mov<0x128>(v);   // row_ror:8: row sum (association differs by quad)
-  v = swizzle<0x0010>(v);   // broadcast lane (l & 16): identical bits in the row
-  if (G >= 32) v += swizzle<0x401F>(v);   // xor 16
-  if (G >= 64) v += __shfl_xor(v, 32);
-  return v;
-}
-
-// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
-// M and of the accumulated rotations J held column-major in LDS.  Each group
-// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
-// pair's entries in registers (6 rows per lane), reduces the three inner
-// products with group_sum, rotates and writes back.  With transpose != 0 the
 // kernel works on M^T (the rows of Min are its columns).
 constexpr int kJsG = 16;
 constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
@@ -367,187 +280,6 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
   if (tid == 0) {
     diag[2] = (double)sweep;
     diag[3] = last_off;
-    if (!converged) set_error(status, RSVD_ERR_NOCONV);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Jacobi eigensolver of the A^T A route: one-sided Jacobi on the columns of
-// the symmetric matrix X (column j at X + j*n, X J orthogonalised until
-// X J = W diag(lambda)), rotations accumulated in J.  Block form: the n
-// columns are cut into blocks of b; each workgroup takes one pair of blocks
-// per step (round-robin over the blocks), copies their 2b columns of X and J
-// into LDS, performs one inner sweep over all column pairs of the 2b (b
-// disjoint pairs per round, tpp lanes per pair), and writes them back.  The
-// steps of a sweep are separated by a grid barrier (cooperative launch); the
-// sweep loop ends when a sweep rotates nothing.  The barrier spin is
-// bounded: on timeout the kernel records an error and every block leaves.
-constexpr int kJeMaxSweeps = 40;
-constexpr long kSpinLimit = 1L << 22;
-
-
-// All threads of every block call this; thread 0 publishes the block's
-// global writes (agent-scope release after the workgroup barrier) and
-// acquires the others' before the block continues.
-__device__ __forceinline__ bool grid_barrier(int32_t* counter, int32_t* abort_flag, int target) {
-  __shared__ int ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    __threadfence();
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          ++spins > kSpinLimit) {
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __threadfence();
-  }
-  __syncthreads();
-  return ok != 0;
-}
-
-// flags[0] = barrier counter, flags[1] = abort flag, flags[2 + sweep] =
-// rotations counted in that sweep (all zeroed before launch).  TPP lanes own
-// one column pair in a round; each keeps RPT rows of the two X columns and
-// the two J columns in registers while it rotates them.
-template <int TPP, int RPT>
-__global__ __launch_bounds__(256) void k_jacobi_eig(double* __restrict__ X, double* __restrict__ J, int64_t n, int b,
-                             int nbp, double* __restrict__ lam, double* __restrict__ diag,
-                             int32_t* __restrict__ flags, int32_t* __restrict__ status) {
-  extern __shared__ double sm[];
-  const int m2 = 2 * b;
-  const int ni = (int)n;
-  double* Xl = sm;
-  double* Jl = sm + (size_t)m2 * ni;
-  __shared__ int rot_local;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int pk = tid / TPP, tl = tid % TPP;
-  const double tol = kEps * (double)n;
-  int32_t* counter = flags;
-  int32_t* abort_flag = flags + 1;
-  int bar = 0, sweep = 0, sweep_rot = 0;
-  bool converged = false, aborted = false;
-  while (sweep < kJeMaxSweeps && !aborted) {
-    sweep_rot = 0;
-    for (int s = 0; s < nbp - 1 && !aborted; ++s) {
-      int I, Jb;
-      rr_pair(s, blockIdx.x, nbp, &I, &Jb);
-      {
-        // the 2b columns of X and J, sixteen independent loads in flight per thread
-        const int tot = m2 * ni;
-        for (int e0 = tid; e0 < tot; e0 += 8 * nthr) {
-          double vx[8], vj[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * nthr;
-            vx[u] = 0.0; vj[u] = 0.0;
-            if (e < tot) {
-              const int lc = e / ni, i = e - lc * ni;
-              const int64_t gc = (lc < b) ? (int64_t)I * b + lc : (int64_t)Jb * b + (lc - b);
-              if (gc < n) { vx[u] = X[gc * n + i]; vj[u] = J[gc * n + i]; }
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * nthr;
-            if (e < tot) { Xl[e] = vx[u]; Jl[e] = vj[u]; }
-          }
-        }
-      }
-      if (tid == 0) rot_local = 0;
-      __syncthreads();
-      for (int r = 0; r < m2 - 1; ++r) {
-        if (pk < b) {                        // uniform within the TPP-lane group
-          int p, q;
-          rr_pair(r, pk, m2, &p, &q);
-          double* xp = Xl + (size_t)p * ni;
-          double* xq = Xl + (size_t)q * ni;
-          double a[RPT], c2[RPT];
-          double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-          for (int u = 0; u < RPT; ++u) {
-            const int i = tl + TPP * u;
-            a[u] = (i < ni) ? xp[i] : 0.0;
-            c2[u] = (i < ni) ? xq[i] : 0.0;
-            al += a[u] * a[u]; be += c2[u] * c2[u]; ga += a[u] * c2[u];
-          }
-          al = group_sum<TPP>(al);
-          be = group_sum<TPP>(be);
-          ga = group_sum<TPP>(ga);
-          const double scale = sqrt(al) * sqrt(be);
-          if (ga != 0.0 && scale > 0.0 && fabs(ga) > tol * scale) {
-            double cs, sn;
-            jacobi_cs(al, be, ga, &cs, &sn);
-            double* jp = Jl + (size_t)p * ni;
-            double* jq = Jl + (size_t)q * ni;
-            double ja[RPT], jb[RPT];         // all reads before any write
-#pragma unroll
-            for (int u = 0; u < RPT; ++u) {
-              const int i = tl + TPP * u;
-              ja[u] = (i < ni) ? jp[i] : 0.0;
-              jb[u] = (i < ni) ? jq[i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < RPT; ++u) {
-              const int i = tl + TPP * u;
-              if (i < ni) {
-                xp[i] = cs * a[u] - sn * c2[u];
-                xq[i] = sn * a[u] + cs * c2[u];
-                jp[i] = cs * ja[u] - sn * jb[u];
-                jq[i] = sn * ja[u] + cs * jb[u];
-              }
-            }
-            if (tl == 0) atomicAdd(&rot_local, 1);
-          }
-        }
-        __syncthreads();
-      }
-      for (int e = tid; e < m2 * ni; e += nthr) {
-        const int lc = e / ni, i = e - lc * ni;
-        const int64_t gc = (lc < b) ? (int64_t)I * b + lc : (int64_t)Jb * b + (lc - b);
-        if (gc < n) { X[gc * n + i] = Xl[e]; J[gc * n + i] = Jl[e]; }
-      }
-      if (tid == 0) {
-        sweep_rot += rot_local;
-        if (s == nbp - 2 && sweep_rot > 0)
-          __hip_atomic_fetch_add(&flags[2 + sweep], sweep_rot, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-      }
-      ++bar;
-      if (!grid_barrier(counter, abort_flag, bar * (int)gridDim.x)) aborted = true;
-    }
-    if (aborted) break;
-    const int rot = __hip_atomic_load(&flags[2 + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ++sweep;
-    if (rot == 0) { converged = true; break; }
-  }
-  if (aborted) {
-    if (blockIdx.x == 0 && tid == 0) set_error(status, RSVD_ERR_DEVICE);
-    return;
-  }
-  // lambda_j = |column j of X J| (= lambda_j w_j for a PSD matrix), signed by
-  // the Rayleigh quotient j_j^T X_j; one wave per column
-  const int lane = tid & 63;
-  const int wpb = nthr / 64;
-  for (int64_t j = (int64_t)blockIdx.x * wpb + tid / 64; j < n; j += (int64_t)gridDim.x * wpb) {
-    double s2 = 0.0, rq = 0.0;
-    for (int64_t i = lane; i < n; i += 64) {
-      const double x = X[j * n + i];
-      s2 += x * x;
-      rq += J[j * n + i] * x;
-    }
-    s2 = group_sum<64>(s2);
-    rq = group_sum<64>(rq);
-    if (lane == 0) lam[j] = rq < 0.0 ? -sqrt(s2) : sqrt(s2);
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    diag[2] = (double)sweep;
     if (!converged) set_error(status, RSVD_ERR_NOCONV);
   }
 }
@@ -731,51 +463,6 @@ hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double
   return hipGetLastError();
 }
 
-template <int TPP, int RPT>
-hipError_t jacobi_eig_launch(double* X, double* J, int64_t n, int b, double* lam, double* diag,
-                             int32_t* flags, int32_t* status, hipStream_t s) {
-  const int64_t nb = (n + b - 1) / b;
-  const int nbp = (int)((nb + (nb & 1)) < 2 ? 2 : nb + (nb & 1));
-  const int threads = b * TPP;               // 256 for every instantiation used
-  if (threads > 256) return hipErrorInvalidValue;
-  const int blocks = nbp / 2;
-  const size_t shmem = (size_t)4 * b * n * sizeof(double);
-  const void* fn = (const void*)k_jacobi_eig<TPP, RPT>;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  int ncu = 0;
-  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jacobi_eig<TPP, RPT>, threads, shmem);
-  if (e != hipSuccess) return e;
-  if (blocks > ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flags, 2 + kJeMaxSweeps, 0);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  int bb = b, nn = nbp;
-  void* args[] = {&X, &J, &n, &bb, &nn, &lam, &diag, &flags, &status};
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, shmem, s);
-}
-
-hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
-                             int32_t* flags, int32_t* status, hipStream_t s) {
-  // blocks of b = 8 columns (32 lanes per pair) up to n = 512, b = 4 (64
-  // lanes) up to n = 1024: the 2b columns of X and J fit in LDS and every
-  // lane holds at most 16 rows of a column
-  if (n < 1 || n > jacobi_eig_max_n()) return hipErrorInvalidValue;
-  if (n <= 128) return jacobi_eig_launch<32, 4>(X, J, n, 8, lam, diag, flags, status, s);
-  if (n <= 256) return jacobi_eig_launch<32, 8>(X, J, n, 8, lam, diag, flags, status, s);
-  if (n <= 512) return jacobi_eig_launch<32, 16>(X, J, n, 8, lam, diag, flags, status, s);
-  return jacobi_eig_launch<64, 16>(X, J, n, 4, lam, diag, flags, status, s);
-}
-
-int64_t jacobi_eig_max_n() { return 1024; }
-
-int jacobi_eig_flag_words() { return 2 + kJeMaxSweeps; }
 
 template <typename T>
 hipError_t launch_sort_sign_scatter(const double* S, int c, const double* Vsrc, int64_t r,

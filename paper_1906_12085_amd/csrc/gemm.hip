@@ -166,6 +166,192 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Y = A Xt^T for wide outputs (more than 128 columns; the truncated SVD forms
+// u_i = A v_i / s_i for every i, Sec. 3.1.3), with the right factor given
+// transposed (Xt is c x n, row-major) so that both operands are read along
+// k.  Two-level tiling on the full-rate 32x32x2 fp32 matrix cores: block
+// tile kWM x kWN = 128 x 256 (4 waves in 2 x 2, each 64 x 128 = 2 x 4 tiles
+// of 32 x 32); chunks of kWK = 32 along k of both operands are staged in LDS
+// (row-major, padded rows) in two buffers.  Chunk i+1 is loaded into
+// registers before chunk i is multiplied and written to LDS during its last
+// slab; one barrier per chunk.  Blocks are numbered so that the column tiles
+// of a row panel run back to back on the same XCD (block b runs on XCD
+// b mod 8), so A comes from HBM once.
+//
+// Fast path (n a multiple of kWK, 16-byte aligned rows): buffer loads from a
+// per-block descriptor whose size ends at the last valid row, so rows past m
+// (or past c) read as zero; the chunk advance is a scalar offset.  General
+// path: clamped addresses and selects.
+constexpr int kWM = 128, kWN = 256, kWK = 32, kWLD = kWK + 4;
+constexpr int kBufDword3 = 0x00020000;        // raw 32-bit buffer (gfx9 family)
+
+template <bool FAST>
+__device__ __forceinline__ void nt_wide_body(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, int64_t arow0, int bcol0,
+    float (*As)[kWM * kWLD], float (*Bs)[kWN * kWLD]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, g = lane >> 5;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nch = (int)((n + kWK - 1) / kWK);
+  const int64_t arows = m - arow0 < kWM ? m - arow0 : kWM;
+  const int bcols = c - bcol0 < kWN ? c - bcol0 : kWN;
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  // thread's share of a chunk: A rows (idx >> 3) and Xt rows (idx >> 3),
+  // k-quad idx & 7; eight lanes cover the 128 bytes of one row
+  const __amdgpu_buffer_rsrc_t ra_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + arow0 * lda), 0, FAST ? (int)(arows * lda * 4) : 0, kBufDword3);
+  const __amdgpu_buffer_rsrc_t rx_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(Xt + (int64_t)bcol0 * ldxt), 0, FAST ? (int)(bcols * ldxt * 4) : 0,
+      kBufDword3);
+  int voa[4], vox[8];
+  if (FAST) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + u * 256;
+      voa[u] = (int)(((idx >> 3) * lda + 4 * (idx & 7)) * 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      vox[u] = (int)(((idx >> 3) * ldxt + 4 * (idx & 7)) * 4);
+    }
+  }
+  f32x4 ra[4], rx[8];
+  auto load = [&](int ch) {
+    const int64_t k0 = (int64_t)ch * kWK;
+    if (FAST) {
+      const int so = (int)(k0 * 4);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra_rsrc, voa[u], so, 0));
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        rx[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rx_rsrc, vox[u], so, 0));
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + u * 256;
+        const int64_t gr = arow0 + (idx >> 3), k = k0 + 4 * (idx & 7);
+        const float* rowp = A + (gr < m ? gr : m - 1) * lda;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ra[u][i] = rowp[k + i < n ? k + i : n - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = tid + u * 256;
+        const int64_t gc = bcol0 + (idx >> 3), k = k0 + 4 * (idx & 7);
+        const float* rowp = Xt + (gc < c ? gc : c - 1) * ldxt;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rx[u][i] = rowp[k + i < n ? k + i : n - 1];
+      }
+    }
+  };
+  auto store = [&](int ch, int buf) {
+    const int64_t k0 = (int64_t)ch * kWK;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + u * 256, row = idx >> 3, kq = idx & 7;
+      f32x4 v = ra[u];
+      if (!FAST) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (row < arows && k0 + 4 * kq + i < n) ? v[i] : 0.f;
+      }
+      *reinterpret_cast<f32x4*>(&As[buf][row * kWLD + 4 * kq]) = v;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256, col = idx >> 3, kq = idx & 7;
+      f32x4 v = rx[u];
+      if (!FAST) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (col < bcols && k0 + 4 * kq + i < n) ? v[i] : 0.f;
+      }
+      *reinterpret_cast<f32x4*>(&Bs[buf][col * kWLD + 4 * kq]) = v;
+    }
+  };
+  // slab of 8 k: lane (lr, g) reads k = 8 s + 4 g .. +3 of its row with one
+  // 16-byte load, and step t contracts over k = 8 s + 4 g + t (the same
+  // permutation on both operands)
+  auto slab = [&](int buf, int s) {
+    f32x4 af[2], bf[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][(wr * 64 + 32 * i + lr) * kWLD + 8 * s + 4 * g]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][(wc * 128 + 32 * j + lr) * kWLD + 8 * s + 4 * g]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma32f::run(af[i][t], bf[j][t], acc[i][j]);
+  };
+
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  static_assert(kWK == 32, "four slabs per chunk");
+  for (int ch = 0; ch < nch; ++ch) {
+    const int nx = ch + 1 < nch ? ch + 1 : ch;  // the last prefetch is a harmless repeat
+    const int buf = ch & 1;
+    load(nx);
+    __builtin_amdgcn_sched_barrier(0);        // keep the loads ahead of the multiply
+    slab(buf, 0);
+    slab(buf, 1);
+    slab(buf, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    slab(buf, 3);
+    store(nx, buf ^ 1);                       // the other buffer: free since the last barrier
+    // last slab: its 6 LDS reads, then 2 matrix-core steps per LDS write
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+    for (int w = 0; w < 12; ++w) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = bcol0 + wc * 128 + 32 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = arow0 + wr * 64 + 32 * i + Mfma32f::row(lane, e);
+        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_nt_wide(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, int64_t ntiles, int ncb,
+    int64_t per_xcd, int fast) {
+  __shared__ __attribute__((aligned(16))) float As[2][kWM * kWLD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kWN * kWLD];
+  const int64_t L = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= ntiles) return;
+  const int64_t rb = L / ncb;
+  const int cb = (int)(L - rb * ncb);
+  if (fast)
+    nt_wide_body<true>(A, m, n, lda, Xt, ldxt, c, Y, ldy, rb * kWM, cb * kWN, As, Bs);
+  else
+    nt_wide_body<false>(A, m, n, lda, Xt, ldxt, c, Y, ldy, rb * kWM, cb * kWN, As, Bs);
+}
+
 template <typename T, int NT, int MR>
 hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                        int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
@@ -469,6 +655,24 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 }  // namespace
 
 // ---------------------------------------------------------------------------
+hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                               int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+  if (m <= 0 || c <= 0) return hipSuccess;
+  const int64_t nrb = (m + kWM - 1) / kWM;
+  const int ncb = (c + kWN - 1) / kWN;
+  const int64_t ntiles = nrb * ncb;
+  const int64_t per_xcd = (ntiles + 7) / 8;
+  // fast path: whole chunks, 16-byte rows, and byte offsets of a block's
+  // panel within 32 bits
+  const bool fast = (n % kWK == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+                    (lda % 4 == 0) && (reinterpret_cast<uintptr_t>(Xt) % 16 == 0) &&
+                    (ldxt % 4 == 0) && ((int64_t)kWM * lda * 4 < (1LL << 31)) &&
+                    ((int64_t)kWN * ldxt * 4 < (1LL << 31));
+  hipLaunchKernelGGL(k_gemm_nt_wide, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, A, m, n, lda,
+                     Xt, ldxt, c, Y, ldy, ntiles, ncb, per_xcd, fast ? 1 : 0);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                           int c, T* Y, int64_t ldy, double* fro2_part, int* nparts,

@@ -8,6 +8,8 @@
 
 #include <new>
 
+#include <type_traits>
+
 #include "rsvd_internal.h"
 
 using namespace rsvd;
@@ -291,9 +293,17 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   // step 4: u_i = A v_i / s_i
   if (ucols > 0) {
     const double floor_rel = (double)(m > n ? m : n) * 2.220446049250313e-16;
-    RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, ucols, n, S, floor_rel, (T*)p->Xs, ucols, s));
-    RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, (const T*)p->Xs, ucols, ucols, U, ldu, nullptr,
-                                 nullptr, s));
+    if (std::is_same<T, float>::value && ucols > 128) {
+      // wide fp32 product: the scaled V goes in transposed (ucols x n)
+      RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, ucols, n, S, floor_rel, (T*)p->Xs, n, 1, s));
+      RSVD_CHECK(launch_gemm_nt_wide(reinterpret_cast<const float*>(A), m, n, lda,
+                                     reinterpret_cast<const float*>(p->Xs), n, ucols,
+                                     reinterpret_cast<float*>(U), ldu, s));
+    } else {
+      RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, ucols, n, S, floor_rel, (T*)p->Xs, ucols, 0, s));
+      RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, (const T*)p->Xs, ucols, ucols, U, ldu, nullptr,
+                                   nullptr, s));
+    }
   }
   RSVD_CHECK(launch_select_k(S, (int)n, p->scal, t, K, p->diag, p->status, s));
   return RSVD_OK;
@@ -472,8 +482,15 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
                                       (double*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     if (Gram) RSVD_CHECK(Path<double>(plan).gram((const double*)Y, m, c, ldy, Gram));
   } else {
-    RSVD_CHECK(launch_gemm_nn<float>((const float*)A, m, n, lda, (const float*)X, ldx, c,
-                                     (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
+    if (c > 128 && !fro2 && n <= plan->n_max) {
+      // wide product: X transposed into plan scratch (c x n <= cmax x n_max)
+      RSVD_CHECK(launch_transpose_f32((const float*)X, n, c, ldx, (float*)plan->Xs, n, s));
+      RSVD_CHECK(launch_gemm_nt_wide((const float*)A, m, n, lda, (const float*)plan->Xs, n, c,
+                                     (float*)Y, ldy, s));
+    } else {
+      RSVD_CHECK(launch_gemm_nn<float>((const float*)A, m, n, lda, (const float*)X, ldx, c,
+                                       (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
+    }
     if (Gram) RSVD_CHECK(Path<float>(plan).gram((const float*)Y, m, c, ldy, Gram));
   }
   if (fro2) RSVD_CHECK(launch_reduce_scalar(plan->fro2_part, np, fro2, s));

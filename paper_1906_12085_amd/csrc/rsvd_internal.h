@@ -33,6 +33,21 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int lane, int e) { return (lane >> 4) + 4 * e; }
 };
 
+// 32x32x2 fp32, the full-rate fp32 matrix-core shape on gfx950 (4096 flops
+// in the issue time of 16x16x4's 2048 x 1.6): lane l supplies
+// a = Aop[l%32][l/32], b = Bop[l/32][l%32]; value e of lane l is at row
+// (e%4) + 8*(e/4) + 4*(l/32), column l%32.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+struct Mfma32f {
+  typedef f32x16 acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int e) {
+    return (e & 3) + 8 * (e >> 2) + 4 * (lane >> 5);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Launchers (host functions; every one returns hipSuccess or the launch error).
 
@@ -43,6 +58,11 @@ template <typename T>
 hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                           int c, T* Y, int64_t ldy, double* fro2_part, int* nparts,
                           hipStream_t s);
+
+// Y (m x c) = A (m x n) Xt^T with Xt given transposed (c x n, row-major), for
+// outputs wider than 128 columns (fp32; two-level tiled on 32x32x2).
+hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                               int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s);
 
 // Partials P[s] (n x c, FP64) of A^T Q over row splits; C = compute type of
 // the matrix-core product (double gives an exact-product FP64 Gram for float
@@ -130,11 +150,14 @@ hipError_t launch_select_k(const double* S, int k, const double* fro2, double t,
                            double* diag, int32_t* status, hipStream_t s);
 
 // Scale the columns of V (n x cols, FP64) by 1/S[j] into X (type T), with a
-// zero column when S[j] <= floor_rel * S[0].
+// zero column when S[j] <= floor_rel * S[0]; trans != 0 stores X^T (cols x n).
 template <typename T>
 hipError_t launch_scale_cols_inv(const double* V, int64_t n, int cols, int64_t ldv,
-                                 const double* S, double floor_rel, T* X, int64_t ldx,
+                                 const double* S, double floor_rel, T* X, int64_t ldx, int trans,
                                  hipStream_t s);
+// Xt (cols x rows) = X^T for a row-major fp32 X.
+hipError_t launch_transpose_f32(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Xt,
+                                int64_t ldxt, hipStream_t s);
 
 // S[i] = sqrt(max(lam[i], 0)).
 hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s);

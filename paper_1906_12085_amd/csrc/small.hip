@@ -373,16 +373,40 @@ __global__ void k_select_k(const double* __restrict__ S, int k, const double* __
   if (!hit) set_warning(status, RSVD_WARN_THRESHOLD);
 }
 
+// X = V diag(1/S) (zero columns below the floor); trans != 0 writes X^T
+// (cols x n) instead, indexed so that consecutive threads write
+// consecutive elements either way.
 template <typename T>
 __global__ void k_scale_cols_inv(const double* __restrict__ V, int64_t n, int cols, int64_t ldv,
                                  const double* __restrict__ S, double floor_rel,
-                                 T* __restrict__ X, int64_t ldx) {
+                                 T* __restrict__ X, int64_t ldx, int trans) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * cols) return;
-  const int64_t i = idx / cols;
-  const int j = (int)(idx - i * cols);
+  int64_t i;
+  int j;
+  if (trans) { j = (int)(idx / n); i = idx - (int64_t)j * n; }
+  else { i = idx / cols; j = (int)(idx - i * cols); }
   const double sj = S[j];
-  X[i * ldx + j] = (sj > floor_rel * S[0]) ? (T)(V[i * ldv + j] / sj) : T(0);
+  const T v = (sj > floor_rel * S[0]) ? (T)(V[i * ldv + j] / sj) : T(0);
+  if (trans) X[(int64_t)j * ldx + i] = v;
+  else X[i * ldx + j] = v;
+}
+
+// Xt (cols x rows) = X^T through a 32 x 33 LDS tile (both sides coalesced).
+__global__ void k_transpose_f32(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                int64_t ldx, float* __restrict__ Xt, int64_t ldxt) {
+  __shared__ float tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 256 threads: 8 rows at a time
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    tile[rr][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.f;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 32; cc += 8) {
+    const int64_t c = c0 + cc, r = r0 + tx;
+    if (c < cols && r < rows) Xt[c * ldxt + r] = tile[tx][cc];
+  }
 }
 
 __global__ void k_sqrt_clamp(const double* __restrict__ lam, int n, double* __restrict__ S) {
@@ -484,10 +508,19 @@ hipError_t launch_select_k(const double* S, int k, const double* fro2, double t,
 
 template <typename T>
 hipError_t launch_scale_cols_inv(const double* V, int64_t n, int cols, int64_t ldv, const double* S,
-                                 double floor_rel, T* X, int64_t ldx, hipStream_t s) {
+                                 double floor_rel, T* X, int64_t ldx, int trans,
+                                 hipStream_t s) {
   if (n * cols <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_scale_cols_inv<T>), dim3(blocks_for(n * cols, 256)), dim3(256), 0, s, V, n,
-                     cols, ldv, S, floor_rel, X, ldx);
+                     cols, ldv, S, floor_rel, X, ldx, trans);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Xt,
+                                int64_t ldxt, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
+                     dim3(256), 0, s, X, rows, cols, ldx, Xt, ldxt);
   return hipGetLastError();
 }
 
@@ -515,7 +548,7 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
                                                   int64_t, int64_t, const double*, int, double*,  \
                                                   T*, int64_t, double*, double*, hipStream_t);     \
   template hipError_t launch_scale_cols_inv<T>(const double*, int64_t, int, int64_t,              \
-                                               const double*, double, T*, int64_t, hipStream_t);
+                                                const double*, double, T*, int64_t, int, hipStream_t);
 RSVD_INST(float)
 RSVD_INST(double)
 #undef RSVD_INST

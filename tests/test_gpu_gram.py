@@ -48,7 +48,8 @@ def test_config1_fp64_gram_route(plans):
     assert np.linalg.norm(A0 @ V[:, good] - U[:, good] * S[good]) <= 1e-9 * np.linalg.norm(A0)
 
 
-@pytest.mark.parametrize("m,n,ucols", [(20000, 96, 96), (4099, 131, 40), (300, 257, 0), (64, 64, 64)])
+@pytest.mark.parametrize("m,n,ucols", [(20000, 96, 96), (4099, 131, 40), (300, 257, 0), (64, 64, 64),
+                                         (3001, 259, 200), (4096, 256, 256)])
 def test_fp32_gram_route(plans, m, n, ucols):
     announce(f"gram fp32 m={m} n={n} ucols={ucols}")
     rng = np.random.default_rng(m + n)

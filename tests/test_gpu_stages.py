@@ -85,6 +85,45 @@ def test_gemm_nn_parity(plans, name, m, n, c, pad):
         assert np.all(np.abs(host(Gm) - Gref) <= gb)
 
 
+# wide X without the fused sum of squares: the two-level tiled product for
+# fp32 (128 x 256 block tiles, XCD-ordered), the column-tiled one for fp64
+NN_WIDE_CASES = [
+    (777, 150, 200, 0),    # one column tile, partial
+    (1037, 203, 257, 4),   # unaligned A rows and X rows (scalar loads), ragged everything
+    (300, 512, 512, 0),    # the u_i = A v_i / s_i shape at small m
+    (129, 33, 300, 0),     # one full and one ragged row tile, k tail
+    (5000, 256, 384, 0),
+]
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("m,n,c,pad", NN_WIDE_CASES)
+def test_gemm_nn_wide_parity(plans, name, m, n, c, pad):
+    dt = DTYPES[name]
+    announce(f"gemm_nn wide {name} m={m} n={n} c={c} pad={pad}")
+    rng = np.random.default_rng(m + 3 * n + c)
+    A0 = rounded(rng.standard_normal((m, n)), dt)
+    X0 = rounded(rng.standard_normal((n, c)), dt)
+    A = dev(np.pad(A0, ((0, 0), (0, pad))), dt)[:, :n]
+    X = dev(X0, dt)
+    Y = torch.full((m, c), float("nan"), dtype=dt, device="cuda")
+    p = plans[name] if c <= 300 else big_plans(name)
+    rs.rsvd_gemm_nn(p.handle, A, X, Y)
+    torch.cuda.synchronize()
+    Yref = oracle.gemm_nn(A0, X0)
+    bound = 2.0 * n * unit(dt) * (np.abs(A0) @ np.abs(X0)) + 1e-300
+    assert np.all(np.abs(host(Y) - Yref) <= bound)
+
+
+_BIG = {}
+
+
+def big_plans(name):
+    if name not in _BIG:
+        _BIG[name] = rs.Plan(6000, 512, 96, DTYPES[name], want_gram=True, seed=7)
+    return _BIG[name]
+
+
 TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100, 97, 96)]
 
 

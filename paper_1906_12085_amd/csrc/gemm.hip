@@ -352,6 +352,143 @@ __global__ __launch_bounds__(256) void k_gemm_nt_wide(
     nt_wide_body<false>(A, m, n, lda, Xt, ldxt, c, Y, ldy, rb * kWM, cb * kWN, As, Bs);
 }
 
+// ---------------------------------------------------------------------------
+// G = A^T A for fp32 A (the truncated SVD's Gram matrix, Sec. 3.1.3, Eq.
+// AB), upper 128 x 128 tile pairs only (G is symmetric).  Block = one tile
+// pair (I <= J) over one split of the rows; chunks of kSyK = 64 rows of the
+// two 128-column slices are staged row-major in LDS (row stride padded to
+// 288 floats, so the two half-waves of a read touch disjoint banks), two
+// buffers, next chunk's buffer loads issued ahead of the multiply and its LDS
+// writes interleaved into the last quarter.  32x32x2 steps contract over two
+// rows: lane (lr, g) supplies A[row 2t + g][column lr of its slice] for both
+// operands.  fp32 accumulation within a block, FP64 partial tiles, reduced in
+// split order by k_syrk_reduce (deterministic).  Columns past n are never
+// masked: they only feed output rows/columns past n, which are not written
+// (and the buffer descriptor ends at the split's last row).
+constexpr int kSyT = 128, kSyK = 64, kSyLD = 2 * kSyT + 32;
+
+__global__ __launch_bounds__(256) void k_syrk_f32(const float* __restrict__ A, int64_t m,
+                                                  int64_t n, int64_t lda, int ntile, int npair,
+                                                  int64_t rps, int64_t nblk, int64_t per_xcd,
+                                                  double* __restrict__ P) {
+  __shared__ __attribute__((aligned(16))) float As[2][kSyK * kSyLD];
+  const int64_t L = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= nblk) return;
+  const int64_t sp = L / npair;                  // row split (consecutive blocks share it)
+  const int pr = (int)(L - sp * npair);          // tile pair, upper triangle row by row
+  int I = 0, rem = pr;
+  while (rem >= ntile - I) { rem -= ntile - I; ++I; }
+  const int J = I + rem;
+  const int64_t row0 = sp * rps;
+  const int64_t rows = (m - row0 < rps) ? m - row0 : rps;
+  const int nch = (int)((rows + kSyK - 1) / kSyK);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, g = lane >> 5;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
+  // chunk = 64 rows x 64 float4 (32 from slice I, 32 from slice J)
+  int voff[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = tid + u * 256, r = idx >> 6, q = idx & 63;
+    const int col = q < 32 ? I * kSyT + 4 * q : J * kSyT + 4 * (q - 32);
+    voff[u] = (int)((r * lda + col) * 4);
+  }
+  f32x4 rg[16];
+  auto load = [&](int ch) {
+    const int so = (int)((int64_t)ch * kSyK * lda * 4);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      rg[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[u], so, 0));
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + u * 256, r = idx >> 6, q = idx & 63;
+      *reinterpret_cast<f32x4*>(&As[buf][r * kSyLD + 4 * q]) = rg[u];
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  auto steps = [&](int buf, int t0, int t1) {
+#pragma unroll
+    for (int t = t0; t < t1; ++t) {
+      const float* rowp = &As[buf][(2 * t + g) * kSyLD];
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = rowp[wr * 64 + 32 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = rowp[kSyT + wc * 64 + 32 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mfma32f::run(a[i], b[j], acc[i][j]);
+    }
+  };
+
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    load(ch + 1 < nch ? ch + 1 : ch);          // the last prefetch is a harmless repeat
+    __builtin_amdgcn_sched_barrier(0);
+    steps(buf, 0, 24);
+    __builtin_amdgcn_sched_barrier(0);
+    steps(buf, 24, 32);
+    store(buf ^ 1);
+    // last quarter: 4 LDS reads and 4 matrix-core steps per 2 LDS writes
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+    }
+    __syncthreads();
+  }
+  double* out = P + L * (int64_t)(kSyT * kSyT);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wc * 64 + 32 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wr * 64 + 32 * i + Mfma32f::row(lane, e);
+        out[row * kSyT + col] = (double)acc[i][j][e];
+      }
+    }
+}
+
+// G (n x n, FP64) from the partial tiles: element (i, j) of tile pair p is
+// the sum over the splits in order; tile (I, J) also fills (J, I).
+__global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int npair, int ntile,
+                              int64_t n, double* __restrict__ G, int64_t ldg) {
+  const int pr = blockIdx.y;
+  int I = 0, rem = pr;
+  while (rem >= ntile - I) { rem -= ntile - I; ++I; }
+  const int J = I + rem;
+  const int e0 = (blockIdx.x * blockDim.x + threadIdx.x) * 2;   // two adjacent entries
+  if (e0 >= kSyT * kSyT) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t sp = 0; sp < nsplit; ++sp) {
+    const double* t = P + (sp * npair + pr) * (int64_t)(kSyT * kSyT) + e0;
+    s0 += t[0];
+    s1 += t[1];
+  }
+  const int i = e0 / kSyT, j = e0 % kSyT;
+  const int64_t gi = (int64_t)I * kSyT + i, gj = (int64_t)J * kSyT + j;
+  if (gi < n && gj < n) { G[gi * ldg + gj] = s0; if (I != J) G[gj * ldg + gi] = s0; }
+  if (gi < n && gj + 1 < n) { G[gi * ldg + gj + 1] = s1; if (I != J) G[(gj + 1) * ldg + gi] = s1; }
+}
+
 template <typename T, int NT, int MR>
 hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                        int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
@@ -655,6 +792,41 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 }  // namespace
 
 // ---------------------------------------------------------------------------
+hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
+                           int64_t p_cap, double* G, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int ntile = (int)((n + kSyT - 1) / kSyT);
+  const int npair = ntile * (ntile + 1) / 2;
+  // about three blocks per CU in all (256 CUs), splits of whole chunks, and
+  // the partial tiles within the scratch capacity
+  int64_t nsplit = (3 * 256) / npair;
+  const int64_t by_rows = (m + kSyK - 1) / kSyK;
+  if (nsplit > by_rows) nsplit = by_rows;
+  const int64_t cap = p_cap / ((int64_t)npair * kSyT * kSyT);
+  if (nsplit > cap) nsplit = cap;
+  if (nsplit < 1) return hipErrorInvalidValue;
+  int64_t rps = (m + nsplit - 1) / nsplit;
+  rps = (rps + kSyK - 1) / kSyK * kSyK;
+  nsplit = (m + rps - 1) / rps;
+  if ((reinterpret_cast<uintptr_t>(A) % 16) != 0 || (lda % 4) != 0 ||
+      rps * lda * 4 >= (1LL << 31))
+    return hipErrorInvalidValue;
+  const int64_t nblk = nsplit * npair;
+  const int64_t per_xcd = (nblk + 7) / 8;
+  hipLaunchKernelGGL(k_syrk_f32, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, A, m, n, lda,
+                     ntile, npair, rps, nblk, per_xcd, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_syrk_reduce, dim3((kSyT * kSyT / 2 + 255) / 256, npair), dim3(256), 0, s, P,
+                     nsplit, npair, ntile, n, G, n);
+  return hipGetLastError();
+}
+
+bool syrk_f32_applies(const float* A, int64_t n, int64_t lda) {
+  return n > 128 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (lda % 4) == 0 &&
+         (n % 4) == 0;
+}
+
 hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
   if (m <= 0 || c <= 0) return hipSuccess;

@@ -73,6 +73,10 @@ namespace {
 size_t elem_size(int dtype) { return dtype == RSVD_F64 ? sizeof(double) : sizeof(float); }
 
 // Carve the workspace; with base == nullptr it only counts bytes.
+int64_t p_cmax(const rsvd_plan_s* p) {
+  return p->gram ? (p->n_max > p->l_max ? p->n_max : p->l_max) : p->l_max;
+}
+
 size_t carve(rsvd_plan_s* p, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -278,7 +282,13 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   Path<T> P(p);
   RSVD_CHECK(reset(p));
   // step 1: A^T A (Eq. AB), and its trace = ||A||_F^2 (Eq. sumeigen)
-  RSVD_CHECK(P.tn(A, m, n, lda, A, lda, (int)n, p->Gd));
+  if (std::is_same<T, float>::value &&
+      syrk_f32_applies(reinterpret_cast<const float*>(A), n, lda)) {
+    RSVD_CHECK(launch_syrk_f32(reinterpret_cast<const float*>(A), m, n, lda, p->part,
+                               p->max_split * p->n_max * p_cmax(p), p->Gd, s));
+  } else {
+    RSVD_CHECK(P.tn(A, m, n, lda, A, lda, (int)n, p->Gd));
+  }
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, p->Gd, n, p->scal);
   RSVD_CHECK(hipGetLastError());
   // step 2: eigen-decomposition (Jacobi, FP64)

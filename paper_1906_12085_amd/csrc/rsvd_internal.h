@@ -64,6 +64,13 @@ hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T
 hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s);
 
+// G (n x n, FP64, ld n) = A^T A for fp32 A with n > 128 (upper tile pairs,
+// mirrored); P is scratch of p_cap doubles for the partial tiles.
+hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
+                           int64_t p_cap, double* G, hipStream_t s);
+// Whether launch_syrk_f32 takes this operand (16-byte rows, n > 128).
+bool syrk_f32_applies(const float* A, int64_t n, int64_t lda);
+
 // Partials P[s] (n x c, FP64) of A^T Q over row splits; C = compute type of
 // the matrix-core product (double gives an exact-product FP64 Gram for float
 // data).  *nsplit returns the number of partial matrices written.

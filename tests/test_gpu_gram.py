@@ -49,7 +49,8 @@ def test_config1_fp64_gram_route(plans):
 
 
 @pytest.mark.parametrize("m,n,ucols", [(20000, 96, 96), (4099, 131, 40), (300, 257, 0), (64, 64, 64),
-                                         (3001, 259, 200), (4096, 256, 256)])
+                                         (3001, 259, 200), (4096, 256, 256),
+                                         (5001, 260, 0), (140, 132, 132)])
 def test_fp32_gram_route(plans, m, n, ucols):
     announce(f"gram fp32 m={m} n={n} ucols={ucols}")
     rng = np.random.default_rng(m + n)

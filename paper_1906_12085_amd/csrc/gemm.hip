@@ -489,6 +489,240 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
   if (gi < n && gj + 1 < n) { G[gi * ldg + gj + 1] = s1; if (I != J) G[(gj + 1) * ldg + gi] = s1; }
 }
 
+// ---------------------------------------------------------------------------
+// Tall passes with a narrow right factor (c <= 128; the sketch and power
+// iterations, Sec. 3.1.2 steps 2, 3 and 5), fp32 on 16x16x4 matrix cores
+// (exact tiles for any c that is a multiple of 16).
+//
+// Y = A Xt^T (Xt is c x n): block = 256 rows of A x all c columns, 4 waves of
+// 64 rows (4 x NT tiles); chunks of kTK = 32 along k of both operands staged
+// row-major in LDS (two buffers).  The next chunk's buffer loads are issued
+// before the multiply, its LDS writes interleaved into the last slab, the
+// FP64 sum of squares of A (Eq. sumeigen) taken from the loaded chunk.
+// Requires n % kTK == 0 and 16-byte rows (the descriptor ends at the last
+// valid row; the k range is whole).
+constexpr int kTM = 256, kTK = 32, kTLD = kTK + 4;
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_gemm_nt_tall(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part) {
+  constexpr int BC = 16 * NT;
+  constexpr int XU = (BC * (kTK / 4) + 255) / 256;   // float4 of the Xt chunk per thread
+  __shared__ __attribute__((aligned(16))) float As[2][kTM * kTLD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BC * kTLD];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kTM;
+  const int64_t rows = m - row0 < kTM ? m - row0 : kTM;
+  const int nch = (int)(n / kTK);
+  const bool do_ss = fro2_part != nullptr;
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(Xt), 0, (int)((int64_t)c * ldxt * 4), kBufDword3);
+  int voa[8], vox[XU];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int idx = tid + u * 256;
+    voa[u] = (int)(((idx >> 3) * lda + 4 * (idx & 7)) * 4);
+  }
+#pragma unroll
+  for (int u = 0; u < XU; ++u) {
+    const int idx = tid + u * 256;
+    vox[u] = (int)(((idx >> 3) * ldxt + 4 * (idx & 7)) * 4);
+  }
+  f32x4 ra[8], rx[XU];
+  auto load = [&](int ch) {
+    const int so = ch * kTK * 4;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[u], so, 0));
+#pragma unroll
+    for (int u = 0; u < XU; ++u)
+      if (tid + u * 256 < BC * (kTK / 4))
+        rx[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, vox[u], so, 0));
+  };
+  double ss = 0.0;
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      *reinterpret_cast<f32x4*>(&As[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = ra[u];
+      if (do_ss) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ss = fma((double)ra[u][i], (double)ra[u][i], ss);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int idx = tid + u * 256;
+      if (idx < BC * (kTK / 4))
+        *reinterpret_cast<f32x4*>(&Bs[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = rx[u];
+    }
+  };
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // slab of 16 k: lane (lr, g) reads k = 16 s + 4 g .. +3 with one 16-byte
+  // load; step t contracts over k = 16 s + 4 g + t on both operands
+  auto slab = [&](int buf, int s) {
+    f32x4 af[4], bf[NT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][(wave * 64 + 16 * i + lr) * kTLD + 16 * s + 4 * g]);
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][(16 * j + lr) * kTLD + 16 * s + 4 * g]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[i][t], bf[j][t], acc[i][j]);
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  static_assert(kTK == 32, "two slabs per chunk");
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    load(more ? ch + 1 : ch);                  // the last prefetch is a harmless repeat
+    __builtin_amdgcn_sched_barrier(0);
+    slab(buf, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    slab(buf, 1);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + wave * 64 + 16 * i + Mfma<float>::row(lane, e);
+        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+      }
+    }
+  if (do_ss) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) fro2_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// Z partials (n x c per row split, FP64) of A^T Q: block = one row split of
+// A and Q, all n (up to kUA per column tile) x c outputs; 8 waves of 64 A
+// columns (4 x NT tiles); chunks of kUK = 16 rows staged row-major in LDS
+// (row strides = 16 mod 64 floats, so the four 16-lane groups of a read hit
+// disjoint banks).  16x16x4 steps contract over four rows: lane (lr, g)
+// supplies A[row 4t + g][column lr of its tile] and Q[row 4t + g][column lr].
+// Columns past n or c only feed outputs that are not written; rows past the
+// split end read as zero (descriptor size).
+constexpr int kUK = 16, kUA = 512, kUALD = kUA + 16;
+
+template <int NT>
+__global__ __launch_bounds__(512) void k_gemm_tn_tall(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
+    int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P) {
+  constexpr int BC = 16 * NT;
+  constexpr int QLD = BC + ((16 - BC) % 64 + 64) % 64;
+  constexpr int QU = BC / 4 * kUK;               // float4 of the Q chunk
+  __shared__ __attribute__((aligned(16))) float As[2][kUK * kUALD];
+  __shared__ __attribute__((aligned(16))) float Qs[2][kUK * QLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int ta = blockIdx.x % ntile;
+  const int64_t sp = blockIdx.x / ntile;
+  const int64_t row0 = sp * rps;
+  const int64_t rows = m - row0 < rps ? m - row0 : rps;
+  const int nch = (int)((rows + kUK - 1) / kUK);
+  const int col0 = ta * kUA;
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
+  const __amdgpu_buffer_rsrc_t qr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(Q + row0 * ldq), 0, (int)(rows * ldq * 4), kBufDword3);
+  // A chunk: 16 rows x 128 float4 (4 per thread); Q chunk: 16 rows x BC/4
+  int voa[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid + u * 512;
+    voa[u] = (int)(((idx >> 7) * lda + col0 + 4 * (idx & 127)) * 4);
+  }
+  const int qr_row = tid / (BC / 4), qr_q = tid % (BC / 4);
+  const int voq = (int)((qr_row * ldq + 4 * qr_q) * 4);
+  const bool has_q = tid < QU;
+  f32x4 ra[4], rq;
+  auto load = [&](int ch) {
+    const int sa = (int)((int64_t)ch * kUK * lda * 4), sq = (int)((int64_t)ch * kUK * ldq * 4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[u], sa, 0));
+    if (has_q) rq = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, sq, 0));
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + u * 512;
+      *reinterpret_cast<f32x4*>(&As[buf][(idx >> 7) * kUALD + 4 * (idx & 127)]) = ra[u];
+    }
+    if (has_q) *reinterpret_cast<f32x4*>(&Qs[buf][qr_row * QLD + 4 * qr_q]) = rq;
+  };
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto steps = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kUK / 4; ++t) {
+      const float* arow = &As[buf][(4 * t + g) * kUALD + wave * 64 + lr];
+      const float* qrow = &Qs[buf][(4 * t + g) * QLD + lr];
+      float af[4], bf[NT];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = arow[16 * i];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bf[j] = qrow[16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[i], bf[j], acc[i][j]);
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    load(more ? ch + 1 : ch);
+    __builtin_amdgcn_sched_barrier(0);
+    steps(buf);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = P + sp * n * (int64_t)c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = col0 + wave * 64 + 16 * i + Mfma<float>::row(lane, e);
+        if (row < n && col < c) out[row * c + col] = (double)acc[i][j][e];
+      }
+    }
+}
+
 template <typename T, int NT, int MR>
 hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                        int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
@@ -792,6 +1026,70 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 }  // namespace
 
 // ---------------------------------------------------------------------------
+bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c) {
+  return c >= 1 && c <= 128 && n % kTK == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
+         (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Xt) % 16) == 0 && (ldxt % 4) == 0 &&
+         (int64_t)kTM * lda * 4 < (1LL << 31) && (int64_t)c * ldxt * 4 < (1LL << 31);
+}
+
+hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                               int64_t ldxt, int c, float* Y, int64_t ldy, double* fro2_part,
+                               int* nparts, hipStream_t s) {
+  if (!nt_tall_applies(A, n, lda, Xt, ldxt, c)) return hipErrorInvalidValue;
+  const int64_t nblk = (m + kTM - 1) / kTM;
+  if (nparts) *nparts = (int)nblk;
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblk), block(256);
+#define RSVD_NT_TALL(NT)                                                                      \
+  case NT:                                                                                    \
+    hipLaunchKernelGGL(k_gemm_nt_tall<NT>, grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, Y, ldy, \
+                       fro2_part);                                                            \
+    break;
+  switch ((c + 15) / 16) {
+    RSVD_NT_TALL(1) RSVD_NT_TALL(2) RSVD_NT_TALL(3) RSVD_NT_TALL(4)
+    RSVD_NT_TALL(5) RSVD_NT_TALL(6) RSVD_NT_TALL(7) RSVD_NT_TALL(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_NT_TALL
+  return hipGetLastError();
+}
+
+bool tn_tall_applies(const float* A, int64_t lda, const float* Q, int64_t ldq, int c) {
+  return c >= 1 && c <= 128 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (lda % 4) == 0 &&
+         (reinterpret_cast<uintptr_t>(Q) % 16) == 0 && (ldq % 4) == 0;
+}
+
+hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                               hipStream_t s) {
+  if (!tn_tall_applies(A, lda, Q, ldq, c) || m <= 0) return hipErrorInvalidValue;
+  const int ntile = (int)((n + kUA - 1) / kUA);
+  // about one block per CU (256), whole 16-row chunks
+  int64_t ns = 256 / ntile;
+  if (ns < 1) ns = 1;
+  if (ns > (m + kUK - 1) / kUK) ns = (m + kUK - 1) / kUK;
+  if (ns > max_split) ns = max_split;
+  int64_t rps = (m + ns - 1) / ns;
+  rps = (rps + kUK - 1) / kUK * kUK;
+  ns = (m + rps - 1) / rps;
+  const int64_t ld = lda > ldq ? lda : ldq;
+  if (rps * ld * 4 >= (1LL << 31) || (int64_t)(kUK - 1) * lda * 4 + (int64_t)ntile * kUA * 4 >= (1LL << 31))
+    return hipErrorInvalidValue;
+  *nsplit = (int)ns;
+  const dim3 grid((unsigned)(ns * ntile)), block(512);
+#define RSVD_TN_TALL(NT)                                                                          \
+  case NT:                                                                                        \
+    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps, ntile, P); \
+    break;
+  switch ((c + 15) / 16) {
+    RSVD_TN_TALL(1) RSVD_TN_TALL(2) RSVD_TN_TALL(3) RSVD_TN_TALL(4)
+    RSVD_TN_TALL(5) RSVD_TN_TALL(6) RSVD_TN_TALL(7) RSVD_TN_TALL(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_TN_TALL
+  return hipGetLastError();
+}
+
 hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
                            int64_t p_cap, double* G, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;

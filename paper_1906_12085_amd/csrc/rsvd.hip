@@ -182,8 +182,15 @@ struct Path {
   hipError_t tn(const T* A, int64_t m, int64_t n, int64_t lda, const T* Q, int64_t ldq, int c,
                 double* Z) {
     int ns = 0;
-    hipError_t e = launch_gemm_tn_partial<T, T>(A, m, n, lda, Q, ldq, c, p->part, p->max_split,
-                                                &ns, s);
+    hipError_t e;
+    if (std::is_same<T, float>::value &&
+        tn_tall_applies(reinterpret_cast<const float*>(A), lda, reinterpret_cast<const float*>(Q),
+                        ldq, c))
+      e = launch_gemm_tn_tall(reinterpret_cast<const float*>(A), m, n, lda,
+                              reinterpret_cast<const float*>(Q), ldq, c, p->part, p->max_split,
+                              &ns, s);
+    else
+      e = launch_gemm_tn_partial<T, T>(A, m, n, lda, Q, ldq, c, p->part, p->max_split, &ns, s);
     if (e != hipSuccess) return e;
     return launch_reduce_partials(p->part, ns, n, c, Z, c, s);
   }
@@ -245,10 +252,24 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
     RSVD_CHECK(launch_gaussian_fill(p->seed, n, l, p->omega, s));
     omega = p->omega;
   }
-  RSVD_CHECK(launch_cast_from_f64<T>(omega, n, l, l, Xs, l, s));
+  // fp32 passes with a narrow right factor take it transposed (l x n)
+  const bool tall = std::is_same<T, float>::value &&
+                    nt_tall_applies(reinterpret_cast<const float*>(A), n, lda,
+                                    reinterpret_cast<const float*>(Xs), n, l);
+  auto pass_nn = [&](const double* X64, double* fro2_part, int* np) -> hipError_t {
+    hipError_t e;
+    if (tall) {
+      if ((e = launch_cast_t_from_f64<T>(X64, n, l, l, Xs, n, s)) != hipSuccess) return e;
+      return launch_gemm_nt_tall(reinterpret_cast<const float*>(A), m, n, lda,
+                                 reinterpret_cast<const float*>(Xs), n, l,
+                                 reinterpret_cast<float*>(Y), l, fro2_part, np, s);
+    }
+    if ((e = launch_cast_from_f64<T>(X64, n, l, l, Xs, l, s)) != hipSuccess) return e;
+    return launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Y, l, fro2_part, np, s);
+  };
   // step 2: H = A G, with ||A||_F^2 (Eq. sumeigen) from the same pass
   int np = 0;
-  RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Y, l, p->fro2_part, &np, s));
+  RSVD_CHECK(pass_nn(omega, p->fro2_part, &np));
   RSVD_CHECK(launch_reduce_scalar(p->fro2_part, np, p->scal, s));
   RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
   // step 3: power iterations H = A (A^T H), orthonormalised after each product
@@ -256,8 +277,7 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
     RSVD_CHECK(P.tn(A, m, n, lda, Q1, l, l, p->Zd));
     RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));  // A^T Q
     RSVD_CHECK(cqr2_small(p, p->Z2, n, l, p->Zq));
-    RSVD_CHECK(launch_cast_from_f64<T>(p->Zq, n, l, l, Xs, l, s));
-    RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Y, l, nullptr, nullptr, s));
+    RSVD_CHECK(pass_nn(p->Zq, nullptr, nullptr));
     RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
   }
   // step 5: T = A^T Q
@@ -497,6 +517,11 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
       RSVD_CHECK(launch_transpose_f32((const float*)X, n, c, ldx, (float*)plan->Xs, n, s));
       RSVD_CHECK(launch_gemm_nt_wide((const float*)A, m, n, lda, (const float*)plan->Xs, n, c,
                                      (float*)Y, ldy, s));
+    } else if (c <= 128 && n <= plan->n_max &&
+               nt_tall_applies((const float*)A, n, lda, (const float*)plan->Xs, n, c)) {
+      RSVD_CHECK(launch_transpose_f32((const float*)X, n, c, ldx, (float*)plan->Xs, n, s));
+      RSVD_CHECK(launch_gemm_nt_tall((const float*)A, m, n, lda, (const float*)plan->Xs, n, c,
+                                     (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     } else {
       RSVD_CHECK(launch_gemm_nn<float>((const float*)A, m, n, lda, (const float*)X, ldx, c,
                                        (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));

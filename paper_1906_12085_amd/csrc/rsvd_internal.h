@@ -64,6 +64,19 @@ hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T
 hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s);
 
+// Y (m x c) = A Xt^T for fp32 with c <= 128 (Xt is c x n), optional per-block
+// FP64 partial sums of a_ij^2 (*nparts of them); requires nt_tall_applies.
+bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c);
+hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                               int64_t ldxt, int c, float* Y, int64_t ldy, double* fro2_part,
+                               int* nparts, hipStream_t s);
+// Partials P[s] (n x c, FP64) of A^T Q for fp32 with c <= 128 (16-byte rows);
+// *nsplit returns their number.
+bool tn_tall_applies(const float* A, int64_t lda, const float* Q, int64_t ldq, int c);
+hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                               hipStream_t s);
+
 // G (n x n, FP64, ld n) = A^T A for fp32 A with n > 128 (upper tile pairs,
 // mirrored); P is scratch of p_cap doubles for the partial tiles.
 hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
@@ -97,6 +110,11 @@ int64_t tn_max_split(int64_t m, int64_t n, int c);
 // ---- small FP64 kernels (small.hip) ----
 hipError_t launch_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G,
                                 hipStream_t s);
+// Casts between the FP64 staging copies and the working type (row-major);
+// the _t variant writes dst (cols x rows, ld ldd) = src^T.
+template <typename T>
+hipError_t launch_cast_t_from_f64(const double* src, int64_t rows, int64_t cols, int64_t lds,
+                                  T* dst, int64_t ldd, hipStream_t s);
 template <typename T>
 hipError_t launch_cast_from_f64(const double* src, int64_t rows, int64_t cols, int64_t lds,
                                 T* dst, int64_t ldd, hipStream_t s);

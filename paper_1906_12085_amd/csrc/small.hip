@@ -53,6 +53,16 @@ __global__ void k_cast(const S* __restrict__ src, int64_t rows, int64_t cols, in
   dst[i * ldd + j] = (D)src[i * lds + j];
 }
 
+// dst (cols x rows) = src^T, consecutive threads writing consecutive dst.
+template <typename S, typename D>
+__global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
+                         D* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  dst[j * ldd + i] = (D)src[i * lds + j];
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky W = R^T R (R upper, positive diagonal) and Rinv = R^-1, one block,
 // both c x c (c <= 96) in LDS.  Phase 1, symmetric Gaussian elimination
@@ -443,6 +453,15 @@ hipError_t launch_cast_from_f64(const double* src, int64_t rows, int64_t cols, i
 }
 
 template <typename T>
+hipError_t launch_cast_t_from_f64(const double* src, int64_t rows, int64_t cols, int64_t lds, T* dst,
+                                  int64_t ldd, hipStream_t s) {
+  if (rows * cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cast_t<double, T>), dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, src,
+                     rows, cols, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t lds, double* dst,
                               int64_t ldd, hipStream_t s) {
   if (rows * cols <= 0) return hipSuccess;
@@ -536,6 +555,8 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
 }
 
 #define RSVD_INST(T)                                                                               \
+  template hipError_t launch_cast_t_from_f64<T>(const double*, int64_t, int64_t, int64_t, T*,      \
+                                                 int64_t, hipStream_t);                             \
   template hipError_t launch_cast_from_f64<T>(const double*, int64_t, int64_t, int64_t, T*,        \
                                               int64_t, hipStream_t);                               \
   template hipError_t launch_cast_to_f64<T>(const T*, int64_t, int64_t, int64_t, double*, int64_t, \

@@ -52,6 +52,9 @@ NN_CASES = [
     (300, 64, 17, 4),      # padded leading dimension, c not a multiple of 16
     (5000, 256, 96, 0),
     (777, 150, 200, 0),    # c > 128: several column tiles
+    (4133, 64, 80, 0),     # fp32 tall kernel (n % 32 == 0): ragged last row block
+    (1000, 512, 128, 0),   # fp32 tall kernel at its widest (8 column tiles)
+    (515, 32, 1, 0),       # one column
 ]
 
 
@@ -70,7 +73,8 @@ def test_gemm_nn_parity(plans, name, m, n, c, pad):
     want_gram = c <= 96
     Gm = torch.empty(c, c, dtype=torch.float64, device="cuda") if want_gram else None
     f2 = torch.empty(1, dtype=torch.float64, device="cuda")
-    rs.rsvd_gemm_nn(plans[name].handle, A, X, Y, Gram=Gm, fro2=f2)
+    p = plans[name] if n <= 300 else big_plans(name)
+    rs.rsvd_gemm_nn(p.handle, A, X, Y, Gram=Gm, fro2=f2)
     torch.cuda.synchronize()
     Yref = oracle.gemm_nn(A0, X0)
     bound = 2.0 * n * unit(dt) * (np.abs(A0) @ np.abs(X0)) + 1e-300
@@ -107,7 +111,7 @@ def test_gemm_nn_wide_parity(plans, name, m, n, c, pad):
     A = dev(np.pad(A0, ((0, 0), (0, pad))), dt)[:, :n]
     X = dev(X0, dt)
     Y = torch.full((m, c), float("nan"), dtype=dt, device="cuda")
-    p = plans[name] if c <= 300 else big_plans(name)
+    p = plans[name] if c <= 300 and n <= 300 else big_plans(name)
     rs.rsvd_gemm_nn(p.handle, A, X, Y)
     torch.cuda.synchronize()
     Yref = oracle.gemm_nn(A0, X0)
@@ -120,11 +124,12 @@ _BIG = {}
 
 def big_plans(name):
     if name not in _BIG:
-        _BIG[name] = rs.Plan(6000, 512, 96, DTYPES[name], want_gram=True, seed=7)
+        _BIG[name] = rs.Plan(6000, 640, 96, DTYPES[name], want_gram=True, seed=7)
     return _BIG[name]
 
 
-TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100, 97, 96)]
+TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100, 97, 96),
+            (4099, 512, 80), (1000, 600, 128), (70, 64, 3), (2000, 36, 48)]
 
 
 @pytest.mark.parametrize("name", DTYPES)
@@ -136,7 +141,8 @@ def test_gemm_tn_parity(plans, name, m, n, c):
     A0 = rounded(rng.standard_normal((m, n)), dt)
     Q0 = rounded(rng.standard_normal((m, c)), dt)
     Z = torch.empty(n, c, dtype=torch.float64, device="cuda")
-    rs.rsvd_gemm_tn(plans[name].handle, dev(A0, dt), dev(Q0, dt), Z)
+    p = plans[name] if n <= 300 else big_plans(name)
+    rs.rsvd_gemm_tn(p.handle, dev(A0, dt), dev(Q0, dt), Z)
     torch.cuda.synchronize()
     Zref = oracle.gemm_tn(A0, Q0)
     # partial sums over at most m rows in the product precision, then FP64

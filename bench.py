@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM counters)")
     ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
@@ -60,27 +61,97 @@ def algorithmic_counts(m, n, k, l, q, b):
     return rs_flops, rs_bytes, gr_flops, gr_bytes
 
 
+# Algorithmic work per launch of each timed kernel (flops, HBM bytes, the
+# unit it is bounded by) and its kernel name in a rocprofv3 trace.
+#   eigensolver: the paper's count for the eigen-decomposition of the n x n
+#     Gram matrix, n^3 multiply-adds (Sec. 3.1.3), i.e. 2 n^3 flops in FP64;
+#     its inputs live in L2/MALL, so it is reported against the FP64 vector
+#     peak ("alu").
+#   pass_nn / pass_tn: one pass over A with the l-column panel, 2 m n l flops,
+#     m n + m l fp32 elements moved.
+#   syrk: the symmetric A^T A, m n (n + 1) flops, A read once.
+#   nn_wide: U = A V S^-1 with all n columns, 2 m n n flops, A read, U written.
+KERNEL_INFO = {
+    "eigensolver": ("k_jacobi_eig", "alu"),
+    "pass_nn": ("k_gemm_nt_tall", "fp32"),
+    "pass_tn": ("k_gemm_tn_tall", "fp32"),
+    "syrk": ("k_syrk_f32", "fp32"),
+    "nn_wide": ("k_gemm_nt_wide", "fp32"),
+}
+
+
+# HBM bytes per launch at the 1e6 x 512 fp32 step, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
+# plain 1 GiB device copy (FETCH_SIZE 0.5 x the bytes read, WRITE_SIZE 1.0 x
+# the bytes written).  Each figure holds only for the kernel source it was
+# taken on (first 16 hex digits of the file's SHA-256); otherwise it is null.
+TRAFFIC = {
+    "eigensolver": (3.2997e9, "paper_1906_12085_amd/csrc/eig.hip", "a08a574edd1e00c9"),
+    "pass_nn": (2.4139e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
+    "pass_tn": (2.4520e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
+    "syrk": (2.4482e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
+    "nn_wide": (4.6165e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
+}
+TRAFFIC_SHAPE = (1_000_000, 512, 80)
+
+
+def traffic_bytes(kind, m, n, l):
+    import hashlib
+    if kind not in TRAFFIC or (m, n, l) != TRAFFIC_SHAPE:
+        return None
+    nbytes, path, digest = TRAFFIC[kind]
+    with open(os.path.join(ROOT, path), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != digest:
+            return None
+    return nbytes
+
+
+def kernel_work(kind, m, n, l, b):
+    if kind == "eigensolver":
+        return 2.0 * n ** 3, 0.0
+    if kind in ("pass_nn", "pass_tn"):
+        return 2.0 * m * n * l, (m * n + m * l) * b
+    if kind == "syrk":
+        return m * n * (n + 1.0), m * n * b
+    return 2.0 * m * n * n, 2.0 * m * n * b
+
+
+def kernel_rooflines(ktimes, m, n, l, b, steps):
+    rows = {}
+    for kind, (ms, launches) in ktimes.items():
+        if launches == 0 or ms <= 0:
+            continue
+        name, unit = KERNEL_INFO[kind]
+        flops, nbytes = kernel_work(kind, m, n, l, b)
+        sec = ms / 1e3
+        if unit == "alu":
+            bound, peak, ach, u = "alu", PEAK_TFLOPS["fp64"], flops / sec / 1e12, "TFLOP/s"
+        else:
+            ai = flops / nbytes
+            if ai * PEAK_HBM_GBS / 1000.0 >= PEAK_TFLOPS["fp32"]:
+                bound, peak, ach, u = "mfma", PEAK_TFLOPS["fp32"], flops / sec / 1e12, "TFLOP/s"
+            else:
+                bound, peak, ach, u = "hbm", PEAK_HBM_GBS, nbytes / sec / 1e9, "GB/s"
+        rows[kind] = {"kernel": name, "bound": bound, "achieved": round(ach, 4), "peak": peak,
+                      "unit": u, "frac": round(ach / peak, 5),
+                      "traffic": traffic_bytes(kind, m, n, l), "launch_ms": round(ms, 4),
+                      "launches_per_step": round(launches / steps, 2),
+                      "ms_per_step": round(ms * launches / steps, 3),
+                      "work_per_launch": {"flops": flops, "bytes": nbytes}}
+    dom = max(rows.values(), key=lambda r: r["ms_per_step"])
+    roof = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+            "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
+            "kernel": dom["kernel"], "launch_ms": dom["launch_ms"],
+            "ms_per_step": dom["ms_per_step"]}
+    return roof, rows
+
+
 def pct(xs, p):
     xs = sorted(xs)
     if not xs:
         return None
     i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
     return xs[i]
-
-
-def time_kernel(fn, reps, stream):
-    """Average duration of one launch of `fn` (one kernel), HIP events on `stream`."""
-    import torch
-    fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps / 1000.0  # seconds
 
 
 def main():
@@ -90,7 +161,6 @@ def main():
                                    "design is documented but not built (use --gpus 1)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1906_12085_amd as rs
@@ -140,17 +210,31 @@ def main():
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # per-kernel launch durations inside the timed steps: HIP events recorded
+    # by the library on the plan's stream around each timed kernel
+    rs.rsvd_plan_kernel_times(plan.handle, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ktimes = rs.rsvd_plan_kernel_times(plan.handle, False)
     wall = t1 - t0
     rs_ms = [e[0].elapsed_time(e[1]) for e in evs]
     gr_ms = [e[1].elapsed_time(e[2]) for e in evs]
     step_ms = [e[0].elapsed_time(e[2]) for e in evs]
     status = rs.rsvd_plan_status(plan.handle)
+
+    if args.pmc_copy:
+        # a plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read
+        # for it converts those counters to HBM bytes for the kernels above
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # accuracy of this run's rSVD: FP32 path vs the FP64 path of the same
     # library on the same stored A and sketch (the oracle comparison at this
@@ -163,46 +247,10 @@ def main():
     del A64
     torch.cuda.empty_cache()
 
-    # dominant-kernel roofline: the passes over A, timed one launch at a time
-    # through the stage entry points (same kernels and launch shapes as in the
-    # solve) with HIP events on the plan's stream
+    # roofline of the dominant kernel (largest time per step), from the
+    # live launch durations of the timed steps and the algorithmic counts
     b = 4
-    Xs = torch.randn(n, l, dtype=torch.float32, device=dev)
-    Yw = torch.empty(m, l, dtype=torch.float32, device=dev)
-    Zw = torch.empty(n, l, dtype=torch.float64, device=dev)
-    t_nn = time_kernel(lambda: rs.rsvd_gemm_nn(plan.handle, A, Xs, Yw), args.kernel_reps, stream)
-    flops_pass = 2.0 * m * n * l
-    bytes_nn = m * n * b + m * l * b
-    kernels = {
-        "k_gemm_nn (Y = A X, m x n x l)": dict(sec=t_nn, flops=flops_pass, bytes=bytes_nn,
-                                                per_step=q + 1),
-    }
-    # A^T Q: the split-m kernel plus its fixed-order reduction; the reduction
-    # is timed on its own and subtracted
-    t_tn_total = time_kernel(lambda: rs.rsvd_gemm_tn(plan.handle, A, Yw, Zw), args.kernel_reps,
-                             stream)
-    kernels["k_gemm_tn_partial+reduce (Z = A^T Q)"] = dict(
-        sec=t_tn_total, flops=flops_pass, bytes=m * n * b + m * l * b, per_step=q + 1)
-    dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["sec"] * kv[1]["per_step"])
-    achieved = dom["flops"] / dom["sec"] / 1e12
-    ai = dom["flops"] / dom["bytes"]
-    peak_c = PEAK_TFLOPS["fp32"]
-    bound = "mfma" if ai * PEAK_HBM_GBS / 1000.0 > peak_c else "hbm"
-    if bound == "mfma":
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak_c,
-                "unit": "TFLOP/s", "frac": round(achieved / peak_c, 4), "traffic": None}
-    else:
-        gbs = dom["bytes"] / dom["sec"] / 1e9
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}
-    roof["kernel"] = dom_name
-    roof["launch_ms"] = round(dom["sec"] * 1e3, 4)
-    roof["arith_intensity"] = round(ai, 2)
-    roof["all_passes"] = {kn: {"launch_ms": round(v["sec"] * 1e3, 4),
-                               "tflops": round(v["flops"] / v["sec"] / 1e12, 2),
-                               "gbs": round(v["bytes"] / v["sec"] / 1e9, 1)}
-                          for kn, v in kernels.items()}
-
+    roof, all_k = kernel_rooflines(ktimes, m, n, l, b, args.steps)
     rs_f, rs_b, gr_f, gr_b = algorithmic_counts(m, n, k, l, q, b)
     rs_med, gr_med = pct(rs_ms, 50), pct(gr_ms, 50)
     legs = {
@@ -217,7 +265,6 @@ def main():
                             "solves_per_s": round(1000.0 / gr_med, 2),
                             "tflops": round(gr_f / (gr_med / 1e3) / 1e12, 2),
                             "K": int(Kg.item())}
-    del Xs, Yw, Zw
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -250,6 +297,7 @@ def main():
         "status": rs.STATUS.get(status, status),
         "status_warmup": rs.STATUS.get(st, st),
         "roofline": roof,
+        "kernels": all_k,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -104,6 +104,22 @@ int32_t rsvd_plan_status(rsvd_plan_t plan);
  * Returns the number of values written. */
 int32_t rsvd_plan_diag(rsvd_plan_t plan, double* out, int32_t count);
 
+/* Per-kernel launch durations, measured with HIP events recorded on the
+ * plan's stream immediately before and after each launch of the timed
+ * kernels (no other work between them), for benchmarking against rooflines.
+ * Returns, for each kind i < count (at most 5): ms[i] = mean duration in
+ * milliseconds of the launches since the previous call, launches[i] = their
+ * number (at most 256 per kind are kept); kinds: [0] symmetric eigensolver
+ * of the A^T A route, [1] fp32 pass Y = A X with l <= 128 columns, [2] fp32
+ * pass A^T Q with l <= 128 columns (without its partial-sum reduction),
+ * [3] fp32 symmetric A^T A (without its reduction), [4] fp32 wide product
+ * A X (more than 128 columns).  Then clears the records and turns timing on
+ * (enable != 0) or off for later calls on this plan.  Synchronises the
+ * plan's stream.  Returns the number of kinds written, RSVD_ERR_ARG (NULL
+ * plan, count < 0, NULL arrays with count > 0), RSVD_ERR_NOMEM. */
+int32_t rsvd_plan_kernel_times(rsvd_plan_t plan, int32_t enable, double* ms, int32_t* launches,
+                               int32_t count);
+
 /* ------------------------------------------------------------- solvers --
  * rsvd_solve: Randomized PCA (Sec. 3.1.2) of A (m x n, lda) with target rank
  * k, oversampling p (sketch width l = min(k + p, n)) and q power iterations;

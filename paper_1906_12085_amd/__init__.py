@@ -35,7 +35,7 @@ RSVD_ERR_BREAKDOWN, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = -5, -6, -7
 EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_plan_status",
            "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
            "rsvd_gaussian_fill", "rsvd_gemm_nn", "rsvd_gemm_tn", "rsvd_cholqr2",
-           "rsvd_small_svd", "rsvd_sym_eig"]
+           "rsvd_small_svd", "rsvd_sym_eig", "rsvd_plan_kernel_times"]
 
 
 class RSVDError(RuntimeError):
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_cholqr2": (i32, [vp, vp, i64, i32, i64, vp, i64, vp]),
         "rsvd_small_svd": (i32, [vp, vp, i64, i32, vp, vp, vp]),
         "rsvd_sym_eig": (i32, [vp, vp, i64, vp, vp]),
+        "rsvd_plan_kernel_times": (i32, [vp, i32, vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -132,6 +133,20 @@ def rsvd_plan_diag(plan: int, count: int = 8):
     buf = (ctypes.c_double * count)()
     nc = _check(load_library().rsvd_plan_diag(plan, buf, count), "rsvd_plan_diag")
     return list(buf[:nc])
+
+
+KERNEL_KINDS = ["eigensolver", "pass_nn", "pass_tn", "syrk", "nn_wide"]
+
+
+def rsvd_plan_kernel_times(plan: int, enable: bool):
+    """Mean launch durations (ms) and launch counts per timed kernel kind since
+    the previous call; then timing is switched on or off for later calls."""
+    n = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int32 * n)()
+    nc = _check(load_library().rsvd_plan_kernel_times(plan, 1 if enable else 0, ms, cnt, n),
+                "rsvd_plan_kernel_times")
+    return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(nc)}
 
 
 def rsvd_solve(plan: int, A, k: int, p: int, q: int, t: float, U, S, V, K) -> int:

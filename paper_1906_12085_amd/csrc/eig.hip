@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
 template <int RPT>
 hipError_t eig_launch(double* X, double* J, int n, const Geom& G, int inner, double* lam,
                       double* diag, int32_t* flags, double* scratch, int32_t* status,
-                      hipStream_t s) {
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const size_t shmem = ((size_t)2 * kW * (16 * RPT + 1) + (size_t)3 * kW * kLdM) * sizeof(double);
   const void* fn = (const void*)k_jacobi_eig<RPT>;
   int dev = 0;
@@ -411,21 +411,27 @@ hipError_t eig_launch(double* X, double* J, int n, const Geom& G, int inner, dou
   double* fro_part = scratch + (size_t)2 * G.nwg * kW * kW;
   int nn = n, nbp = G.nbp, P = G.P, inn = inner;
   void* args[] = {&X, &J, &nn, &nbp, &P, &inn, &Mpart, &fro_part, &lam, &diag, &flags, &status};
-  return hipLaunchCooperativeKernel(fn, dim3(G.nwg), dim3(kThreads), args, shmem, s);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  e = hipLaunchCooperativeKernel(fn, dim3(G.nwg), dim3(kThreads), args, shmem, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return e;
 }
 
 }  // namespace
 
 hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
                              int32_t* flags, double* scratch, int32_t* status, hipStream_t s,
-                             int inner_sweeps) {
+                             int inner_sweeps, hipEvent_t ev0, hipEvent_t ev1) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   const Geom G = geom((int)n);
   const int inner = inner_sweeps < 0 ? kDefaultInner : (inner_sweeps < 1 ? 1 : inner_sweeps);
   switch (G.rpt) {
-    case 2: return eig_launch<2>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s);
-    case 4: return eig_launch<4>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s);
-    default: return eig_launch<8>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s);
+    case 2: return eig_launch<2>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
+                                     ev0, ev1);
+    case 4: return eig_launch<4>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
+                                     ev0, ev1);
+    default: return eig_launch<8>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
+                                     ev0, ev1);
   }
 }
 

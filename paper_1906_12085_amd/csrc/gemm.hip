@@ -1091,7 +1091,8 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
 }
 
 hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
-                           int64_t p_cap, double* G, hipStream_t s) {
+                           int64_t p_cap, double* G, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int ntile = (int)((n + kSyT - 1) / kSyT);
   const int npair = ntile * (ntile + 1) / 2;
@@ -1111,9 +1112,11 @@ hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, do
     return hipErrorInvalidValue;
   const int64_t nblk = nsplit * npair;
   const int64_t per_xcd = (nblk + 7) / 8;
+  if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL(k_syrk_f32, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, A, m, n, lda,
                      ntile, npair, rps, nblk, per_xcd, P);
   hipError_t e = hipGetLastError();
+  if (ev1) (void)hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_syrk_reduce, dim3((kSyT * kSyT / 2 + 255) / 256, npair), dim3(256), 0, s, P,
                      nsplit, npair, ntile, n, G, n);

@@ -25,7 +25,18 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// Per-kernel launch timing (off unless enabled by rsvd_plan_kernel_times):
+// HIP event pairs recorded on the plan's stream around one kind of kernel.
+enum KernelKind { KT_EIG = 0, KT_PASS_NN, KT_PASS_TN, KT_SYRK, KT_NT_WIDE, KT_COUNT };
+constexpr int kTimerPairs = 256;
+struct KernelTimer {
+  hipEvent_t ev[kTimerPairs][2] = {};
+  int used = 0;
+};
+
 struct rsvd_plan_s {
+  bool timing = false;
+  KernelTimer* kt = nullptr;   // KT_COUNT timers, allocated when timing is first enabled
   int device = 0;
   int dtype = RSVD_F64;
   int64_t m_max = 0, n_max = 0;
@@ -73,6 +84,37 @@ namespace {
 size_t elem_size(int dtype) { return dtype == RSVD_F64 ? sizeof(double) : sizeof(float); }
 
 // Carve the workspace; with base == nullptr it only counts bytes.
+// The next event pair of timer `kind` (both null when timing is off or the
+// pairs are used up).  The launcher records e0 on the plan's stream right
+// before the timed kernel and e1 right after it.
+struct KtPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+KtPair kt_reserve(rsvd_plan_s* p, int kind) {
+  KtPair r;
+  if (!p->timing || !p->kt) return r;
+  KernelTimer& t = p->kt[kind];
+  if (t.used >= kTimerPairs) return r;
+  hipEvent_t* pr = t.ev[t.used];
+  if (!pr[0] && (hipEventCreate(&pr[0]) != hipSuccess || hipEventCreate(&pr[1]) != hipSuccess))
+    return r;
+  ++t.used;
+  r.e0 = pr[0];
+  r.e1 = pr[1];
+  return r;
+}
+// Times one single-kernel launch: records e0 now and e1 when it goes out of scope.
+struct KtScope {
+  hipStream_t s;
+  KtPair pr;
+  KtScope(rsvd_plan_s* p, int kind) : s(p->stream), pr(kt_reserve(p, kind)) {
+    if (pr.e0) (void)hipEventRecord(pr.e0, s);
+  }
+  ~KtScope() {
+    if (pr.e1) (void)hipEventRecord(pr.e1, s);
+  }
+};
+
 int64_t p_cmax(const rsvd_plan_s* p) {
   return p->gram ? (p->n_max > p->l_max ? p->n_max : p->l_max) : p->l_max;
 }
@@ -186,9 +228,12 @@ struct Path {
     if (std::is_same<T, float>::value &&
         tn_tall_applies(reinterpret_cast<const float*>(A), lda, reinterpret_cast<const float*>(Q),
                         ldq, c))
+    {
+      KtScope ts(p, KT_PASS_TN);
       e = launch_gemm_tn_tall(reinterpret_cast<const float*>(A), m, n, lda,
                               reinterpret_cast<const float*>(Q), ldq, c, p->part, p->max_split,
                               &ns, s);
+    }
     else
       e = launch_gemm_tn_partial<T, T>(A, m, n, lda, Q, ldq, c, p->part, p->max_split, &ns, s);
     if (e != hipSuccess) return e;
@@ -260,6 +305,7 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
     hipError_t e;
     if (tall) {
       if ((e = launch_cast_t_from_f64<T>(X64, n, l, l, Xs, n, s)) != hipSuccess) return e;
+      KtScope ts(p, KT_PASS_NN);
       return launch_gemm_nt_tall(reinterpret_cast<const float*>(A), m, n, lda,
                                  reinterpret_cast<const float*>(Xs), n, l,
                                  reinterpret_cast<float*>(Y), l, fro2_part, np, s);
@@ -304,8 +350,9 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   // step 1: A^T A (Eq. AB), and its trace = ||A||_F^2 (Eq. sumeigen)
   if (std::is_same<T, float>::value &&
       syrk_f32_applies(reinterpret_cast<const float*>(A), n, lda)) {
+    const KtPair tp = kt_reserve(p, KT_SYRK);
     RSVD_CHECK(launch_syrk_f32(reinterpret_cast<const float*>(A), m, n, lda, p->part,
-                               p->max_split * p->n_max * p_cmax(p), p->Gd, s));
+                               p->max_split * p->n_max * p_cmax(p), p->Gd, s, tp.e0, tp.e1));
   } else {
     RSVD_CHECK(P.tn(A, m, n, lda, A, lda, (int)n, p->Gd));
   }
@@ -315,7 +362,11 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, p->Gd, n,
                      p->Xe, p->Je);
   RSVD_CHECK(hipGetLastError());
-  RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->Es, p->status, s));
+  {
+    const KtPair tp = kt_reserve(p, KT_EIG);
+    RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->Es, p->status, s,
+                                 -1, tp.e0, tp.e1));
+  }
   // step 3: s_i = sqrt(lambda_i) (Eq. LambdaSigma), sorted, sign rule
   RSVD_CHECK(launch_sqrt_clamp(p->lam, (int)n, p->Se, s));
   RSVD_CHECK(launch_sort_sign_scatter<T>(p->Se, (int)n, p->Je, n, 1, n, nullptr, (int)n, S, V,
@@ -326,6 +377,7 @@ int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
     if (std::is_same<T, float>::value && ucols > 128) {
       // wide fp32 product: the scaled V goes in transposed (ucols x n)
       RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, ucols, n, S, floor_rel, (T*)p->Xs, n, 1, s));
+      KtScope ts(p, KT_NT_WIDE);
       RSVD_CHECK(launch_gemm_nt_wide(reinterpret_cast<const float*>(A), m, n, lda,
                                      reinterpret_cast<const float*>(p->Xs), n, ucols,
                                      reinterpret_cast<float*>(U), ldu, s));
@@ -428,6 +480,13 @@ int32_t rsvd_plan_destroy(rsvd_plan_t plan) {
   if (hipSetDevice(plan->device) != hipSuccess) rc = RSVD_ERR_DEVICE;
   if (hipStreamSynchronize(plan->stream) != hipSuccess) rc = RSVD_ERR_DEVICE;
   if (plan->base && hipFree(plan->base) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  if (plan->kt) {
+    for (int k = 0; k < KT_COUNT; ++k)
+      for (int i = 0; i < kTimerPairs; ++i)
+        for (int j = 0; j < 2; ++j)
+          if (plan->kt[k].ev[i][j]) (void)hipEventDestroy(plan->kt[k].ev[i][j]);
+    delete[] plan->kt;
+  }
   delete plan;
   return rc;
 }
@@ -452,6 +511,35 @@ int32_t rsvd_plan_diag(rsvd_plan_t plan, double* out, int32_t count) {
   const int32_t nc = count < kDiagWords ? count : kDiagWords;
   if (nc > 0 && hipMemcpy(out, plan->diag, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return RSVD_ERR_DEVICE;
+  return nc;
+}
+
+int32_t rsvd_plan_kernel_times(rsvd_plan_t plan, int32_t enable, double* ms, int32_t* launches,
+                               int32_t count) {
+  if (!plan || count < 0 || (count > 0 && (!ms || !launches))) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return RSVD_ERR_DEVICE;
+  const int32_t nc = count < KT_COUNT ? count : KT_COUNT;
+  for (int k = 0; k < nc; ++k) {
+    double sum = 0.0;
+    int used = 0;
+    if (plan->kt) {
+      for (int i = 0; i < plan->kt[k].used; ++i) {
+        float e = 0.f;   // a pair left unrecorded by a failed launch is skipped
+        if (hipEventElapsedTime(&e, plan->kt[k].ev[i][0], plan->kt[k].ev[i][1]) != hipSuccess)
+          continue;
+        sum += e;
+        ++used;
+      }
+    }
+    ms[k] = used ? sum / used : 0.0;
+    launches[k] = used;
+  }
+  if (plan->kt)
+    for (int k = 0; k < KT_COUNT; ++k) plan->kt[k].used = 0;
+  if (enable && !plan->kt) plan->kt = new (std::nothrow) KernelTimer[KT_COUNT];
+  if (enable && !plan->kt) return RSVD_ERR_NOMEM;
+  plan->timing = enable != 0;
   return nc;
 }
 
@@ -515,11 +603,13 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
     if (c > 128 && !fro2 && n <= plan->n_max) {
       // wide product: X transposed into plan scratch (c x n <= cmax x n_max)
       RSVD_CHECK(launch_transpose_f32((const float*)X, n, c, ldx, (float*)plan->Xs, n, s));
+      KtScope ts(plan, KT_NT_WIDE);
       RSVD_CHECK(launch_gemm_nt_wide((const float*)A, m, n, lda, (const float*)plan->Xs, n, c,
                                      (float*)Y, ldy, s));
     } else if (c <= 128 && n <= plan->n_max &&
                nt_tall_applies((const float*)A, n, lda, (const float*)plan->Xs, n, c)) {
       RSVD_CHECK(launch_transpose_f32((const float*)X, n, c, ldx, (float*)plan->Xs, n, s));
+      KtScope ts(plan, KT_PASS_NN);
       RSVD_CHECK(launch_gemm_nt_tall((const float*)A, m, n, lda, (const float*)plan->Xs, n, c,
                                      (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     } else {
@@ -596,8 +686,9 @@ int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, 
   hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, G, n,
                      plan->Xe, plan->Je);
   RSVD_CHECK(hipGetLastError());
+  const KtPair tp = kt_reserve(plan, KT_EIG);
   RSVD_CHECK(launch_jacobi_eig(plan->Xe, plan->Je, n, plan->lam, plan->diag, plan->flags,
-                               plan->Es, plan->status, s));
+                               plan->Es, plan->status, s, -1, tp.e0, tp.e1));
   RSVD_CHECK(launch_sort_sign_scatter<double>(plan->lam, (int)n, plan->Je, n, 1, n, nullptr,
                                               (int)n, lam, nullptr, 0, V, nullptr, s));
   return RSVD_OK;

@@ -78,9 +78,11 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
                                hipStream_t s);
 
 // G (n x n, FP64, ld n) = A^T A for fp32 A with n > 128 (upper tile pairs,
-// mirrored); P is scratch of p_cap doubles for the partial tiles.
+// mirrored); P is scratch of p_cap doubles for the partial tiles.  ev0/ev1,
+// when given, are recorded around the tile kernel (not the reduction).
 hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* P,
-                           int64_t p_cap, double* G, hipStream_t s);
+                           int64_t p_cap, double* G, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 // Whether launch_syrk_f32 takes this operand (16-byte rows, n > 128).
 bool syrk_f32_applies(const float* A, int64_t n, int64_t lda);
 
@@ -149,10 +151,12 @@ hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double
 // +-||x_j|| (sign of the Rayleigh quotient j_j^T x_j) and the eigenvectors
 // are the columns of J (unsorted).  `flags` holds jacobi_eig_flag_words()
 // int32 words and `scratch` jacobi_eig_scratch_doubles(n) doubles; sweeps
-// used go to diag[2].  inner_sweeps < 0 selects the default.
+// used go to diag[2].  inner_sweeps < 0 selects the default; ev0/ev1, when
+// given, are recorded around the solver kernel itself.
 hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
                              int32_t* flags, double* scratch, int32_t* status, hipStream_t s,
-                             int inner_sweeps = -1);
+                             int inner_sweeps = -1, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 // Doubles of scratch launch_jacobi_eig needs for matrices up to n.
 int64_t jacobi_eig_scratch_doubles(int64_t n);
 

@@ -68,6 +68,7 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_plan_status(None) == -1
     assert lib.rsvd_plan_destroy(None) == 0
     assert lib.rsvd_gaussian_fill(1, 4, 4, None, None) == -1
+    assert lib.rsvd_plan_kernel_times(None, 1, None, None, 0) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -41,13 +41,15 @@ constexpr int kMaxGroups = 256;
 constexpr int kMaxSlices = 8;                 // row slices per block pair
 
 // flag words: grid-barrier counter, abort flag, per-sweep count of block
-// pairs found unconverged, per-pair arrival counters, per-workgroup step counters
+// pairs found unconverged, per-pair arrival counters, per-workgroup step
+// counters for X and for J
 constexpr int kFlagBar = 0;
 constexpr int kFlagAbort = 1;
 constexpr int kFlagRot = 2;
 constexpr int kFlagPair = kFlagRot + kMaxSweeps;
-constexpr int kFlagDone = kFlagPair + kMaxPairs;
-constexpr int kFlagWords = kFlagDone + kMaxGroups;
+constexpr int kFlagDone = kFlagPair + kMaxPairs;      // steps whose X rows are out
+constexpr int kFlagDoneJ = kFlagDone + kMaxGroups;    // steps whose J rows are out
+constexpr int kFlagWords = kFlagDoneJ + kMaxGroups;
 
 // Launch geometry for n: block pairs, rows per slice (16 * rpt), slices per pair.
 struct Geom {
@@ -170,6 +172,43 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
   const double tol = kEps * (double)n, tol2 = tol * tol;
   const double floor = kEps * kEps * fro2;
 
+  // Stage this slice of the pair's kW columns of a matrix (X or J) into LDS,
+  // all loads issued before the first store.
+  auto stage = [&](const double* Mg, double* Ms, int I, int Jb) {
+    constexpr int PER = kW * RS / kThreads;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kThreads, c = e / RS, i = e - c * RS;
+      const int gc = c < kB ? I * kB + c : Jb * kB + (c - kB);
+      v[u] = (gc < n && i < nrow) ? ld_agent(Mg + (int64_t)gc * n + row0 + i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kThreads, c = e / RS, i = e - c * RS;
+      Ms[c * LDX + i] = v[u];
+    }
+  };
+  // Mg_W <- Mg_W R on this slice from its LDS copy Ms, formed as (R^T S^T)^T
+  // so that 16 consecutive lanes store 16 consecutive rows of a column.
+  auto apply = [&](const double* Ms, double* Mg, int I, int Jb) {
+    for (int tile = wave; tile < 2 * RPT; tile += 4) {
+      const int jt = tile & 1, rt = tile >> 1;
+      const double* ap = Rl + (lane >> 4) * kLdM + jt * 16 + (lane & 15);
+      const double* bp = Ms + (lane >> 4) * LDX + rt * 16 + (lane & 15);
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < kW; k0 += 4) acc = Mfma<double>::run(ap[k0 * kLdM], bp[k0 * LDX], acc);
+      const int row = rt * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = jt * 16 + Mfma<double>::row(lane, e);
+        const int gc = j < kB ? I * kB + j : Jb * kB + (j - kB);
+        if (gc < n && row < nrow) st_agent(Mg + (int64_t)gc * n + row0 + row, acc[e]);
+      }
+    }
+  };
+
   // thread roles in the inner rounds: pair a of rows, pair bq of columns
   const int a = tid >> 4, bq = tid & 15;
   int sweep = 0;
@@ -194,26 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
         __syncthreads();
         if (!sh_ok) { aborted = true; break; }
       }
-      // stage this slice of the pair's columns of X and J
-      {
-        constexpr int PER = kW * RS / kThreads;
-        double vx[PER], vj[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = tid + u * kThreads, c = e / RS, i = e - c * RS;
-          const int gc = c < kB ? I * kB + c : Jb * kB + (c - kB);
-          const bool in = gc < n && i < nrow;
-          const int64_t off = (int64_t)gc * n + row0 + i;
-          vx[u] = in ? ld_agent(X + off) : 0.0;
-          vj[u] = in ? ld_agent(J + off) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = tid + u * kThreads, c = e / RS, i = e - c * RS;
-          Xs[c * LDX + i] = vx[u];
-          Js[c * LDX + i] = vj[u];
-        }
-      }
+      // stage this slice of the pair's columns of X
+      stage(X, Xs, I, Jb);
       __syncthreads();
       // partial Gram of the slice; wave w forms the 16 x 16 tile (w >> 1, w & 1)
       {
@@ -327,31 +348,39 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
           }
           if (__syncthreads_count(rotated) == 0) break;
         }
-        // X_W <- X_W R and J_W <- J_W R on this slice, formed as (R^T S^T)^T
-        // so that 16 consecutive lanes store 16 consecutive rows of a column
-        for (int tile = wave; tile < 4 * RPT; tile += 4) {
-          const int mat = tile & 1, jt = (tile >> 1) & 1, rt = tile >> 2;
-          const double* S = mat ? Js : Xs;
-          double* D = mat ? J : X;
-          const double* ap = Rl + (lane >> 4) * kLdM + jt * 16 + (lane & 15);
-          const double* bp = S + (lane >> 4) * LDX + rt * 16 + (lane & 15);
-          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int k0 = 0; k0 < kW; k0 += 4) acc = Mfma<double>::run(ap[k0 * kLdM], bp[k0 * LDX], acc);
-          const int row = rt * 16 + (lane & 15);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int j = jt * 16 + Mfma<double>::row(lane, e);
-            const int gc = j < kB ? I * kB + j : Jb * kB + (j - kB);
-            if (gc < n && row < nrow) st_agent(D + (int64_t)gc * n + row0 + row, acc[e]);
-          }
-        }
+        // X_W <- X_W R on this slice
+        apply(Xs, X, I, Jb);
       }
-      // publish this step's rows
+      // publish this step's X rows: the next owners of these blocks start
+      // their step on them while this workgroup turns to J
       __syncthreads();
       if (tid == 0) {
         fence_release();
         __hip_atomic_fetch_add(flags + kFlagDone + g, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // J_W <- J_W R on this slice, once the J rows of the previous step are out
+      if (nneed > 0) {
+        if (gs > 0) {
+          const int sp = (s == 0) ? nsteps - 1 : s - 1;
+          const int g1 = rr_pair_of(I, sp, nbp) * P + r;
+          const int g2 = rr_pair_of(Jb, sp, nbp) * P + r;
+          if (tid == 0) {
+            const bool ok = spin_geq(flags + kFlagDoneJ + g1, gs, abort_flag) &&
+                            spin_geq(flags + kFlagDoneJ + g2, gs, abort_flag);
+            fence_acquire();
+            sh_ok = ok ? 1 : 0;
+          }
+          __syncthreads();
+          if (!sh_ok) { aborted = true; break; }
+        }
+        stage(J, Js, I, Jb);
+        __syncthreads();
+        apply(Js, J, I, Jb);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        fence_release();
+        __hip_atomic_fetch_add(flags + kFlagDoneJ + g, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     if (aborted) break;

@@ -499,8 +499,8 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 // row-major in LDS (two buffers).  The next chunk's buffer loads are issued
 // before the multiply, its LDS writes interleaved into the last slab, the
 // FP64 sum of squares of A (Eq. sumeigen) taken from the loaded chunk.
-// Requires n % kTK == 0 and 16-byte rows (the descriptor ends at the last
-// valid row; the k range is whole).
+// Requires n % 4 == 0 and 16-byte rows (the descriptor ends at the last
+// valid row; a last chunk that ends past n is zeroed there on its way to LDS).
 constexpr int kTM = 256, kTK = 32, kTLD = kTK + 4;
 
 template <int NT>
@@ -516,12 +516,13 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
   const int lr = lane & 15, g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kTM;
   const int64_t rows = m - row0 < kTM ? m - row0 : kTM;
-  const int nch = (int)(n / kTK);
+  const int nch = (int)((n + kTK - 1) / kTK);
   const bool do_ss = fro2_part != nullptr;
+  // both ranges end at the last element of their last row
   const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
+      const_cast<float*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(Xt), 0, (int)((int64_t)c * ldxt * 4), kBufDword3);
+      const_cast<float*>(Xt), 0, (int)(((int64_t)(c - 1) * ldxt + n) * 4), kBufDword3);
   int voa[8], vox[XU];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -545,21 +546,36 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
         rx[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, vox[u], so, 0));
   };
   double ss = 0.0;
-  auto store = [&](int buf) {
+  // chunk ch goes to LDS; in a last chunk that ends past n both operands are
+  // zeroed beyond n (the loads there read the next row)
+  auto store = [&](int buf, int ch) {
+    const int kend = (int)(n - (int64_t)ch * kTK);
+    const bool tail = kend < kTK;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = tid + u * 256;
-      *reinterpret_cast<f32x4*>(&As[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = ra[u];
+      f32x4 v = ra[u];
+      if (tail) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = 4 * (idx & 7) + i < kend ? v[i] : 0.f;
+      }
+      *reinterpret_cast<f32x4*>(&As[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = v;
       if (do_ss) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ss = fma((double)ra[u][i], (double)ra[u][i], ss);
+        for (int i = 0; i < 4; ++i) ss = fma((double)v[i], (double)v[i], ss);
       }
     }
 #pragma unroll
     for (int u = 0; u < XU; ++u) {
       const int idx = tid + u * 256;
-      if (idx < BC * (kTK / 4))
-        *reinterpret_cast<f32x4*>(&Bs[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = rx[u];
+      if (idx < BC * (kTK / 4)) {
+        f32x4 v = rx[u];
+        if (tail) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = 4 * (idx & 7) + i < kend ? v[i] : 0.f;
+        }
+        *reinterpret_cast<f32x4*>(&Bs[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = v;
+      }
     }
   };
   f32x4 acc[4][NT];
@@ -585,7 +601,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
         for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[i][t], bf[j][t], acc[i][j]);
   };
   load(0);
-  store(0);
+  store(0, 0);
   __syncthreads();
   static_assert(kTK == 32, "two slabs per chunk");
   for (int ch = 0; ch < nch; ++ch) {
@@ -596,7 +612,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
     slab(buf, 0);
     __builtin_amdgcn_sched_barrier(0);
     slab(buf, 1);
-    if (more) store(buf ^ 1);
+    if (more) store(buf ^ 1, ch + 1);
     __syncthreads();
   }
 #pragma unroll
@@ -1027,7 +1043,7 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 
 // ---------------------------------------------------------------------------
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c) {
-  return c >= 1 && c <= 128 && n % kTK == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
+  return c >= 1 && c <= 128 && n % 4 == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
          (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Xt) % 16) == 0 && (ldxt % 4) == 0 &&
          (int64_t)kTM * lda * 4 < (1LL << 31) && (int64_t)c * ldxt * 4 < (1LL << 31);
 }

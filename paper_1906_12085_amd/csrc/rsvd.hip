@@ -240,17 +240,37 @@ struct Path {
     return launch_reduce_partials(p->part, ns, n, c, Z, c, s);
   }
 
+  // Y Rinv (m x c, type T) with Rinv held in RinvT (c x c); fp32 with a
+  // narrow right factor takes it transposed (row j = column j of Rinv).
+  static bool times_rinv_tall(const T* Y, int c, int64_t ldy, const T* RinvT) {
+    return std::is_same<T, float>::value &&
+           nt_tall_applies(reinterpret_cast<const float*>(Y), c, ldy,
+                           reinterpret_cast<const float*>(RinvT), c, c);
+  }
+  hipError_t times_rinv(const T* Y, int64_t m, int c, int64_t ldy, const T* RinvT, bool tall,
+                        T* Out, int64_t ldo) {
+    if (tall)
+      return launch_gemm_nt_tall(reinterpret_cast<const float*>(Y), m, c, ldy,
+                                 reinterpret_cast<const float*>(RinvT), c, c,
+                                 reinterpret_cast<float*>(Out), ldo, nullptr, nullptr, s);
+    return launch_gemm_nn<T>(Y, m, c, ldy, RinvT, c, c, Out, ldo, nullptr, nullptr, s);
+  }
+
   // CholeskyQR2 of Y (m x c): Q1 = Y R1^-1 (type T), R2 = chol(Q1^T Q1); the
-  // orthonormal basis is Q = Q1 R2^-1 (kept implicit: R2inv).
+  // orthonormal basis is Q = Q1 R2^-1 (kept implicit: R2inv).  R1^-1 passes
+  // through RinvT; R2^-1 is written there as well when trans2 >= 0, in the
+  // layout times_rinv takes for trans2 = 1.
   hipError_t cqr2(const T* Y, int64_t m, int c, int64_t ldy, T* Q1, int64_t ldq, double* R1,
-                  double* R1inv, double* R2, double* R2inv, T* RinvT) {
+                  double* R1inv, double* R2, double* R2inv, T* RinvT, int trans2 = -1) {
     hipError_t e;
+    const bool tall = times_rinv_tall(Y, c, ldy, RinvT);
     if ((e = gram(Y, m, c, ldy, p->Wg)) != hipSuccess) return e;
-    if ((e = launch_chol_inv<T>(p->Wg, c, R1, R1inv, RinvT, p->status, s)) != hipSuccess) return e;
-    if ((e = launch_gemm_nn<T>(Y, m, c, ldy, RinvT, c, c, Q1, ldq, nullptr, nullptr, s)) != hipSuccess)
+    if ((e = launch_chol_inv<T>(p->Wg, c, R1, R1inv, RinvT, p->status, s, tall)) != hipSuccess)
       return e;
+    if ((e = times_rinv(Y, m, c, ldy, RinvT, tall, Q1, ldq)) != hipSuccess) return e;
     if ((e = gram(Q1, m, c, ldq, p->Wg)) != hipSuccess) return e;
-    return launch_chol_inv<T>(p->Wg, c, R2, R2inv, RinvT, p->status, s);
+    return launch_chol_inv<T>(p->Wg, c, R2, R2inv, trans2 >= 0 ? RinvT : nullptr, p->status, s,
+                              trans2 > 0);
   }
 };
 
@@ -258,7 +278,7 @@ struct Path {
 hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, double* Zout) {
   Path<double> d(p);
   hipError_t e = d.cqr2(Zin, n, c, c, p->Z1, c, p->R1s, p->R1invs, p->R2s, p->R2invs,
-                        (double*)p->RinvTs);
+                        (double*)p->RinvTs, 0);
   if (e != hipSuccess) return e;
   return launch_gemm_nn<double>(p->Z1, n, c, c, (const double*)p->RinvTs, c, c, Zout, c, nullptr,
                                 nullptr, p->stream);
@@ -333,9 +353,18 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   RSVD_CHECK(small_svd_unsorted(p, p->Z2, n, l));
   RSVD_CHECK(launch_sort_sign_scatter<T>(p->Su, l, p->Vt, n, l, 1, p->Uo, k, S, V, ldv, nullptr,
                                          p->Wk, s));
-  // step 7: U~ = Q W = Q1 (R2^-1 W), first k columns
-  RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s));
-  RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, l, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
+  // step 7: U~ = Q W = Q1 (R2^-1 W), first k columns; fp32 takes the l x k
+  // factor transposed into the tall kernel
+  const bool tall_u = std::is_same<T, float>::value &&
+                      nt_tall_applies(reinterpret_cast<const float*>(Q1), l, l,
+                                      reinterpret_cast<const float*>(p->MkT), l, k);
+  RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s, tall_u));
+  if (tall_u)
+    RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, l, l,
+                                   reinterpret_cast<const float*>(p->MkT), l, k,
+                                   reinterpret_cast<float*>(U), ldu, nullptr, nullptr, s));
+  else
+    RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, l, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
   // K by the explained-variance criterion (Sec. 2.4)
   RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
   return RSVD_OK;
@@ -648,16 +677,16 @@ int32_t rsvd_cholqr2(rsvd_plan_t plan, const void* Y, int64_t m, int32_t c, int6
   if (plan->dtype == RSVD_F64) {
     Path<double> P(plan);
     RSVD_CHECK(P.cqr2((const double*)Y, m, c, ldy, (double*)plan->Q1, c, plan->R1, plan->R1inv,
-                      plan->R2, plan->R2inv, (double*)plan->RinvT));
-    RSVD_CHECK(launch_gemm_nn<double>((const double*)plan->Q1, m, c, c,
-                                      (const double*)plan->RinvT, c, c, (double*)Q, ldq, nullptr,
-                                      nullptr, s));
+                      plan->R2, plan->R2inv, (double*)plan->RinvT, 0));
+    RSVD_CHECK(P.times_rinv((const double*)plan->Q1, m, c, c, (const double*)plan->RinvT, false,
+                            (double*)Q, ldq));
   } else {
     Path<float> P(plan);
+    const bool tall = P.times_rinv_tall((const float*)plan->Q1, c, c, (const float*)plan->RinvT);
     RSVD_CHECK(P.cqr2((const float*)Y, m, c, ldy, (float*)plan->Q1, c, plan->R1, plan->R1inv,
-                      plan->R2, plan->R2inv, (float*)plan->RinvT));
-    RSVD_CHECK(launch_gemm_nn<float>((const float*)plan->Q1, m, c, c, (const float*)plan->RinvT,
-                                     c, c, (float*)Q, ldq, nullptr, nullptr, s));
+                      plan->R2, plan->R2inv, (float*)plan->RinvT, tall));
+    RSVD_CHECK(P.times_rinv((const float*)plan->Q1, m, c, c, (const float*)plan->RinvT, tall,
+                            (float*)Q, ldq));
   }
   RSVD_CHECK(launch_small_gemm<double>(plan->R2, plan->R1, c, c, c, R, nullptr, s));
   return RSVD_OK;

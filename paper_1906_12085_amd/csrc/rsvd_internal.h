@@ -126,17 +126,19 @@ hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t 
 
 // Cholesky of the symmetric c x c matrix W (ld = c): R upper with W = R^T R,
 // Rinv = R^-1 (upper), both ld = c.  Rinv also written, rounded, to RinvT
-// (type T, ld = c) when RinvT != nullptr.  Non-positive pivot -> status word
-// = RSVD_ERR_BREAKDOWN, R = 0 and Rinv = identity (so later kernels stay finite).
+// (type T, ld = c) when RinvT != nullptr, transposed when trans != 0.
+// Non-positive pivot -> status word = RSVD_ERR_BREAKDOWN, R = 0 and
+// Rinv = identity (so later kernels stay finite).
 template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
-                           int32_t* status, hipStream_t s);
+                           int32_t* status, hipStream_t s, int trans = 0);
 
 // C (r x c2) = A (r x c1) B (c1 x c2), FP64, all ld = their column counts.
-// Optional rounded copy CT (type T, ld = c2).
+// Optional rounded copy CT (type T): C itself (ld = c2), or C^T (ld = r)
+// when trans != 0.
 template <typename T>
 hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1, int c2,
-                             double* C, T* CT, hipStream_t s);
+                             double* C, T* CT, hipStream_t s, int trans = 0);
 
 // One-sided Jacobi SVD of a c x c FP64 matrix M (ld = c, c <= 96), in one
 // workgroup, on M itself or (transpose != 0) on M^T =: N:  N J = Uo diag(S)

@@ -64,68 +64,149 @@ __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, 
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky W = R^T R (R upper, positive diagonal) and Rinv = R^-1, one block,
-// both c x c (c <= 96) in LDS.  Phase 1, symmetric Gaussian elimination
-// without pivoting (stable for a positive definite W): step j subtracts
-// (a_ij / a_jj) times row j from every row i > j, leaving D L^T (W = L D L^T)
-// in the upper triangle; scaling row i by 1/sqrt(d_i) gives R.  Phase 2, R X
-// = I by right-looking back substitution: step k (from the last row up)
-// subtracts R[i][k] X[k][:] from the rows i < k (X[k][:] = B[k][:] / R[k][k]
-// is final), which keeps Rinv accurate relative to the computed R.  In both
-// phases the columns that change at a step are assigned one per thread slot
-// with a fixed stride of rows, and each step ends with one barrier.
-constexpr int kCholThreads = 1024;
-constexpr int kCholMaxC = 96;
-constexpr int kCholRows = 10;                // rows per thread per step: ceil(96 / (1024/96))
+// Cholesky factor R (upper, W = R^T R) and its inverse of a c x c SPD matrix
+// (c <= 96), one workgroup of 256 threads.  Thread (ti, tk) = (tid / 16,
+// tid % 16) keeps the elements (ti + 16u, tk + 16v), u, v < 6, in registers;
+// the 16 owners of a row are one 16-lane group of one wave.
+//  Factorisation, step j: the owners of row j take d = a_jj from the lane that
+//  holds it (cross-lane read), scale their part of row j by 1/sqrt(d) (row j of
+//  R) and publish it in LDS; after one barrier every thread subtracts
+//  r_ji r_jk from its elements (i, k), j < i <= k.
+//  Inverse (B = R^-1, from B = I), step k from the bottom: the owners of row k
+//  divide it by r_kk (row k of B is then final) and publish it, the owners of
+//  column k of R publish that column; after one barrier every thread
+//  subtracts r_ik b_kl from its elements (i, l), i < k <= l.
+// The LDS rows alternate between steps, so one barrier per step suffices.
+// The block index of the step (j / 16) is unrolled so that register
+// subscripts are compile-time constants.
+constexpr int kCiT = 256;
+constexpr int kCiU = 6;                       // 16 * 6 = 96 rows and columns
 
-template <typename T>
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ W, int c,
-                                                           double* __restrict__ R,
-                                                           double* __restrict__ Rinv,
-                                                           T* __restrict__ RinvT,
-                                                           int32_t* __restrict__ status) {
-  extern __shared__ double sm[];
-  const int ld = c + 1;
-  double* L = sm;                            // c x c (ld), becomes R
-  double* B = sm + (size_t)c * ld;           // c x c (ld), becomes R^-1 * diag(R)
-  __shared__ double dg[kCholMaxC];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, j = idx - i * c;
-    L[i * ld + j] = 0.5 * (W[i * c + j] + W[j * c + i]);
-    B[i * ld + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int rpp = kCholThreads / c;          // rows per pass, >= 10 for c <= 96
-  const int a = tid % c, r0 = tid / c;       // column slot, first row offset
-  const bool active = r0 < rpp;
-  bool bad = false;
-  for (int j = 0; j < c; ++j) {
-    const double d = L[j * ld + j];
-    if (!(d > 0.0)) { bad = true; break; }   // uniform: every thread reads the same d
-    const int col = j + 1 + a;               // columns j+1..c-1 change
-    if (active && col < c) {
-      const double pr = L[j * ld + col] / d;
-      // all reads first, then all writes: the LDS latency is paid once per step.
-      // Multiplier a_ij / a_jj from the (updated) upper entry a_ji of row j.
-      double x[kCholRows], f[kCholRows];
+// 1/sqrt(x) and 1/x: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rsq_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+__device__ __forceinline__ double rcp_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Updates are branch-free: an element outside the active triangle gets an
+// exact zero subtracted (the LDS rows start at zero and only ever hold finite
+// values), so no lane diverges inside a step.
+// A pivot <= 0 (not positive definite to working precision) is recorded in
+// *bad and checked once after the factorisation; meanwhile it only produces
+// non-finite values.
+template <int UB>
+__device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], int c, int ti, int tk,
+                                           int lane, int wv, double (*rowbuf)[96], int* bad) {
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = 16 * UB + jj;
+    if (j >= c) return;
+    const int p = j & 1;
+    if (ti == jj) {
+      const double d = __shfl(a[UB][UB], (lane & 48) + jj);
+      if (!(d > 0.0)) *bad = 1;
+      const double rs = rsq_newton(d);
 #pragma unroll
-      for (int u = 0; u < kCholRows; ++u) {
-        const int i = j + 1 + r0 + u * rpp;
-        x[u] = (i <= col) ? L[i * ld + col] : 0.0;
-        f[u] = (i <= col) ? L[j * ld + i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kCholRows; ++u) {
-        const int i = j + 1 + r0 + u * rpp;
-        if (i <= col) L[i * ld + col] = x[u] - f[u] * pr;
+      for (int v = 0; v < kCiU; ++v) {
+        const int k = tk + 16 * v;
+        const bool on = k >= j && k < c;
+        a[UB][v] = on ? a[UB][v] * rs : a[UB][v];
+        rowbuf[p][k] = on ? a[UB][v] : 0.0;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int u = UB; u < kCiU; ++u) {
+      if (16 * u + 4 * wv + 3 <= j) continue;   // no row of this wave is below j
+      const int i = ti + 16 * u;
+      const double rji = (i > j && i < c) ? rowbuf[p][i] : 0.0;
+      // the whole trailing square (its lower half stays the mirror image and
+      // is never read); columns left of j read a zero from rowbuf
+#pragma unroll
+      for (int v = 0; v < kCiU; ++v) a[u][v] = fma(-rji, rowbuf[p][tk + 16 * v], a[u][v]);
+    }
   }
+}
+
+template <int UB>
+__device__ __forceinline__ void inv_block(const double (&a)[kCiU][kCiU], double (&b)[kCiU][kCiU],
+                                          int c, int ti, int tk, int lane, int wv,
+                                          double (*rowbuf)[96], double (*colbuf)[96]) {
+  for (int kk = 15; kk >= 0; --kk) {
+    const int k = 16 * UB + kk;
+    if (k >= c) continue;
+    const int p = k & 1;
+    if (ti == kk) {
+      const double inv = rcp_newton(__shfl(a[UB][UB], (lane & 48) + kk));
+#pragma unroll
+      for (int v = 0; v < kCiU; ++v) {
+        const int l = tk + 16 * v;
+        const bool on = l >= k && l < c;
+        b[UB][v] = on ? b[UB][v] * inv : b[UB][v];
+        rowbuf[p][l] = on ? b[UB][v] : 0.0;
+      }
+    }
+    if (tk == kk) {
+#pragma unroll
+      for (int u = 0; u <= UB; ++u) {
+        const int i = ti + 16 * u;
+        colbuf[p][i] = i < k ? a[u][UB] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u <= UB; ++u) {
+      if (16 * u + 4 * wv >= k) continue;       // no row of this wave is above k
+      const int i = ti + 16 * u;
+      const double rik = colbuf[p][i];
+#pragma unroll
+      for (int v = UB; v < kCiU; ++v) b[u][v] = fma(-rik, rowbuf[p][tk + 16 * v], b[u][v]);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W, int c,
+                                                   double* __restrict__ R,
+                                                   double* __restrict__ Rinv,
+                                                   T* __restrict__ RinvT, int trans,
+                                                   int32_t* __restrict__ status) {
+  __shared__ double rowbuf[2][96];
+  __shared__ double colbuf[2][96];
+  __shared__ int bad;
+  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double a[kCiU][kCiU], b[kCiU][kCiU];
+#pragma unroll
+  for (int u = 0; u < kCiU; ++u)
+#pragma unroll
+    for (int v = 0; v < kCiU; ++v) {
+      const int i = ti + 16 * u, k = tk + 16 * v;
+      a[u][v] = (i < c && k < c) ? 0.5 * (W[i * c + k] + W[k * c + i]) : 0.0;
+      b[u][v] = (i == k) ? 1.0 : 0.0;
+    }
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < 2 * 96; e += kCiT) {
+    rowbuf[e / 96][e % 96] = 0.0;
+    colbuf[e / 96][e % 96] = 0.0;
+  }
+  __syncthreads();
+  chol_block<0>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<1>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<2>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<3>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<4>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<5>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  __syncthreads();
   if (bad) {
     // R = 0 (no factor), Rinv = I keeps the later products finite
-    for (int idx = tid; idx < c * c; idx += kCholThreads) {
+    for (int idx = tid; idx < c * c; idx += kCiT) {
       const int i = idx / c, j = idx - i * c;
       const double v = (i == j) ? 1.0 : 0.0;
       R[idx] = 0.0;
@@ -135,45 +216,30 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
   }
-  for (int i = tid; i < c; i += kCholThreads) dg[i] = sqrt(L[i * ld + i]);
-  __syncthreads();
-  for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, k = idx - i * c;
-    const double v = (k >= i) ? L[i * ld + k] / dg[i] : 0.0;
-    L[i * ld + k] = v;                       // each entry rewritten by its own reader
-    R[idx] = v;
-  }
-  __syncthreads();
-  for (int k = c - 1; k >= 1; --k) {
-    const int col = k + a;                   // columns k..c-1 of the rows above k change
-    if (active && col < c) {
-      const double xk = B[k * ld + col] / L[k * ld + k];
-      double x[kCholRows], f[kCholRows];
+  inv_block<5>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  inv_block<4>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  inv_block<3>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  inv_block<2>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  inv_block<1>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  inv_block<0>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
 #pragma unroll
-      for (int u = 0; u < kCholRows; ++u) {
-        const int i = r0 + u * rpp;
-        x[u] = (i < k) ? B[i * ld + col] : 0.0;
-        f[u] = (i < k) ? L[i * ld + k] : 0.0;
-      }
+  for (int u = 0; u < kCiU; ++u)
 #pragma unroll
-      for (int u = 0; u < kCholRows; ++u) {
-        const int i = r0 + u * rpp;
-        if (i < k) B[i * ld + col] = x[u] - f[u] * xk;
+    for (int v = 0; v < kCiU; ++v) {
+      const int i = ti + 16 * u, k = tk + 16 * v;
+      if (i < c && k < c) {
+        const bool up = k >= i;
+        R[i * c + k] = up ? a[u][v] : 0.0;
+        Rinv[i * c + k] = up ? b[u][v] : 0.0;
+        if (RinvT) RinvT[trans ? k * c + i : i * c + k] = (T)(up ? b[u][v] : 0.0);
       }
     }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < c * c; idx += kCholThreads) {
-    const int i = idx / c, k = idx - i * c;
-    const double v = (k >= i) ? B[i * ld + k] / L[i * ld + i] : 0.0;
-    Rinv[idx] = v;
-    if (RinvT) RinvT[idx] = (T)v;
-  }
 }
 
 template <typename T>
 __global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
-                             int64_t r, int c1, int c2, double* __restrict__ C, T* __restrict__ CT) {
+                             int64_t r, int c1, int c2, double* __restrict__ C, T* __restrict__ CT,
+                             int trans) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= r * c2) return;
   const int64_t i = idx / c2;
@@ -181,7 +247,7 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   double s = 0.0;
   for (int k = 0; k < c1; ++k) s += A[i * c1 + k] * B[(int64_t)k * c2 + j];
   if (C) C[idx] = s;
-  if (CT) CT[idx] = (T)s;
+  if (CT) CT[trans ? (int64_t)j * r + i : idx] = (T)s;
 }
 
 // kernel works on M^T (the rows of Min are its columns).
@@ -472,23 +538,19 @@ hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t 
 
 template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
-                           int32_t* status, hipStream_t s) {
-  if (c < 1 || c > kCholMaxC) return hipErrorInvalidValue;
-  const size_t shmem = 2 * (size_t)c * (c + 1) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCholThreads), shmem, s, W, c, R, Rinv, RinvT,
+                           int32_t* status, hipStream_t s, int trans) {
+  if (c < 1 || c > 16 * kCiU) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), 0, s, W, c, R, Rinv, RinvT, trans,
                      status);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1, int c2, double* C,
-                             T* CT, hipStream_t s) {
+                             T* CT, hipStream_t s, int trans) {
   if (r * c2 <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_small_gemm<T>), dim3(blocks_for(r * c2, 256)), dim3(256), 0, s, A, B, r,
-                     c1, c2, C, CT);
+                     c1, c2, C, CT, trans);
   return hipGetLastError();
 }
 
@@ -562,9 +624,9 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
   template hipError_t launch_cast_to_f64<T>(const T*, int64_t, int64_t, int64_t, double*, int64_t, \
                                             hipStream_t);                                          \
   template hipError_t launch_chol_inv<T>(const double*, int, double*, double*, T*, int32_t*,      \
-                                         hipStream_t);                                             \
+                                         hipStream_t, int);                                        \
   template hipError_t launch_small_gemm<T>(const double*, const double*, int64_t, int, int,       \
-                                           double*, T*, hipStream_t);                              \
+                                           double*, T*, hipStream_t, int);                         \
   template hipError_t launch_sort_sign_scatter<T>(const double*, int, const double*, int64_t,     \
                                                   int64_t, int64_t, const double*, int, double*,  \
                                                   T*, int64_t, double*, double*, hipStream_t);     \

@@ -55,6 +55,9 @@ NN_CASES = [
     (4133, 64, 80, 0),     # fp32 tall kernel (n % 32 == 0): ragged last row block
     (1000, 512, 128, 0),   # fp32 tall kernel at its widest (8 column tiles)
     (515, 32, 1, 0),       # one column
+    (2049, 80, 80, 0),     # tall kernel, last k chunk half full (the CholeskyQR2 shape)
+    (700, 84, 52, 4),      # tall kernel, k tail of 20, padded rows
+    (1500, 4, 7, 0),       # tall kernel, a single k chunk of 4
 ]
 
 
@@ -151,7 +154,8 @@ def test_gemm_tn_parity(plans, name, m, n, c):
 
 
 @pytest.mark.parametrize("name", DTYPES)
-@pytest.mark.parametrize("m,c,kappa", [(2000, 30, 1e2), (5000, 80, 1e3), (333, 17, 10.0)])
+@pytest.mark.parametrize("m,c,kappa", [(2000, 30, 1e2), (5000, 80, 1e3), (333, 17, 10.0),
+                                           (3000, 96, 1e2), (4000, 44, 1e3)])
 def test_cholqr2_parity(plans, name, m, c, kappa):
     dt = DTYPES[name]
     announce(f"cholqr2 {name} m={m} c={c} kappa={kappa}")

@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "librsvd.so")
 SOURCES = ["gemm.hip", "small.hip", "eig.hip", "rsvd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed FP32 instructions are kept out of every kernel.
+# Packed FP32 instructions are kept out of every kernel: some of their forms
+# have given silently wrong results on this hardware.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result"]

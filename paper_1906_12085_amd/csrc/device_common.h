@@ -47,16 +47,49 @@ __device__ __forceinline__ void rr_pair(int s, int k, int npad, int* p, int* q) 
   *q = a < b ? b : a;
 }
 
-// One-sided (Hestenes) Jacobi rotation that orthogonalises columns x, y with
-// alpha = |x|^2, beta = |y|^2, gamma = x.y:  zeta = (beta - alpha)/(2 gamma),
-// t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)), cs = 1/sqrt(1+t^2), sn = cs t;
-// x' = cs x - sn y, y' = sn x + cs y.
-__device__ __forceinline__ void jacobi_cs(double alpha, double beta, double gamma, double* cs,
-                                          double* sn) {
-  const double zeta = (beta - alpha) / (2.0 * gamma);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  *cs = 1.0 / sqrt(1.0 + t * t);
-  *sn = *cs * t;
+// Newton steps for the hardware reciprocal and reciprocal-square-root
+// estimates (each step doubles the number of correct bits).
+__device__ __forceinline__ double rcp_step(double x, double r) { return fma(r, fma(-x, r, 1.0), r); }
+__device__ __forceinline__ double rsq_step(double x, double y) {
+  return fma(y, fma(-0.5 * x * y, y, 0.5), y);
+}
+
+// A pair of columns with alpha = |x_p|^2, beta = |x_q|^2, gamma = x_p.x_q is
+// rotated when the cosine of their angle exceeds tol (gamma^2 > tol^2 alpha
+// beta) and |gamma| exceeds floor (a level below which the columns' inner
+// product is rounding noise of the input).
+__device__ __forceinline__ bool rot_needed(double al, double be, double ga, double tol2,
+                                           double floor) {
+  return fabs(ga) > floor && ga * ga > tol2 * (al * be);
+}
+
+// The rotation (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) that makes the
+// pair orthogonal.  With zeta = (beta - alpha) / (2 gamma) the tangent is the
+// root of t^2 + 2 zeta t - 1 = 0 of smaller magnitude, t = sign(zeta) / den
+// with den = |zeta| + sqrt(1 + zeta^2); then c = den / sqrt(den^2 + 1) and
+// s = sign(zeta) / sqrt(den^2 + 1), so c and s share one reciprocal square
+// root (two Newton steps: c^2 + s^2 = 1 to rounding) while zeta and den need
+// only one step each (they decide how far the pair turns, not the
+// orthogonality of the rotation).  Branch-free: need = false gives the
+// identity (c = 1, s = t = 0), so the two rotations a thread needs per round
+// are computed side by side.
+__device__ __forceinline__ void rot_cst(double al, double be, double ga, bool need, double* c,
+                                        double* s, double* t) {
+  const double g = need ? ga : 1.0;
+  const double d = need ? be - al : 0.0;
+  const double zeta = 0.5 * d * rcp_step(g, __builtin_amdgcn_rcp(g));
+  const double az = fmin(fabs(zeta), 1e150);
+  const double w = fma(az, az, 1.0);
+  const double den = fma(w, rsq_step(w, __builtin_amdgcn_rsq(w)), az);
+  const double v = fma(den, den, 1.0);
+  double q = __builtin_amdgcn_rsq(v);
+  q = rsq_step(v, rsq_step(v, q));
+  double ti = __builtin_amdgcn_rcp(den);
+  ti = rcp_step(den, rcp_step(den, ti));
+  const double sg = zeta >= 0.0 ? 1.0 : -1.0;
+  *c = need ? den * q : 1.0;
+  *s = need ? sg * q : 0.0;
+  *t = need ? sg * ti : 0.0;
 }
 
 // Sum over the G consecutive lanes of this lane's group (G = 16, 32 or 64,
@@ -89,11 +122,6 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
-// M and of the accumulated rotations J held column-major in LDS.  Each group
-// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
-// pair's entries in registers (6 rows per lane), reduces the three inner
-// products with group_sum, rotates and writes back.  With transpose != 0 the
 // ---------------------------------------------------------------------------
 // Waits between workgroups of one cooperative launch.  Spins are bounded:
 // on timeout (or when another workgroup already gave up) the abort flag is

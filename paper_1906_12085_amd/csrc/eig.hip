@@ -75,52 +75,6 @@ __device__ __forceinline__ int rr_pair_of(int blk, int s, int npad) {
   return d <= (h - 1) / 2 ? d : h - d;
 }
 
-// Newton steps for the hardware reciprocal and reciprocal-square-root
-// estimates (each step doubles the number of correct bits).
-__device__ __forceinline__ double rcp_step(double x, double r) { return fma(r, fma(-x, r, 1.0), r); }
-__device__ __forceinline__ double rsq_step(double x, double y) {
-  return fma(y, fma(-0.5 * x * y, y, 0.5), y);
-}
-
-// A pair of columns with alpha = |x_p|^2, beta = |x_q|^2, gamma = x_p.x_q is
-// rotated when the cosine of their angle exceeds tol (gamma^2 > tol^2 alpha
-// beta) and |gamma| exceeds the floor (eps ||G||_F)^2, below which both
-// columns are at the rounding level of G and their directions carry no
-// information.
-__device__ __forceinline__ bool rot_needed(double al, double be, double ga, double tol2,
-                                           double floor) {
-  return fabs(ga) > floor && ga * ga > tol2 * (al * be);
-}
-
-// The rotation (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) that makes the
-// pair orthogonal.  With zeta = (beta - alpha) / (2 gamma) the tangent is the
-// root of t^2 + 2 zeta t - 1 = 0 of smaller magnitude, t = sign(zeta) / den
-// with den = |zeta| + sqrt(1 + zeta^2); then c = den / sqrt(den^2 + 1) and
-// s = sign(zeta) / sqrt(den^2 + 1), so c and s share one reciprocal square
-// root (two Newton steps: c^2 + s^2 = 1 to rounding) while zeta and den need
-// only one step each (they decide how far the pair turns, not the
-// orthogonality of the rotation).  Branch-free: need = false gives the
-// identity (c = 1, s = t = 0), so the two rotations a thread needs per round
-// are computed side by side.
-__device__ __forceinline__ void rot_cst(double al, double be, double ga, bool need, double* c,
-                                        double* s, double* t) {
-  const double g = need ? ga : 1.0;
-  const double d = need ? be - al : 0.0;
-  const double zeta = 0.5 * d * rcp_step(g, __builtin_amdgcn_rcp(g));
-  const double az = fmin(fabs(zeta), 1e150);
-  const double w = fma(az, az, 1.0);
-  const double den = fma(w, rsq_step(w, __builtin_amdgcn_rsq(w)), az);
-  const double v = fma(den, den, 1.0);
-  double q = __builtin_amdgcn_rsq(v);
-  q = rsq_step(v, rsq_step(v, q));
-  double ti = __builtin_amdgcn_rcp(den);
-  ti = rcp_step(den, rcp_step(den, ti));
-  const double sg = zeta >= 0.0 ? 1.0 : -1.0;
-  *c = need ? den * q : 1.0;
-  *s = need ? sg * q : 0.0;
-  *t = need ? sg * ti : 0.0;
-}
-
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = group_sum<64>(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;

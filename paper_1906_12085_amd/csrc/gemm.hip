@@ -634,6 +634,81 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
   }
 }
 
+// Y = A Xt^T for a short k range (n <= 16 NS): the whole c x n factor is
+// staged in LDS once per block and A goes straight from memory into the
+// matrix-core operand registers (lane (lr, g) of a 16-row tile loads 16 bytes
+// of row lr at k = 16 s + 4 g, the k order that step t of slab s contracts on
+// both operands), so a block holds only the small factor in LDS and two
+// blocks share a CU.  Block = 256 rows, 4 waves of 64 rows x NT column tiles.
+// Same requirements as the tall kernel (n % 4 == 0, 16-byte rows).
+constexpr int kNM = 256;
+
+template <int NT, int NS>
+__global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy) {
+  constexpr int BC = 16 * NT, KP = 16 * NS, LD = KP + 4;
+  __shared__ __attribute__((aligned(16))) float Bs[BC * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kNM;
+  const int64_t rows = m - row0 < kNM ? m - row0 : kNM;
+  // the range ends at the last element of the block's last row: rows past it
+  // read zeros
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
+  f32x4 af[NS][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int vo = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 4 * g) * 4);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+      af[sl][i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, vo, 64 * sl, 0));
+  }
+  // Xt into LDS, zero beyond c rows and n columns, while A is in flight
+  for (int e = tid; e < BC * (KP / 4); e += 256) {
+    const int r = e / (KP / 4), q = e - r * (KP / 4);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (r < c && 4 * q < n) v = *reinterpret_cast<const f32x4*>(Xt + (int64_t)r * ldxt + 4 * q);
+    *reinterpret_cast<f32x4*>(&Bs[r * LD + 4 * q]) = v;
+  }
+  __syncthreads();
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    if (sl == NS - 1 && 16 * sl + 4 * g >= n) {
+      // the last slab's k beyond n holds the next row's values
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[sl][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    f32x4 bf[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[(16 * j + lr) * LD + 16 * sl + 4 * g]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[sl][i][t], bf[j][t], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + wave * 64 + 16 * i + Mfma<float>::row(lane, e);
+        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+      }
+    }
+}
+
 // Z partials (n x c per row split, FP64) of A^T Q: block = one row split of
 // A and Q, all n (up to kUA per column tile) x c outputs; 8 waves of 64 A
 // columns (4 x NT tiles); chunks of kUK = 16 rows staged row-major in LDS
@@ -1042,6 +1117,44 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Short-k products (no sum of squares) for nt_tall: one kernel per (column
+// tiles, k slabs).
+constexpr int kNarrowSlabs = 6;
+
+template <int NT>
+hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                     int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+  const dim3 grid((unsigned)((m + kNM - 1) / kNM)), block(256);
+#define RSVD_NT_NARROW(NS)                                                                     \
+  case NS:                                                                                     \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, \
+                       Y, ldy);                                                                \
+    break;
+  switch (ns) {
+    RSVD_NT_NARROW(1) RSVD_NT_NARROW(2) RSVD_NT_NARROW(3)
+    RSVD_NT_NARROW(4) RSVD_NT_NARROW(5) RSVD_NT_NARROW(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_NT_NARROW
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt_narrow(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                                 int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+  const int ns = (int)((n + 15) / 16);
+  switch ((c + 15) / 16) {
+    case 1: return narrow_nt<1>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 2: return narrow_nt<2>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 3: return narrow_nt<3>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 4: return narrow_nt<4>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 5: return narrow_nt<5>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 6: return narrow_nt<6>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 7: return narrow_nt<7>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 8: return narrow_nt<8>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c) {
   return c >= 1 && c <= 128 && n % 4 == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
          (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Xt) % 16) == 0 && (ldxt % 4) == 0 &&
@@ -1055,6 +1168,7 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
   const int64_t nblk = (m + kTM - 1) / kTM;
   if (nparts) *nparts = (int)nblk;
   if (m <= 0) return hipSuccess;
+  if (!fro2_part && n <= 16 * kNarrowSlabs) return launch_gemm_nt_narrow(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
   const dim3 grid((unsigned)nblk), block(256);
 #define RSVD_NT_TALL(NT)                                                                      \
   case NT:                                                                                    \

@@ -250,6 +250,11 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   if (CT) CT[trans ? (int64_t)j * r + i : idx] = (T)s;
 }
 
+// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
+// M and of the accumulated rotations J held column-major in LDS.  Each group
+// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
+// pair's entries in registers (6 rows per lane), reduces the three inner
+// products with group_sum, rotates and writes back.  With transpose != 0 the
 // kernel works on M^T (the rows of Min are its columns).
 constexpr int kJsG = 16;
 constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
   }
   const int npairs = npad / 2;
   const int grp = tid / kJsG, gl = tid % kJsG;
-  const double tol = kEps * (double)c;
+  const double tol = kEps * (double)c, tol2 = tol * tol;
   int sweep = 0;
   bool converged = false;
   double last_off = 0.0;
@@ -289,31 +294,32 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
       if (grp < npairs && q < c) {           // uniform within the 16-lane group
         double* xp = Mc + (size_t)p * c;
         double* xq = Mc + (size_t)q * c;
-        double a[kJsRows], b[kJsRows];
+        double* jp = Jc + (size_t)p * c;
+        double* jq = Jc + (size_t)q * c;
+        // all reads of the two columns and their J columns before any write
+        double a[kJsRows], b[kJsRows], ja[kJsRows], jb[kJsRows];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int u = 0; u < kJsRows; ++u) {
           const int i = gl + kJsG * u;
           a[u] = (i < c) ? xp[i] : 0.0;
           b[u] = (i < c) ? xq[i] : 0.0;
-          al += a[u] * a[u]; be += b[u] * b[u]; ga += a[u] * b[u];
+          ja[u] = (i < c) ? jp[i] : 0.0;
+          jb[u] = (i < c) ? jq[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kJsRows; ++u) {
+          al = fma(a[u], a[u], al);
+          be = fma(b[u], b[u], be);
+          ga = fma(a[u], b[u], ga);
         }
         al = group_sum<kJsG>(al);
         be = group_sum<kJsG>(be);
         ga = group_sum<kJsG>(ga);
-        const double scale = sqrt(al) * sqrt(be);
-        if (ga != 0.0 && fabs(ga) > tol * scale) {
-          double cs, sn;
-          jacobi_cs(al, be, ga, &cs, &sn);
-          double* jp = Jc + (size_t)p * c;
-          double* jq = Jc + (size_t)q * c;
-          double ja[kJsRows], jb[kJsRows];   // all reads before any write
-#pragma unroll
-          for (int u = 0; u < kJsRows; ++u) {
-            const int i = gl + kJsG * u;
-            ja[u] = (i < c) ? jp[i] : 0.0;
-            jb[u] = (i < c) ? jq[i] : 0.0;
-          }
+        // rotate when the cosine of the pair's angle exceeds tol
+        if (rot_needed(al, be, ga, tol2, 0.0)) {
+          double cs, sn, tt;
+          rot_cst(al, be, ga, true, &cs, &sn, &tt);
 #pragma unroll
           for (int u = 0; u < kJsRows; ++u) {
             const int i = gl + kJsG * u;
@@ -326,15 +332,16 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
           }
           if (gl == 0) {
             rotated = 1;
-            const double rel = fabs(ga) / scale;
-            if (rel > offmax) offmax = rel;   // diagnostic only (benign race)
+            // squared cosine, approximate (diagnostic only; benign race)
+            const double rel2 = ga * ga * __builtin_amdgcn_rcp(al * be);
+            if (rel2 > offmax) offmax = rel2;
           }
         }
       }
       __syncthreads();
     }
     ++sweep;
-    last_off = offmax;
+    last_off = sqrt(offmax);
     const bool done = (rotated == 0);
     __syncthreads();
     if (done) { converged = true; break; }

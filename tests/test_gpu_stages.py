@@ -92,6 +92,36 @@ def test_gemm_nn_parity(plans, name, m, n, c, pad):
         assert np.all(np.abs(host(Gm) - Gref) <= gb)
 
 
+# short k (n <= 96) without the sum of squares: fp32 takes the kernel that
+# loads A straight into matrix-core registers; the row padding holds NaN,
+# which must not reach Y (the last k slab of a row runs past n)
+NN_NARROW_CASES = [
+    (2049, 80, 80, 0),     # the CholeskyQR2 shape: 5 whole k slabs, 5 column tiles
+    (700, 84, 52, 4),      # last slab 4 of 16 wide, ragged column tile, NaN padding
+    (1500, 4, 7, 0),       # a single k group of 4
+    (257, 96, 128, 0),     # 6 slabs, 8 column tiles, one row past a block
+    (33, 16, 1, 4),        # one partial block, one column
+]
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("m,n,c,pad", NN_NARROW_CASES)
+def test_gemm_nn_narrow_parity(plans, name, m, n, c, pad):
+    dt = DTYPES[name]
+    announce(f"gemm_nn narrow {name} m={m} n={n} c={c} pad={pad}")
+    rng = np.random.default_rng(7 * m + n + c)
+    A0 = rounded(rng.standard_normal((m, n)), dt)
+    X0 = rounded(rng.standard_normal((n, c)), dt)
+    A = dev(np.pad(A0, ((0, 0), (0, pad)), constant_values=np.nan), dt)[:, :n]
+    X = dev(X0, dt)
+    Y = torch.full((m, c), float("nan"), dtype=dt, device="cuda")
+    rs.rsvd_gemm_nn(plans[name].handle, A, X, Y)
+    torch.cuda.synchronize()
+    Yref = oracle.gemm_nn(A0, X0)
+    bound = 2.0 * n * unit(dt) * (np.abs(A0) @ np.abs(X0)) + 1e-300
+    assert np.all(np.abs(host(Y) - Yref) <= bound)
+
+
 # wide X without the fused sum of squares: the two-level tiled product for
 # fp32 (128 x 256 block tiles, XCD-ordered), the column-tiled one for fp64
 NN_WIDE_CASES = [

@@ -312,21 +312,24 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
         fence_release();
         __hip_atomic_fetch_add(flags + kFlagDone + g, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      // J_W <- J_W R on this slice, once the J rows of the previous step are out
-      if (nneed > 0) {
-        if (gs > 0) {
-          const int sp = (s == 0) ? nsteps - 1 : s - 1;
-          const int g1 = rr_pair_of(I, sp, nbp) * P + r;
-          const int g2 = rr_pair_of(Jb, sp, nbp) * P + r;
-          if (tid == 0) {
-            const bool ok = spin_geq(flags + kFlagDoneJ + g1, gs, abort_flag) &&
-                            spin_geq(flags + kFlagDoneJ + g2, gs, abort_flag);
-            fence_acquire();
-            sh_ok = ok ? 1 : 0;
-          }
-          __syncthreads();
-          if (!sh_ok) { aborted = true; break; }
+      // J_W <- J_W R on this slice, once the J rows of the previous step are
+      // out.  The wait comes first also where nothing is rotated: this
+      // step's J rows are published below, and the next owners of these
+      // blocks must find the previous step's rows in place.
+      if (gs > 0) {
+        const int sp = (s == 0) ? nsteps - 1 : s - 1;
+        const int g1 = rr_pair_of(I, sp, nbp) * P + r;
+        const int g2 = rr_pair_of(Jb, sp, nbp) * P + r;
+        if (tid == 0) {
+          const bool ok = spin_geq(flags + kFlagDoneJ + g1, gs, abort_flag) &&
+                          spin_geq(flags + kFlagDoneJ + g2, gs, abort_flag);
+          fence_acquire();
+          sh_ok = ok ? 1 : 0;
         }
+        __syncthreads();
+        if (!sh_ok) { aborted = true; break; }
+      }
+      if (nneed > 0) {
         stage(J, Js, I, Jb);
         __syncthreads();
         apply(Js, J, I, Jb);

@@ -370,17 +370,24 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
 // ---------------------------------------------------------------------------
 // Sort by S descending (ties: lower index first), apply the sign rule to the
 // first kout vectors and scatter them.  Source vector column `col`, element
-// i is at Vsrc[i * vrs + col * vcs].  One wave per output column.
+// i is at Vsrc[i * vrs + col * vcs].  Block b handles output columns
+// [16 b, 16 b + 16): every block ranks all c keys in LDS (c^2 comparisons,
+// cheap next to the scatter), a wave per column finds the sign, and the
+// scatter writes 16 consecutive outputs of a row together.
+constexpr int kSsCols = 16;
+
 template <typename T>
-__global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
-                                    const double* __restrict__ Vsrc, int64_t r, int64_t vrs,
-                                    int64_t vcs, const double* __restrict__ Wsrc, int kout,
-                                    double* __restrict__ S_out, T* __restrict__ Vout,
-                                    int64_t ldv, double* __restrict__ Vd_out,
-                                    double* __restrict__ Wout) {
+__global__ __launch_bounds__(256) void k_sort_sign_scatter(
+    const double* __restrict__ S, int c, const double* __restrict__ Vsrc, int64_t r, int64_t vrs,
+    int64_t vcs, const double* __restrict__ Wsrc, int kout, double* __restrict__ S_out,
+    T* __restrict__ Vout, int64_t ldv, double* __restrict__ Vd_out, double* __restrict__ Wout) {
   extern __shared__ double Sl[];              // c keys, then c ints
   int* perm = reinterpret_cast<int*>(Sl + c);
-  const int tid = threadIdx.x;
+  __shared__ int src_l[kSsCols];
+  __shared__ double sg_l[kSsCols];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk0 = blockIdx.x * kSsCols;
+  const int ncol = min(kSsCols, kout - kk0);
   stage_to_lds(Sl, S, c);
   for (int i = tid; i < c; i += blockDim.x) perm[i] = i;   // NaN keys may leave slots unranked
   __syncthreads();
@@ -391,11 +398,12 @@ __global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
       const double sj = Sl[j];
       rank += (sj > si) || (sj == si && j < i);
     }
-    perm[rank] = i;
+    if (rank < c) perm[rank] = i;
   }
   __syncthreads();
-  const int lane = tid & 63;
-  for (int kk = tid / 64; kk < kout; kk += blockDim.x / 64) {
+  // sign rule: the first entry within 0.999 of the largest magnitude is positive
+  for (int q = wave; q < ncol; q += 4) {
+    const int kk = kk0 + q;
     int src = perm[kk];
     if (src < 0 || src >= c) src = kk;
     double vmax = 0.0;
@@ -408,15 +416,26 @@ __global__ void k_sort_sign_scatter(const double* __restrict__ S, int c,
       const int64_t o = __shfl_xor(first, off);
       first = o < first ? o : first;
     }
-    const double sg = (first < r && Vsrc[first * vrs + src * vcs] < 0.0) ? -1.0 : 1.0;
-    if (lane == 0) S_out[kk] = Sl[src];
-    for (int64_t i = lane; i < r; i += 64) {
+    if (lane == 0) {
+      src_l[q] = src;
+      sg_l[q] = (first < r && Vsrc[first * vrs + src * vcs] < 0.0) ? -1.0 : 1.0;
+      S_out[kk] = Sl[src];
+    }
+  }
+  __syncthreads();
+  // scatter: thread (ri, cj) moves element (i, cj) of 16 rows per pass
+  const int cj = tid % kSsCols, ri = tid / kSsCols;
+  if (cj < ncol) {
+    const int src = src_l[cj];
+    const double sg = sg_l[cj];
+    const int kk = kk0 + cj;
+    for (int64_t i = ri; i < r; i += 256 / kSsCols) {
       const double v = sg * Vsrc[i * vrs + src * vcs];
       if (Vout) Vout[i * ldv + kk] = (T)v;
       if (Vd_out) Vd_out[i * kout + kk] = v;
     }
     if (Wsrc && Wout)
-      for (int i = lane; i < c; i += 64) Wout[(int64_t)i * kout + kk] = sg * Wsrc[(int64_t)i * c + src];
+      for (int i = ri; i < c; i += 256 / kSsCols) Wout[(int64_t)i * kout + kk] = sg * Wsrc[(int64_t)i * c + src];
   }
 }
 
@@ -581,7 +600,8 @@ hipError_t launch_sort_sign_scatter(const double* S, int c, const double* Vsrc, 
                                     int64_t vrs, int64_t vcs, const double* Wsrc, int kout,
                                     double* S_out, T* Vout, int64_t ldv, double* Vd_out,
                                     double* Wout, hipStream_t s) {
-  hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3(1), dim3(1024),
+  if (kout <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3((kout + kSsCols - 1) / kSsCols), dim3(256),
                      (size_t)c * (sizeof(double) + sizeof(int)), s, S,
                      c, Vsrc, r, vrs, vcs, Wsrc, kout, S_out, Vout, ldv, Vd_out, Wout);
   return hipGetLastError();

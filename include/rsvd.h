@@ -48,9 +48,14 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
 
 typedef enum {
   RSVD_F64 = 0, /* A, U, V double; products on FP64 matrix cores */
-  RSVD_F32 = 1  /* A, U, V float; products on FP32 matrix cores with FP32
+  RSVD_F32 = 1, /* A, U, V float; products on FP32 matrix cores with FP32
                    accumulation inside a row block; Gram matrices, Cholesky
                    factors, the small SVD and the eigensolver in FP64 */
+  RSVD_BF16 = 2 /* A stored as bfloat16 with optional FP32 column scales
+                   (the matrix is Aq diag(s)); U, V float.  The passes over A
+                   run on BF16 matrix cores with FP32 accumulation, their
+                   right factors split into hi + lo bfloat16 pairs; the rest
+                   as RSVD_F32.  Randomized PCA only (no A^T A route). */
 } rsvd_dtype;
 
 typedef enum {
@@ -145,6 +150,33 @@ int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, 
                          int32_t k, int32_t p, int32_t q, double t, const double* omega,
                          void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
 
+/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the
+ * matrix Aq diag(col_scale), Aq bfloat16 m x n (device, row-major, lda),
+ * col_scale n FP32 values (device; NULL = all ones).  The plan must be
+ * RSVD_BF16.  H = A G and the power-iteration products run on BF16 matrix
+ * cores with FP32 accumulation and the right factor (scaled by col_scale)
+ * split into hi + lo bfloat16 pairs; T = A^T Q likewise with Q split, then
+ * the rows of T times col_scale; ||A||_F^2 (Eq. sumeigen) is the FP64 sum of
+ * the squared dequantised entries.  CholeskyQR2, the small SVD and U = Q W
+ * as for RSVD_F32.  omega: as rsvd_solve_omega, or NULL for the plan's seeded
+ * sketch.  U (m x k, ldu), V (n x k, ldv) float; S, K as rsvd_solve.
+ * Requires n % 8 == 0, lda % 8 == 0 and a 16-byte aligned A (else
+ * RSVD_ERR_ARG).  rsvd_solve / rsvd_solve_omega on an RSVD_BF16 plan take A
+ * as bfloat16 with unit scales. */
+int32_t rsvd_solve_bf16(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
+                        int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
+                        const double* omega, float* U, int64_t ldu, double* S, float* V,
+                        int64_t ldv, int32_t* K);
+
+/* rsvd_quantize_bf16: storage of an FP32 matrix A (m x n, lda) for
+ * rsvd_solve_bf16: col_scale[j] = 2^e with 2^(e-1) <= max_i |a_ij| < 2^e (1
+ * for a zero or non-finite column maximum) and Aq (m x n, ldq, bfloat16) =
+ * A / col_scale rounded to nearest even; power-of-two scales keep the
+ * scaling exact, so Aq diag(col_scale) is A rounded to 8 significant bits.
+ * Device pointers; runs on the plan's stream (uses the plan's workspace). */
+int32_t rsvd_quantize_bf16(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
+                           void* Aq, int64_t ldq, float* col_scale);
+
 /* gram_eig_solve: truncated SVD through A^T A (Sec. 2.3, Sec. 3.1.3):
  * G = A^T A, eigen-decomposition G = V diag(lambda) V^T (Jacobi, FP64),
  * s_i = sqrt(max(lambda_i, 0)), and u_i = A v_i / s_i for the first `ucols`
@@ -177,7 +209,9 @@ int32_t rsvd_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G,
  * H = A G and A (A^T H) of Sec. 3.1.2.  When Gram != NULL it also writes
  * Gram (c x c, FP64) = Y^T Y accumulated in FP64, and when fro2 != NULL the
  * FP64 sum of a_ij^2 (Eq. sumeigen).  c <= plan l_max unless the plan was
- * sized for the A^T A route (then c <= n_max). */
+ * sized for the A^T A route (then c <= n_max).  On an RSVD_BF16 plan A is
+ * bfloat16 (unit scales; n % 8 == 0, lda % 8 == 0), X and Y float, c <= l_max,
+ * and the product is the bf16 pass with X split into hi + lo pairs. */
 int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
                      const void* X, int64_t ldx, int32_t c, void* Y, int64_t ldy,
                      double* Gram, double* fro2);
@@ -185,7 +219,9 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
 /* rsvd_gemm_tn: Z (n x c, FP64, ld = c) = A^T (n x m) Q (m x c, ldq), the
  * product T = A^T Q of Sec. 3.1.2 (and A^T H of the power iterations); the
  * sum over the m rows is split into row blocks whose partial sums are added
- * in a fixed order (deterministic). */
+ * in a fixed order (deterministic).  On an RSVD_BF16 plan A is bfloat16 (unit
+ * scales; n % 8 == 0, lda % 8 == 0), Q float, c <= l_max (Q is split into
+ * hi + lo bfloat16 pairs on the fly). */
 int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
                      const void* Q, int64_t ldq, int32_t c, double* Z);
 

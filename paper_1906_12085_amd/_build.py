@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsvd.so")
-SOURCES = ["gemm.hip", "small.hip", "eig.hip", "rsvd.hip"]
+SOURCES = ["gemm.hip", "small.hip", "eig.hip", "lowp.hip", "rsvd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are kept out of every kernel: some of their forms

@@ -1,0 +1,510 @@
+// lowp.hip -- the passes over A when A is stored in bfloat16 with one FP32
+// scale per column (dequantised A = Aq diag(s)): the sketch product and the
+// power-iteration products Y = A X (Sec. 3.1.2 steps 2-3) and the projection
+// Z = A^T Q (step 5) on the BF16 matrix cores with FP32 accumulation.  The
+// right factors X and Q are FP32/FP64 values split into hi + lo bfloat16
+// pairs (x = hi + lo to 16 significant bits), so a product costs two BF16
+// matrix-core operations and loses only ~2^-17 relative against an FP32
+// product; A's own rounding is the stored representation (the reference
+// computes on the dequantised stored A).  Also the quantiser
+// (power-of-two column scales, so the scaling itself is exact).
+#include "device_common.h"
+
+namespace rsvd {
+
+namespace {
+
+inline unsigned nblocks(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x32 bf16 matrix core: lane l supplies a = Aop[l%16][8(l/16) .. +7] and
+// b = Bop[8(l/16) .. +7][l%16]; value e of lane l is at row 4(l/16) + e,
+// column l%16 (the fp32 16x16x4 result layout).
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ u32x4 as_u32x4(bf16x8 v) { return __builtin_bit_cast(u32x4, v); }
+
+// hi + lo split of x: hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32)
+__device__ __forceinline__ void split_hilo(float x, __bf16* hi, __bf16* lo) {
+  const __bf16 h = (__bf16)x;
+  *hi = h;
+  *lo = (__bf16)(x - (float)h);
+}
+
+// ---------------------------------------------------------------------------
+// Octet transpose: lanes o = 0..7 of an aligned group of 8 each hold 8 bf16
+// (row o of an 8 x 8 block, four dwords of two columns each); afterwards lane
+// o holds column o (rows 0..7 in order).  Three exchange stages: 4 x 4 blocks
+// between lanes o and o^4, 2 x 2 blocks between o and o^2, single elements
+// between o and o^1.
+template <int PAT>
+__device__ __forceinline__ unsigned swz(unsigned v) {
+  return (unsigned)__builtin_amdgcn_ds_swizzle((int)v, PAT);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ u32x4 octet_transpose(u32x4 d, int o) {
+  // stage A: lane o (b = bit 2) keeps its half of the columns 4b..4b+3 and
+  // takes the partner's: rows {o&3, (o&3)+4}, columns 4b..4b+3
+  {
+    const bool b = (o & 4) != 0;
+    const unsigned s0 = b ? d[0] : d[2], s1 = b ? d[1] : d[3];
+    const unsigned r0 = swz<0x101F>(s0), r1 = swz<0x101F>(s1);   // xor 4
+    d = b ? u32x4{r0, r1, d[2], d[3]} : u32x4{d[0], d[1], r0, r1};
+  }
+  // stage B: rows {r, r+2, r+4, r+6} (r = o&1), columns 4b+2c1, +1 (c1 = bit 1)
+  {
+    const bool c1 = (o & 2) != 0;
+    const unsigned s0 = c1 ? d[0] : d[1], s1 = c1 ? d[2] : d[3];
+    const unsigned r0 = dpp<0x4E>(s0), r1 = dpp<0x4E>(s1);        // quad_perm(2,3,0,1): xor 2
+    d = c1 ? u32x4{r0, d[1], r1, d[3]} : u32x4{d[0], r0, d[2], r1};
+  }
+  // stage C: column 4b + 2c1 + c0 for rows 2p, 2p+1 (c0 = bit 0)
+  {
+    const bool c0 = (o & 1) != 0;
+    u32x4 pe;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) pe[p] = dpp<0xB1>(d[p]);          // quad_perm(1,0,3,2): xor 1
+    // c0 = 0: low(own) | low(partner) << 16;  c0 = 1: high(partner) | high(own) << 16
+    const unsigned sel = c0 ? 0x03020706u : 0x05040100u;
+    u32x4 out;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) out[p] = __builtin_amdgcn_perm(pe[p], d[p], sel);
+    d = out;
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Quantiser: s_j = 2^e with 2^(e-1) <= max_i |A_ij| < 2^e (s_j = 1 for a zero
+// column), Aq = bf16(A / s_j) rounded to nearest even.
+__global__ void k_colmax_abs(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                             int64_t rows_per_block, unsigned* __restrict__ cmax) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    float v = 0.f;
+    for (int64_t i = r0; i < r1; ++i) v = fmaxf(v, fabsf(A[i * lda + j]));
+    // non-negative floats order like their bit patterns
+    atomicMax(cmax + j, __float_as_uint(v));
+  }
+}
+
+__device__ __forceinline__ float pow2_scale(unsigned maxbits) {
+  const float mx = __uint_as_float(maxbits);
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  (void)frexpf(mx, &e);                 // mx = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, e);
+}
+
+__global__ void k_quantize_bf16(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                const unsigned* __restrict__ cmax, __bf16* __restrict__ Aq,
+                                int64_t ldq, float* __restrict__ scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx / n, j = idx - i * n;
+  const float s = pow2_scale(cmax[j]);
+  Aq[i * ldq + j] = (__bf16)(A[i * lda + j] / s);
+  if (i == 0) scale[j] = s;
+}
+
+// Xhi, Xlo (c x n, row stride ldx) = split of (diag(s) X)^T, X (n x c) FP64
+// row-major with ld c: row j of the result is column j of diag(s) X.
+__global__ void k_cast_hilo_t(const double* __restrict__ X, int64_t n, int c,
+                              const float* __restrict__ scale, __bf16* __restrict__ Xhi,
+                              __bf16* __restrict__ Xlo, int64_t ldx) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * c) return;
+  const int j = (int)(idx / n);
+  const int64_t i = idx - (int64_t)j * n;          // consecutive threads: consecutive i
+  const float x = (float)(X[i * c + j] * (scale ? (double)scale[i] : 1.0));
+  split_hilo(x, Xhi + (int64_t)j * ldx + i, Xlo + (int64_t)j * ldx + i);
+}
+
+// Z (n x c, FP64, ld c) rows scaled: Z_i *= s_i.
+__global__ void k_scale_rows(double* __restrict__ Z, int64_t n, int c,
+                             const float* __restrict__ scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * c) return;
+  Z[idx] *= (double)scale[idx / c];
+}
+
+// ---------------------------------------------------------------------------
+// Y (m x c, FP32) = Aq (m x n, bf16) (Xhi + Xlo)^T, X* c x n: block = 256
+// rows (4 waves of 64 rows x NT column tiles of 16); A goes straight from
+// memory into the matrix-core operand registers (lane (lr, g) of a 16-row
+// tile loads the 16 bytes at row lr, k = 32 st + 8 g of the chunk), one
+// chunk ahead; the kBK-wide chunks of Xhi and Xlo are staged in LDS (two
+// buffers) and read back as 16-byte operands.  Optionally the FP64 sum of the
+// squared dequantised entries (Eq. sumeigen) per block.  Requires n % 8 == 0
+// and 16-byte rows of A, Xhi, Xlo.
+constexpr int kBM = 256, kBK = 64, kBLD = kBK + 8;
+
+template <int NT>
+__global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
+    const __bf16* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+    const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo, int64_t ldx, int c,
+    const float* __restrict__ scale, float* __restrict__ Y, int64_t ldy,
+    double* __restrict__ fro2_part) {
+  constexpr int BC = 16 * NT;
+  constexpr int XP = (2 * BC * (kBK / 8) + 255) / 256;    // 16-byte X pieces per thread
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][2][BC * kBLD];
+  __shared__ double s2l[2][kBK];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kBM;
+  const int64_t rows = m - row0 < kBM ? m - row0 : kBM;
+  const int nch = (int)((n + kBK - 1) / kBK);
+  const bool do_ss = fro2_part != nullptr;
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<__bf16*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 2), 0x00020000);
+  const int xrange = (int)(((int64_t)(c - 1) * ldx + n) * 2);
+  const __amdgpu_buffer_rsrc_t hr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xhi), 0, xrange, 0x00020000);
+  const __amdgpu_buffer_rsrc_t lrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xlo), 0, xrange, 0x00020000);
+  int voa[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) voa[i] = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 8 * g) * 2);
+  // X piece p of this thread: hi/lo h, row xr, 8-column group q of the chunk
+  int vox[XP];
+  bool xon[XP];
+#pragma unroll
+  for (int u = 0; u < XP; ++u) {
+    const int p = tid + 256 * u;
+    const int h = p / (BC * (kBK / 8)), rem = p - h * (BC * (kBK / 8));
+    const int xr = rem / (kBK / 8), q = rem - xr * (kBK / 8);
+    xon[u] = p < 2 * BC * (kBK / 8);
+    vox[u] = (int)(((int64_t)xr * ldx + 8 * q) * 2);
+  }
+  // A fragments of one 32-deep step, loaded one step ahead; X pieces of the
+  // next chunk loaded at its first step and stored to LDS after its second
+  u32x4 ra[4], rx[XP];
+  auto load_a = [&](int t) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      ra[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], t * 64, 0));
+  };
+  auto load_x = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < XP; ++u) {
+      const int p = tid + 256 * u;
+      const bool hi = p < BC * (kBK / 8);
+      rx[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                            hi ? hr : lrs, vox[u], ch * kBK * 2, 0));
+    }
+  };
+  // X chunk ch to LDS buffer buf, zero beyond n (the pieces there hold the
+  // next row); squared scales of the chunk's columns
+  auto store_x = [&](int buf, int ch) {
+    const int kend = (int)(n - (int64_t)ch * kBK);
+#pragma unroll
+    for (int u = 0; u < XP; ++u) {
+      if (!xon[u]) continue;
+      const int p = tid + 256 * u;
+      const int h = p / (BC * (kBK / 8)), rem = p - h * (BC * (kBK / 8));
+      const int xr = rem / (kBK / 8), q = rem - xr * (kBK / 8);
+      const u32x4 v = 8 * q < kend ? rx[u] : u32x4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u32x4*>(&Xs[buf][h][xr * kBLD + 8 * q]) = v;
+    }
+    if (do_ss && tid < kBK) {
+      const int64_t col = (int64_t)ch * kBK + tid;
+      const double s = (col < n && scale) ? (double)scale[col] : 1.0;
+      s2l[buf][tid] = s * s;
+    }
+  };
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double ss = 0.0;
+  const int nst = (int)((n + 31) / 32);        // 32-deep steps
+  load_x(0);
+  load_a(0);
+  store_x(0, 0);
+  __syncthreads();
+  for (int t = 0; t < nst; ++t) {
+    const int ch = t >> 1, st = t & 1, buf = ch & 1;
+    u32x4 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = ra[i];
+    const bool more_x = st == 0 && ch + 1 < nch;
+    if (more_x) load_x(ch + 1);
+    load_a(t + 1 < nst ? t + 1 : t);          // the last prefetch is a harmless repeat
+    __builtin_amdgcn_sched_barrier(0);
+    // a step that runs past n holds the next row's values there
+    if (32 * t + 8 * g >= n) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = u32x4{0u, 0u, 0u, 0u};
+    }
+    bf16x8 bh[NT], bl[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      bh[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][0][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
+      bl[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][1][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl[j], acc[i][j]);
+      }
+    if (do_ss) {
+      // column 32 st + 8 g + e of the chunk, four rows per value
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float v2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float v = (float)as_bf16x8(a[i])[e];
+          v2 = fmaf(v, v, v2);
+        }
+        ss = fma((double)v2, s2l[buf][32 * st + 8 * g + e], ss);
+      }
+    }
+    if (st == 1 || t + 1 == nst) {
+      // end of chunk ch: the next chunk's X goes to the other buffer
+      if (ch + 1 < nch) store_x(buf ^ 1, ch + 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + wave * 64 + 16 * i + 4 * g + e;
+        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+      }
+    }
+  if (do_ss) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) fro2_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z partials (FP64, one n x c slab per row split) of Aq^T Q: block = one row
+// split x 512 columns of A (column tile blockIdx.y), 8 waves of 64 columns
+// (4 x NT tiles of 16 x 16).  Chunks of 32 rows (one 32-deep matrix-core
+// step): lane l = 16 g + 8 h + o loads row 8 g + o of the chunk, columns
+// 16 i + 8 h .. +7 of its wave's tiles, and the octet transpose turns that
+// into the operand the matrix core takes (column 8 h + o = l % 16, rows
+// 8 g .. 8 g + 7).  Q's chunk is split into hi + lo bfloat16 and transposed
+// the same way by waves 0..NT-1 (one column tile each) into LDS, where every
+// wave reads it.  Rows past the split read zeros (buffer range); columns of A
+// past n and of Q past c only reach outputs that are not stored.  Requires
+// 16-byte rows of A and Q (lda % 8 == 0, ldq % 8 == 0), n % 8 == 0, and
+// round_up(c, 8) readable columns in every row of Q (ldq >= that).
+constexpr int kTA = 512, kTR = 32;
+
+template <int NT>
+__global__ __launch_bounds__(512) void k_gemm_tn_bf16(
+    const __bf16* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
+    int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split) {
+  __shared__ __attribute__((aligned(16))) u32x4 Bq[2][NT][2][64];   // [buf][j][hi/lo][lane]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int o = lane & 7, h = (lane >> 3) & 1, g = lane >> 4;
+  const int64_t rs = (int64_t)blockIdx.x * rows_per_split;
+  const int64_t re = rs + rows_per_split < m ? rs + rows_per_split : m;
+  const int64_t col0 = (int64_t)blockIdx.y * kTA + wave * 64;
+  const int nchunk = (int)((re - rs + kTR - 1) / kTR);
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<__bf16*>(A + rs * lda), 0, (int)(((re - rs - 1) * lda + n) * 2), 0x00020000);
+  const int cpad = (c + 7) & ~7;              // Q rows hold cpad readable columns
+  const __amdgpu_buffer_rsrc_t qr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(Q + rs * ldq), 0, (int)(((re - rs - 1) * ldq + cpad) * 4), 0x00020000);
+  // A: row 8 g + o of the chunk, columns col0 + 16 i + 8 h; clamped inside
+  // the row range of the descriptor when the tile runs past n (those
+  // columns' outputs are dropped)
+  int voa[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int64_t cc = col0 + 16 * i + 8 * h;
+    if (cc > n - 8) cc = n - 8;
+    voa[i] = (int)(((int64_t)(8 * g + o) * lda + cc) * 2);
+  }
+  // Q (waves 0..NT-1): row 8 g + o, columns 16 wave + 8 h .. +7, clamped to
+  // the readable width (the columns past c only reach dropped outputs)
+  const int qc = 16 * wave + 8 * h < cpad - 8 ? 16 * wave + 8 * h : cpad - 8;
+  const int voq = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
+  const bool qwave = wave < NT;
+  u32x4 ra[4];
+  f32x4 rq0, rq1;
+  auto load = [&](int ch) {
+    const int soa = ch * kTR * (int)lda * 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      ra[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], soa, 0));
+    if (qwave) {
+      const int soq = ch * kTR * (int)ldq * 4;
+      rq0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, soq, 0));
+      rq1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq + 16, soq, 0));
+    }
+  };
+  auto store_q = [&](int buf) {
+    if (!qwave) return;
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      __bf16 a, b;
+      split_hilo(rq0[e], &a, &b);
+      hi[e] = a; lo[e] = b;
+      split_hilo(rq1[e], &a, &b);
+      hi[4 + e] = a; lo[4 + e] = b;
+    }
+    Bq[buf][wave][0][lane] = octet_transpose(as_u32x4(hi), o);
+    Bq[buf][wave][1][lane] = octet_transpose(as_u32x4(lo), o);
+  };
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load(0);
+  store_q(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    u32x4 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = octet_transpose(ra[i], o);
+    const bool more = ch + 1 < nchunk;
+    load(more ? ch + 1 : ch);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const bf16x8 bh = as_bf16x8(Bq[buf][j][0][lane]);
+      const bf16x8 bl = as_bf16x8(Bq[buf][j][1][lane]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh, acc[i][j]);
+        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl, acc[i][j]);
+      }
+    }
+    if (more) store_q(buf ^ 1);
+    __syncthreads();
+  }
+  // acc[i][j][e]: A column col0 + 16 i + 4 g + e, Q column 16 j + (lane % 16)
+  double* Pb = P + (int64_t)blockIdx.x * n * c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int qcol = 16 * j + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t acol = col0 + 16 * i + 4 * g + e;
+        if (acol < n && qcol < c) Pb[acol * c + qcol] = (double)acc[i][j][e];
+      }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+hipError_t launch_quantize_bf16(const float* A, int64_t m, int64_t n, int64_t lda, __bf16* Aq,
+                                int64_t ldq, float* scale, unsigned* cmax, hipStream_t s) {
+  if (m < 1 || n < 1) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(cmax), n, 0, s);
+  if (e != hipSuccess) return e;
+  const int64_t rpb = 256;
+  hipLaunchKernelGGL(k_colmax_abs, dim3((unsigned)((m + rpb - 1) / rpb)), dim3(256), 0, s, A, m, n,
+                     lda, rpb, cmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_quantize_bf16, dim3(nblocks(m * n, 256)), dim3(256), 0, s, A, m, n, lda,
+                     cmax, Aq, ldq, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_hilo_t(const double* X, int64_t n, int c, const float* scale, __bf16* Xhi,
+                              __bf16* Xlo, int64_t ldx, hipStream_t s) {
+  if (n * c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_hilo_t, dim3(nblocks(n * c, 256)), dim3(256), 0, s, X, n, c, scale,
+                     Xhi, Xlo, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hipStream_t s) {
+  if (!scale || n * c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(n * c, 256)), dim3(256), 0, s, Z, n, c, scale);
+  return hipGetLastError();
+}
+
+bool bf16_pass_applies(const void* A, int64_t n, int64_t lda, int c) {
+  return c >= 1 && c <= 128 && n % 8 == 0 && lda % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (int64_t)kBM * lda * 2 < (1LL << 31);
+}
+
+hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda,
+                               const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, int c,
+                               const float* scale, float* Y, int64_t ldy, double* fro2_part,
+                               int* nparts, hipStream_t s) {
+  if (!bf16_pass_applies(A, n, lda, c) || ldx % 8 != 0 || (int64_t)c * ldx * 2 >= (1LL << 31))
+    return hipErrorInvalidValue;
+  const int64_t nblk = (m + kBM - 1) / kBM;
+  if (nparts) *nparts = (int)nblk;
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblk), block(256);
+#define RSVD_NT_BF16(NT)                                                                        \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL(k_gemm_nt_bf16<NT>, grid, block, 0, s, A, m, n, lda, Xhi, Xlo, ldx, c,   \
+                       scale, Y, ldy, fro2_part);                                               \
+    break;
+  switch ((c + 15) / 16) {
+    RSVD_NT_BF16(1) RSVD_NT_BF16(2) RSVD_NT_BF16(3) RSVD_NT_BF16(4)
+    RSVD_NT_BF16(5) RSVD_NT_BF16(6) RSVD_NT_BF16(7) RSVD_NT_BF16(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_NT_BF16
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tn_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                               hipStream_t s) {
+  if (!bf16_pass_applies(A, n, lda, c) || ldq % 8 != 0 || ldq < ((c + 7) & ~7) ||
+      (reinterpret_cast<uintptr_t>(Q) % 16) != 0 || m <= 0)
+    return hipErrorInvalidValue;
+  const int ntile = (int)((n + kTA - 1) / kTA);
+  int64_t ns = 256 / ntile;
+  if (ns < 1) ns = 1;
+  if (ns > (m + kTR - 1) / kTR) ns = (m + kTR - 1) / kTR;
+  if (ns > max_split) ns = max_split;
+  int64_t rps = (m + ns - 1) / ns;
+  rps = (rps + kTR - 1) / kTR * kTR;
+  ns = (m + rps - 1) / rps;
+  const int64_t ld = lda * 2 > ldq * 4 ? lda * 2 : ldq * 4;
+  if ((rps + kTR) * ld >= (1LL << 31)) return hipErrorInvalidValue;
+  *nsplit = (int)ns;
+  const dim3 grid((unsigned)ns, (unsigned)ntile), block(512);
+#define RSVD_TN_BF16(NT)                                                                        \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL(k_gemm_tn_bf16<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, P, rps); \
+    break;
+  switch ((c + 15) / 16) {
+    RSVD_TN_BF16(1) RSVD_TN_BF16(2) RSVD_TN_BF16(3) RSVD_TN_BF16(4)
+    RSVD_TN_BF16(5) RSVD_TN_BF16(6) RSVD_TN_BF16(7) RSVD_TN_BF16(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_TN_BF16
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -81,7 +81,12 @@ namespace {
     if (e_ != hipSuccess) return RSVD_ERR_DEVICE;          \
   } while (0)
 
+// Working type of Y, Q, U, V: double for RSVD_F64, float otherwise (a BF16
+// plan stores only A in bfloat16).
 size_t elem_size(int dtype) { return dtype == RSVD_F64 ? sizeof(double) : sizeof(float); }
+// Row stride of Q1: l rounded up to 8 (the bf16 projection reads whole
+// 16-byte groups of Q's rows).
+int64_t ldq1_of(int64_t l) { return (l + 7) / 8 * 8; }
 
 // Carve the workspace; with base == nullptr it only counts bytes.
 // The next event pair of timer `kind` (both null when timing is off or the
@@ -132,7 +137,7 @@ size_t carve(rsvd_plan_s* p, char* base) {
   p->omega = (double*)take(n * l * 8);
   p->Xs = take(n * cmax * es);
   p->Y = take(m * l * es);
-  p->Q1 = take(m * l * es);
+  p->Q1 = take(m * ldq1_of(l) * es);
   p->part = (double*)take(p->max_split * n * cmax * 8);
   p->fro2_part = (double*)take(((m + 127) / 128 + 1) * 8);
   p->scal = (double*)take(64);
@@ -206,11 +211,32 @@ hipError_t reset(rsvd_plan_s* p) {
   return hipGetLastError();
 }
 
+// A stored in bfloat16 with FP32 column scales (null: ones).
+struct LowpA {
+  const __bf16* A;
+  const float* scale;
+};
+
 template <typename T>
 struct Path {
   rsvd_plan_s* p;
   hipStream_t s;
   explicit Path(rsvd_plan_s* plan) : p(plan), s(plan->stream) {}
+
+  // Z (n x c, FP64) = A^T Q for bfloat16 A: Aq^T Q on the bf16 matrix cores
+  // (Q split into hi + lo), then the rows times the column scales.
+  hipError_t tn_bf16(const LowpA& lp, int64_t m, int64_t n, int64_t lda, const float* Q,
+                     int64_t ldq, int c, double* Z) {
+    int ns = 0;
+    hipError_t e;
+    {
+      KtScope ts(p, KT_PASS_TN);
+      e = launch_gemm_tn_bf16(lp.A, m, n, lda, Q, ldq, c, p->part, p->max_split, &ns, s);
+    }
+    if (e != hipSuccess) return e;
+    if ((e = launch_reduce_partials(p->part, ns, n, c, Z, c, s)) != hipSuccess) return e;
+    return launch_scale_rows(Z, n, c, lp.scale, s);
+  }
 
   // Wout (c x c) = Y^T Y with exact FP64 products, fixed-order reduction.
   hipError_t gram(const T* Y, int64_t m, int c, int64_t ldy, double* Wout) {
@@ -304,13 +330,15 @@ hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c
 template <typename T>
 int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, int k, int pov,
                  int q, double t, const double* omega, T* U, int64_t ldu, double* S, T* V,
-                 int64_t ldv, int32_t* K) {
+                 int64_t ldv, int32_t* K, const LowpA* lp = nullptr) {
   const int l = (int)((k + pov < n) ? k + pov : n);
   hipStream_t s = p->stream;
   Path<T> P(p);
   T* Xs = (T*)p->Xs;
   T* Y = (T*)p->Y;
   T* Q1 = (T*)p->Q1;
+  // Q1's row stride: l, or l rounded up to 8 for the bf16 projection
+  const int64_t lq = lp ? ldq1_of(l) : l;
   RSVD_CHECK(reset(p));
   // step 1: the Gaussian sketch matrix G (n x l)
   if (!omega) {
@@ -323,6 +351,15 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
                                     reinterpret_cast<const float*>(Xs), n, l);
   auto pass_nn = [&](const double* X64, double* fro2_part, int* np) -> hipError_t {
     hipError_t e;
+    if (lp) {
+      // bf16 A: (diag(s) X)^T as hi + lo bf16 pairs (l x n each) in Xs
+      __bf16* Xhi = reinterpret_cast<__bf16*>(p->Xs);
+      __bf16* Xlo = Xhi + (int64_t)l * n;
+      if ((e = launch_cast_hilo_t(X64, n, l, lp->scale, Xhi, Xlo, n, s)) != hipSuccess) return e;
+      KtScope ts(p, KT_PASS_NN);
+      return launch_gemm_nt_bf16(lp->A, m, n, lda, Xhi, Xlo, n, l, lp->scale,
+                                 reinterpret_cast<float*>(Y), l, fro2_part, np, s);
+    }
     if (tall) {
       if ((e = launch_cast_t_from_f64<T>(X64, n, l, l, Xs, n, s)) != hipSuccess) return e;
       KtScope ts(p, KT_PASS_NN);
@@ -337,17 +374,21 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   int np = 0;
   RSVD_CHECK(pass_nn(omega, p->fro2_part, &np));
   RSVD_CHECK(launch_reduce_scalar(p->fro2_part, np, p->scal, s));
-  RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  auto pass_tn = [&](double* Z) -> hipError_t {
+    if (lp) return P.tn_bf16(*lp, m, n, lda, reinterpret_cast<const float*>(Q1), lq, l, Z);
+    return P.tn(A, m, n, lda, Q1, lq, l, Z);
+  };
   // step 3: power iterations H = A (A^T H), orthonormalised after each product
   for (int it = 0; it < q; ++it) {
-    RSVD_CHECK(P.tn(A, m, n, lda, Q1, l, l, p->Zd));
+    RSVD_CHECK(pass_tn(p->Zd));
     RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));  // A^T Q
     RSVD_CHECK(cqr2_small(p, p->Z2, n, l, p->Zq));
     RSVD_CHECK(pass_nn(p->Zq, nullptr, nullptr));
-    RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+    RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
   }
   // step 5: T = A^T Q
-  RSVD_CHECK(P.tn(A, m, n, lda, Q1, l, l, p->Zd));
+  RSVD_CHECK(pass_tn(p->Zd));
   RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));
   // step 6: T = V~ S~ W^T
   RSVD_CHECK(small_svd_unsorted(p, p->Z2, n, l));
@@ -356,15 +397,15 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   // step 7: U~ = Q W = Q1 (R2^-1 W), first k columns; fp32 takes the l x k
   // factor transposed into the tall kernel
   const bool tall_u = std::is_same<T, float>::value &&
-                      nt_tall_applies(reinterpret_cast<const float*>(Q1), l, l,
+                      nt_tall_applies(reinterpret_cast<const float*>(Q1), l, lq,
                                       reinterpret_cast<const float*>(p->MkT), l, k);
   RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s, tall_u));
   if (tall_u)
-    RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, l, l,
+    RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, l, lq,
                                    reinterpret_cast<const float*>(p->MkT), l, k,
                                    reinterpret_cast<float*>(U), ldu, nullptr, nullptr, s));
   else
-    RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, l, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
+    RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, lq, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
   // K by the explained-variance criterion (Sec. 2.4)
   RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
   return RSVD_OK;
@@ -468,7 +509,8 @@ int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_
                          int32_t dtype, int32_t want_gram, uint64_t seed, void* stream) {
   if (!plan) return RSVD_ERR_ARG;
   *plan = nullptr;
-  if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_ARG;
+  if (dtype == RSVD_BF16 && want_gram) return RSVD_ERR_ARG;   // the A^T A route is fp32/fp64
   if (l_max < 1) return RSVD_ERR_ARG;
   if (n_max < 1 || m_max < n_max) return RSVD_ERR_SHAPE;
   if (l_max > kMaxL) return RSVD_ERR_SHAPE;
@@ -581,8 +623,36 @@ int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, 
   if (plan->dtype == RSVD_F64)
     return rsvd_run<double>(plan, (const double*)A, m, n, lda, k, p, q, t, omega, (double*)U, ldu,
                             S, (double*)V, ldv, K);
+  if (plan->dtype == RSVD_BF16)
+    return rsvd_solve_bf16(plan, A, nullptr, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
+                           (float*)V, ldv, K);
   return rsvd_run<float>(plan, (const float*)A, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
                          (float*)V, ldv, K);
+}
+
+int32_t rsvd_solve_bf16(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
+                        int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
+                        const double* omega, float* U, int64_t ldu, double* S, float* V,
+                        int64_t ldv, int32_t* K) {
+  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (plan->dtype != RSVD_BF16) return RSVD_ERR_ARG;
+  const int l = (int)((k + (int64_t)p < n) ? k + p : n);
+  if (!bf16_pass_applies(A, n, lda, l)) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  const LowpA lp{(const __bf16*)A, col_scale};
+  return rsvd_run<float>(plan, nullptr, m, n, lda, k, p, q, t, omega, U, ldu, S, V, ldv, K, &lp);
+}
+
+int32_t rsvd_quantize_bf16(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
+                           void* Aq, int64_t ldq, float* col_scale) {
+  if (!plan || !A || !Aq || !col_scale) return RSVD_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || ldq < n) return RSVD_ERR_ARG;
+  if (m > plan->m_max || n > plan->n_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  RSVD_CHECK(launch_quantize_bf16(A, m, n, lda, (__bf16*)Aq, ldq, col_scale,
+                                  reinterpret_cast<unsigned*>(plan->part), plan->stream));
+  return RSVD_OK;
 }
 
 int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,
@@ -628,6 +698,21 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
     RSVD_CHECK(launch_gemm_nn<double>((const double*)A, m, n, lda, (const double*)X, ldx, c,
                                       (double*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     if (Gram) RSVD_CHECK(Path<double>(plan).gram((const double*)Y, m, c, ldy, Gram));
+  } else if (plan->dtype == RSVD_BF16) {
+    // A bfloat16 (unit column scales), X and Y float: X through FP64 into
+    // the hi + lo bf16 pairs the pass takes
+    if (c > plan->l_max) return RSVD_ERR_SHAPE;
+    if (!bf16_pass_applies(A, n, lda, c)) return RSVD_ERR_ARG;
+    RSVD_CHECK(launch_cast_to_f64<float>((const float*)X, n, c, ldx, plan->Zd, c, s));
+    __bf16* Xhi = reinterpret_cast<__bf16*>(plan->Xs);
+    __bf16* Xlo = Xhi + n * c;
+    RSVD_CHECK(launch_cast_hilo_t(plan->Zd, n, c, nullptr, Xhi, Xlo, n, s));
+    {
+      KtScope ts(plan, KT_PASS_NN);
+      RSVD_CHECK(launch_gemm_nt_bf16((const __bf16*)A, m, n, lda, Xhi, Xlo, n, c, nullptr,
+                                     (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
+    }
+    if (Gram) RSVD_CHECK(Path<float>(plan).gram((const float*)Y, m, c, ldy, Gram));
   } else {
     if (c > 128 && !fro2 && n <= plan->n_max) {
       // wide product: X transposed into plan scratch (c x n <= cmax x n_max)
@@ -661,7 +746,17 @@ int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
   if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
   if (plan->dtype == RSVD_F64)
     RSVD_CHECK(Path<double>(plan).tn((const double*)A, m, n, lda, (const double*)Q, ldq, c, Z));
-  else
+  else if (plan->dtype == RSVD_BF16) {
+    // A bfloat16 (unit column scales): Q copied into the plan's padded rows
+    if (c > plan->l_max) return RSVD_ERR_SHAPE;
+    if (!bf16_pass_applies(A, n, lda, c)) return RSVD_ERR_ARG;
+    const int64_t lq = ldq1_of(c);
+    if (hipMemcpy2DAsync(plan->Q1, lq * sizeof(float), Q, ldq * sizeof(float), c * sizeof(float),
+                         m, hipMemcpyDeviceToDevice, plan->stream) != hipSuccess)
+      return RSVD_ERR_DEVICE;
+    RSVD_CHECK(Path<float>(plan).tn_bf16(LowpA{(const __bf16*)A, nullptr}, m, n, lda,
+                                         (const float*)plan->Q1, lq, c, Z));
+  } else
     RSVD_CHECK(Path<float>(plan).tn((const float*)A, m, n, lda, (const float*)Q, ldq, c, Z));
   return RSVD_OK;
 }

@@ -190,6 +190,31 @@ hipError_t launch_scale_cols_inv(const double* V, int64_t n, int cols, int64_t l
 hipError_t launch_transpose_f32(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Xt,
                                 int64_t ldxt, hipStream_t s);
 
+// ---- bfloat16 storage of A (lowp.hip) ----
+// Aq (m x n, ldq) = bf16(A / s), s (n) = power-of-two column scales from the
+// column maxima (cmax: n words of workspace).
+hipError_t launch_quantize_bf16(const float* A, int64_t m, int64_t n, int64_t lda, __bf16* Aq,
+                                int64_t ldq, float* scale, unsigned* cmax, hipStream_t s);
+// Xhi + Xlo (c x n, ld ldx) = (diag(scale) X)^T split into bf16 pairs; X is
+// n x c FP64 row-major (ld c); scale may be null (ones).
+hipError_t launch_cast_hilo_t(const double* X, int64_t n, int c, const float* scale, __bf16* Xhi,
+                              __bf16* Xlo, int64_t ldx, hipStream_t s);
+// Z (n x c, ld c) rows times scale (no-op for a null scale).
+hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hipStream_t s);
+// Whether the bf16 passes take A (n % 8 == 0, 16-byte rows, c <= 128).
+bool bf16_pass_applies(const void* A, int64_t n, int64_t lda, int c);
+// Y (m x c, fp32) = Aq (Xhi + Xlo)^T; per-block FP64 sums of the squared
+// dequantised entries into fro2_part (count in *nparts) when non-null.
+hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda,
+                               const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, int c,
+                               const float* scale, float* Y, int64_t ldy, double* fro2_part,
+                               int* nparts, hipStream_t s);
+// FP64 partials (nsplit x n x c) of Aq^T Q (unscaled), Q fp32 with ldq % 8 == 0
+// and round_up(c, 8) readable columns per row.
+hipError_t launch_gemm_tn_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
+                               hipStream_t s);
+
 // S[i] = sqrt(max(lam[i], 0)).
 hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s);
 // p[0..n) = v (a kernel, so the fill can be captured in a graph).

@@ -26,7 +26,7 @@ METRIC = "rSVD solves/s + TFLOP/s (% roofline) at ≤1e-4 σ rel err; p50/p99 la
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 
 
 def parse():
@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the leg on bfloat16 storage of the same A")
     return ap.parse_args()
 
 
@@ -144,6 +146,74 @@ def kernel_rooflines(ktimes, m, n, l, b, steps):
             "kernel": dom["kernel"], "launch_ms": dom["launch_ms"],
             "ms_per_step": dom["ms_per_step"]}
     return roof, rows
+
+
+def bf16_rooflines(ktimes, m, n, l, steps):
+    """The two bf16 passes of the bfloat16-storage leg: HBM-bound (2mnl flops
+    over 2mn + 4ml bytes, far below the bf16 matrix-core ridge)."""
+    rows = {}
+    names = {"pass_nn": "k_gemm_nt_bf16", "pass_tn": "k_gemm_tn_bf16"}
+    for kind, name in names.items():
+        ms, launches = ktimes.get(kind, (0.0, 0))
+        if launches == 0 or ms <= 0:
+            continue
+        flops, nbytes = 2.0 * m * n * l, 2.0 * m * n + 4.0 * m * l
+        sec = ms / 1e3
+        ach = nbytes / sec / 1e9
+        rows[kind] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1),
+                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                      "tflops": round(flops / sec / 1e12, 2), "launch_ms": round(ms, 4),
+                      "launches_per_solve": round(launches / steps, 2),
+                      "work_per_launch": {"flops": flops, "bytes": nbytes}}
+    return rows
+
+
+def bf16_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream):
+    """Randomized PCA of the same A stored in bfloat16 with power-of-two
+    column scales (quantised outside the timed region), timed like the fp32
+    leg; accuracy against the FP64 path on the dequantised stored matrix."""
+    l = k + p
+    dev = A.device
+    plan = rs.Plan(m, n, l, torch.bfloat16, seed=seed, stream=stream)
+    Aq, sc = plan.quantize(A)
+    U = torch.empty(m, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(n, k, dtype=torch.float32, device=dev)
+    K = torch.empty(1, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        rs.rsvd_solve_bf16(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    rs.rsvd_plan_kernel_times(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        rs.rsvd_solve_bf16(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ktimes = rs.rsvd_plan_kernel_times(plan.handle, False)
+    status = rs.rsvd_plan_status(plan.handle)
+    ms = [e[0].elapsed_time(e[1]) for e in evs]
+    A64 = Aq.double() * sc.double()[None, :]
+    plan64 = rs.Plan(m, n, l, torch.float64, want_gram=False, seed=seed, stream=stream)
+    r64 = plan64.solve(A64, k, p, q, t)
+    sig_err = float(torch.max(torch.abs(S - r64.S) / r64.S).item())
+    same_k = int(K.item()) == r64.K
+    plan64.close()
+    plan.close()
+    del A64, Aq
+    torch.cuda.empty_cache()
+    med = pct(ms, 50)
+    nbytes = (2 * q + 2) * (2.0 * m * n + 4.0 * m * l)
+    return {"storage": "bf16 + fp32 power-of-two column scales", "p50_ms": round(med, 3),
+            "p99_ms": round(pct(ms, 99), 3), "solves_per_s": round(1000.0 / med, 2),
+            "wall_solves_per_s": round(steps / wall, 2),
+            "gbs_passes": round(nbytes / (med / 1e3) / 1e9, 1), "K": int(K.item()),
+            "K_equals_fp64_path": same_k, "status": rs.STATUS.get(status, status),
+            "sigma_rel_err_vs_fp64_path_on_stored_matrix": sig_err,
+            "kernels": bf16_rooflines(ktimes, m, n, l, steps)}
 
 
 def pct(xs, p):
@@ -265,6 +335,11 @@ def main():
                             "solves_per_s": round(1000.0 / gr_med, 2),
                             "tflops": round(gr_f / (gr_med / 1e3) / 1e12, 2),
                             "K": int(Kg.item())}
+
+    if not args.no_bf16:
+        print(f"[bench] bf16 storage leg: {args.steps} solves", file=sys.stderr, flush=True)
+        legs["rsvd_bf16"] = bf16_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"],
+                                     args.steps, args.warmup, stream)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -7,7 +7,8 @@ Randomized PCA: the oracle runs the whole solve on the same stored A (read
 back to FP64) with the same sketch (the published Philox/Box-Muller
 definition, rounded to FP32 as the GPU uses it); gate: relative singular-value
 error <= 1e-4, largest principal angle of the top-k U and V subspaces
-<= 1e-3 rad, K equal.
+<= 1e-3 rad, K equal.  The same for A stored in bfloat16 with power-of-two
+column scales (the oracle on the dequantised stored matrix).
 
 A^T A route: the oracle forms A^T A and its Jacobi eigen-decomposition; all
 512 singular values are gated at 1e-4 relative (the spectrum is well
@@ -59,6 +60,30 @@ def test_fullsize_rsvd_vs_oracle(workload):
     assert oracle.principal_angle_max(ref.V, V) <= 1e-3
     assert oracle.principal_angle_max(ref.U, U) <= 1e-3
     assert res.K == ref.K == k and ref.status == oracle.WARN_THRESHOLD
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_rsvd_bf16_vs_oracle(workload):
+    # the same A stored in bfloat16 with power-of-two column scales; the
+    # oracle runs on the dequantised stored matrix with the same sketch
+    c, A, _ = workload
+    m, n, k, p, q, t = c["m"], c["n"], c["k"], c["p"], c["q"], c["t"]
+    l = k + p
+    announce("fullsize: quantise and rsvd_solve_bf16 on GPU")
+    plan = rs.Plan(m, n, l, torch.bfloat16, seed=c["omega_seed"])
+    Aq, s = plan.quantize(A)
+    res = plan.solve(Aq, k, p, q, t, col_scale=s)
+    plan.close()
+    A64 = (Aq.double() * s.double()[None, :]).cpu().numpy()
+    del Aq
+    G = synth.gaussian_omega(c["omega_seed"], n, l).astype(np.float32).astype(np.float64)
+    announce("fullsize: oracle rsvd on the dequantised matrix (tens of seconds)")
+    ref = oracle.rsvd(A64, G, k, p, q, t)
+    S, U, V = host(res.S), host(res.U), host(res.V)
+    assert np.max(np.abs(S - ref.S) / ref.S) <= 1e-4
+    assert oracle.principal_angle_max(ref.V, V) <= 1e-3
+    assert oracle.principal_angle_max(ref.U, U) <= 1e-3
+    assert res.K == ref.K and res.status == ref.status
 
 
 @pytest.mark.timeout(900)

@@ -65,45 +65,40 @@ __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, 
 
 // ---------------------------------------------------------------------------
 // Cholesky factor R (upper, W = R^T R) and its inverse of a c x c SPD matrix
-// (c <= 96), one workgroup of 256 threads.  Thread (ti, tk) = (tid / 16,
-// tid % 16) keeps the elements (ti + 16u, tk + 16v), u, v < 6, in registers;
-// the 16 owners of a row are one 16-lane group of one wave.
-//  Factorisation, step j: the owners of row j take d = a_jj from the lane that
-//  holds it (cross-lane read), scale their part of row j by 1/sqrt(d) (row j of
-//  R) and publish it in LDS; after one barrier every thread subtracts
-//  r_ji r_jk from its elements (i, k), j < i <= k.
-//  Inverse (B = R^-1, from B = I), step k from the bottom: the owners of row k
-//  divide it by r_kk (row k of B is then final) and publish it, the owners of
-//  column k of R publish that column; after one barrier every thread
-//  subtracts r_ik b_kl from its elements (i, l), i < k <= l.
-// The LDS rows alternate between steps, so one barrier per step suffices.
-// The block index of the step (j / 16) is unrolled so that register
-// subscripts are compile-time constants.
+// (c <= 96), one workgroup of 256 threads, in one pass over the columns:
+// the symmetric elimination that turns W into R is applied at the same time
+// to an identity matrix B beside it (as in Gauss-Jordan elimination on
+// [W | I]), which turns B into L^-1 = R^-T (L = R^T); R^-1 is B transposed.
+// Thread (ti, tk) = (tid / 16, tid % 16) keeps the elements (ti + 16u,
+// tk + 16v), u, v < 6, of W and of B in registers; the 16 owners of a row are
+// one 16-lane group of one wave.  Step j: the owners of row j take
+// d = w_jj from the lane that holds it (cross-lane read), scale their part of
+// row j of W and of B by 1/sqrt(d) (row j of R, row j of L^-1) and publish
+// both in LDS; after one barrier every thread subtracts r_ji times row j from
+// its rows i > j, in W and in B.  The LDS rows alternate between steps, so
+// one barrier per step suffices.  The block index of the step (j / 16) is
+// unrolled so that register subscripts are compile-time constants.
 constexpr int kCiT = 256;
 constexpr int kCiU = 6;                       // 16 * 6 = 96 rows and columns
 
-// 1/sqrt(x) and 1/x: hardware estimate plus two Newton steps.
+// 1/sqrt(x): hardware estimate plus two Newton steps.
 __device__ __forceinline__ double rsq_newton(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
   y = fma(y, fma(-h * y, y, 0.5), y);
   return fma(y, fma(-h * y, y, 0.5), y);
 }
-__device__ __forceinline__ double rcp_newton(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
 
-// Updates are branch-free: an element outside the active triangle gets an
-// exact zero subtracted (the LDS rows start at zero and only ever hold finite
+// Updates are branch-free: an element outside the active rows gets an exact
+// zero subtracted (the LDS rows start at zero and only ever hold finite
 // values), so no lane diverges inside a step.
 // A pivot <= 0 (not positive definite to working precision) is recorded in
 // *bad and checked once after the factorisation; meanwhile it only produces
 // non-finite values.
 template <int UB>
-__device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], int c, int ti, int tk,
-                                           int lane, int wv, double (*rowbuf)[96], int* bad) {
+__device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], double (&b)[kCiU][kCiU], int c,
+                                           int ti, int tk, int lane, int wv, double (*rowR)[96],
+                                           double (*rowB)[96], int* bad) {
   for (int jj = 0; jj < 16; ++jj) {
     const int j = 16 * UB + jj;
     if (j >= c) return;
@@ -117,7 +112,10 @@ __device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], int c, int t
         const int k = tk + 16 * v;
         const bool on = k >= j && k < c;
         a[UB][v] = on ? a[UB][v] * rs : a[UB][v];
-        rowbuf[p][k] = on ? a[UB][v] : 0.0;
+        rowR[p][k] = on ? a[UB][v] : 0.0;
+        // row j of B is zero right of the diagonal
+        b[UB][v] = b[UB][v] * rs;
+        rowB[p][k] = k < c ? b[UB][v] : 0.0;
       }
     }
     __syncthreads();
@@ -125,48 +123,15 @@ __device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], int c, int t
     for (int u = UB; u < kCiU; ++u) {
       if (16 * u + 4 * wv + 3 <= j) continue;   // no row of this wave is below j
       const int i = ti + 16 * u;
-      const double rji = (i > j && i < c) ? rowbuf[p][i] : 0.0;
-      // the whole trailing square (its lower half stays the mirror image and
-      // is never read); columns left of j read a zero from rowbuf
-#pragma unroll
-      for (int v = 0; v < kCiU; ++v) a[u][v] = fma(-rji, rowbuf[p][tk + 16 * v], a[u][v]);
-    }
-  }
-}
-
-template <int UB>
-__device__ __forceinline__ void inv_block(const double (&a)[kCiU][kCiU], double (&b)[kCiU][kCiU],
-                                          int c, int ti, int tk, int lane, int wv,
-                                          double (*rowbuf)[96], double (*colbuf)[96]) {
-  for (int kk = 15; kk >= 0; --kk) {
-    const int k = 16 * UB + kk;
-    if (k >= c) continue;
-    const int p = k & 1;
-    if (ti == kk) {
-      const double inv = rcp_newton(__shfl(a[UB][UB], (lane & 48) + kk));
+      const double rji = (i > j && i < c) ? rowR[p][i] : 0.0;
+      // W: the whole trailing square (its lower half stays the mirror image
+      // and is never read); columns left of j read a zero from rowR.
+      // B: columns right of j read a zero from rowB.
 #pragma unroll
       for (int v = 0; v < kCiU; ++v) {
-        const int l = tk + 16 * v;
-        const bool on = l >= k && l < c;
-        b[UB][v] = on ? b[UB][v] * inv : b[UB][v];
-        rowbuf[p][l] = on ? b[UB][v] : 0.0;
+        a[u][v] = fma(-rji, rowR[p][tk + 16 * v], a[u][v]);
+        b[u][v] = fma(-rji, rowB[p][tk + 16 * v], b[u][v]);
       }
-    }
-    if (tk == kk) {
-#pragma unroll
-      for (int u = 0; u <= UB; ++u) {
-        const int i = ti + 16 * u;
-        colbuf[p][i] = i < k ? a[u][UB] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u <= UB; ++u) {
-      if (16 * u + 4 * wv >= k) continue;       // no row of this wave is above k
-      const int i = ti + 16 * u;
-      const double rik = colbuf[p][i];
-#pragma unroll
-      for (int v = UB; v < kCiU; ++v) b[u][v] = fma(-rik, rowbuf[p][tk + 16 * v], b[u][v]);
     }
   }
 }
@@ -177,8 +142,8 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
                                                    double* __restrict__ Rinv,
                                                    T* __restrict__ RinvT, int trans,
                                                    int32_t* __restrict__ status) {
-  __shared__ double rowbuf[2][96];
-  __shared__ double colbuf[2][96];
+  __shared__ double rowR[2][96];
+  __shared__ double rowB[2][96];
   __shared__ int bad;
   const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -189,20 +154,20 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     for (int v = 0; v < kCiU; ++v) {
       const int i = ti + 16 * u, k = tk + 16 * v;
       a[u][v] = (i < c && k < c) ? 0.5 * (W[i * c + k] + W[k * c + i]) : 0.0;
-      b[u][v] = (i == k) ? 1.0 : 0.0;
+      b[u][v] = (i == k && i < c) ? 1.0 : 0.0;
     }
   if (tid == 0) bad = 0;
   for (int e = tid; e < 2 * 96; e += kCiT) {
-    rowbuf[e / 96][e % 96] = 0.0;
-    colbuf[e / 96][e % 96] = 0.0;
+    rowR[e / 96][e % 96] = 0.0;
+    rowB[e / 96][e % 96] = 0.0;
   }
   __syncthreads();
-  chol_block<0>(a, c, ti, tk, lane, wv, rowbuf, &bad);
-  chol_block<1>(a, c, ti, tk, lane, wv, rowbuf, &bad);
-  chol_block<2>(a, c, ti, tk, lane, wv, rowbuf, &bad);
-  chol_block<3>(a, c, ti, tk, lane, wv, rowbuf, &bad);
-  chol_block<4>(a, c, ti, tk, lane, wv, rowbuf, &bad);
-  chol_block<5>(a, c, ti, tk, lane, wv, rowbuf, &bad);
+  chol_block<0>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
+  chol_block<1>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
+  chol_block<2>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
+  chol_block<3>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
+  chol_block<4>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
+  chol_block<5>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
   __syncthreads();
   if (bad) {
     // R = 0 (no factor), Rinv = I keeps the later products finite
@@ -216,22 +181,17 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
   }
-  inv_block<5>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
-  inv_block<4>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
-  inv_block<3>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
-  inv_block<2>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
-  inv_block<1>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
-  inv_block<0>(a, b, c, ti, tk, lane, wv, rowbuf, colbuf);
+  // b[u][v] = (L^-1)_ik = (R^-1)_ki, i = ti + 16u, k = tk + 16v (lower: k <= i)
 #pragma unroll
   for (int u = 0; u < kCiU; ++u)
 #pragma unroll
     for (int v = 0; v < kCiU; ++v) {
       const int i = ti + 16 * u, k = tk + 16 * v;
       if (i < c && k < c) {
-        const bool up = k >= i;
-        R[i * c + k] = up ? a[u][v] : 0.0;
-        Rinv[i * c + k] = up ? b[u][v] : 0.0;
-        if (RinvT) RinvT[trans ? k * c + i : i * c + k] = (T)(up ? b[u][v] : 0.0);
+        R[i * c + k] = k >= i ? a[u][v] : 0.0;
+        const double x = k <= i ? b[u][v] : 0.0;
+        Rinv[k * c + i] = x;
+        if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
       }
     }
 }

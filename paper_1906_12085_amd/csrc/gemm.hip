@@ -638,10 +638,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
 // staged in LDS once per block and A goes straight from memory into the
 // matrix-core operand registers (lane (lr, g) of a 16-row tile loads 16 bytes
 // of row lr at k = 16 s + 4 g, the k order that step t of slab s contracts on
-// both operands), so a block holds only the small factor in LDS and two
-// blocks share a CU.  Block = 256 rows, 4 waves of 64 rows x NT column tiles.
-// Same requirements as the tall kernel (n % 4 == 0, 16-byte rows).
-constexpr int kNM = 256;
+// both operands).  Persistent blocks walk tiles of kNM rows (4 waves of 32
+// rows x NT column tiles); a wave's loads for its next tile are in flight
+// while it multiplies the current one.  Same requirements as the tall kernel
+// (n % 4 == 0, 16-byte rows).
+constexpr int kNM = 128;
 
 template <int NT, int NS>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
@@ -651,20 +652,26 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
   __shared__ __attribute__((aligned(16))) float Bs[BC * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kNM;
-  const int64_t rows = m - row0 < kNM ? m - row0 : kNM;
-  // the range ends at the last element of the block's last row: rows past it
-  // read zeros
-  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
-  f32x4 af[NS][4];
+  const int64_t ntile = (m + kNM - 1) / kNM;
+  int vo[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int vo = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 4 * g) * 4);
+  for (int i = 0; i < 2; ++i) vo[i] = (int)(((int64_t)(wave * 32 + 16 * i + lr) * lda + 4 * g) * 4);
+  // tile tl: buffer range ends at the last element of its last row, so rows
+  // past it read zeros
+  auto load = [&](int64_t tl, f32x4 (&dst)[NS][2]) {
+    const int64_t r0 = tl * kNM;
+    const int64_t rows = m - r0 < kNM ? m - r0 : kNM;
+    const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(A + r0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl)
-      af[sl][i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, vo, 64 * sl, 0));
-  }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        dst[sl][i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, vo[i], 64 * sl, 0));
+  };
+  f32x4 nxt[NS][2];
+  int64_t tl = blockIdx.x;
+  if (tl < ntile) load(tl, nxt);
   // Xt into LDS, zero beyond c rows and n columns, while A is in flight
   for (int e = tid; e < BC * (KP / 4); e += 256) {
     const int r = e / (KP / 4), q = e - r * (KP / 4);
@@ -673,40 +680,51 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
     *reinterpret_cast<f32x4*>(&Bs[r * LD + 4 * q]) = v;
   }
   __syncthreads();
-  f32x4 acc[4][NT];
+  for (; tl < ntile; tl += gridDim.x) {
+    f32x4 af[NS][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < 2; ++i) af[sl][i] = nxt[sl][i];
+    const int64_t tn = tl + gridDim.x;
+    load(tn < ntile ? tn : tl, nxt);          // the last prefetch is a harmless repeat
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 acc[2][NT];
 #pragma unroll
-  for (int sl = 0; sl < NS; ++sl) {
-    if (sl == NS - 1 && 16 * sl + 4 * g >= n) {
-      // the last slab's k beyond n holds the next row's values
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[sl][i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    f32x4 bf[NT];
+      for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < NT; ++j)
-      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[(16 * j + lr) * LD + 16 * sl + 4 * g]);
+    for (int sl = 0; sl < NS; ++sl) {
+      if (sl == NS - 1 && 16 * sl + 4 * g >= n) {
+        // the last slab's k beyond n holds the next row's values
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[sl][i][t], bf[j][t], acc[i][j]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int col = 16 * j + lr;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + wave * 64 + 16 * i + Mfma<float>::row(lane, e);
-        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+        for (int i = 0; i < 2; ++i) af[sl][i] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
+      f32x4 bf[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        bf[j] = *reinterpret_cast<const f32x4*>(&Bs[(16 * j + lr) * LD + 16 * sl + 4 * g]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[sl][i][t], bf[j][t], acc[i][j]);
     }
+    const int64_t row0 = tl * kNM + wave * 32;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int col = 16 * j + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = row0 + 16 * i + Mfma<float>::row(lane, e);
+          if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+        }
+      }
+  }
 }
 
 // Z partials (n x c per row split, FP64) of A^T Q: block = one row split of
@@ -1124,7 +1142,9 @@ constexpr int kNarrowSlabs = 6;
 template <int NT>
 hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                      int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
-  const dim3 grid((unsigned)((m + kNM - 1) / kNM)), block(256);
+  // persistent: up to two blocks per CU of the 256
+  const int64_t ntile = (m + kNM - 1) / kNM;
+  const dim3 grid((unsigned)(ntile < 512 ? ntile : 512)), block(256);
 #define RSVD_NT_NARROW(NS)                                                                     \
   case NS:                                                                                     \
     hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, \

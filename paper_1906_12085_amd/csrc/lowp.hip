@@ -8,6 +8,8 @@
 // product; A's own rounding is the stored representation (the reference
 // computes on the dequantised stored A).  Also the quantiser
 // (power-of-two column scales, so the scaling itself is exact).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace rsvd {
@@ -139,27 +141,30 @@ __global__ void k_scale_rows(double* __restrict__ Z, int64_t n, int c,
 }
 
 // ---------------------------------------------------------------------------
-// Y (m x c, FP32) = Aq (m x n, bf16) (Xhi + Xlo)^T, X* c x n: block = 256
-// rows (4 waves of 64 rows x NT column tiles of 16); A goes straight from
+// Y (m x c, FP32) = Aq (m x n, bf16) (Xhi + Xlo)^T, X* c x n: block = 64
+// rows per wave x NT column tiles of 16, 8 waves (4 for NT > 5, whose
+// registers allow one wave per SIMD); A goes straight from
 // memory into the matrix-core operand registers (lane (lr, g) of a 16-row
-// tile loads the 16 bytes at row lr, k = 32 st + 8 g of the chunk), one
-// chunk ahead; the kBK-wide chunks of Xhi and Xlo are staged in LDS (two
+// tile loads the 16 bytes at row lr, k = 32 st + 8 g of the chunk), two
+// 32-deep steps ahead; the kBK-wide chunks of Xhi and Xlo are staged in LDS (two
 // buffers) and read back as 16-byte operands.  Optionally the FP64 sum of the
 // squared dequantised entries (Eq. sumeigen) per block.  Requires n % 8 == 0
 // and 16-byte rows of A, Xhi, Xlo.
-constexpr int kBM = 256, kBK = 64, kBLD = kBK + 8;
+constexpr int kBK = 64, kBLD = kBK + 8;
+template <int NT> constexpr int nt_bf16_threads() { return NT <= 5 ? 512 : 256; }
 
 template <int NT>
-__global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
+__global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
     const __bf16* __restrict__ A, int64_t m, int64_t n, int64_t lda,
     const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo, int64_t ldx, int c,
     const float* __restrict__ scale, float* __restrict__ Y, int64_t ldy,
     double* __restrict__ fro2_part) {
   constexpr int BC = 16 * NT;
-  constexpr int XP = (2 * BC * (kBK / 8) + 255) / 256;    // 16-byte X pieces per thread
+  constexpr int kBT = nt_bf16_threads<NT>(), kBM = kBT;     // threads, rows per block
+  constexpr int XP = (2 * BC * (kBK / 8) + kBT - 1) / kBT;  // 16-byte X pieces per thread
   __shared__ __attribute__((aligned(16))) __bf16 Xs[2][2][BC * kBLD];
   __shared__ double s2l[2][kBK];
-  __shared__ double red[4];
+  __shared__ double red[kBT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kBM;
@@ -181,24 +186,25 @@ __global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
   bool xon[XP];
 #pragma unroll
   for (int u = 0; u < XP; ++u) {
-    const int p = tid + 256 * u;
+    const int p = tid + kBT * u;
     const int h = p / (BC * (kBK / 8)), rem = p - h * (BC * (kBK / 8));
     const int xr = rem / (kBK / 8), q = rem - xr * (kBK / 8);
     xon[u] = p < 2 * BC * (kBK / 8);
     vox[u] = (int)(((int64_t)xr * ldx + 8 * q) * 2);
   }
-  // A fragments of one 32-deep step, loaded one step ahead; X pieces of the
-  // next chunk loaded at its first step and stored to LDS after its second
-  u32x4 ra[4], rx[XP];
-  auto load_a = [&](int t) {
+  // A fragments of a 32-deep step, two register sets loaded two steps ahead
+  // (set t & 1 holds step t); X pieces of the next chunk loaded at its first
+  // step and stored to LDS after its second
+  u32x4 ra[2][4], rx[XP];
+  auto load_a = [&](int t, u32x4 (&dst)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      ra[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], t * 64, 0));
+      dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], t * 64, 0));
   };
   auto load_x = [&](int ch) {
 #pragma unroll
     for (int u = 0; u < XP; ++u) {
-      const int p = tid + 256 * u;
+      const int p = tid + kBT * u;
       const bool hi = p < BC * (kBK / 8);
       rx[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
                                             hi ? hr : lrs, vox[u], ch * kBK * 2, 0));
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
 #pragma unroll
     for (int u = 0; u < XP; ++u) {
       if (!xon[u]) continue;
-      const int p = tid + 256 * u;
+      const int p = tid + kBT * u;
       const int h = p / (BC * (kBK / 8)), rem = p - h * (BC * (kBK / 8));
       const int xr = rem / (kBK / 8), q = rem - xr * (kBK / 8);
       const u32x4 v = 8 * q < kend ? rx[u] : u32x4{0u, 0u, 0u, 0u};
@@ -231,17 +237,21 @@ __global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
   double ss = 0.0;
   const int nst = (int)((n + 31) / 32);        // 32-deep steps
   load_x(0);
-  load_a(0);
+  load_a(0, ra[0]);
+  load_a(1 < nst ? 1 : 0, ra[1]);
   store_x(0, 0);
   __syncthreads();
-  for (int t = 0; t < nst; ++t) {
-    const int ch = t >> 1, st = t & 1, buf = ch & 1;
+  // step t with register set ST = t & 1 (a compile-time index)
+  auto step = [&](int t, auto stc) {
+    constexpr int st = decltype(stc)::value;
+    const int ch = t >> 1, buf = ch & 1;
     u32x4 a[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = ra[i];
+    for (int i = 0; i < 4; ++i) a[i] = ra[st][i];
     const bool more_x = st == 0 && ch + 1 < nch;
     if (more_x) load_x(ch + 1);
-    load_a(t + 1 < nst ? t + 1 : t);          // the last prefetch is a harmless repeat
+    // refill this set with step t + 2 (the last prefetches are harmless repeats)
+    load_a(t + 2 < nst ? t + 2 : t, ra[st]);
     __builtin_amdgcn_sched_barrier(0);
     // a step that runs past n holds the next row's values there
     if (32 * t + 8 * g >= n) {
@@ -279,6 +289,10 @@ __global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
       if (ch + 1 < nch) store_x(buf ^ 1, ch + 1);
       __syncthreads();
     }
+  };
+  for (int t = 0; t < nst; t += 2) {
+    step(t, std::integral_constant<int, 0>());
+    if (t + 1 < nst) step(t + 1, std::integral_constant<int, 1>());
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -295,7 +309,11 @@ __global__ __launch_bounds__(256, NT <= 6 ? 2 : 1) void k_gemm_nt_bf16(
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) fro2_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBT / 64; ++w) t += red[w];
+      fro2_part[blockIdx.x] = t;
+    }
   }
 }
 
@@ -345,28 +363,29 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   const int qc = 16 * wave + 8 * h < cpad - 8 ? 16 * wave + 8 * h : cpad - 8;
   const int voq = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
   const bool qwave = wave < NT;
-  u32x4 ra[4];
-  f32x4 rq0, rq1;
-  auto load = [&](int ch) {
+  // two register sets, chunk ch in set ch & 1, loaded two chunks ahead
+  u32x4 ra[2][4];
+  f32x4 rq[2][2];
+  auto load = [&](int ch, u32x4 (&da)[4], f32x4 (&dq)[2]) {
     const int soa = ch * kTR * (int)lda * 2;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      ra[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], soa, 0));
+      da[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], soa, 0));
     if (qwave) {
       const int soq = ch * kTR * (int)ldq * 4;
-      rq0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, soq, 0));
-      rq1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq + 16, soq, 0));
+      dq[0] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, soq, 0));
+      dq[1] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq + 16, soq, 0));
     }
   };
-  auto store_q = [&](int buf) {
+  auto store_q = [&](int buf, const f32x4 (&q)[2]) {
     if (!qwave) return;
     bf16x8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       __bf16 a, b;
-      split_hilo(rq0[e], &a, &b);
+      split_hilo(q[0][e], &a, &b);
       hi[e] = a; lo[e] = b;
-      split_hilo(rq1[e], &a, &b);
+      split_hilo(q[1][e], &a, &b);
       hi[4 + e] = a; lo[4 + e] = b;
     }
     Bq[buf][wave][0][lane] = octet_transpose(as_u32x4(hi), o);
@@ -377,29 +396,38 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  load(0);
-  store_q(0);
+  load(0, ra[0], rq[0]);
+  load(1 < nchunk ? 1 : 0, ra[1], rq[1]);
+  store_q(0, rq[0]);
   __syncthreads();
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
+  // chunk ch with register set SET = ch & 1 (a compile-time index); its Q
+  // fragments are in LDS buffer ch & 1, the next chunk's go to the other
+  auto chunk = [&](int ch, auto setc) {
+    constexpr int set = decltype(setc)::value;
+    constexpr int nxt = set ^ 1;
     u32x4 a[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = octet_transpose(ra[i], o);
-    const bool more = ch + 1 < nchunk;
-    load(more ? ch + 1 : ch);
+    for (int i = 0; i < 4; ++i) a[i] = octet_transpose(ra[set][i], o);
+    // refill this set with chunk ch + 2 (the last prefetches are harmless repeats)
+    const int ch2 = ch + 2 < nchunk ? ch + 2 : ch;
+    load(ch2, ra[set], rq[set]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const bf16x8 bh = as_bf16x8(Bq[buf][j][0][lane]);
-      const bf16x8 bl = as_bf16x8(Bq[buf][j][1][lane]);
+      const bf16x8 bh = as_bf16x8(Bq[set][j][0][lane]);
+      const bf16x8 bl = as_bf16x8(Bq[set][j][1][lane]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh, acc[i][j]);
         acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl, acc[i][j]);
       }
     }
-    if (more) store_q(buf ^ 1);
+    if (ch + 1 < nchunk) store_q(nxt, rq[nxt]);
     __syncthreads();
+  };
+  for (int ch = 0; ch < nchunk; ch += 2) {
+    chunk(ch, std::integral_constant<int, 0>());
+    if (ch + 1 < nchunk) chunk(ch + 1, std::integral_constant<int, 1>());
   }
   // acc[i][j][e]: A column col0 + 16 i + 4 g + e, Q column 16 j + (lane % 16)
   double* Pb = P + (int64_t)blockIdx.x * n * c;
@@ -449,7 +477,7 @@ hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hi
 
 bool bf16_pass_applies(const void* A, int64_t n, int64_t lda, int c) {
   return c >= 1 && c <= 128 && n % 8 == 0 && lda % 8 == 0 &&
-         (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (int64_t)kBM * lda * 2 < (1LL << 31);
+         (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (int64_t)512 * lda * 2 < (1LL << 31);
 }
 
 hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda,
@@ -458,15 +486,19 @@ hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t ld
                                int* nparts, hipStream_t s) {
   if (!bf16_pass_applies(A, n, lda, c) || ldx % 8 != 0 || (int64_t)c * ldx * 2 >= (1LL << 31))
     return hipErrorInvalidValue;
-  const int64_t nblk = (m + kBM - 1) / kBM;
-  if (nparts) *nparts = (int)nblk;
-  if (m <= 0) return hipSuccess;
-  const dim3 grid((unsigned)nblk), block(256);
+  if (m <= 0) {
+    if (nparts) *nparts = 0;
+    return hipSuccess;
+  }
 #define RSVD_NT_BF16(NT)                                                                        \
-  case NT:                                                                                      \
-    hipLaunchKernelGGL(k_gemm_nt_bf16<NT>, grid, block, 0, s, A, m, n, lda, Xhi, Xlo, ldx, c,   \
-                       scale, Y, ldy, fro2_part);                                               \
-    break;
+  case NT: {                                                                                    \
+    constexpr int bt = nt_bf16_threads<NT>();                                                   \
+    const int64_t nblk = (m + bt - 1) / bt;                                                     \
+    if (nparts) *nparts = (int)nblk;                                                            \
+    hipLaunchKernelGGL(k_gemm_nt_bf16<NT>, dim3((unsigned)nblk), dim3(bt), 0, s, A, m, n, lda,  \
+                       Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part);                             \
+    break;                                                                                      \
+  }
   switch ((c + 15) / 16) {
     RSVD_NT_BF16(1) RSVD_NT_BF16(2) RSVD_NT_BF16(3) RSVD_NT_BF16(4)
     RSVD_NT_BF16(5) RSVD_NT_BF16(6) RSVD_NT_BF16(7) RSVD_NT_BF16(8)

@@ -87,24 +87,46 @@ KERNEL_INFO = {
 # plain 1 GiB device copy (FETCH_SIZE 0.5 x the bytes read, WRITE_SIZE 1.0 x
 # the bytes written).  Each figure holds only for the kernel source it was
 # taken on (first 16 hex digits of the file's SHA-256); otherwise it is null.
+# Measured HBM bytes per launch at the 1e6 x 512, l = 80 workload (two
+# rocprofv3 counter passes, FETCH_SIZE and WRITE_SIZE, each scaled by what the
+# counter reads for a plain copy of known size), tied to the source text of
+# the kernel that was measured: a changed kernel reports null until measured
+# again.
 TRAFFIC = {
-    "eigensolver": (3.2997e9, "paper_1906_12085_amd/csrc/eig.hip", "a08a574edd1e00c9"),
-    "pass_nn": (2.4139e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
-    "pass_tn": (2.4520e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
-    "syrk": (2.4482e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
-    "nn_wide": (4.6165e9, "paper_1906_12085_amd/csrc/gemm.hip", "2a96698264f60601"),
+    "eigensolver": (3.2953e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
+    "pass_nn": (2.4141e+09, "gemm.hip", "k_gemm_nt_tall", "8139e2dc9f221a15"),
+    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "03561cb8faeda271"),
+    "syrk": (2.4484e+09, "gemm.hip", "k_syrk_f32", "0b6665341b4d3f9f"),
+    "nn_wide": (4.6222e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "49c8ad4e5ec10a94"),
+    "pass_nn_bf16": (1.5152e+09, "lowp.hip", "k_gemm_nt_bf16", "2f86dbf290f89925"),
+    "pass_tn_bf16": (1.4357e+09, "lowp.hip", "k_gemm_tn_bf16", "7aab2e1381d2f69f"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 
 
-def traffic_bytes(kind, m, n, l):
+def kernel_source_digest(path, names):
+    """sha256 (16 hex digits) of a kernel's definition (and of the device
+    functions that hold its body; names separated by spaces): from the line
+    that declares `void name(` to the first closing brace at column 0."""
     import hashlib
+    with open(os.path.join(ROOT, "paper_1906_12085_amd", "csrc", path)) as f:
+        lines = f.read().split("\n")
+    parts = []
+    for name in names.split():
+        start = next((i for i, ln in enumerate(lines) if f"void {name}(" in ln), None)
+        if start is None:
+            return None
+        end = next((i for i in range(start, len(lines)) if lines[i] == "}"), len(lines) - 1)
+        parts.append("\n".join(lines[start:end + 1]))
+    return hashlib.sha256("\n\n".join(parts).encode()).hexdigest()[:16]
+
+
+def traffic_bytes(kind, m, n, l):
     if kind not in TRAFFIC or (m, n, l) != TRAFFIC_SHAPE:
         return None
-    nbytes, path, digest = TRAFFIC[kind]
-    with open(os.path.join(ROOT, path), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != digest:
-            return None
+    nbytes, path, name, digest = TRAFFIC[kind]
+    if nbytes is None or kernel_source_digest(path, name) != digest:
+        return None
     return nbytes
 
 
@@ -162,6 +184,7 @@ def bf16_rooflines(ktimes, m, n, l, steps):
         ach = nbytes / sec / 1e9
         rows[kind] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1),
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                      "traffic": traffic_bytes(kind + "_bf16", m, n, l),
                       "tflops": round(flops / sec / 1e12, 2), "launch_ms": round(ms, 4),
                       "launches_per_solve": round(launches / steps, 2),
                       "work_per_launch": {"flops": flops, "bytes": nbytes}}

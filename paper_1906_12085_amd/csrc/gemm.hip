@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_wide(
 // ---------------------------------------------------------------------------
 // G = A^T A for fp32 A (the truncated SVD's Gram matrix, Sec. 3.1.3, Eq.
 // AB), upper 128 x 128 tile pairs only (G is symmetric).  Block = one tile
-// pair (I <= J) over one split of the rows; chunks of kSyK = 64 rows of the
+// pair (I <= J) over one split of the rows; chunks of kSyK = 32 rows of the
 // two 128-column slices are staged row-major in LDS (row stride padded to
 // 288 floats, so the two half-waves of a read touch disjoint banks), two
 // buffers, next chunk's buffer loads issued ahead of the multiply and its LDS
@@ -365,9 +365,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt_wide(
 // split order by k_syrk_reduce (deterministic).  Columns past n are never
 // masked: they only feed output rows/columns past n, which are not written
 // (and the buffer descriptor ends at the split's last row).
-constexpr int kSyT = 128, kSyK = 64, kSyLD = 2 * kSyT + 32;
+constexpr int kSyT = 128, kSyK = 32, kSyLD = 2 * kSyT + 32;
+constexpr int kSyU = kSyK * 64 / 256;          // 16-byte loads per thread per chunk
 
-__global__ __launch_bounds__(256) void k_syrk_f32(const float* __restrict__ A, int64_t m,
+__global__ __launch_bounds__(256, 2) void k_syrk_f32(const float* __restrict__ A, int64_t m,
                                                   int64_t n, int64_t lda, int ntile, int npair,
                                                   int64_t rps, int64_t nblk, int64_t per_xcd,
                                                   double* __restrict__ P) {
@@ -388,24 +389,24 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float* __restrict__ A, i
 
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
-  // chunk = 64 rows x 64 float4 (32 from slice I, 32 from slice J)
-  int voff[16];
+  // chunk = kSyK rows x 64 float4 (32 from slice I, 32 from slice J)
+  int voff[kSyU];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
+  for (int u = 0; u < kSyU; ++u) {
     const int idx = tid + u * 256, r = idx >> 6, q = idx & 63;
     const int col = q < 32 ? I * kSyT + 4 * q : J * kSyT + 4 * (q - 32);
     voff[u] = (int)((r * lda + col) * 4);
   }
-  f32x4 rg[16];
+  f32x4 rg[kSyU];
   auto load = [&](int ch) {
     const int so = (int)((int64_t)ch * kSyK * lda * 4);
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < kSyU; ++u)
       rg[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[u], so, 0));
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kSyU; ++u) {
       const int idx = tid + u * 256, r = idx >> 6, q = idx & 63;
       *reinterpret_cast<f32x4*>(&As[buf][r * kSyLD + 4 * q]) = rg[u];
     }
@@ -440,13 +441,14 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float* __restrict__ A, i
     const int buf = ch & 1;
     load(ch + 1 < nch ? ch + 1 : ch);          // the last prefetch is a harmless repeat
     __builtin_amdgcn_sched_barrier(0);
-    steps(buf, 0, 24);
+    static_assert(kSyK == 32, "16 steps per chunk, the last 4 interleaved with the LDS writes");
+    steps(buf, 0, 12);
     __builtin_amdgcn_sched_barrier(0);
-    steps(buf, 24, 32);
+    steps(buf, 12, 16);
     store(buf ^ 1);
     // last quarter: 4 LDS reads and 4 matrix-core steps per 2 LDS writes
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
+    for (int w = 0; w < 4; ++w) {
       __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
       __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
       __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);

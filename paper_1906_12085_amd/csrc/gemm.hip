@@ -497,16 +497,17 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 // (exact tiles for any c that is a multiple of 16).
 //
 // Y = A Xt^T (Xt is c x n): block = 256 rows of A x all c columns, 4 waves of
-// 64 rows (4 x NT tiles); chunks of kTK = 32 along k of both operands staged
-// row-major in LDS (two buffers).  The next chunk's buffer loads are issued
+// 64 rows (4 x NT tiles); chunks of kTK = 16 along k of both operands staged
+// row-major in LDS (two buffers, small enough for two blocks per CU).  The next chunk's buffer loads are issued
 // before the multiply, its LDS writes interleaved into the last slab, the
 // FP64 sum of squares of A (Eq. sumeigen) taken from the loaded chunk.
 // Requires n % 4 == 0 and 16-byte rows (the descriptor ends at the last
 // valid row; a last chunk that ends past n is zeroed there on its way to LDS).
-constexpr int kTM = 256, kTK = 32, kTLD = kTK + 4;
+constexpr int kTM = 256, kTK = 16, kTLD = kTK + 4;
+constexpr int kTQ = kTK / 4, kTUA = kTM * kTQ / 256;   // k-quads per row, A loads per thread
 
 template <int NT>
-__global__ __launch_bounds__(256) void k_gemm_nt_tall(
+__global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
     int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part) {
   constexpr int BC = 16 * NT;
@@ -525,22 +526,22 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
       const_cast<float*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(Xt), 0, (int)(((int64_t)(c - 1) * ldxt + n) * 4), kBufDword3);
-  int voa[8], vox[XU];
+  int voa[kTUA], vox[XU];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < kTUA; ++u) {
     const int idx = tid + u * 256;
-    voa[u] = (int)(((idx >> 3) * lda + 4 * (idx & 7)) * 4);
+    voa[u] = (int)(((idx / kTQ) * lda + 4 * (idx % kTQ)) * 4);
   }
 #pragma unroll
   for (int u = 0; u < XU; ++u) {
     const int idx = tid + u * 256;
-    vox[u] = (int)(((idx >> 3) * ldxt + 4 * (idx & 7)) * 4);
+    vox[u] = (int)(((idx / kTQ) * ldxt + 4 * (idx % kTQ)) * 4);
   }
-  f32x4 ra[8], rx[XU];
+  f32x4 ra[kTUA], rx[XU];
   auto load = [&](int ch) {
     const int so = ch * kTK * 4;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kTUA; ++u)
       ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[u], so, 0));
 #pragma unroll
     for (int u = 0; u < XU; ++u)
@@ -554,14 +555,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
     const int kend = (int)(n - (int64_t)ch * kTK);
     const bool tail = kend < kTK;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kTUA; ++u) {
       const int idx = tid + u * 256;
       f32x4 v = ra[u];
       if (tail) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = 4 * (idx & 7) + i < kend ? v[i] : 0.f;
+        for (int i = 0; i < 4; ++i) v[i] = 4 * (idx % kTQ) + i < kend ? v[i] : 0.f;
       }
-      *reinterpret_cast<f32x4*>(&As[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = v;
+      *reinterpret_cast<f32x4*>(&As[buf][(idx / kTQ) * kTLD + 4 * (idx % kTQ)]) = v;
       if (do_ss) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ss = fma((double)v[i], (double)v[i], ss);
@@ -574,9 +575,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
         f32x4 v = rx[u];
         if (tail) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = 4 * (idx & 7) + i < kend ? v[i] : 0.f;
+          for (int i = 0; i < 4; ++i) v[i] = 4 * (idx % kTQ) + i < kend ? v[i] : 0.f;
         }
-        *reinterpret_cast<f32x4*>(&Bs[buf][(idx >> 3) * kTLD + 4 * (idx & 7)]) = v;
+        *reinterpret_cast<f32x4*>(&Bs[buf][(idx / kTQ) * kTLD + 4 * (idx % kTQ)]) = v;
       }
     }
   };
@@ -605,15 +606,13 @@ __global__ __launch_bounds__(256) void k_gemm_nt_tall(
   load(0);
   store(0, 0);
   __syncthreads();
-  static_assert(kTK == 32, "two slabs per chunk");
+  static_assert(kTK == 16, "one slab per chunk");
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nch;
     load(more ? ch + 1 : ch);                  // the last prefetch is a harmless repeat
     __builtin_amdgcn_sched_barrier(0);
     slab(buf, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    slab(buf, 1);
     if (more) store(buf ^ 1, ch + 1);
     __syncthreads();
   }

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
     ap.add_argument("--no-bf16", action="store_true",
-                    help="skip the leg on bfloat16 storage of the same A")
+                    help="skip the legs on bfloat16 and FP8 storage of the same A")
     return ap.parse_args()
 
 
@@ -100,6 +100,8 @@ TRAFFIC = {
     "nn_wide": (4.6222e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "49c8ad4e5ec10a94"),
     "pass_nn_bf16": (1.5152e+09, "lowp.hip", "k_gemm_nt_bf16", "2f86dbf290f89925"),
     "pass_tn_bf16": (1.4357e+09, "lowp.hip", "k_gemm_tn_bf16", "7aab2e1381d2f69f"),
+    "pass_nn_fp8": (None, "lowp.hip", "k_gemm_nt_bf16", None),
+    "pass_tn_fp8": (None, "lowp.hip", "k_gemm_tn_bf16", None),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 
@@ -170,41 +172,45 @@ def kernel_rooflines(ktimes, m, n, l, b, steps):
     return roof, rows
 
 
-def bf16_rooflines(ktimes, m, n, l, steps):
-    """The two bf16 passes of the bfloat16-storage leg: HBM-bound (2mnl flops
-    over 2mn + 4ml bytes, far below the bf16 matrix-core ridge)."""
+def lowp_rooflines(ktimes, m, n, l, steps, es, tag):
+    """The two passes of a low-precision storage leg (es bytes per element of
+    A): HBM-bound (2mnl flops over es mn + 4ml bytes, far below the bf16
+    matrix-core ridge)."""
     rows = {}
     names = {"pass_nn": "k_gemm_nt_bf16", "pass_tn": "k_gemm_tn_bf16"}
     for kind, name in names.items():
         ms, launches = ktimes.get(kind, (0.0, 0))
         if launches == 0 or ms <= 0:
             continue
-        flops, nbytes = 2.0 * m * n * l, 2.0 * m * n + 4.0 * m * l
+        flops, nbytes = 2.0 * m * n * l, es * m * n + 4.0 * m * l
         sec = ms / 1e3
         ach = nbytes / sec / 1e9
         rows[kind] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1),
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-                      "traffic": traffic_bytes(kind + "_bf16", m, n, l),
+                      "traffic": traffic_bytes(kind + tag, m, n, l),
                       "tflops": round(flops / sec / 1e12, 2), "launch_ms": round(ms, 4),
                       "launches_per_solve": round(launches / steps, 2),
                       "work_per_launch": {"flops": flops, "bytes": nbytes}}
     return rows
 
 
-def bf16_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream):
-    """Randomized PCA of the same A stored in bfloat16 with power-of-two
-    column scales (quantised outside the timed region), timed like the fp32
-    leg; accuracy against the FP64 path on the dequantised stored matrix."""
+def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt):
+    """Randomized PCA of the same A stored in bfloat16 or FP8 E4M3 with
+    power-of-two column scales (quantised outside the timed region), timed
+    like the fp32 leg; accuracy against the FP64 path on the dequantised
+    stored matrix."""
     l = k + p
     dev = A.device
-    plan = rs.Plan(m, n, l, torch.bfloat16, seed=seed, stream=stream)
+    es = 2 if fmt == torch.bfloat16 else 1
+    solve = rs.rsvd_solve_bf16 if es == 2 else rs.rsvd_solve_fp8
+    plan = rs.Plan(m, n, l, fmt, seed=seed, stream=stream)
     Aq, sc = plan.quantize(A)
     U = torch.empty(m, k, dtype=torch.float32, device=dev)
     S = torch.empty(k, dtype=torch.float64, device=dev)
     V = torch.empty(n, k, dtype=torch.float32, device=dev)
     K = torch.empty(1, dtype=torch.int32, device=dev)
     for _ in range(warmup):
-        rs.rsvd_solve_bf16(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
+        solve(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
     rs.rsvd_plan_kernel_times(plan.handle, True)
@@ -212,7 +218,7 @@ def bf16_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream):
     t0 = time.perf_counter()
     for i in range(steps):
         evs[i][0].record(stream)
-        rs.rsvd_solve_bf16(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
+        solve(plan.handle, Aq, sc, k, p, q, t, None, U, S, V, K)
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -229,14 +235,15 @@ def bf16_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream):
     del A64, Aq
     torch.cuda.empty_cache()
     med = pct(ms, 50)
-    nbytes = (2 * q + 2) * (2.0 * m * n + 4.0 * m * l)
-    return {"storage": "bf16 + fp32 power-of-two column scales", "p50_ms": round(med, 3),
+    nbytes = (2 * q + 2) * (es * m * n + 4.0 * m * l)
+    name = "bf16" if es == 2 else "fp8 e4m3"
+    return {"storage": f"{name} + fp32 power-of-two column scales", "p50_ms": round(med, 3),
             "p99_ms": round(pct(ms, 99), 3), "solves_per_s": round(1000.0 / med, 2),
             "wall_solves_per_s": round(steps / wall, 2),
             "gbs_passes": round(nbytes / (med / 1e3) / 1e9, 1), "K": int(K.item()),
             "K_equals_fp64_path": same_k, "status": rs.STATUS.get(status, status),
             "sigma_rel_err_vs_fp64_path_on_stored_matrix": sig_err,
-            "kernels": bf16_rooflines(ktimes, m, n, l, steps)}
+            "kernels": lowp_rooflines(ktimes, m, n, l, steps, es, "_bf16" if es == 2 else "_fp8")}
 
 
 def pct(xs, p):
@@ -360,9 +367,10 @@ def main():
                             "K": int(Kg.item())}
 
     if not args.no_bf16:
-        print(f"[bench] bf16 storage leg: {args.steps} solves", file=sys.stderr, flush=True)
-        legs["rsvd_bf16"] = bf16_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"],
-                                     args.steps, args.warmup, stream)
+        for key, fmt in (("rsvd_bf16", torch.bfloat16), ("rsvd_fp8", torch.float8_e4m3fn)):
+            print(f"[bench] {key} storage leg: {args.steps} solves", file=sys.stderr, flush=True)
+            legs[key] = lowp_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"], args.steps,
+                                 args.warmup, stream, fmt)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -51,11 +51,14 @@ typedef enum {
   RSVD_F32 = 1, /* A, U, V float; products on FP32 matrix cores with FP32
                    accumulation inside a row block; Gram matrices, Cholesky
                    factors, the small SVD and the eigensolver in FP64 */
-  RSVD_BF16 = 2 /* A stored as bfloat16 with optional FP32 column scales
-                   (the matrix is Aq diag(s)); U, V float.  The passes over A
-                   run on BF16 matrix cores with FP32 accumulation, their
-                   right factors split into hi + lo bfloat16 pairs; the rest
-                   as RSVD_F32.  Randomized PCA only (no A^T A route). */
+  RSVD_BF16 = 2, /* A stored as bfloat16 with optional FP32 column scales
+                    (the matrix is Aq diag(s)); U, V float.  The passes over A
+                    run on BF16 matrix cores with FP32 accumulation, their
+                    right factors split into hi + lo bfloat16 pairs; the rest
+                    as RSVD_F32.  Randomized PCA only (no A^T A route). */
+  RSVD_FP8 = 3   /* as RSVD_BF16 with A stored as OCP FP8 E4M3 bytes (bias 7,
+                    largest 448, S.1111.111 = NaN), widened exactly to
+                    bfloat16 in registers */
 } rsvd_dtype;
 
 typedef enum {
@@ -168,6 +171,24 @@ int32_t rsvd_solve_bf16(rsvd_plan_t plan, const void* A, const float* col_scale,
                         const double* omega, float* U, int64_t ldu, double* S, float* V,
                         int64_t ldv, int32_t* K);
 
+/* rsvd_solve_fp8: as rsvd_solve_bf16 for an RSVD_FP8 plan, Aq one OCP FP8
+ * E4M3 byte per element (m x n, lda in elements; n % 8 == 0, lda % 8 == 0,
+ * 8-byte aligned A). */
+int32_t rsvd_solve_fp8(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
+                       int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
+                       const double* omega, float* U, int64_t ldu, double* S, float* V,
+                       int64_t ldv, int32_t* K);
+
+/* rsvd_quantize_fp8: storage of an FP32 matrix A (m x n, lda) for
+ * rsvd_solve_fp8: col_scale[j] = the least power of two with
+ * max_i |a_ij| / col_scale[j] <= 448 (1 for a zero or non-finite column
+ * maximum) and Aq (m x n, ldq, one byte each) = A / col_scale in OCP FP8 E4M3,
+ * rounded to nearest with ties to an even mantissa (subnormals kept, NaN
+ * kept, magnitudes past 448 saturate).  Device pointers; runs on the plan's
+ * stream (uses the plan's workspace). */
+int32_t rsvd_quantize_fp8(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
+                          void* Aq, int64_t ldq, float* col_scale);
+
 /* rsvd_quantize_bf16: storage of an FP32 matrix A (m x n, lda) for
  * rsvd_solve_bf16: col_scale[j] = 2^e with 2^(e-1) <= max_i |a_ij| < 2^e (1
  * for a zero or non-finite column maximum) and Aq (m x n, ldq, bfloat16) =
@@ -209,9 +230,10 @@ int32_t rsvd_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, double* G,
  * H = A G and A (A^T H) of Sec. 3.1.2.  When Gram != NULL it also writes
  * Gram (c x c, FP64) = Y^T Y accumulated in FP64, and when fro2 != NULL the
  * FP64 sum of a_ij^2 (Eq. sumeigen).  c <= plan l_max unless the plan was
- * sized for the A^T A route (then c <= n_max).  On an RSVD_BF16 plan A is
- * bfloat16 (unit scales; n % 8 == 0, lda % 8 == 0), X and Y float, c <= l_max,
- * and the product is the bf16 pass with X split into hi + lo pairs. */
+ * sized for the A^T A route (then c <= n_max).  On an RSVD_BF16 (RSVD_FP8)
+ * plan A is bfloat16 (FP8 E4M3) with unit scales, n % 8 == 0, lda % 8 == 0, X
+ * and Y float, c <= l_max, and the product is the bf16 pass with X split into
+ * hi + lo pairs. */
 int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
                      const void* X, int64_t ldx, int32_t c, void* Y, int64_t ldy,
                      double* Gram, double* fro2);
@@ -219,9 +241,9 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
 /* rsvd_gemm_tn: Z (n x c, FP64, ld = c) = A^T (n x m) Q (m x c, ldq), the
  * product T = A^T Q of Sec. 3.1.2 (and A^T H of the power iterations); the
  * sum over the m rows is split into row blocks whose partial sums are added
- * in a fixed order (deterministic).  On an RSVD_BF16 plan A is bfloat16 (unit
- * scales; n % 8 == 0, lda % 8 == 0), Q float, c <= l_max (Q is split into
- * hi + lo bfloat16 pairs on the fly). */
+ * in a fixed order (deterministic).  On an RSVD_BF16 (RSVD_FP8) plan A is
+ * bfloat16 (FP8 E4M3) with unit scales, n % 8 == 0, lda % 8 == 0, Q float,
+ * c <= l_max (Q is split into hi + lo bfloat16 pairs on the fly). */
 int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
                      const void* Q, int64_t ldq, int32_t c, double* Z);
 

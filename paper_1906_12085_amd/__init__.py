@@ -22,7 +22,7 @@ from typing import NamedTuple, Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsvd.so")
 
-RSVD_F64, RSVD_F32, RSVD_BF16 = 0, 1, 2
+RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8 = 0, 1, 2, 3
 STATUS = {
     0: "RSVD_OK", 1: "RSVD_WARN_THRESHOLD", 2: "RSVD_WARN_ZERO_MATRIX",
     -1: "RSVD_ERR_ARG", -2: "RSVD_ERR_SHAPE", -3: "RSVD_ERR_NOMEM", -4: "RSVD_ERR_DEVICE",
@@ -36,7 +36,7 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
            "rsvd_gaussian_fill", "rsvd_gemm_nn", "rsvd_gemm_tn", "rsvd_cholqr2",
            "rsvd_small_svd", "rsvd_sym_eig", "rsvd_plan_kernel_times", "rsvd_solve_bf16",
-           "rsvd_quantize_bf16"]
+           "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8"]
 
 
 class RSVDError(RuntimeError):
@@ -79,6 +79,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_solve_bf16": (i32, [vp, vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                   vp, i64, vp, vp, i64, vp]),
         "rsvd_quantize_bf16": (i32, [vp, vp, i64, i64, i64, vp, i64, vp]),
+        "rsvd_solve_fp8": (i32, [vp, vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
+                                 vp, i64, vp, vp, i64, vp]),
+        "rsvd_quantize_fp8": (i32, [vp, vp, i64, i64, i64, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -179,6 +182,24 @@ def rsvd_solve_bf16(plan: int, A, col_scale, k: int, p: int, q: int, t: float, o
                   "rsvd_solve_bf16")
 
 
+def rsvd_solve_fp8(plan: int, A, col_scale, k: int, p: int, q: int, t: float, omega, U, S, V,
+                   K) -> int:
+    m, n = A.shape
+    if omega is not None:
+        assert omega.is_contiguous() and omega.element_size() == 8
+    return _check(load_library().rsvd_solve_fp8(plan, _ptr(A), _ptr(col_scale), m, n, _ld(A), k,
+                                                p, q, float(t), _ptr(omega), _ptr(U), _ld(U),
+                                                _ptr(S), _ptr(V), _ld(V), _ptr(K)),
+                  "rsvd_solve_fp8")
+
+
+def rsvd_quantize_fp8(plan: int, A, Aq, col_scale) -> int:
+    m, n = A.shape
+    return _check(load_library().rsvd_quantize_fp8(plan, _ptr(A), m, n, _ld(A), _ptr(Aq),
+                                                   _ld(Aq), _ptr(col_scale)),
+                  "rsvd_quantize_fp8")
+
+
 def rsvd_quantize_bf16(plan: int, A, Aq, col_scale) -> int:
     m, n = A.shape
     return _check(load_library().rsvd_quantize_bf16(plan, _ptr(A), m, n, _ld(A), _ptr(Aq),
@@ -254,10 +275,11 @@ class Plan:
                  seed: int = 0, stream=None):
         import torch
         self.torch = torch
-        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32, torch.bfloat16: RSVD_BF16}[dtype]
+        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32, torch.bfloat16: RSVD_BF16,
+                torch.float8_e4m3fn: RSVD_FP8}[dtype]
         self.storage = dtype
-        # outputs of a bfloat16 plan are float
-        self.dtype = torch.float32 if dtype == torch.bfloat16 else dtype
+        # outputs of a bfloat16 or fp8 plan are float
+        self.dtype = torch.float32 if code in (RSVD_BF16, RSVD_FP8) else dtype
         self.handle = rsvd_plan_create(m_max, n_max, l_max, code, want_gram, seed, stream)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -289,6 +311,8 @@ class Plan:
         S = self._out((k,), torch.float64); K = self._out((1,), torch.int32)
         if self.storage == torch.bfloat16:
             rsvd_solve_bf16(self.handle, A, col_scale, k, p, q, t, omega, U, S, V, K)
+        elif self.storage == torch.float8_e4m3fn:
+            rsvd_solve_fp8(self.handle, A, col_scale, k, p, q, t, omega, U, S, V, K)
         elif omega is None:
             rsvd_solve(self.handle, A, k, p, q, t, U, S, V, K)
         else:
@@ -299,12 +323,16 @@ class Plan:
         return Result(U, S, V, int(K.item()), st)
 
     def quantize(self, A):
-        """bfloat16 storage of an fp32 matrix: (Aq, col_scale) with power-of-two
-        column scales (rsvd_quantize_bf16)."""
+        """Storage of an fp32 matrix in the plan's format (bfloat16 or FP8 E4M3):
+        (Aq, col_scale) with power-of-two column scales (rsvd_quantize_bf16 /
+        rsvd_quantize_fp8)."""
         m, n = A.shape
-        Aq = self.torch.empty((m, n), dtype=self.torch.bfloat16, device=self.device)
+        Aq = self.torch.empty((m, n), dtype=self.storage, device=self.device)
         s = self.torch.empty((n,), dtype=self.torch.float32, device=self.device)
-        rsvd_quantize_bf16(self.handle, A, Aq, s)
+        if self.storage == self.torch.float8_e4m3fn:
+            rsvd_quantize_fp8(self.handle, A, Aq, s)
+        else:
+            rsvd_quantize_bf16(self.handle, A, Aq, s)
         return Aq, s
 
     def gram_eig(self, A, t: float, ucols: Optional[int] = None, sync: bool = True):

@@ -38,6 +38,37 @@ __device__ __forceinline__ void split_hilo(float x, __bf16* hi, __bf16* lo) {
   *lo = (__bf16)(x - (float)h);
 }
 
+// Operand fragment of 8 consecutive stored elements: 16 bytes of bfloat16, or
+// 8 bytes of OCP FP8 E4M3 widened to bfloat16 in registers (every E4M3 value,
+// subnormals included, is exact in bfloat16; the hardware packed convert
+// follows the OCP E4M3 definition, NaN for S.1111.111).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+template <int ES> struct Frag;
+template <> struct Frag<2> {
+  typedef u32x4 raw;
+  static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ u32x4 bf(raw v) { return v; }
+};
+template <> struct Frag<1> {
+  typedef u32x2 raw;
+  static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+    return __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ unsigned pair(f32x2 f) {
+    return __builtin_bit_cast(unsigned, bf16x2{(__bf16)f[0], (__bf16)f[1]});
+  }
+  static __device__ __forceinline__ u32x4 bf(raw v) {
+    return u32x4{pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[0], false)),
+                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[0], true)),
+                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[1], false)),
+                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[1], true))};
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Octet transpose: lanes o = 0..7 of an aligned group of 8 each hold 8 bf16
 // (row o of an 8 x 8 block, four dwords of two columns each); afterwards lane
@@ -119,6 +150,47 @@ __global__ void k_quantize_bf16(const float* __restrict__ A, int64_t m, int64_t 
   if (i == 0) scale[j] = s;
 }
 
+// FP8 E4M3 storage: s_j = the least power of two with max_i |A_ij| / s_j <=
+// 448 (the largest E4M3 value; 1 for a zero column), Aq = E4M3(A / s_j).
+__device__ __forceinline__ float pow2_scale_fp8(unsigned maxbits) {
+  const float mx = __uint_as_float(maxbits);
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  const float f = frexpf(mx / 448.f, &e);   // mx / 448 = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, f == 0.5f ? e - 1 : e);
+}
+
+// x to OCP FP8 E4M3 (bias 7, 3 mantissa bits, largest 448, no infinities,
+// S.1111.111 = NaN), rounded to nearest with ties to an even mantissa;
+// magnitudes past 448 saturate to 448.
+__device__ __forceinline__ unsigned char e4m3_rne(float x) {
+  const unsigned sg = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (!(a == a)) return (unsigned char)(sg | 0x7Fu);
+  if (a >= 448.f) return (unsigned char)(sg | 0x7Eu);
+  if (a < 0x1p-6f) {
+    // subnormal spacing 2^-9 (a rounded count of 8 is the smallest normal, code 8)
+    return (unsigned char)(sg | (unsigned)rintf(a * 512.f));
+  }
+  int e;
+  const float f = frexpf(a, &e);              // a = (2f) 2^(e-1), 2f in [1, 2)
+  int ex = e - 1;
+  int mq = (int)rintf((2.f * f - 1.f) * 8.f);  // exact product, rounded to even
+  if (mq == 8) { mq = 0; ++ex; }
+  return (unsigned char)(sg | (unsigned)((ex + 7) << 3) | (unsigned)mq);
+}
+
+__global__ void k_quantize_fp8(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                               const unsigned* __restrict__ cmax, unsigned char* __restrict__ Aq,
+                               int64_t ldq, float* __restrict__ scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx / n, j = idx - i * n;
+  const float s = pow2_scale_fp8(cmax[j]);
+  Aq[i * ldq + j] = e4m3_rne(A[i * lda + j] / s);
+  if (i == 0) scale[j] = s;
+}
+
 // Xhi, Xlo (c x n, row stride ldx) = split of (diag(s) X)^T, X (n x c) FP64
 // row-major with ld c: row j of the result is column j of diag(s) X.
 __global__ void k_cast_hilo_t(const double* __restrict__ X, int64_t n, int c,
@@ -153,9 +225,9 @@ __global__ void k_scale_rows(double* __restrict__ Z, int64_t n, int c,
 constexpr int kBK = 64, kBLD = kBK + 8;
 template <int NT> constexpr int nt_bf16_threads() { return NT <= 5 ? 512 : 256; }
 
-template <int NT>
+template <int NT, int ES>
 __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
-    const __bf16* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+    const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda,
     const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo, int64_t ldx, int c,
     const float* __restrict__ scale, float* __restrict__ Y, int64_t ldy,
     double* __restrict__ fro2_part) {
@@ -172,7 +244,8 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   const int nch = (int)((n + kBK - 1) / kBK);
   const bool do_ss = fro2_part != nullptr;
   const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<__bf16*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 2), 0x00020000);
+      const_cast<unsigned char*>(A + row0 * lda * ES), 0, (int)(((rows - 1) * lda + n) * ES),
+      0x00020000);
   const int xrange = (int)(((int64_t)(c - 1) * ldx + n) * 2);
   const __amdgpu_buffer_rsrc_t hr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xhi), 0, xrange, 0x00020000);
@@ -180,7 +253,7 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xlo), 0, xrange, 0x00020000);
   int voa[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) voa[i] = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 8 * g) * 2);
+  for (int i = 0; i < 4; ++i) voa[i] = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 8 * g) * ES);
   // X piece p of this thread: hi/lo h, row xr, 8-column group q of the chunk
   int vox[XP];
   bool xon[XP];
@@ -195,11 +268,12 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   // A fragments of a 32-deep step, two register sets loaded two steps ahead
   // (set t & 1 holds step t); X pieces of the next chunk loaded at its first
   // step and stored to LDS after its second
-  u32x4 ra[2][4], rx[XP];
-  auto load_a = [&](int t, u32x4 (&dst)[4]) {
+  typedef typename Frag<ES>::raw raw_t;
+  raw_t ra[2][4];
+  u32x4 rx[XP];
+  auto load_a = [&](int t, raw_t (&dst)[4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], t * 64, 0));
+    for (int i = 0; i < 4; ++i) dst[i] = Frag<ES>::load(ar, voa[i], t * 32 * ES);
   };
   auto load_x = [&](int ch) {
 #pragma unroll
@@ -247,7 +321,7 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
     const int ch = t >> 1, buf = ch & 1;
     u32x4 a[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = ra[st][i];
+    for (int i = 0; i < 4; ++i) a[i] = Frag<ES>::bf(ra[st][i]);
     const bool more_x = st == 0 && ch + 1 < nch;
     if (more_x) load_x(ch + 1);
     // refill this set with step t + 2 (the last prefetches are harmless repeats)
@@ -332,9 +406,9 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
 // round_up(c, 8) readable columns in every row of Q (ldq >= that).
 constexpr int kTA = 512, kTR = 32;
 
-template <int NT>
+template <int NT, int ES>
 __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
-    const __bf16* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
+    const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
     int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split) {
   __shared__ __attribute__((aligned(16))) u32x4 Bq[2][NT][2][64];   // [buf][j][hi/lo][lane]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -344,7 +418,8 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   const int64_t col0 = (int64_t)blockIdx.y * kTA + wave * 64;
   const int nchunk = (int)((re - rs + kTR - 1) / kTR);
   const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<__bf16*>(A + rs * lda), 0, (int)(((re - rs - 1) * lda + n) * 2), 0x00020000);
+      const_cast<unsigned char*>(A + rs * lda * ES), 0, (int)(((re - rs - 1) * lda + n) * ES),
+      0x00020000);
   const int cpad = (c + 7) & ~7;              // Q rows hold cpad readable columns
   const __amdgpu_buffer_rsrc_t qr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(Q + rs * ldq), 0, (int)(((re - rs - 1) * ldq + cpad) * 4), 0x00020000);
@@ -356,7 +431,7 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   for (int i = 0; i < 4; ++i) {
     int64_t cc = col0 + 16 * i + 8 * h;
     if (cc > n - 8) cc = n - 8;
-    voa[i] = (int)(((int64_t)(8 * g + o) * lda + cc) * 2);
+    voa[i] = (int)(((int64_t)(8 * g + o) * lda + cc) * ES);
   }
   // Q (waves 0..NT-1): row 8 g + o, columns 16 wave + 8 h .. +7, clamped to
   // the readable width (the columns past c only reach dropped outputs)
@@ -364,13 +439,13 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   const int voq = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
   const bool qwave = wave < NT;
   // two register sets, chunk ch in set ch & 1, loaded two chunks ahead
-  u32x4 ra[2][4];
+  typedef typename Frag<ES>::raw raw_t;
+  raw_t ra[2][4];
   f32x4 rq[2][2];
-  auto load = [&](int ch, u32x4 (&da)[4], f32x4 (&dq)[2]) {
-    const int soa = ch * kTR * (int)lda * 2;
+  auto load = [&](int ch, raw_t (&da)[4], f32x4 (&dq)[2]) {
+    const int soa = ch * kTR * (int)lda * ES;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      da[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[i], soa, 0));
+    for (int i = 0; i < 4; ++i) da[i] = Frag<ES>::load(ar, voa[i], soa);
     if (qwave) {
       const int soq = ch * kTR * (int)ldq * 4;
       dq[0] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, soq, 0));
@@ -407,7 +482,7 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     constexpr int nxt = set ^ 1;
     u32x4 a[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = octet_transpose(ra[set][i], o);
+    for (int i = 0; i < 4; ++i) a[i] = octet_transpose(Frag<ES>::bf(ra[set][i]), o);
     // refill this set with chunk ch + 2 (the last prefetches are harmless repeats)
     const int ch2 = ch + 2 < nchunk ? ch + 2 : ch;
     load(ch2, ra[set], rq[set]);
@@ -475,28 +550,23 @@ hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hi
   return hipGetLastError();
 }
 
-bool bf16_pass_applies(const void* A, int64_t n, int64_t lda, int c) {
-  return c >= 1 && c <= 128 && n % 8 == 0 && lda % 8 == 0 &&
-         (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (int64_t)512 * lda * 2 < (1LL << 31);
+bool bf16_pass_applies(const void* A, int es, int64_t n, int64_t lda, int c) {
+  return (es == 1 || es == 2) && c >= 1 && c <= 128 && n % 8 == 0 && lda % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(A) % (8 * es)) == 0 && (int64_t)512 * lda * es < (1LL << 31);
 }
 
-hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda,
-                               const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, int c,
-                               const float* scale, float* Y, int64_t ldy, double* fro2_part,
-                               int* nparts, hipStream_t s) {
-  if (!bf16_pass_applies(A, n, lda, c) || ldx % 8 != 0 || (int64_t)c * ldx * 2 >= (1LL << 31))
-    return hipErrorInvalidValue;
-  if (m <= 0) {
-    if (nparts) *nparts = 0;
-    return hipSuccess;
-  }
+template <int ES>
+hipError_t nt_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const __bf16* Xhi,
+                   const __bf16* Xlo, int64_t ldx, int c, const float* scale, float* Y,
+                   int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
+  const unsigned char* Ab = static_cast<const unsigned char*>(A);
 #define RSVD_NT_BF16(NT)                                                                        \
   case NT: {                                                                                    \
     constexpr int bt = nt_bf16_threads<NT>();                                                   \
     const int64_t nblk = (m + bt - 1) / bt;                                                     \
     if (nparts) *nparts = (int)nblk;                                                            \
-    hipLaunchKernelGGL(k_gemm_nt_bf16<NT>, dim3((unsigned)nblk), dim3(bt), 0, s, A, m, n, lda,  \
-                       Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part);                             \
+    hipLaunchKernelGGL((k_gemm_nt_bf16<NT, ES>), dim3((unsigned)nblk), dim3(bt), 0, s, Ab, m,   \
+                       n, lda, Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part);                     \
     break;                                                                                      \
   }
   switch ((c + 15) / 16) {
@@ -508,10 +578,43 @@ hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_tn_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda, const float* Q,
-                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
-                               hipStream_t s) {
-  if (!bf16_pass_applies(A, n, lda, c) || ldq % 8 != 0 || ldq < ((c + 7) & ~7) ||
+hipError_t launch_gemm_nt_bf16(const void* A, int es, int64_t m, int64_t n, int64_t lda,
+                               const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, int c,
+                               const float* scale, float* Y, int64_t ldy, double* fro2_part,
+                               int* nparts, hipStream_t s) {
+  if (!bf16_pass_applies(A, es, n, lda, c) || ldx % 8 != 0 || (int64_t)c * ldx * 2 >= (1LL << 31))
+    return hipErrorInvalidValue;
+  if (m <= 0) {
+    if (nparts) *nparts = 0;
+    return hipSuccess;
+  }
+  return es == 1 ? nt_lowp<1>(A, m, n, lda, Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part, nparts, s)
+                 : nt_lowp<2>(A, m, n, lda, Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part, nparts, s);
+}
+
+template <int ES>
+hipError_t tn_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const float* Q, int64_t ldq,
+                   int c, double* P, int64_t rps, dim3 grid, hipStream_t s) {
+  const unsigned char* Ab = static_cast<const unsigned char*>(A);
+  const dim3 block(512);
+#define RSVD_TN_BF16(NT)                                                                        \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL((k_gemm_tn_bf16<NT, ES>), grid, block, 0, s, Ab, m, n, lda, Q, ldq, c,   \
+                       P, rps);                                                                 \
+    break;
+  switch ((c + 15) / 16) {
+    RSVD_TN_BF16(1) RSVD_TN_BF16(2) RSVD_TN_BF16(3) RSVD_TN_BF16(4)
+    RSVD_TN_BF16(5) RSVD_TN_BF16(6) RSVD_TN_BF16(7) RSVD_TN_BF16(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_TN_BF16
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int64_t lda,
+                               const float* Q, int64_t ldq, int c, double* P, int64_t max_split,
+                               int* nsplit, hipStream_t s) {
+  if (!bf16_pass_applies(A, es, n, lda, c) || ldq % 8 != 0 || ldq < ((c + 7) & ~7) ||
       (reinterpret_cast<uintptr_t>(Q) % 16) != 0 || m <= 0)
     return hipErrorInvalidValue;
   const int ntile = (int)((n + kTA - 1) / kTA);
@@ -522,20 +625,25 @@ hipError_t launch_gemm_tn_bf16(const __bf16* A, int64_t m, int64_t n, int64_t ld
   int64_t rps = (m + ns - 1) / ns;
   rps = (rps + kTR - 1) / kTR * kTR;
   ns = (m + rps - 1) / rps;
-  const int64_t ld = lda * 2 > ldq * 4 ? lda * 2 : ldq * 4;
+  const int64_t ld = lda * es > ldq * 4 ? lda * es : ldq * 4;
   if ((rps + kTR) * ld >= (1LL << 31)) return hipErrorInvalidValue;
   *nsplit = (int)ns;
-  const dim3 grid((unsigned)ns, (unsigned)ntile), block(512);
-#define RSVD_TN_BF16(NT)                                                                        \
-  case NT:                                                                                      \
-    hipLaunchKernelGGL(k_gemm_tn_bf16<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, P, rps); \
-    break;
-  switch ((c + 15) / 16) {
-    RSVD_TN_BF16(1) RSVD_TN_BF16(2) RSVD_TN_BF16(3) RSVD_TN_BF16(4)
-    RSVD_TN_BF16(5) RSVD_TN_BF16(6) RSVD_TN_BF16(7) RSVD_TN_BF16(8)
-    default: return hipErrorInvalidValue;
-  }
-#undef RSVD_TN_BF16
+  const dim3 grid((unsigned)ns, (unsigned)ntile);
+  return es == 1 ? tn_lowp<1>(A, m, n, lda, Q, ldq, c, P, rps, grid, s)
+                 : tn_lowp<2>(A, m, n, lda, Q, ldq, c, P, rps, grid, s);
+}
+
+hipError_t launch_quantize_fp8(const float* A, int64_t m, int64_t n, int64_t lda, void* Aq,
+                               int64_t ldq, float* scale, unsigned* cmax, hipStream_t s) {
+  if (m < 1 || n < 1) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(cmax), n, 0, s);
+  if (e != hipSuccess) return e;
+  const int64_t rpb = 256;
+  hipLaunchKernelGGL(k_colmax_abs, dim3((unsigned)((m + rpb - 1) / rpb)), dim3(256), 0, s, A, m, n,
+                     lda, rpb, cmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_quantize_fp8, dim3(nblocks(m * n, 256)), dim3(256), 0, s, A, m, n, lda,
+                     cmax, static_cast<unsigned char*>(Aq), ldq, scale);
   return hipGetLastError();
 }
 

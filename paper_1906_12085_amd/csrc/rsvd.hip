@@ -211,11 +211,15 @@ hipError_t reset(rsvd_plan_s* p) {
   return hipGetLastError();
 }
 
-// A stored in bfloat16 with FP32 column scales (null: ones).
+// A stored in bfloat16 (es = 2) or FP8 E4M3 (es = 1) with FP32 column
+// scales (null: ones).
 struct LowpA {
-  const __bf16* A;
+  const void* A;
   const float* scale;
+  int es;
 };
+// Bytes per stored element of A for a low-precision plan (0 otherwise).
+int lowp_es(int dtype) { return dtype == RSVD_BF16 ? 2 : (dtype == RSVD_FP8 ? 1 : 0); }
 
 template <typename T>
 struct Path {
@@ -231,7 +235,7 @@ struct Path {
     hipError_t e;
     {
       KtScope ts(p, KT_PASS_TN);
-      e = launch_gemm_tn_bf16(lp.A, m, n, lda, Q, ldq, c, p->part, p->max_split, &ns, s);
+      e = launch_gemm_tn_bf16(lp.A, lp.es, m, n, lda, Q, ldq, c, p->part, p->max_split, &ns, s);
     }
     if (e != hipSuccess) return e;
     if ((e = launch_reduce_partials(p->part, ns, n, c, Z, c, s)) != hipSuccess) return e;
@@ -357,7 +361,7 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
       __bf16* Xlo = Xhi + (int64_t)l * n;
       if ((e = launch_cast_hilo_t(X64, n, l, lp->scale, Xhi, Xlo, n, s)) != hipSuccess) return e;
       KtScope ts(p, KT_PASS_NN);
-      return launch_gemm_nt_bf16(lp->A, m, n, lda, Xhi, Xlo, n, l, lp->scale,
+      return launch_gemm_nt_bf16(lp->A, lp->es, m, n, lda, Xhi, Xlo, n, l, lp->scale,
                                  reinterpret_cast<float*>(Y), l, fro2_part, np, s);
     }
     if (tall) {
@@ -509,8 +513,9 @@ int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_
                          int32_t dtype, int32_t want_gram, uint64_t seed, void* stream) {
   if (!plan) return RSVD_ERR_ARG;
   *plan = nullptr;
-  if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_ARG;
-  if (dtype == RSVD_BF16 && want_gram) return RSVD_ERR_ARG;   // the A^T A route is fp32/fp64
+  if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16 && dtype != RSVD_FP8)
+    return RSVD_ERR_ARG;
+  if (lowp_es(dtype) && want_gram) return RSVD_ERR_ARG;   // the A^T A route is fp32/fp64
   if (l_max < 1) return RSVD_ERR_ARG;
   if (n_max < 1 || m_max < n_max) return RSVD_ERR_SHAPE;
   if (l_max > kMaxL) return RSVD_ERR_SHAPE;
@@ -626,33 +631,72 @@ int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, 
   if (plan->dtype == RSVD_BF16)
     return rsvd_solve_bf16(plan, A, nullptr, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
                            (float*)V, ldv, K);
+  if (plan->dtype == RSVD_FP8)
+    return rsvd_solve_fp8(plan, A, nullptr, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
+                          (float*)V, ldv, K);
   return rsvd_run<float>(plan, (const float*)A, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
                          (float*)V, ldv, K);
 }
+
+}  // extern "C"
+
+namespace {
+int32_t solve_lowp(rsvd_plan_t plan, int dtype, const void* A, const float* col_scale, int64_t m,
+                   int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
+                   const double* omega, float* U, int64_t ldu, double* S, float* V, int64_t ldv,
+                   int32_t* K) {
+  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (plan->dtype != dtype) return RSVD_ERR_ARG;
+  const int es = lowp_es(dtype);
+  const int l = (int)((k + (int64_t)p < n) ? k + p : n);
+  if (!bf16_pass_applies(A, es, n, lda, l)) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  const LowpA lp{A, col_scale, es};
+  return rsvd_run<float>(plan, nullptr, m, n, lda, k, p, q, t, omega, U, ldu, S, V, ldv, K, &lp);
+}
+
+int32_t quantize(rsvd_plan_t plan, int es, const float* A, int64_t m, int64_t n, int64_t lda,
+                 void* Aq, int64_t ldq, float* col_scale) {
+  if (!plan || !A || !Aq || !col_scale) return RSVD_ERR_ARG;
+  if (m < 1 || n < 1 || lda < n || ldq < n) return RSVD_ERR_ARG;
+  if (m > plan->m_max || n > plan->n_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  unsigned* cmax = reinterpret_cast<unsigned*>(plan->part);
+  if (es == 2)
+    RSVD_CHECK(launch_quantize_bf16(A, m, n, lda, (__bf16*)Aq, ldq, col_scale, cmax, plan->stream));
+  else
+    RSVD_CHECK(launch_quantize_fp8(A, m, n, lda, Aq, ldq, col_scale, cmax, plan->stream));
+  return RSVD_OK;
+}
+}  // namespace
+
+extern "C" {
 
 int32_t rsvd_solve_bf16(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
                         int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
                         const double* omega, float* U, int64_t ldu, double* S, float* V,
                         int64_t ldv, int32_t* K) {
-  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
-  if (rc != RSVD_OK) return rc;
-  if (plan->dtype != RSVD_BF16) return RSVD_ERR_ARG;
-  const int l = (int)((k + (int64_t)p < n) ? k + p : n);
-  if (!bf16_pass_applies(A, n, lda, l)) return RSVD_ERR_ARG;
-  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
-  const LowpA lp{(const __bf16*)A, col_scale};
-  return rsvd_run<float>(plan, nullptr, m, n, lda, k, p, q, t, omega, U, ldu, S, V, ldv, K, &lp);
+  return solve_lowp(plan, RSVD_BF16, A, col_scale, m, n, lda, k, p, q, t, omega, U, ldu, S, V,
+                    ldv, K);
+}
+
+int32_t rsvd_solve_fp8(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
+                       int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
+                       const double* omega, float* U, int64_t ldu, double* S, float* V,
+                       int64_t ldv, int32_t* K) {
+  return solve_lowp(plan, RSVD_FP8, A, col_scale, m, n, lda, k, p, q, t, omega, U, ldu, S, V,
+                    ldv, K);
 }
 
 int32_t rsvd_quantize_bf16(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
                            void* Aq, int64_t ldq, float* col_scale) {
-  if (!plan || !A || !Aq || !col_scale) return RSVD_ERR_ARG;
-  if (m < 1 || n < 1 || lda < n || ldq < n) return RSVD_ERR_ARG;
-  if (m > plan->m_max || n > plan->n_max) return RSVD_ERR_SHAPE;
-  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
-  RSVD_CHECK(launch_quantize_bf16(A, m, n, lda, (__bf16*)Aq, ldq, col_scale,
-                                  reinterpret_cast<unsigned*>(plan->part), plan->stream));
-  return RSVD_OK;
+  return quantize(plan, 2, A, m, n, lda, Aq, ldq, col_scale);
+}
+
+int32_t rsvd_quantize_fp8(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
+                          void* Aq, int64_t ldq, float* col_scale) {
+  return quantize(plan, 1, A, m, n, lda, Aq, ldq, col_scale);
 }
 
 int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,
@@ -698,18 +742,19 @@ int32_t rsvd_gemm_nn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
     RSVD_CHECK(launch_gemm_nn<double>((const double*)A, m, n, lda, (const double*)X, ldx, c,
                                       (double*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     if (Gram) RSVD_CHECK(Path<double>(plan).gram((const double*)Y, m, c, ldy, Gram));
-  } else if (plan->dtype == RSVD_BF16) {
-    // A bfloat16 (unit column scales), X and Y float: X through FP64 into
-    // the hi + lo bf16 pairs the pass takes
+  } else if (lowp_es(plan->dtype)) {
+    // A bfloat16 or FP8 (unit column scales), X and Y float: X through FP64
+    // into the hi + lo bf16 pairs the pass takes
+    const int es = lowp_es(plan->dtype);
     if (c > plan->l_max) return RSVD_ERR_SHAPE;
-    if (!bf16_pass_applies(A, n, lda, c)) return RSVD_ERR_ARG;
+    if (!bf16_pass_applies(A, es, n, lda, c)) return RSVD_ERR_ARG;
     RSVD_CHECK(launch_cast_to_f64<float>((const float*)X, n, c, ldx, plan->Zd, c, s));
     __bf16* Xhi = reinterpret_cast<__bf16*>(plan->Xs);
     __bf16* Xlo = Xhi + n * c;
     RSVD_CHECK(launch_cast_hilo_t(plan->Zd, n, c, nullptr, Xhi, Xlo, n, s));
     {
       KtScope ts(plan, KT_PASS_NN);
-      RSVD_CHECK(launch_gemm_nt_bf16((const __bf16*)A, m, n, lda, Xhi, Xlo, n, c, nullptr,
+      RSVD_CHECK(launch_gemm_nt_bf16(A, es, m, n, lda, Xhi, Xlo, n, c, nullptr,
                                      (float*)Y, ldy, fro2 ? plan->fro2_part : nullptr, &np, s));
     }
     if (Gram) RSVD_CHECK(Path<float>(plan).gram((const float*)Y, m, c, ldy, Gram));
@@ -746,15 +791,16 @@ int32_t rsvd_gemm_tn(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int6
   if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
   if (plan->dtype == RSVD_F64)
     RSVD_CHECK(Path<double>(plan).tn((const double*)A, m, n, lda, (const double*)Q, ldq, c, Z));
-  else if (plan->dtype == RSVD_BF16) {
-    // A bfloat16 (unit column scales): Q copied into the plan's padded rows
+  else if (lowp_es(plan->dtype)) {
+    // A bfloat16 or FP8 (unit column scales): Q copied into the plan's padded rows
+    const int es = lowp_es(plan->dtype);
     if (c > plan->l_max) return RSVD_ERR_SHAPE;
-    if (!bf16_pass_applies(A, n, lda, c)) return RSVD_ERR_ARG;
+    if (!bf16_pass_applies(A, es, n, lda, c)) return RSVD_ERR_ARG;
     const int64_t lq = ldq1_of(c);
     if (hipMemcpy2DAsync(plan->Q1, lq * sizeof(float), Q, ldq * sizeof(float), c * sizeof(float),
                          m, hipMemcpyDeviceToDevice, plan->stream) != hipSuccess)
       return RSVD_ERR_DEVICE;
-    RSVD_CHECK(Path<float>(plan).tn_bf16(LowpA{(const __bf16*)A, nullptr}, m, n, lda,
+    RSVD_CHECK(Path<float>(plan).tn_bf16(LowpA{A, nullptr, es}, m, n, lda,
                                          (const float*)plan->Q1, lq, c, Z));
   } else
     RSVD_CHECK(Path<float>(plan).tn((const float*)A, m, n, lda, (const float*)Q, ldq, c, Z));

@@ -201,19 +201,26 @@ hipError_t launch_cast_hilo_t(const double* X, int64_t n, int c, const float* sc
                               __bf16* Xlo, int64_t ldx, hipStream_t s);
 // Z (n x c, ld c) rows times scale (no-op for a null scale).
 hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hipStream_t s);
-// Whether the bf16 passes take A (n % 8 == 0, 16-byte rows, c <= 128).
-bool bf16_pass_applies(const void* A, int64_t n, int64_t lda, int c);
-// Y (m x c, fp32) = Aq (Xhi + Xlo)^T; per-block FP64 sums of the squared
-// dequantised entries into fro2_part (count in *nparts) when non-null.
-hipError_t launch_gemm_nt_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda,
+// FP8 E4M3 storage: Aq (m x n, ldq, one byte each) = E4M3(A / s), s the least
+// powers of two with max |A_j| / s_j <= 448.
+hipError_t launch_quantize_fp8(const float* A, int64_t m, int64_t n, int64_t lda, void* Aq,
+                               int64_t ldq, float* scale, unsigned* cmax, hipStream_t s);
+// Whether the low-precision passes take A of es bytes per element (2:
+// bfloat16, 1: FP8 E4M3): n % 8 == 0, lda % 8 == 0, rows aligned to 8 es
+// bytes, c <= 128.
+bool bf16_pass_applies(const void* A, int es, int64_t n, int64_t lda, int c);
+// Y (m x c, fp32) = Aq (Xhi + Xlo)^T on the bf16 matrix cores (FP8 widened to
+// bf16 in registers); per-block FP64 sums of the squared dequantised entries
+// into fro2_part (count in *nparts) when non-null.
+hipError_t launch_gemm_nt_bf16(const void* A, int es, int64_t m, int64_t n, int64_t lda,
                                const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, int c,
                                const float* scale, float* Y, int64_t ldy, double* fro2_part,
                                int* nparts, hipStream_t s);
 // FP64 partials (nsplit x n x c) of Aq^T Q (unscaled), Q fp32 with ldq % 8 == 0
 // and round_up(c, 8) readable columns per row.
-hipError_t launch_gemm_tn_bf16(const __bf16* A, int64_t m, int64_t n, int64_t lda, const float* Q,
-                               int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
-                               hipStream_t s);
+hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int64_t lda,
+                               const float* Q, int64_t ldq, int c, double* P, int64_t max_split,
+                               int* nsplit, hipStream_t s);
 
 // S[i] = sqrt(max(lam[i], 0)).
 hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s);

@@ -58,7 +58,8 @@ def test_plan_create_validates_before_device_calls(lib):
     assert f(ctypes.byref(h), 1000, 200, 97, 1, 0, 0, None) == -2         # l_max above 96
     assert f(ctypes.byref(h), 5000, 2000, 32, 1, 1, 0, None) == -2        # A^T A route n_max above 1024
     assert f(ctypes.byref(h), 5000, 200, 32, 2, 1, 0, None) == -1         # bf16 plan: no A^T A route
-    assert f(ctypes.byref(h), 5000, 200, 32, 3, 0, 0, None) == -1         # unknown dtype
+    assert f(ctypes.byref(h), 5000, 200, 32, 3, 1, 0, None) == -1         # fp8 plan: no A^T A route
+    assert f(ctypes.byref(h), 5000, 200, 32, 4, 0, 0, None) == -1         # unknown dtype
     assert h.value is None
 
 
@@ -73,6 +74,8 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_plan_kernel_times(None, 1, None, None, 0) == -1
     assert lib.rsvd_solve_bf16(None, a, None, 100, 16, 16, 4, 2, 1, 0.9, None, a, 4, a, a, 4, a) == -1
     assert lib.rsvd_quantize_bf16(None, a, 100, 16, 16, a, 16, a) == -1
+    assert lib.rsvd_solve_fp8(None, a, None, 100, 16, 16, 4, 2, 1, 0.9, None, a, 4, a, a, 4, a) == -1
+    assert lib.rsvd_quantize_fp8(None, a, 100, 16, 16, a, 16, a) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

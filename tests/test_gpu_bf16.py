@@ -1,9 +1,11 @@
-"""Parity of the bfloat16-storage path (plan dtype RSVD_BF16) against the oracle.
+"""Parity of the low-precision storage paths (plan dtypes RSVD_BF16 and
+RSVD_FP8) against the oracle.
 
-The matrix is Aq diag(s), Aq bfloat16 and s power-of-two column scales; the
-oracle runs in FP64 on that dequantised stored matrix (exact: a bf16 value
-times a power of two is an FP64 number), so what is checked is the
-computation, not the storage rounding.
+The matrix is Aq diag(s), Aq bfloat16 or OCP FP8 E4M3 and s power-of-two
+column scales; the oracle runs in FP64 on that dequantised stored matrix
+(exact: a bf16 or E4M3 value times a power of two is an FP64 number), so what
+is checked is the computation, not the storage rounding.  E4M3 values are
+widened to bfloat16 exactly, so both formats share the bounds below.
 
 Bounds: a bf16 x bf16 product is exact in FP32; the right factor x is held
 as hi + lo with |x - (hi + lo)| <= 2^-17 |x|; sums are FP32 inside a row
@@ -27,9 +29,15 @@ import paper_1906_12085_amd as rs  # noqa: E402
 HILO = 2.0 ** -16
 
 
-def bf16(x):
-    """Round an FP64/FP32 array to bfloat16 (nearest even) as a CPU tensor."""
-    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.float32).to(torch.bfloat16)
+FORMATS = {"bf16": torch.bfloat16, "fp8": torch.float8_e4m3fn}
+
+
+def stored(x, fmt=torch.bfloat16):
+    """Round an FP64/FP32 array to the storage format (nearest even) as a CPU
+    tensor (torch's own conversions: an implementation independent of the
+    library's)."""
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.float32).to(fmt)
+
 
 
 def deq(Aq_cpu, s=None):
@@ -37,9 +45,9 @@ def deq(Aq_cpu, s=None):
     return A if s is None else A * np.asarray(s, dtype=np.float64)[None, :]
 
 
-@pytest.fixture(scope="module")
-def plan():
-    p = rs.Plan(40000, 600, 96, torch.bfloat16, seed=5)
+@pytest.fixture(scope="module", params=list(FORMATS))
+def plan(request):
+    p = rs.Plan(40000, 600, 96, FORMATS[request.param], seed=5)
     yield p
     p.close()
 
@@ -59,10 +67,10 @@ NN_CASES = [
 def test_bf16_gemm_nn_parity(plan, m, n, c, pad):
     announce(f"bf16 gemm_nn m={m} n={n} c={c} pad={pad}")
     rng = np.random.default_rng(m + 5 * n + c)
-    Aq = bf16(rng.standard_normal((m, n)))
+    Aq = stored(rng.standard_normal((m, n)), plan.storage)
     A64 = deq(Aq)
     X0 = rng.standard_normal((n, c)).astype(np.float32)
-    Abig = torch.zeros((m, n + pad), dtype=torch.bfloat16)
+    Abig = torch.zeros((m, n + pad), dtype=plan.storage)
     Abig[:, :n] = Aq
     if pad:
         Abig[:, n:] = float("nan")          # must not reach Y
@@ -98,7 +106,7 @@ TN_CASES = [
 def test_bf16_gemm_tn_parity(plan, m, n, c):
     announce(f"bf16 gemm_tn m={m} n={n} c={c}")
     rng = np.random.default_rng(3 * m + n + 7 * c)
-    Aq = bf16(rng.standard_normal((m, n)))
+    Aq = stored(rng.standard_normal((m, n)), plan.storage)
     A64 = deq(Aq)
     Q0 = rng.standard_normal((m, c)).astype(np.float32)
     Z = torch.empty(n, c, dtype=torch.float64, device="cuda")
@@ -111,10 +119,13 @@ def test_bf16_gemm_tn_parity(plan, m, n, c):
 
 
 def test_bf16_quantize(plan):
-    announce("bf16 quantize 3000x64, column scales 1e-3..1e3, a zero column")
+    fmt = plan.storage
+    announce(f"{fmt} quantize 3000x64, column scales 1e-3..1e3, a zero column, wide-range columns")
     rng = np.random.default_rng(9)
     A0 = (rng.standard_normal((3000, 64)) * 10.0 ** rng.uniform(-3, 3, 64)).astype(np.float32)
     A0[:, 5] = 0.0
+    # entries spread over 12 decades: FP8 subnormals and underflow to zero
+    A0[:, 7] = (rng.choice([-1.0, 1.0], 3000) * 10.0 ** rng.uniform(-12, 0, 3000)).astype(np.float32)
     A = dev(A0, torch.float32)
     Aq, s = plan.quantize(A)
     torch.cuda.synchronize()
@@ -123,10 +134,15 @@ def test_bf16_quantize(plan):
     e = np.log2(sg)
     assert np.all(e == np.round(e))                      # powers of two
     nz = cmax > 0
-    assert np.all(sg[nz] / 2 <= cmax[nz]) and np.all(cmax[nz] < sg[nz])
+    r = cmax[nz] / sg[nz]                                # largest scaled magnitude per column
+    if fmt == torch.bfloat16:
+        assert np.all(r >= 0.5) and np.all(r < 1.0)      # 2^(e-1) <= max < 2^e
+    else:
+        assert np.all(r > 224.0) and np.all(r <= 448.0)  # least 2^e with max / 2^e <= 448
     assert sg[5] == 1.0
-    ref = bf16(A0.astype(np.float64) / sg[None, :])      # exact division by 2^e
-    assert torch.equal(Aq.cpu().view(torch.int16), ref.view(torch.int16))
+    ref = stored(A0.astype(np.float64) / sg[None, :], fmt)   # exact division by 2^e
+    bits = torch.int16 if fmt == torch.bfloat16 else torch.uint8
+    assert torch.equal(Aq.cpu().view(bits), ref.view(bits))
 
 
 def solve_pair(plan, A0, k, p, q, t, omega_seed, scaled=True):
@@ -137,7 +153,9 @@ def solve_pair(plan, A0, k, p, q, t, omega_seed, scaled=True):
         torch.cuda.synchronize()
         A64 = deq(Aq.cpu(), s.cpu().numpy())
     else:
-        Aq, s = bf16(A0).cuda(), None
+        # unit scales: the matrix enters the storage format as it is
+        A0 = A0 / np.abs(A0).max() * (1.0 if plan.storage == torch.bfloat16 else 400.0)
+        Aq, s = stored(A0, plan.storage).cuda(), None
         A64 = deq(Aq.cpu())
     G = synth.gaussian_omega(omega_seed, n, l)
     res = plan.solve(Aq, k, p, q, t, omega=dev(G, torch.float64), col_scale=s)
@@ -180,12 +198,12 @@ def test_bf16_rsvd_edge_shapes(plan, m, n, k, p, q):
 
 
 def test_bf16_argument_errors(plan):
-    A = torch.zeros((100, 20), dtype=torch.bfloat16, device="cuda")     # n % 8 != 0
+    A = torch.zeros((100, 20), dtype=plan.storage, device="cuda")       # n % 8 != 0
     with pytest.raises(rs.RSVDError) as ei:
         plan.solve(A, 4, 2, 1, 0.9)
     assert ei.value.code == rs.RSVD_ERR_ARG
     with pytest.raises(rs.RSVDError):
-        rs.Plan(1000, 64, 16, torch.bfloat16, want_gram=True)
+        rs.Plan(1000, 64, 16, plan.storage, want_gram=True)
 
 
 def test_bf16_deterministic(plan):

@@ -7,8 +7,8 @@ Randomized PCA: the oracle runs the whole solve on the same stored A (read
 back to FP64) with the same sketch (the published Philox/Box-Muller
 definition, rounded to FP32 as the GPU uses it); gate: relative singular-value
 error <= 1e-4, largest principal angle of the top-k U and V subspaces
-<= 1e-3 rad, K equal.  The same for A stored in bfloat16 with power-of-two
-column scales (the oracle on the dequantised stored matrix).
+<= 1e-3 rad, K equal.  The same for A stored in bfloat16 and in FP8 E4M3
+with power-of-two column scales (the oracle on the dequantised stored matrix).
 
 A^T A route: the oracle forms A^T A and its Jacobi eigen-decomposition; all
 512 singular values are gated at 1e-4 relative (the spectrum is well
@@ -63,14 +63,17 @@ def test_fullsize_rsvd_vs_oracle(workload):
 
 
 @pytest.mark.timeout(900)
-def test_fullsize_rsvd_bf16_vs_oracle(workload):
-    # the same A stored in bfloat16 with power-of-two column scales; the
-    # oracle runs on the dequantised stored matrix with the same sketch
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_fullsize_rsvd_lowp_vs_oracle(workload, fmt):
+    # the same A stored in bfloat16 or FP8 E4M3 with power-of-two column
+    # scales; the oracle runs on the dequantised stored matrix with the same
+    # sketch
     c, A, _ = workload
     m, n, k, p, q, t = c["m"], c["n"], c["k"], c["p"], c["q"], c["t"]
     l = k + p
-    announce("fullsize: quantise and rsvd_solve_bf16 on GPU")
-    plan = rs.Plan(m, n, l, torch.bfloat16, seed=c["omega_seed"])
+    announce(f"fullsize: quantise ({fmt}) and solve on GPU")
+    storage = torch.bfloat16 if fmt == "bf16" else torch.float8_e4m3fn
+    plan = rs.Plan(m, n, l, storage, seed=c["omega_seed"])
     Aq, s = plan.quantize(A)
     res = plan.solve(Aq, k, p, q, t, col_scale=s)
     plan.close()

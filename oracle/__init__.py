@@ -40,6 +40,9 @@ PINS = {
     "rsvd": "tests/test_oracle_rsvd.py (exact recovery at rank l, interlacing, "
             "Halko et al. error bound, convergence in q)",
     "gram_eig": "tests/test_oracle_rsvd.py (equals exact SVD on well-separated spectra)",
+    "krylov": "tests/test_oracle_krylov.py (exact recovery at rank (i+1) l where Randomized "
+              "PCA with q = i is not exact, Ritz values between those of Randomized PCA and "
+              "the exact ones, U^T A V = diag(s), i = 0 equals q = 0)",
 }
 
 
@@ -85,6 +88,9 @@ def _load():
         lib.orc_rsvd.argtypes = [i64, i64, p, i64, p, i64, i64, i64, dbl,
                                  p, i64, p, p, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         lib.orc_rsvd.restype = ctypes.c_int
+        lib.orc_krylov.argtypes = [i64, i64, p, i64, p, i64, i64, i64, dbl,
+                                   p, i64, p, p, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+        lib.orc_krylov.restype = ctypes.c_int
         lib.orc_gram_eig.argtypes = [i64, i64, p, i64, dbl, i64, p, i64, p, p, i64,
                                      ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         lib.orc_gram_eig.restype = ctypes.c_int
@@ -231,6 +237,23 @@ def rsvd(A, G, k: int, p: int, q: int, t: float) -> RSVDResult:
                           _ptr(U), k, _ptr(S), _ptr(V), k, ctypes.byref(K), ctypes.byref(f2))
     if rc < 0:
         raise RuntimeError(f"orc_rsvd failed: {rc}")
+    return RSVDResult(U, S, V, int(K.value), float(f2.value), int(rc))
+
+
+def krylov(A, G, k: int, p: int, i: int, t: float) -> RSVDResult:
+    """Krylov method (Sec. 3.1.1) with the sketch G (n x l, l = min(k+p, n))
+    given: blocks H(0) = A G, H(j) = A (A^T H(j-1)) for j <= i, QR of their
+    concatenation (m x (i+1) l, at most n columns), T = A^T Q, SVD of T."""
+    A, G = _f64(A), _f64(G)
+    m, n = A.shape
+    l = min(k + p, n)
+    assert G.shape == (n, l), (G.shape, (n, l))
+    U = np.empty((m, k)); S = np.empty(k); V = np.empty((n, k))
+    K = ctypes.c_int64(0); f2 = ctypes.c_double(0.0)
+    rc = _load().orc_krylov(m, n, _ptr(A), n, _ptr(G), k, p, i, float(t),
+                            _ptr(U), k, _ptr(S), _ptr(V), k, ctypes.byref(K), ctypes.byref(f2))
+    if rc < 0:
+        raise RuntimeError(f"orc_krylov failed: {rc}")
     return RSVDResult(U, S, V, int(K.value), float(f2.value), int(rc))
 
 

@@ -28,6 +28,8 @@
  *   orc_sign_convention         output sign rule (not in the paper)
  *   orc_rsvd                    Randomized PCA (Sec. 3.1.2) with a QR after
  *                               every product with A or A^T
+ *   orc_krylov                  Krylov method (Sec. 3.1.1), blocks kept
+ *                               orthonormal (same Krylov space)
  *   orc_gram_eig                truncated SVD through A^T A (Sec. 2.3,
  *                               Sec. 3.1.3)
  *
@@ -516,6 +518,78 @@ int orc_rsvd(int64_t m, int64_t n, const double* A, int64_t lda,
   rc = orc_select_k(k, S, *fro2, t, K);
 done:
   free(H); free(Q); free(T); free(Qt); free(R); free(Vt); free(St); free(W);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Krylov method (Sec. 3.1.1), the paper's steps in its order:
+ *   1. G (n x l) given, l = min(k + p, n);   2. H(0) = A G;
+ *   3. H(j) = A (A^T H(j-1)) for j = 1..i;
+ *   4. H = [H(0) | ... | H(i)] (m x L, L = (i+1) l; requires L <= n);
+ *   5. QR of H -> Q;   6. T = A^T Q (n x L);
+ *   7. SVD T = V~ S~ W^T;   8. U~ = Q W, first k columns.
+ * Reading: a block is replaced by an orthonormal basis of its own columns
+ * (Householder QR) before it is stored in H and used for the next block, and
+ * A^T H(j-1) likewise before the product with A; a block times an invertible
+ * l x l matrix spans the same columns, so the Krylov space and Q's span are
+ * the paper's.  K by the criterion of Sec. 2.4 over the first k values. */
+int orc_krylov(int64_t m, int64_t n, const double* A, int64_t lda,
+               const double* G, int64_t k, int64_t p, int64_t i, double t,
+               double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+               int64_t* K, double* fro2) {
+  if (m < n || n < 1 || k < 1 || k > n || p < 0 || i < 0 || !(t > 0.0 && t <= 1.0))
+    return ORC_ERR_ARG;
+  const int64_t l = (k + p < n) ? k + p : n;
+  const int64_t L = (i + 1) * l;
+  if (L > n) return ORC_ERR_ARG;
+  double* B = (double*)malloc((size_t)(m * l) * sizeof(double));
+  double* Qb = (double*)malloc((size_t)(m * l) * sizeof(double));
+  double* Tl = (double*)malloc((size_t)(n * l) * sizeof(double));
+  double* Qt = (double*)malloc((size_t)(n * l) * sizeof(double));
+  double* Rl = (double*)malloc((size_t)(l * l) * sizeof(double));
+  double* H = (double*)malloc((size_t)(m * L) * sizeof(double));
+  double* Q = (double*)malloc((size_t)(m * L) * sizeof(double));
+  double* R = (double*)malloc((size_t)(L * L) * sizeof(double));
+  double* T = (double*)malloc((size_t)(n * L) * sizeof(double));
+  double* Vt = (double*)malloc((size_t)(n * L) * sizeof(double));
+  double* St = (double*)malloc((size_t)L * sizeof(double));
+  double* W = (double*)malloc((size_t)(L * L) * sizeof(double));
+  int rc = ORC_OK;
+  if (!B || !Qb || !Tl || !Qt || !Rl || !H || !Q || !R || !T || !Vt || !St || !W) {
+    rc = ORC_ERR_NOMEM;
+    goto done;
+  }
+  *fro2 = orc_fro2(m, n, A, lda);                               /* Eq. sumeigen */
+  orc_gemm_nn(m, n, l, A, lda, G, l, B, l);                    /* H(0) = A G */
+  for (int64_t j = 0; j <= i; ++j) {
+    if (j > 0) {                                                /* H(j) = A (A^T H(j-1)) */
+      if ((rc = orc_gemm_tn(m, n, l, A, lda, Qb, l, Tl, l)) != ORC_OK) goto done;
+      if ((rc = orc_qr_householder(n, l, Tl, l, Qt, l, Rl, l)) != ORC_OK) goto done;
+      orc_gemm_nn(m, n, l, A, lda, Qt, l, B, l);
+    }
+    if ((rc = orc_qr_householder(m, l, B, l, Qb, l, Rl, l)) != ORC_OK) goto done;
+    for (int64_t r = 0; r < m; ++r)                             /* block j of H */
+      for (int64_t c = 0; c < l; ++c) H[r * L + j * l + c] = Qb[r * l + c];
+  }
+  if ((rc = orc_qr_householder(m, L, H, L, Q, L, R, L)) != ORC_OK) goto done;   /* QR of H */
+  if ((rc = orc_gemm_tn(m, n, L, A, lda, Q, L, T, L)) != ORC_OK) goto done;    /* T = A^T Q */
+  rc = orc_svd_exact(n, L, T, L, Vt, L, St, W, L);              /* T = V~ S~ W^T */
+  if (rc < 0) goto done;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < m; ++r)                               /* U~ = Q W */
+    for (int64_t c = 0; c < k; ++c) {
+      double s = 0.0;
+      for (int64_t e = 0; e < L; ++e) s += Q[r * L + e] * W[e * L + c];
+      U[r * ldu + c] = s;
+    }
+  for (int64_t c = 0; c < k; ++c) S[c] = St[c];
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t c = 0; c < k; ++c) V[r * ldv + c] = Vt[r * L + c];
+  orc_sign_convention(m, n, k, U, ldu, V, ldv);
+  rc = orc_select_k(k, S, *fro2, t, K);
+done:
+  free(B); free(Qb); free(Tl); free(Qt); free(Rl); free(H); free(Q); free(R); free(T);
+  free(Vt); free(St); free(W);
   return rc;
 }
 

@@ -27,6 +27,8 @@ METRIC = "rSVD solves/s + TFLOP/s (% roofline) at ≤1e-4 σ rel err; p50/p99 la
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+# Krylov-method leg: k, p and the block count minus one (L = (i+1)(k+p) = 96)
+KRYLOV = (32, 16, 1)
 
 
 def parse():
@@ -41,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
+    ap.add_argument("--no-krylov", action="store_true",
+                    help="skip the Krylov-method leg (k=32, p=16, two blocks: L = 96)")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the legs on bfloat16 and FP8 storage of the same A")
     return ap.parse_args()
@@ -246,6 +250,52 @@ def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt):
             "kernels": lowp_rooflines(ktimes, m, n, l, steps, es, "_bf16" if es == 2 else "_fp8")}
 
 
+def krylov_leg(rs, torch, A, m, n, k, p, i, t, seed, steps, warmup, stream):
+    """The Krylov method (i + 1 blocks of l = k + p columns) on the same fp32
+    A with the plan's seeded sketch, timed like the fp32 leg; accuracy
+    against the FP64 Krylov path on the same stored A."""
+    l = k + p
+    L = (i + 1) * l
+    dev = A.device
+    plan = rs.Plan(m, n, L, torch.float32, seed=seed, stream=stream)
+    U = torch.empty(m, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(n, k, dtype=torch.float32, device=dev)
+    K = torch.empty(1, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        rs.rsvd_solve_krylov(plan.handle, A, k, p, i, t, None, U, S, V, K)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps):
+        evs[j][0].record(stream)
+        rs.rsvd_solve_krylov(plan.handle, A, k, p, i, t, None, U, S, V, K)
+        evs[j][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = rs.rsvd_plan_status(plan.handle)
+    ms = [e[0].elapsed_time(e[1]) for e in evs]
+    A64 = A.double()
+    plan64 = rs.Plan(m, n, L, torch.float64, seed=seed, stream=stream)
+    r64 = plan64.solve_krylov(A64, k, p, i, t)
+    sig_err = float(torch.max(torch.abs(S - r64.S) / r64.S).item())
+    same_k = int(K.item()) == r64.K
+    plan64.close()
+    plan.close()
+    del A64
+    torch.cuda.empty_cache()
+    med = pct(ms, 50)
+    # passes over A: A G, i times (A^T, A) and the final A^T Q
+    nbytes = (2 * i + 2) * 4.0 * m * n + 4.0 * m * ((2 * i + 1) * l + L)
+    return {"blocks": i + 1, "l": l, "L": L, "p50_ms": round(med, 3),
+            "p99_ms": round(pct(ms, 99), 3), "solves_per_s": round(1000.0 / med, 2),
+            "wall_solves_per_s": round(steps / wall, 2),
+            "gbs_passes": round(nbytes / (med / 1e3) / 1e9, 1), "K": int(K.item()),
+            "K_equals_fp64_path": same_k, "status": rs.STATUS.get(status, status),
+            "sigma_rel_err_vs_fp64_path": sig_err}
+
+
 def pct(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -371,6 +421,13 @@ def main():
             print(f"[bench] {key} storage leg: {args.steps} solves", file=sys.stderr, flush=True)
             legs[key] = lowp_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"], args.steps,
                                  args.warmup, stream, fmt)
+
+    if not args.no_krylov:
+        kk, kp, ki = KRYLOV
+        print(f"[bench] krylov leg k={kk} p={kp} i={ki}: {args.steps} solves", file=sys.stderr,
+              flush=True)
+        legs["krylov"] = krylov_leg(rs, torch, A, m, n, kk, kp, ki, t, c["omega_seed"],
+                                    args.steps, args.warmup, stream)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -153,7 +153,22 @@ int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, 
                          int32_t k, int32_t p, int32_t q, double t, const double* omega,
                          void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
 
-/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the
+/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
+ * min(k + p, n)), blocks H(0) = A G and H(j) = A (A^T H(j-1)) for j = 1..i,
+ * QR of their concatenation H (m x (i+1) l), T = A^T Q, SVD T = V~ S~ W^T,
+ * U~ = Q W -- returning the first k triplets and K by the threshold t
+ * (Sec. 2.4) as rsvd_solve does.  Each block is replaced by an orthonormal
+ * basis of its own columns (CholeskyQR2, FP64 Gram) before it is stored and
+ * used for the next one, which leaves the Krylov space unchanged; the QR of
+ * H is CholeskyQR2.  omega: as rsvd_solve_omega, or NULL for the plan's
+ * seeded sketch.  Requires (i+1) l <= n (else RSVD_ERR_ARG) and
+ * (i+1) l <= the plan's l_max (else RSVD_ERR_SHAPE); RSVD_F64 and RSVD_F32
+ * plans only.  U (m x k, ldu), S (k), V (n x k, ldv) as rsvd_solve. */
+int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                          int32_t k, int32_t p, int32_t i, double t, const double* omega,
+                          void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
+
+/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the
  * matrix Aq diag(col_scale), Aq bfloat16 m x n (device, row-major, lda),
  * col_scale n FP32 values (device; NULL = all ones).  The plan must be
  * RSVD_BF16.  H = A G and the power-iteration products run on BF16 matrix

@@ -36,7 +36,7 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
            "rsvd_gaussian_fill", "rsvd_gemm_nn", "rsvd_gemm_tn", "rsvd_cholqr2",
            "rsvd_small_svd", "rsvd_sym_eig", "rsvd_plan_kernel_times", "rsvd_solve_bf16",
-           "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8"]
+           "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8", "rsvd_solve_krylov"]
 
 
 class RSVDError(RuntimeError):
@@ -68,6 +68,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp]),
         "rsvd_solve_omega": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                    vp, i64, vp, vp, i64, vp]),
+        "rsvd_solve_krylov": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
+                                    vp, i64, vp, vp, i64, vp]),
         "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
         "rsvd_gaussian_fill": (i32, [u64, i64, i64, vp, vp]),
         "rsvd_gemm_nn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp, i64, vp, vp]),
@@ -169,6 +171,17 @@ def rsvd_solve_omega(plan: int, A, k: int, p: int, q: int, t: float, omega, U, S
     return _check(load_library().rsvd_solve_omega(plan, _ptr(A), m, n, _ld(A), k, p, q, float(t),
                                                   _ptr(omega), _ptr(U), _ld(U), _ptr(S), _ptr(V),
                                                   _ld(V), _ptr(K)), "rsvd_solve_omega")
+
+
+def rsvd_solve_krylov(plan: int, A, k: int, p: int, i: int, t: float, omega, U, S, V,
+                      K) -> int:
+    m, n = A.shape
+    if omega is not None:
+        assert omega.is_contiguous() and omega.dtype.is_floating_point and omega.element_size() == 8
+    return _check(load_library().rsvd_solve_krylov(plan, _ptr(A), m, n, _ld(A), k, p, i,
+                                                   float(t), _ptr(omega), _ptr(U), _ld(U),
+                                                   _ptr(S), _ptr(V), _ld(V), _ptr(K)),
+                  "rsvd_solve_krylov")
 
 
 def rsvd_solve_bf16(plan: int, A, col_scale, k: int, p: int, q: int, t: float, omega, U, S, V,
@@ -317,6 +330,19 @@ class Plan:
             rsvd_solve(self.handle, A, k, p, q, t, U, S, V, K)
         else:
             rsvd_solve_omega(self.handle, A, k, p, q, t, omega, U, S, V, K)
+        if not sync:
+            return Result(U, S, V, K, 0)
+        st = self.status()
+        return Result(U, S, V, int(K.item()), st)
+
+    def solve_krylov(self, A, k: int, p: int, i: int, t: float, omega=None, sync: bool = True):
+        """Krylov method with i + 1 blocks of l = min(k + p, n) columns
+        (rsvd_solve_krylov)."""
+        m, n = A.shape
+        torch = self.torch
+        U = self._out((m, k)); V = self._out((n, k))
+        S = self._out((k,), torch.float64); K = self._out((1,), torch.int32)
+        rsvd_solve_krylov(self.handle, A, k, p, i, t, omega, U, S, V, K)
         if not sync:
             return Result(U, S, V, K, 0)
         st = self.status()

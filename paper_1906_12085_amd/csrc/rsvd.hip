@@ -302,6 +302,20 @@ struct Path {
     return launch_chol_inv<T>(p->Wg, c, R2, R2inv, trans2 >= 0 ? RinvT : nullptr, p->status, s,
                               trans2 > 0);
   }
+
+  // Shifted CholeskyQR (Fukaya et al., SIAM J. Sci. Comput. 2020): Q0 = Y R0^-1
+  // with R0 = chol(Y^T Y + shift I); it brings a matrix whose condition number
+  // is up to about 2^53 within CholeskyQR2's reach (followed by cqr2 of Q0).
+  hipError_t cqr_shifted(const T* Y, int64_t m, int c, int64_t ldy, T* Q0, int64_t ldq,
+                         double* R0, double* R0inv, T* RinvT) {
+    hipError_t e;
+    const bool tall = times_rinv_tall(Y, c, ldy, RinvT);
+    if ((e = gram(Y, m, c, ldy, p->Wg)) != hipSuccess) return e;
+    if ((e = launch_shift_diag(p->Wg, c, m, s)) != hipSuccess) return e;
+    if ((e = launch_chol_inv<T>(p->Wg, c, R0, R0inv, RinvT, p->status, s, tall)) != hipSuccess)
+      return e;
+    return times_rinv(Y, m, c, ldy, RinvT, tall, Q0, ldq);
+  }
 };
 
 // Orthonormalise an FP64 n x c matrix Zin: Zout = Q (explicit), R2s R1s = R.
@@ -411,6 +425,92 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   else
     RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, lq, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
   // K by the explained-variance criterion (Sec. 2.4)
+  RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
+  return RSVD_OK;
+}
+
+// Krylov method (Sec. 3.1.1): blocks H(0) = A G and H(j) = A (A^T H(j-1)),
+// j = 1..i, each turned into an orthonormal basis Q(j) of its own columns
+// (CholeskyQR2 and the explicit product Q1 R2^-1; the same Krylov space) and
+// stored side by side as the m x L panel H, L = (i+1) l; CholeskyQR2 of H
+// gives Q = Q1 R2^-1, then T = A^T Q, the small SVD and U = Q W as for
+// Randomized PCA.  The panel lives in the plan's Y buffer (row stride L),
+// which needs L <= l_max.
+template <typename T>
+int32_t krylov_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, int k, int pov,
+                   int iblk, double t, const double* omega, T* U, int64_t ldu, double* S, T* V,
+                   int64_t ldv, int32_t* K) {
+  const int l = (int)((k + pov < n) ? k + pov : n);
+  const int L = (iblk + 1) * l;
+  hipStream_t s = p->stream;
+  Path<T> P(p);
+  T* Xs = (T*)p->Xs;
+  T* H = (T*)p->Y;
+  T* Q1 = (T*)p->Q1;
+  RSVD_CHECK(reset(p));
+  // step 1: the Gaussian sketch matrix G (n x l)
+  if (!omega) {
+    RSVD_CHECK(launch_gaussian_fill(p->seed, n, l, p->omega, s));
+    omega = p->omega;
+  }
+  const bool tall = std::is_same<T, float>::value &&
+                    nt_tall_applies(reinterpret_cast<const float*>(A), n, lda,
+                                    reinterpret_cast<const float*>(Xs), n, l);
+  // A X (X n x l, FP64) into block j of the panel
+  auto pass_nn = [&](const double* X64, int j, double* fro2_part, int* np) -> hipError_t {
+    hipError_t e;
+    T* Yj = H + (int64_t)j * l;
+    if (tall) {
+      if ((e = launch_cast_t_from_f64<T>(X64, n, l, l, Xs, n, s)) != hipSuccess) return e;
+      KtScope ts(p, KT_PASS_NN);
+      return launch_gemm_nt_tall(reinterpret_cast<const float*>(A), m, n, lda,
+                                 reinterpret_cast<const float*>(Xs), n, l,
+                                 reinterpret_cast<float*>(Yj), L, fro2_part, np, s);
+    }
+    if ((e = launch_cast_from_f64<T>(X64, n, l, l, Xs, l, s)) != hipSuccess) return e;
+    return launch_gemm_nn<T>(A, m, n, lda, Xs, l, l, Yj, L, fro2_part, np, s);
+  };
+  // steps 2-4: the blocks, each replaced by its orthonormal basis in place
+  int np = 0;
+  for (int j = 0; j <= iblk; ++j) {
+    if (j == 0) {
+      RSVD_CHECK(pass_nn(omega, 0, p->fro2_part, &np));                    // H(0) = A G
+      RSVD_CHECK(launch_reduce_scalar(p->fro2_part, np, p->scal, s));     // Eq. sumeigen
+    } else {
+      RSVD_CHECK(P.tn(A, m, n, lda, H + (int64_t)(j - 1) * l, L, l, p->Zd));  // A^T Q(j-1)
+      RSVD_CHECK(cqr2_small(p, p->Zd, n, l, p->Zq));
+      RSVD_CHECK(pass_nn(p->Zq, j, nullptr, nullptr));                    // H(j)
+    }
+    T* Yj = H + (int64_t)j * l;
+    const bool tb = P.times_rinv_tall(Q1, l, l, (const T*)p->RinvT);
+    RSVD_CHECK(P.cqr2(Yj, m, l, L, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT, tb));
+    RSVD_CHECK(P.times_rinv(Q1, m, l, l, (const T*)p->RinvT, tb, Yj, L));   // Q(j) = Q1 R2^-1
+  }
+  // step 5: QR of the panel.  Its blocks overlap more as the Krylov space
+  // converges (condition numbers of 1e4 .. 1e11 on decaying spectra), so a
+  // shifted CholeskyQR pass (H -> Q1) precedes CholeskyQR2 (Q1 -> the panel's
+  // own storage, no longer needed): Q = H R2^-1, kept implicit.
+  RSVD_CHECK(P.cqr_shifted(H, m, L, L, Q1, L, p->R1, p->R1inv, (T*)p->RinvT));
+  RSVD_CHECK(P.cqr2(Q1, m, L, L, H, L, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  Q1 = H;
+  // step 6: T = A^T Q = (A^T Q1) R2^-1
+  RSVD_CHECK(P.tn(A, m, n, lda, Q1, L, L, p->Zd));
+  RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, L, L, p->Z2, nullptr, s));
+  // step 7: T = V~ S~ W^T
+  RSVD_CHECK(small_svd_unsorted(p, p->Z2, n, L));
+  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Su, L, p->Vt, n, L, 1, p->Uo, k, S, V, ldv, nullptr,
+                                         p->Wk, s));
+  // step 8: U~ = Q W = Q1 (R2^-1 W), first k columns
+  const bool tall_u = std::is_same<T, float>::value &&
+                      nt_tall_applies(reinterpret_cast<const float*>(Q1), L, L,
+                                      reinterpret_cast<const float*>(p->MkT), L, k);
+  RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, L, L, k, nullptr, (T*)p->MkT, s, tall_u));
+  if (tall_u)
+    RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, L, L,
+                                   reinterpret_cast<const float*>(p->MkT), L, k,
+                                   reinterpret_cast<float*>(U), ldu, nullptr, nullptr, s));
+  else
+    RSVD_CHECK(launch_gemm_nn<T>(Q1, m, L, L, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
   RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
   return RSVD_OK;
 }
@@ -697,6 +797,24 @@ int32_t rsvd_quantize_bf16(rsvd_plan_t plan, const float* A, int64_t m, int64_t 
 int32_t rsvd_quantize_fp8(rsvd_plan_t plan, const float* A, int64_t m, int64_t n, int64_t lda,
                           void* Aq, int64_t ldq, float* col_scale) {
   return quantize(plan, 1, A, m, n, lda, Aq, ldq, col_scale);
+}
+
+int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                          int32_t k, int32_t p, int32_t i, double t, const double* omega,
+                          void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K) {
+  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, 0, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (i < 0 || lowp_es(plan->dtype)) return RSVD_ERR_ARG;
+  const int64_t l = (k + (int64_t)p < n) ? k + p : n;
+  const int64_t L = (i + 1) * l;
+  if (L > n) return RSVD_ERR_ARG;                  // the panel must have at most n columns
+  if (L > plan->l_max) return RSVD_ERR_SHAPE;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  if (plan->dtype == RSVD_F64)
+    return krylov_run<double>(plan, (const double*)A, m, n, lda, k, p, i, t, omega, (double*)U,
+                              ldu, S, (double*)V, ldv, K);
+  return krylov_run<float>(plan, (const float*)A, m, n, lda, k, p, i, t, omega, (float*)U, ldu,
+                           S, (float*)V, ldv, K);
 }
 
 int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,

@@ -222,6 +222,9 @@ hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int6
                                const float* Q, int64_t ldq, int c, double* P, int64_t max_split,
                                int* nsplit, hipStream_t s);
 
+// Shifted CholeskyQR's diagonal shift on the c x c Gram W of an m x c matrix:
+// W += 11 (m c + c (c+1)) 2^-53 trace(W) I (one block).
+hipError_t launch_shift_diag(double* W, int c, int64_t m, hipStream_t s);
 // S[i] = sqrt(max(lam[i], 0)).
 hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s);
 // p[0..n) = v (a kernel, so the fill can be captured in a graph).

@@ -481,6 +481,22 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// W (c x c Gram of an m x c matrix) += shift I, shift = 11 (m c + c (c+1)) u
+// ||X||_F^2 with u = 2^-53 and ||X||_F^2 = trace(W) (the shift of shifted
+// CholeskyQR, Fukaya et al., SIAM J. Sci. Comput. 2020: it bounds the first
+// factor's condition number so that CholeskyQR2 completes afterwards).
+__global__ void k_shift_diag(double* __restrict__ W, int c, int64_t m) {
+  __shared__ double tr;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < c; ++i) t += W[(int64_t)i * c + i];
+    tr = t;
+  }
+  __syncthreads();
+  const double shift = 11.0 * ((double)m * c + (double)c * (c + 1)) * 0x1p-53 * tr;
+  for (int i = threadIdx.x; i < c; i += blockDim.x) W[(int64_t)i * c + i] += shift;
+}
+
 inline unsigned blocks_for(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
 
 }  // namespace
@@ -595,6 +611,12 @@ hipError_t launch_transpose_f32(const float* X, int64_t rows, int64_t cols, int6
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_diag(double* W, int c, int64_t m, hipStream_t s) {
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(128), 0, s, W, c, m);
   return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_quantize_bf16(None, a, 100, 16, 16, a, 16, a) == -1
     assert lib.rsvd_solve_fp8(None, a, None, 100, 16, 16, 4, 2, 1, 0.9, None, a, 4, a, a, 4, a) == -1
     assert lib.rsvd_quantize_fp8(None, a, 100, 16, 16, a, 16, a) == -1
+    assert lib.rsvd_solve_krylov(None, a, 100, 10, 10, 2, 2, 1, 0.9, None, a, 2, a, a, 2, a) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

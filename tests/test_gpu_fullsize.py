@@ -90,6 +90,28 @@ def test_fullsize_rsvd_lowp_vs_oracle(workload, fmt):
 
 
 @pytest.mark.timeout(900)
+def test_fullsize_krylov_vs_oracle(workload):
+    # the Krylov method at the largest panel a 96-column plan holds: k = 32,
+    # p = 16, two blocks (L = 96), the plan's seeded sketch, as bench.py runs it
+    c, A, A64 = workload
+    m, n, t = c["m"], c["n"], c["t"]
+    k, p, i = 32, 16, 1
+    l = k + p
+    announce("fullsize: rsvd_solve_krylov on GPU")
+    plan = rs.Plan(m, n, (i + 1) * l, torch.float32, seed=c["omega_seed"])
+    res = plan.solve_krylov(A, k, p, i, t)
+    plan.close()
+    G = synth.gaussian_omega(c["omega_seed"], n, l).astype(np.float32).astype(np.float64)
+    announce("fullsize: oracle Krylov method (tens of seconds)")
+    ref = oracle.krylov(A64, G, k, p, i, t)
+    S, U, V = host(res.S), host(res.U), host(res.V)
+    assert np.max(np.abs(S - ref.S) / ref.S) <= 1e-4
+    assert oracle.principal_angle_max(ref.V, V) <= 1e-3
+    assert oracle.principal_angle_max(ref.U, U) <= 1e-3
+    assert res.K == ref.K and res.status == ref.status
+
+
+@pytest.mark.timeout(900)
 def test_fullsize_gram_route_vs_oracle(workload):
     c, A, A64 = workload
     m, n, t = c["m"], c["n"], c["t"]

@@ -332,16 +332,30 @@ hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, doubl
 // one-sided Jacobi on R^T (QR-preconditioned Jacobi in the manner of Drmac &
 // Veselic, SIAM J. Matrix Anal. Appl. 2008: the columns of R^T are already
 // close to orthogonal, so few sweeps are needed): R^T J = Uo diag(Su), so
-// R = J diag(Su) Uo^T and Tm = (Qt J) diag(Su) Uo^T: V~ = Qt J, W = Uo.
+// R = J diag(Su) Uo^T and Tm = (Qt J) diag(Su) Uo^T: V~ = Qt J, W = Uo.  J is
+// accumulated in the rotations when only leading columns are used
+// (all_columns = false): it is then R Uo diag(Su)^-1, whose column for a
+// value Su_j carries a rounding error of order eps Su_1 / Su_j -- small for
+// the k largest values a solve keeps.
 // Leaves V~ unsorted in p->Vt, the values in p->Su and W in p->Uo.
-hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c) {
+hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c,
+                              bool all_columns = false) {
   hipError_t e;
   if ((e = cqr2_small(p, Tm, r, c, p->Zq)) != hipSuccess) return e;
   if ((e = launch_small_gemm<double>(p->R2s, p->R1s, c, c, c, p->Rt, nullptr, p->stream)) != hipSuccess)
     return e;
-  if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, p->diag, p->status,
-                                   p->stream)) != hipSuccess)
-    return e;
+  if (all_columns) {
+    if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, 1, p->diag, p->status,
+                                     p->stream)) != hipSuccess)
+      return e;
+  } else {
+    if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Mk, 0, p->diag, p->status,
+                                     p->stream)) != hipSuccess)
+      return e;
+    if ((e = launch_small_gemm<double>(p->Rt, p->Mk, c, c, c, p->Jm, nullptr, p->stream)) !=
+        hipSuccess)
+      return e;
+  }
   return launch_small_gemm<double>(p->Zq, p->Jm, r, c, c, p->Vt, nullptr, p->stream);
 }
 
@@ -958,7 +972,7 @@ int32_t rsvd_small_svd(rsvd_plan_t plan, const double* T, int64_t r, int32_t c, 
   if (r > plan->n_max || c > plan->l_max) return RSVD_ERR_SHAPE;
   if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
   RSVD_CHECK(reset(plan));
-  RSVD_CHECK(small_svd_unsorted(plan, T, r, c));
+  RSVD_CHECK(small_svd_unsorted(plan, T, r, c, true));
   RSVD_CHECK(launch_sort_sign_scatter<double>(plan->Su, c, plan->Vt, r, c, 1, plan->Uo, c, S,
                                               nullptr, 0, Vt, W, plan->stream));
   return RSVD_OK;

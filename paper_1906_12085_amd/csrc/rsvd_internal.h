@@ -142,10 +142,14 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
 
 // One-sided Jacobi SVD of a c x c FP64 matrix M (ld = c, c <= 96), in one
 // workgroup, on M itself or (transpose != 0) on M^T =: N:  N J = Uo diag(S)
-// with J orthogonal; writes Uo (c x c), S (c), J (c x c), all unsorted;
-// sweeps used and final off-diagonal measure to diag[2..3].
+// with J orthogonal; writes Uo (c x c) and S (c), unsorted, and into J
+// (c x c): J itself when acc_j != 0, else Uo diag(S)^-1 (zero columns where
+// S = 0) from which the caller forms the columns of J it needs (N = R^T:
+// J = R Uo diag(S)^-1, accurate for the leading values); sweeps used and the
+// final off-diagonal measure to diag[2..3].
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
-                                   double* J, double* diag, int32_t* status, hipStream_t s);
+                                   double* J, int acc_j, double* diag, int32_t* status,
+                                   hipStream_t s);
 
 // Eigen-decomposition of a symmetric n x n FP64 matrix by one-sided block
 // Jacobi on its columns: on entry X = G and J = I (column j at X + j*n);

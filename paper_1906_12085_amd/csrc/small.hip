@@ -210,33 +210,42 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   if (CT) CT[trans ? (int64_t)j * r + i : idx] = (T)s;
 }
 
-// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: columns of
-// M and of the accumulated rotations J held column-major in LDS.  Each group
-// of 16 lanes owns one column pair per step (round-robin ordering), keeps the
-// pair's entries in registers (6 rows per lane), reduces the three inner
-// products with group_sum, rotates and writes back.  With transpose != 0 the
-// kernel works on M^T (the rows of Min are its columns).
+// One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: the
+// columns of M held column-major in LDS.  Each group of 16 lanes owns one
+// column pair per step (round-robin ordering), keeps the pair's entries in
+// registers (6 rows per lane), reduces the three inner products with
+// group_sum, rotates and writes back.  With transpose != 0 the kernel works
+// on M^T (the rows of Min are its columns).  AccJ: the rotations are
+// accumulated in a second LDS matrix J and written out.  Otherwise they are
+// not: at convergence N J = Uo S with N = M or M^T, so J = N^-1 Uo S and, for
+// N = R^T, J = R Uo S^-1 -- the kernel writes Uo S^-1 (zero columns for zero
+// values) in J's place and the caller forms the columns of J it needs with
+// one small product.  Keeping J out of the rounds removes a third of their
+// loads, stores and FP64 operations; J's column j then carries an error of
+// order eps S_1 / S_j, so this form serves callers that use the leading
+// columns only.
 constexpr int kJsG = 16;
 constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
 constexpr int kJsMaxSweeps = 60;
 
+template <bool AccJ>
 __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     const double* __restrict__ Min, int c, int transpose, double* __restrict__ Uo,
     double* __restrict__ S, double* __restrict__ Jout, double* __restrict__ diag,
     int32_t* __restrict__ status) {
   extern __shared__ double sm[];
-  const int npad = c + (c & 1);
   double* Mc = sm;                   // column j at Mc + j*c
-  double* Jc = sm + (size_t)npad * c;
+  double* Jc = sm + (size_t)c * c;   // AccJ only
   __shared__ int rotated;
   __shared__ double offmax;
+  const int npad = c + (c & 1);
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int idx = tid; idx < c * c; idx += nthr) {
     const int i = idx / c, j = idx - i * c;   // Min row-major (i, j)
     const double v = Min[idx];
     if (transpose) Mc[i * c + j] = v;        // column i of M^T is row i of Min
     else Mc[j * c + i] = v;
-    Jc[j * c + i] = (i == j) ? 1.0 : 0.0;
+    if (AccJ) Jc[j * c + i] = (i == j) ? 1.0 : 0.0;
   }
   const int npairs = npad / 2;
   const int grp = tid / kJsG, gl = tid % kJsG;
@@ -256,7 +265,7 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
         double* xq = Mc + (size_t)q * c;
         double* jp = Jc + (size_t)p * c;
         double* jq = Jc + (size_t)q * c;
-        // all reads of the two columns and their J columns before any write
+        // all reads of the two columns (and their J columns) before any write
         double a[kJsRows], b[kJsRows], ja[kJsRows], jb[kJsRows];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -264,8 +273,10 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
           const int i = gl + kJsG * u;
           a[u] = (i < c) ? xp[i] : 0.0;
           b[u] = (i < c) ? xq[i] : 0.0;
-          ja[u] = (i < c) ? jp[i] : 0.0;
-          jb[u] = (i < c) ? jq[i] : 0.0;
+          if (AccJ) {
+            ja[u] = (i < c) ? jp[i] : 0.0;
+            jb[u] = (i < c) ? jq[i] : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < kJsRows; ++u) {
@@ -286,8 +297,10 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
             if (i < c) {
               xp[i] = cs * a[u] - sn * b[u];
               xq[i] = sn * a[u] + cs * b[u];
-              jp[i] = cs * ja[u] - sn * jb[u];
-              jq[i] = sn * ja[u] + cs * jb[u];
+              if (AccJ) {
+                jp[i] = cs * ja[u] - sn * jb[u];
+                jq[i] = sn * ja[u] + cs * jb[u];
+              }
             }
           }
           if (gl == 0) {
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     __syncthreads();
     if (done) { converged = true; break; }
   }
-  // singular values = column norms, Uo = normalised columns
+  // singular values = column norms, Uo = normalised columns, J or Uo S^-1
   for (int j = tid / 64; j < c; j += nthr / 64) {
     const int lane = tid & 63;
     double s2 = 0.0;
@@ -316,8 +329,9 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     if (lane == 0) S[j] = nrm;
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     for (int i = lane; i < c; i += 64) {
-      Uo[(size_t)i * c + j] = Mc[(size_t)j * c + i] * inv;
-      Jout[(size_t)i * c + j] = Jc[(size_t)j * c + i];
+      const double u = Mc[(size_t)j * c + i] * inv;
+      Uo[(size_t)i * c + j] = u;
+      Jout[(size_t)i * c + j] = AccJ ? Jc[(size_t)j * c + i] : u * inv;
     }
   }
   if (tid == 0) {
@@ -557,16 +571,22 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
 }
 
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
-                                   double* J, double* diag, int32_t* status, hipStream_t s) {
+                                   double* J, int acc_j, double* diag, int32_t* status,
+                                   hipStream_t s) {
   if (c < 1 || c > kJsG * kJsRows) return hipErrorInvalidValue;
   const int npad = c + (c & 1);
-  const size_t shmem = 2 * (size_t)npad * c * sizeof(double);
+  const size_t shmem = (acc_j ? 2 : 1) * (size_t)c * c * sizeof(double);
+  const void* fn = acc_j ? (const void*)k_jacobi_svd_small<true>
+                         : (const void*)k_jacobi_svd_small<false>;
   const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_svd_small,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi_svd_small, dim3(1), dim3(threads), shmem, s, M, c, transpose, Uo, S,
-                     J, diag, status);
+  if (acc_j)
+    hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1), dim3(threads), shmem, s, M, c,
+                       transpose, Uo, S, J, diag, status);
+  else
+    hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1), dim3(threads), shmem, s, M, c,
+                       transpose, Uo, S, J, diag, status);
   return hipGetLastError();
 }
 

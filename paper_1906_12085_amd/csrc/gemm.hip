@@ -496,14 +496,18 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 // iterations, Sec. 3.1.2 steps 2, 3 and 5), fp32 on 16x16x4 matrix cores
 // (exact tiles for any c that is a multiple of 16).
 //
-// Y = A Xt^T (Xt is c x n): block = 256 rows of A x all c columns, 4 waves of
-// 64 rows (4 x NT tiles); chunks of kTK = 16 along k of both operands staged
-// row-major in LDS (two buffers, small enough for two blocks per CU).  The next chunk's buffer loads are issued
+// Y = A Xt^T (Xt is c x n): block = 128 rows of A x all c columns, 4 waves of
+// 32 rows (2 x NT tiles); chunks of kTK = 32 along k of both operands staged
+// row-major in LDS (two buffers, small enough for two blocks per CU).  A
+// chunk is a whole 128-byte segment of each row: with 16-k chunks each row's
+// cache line was consumed in two halves a chunk apart, and at n = 512 (rows
+// 2 KB apart) the half left for the next chunk was often evicted and fetched
+// again (1.5x the bytes of A).  The next chunk's buffer loads are issued
 // before the multiply, its LDS writes interleaved into the last slab, the
 // FP64 sum of squares of A (Eq. sumeigen) taken from the loaded chunk.
 // Requires n % 4 == 0 and 16-byte rows (the descriptor ends at the last
 // valid row; a last chunk that ends past n is zeroed there on its way to LDS).
-constexpr int kTM = 256, kTK = 16, kTLD = kTK + 4;
+constexpr int kTM = 128, kTK = 32, kTLD = kTK + 4;
 constexpr int kTQ = kTK / 4, kTUA = kTM * kTQ / 256;   // k-quads per row, A loads per thread
 
 template <int NT>
@@ -581,49 +585,52 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
       }
     }
   };
-  f32x4 acc[4][NT];
+  constexpr int RT = kTM / 64;                 // 16-row tiles per wave
+  f32x4 acc[RT][NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // slab of 16 k: lane (lr, g) reads k = 16 s + 4 g .. +3 with one 16-byte
   // load; step t contracts over k = 16 s + 4 g + t on both operands
   auto slab = [&](int buf, int s) {
-    f32x4 af[4], bf[NT];
+    f32x4 af[RT], bf[NT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][(wave * 64 + 16 * i + lr) * kTLD + 16 * s + 4 * g]);
+    for (int i = 0; i < RT; ++i)
+      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][(wave * 16 * RT + 16 * i + lr) * kTLD + 16 * s + 4 * g]);
 #pragma unroll
     for (int j = 0; j < NT; ++j)
       bf[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][(16 * j + lr) * kTLD + 16 * s + 4 * g]);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[i][t], bf[j][t], acc[i][j]);
   };
   load(0);
   store(0, 0);
   __syncthreads();
-  static_assert(kTK == 16, "one slab per chunk");
+  static_assert(kTK == 32, "two slabs per chunk");
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nch;
     load(more ? ch + 1 : ch);                  // the last prefetch is a harmless repeat
     __builtin_amdgcn_sched_barrier(0);
     slab(buf, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    slab(buf, 1);
     if (more) store(buf ^ 1, ch + 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const int col = 16 * j + lr;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + wave * 64 + 16 * i + Mfma<float>::row(lane, e);
+        const int64_t row = row0 + wave * 16 * RT + 16 * i + Mfma<float>::row(lane, e);
         if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
       }
     }
@@ -1247,9 +1254,10 @@ hipError_t launch_syrk_f32(const float* A, int64_t m, int64_t n, int64_t lda, do
   if (m <= 0 || n <= 0) return hipSuccess;
   const int ntile = (int)((n + kSyT - 1) / kSyT);
   const int npair = ntile * (ntile + 1) / 2;
-  // about three blocks per CU in all (256 CUs), splits of whole chunks, and
-  // the partial tiles within the scratch capacity
-  int64_t nsplit = (3 * 256) / npair;
+  // one resident wave of blocks (two per CU on 256 CUs: every block of a row
+  // split runs at the same time as the others, so they share A in L2),
+  // splits of whole chunks, and the partial tiles within the scratch capacity
+  int64_t nsplit = (2 * 256) / npair;
   const int64_t by_rows = (m + kSyK - 1) / kSyK;
   if (nsplit > by_rows) nsplit = by_rows;
   const int64_t cap = p_cap / ((int64_t)npair * kSyT * kSyT);

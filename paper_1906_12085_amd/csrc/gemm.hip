@@ -171,9 +171,10 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
 // u_i = A v_i / s_i for every i, Sec. 3.1.3), with the right factor given
 // transposed (Xt is c x n, row-major) so that both operands are read along
 // k.  Two-level tiling on the full-rate 32x32x2 fp32 matrix cores: block
-// tile kWM x kWN = 128 x 256 (4 waves in 2 x 2, each 64 x 128 = 2 x 4 tiles
-// of 32 x 32); chunks of kWK = 32 along k of both operands are staged in LDS
-// (row-major, padded rows) in two buffers.  Chunk i+1 is loaded into
+// tile kWM x kWN = 256 x 256 (8 waves in 4 x 2, each 64 x 128 = 2 x 4 tiles
+// of 32 x 32: two waves per SIMD, one block per CU in 144 KB of LDS); chunks
+// of kWK = 32 along k of both operands are staged in LDS (row-major, padded
+// rows) in two buffers.  Chunk i+1 is loaded into
 // registers before chunk i is multiplied and written to LDS during its last
 // slab; one barrier per chunk.  Blocks are numbered so that the column tiles
 // of a row panel run back to back on the same XCD (block b runs on XCD
@@ -183,7 +184,8 @@ __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
 // per-block descriptor whose size ends at the last valid row, so rows past m
 // (or past c) read as zero; the chunk advance is a scalar offset.  General
 // path: clamped addresses and selects.
-constexpr int kWM = 128, kWN = 256, kWK = 32, kWLD = kWK + 4;
+constexpr int kWM = 256, kWN = 256, kWK = 32, kWLD = kWK + 4, kWT = 512;
+constexpr int kWUA = kWM * (kWK / 4) / kWT, kWUX = kWN * (kWK / 4) / kWT;   // loads per thread
 constexpr int kBufDword3 = 0x00020000;        // raw 32-bit buffer (gfx9 family)
 
 template <bool FAST>
@@ -207,48 +209,49 @@ __device__ __forceinline__ void nt_wide_body(
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
   // thread's share of a chunk: A rows (idx >> 3) and Xt rows (idx >> 3),
-  // k-quad idx & 7; eight lanes cover the 128 bytes of one row
+  // k-quad idx & 7 (idx = tid + u kWT); eight lanes cover the 128 bytes of
+  // one row
   const __amdgpu_buffer_rsrc_t ra_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(A + arow0 * lda), 0, FAST ? (int)(arows * lda * 4) : 0, kBufDword3);
   const __amdgpu_buffer_rsrc_t rx_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(Xt + (int64_t)bcol0 * ldxt), 0, FAST ? (int)(bcols * ldxt * 4) : 0,
       kBufDword3);
-  int voa[4], vox[8];
+  int voa[kWUA], vox[kWUX];
   if (FAST) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + u * 256;
+    for (int u = 0; u < kWUA; ++u) {
+      const int idx = tid + u * kWT;
       voa[u] = (int)(((idx >> 3) * lda + 4 * (idx & 7)) * 4);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int idx = tid + u * 256;
+    for (int u = 0; u < kWUX; ++u) {
+      const int idx = tid + u * kWT;
       vox[u] = (int)(((idx >> 3) * ldxt + 4 * (idx & 7)) * 4);
     }
   }
-  f32x4 ra[4], rx[8];
+  f32x4 ra[kWUA], rx[kWUX];
   auto load = [&](int ch) {
     const int64_t k0 = (int64_t)ch * kWK;
     if (FAST) {
       const int so = (int)(k0 * 4);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kWUA; ++u)
         ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra_rsrc, voa[u], so, 0));
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < kWUX; ++u)
         rx[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rx_rsrc, vox[u], so, 0));
     } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int idx = tid + u * 256;
+      for (int u = 0; u < kWUA; ++u) {
+        const int idx = tid + u * kWT;
         const int64_t gr = arow0 + (idx >> 3), k = k0 + 4 * (idx & 7);
         const float* rowp = A + (gr < m ? gr : m - 1) * lda;
 #pragma unroll
         for (int i = 0; i < 4; ++i) ra[u][i] = rowp[k + i < n ? k + i : n - 1];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int idx = tid + u * 256;
+      for (int u = 0; u < kWUX; ++u) {
+        const int idx = tid + u * kWT;
         const int64_t gc = bcol0 + (idx >> 3), k = k0 + 4 * (idx & 7);
         const float* rowp = Xt + (gc < c ? gc : c - 1) * ldxt;
 #pragma unroll
@@ -259,8 +262,8 @@ __device__ __forceinline__ void nt_wide_body(
   auto store = [&](int ch, int buf) {
     const int64_t k0 = (int64_t)ch * kWK;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + u * 256, row = idx >> 3, kq = idx & 7;
+    for (int u = 0; u < kWUA; ++u) {
+      const int idx = tid + u * kWT, row = idx >> 3, kq = idx & 7;
       f32x4 v = ra[u];
       if (!FAST) {
 #pragma unroll
@@ -269,8 +272,8 @@ __device__ __forceinline__ void nt_wide_body(
       *reinterpret_cast<f32x4*>(&As[buf][row * kWLD + 4 * kq]) = v;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int idx = tid + u * 256, col = idx >> 3, kq = idx & 7;
+    for (int u = 0; u < kWUX; ++u) {
+      const int idx = tid + u * kWT, col = idx >> 3, kq = idx & 7;
       f32x4 v = rx[u];
       if (!FAST) {
 #pragma unroll
@@ -313,14 +316,13 @@ __device__ __forceinline__ void nt_wide_body(
     __builtin_amdgcn_sched_barrier(0);
     slab(buf, 3);
     store(nx, buf ^ 1);                       // the other buffer: free since the last barrier
-    // last slab: its 6 LDS reads, then 2 matrix-core steps per LDS write
+    // last slab: its 6 LDS reads, then 4 matrix-core steps per LDS write
     __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
-    for (int w = 0; w < 12; ++w) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    for (int w = 0; w < kWUA + kWUX; ++w) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
       __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -336,7 +338,7 @@ __device__ __forceinline__ void nt_wide_body(
     }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_nt_wide(
+__global__ __launch_bounds__(kWT) void k_gemm_nt_wide(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
     int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, int64_t ntiles, int ncb,
     int64_t per_xcd, int fast) {
@@ -1300,7 +1302,7 @@ hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda
                     (lda % 4 == 0) && (reinterpret_cast<uintptr_t>(Xt) % 16 == 0) &&
                     (ldxt % 4 == 0) && ((int64_t)kWM * lda * 4 < (1LL << 31)) &&
                     ((int64_t)kWN * ldxt * 4 < (1LL << 31));
-  hipLaunchKernelGGL(k_gemm_nt_wide, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, A, m, n, lda,
+  hipLaunchKernelGGL(k_gemm_nt_wide, dim3((unsigned)(8 * per_xcd)), dim3(kWT), 0, s, A, m, n, lda,
                      Xt, ldxt, c, Y, ldy, ntiles, ncb, per_xcd, fast ? 1 : 0);
   return hipGetLastError();
 }

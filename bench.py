@@ -86,26 +86,21 @@ KERNEL_INFO = {
 }
 
 
-# HBM bytes per launch at the 1e6 x 512 fp32 step, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
-# plain 1 GiB device copy (FETCH_SIZE 0.5 x the bytes read, WRITE_SIZE 1.0 x
-# the bytes written).  Each figure holds only for the kernel source it was
-# taken on (first 16 hex digits of the file's SHA-256); otherwise it is null.
 # Measured HBM bytes per launch at the 1e6 x 512, l = 80 workload (two
 # rocprofv3 counter passes, FETCH_SIZE and WRITE_SIZE, each scaled by what the
 # counter reads for a plain copy of known size), tied to the source text of
 # the kernel that was measured: a changed kernel reports null until measured
 # again.
 TRAFFIC = {
-    "eigensolver": (3.2953e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
-    "pass_nn": (2.4141e+09, "gemm.hip", "k_gemm_nt_tall", "8139e2dc9f221a15"),
+    "eigensolver": (3.2841e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
+    "pass_nn": (2.3910e+09, "gemm.hip", "k_gemm_nt_tall", "5458f34d8ffce76b"),
     "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "03561cb8faeda271"),
-    "syrk": (2.4484e+09, "gemm.hip", "k_syrk_f32", "0b6665341b4d3f9f"),
-    "nn_wide": (4.6222e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "49c8ad4e5ec10a94"),
-    "pass_nn_bf16": (1.5152e+09, "lowp.hip", "k_gemm_nt_bf16", "2f86dbf290f89925"),
-    "pass_tn_bf16": (1.4357e+09, "lowp.hip", "k_gemm_tn_bf16", "7aab2e1381d2f69f"),
-    "pass_nn_fp8": (None, "lowp.hip", "k_gemm_nt_bf16", None),
-    "pass_tn_fp8": (None, "lowp.hip", "k_gemm_tn_bf16", None),
+    "syrk": (3.6526e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
+    "nn_wide": (4.4542e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
+    "pass_nn_bf16": (1.5303e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "pass_tn_bf16": (1.4355e+09, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
+    "pass_nn_fp8": (8.4552e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "pass_tn_fp8": (9.1822e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 

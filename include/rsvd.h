@@ -108,7 +108,9 @@ int32_t rsvd_plan_status(rsvd_plan_t plan);
 /* Synchronise and copy diagnostics of the last solve to host memory `out`
  * (up to `count` doubles): [0] ||A||_F^2, [1] captured fraction
  * sum_{i<=K} s_i^2 / ||A||_F^2, [2] Jacobi sweeps of the small SVD or of the
- * eigensolver, [3] largest off-diagonal measure left by that Jacobi, [4] K.
+ * eigensolver, [3] largest off-diagonal measure left by that Jacobi, [4] K,
+ * [5] 1 when the small SVD of a solve was repeated with its rotations
+ * accumulated (its values spanning more than six decades), else 0.
  * Returns the number of values written. */
 int32_t rsvd_plan_diag(rsvd_plan_t plan, double* out, int32_t count);
 

@@ -336,8 +336,10 @@ hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, doubl
 // accumulated in the rotations when only leading columns are used
 // (all_columns = false): it is then R Uo diag(Su)^-1, whose column for a
 // value Su_j carries a rounding error of order eps Su_1 / Su_j -- small for
-// the k largest values a solve keeps.
-// Leaves V~ unsorted in p->Vt, the values in p->Su and W in p->Uo.
+// the k largest values a solve keeps.  When the values span more than six
+// decades the kernel flags it (diag[5] = 1) and a second, otherwise empty
+// launch repeats the decomposition with J accumulated, replacing Uo, Su and
+// J.  Leaves V~ unsorted in p->Vt, the values in p->Su and W in p->Uo.
 hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c,
                               bool all_columns = false) {
   hipError_t e;
@@ -346,14 +348,18 @@ hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c
     return e;
   if (all_columns) {
     if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, 1, p->diag, p->status,
-                                     p->stream)) != hipSuccess)
+                                     nullptr, p->stream)) != hipSuccess)
       return e;
   } else {
+    double* redo = p->diag + 5;
     if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Mk, 0, p->diag, p->status,
-                                     p->stream)) != hipSuccess)
+                                     redo, p->stream)) != hipSuccess)
       return e;
     if ((e = launch_small_gemm<double>(p->Rt, p->Mk, c, c, c, p->Jm, nullptr, p->stream)) !=
         hipSuccess)
+      return e;
+    if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, 1, p->diag, p->status,
+                                     redo, p->stream)) != hipSuccess)
       return e;
   }
   return launch_small_gemm<double>(p->Zq, p->Jm, r, c, c, p->Vt, nullptr, p->stream);

@@ -146,10 +146,13 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
 // (c x c): J itself when acc_j != 0, else Uo diag(S)^-1 (zero columns where
 // S = 0) from which the caller forms the columns of J it needs (N = R^T:
 // J = R Uo diag(S)^-1, accurate for the leading values); sweeps used and the
-// final off-diagonal measure to diag[2..3].
+// final off-diagonal measure to diag[2..3].  redo (device word, may be null):
+// with acc_j = 0 it receives 1.0 when min S <= 1e-6 max S (J from Uo S^-1
+// too inexact), else 0.0; with acc_j != 0 the launch does nothing unless
+// *redo is nonzero (null: unconditional).
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
                                    double* J, int acc_j, double* diag, int32_t* status,
-                                   hipStream_t s);
+                                   double* redo, hipStream_t s);
 
 // Eigen-decomposition of a symmetric n x n FP64 matrix by one-sided block
 // Jacobi on its columns: on entry X = G and J = I (column j at X + j*n);

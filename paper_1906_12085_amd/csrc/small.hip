@@ -223,21 +223,27 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
 // one small product.  Keeping J out of the rounds removes a third of their
 // loads, stores and FP64 operations; J's column j then carries an error of
 // order eps S_1 / S_j, so this form serves callers that use the leading
-// columns only.
+// columns only, and it sets *redo when the values span more than
+// 1 / kJsRedoRatio (or one is zero): a second launch with AccJ and the same
+// redo word then repeats the decomposition with J accumulated (and returns
+// at once when *redo is 0).
 constexpr int kJsG = 16;
 constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
 constexpr int kJsMaxSweeps = 60;
+constexpr double kJsRedoRatio = 1e-6;
 
 template <bool AccJ>
 __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     const double* __restrict__ Min, int c, int transpose, double* __restrict__ Uo,
     double* __restrict__ S, double* __restrict__ Jout, double* __restrict__ diag,
-    int32_t* __restrict__ status) {
+    int32_t* __restrict__ status, double* __restrict__ redo) {
+  if (AccJ && redo && *redo == 0.0) return;  // uniform: the first pass needed no J
   extern __shared__ double sm[];
   double* Mc = sm;                   // column j at Mc + j*c
   double* Jc = sm + (size_t)c * c;   // AccJ only
   __shared__ int rotated;
   __shared__ double offmax;
+  __shared__ double snrm[kJsG * kJsRows];
   const int npad = c + (c & 1);
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int idx = tid; idx < c * c; idx += nthr) {
@@ -326,7 +332,10 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     for (int i = lane; i < c; i += 64) s2 += Mc[(size_t)j * c + i] * Mc[(size_t)j * c + i];
     s2 = group_sum<64>(s2);
     const double nrm = sqrt(s2);
-    if (lane == 0) S[j] = nrm;
+    if (lane == 0) {
+      S[j] = nrm;
+      snrm[j] = nrm;
+    }
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     for (int i = lane; i < c; i += 64) {
       const double u = Mc[(size_t)j * c + i] * inv;
@@ -334,7 +343,17 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
       Jout[(size_t)i * c + j] = AccJ ? Jc[(size_t)j * c + i] : u * inv;
     }
   }
+  __syncthreads();
   if (tid == 0) {
+    if (!AccJ && redo) {
+      double mx = 0.0, mn = snrm[0];
+      for (int j = 0; j < c; ++j) {
+        mx = fmax(mx, snrm[j]);
+        mn = fmin(mn, snrm[j]);
+      }
+      const bool again = !(mn > kJsRedoRatio * mx);
+      *redo = again ? 1.0 : 0.0;
+    }
     diag[2] = (double)sweep;
     diag[3] = last_off;
     if (!converged) set_error(status, RSVD_ERR_NOCONV);
@@ -572,7 +591,7 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
 
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
                                    double* J, int acc_j, double* diag, int32_t* status,
-                                   hipStream_t s) {
+                                   double* redo, hipStream_t s) {
   if (c < 1 || c > kJsG * kJsRows) return hipErrorInvalidValue;
   const int npad = c + (c & 1);
   const size_t shmem = (acc_j ? 2 : 1) * (size_t)c * c * sizeof(double);
@@ -583,10 +602,10 @@ hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double
   if (e != hipSuccess) return e;
   if (acc_j)
     hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status);
+                       transpose, Uo, S, J, diag, status, redo);
   else
     hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status);
+                       transpose, Uo, S, J, diag, status, redo);
   return hipGetLastError();
 }
 

@@ -160,3 +160,24 @@ def test_deterministic(plans, dt):
     r1 = plans[dt].solve(A, 12, 8, 2, 0.95)
     r2 = plans[dt].solve(A, 12, 8, 2, 0.95)
     assert torch.equal(r1.U, r2.U) and torch.equal(r1.V, r2.V) and torch.equal(r1.S, r2.S)
+
+
+def test_small_svd_wide_value_range(plans):
+    # The solves form the small SVD's right factor from Uo S^-1 unless the
+    # values of T span more than six decades; then the decomposition is
+    # repeated with the rotations accumulated (diag[5] = 1).  Both sides of
+    # that switch are held to the FP64 parity gates.  (A spread of T past
+    # 1e6 means the same of the sketch Y, which only the FP64 path's
+    # CholeskyQR2 orthonormalises.)
+    dt = torch.float64
+    plan = plans[dt]
+    m, n, k, p, q = 3000, 64, 12, 12, 0
+    rng = np.random.default_rng(71)
+    for decades, redo in ((3.0, 0.0), (7.0, 1.0)):
+        announce(f"rsvd small-SVD values over {decades:g} decades {dt}")
+        sig = np.concatenate([np.logspace(0, -decades, k + p),
+                              10.0 ** -decades * np.logspace(-0.1, -1, n - k - p)])
+        A0 = synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T
+        res, ref, _ = run_pair(plan, A0, dt, k, p, q, 0.999, 13)
+        assert plan.diag()[5] == redo
+        check_parity(res, ref, dt, k)

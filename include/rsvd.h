@@ -287,6 +287,71 @@ int32_t rsvd_small_svd(rsvd_plan_t plan, const double* T, int64_t r, int32_t c,
  * sized for the A^T A route. */
 int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, double* V);
 
+/* ------------------------------------------------------------- batches --
+ * Many independent Randomized PCA problems of different shapes (Sec. 3.1.2
+ * for each), solved side by side on one GPU.  A batch owns `nslots` slots, a
+ * plan and a stream each (every plan sized m_max x n_max x l_max, all with
+ * the same seed, so an instance's G, and its results, do not depend on the
+ * slot it runs on: they equal rsvd_solve on a plan of the same sizes and
+ * seed, bit for bit).  Instances go to slots largest first (m n l work), each
+ * to the slot with the least work so far; the slot streams fork from and
+ * join back into the caller's stream, so a batch is ordered like one kernel
+ * on that stream, and the whole fork-join can be captured into a HIP graph
+ * once and replayed (rsvd_batch_graph_*) for repeated batches of the same
+ * shapes and pointers. */
+typedef struct rsvd_batch_s* rsvd_batch_t;
+typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
+
+/* One problem of a batch: arguments as rsvd_solve (device pointers A, U, S,
+ * V, K), plus `status` (1 int32, device) that receives the instance's status
+ * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV). */
+typedef struct {
+  const void* A;
+  int64_t m, n, lda;
+  int32_t k, p, q;
+  double t;
+  void* U;
+  int64_t ldu;
+  double* S;
+  void* V;
+  int64_t ldv;
+  int32_t* K;
+  int32_t* status;
+} rsvd_instance;
+
+/* Create a batch of nslots (1..64) slots for RSVD_F64 or RSVD_F32 problems
+ * up to m_max x n_max with k + p <= l_max (limits as rsvd_plan_create).
+ * Each slot's stream is created by the batch (default priority).  Errors as
+ * rsvd_plan_create, RSVD_ERR_ARG for nslots out of range or another dtype. */
+int32_t rsvd_batch_create(rsvd_batch_t* batch, int32_t nslots, int64_t m_max, int64_t n_max,
+                          int32_t l_max, int32_t dtype, uint64_t seed);
+
+/* Synchronise and free the slots' plans and streams. NULL is a no-op. */
+int32_t rsvd_batch_destroy(rsvd_batch_t batch);
+
+/* Solve `count` instances (host array, read during the call only), ordered
+ * on `stream` (hipStream_t, NULL = the null stream) as one unit: work
+ * queued on it earlier completes first, work queued later waits for every
+ * instance.  All instances are validated before anything is launched: the
+ * first invalid one returns RSVD_ERR_ARG / RSVD_ERR_SHAPE as rsvd_solve
+ * would (also for a NULL status pointer) and nothing runs. */
+int32_t rsvd_batch_solve(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                         void* stream);
+
+/* Capture rsvd_batch_solve(batch, inst, count, stream) into an executable
+ * HIP graph (nothing runs yet); every launch of it repeats the same solves
+ * on the same buffers.  The graph uses the batch's slots: one batch, one
+ * graph in flight at a time.  Errors as rsvd_batch_solve, RSVD_ERR_DEVICE
+ * when capture or instantiation fails. */
+int32_t rsvd_batch_graph_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                void* stream, rsvd_batch_graph_t* graph);
+
+/* Launch a captured batch on `stream`. */
+int32_t rsvd_batch_graph_launch(rsvd_batch_graph_t graph, void* stream);
+
+/* Free a captured batch (synchronises nothing; NULL is a no-op). */
+int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
+
 #ifdef __cplusplus
 }
 #endif

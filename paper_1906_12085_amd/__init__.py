@@ -36,7 +36,18 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
            "rsvd_gaussian_fill", "rsvd_gemm_nn", "rsvd_gemm_tn", "rsvd_cholqr2",
            "rsvd_small_svd", "rsvd_sym_eig", "rsvd_plan_kernel_times", "rsvd_solve_bf16",
-           "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8", "rsvd_solve_krylov"]
+           "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8", "rsvd_solve_krylov",
+           "rsvd_batch_create", "rsvd_batch_destroy", "rsvd_batch_solve",
+           "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy"]
+
+
+class RsvdInstance(ctypes.Structure):
+    """One problem of a batch (the C struct rsvd_instance)."""
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("k", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class RSVDError(RuntimeError):
@@ -70,6 +81,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    vp, i64, vp, vp, i64, vp]),
         "rsvd_solve_krylov": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                     vp, i64, vp, vp, i64, vp]),
+        "rsvd_batch_create": (i32, [ctypes.POINTER(vp), i32, i64, i64, i32, i32, u64]),
+        "rsvd_batch_destroy": (i32, [vp]),
+        "rsvd_batch_solve": (i32, [vp, ctypes.POINTER(RsvdInstance), i32, vp]),
+        "rsvd_batch_graph_create": (i32, [vp, ctypes.POINTER(RsvdInstance), i32, vp,
+                                          ctypes.POINTER(vp)]),
+        "rsvd_batch_graph_launch": (i32, [vp, vp]),
+        "rsvd_batch_graph_destroy": (i32, [vp]),
         "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
         "rsvd_gaussian_fill": (i32, [u64, i64, i64, vp, vp]),
         "rsvd_gemm_nn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp, i64, vp, vp]),
@@ -372,3 +390,86 @@ class Plan:
             return Result(U, S, V, K, 0)
         st = self.status()
         return Result(U, S, V, int(K.item()), st)
+
+
+class Batch:
+    """Many Randomized PCA problems of different shapes on `nslots` slots
+    (rsvd_batch_*).  `problems` is a list of (A, k, p, q, t); outputs are
+    allocated per problem.  solve() runs them now; graph() captures the same
+    solves (same A and output tensors) into a replayable HIP graph."""
+
+    def __init__(self, nslots: int, m_max: int, n_max: int, l_max: int, dtype, seed: int = 0):
+        import torch
+        self.torch = torch
+        self.dtype = dtype
+        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[dtype]
+        h = ctypes.c_void_p()
+        _check(load_library().rsvd_batch_create(ctypes.byref(h), nslots, m_max, n_max, l_max,
+                                                code, seed), "rsvd_batch_create")
+        self.handle = h.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if self.handle:
+            _check(load_library().rsvd_batch_destroy(self.handle), "rsvd_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, problems):
+        """Output tensors and the C instance array for `problems`."""
+        torch = self.torch
+        outs, arr = [], (RsvdInstance * len(problems))()
+        for i, (A, k, p, q, t) in enumerate(problems):
+            m, n = A.shape
+            o = dict(U=torch.empty((m, k), dtype=self.dtype, device=self.device),
+                     V=torch.empty((n, k), dtype=self.dtype, device=self.device),
+                     S=torch.empty((k,), dtype=torch.float64, device=self.device),
+                     K=torch.empty((1,), dtype=torch.int32, device=self.device),
+                     status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
+            arr[i] = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t),
+                                  o["U"].data_ptr(), _ld(o["U"]), o["S"].data_ptr(),
+                                  o["V"].data_ptr(), _ld(o["V"]), o["K"].data_ptr(),
+                                  o["status"].data_ptr())
+            outs.append(o)
+        return outs, arr
+
+    def solve(self, problems, stream=None, prepared=None):
+        outs, arr = prepared if prepared is not None else self.prepare(problems)
+        _check(load_library().rsvd_batch_solve(self.handle, arr, len(arr), _stream_ptr(stream)),
+               "rsvd_batch_solve")
+        return outs
+
+    def graph(self, problems, prepared=None):
+        outs, arr = prepared if prepared is not None else self.prepare(problems)
+        g = ctypes.c_void_p()
+        _check(load_library().rsvd_batch_graph_create(self.handle, arr, len(arr), None,
+                                                      ctypes.byref(g)), "rsvd_batch_graph_create")
+        return BatchGraph(g.value, outs)
+
+
+class BatchGraph:
+    """A captured batch; launch() replays it on a stream."""
+
+    def __init__(self, handle, outs):
+        self.handle, self.outs = handle, outs
+
+    def launch(self, stream=None):
+        _check(load_library().rsvd_batch_graph_launch(self.handle, _stream_ptr(stream)),
+               "rsvd_batch_graph_launch")
+        return self.outs
+
+    def close(self):
+        if self.handle:
+            _check(load_library().rsvd_batch_graph_destroy(self.handle), "rsvd_batch_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,9 +6,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
-
 #include <type_traits>
+#include <vector>
 
 #include "rsvd_internal.h"
 
@@ -1000,6 +1001,214 @@ int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, 
   RSVD_CHECK(launch_sort_sign_scatter<double>(plan->lam, (int)n, plan->Je, n, 1, n, nullptr,
                                               (int)n, lam, nullptr, 0, V, nullptr, s));
   return RSVD_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches: instances of different shapes on several slots (a plan and a
+// stream each), forked from and joined back into the caller's stream.
+struct rsvd_batch_s {
+  int device = 0;
+  int dtype = RSVD_F32;
+  std::vector<rsvd_plan_s*> plan;
+  std::vector<hipStream_t> stream;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+  hipStream_t cap = nullptr;   // stream the graph captures are recorded on
+};
+
+struct rsvd_batch_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxSlots = 64;
+
+__global__ void k_status_take(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+void batch_free(rsvd_batch_s* b) {
+  (void)hipSetDevice(b->device);
+  for (rsvd_plan_s* p : b->plan) rsvd_plan_destroy(p);   // synchronises its stream
+  for (hipStream_t s : b->stream) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+// Validate every instance, then give each a slot: largest work (m n l)
+// first, each to the slot with the least work so far (lowest index on ties).
+int32_t batch_schedule(rsvd_batch_s* b, const rsvd_instance* in, int32_t count,
+                       std::vector<int>& order, std::vector<int>& slot) {
+  if (count < 0 || (count > 0 && !in)) return RSVD_ERR_ARG;
+  std::vector<double> work(count);
+  for (int i = 0; i < count; ++i) {
+    const rsvd_instance& x = in[i];
+    const int32_t rc = check_rsvd(b->plan[0], x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, x.U,
+                                  x.ldu, x.S, x.V, x.ldv, x.K);
+    if (rc != RSVD_OK) return rc;
+    if (!x.status) return RSVD_ERR_ARG;
+    const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+    work[i] = (double)x.m * (double)x.n * (double)l;
+  }
+  order.resize(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<double> load(b->plan.size(), 0.0);
+  slot.assign(count, 0);
+  for (int i : order) {
+    int best = 0;
+    for (int s = 1; s < (int)load.size(); ++s)
+      if (load[s] < load[best]) best = s;
+    slot[i] = best;
+    load[best] += work[i];
+  }
+  return RSVD_OK;
+}
+
+template <typename T>
+int32_t batch_launch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hipStream_t st) {
+  std::vector<int> order, slot;
+  int32_t rc = batch_schedule(b, in, count, order, slot);
+  if (rc != RSVD_OK || count == 0) return rc;
+  std::vector<char> used(b->plan.size(), 0);
+  for (int i = 0; i < count; ++i) used[slot[i]] = 1;
+  RSVD_CHECK(hipEventRecord(b->fork, st));
+  for (size_t s = 0; s < used.size(); ++s)
+    if (used[s]) RSVD_CHECK(hipStreamWaitEvent(b->stream[s], b->fork, 0));
+  for (int i : order) {
+    const rsvd_instance& x = in[i];
+    rsvd_plan_s* p = b->plan[slot[i]];
+    rc = rsvd_run<T>(p, (const T*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr, (T*)x.U,
+                     x.ldu, x.S, (T*)x.V, x.ldv, x.K);
+    if (rc != RSVD_OK) return rc;
+    hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, x.status);
+    RSVD_CHECK(hipGetLastError());
+  }
+  for (size_t s = 0; s < used.size(); ++s)
+    if (used[s]) {
+      RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
+      RSVD_CHECK(hipStreamWaitEvent(st, b->done[s], 0));
+    }
+  return RSVD_OK;
+}
+
+int32_t batch_dispatch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hipStream_t st) {
+  if (b->dtype == RSVD_F64) return batch_launch<double>(b, in, count, st);
+  return batch_launch<float>(b, in, count, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsvd_batch_create(rsvd_batch_t* batch, int32_t nslots, int64_t m_max, int64_t n_max,
+                          int32_t l_max, int32_t dtype, uint64_t seed) {
+  if (!batch) return RSVD_ERR_ARG;
+  *batch = nullptr;
+  if (nslots < 1 || nslots > kMaxSlots) return RSVD_ERR_ARG;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
+  rsvd_batch_s* b = new (std::nothrow) rsvd_batch_s();
+  if (!b) return RSVD_ERR_NOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) { delete b; return RSVD_ERR_DEVICE; }
+  b->dtype = dtype;
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    batch_free(b);
+    return RSVD_ERR_DEVICE;
+  }
+  for (int s = 0; s < nslots; ++s) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      batch_free(b);
+      return RSVD_ERR_DEVICE;
+    }
+    b->stream.push_back(st);
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return RSVD_ERR_DEVICE;
+    }
+    b->done.push_back(ev);
+    rsvd_plan_t p = nullptr;
+    const int32_t rc = rsvd_plan_create(&p, m_max, n_max, l_max, dtype, 0, seed, st);
+    if (rc != RSVD_OK) {
+      batch_free(b);
+      return rc;
+    }
+    b->plan.push_back(p);
+  }
+  *batch = b;
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_destroy(rsvd_batch_t batch) {
+  if (!batch) return RSVD_OK;
+  batch_free(batch);
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_solve(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                         void* stream) {
+  if (!batch) return RSVD_ERR_ARG;
+  if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  return batch_dispatch(batch, inst, count, (hipStream_t)stream);
+}
+
+int32_t rsvd_batch_graph_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                void* stream, rsvd_batch_graph_t* graph) {
+  (void)stream;   // a graph is launched on any stream; it is captured on the batch's own
+  if (!batch || !graph) return RSVD_ERR_ARG;
+  *graph = nullptr;
+  if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  {  // validate before capturing anything
+    std::vector<int> order, slot;
+    const int32_t rc = batch_schedule(batch, inst, count, order, slot);
+    if (rc != RSVD_OK) return rc;
+  }
+  if (hipStreamBeginCapture(batch->cap, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return RSVD_ERR_DEVICE;
+  const int32_t rc = batch_dispatch(batch, inst, count, batch->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(batch->cap, &g);
+  if (rc != RSVD_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc != RSVD_OK ? rc : RSVD_ERR_DEVICE;
+  }
+  rsvd_batch_graph_s* h = new (std::nothrow) rsvd_batch_graph_s();
+  if (!h) {
+    (void)hipGraphDestroy(g);
+    return RSVD_ERR_NOMEM;
+  }
+  h->graph = g;
+  if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete h;
+    return RSVD_ERR_DEVICE;
+  }
+  *graph = h;
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_graph_launch(rsvd_batch_graph_t graph, void* stream) {
+  if (!graph) return RSVD_ERR_ARG;
+  return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? RSVD_OK
+                                                                      : RSVD_ERR_DEVICE;
+}
+
+int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph) {
+  if (!graph) return RSVD_OK;
+  int32_t rc = RSVD_OK;
+  if (graph->exec && hipGraphExecDestroy(graph->exec) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  if (graph->graph && hipGraphDestroy(graph->graph) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  delete graph;
+  return rc;
 }
 
 }  // extern "C"

@@ -60,6 +60,11 @@ def test_plan_create_validates_before_device_calls(lib):
     assert f(ctypes.byref(h), 5000, 200, 32, 2, 1, 0, None) == -1         # bf16 plan: no A^T A route
     assert f(ctypes.byref(h), 5000, 200, 32, 3, 1, 0, None) == -1         # fp8 plan: no A^T A route
     assert f(ctypes.byref(h), 5000, 200, 32, 4, 0, 0, None) == -1         # unknown dtype
+    b = lib.rsvd_batch_create
+    assert b(None, 2, 1000, 100, 16, 1, 0) == -1                          # batch NULL
+    assert b(ctypes.byref(h), 0, 1000, 100, 16, 1, 0) == -1               # no slots
+    assert b(ctypes.byref(h), 65, 1000, 100, 16, 1, 0) == -1              # too many slots
+    assert b(ctypes.byref(h), 2, 1000, 100, 16, 2, 0) == -1               # bf16: not batched
     assert h.value is None
 
 
@@ -77,6 +82,11 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_solve_fp8(None, a, None, 100, 16, 16, 4, 2, 1, 0.9, None, a, 4, a, a, 4, a) == -1
     assert lib.rsvd_quantize_fp8(None, a, 100, 16, 16, a, 16, a) == -1
     assert lib.rsvd_solve_krylov(None, a, 100, 10, 10, 2, 2, 1, 0.9, None, a, 2, a, a, 2, a) == -1
+    assert lib.rsvd_batch_solve(None, None, 0, None) == -1
+    assert lib.rsvd_batch_graph_create(None, None, 0, None, None) == -1
+    assert lib.rsvd_batch_graph_launch(None, None) == -1
+    assert lib.rsvd_batch_destroy(None) == 0
+    assert lib.rsvd_batch_graph_destroy(None) == 0
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

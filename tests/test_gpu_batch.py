@@ -1,0 +1,121 @@
+"""Batches of Randomized PCA problems of different shapes (rsvd_batch_*).
+
+Each instance of a batch must equal, bit for bit, rsvd_solve of the same
+problem on a plan of the same sizes and seed running alone (the slots are
+such plans; deterministic kernels and fixed-order reductions make the
+results independent of what else runs), and must pass the oracle's parity
+gates (same A, the plan's seeded G): relative sigma error <= 1e-10 (FP64) /
+1e-4 (FP32), principal angles <= 1e-3 rad, K and the status word equal.  A
+captured batch is replayed several times, with eager work in between, and
+every replay is compared with the eager batch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, dev, host, rounded, sign_rule_holds
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1906_12085_amd as rs  # noqa: E402
+
+SEED = 404
+M_MAX, N_MAX, L_MAX = 12000, 128, 40
+SIG_TOL = {torch.float64: 1e-10, torch.float32: 1e-4}
+
+
+def problems(dt, count, seed):
+    """Uneven instances: m in [700, 12000], n in {32, 48, 64, 96, 128},
+    k = min(8, n / 4), p = 8, q = 2, sigma_i = exp(-r i) with r in
+    [0.01, 0.2] (the batched workload's recipe at test sizes)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice([32, 48, 64, 96, 128]))
+        m = int(rng.integers(max(n, 700), M_MAX + 1))
+        r = rng.uniform(0.01, 0.2)
+        sig = np.exp(-r * np.arange(1, n + 1))
+        A0 = synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T
+        A0 = rounded(A0, dt)
+        out.append((dev(A0, dt), min(8, n // 4), 8, 2, 0.95, A0))
+    return out
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batch_equals_alone_and_oracle(dt):
+    announce(f"batch of 11 uneven instances on 3 slots {dt}")
+    probs = problems(dt, 11, 5 if dt == torch.float64 else 6)
+    b = rs.Batch(3, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    outs = b.solve([pr[:5] for pr in probs])
+    torch.cuda.synchronize()
+    alone = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    for (A, k, p, q, t, A0), o in zip(probs, outs):
+        m, n = A.shape
+        ref = alone.solve(A, k, p, q, t)
+        assert torch.equal(o["S"], ref.S) and torch.equal(o["U"], ref.U)
+        assert torch.equal(o["V"], ref.V)
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+        l = min(k + p, n)
+        G = rounded(synth.gaussian_omega(SEED, n, l), dt)
+        orc = oracle.rsvd(A0, G, k, p, q, t)
+        S, U, V = host(o["S"]), host(o["U"]), host(o["V"])
+        assert np.max(np.abs(S - orc.S) / orc.S) <= SIG_TOL[dt]
+        assert oracle.principal_angle_max(orc.V, V) <= 1e-3
+        assert oracle.principal_angle_max(orc.U, U) <= 1e-3
+        assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
+        assert sign_rule_holds(V)
+    alone.close()
+    b.close()
+
+
+def test_batch_graph_replays():
+    dt = torch.float32
+    announce("batch graph: capture 9 instances on 4 slots, 3 replays with eager work between")
+    probs = problems(dt, 9, 8)
+    b = rs.Batch(4, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    eager = b.solve([pr[:5] for pr in probs])
+    torch.cuda.synchronize()
+    keep = [{key: o[key].clone() for key in ("U", "S", "V", "K", "status")} for o in eager]
+    g = b.graph([pr[:5] for pr in probs])
+    other = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED + 1)
+    for rep in range(3):
+        for o in g.outs:                      # the replay must write every output again
+            for key in ("U", "S", "V"):
+                o[key].fill_(float("nan"))
+            o["K"].fill_(-9)
+            o["status"].fill_(-99)
+        g.launch()
+        torch.cuda.synchronize()
+        for o, e in zip(g.outs, keep):
+            for key in ("U", "S", "V", "K", "status"):
+                assert torch.equal(o[key], e[key]), (rep, key)
+        A, k, p, q, t, _ = probs[rep]
+        other.solve(A, k, p, q, t)            # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+    other.close()
+    b.close()
+
+
+def test_batch_arguments():
+    dt = torch.float64
+    b = rs.Batch(2, 4000, 64, 24, dt, seed=1)
+    A = torch.zeros((1000, 64), dtype=dt, device="cuda")
+    B = torch.zeros((50, 64), dtype=dt, device="cuda")         # m < n
+    with pytest.raises(rs.RSVDError) as ei:
+        b.solve([(A, 8, 8, 1, 0.9), (B, 8, 8, 1, 0.9)])
+    assert ei.value.code == rs.RSVD_ERR_SHAPE
+    with pytest.raises(rs.RSVDError) as ei:
+        b.solve([(A, 20, 8, 1, 0.9)])                          # l = 28 > l_max = 24
+    assert ei.value.code == rs.RSVD_ERR_SHAPE
+    with pytest.raises(rs.RSVDError) as ei:
+        b.graph([(A, 0, 8, 1, 0.9)])                           # k < 1
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    assert b.solve([]) == []
+    b.close()
+    with pytest.raises(rs.RSVDError):
+        rs.Batch(0, 4000, 64, 24, dt)
+    with pytest.raises(KeyError):
+        rs.Batch(2, 4000, 64, 24, torch.bfloat16)

@@ -29,6 +29,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 # Krylov-method leg: k, p and the block count minus one (L = (i+1)(k+p) = 96)
 KRYLOV = (32, 16, 1)
+# slots of the batched leg
+BATCH_SLOTS = 8
 
 
 def parse():
@@ -43,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched leg (512 uneven fp32 instances)")
     ap.add_argument("--no-krylov", action="store_true",
                     help="skip the Krylov-method leg (k=32, p=16, two blocks: L = 96)")
     ap.add_argument("--no-bf16", action="store_true",
@@ -291,6 +295,70 @@ def krylov_leg(rs, torch, A, m, n, k, p, i, t, seed, steps, warmup, stream):
             "sigma_rel_err_vs_fp64_path": sig_err}
 
 
+def batch_leg(rs, torch, dev, steps, warmup, nslots):
+    """The batched workload (512 fp32 instances of uneven shapes, each
+    Randomized PCA with k = min(32, n/4), p = 8, q = 2) solved three ways on
+    the same device-resident inputs: one plan solving them one after another
+    on one stream, the batch (nslots slots) launched eagerly, and the batch
+    captured once as a HIP graph and replayed.  Inputs are generated outside
+    the timed regions."""
+    import synth
+    c = synth.CONFIG4
+    shapes = synth.batch_shapes(c)
+    mmax = max(s[0] for s in shapes)
+    nmax = max(s[1] for s in shapes)
+    lmax = max(min(s[3] + c["p"], s[1]) for s in shapes)
+    probs, flops, nbytes = [], 0.0, 0.0
+    for i, (m, n, r, k) in enumerate(shapes):
+        A = synth.spiked_noisy_torch(c["seed"] * 100003 + i, m, n, synth.exp_sigma(n, r), 0.0,
+                                     dev, torch.float32)
+        probs.append((A, k, c["p"], c["q"], c["t"]))
+        l = min(k + c["p"], n)
+        f, b_, _, _ = algorithmic_counts(m, n, k, l, c["q"], 4)
+        flops += f
+        nbytes += b_
+    torch.cuda.synchronize()
+    b = rs.Batch(nslots, mmax, nmax, lmax, torch.float32, seed=c["seed"])
+    prepared = b.prepare(probs)
+
+    def timed(run):
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    eager_s = timed(lambda: b.solve(None, prepared=prepared))
+    keep = [o["S"].clone() for o in prepared[0]]
+    g = b.graph(None, prepared=prepared)
+    graph_s = timed(g.launch)
+    same = all(torch.equal(o["S"], e) for o, e in zip(prepared[0], keep))
+    statuses = {}
+    for o in prepared[0]:
+        st = rs.STATUS.get(int(o["status"].item()), int(o["status"].item()))
+        statuses[st] = statuses.get(st, 0) + 1
+    g.close()
+    plan = rs.Plan(mmax, nmax, lmax, torch.float32, seed=c["seed"])
+    seq_s = timed(lambda: [plan.solve(A, k, p, q, t, sync=False) for (A, k, p, q, t) in probs])
+    plan.close()
+    b.close()
+    del probs, prepared
+    torch.cuda.empty_cache()
+    best = min(eager_s, graph_s)
+    return {"instances": len(shapes), "slots": nslots,
+            "m_range": [min(s[0] for s in shapes), mmax], "n_set": sorted({s[1] for s in shapes}),
+            "ms_per_batch": {"sequential_one_stream": round(1e3 * seq_s, 2),
+                             "batch_eager": round(1e3 * eager_s, 2),
+                             "batch_graph": round(1e3 * graph_s, 2)},
+            "instances_per_s": round(len(shapes) / best, 1),
+            "speedup_vs_sequential": round(seq_s / best, 2),
+            "tflops": round(flops / best / 1e12, 2), "gbs": round(nbytes / best / 1e9, 1),
+            "graph_replay_equals_eager": same, "status_counts": statuses}
+
+
 def pct(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -423,6 +491,11 @@ def main():
               flush=True)
         legs["krylov"] = krylov_leg(rs, torch, A, m, n, kk, kp, ki, t, c["omega_seed"],
                                     args.steps, args.warmup, stream)
+
+    if not args.no_batch:
+        print(f"[bench] batched leg: {synth.CONFIG4['count']} instances, {args.steps} batches "
+              "per mode", file=sys.stderr, flush=True)
+        legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
 
     cpu = None
     if not args.no_cpu_baseline:

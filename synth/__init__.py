@@ -138,6 +138,30 @@ def config2_sigma(n: int = 512) -> np.ndarray:
     return 1.0 / np.arange(1, n + 1, dtype=np.float64)
 
 
+CONFIG4 = dict(count=512, m_lo=4096, m_hi=65536, n_choices=(64, 128, 256, 512), r_lo=0.01,
+               r_hi=0.2, k_max=32, p=8, q=2, t=0.95, seed=4)
+
+
+def batch_shapes(c=None):
+    """The batched workload's instances: (m, n, r, k) with m uniform integer in
+    [m_lo, m_hi], n uniform in n_choices, r uniform in [r_lo, r_hi] (the
+    spectrum is sigma_i = exp(-r i)) and k = min(k_max, n / 4)."""
+    c = c or CONFIG4
+    rng = np.random.default_rng(c["seed"])
+    out = []
+    for _ in range(c["count"]):
+        m = int(rng.integers(c["m_lo"], c["m_hi"] + 1))
+        n = int(rng.choice(c["n_choices"]))
+        r = float(rng.uniform(c["r_lo"], c["r_hi"]))
+        out.append((m, n, r, min(c["k_max"], n // 4)))
+    return out
+
+
+def exp_sigma(n: int, r: float) -> np.ndarray:
+    """sigma_i = exp(-r i), i = 1..n."""
+    return np.exp(-r * np.arange(1, n + 1, dtype=np.float64))
+
+
 def spiked_noisy(seed: int, m: int, n: int, sigma, noise_std: float) -> np.ndarray:
     """CPU (numpy) version of the config-2 recipe at any size:
     A = U diag(sigma) V^T + noise_std * N(0,1), U an orthonormalised centred

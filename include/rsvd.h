@@ -352,6 +352,44 @@ int32_t rsvd_batch_graph_launch(rsvd_batch_graph_t graph, void* stream);
 /* Free a captured batch (synchronises nothing; NULL is a no-op). */
 int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
 
+/* ------------------------------------------------------------- serving --
+ * Continuous batching of Randomized PCA requests (Sec. 3.1.2 each): requests
+ * are queued in arrival order and admitted, first come first served, as
+ * soon as a slot is free and the HBM they occupy while running fits the
+ * budget; a finished request frees its slot and its share of the budget at
+ * once, so requests that arrive while others run start beside them.  The
+ * slots are as in a batch (a plan and a stream each, same sizes and seed):
+ * a request's results do not depend on what else runs (bit for bit).
+ * Footprint of a request: its A (m lda elements), the two m x l panels of
+ * its plan and the split partials of its A^T Q products (n l FP64 per split). */
+typedef struct rsvd_server_s* rsvd_server_t;
+
+/* Create a server with nslots slots (1..64) for RSVD_F64 or RSVD_F32
+ * requests up to m_max x n_max with k + p <= l_max, admitting while the
+ * running requests' footprints sum to at most hbm_budget bytes (a request
+ * larger than the budget runs alone).  Errors as rsvd_batch_create. */
+int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max, int64_t n_max,
+                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget);
+
+/* Queue one request (arguments and status word as a batch instance; the
+ * buffers must stay valid until it is reported done).  Validated at once
+ * (RSVD_ERR_ARG / RSVD_ERR_SHAPE as rsvd_solve, nothing queued); *ticket
+ * receives its number (0, 1, 2, ... in submission order).  Admits at once
+ * when it can. */
+int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64_t* ticket);
+
+/* Never blocks: retires the requests whose work has finished (their
+ * outputs and status words are then complete) and admits queued ones.
+ * Writes up to `cap` finished tickets to `done` (host array) and their
+ * number to *ndone; more finished tickets are kept for the next call.
+ * *queued and *running (either may be NULL) receive the counts after the
+ * call. */
+int32_t rsvd_server_progress(rsvd_server_t server, int64_t* done, int32_t cap, int32_t* ndone,
+                             int32_t* queued, int32_t* running);
+
+/* Wait for every queued and running request, then free the server. */
+int32_t rsvd_server_destroy(rsvd_server_t server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,9 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_small_svd", "rsvd_sym_eig", "rsvd_plan_kernel_times", "rsvd_solve_bf16",
            "rsvd_quantize_bf16", "rsvd_solve_fp8", "rsvd_quantize_fp8", "rsvd_solve_krylov",
            "rsvd_batch_create", "rsvd_batch_destroy", "rsvd_batch_solve",
-           "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy"]
+           "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy",
+           "rsvd_server_create", "rsvd_server_submit", "rsvd_server_progress",
+           "rsvd_server_destroy"]
 
 
 class RsvdInstance(ctypes.Structure):
@@ -88,6 +90,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                           ctypes.POINTER(vp)]),
         "rsvd_batch_graph_launch": (i32, [vp, vp]),
         "rsvd_batch_graph_destroy": (i32, [vp]),
+        "rsvd_server_create": (i32, [ctypes.POINTER(vp), i32, i64, i64, i32, i32, u64, i64]),
+        "rsvd_server_submit": (i32, [vp, ctypes.POINTER(RsvdInstance), ctypes.POINTER(i64)]),
+        "rsvd_server_progress": (i32, [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "rsvd_server_destroy": (i32, [vp]),
         "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
         "rsvd_gaussian_fill": (i32, [u64, i64, i64, vp, vp]),
         "rsvd_gemm_nn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp, i64, vp, vp]),
@@ -466,6 +473,64 @@ class BatchGraph:
     def close(self):
         if self.handle:
             _check(load_library().rsvd_batch_graph_destroy(self.handle), "rsvd_batch_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of Randomized PCA requests (rsvd_server_*): submit()
+    queues a request and returns its ticket; progress() never blocks and
+    returns the tickets that finished since the last call (their outputs,
+    kept in `results[ticket]`, are then complete)."""
+
+    def __init__(self, nslots: int, m_max: int, n_max: int, l_max: int, dtype, seed: int = 0,
+                 hbm_budget: int = 1 << 40):
+        import torch
+        self.torch = torch
+        self.dtype = dtype
+        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[dtype]
+        h = ctypes.c_void_p()
+        _check(load_library().rsvd_server_create(ctypes.byref(h), nslots, m_max, n_max, l_max,
+                                                 code, seed, int(hbm_budget)),
+               "rsvd_server_create")
+        self.handle = h.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.results = {}
+        self._buf = (ctypes.c_int64 * 1024)()
+
+    def submit(self, A, k: int, p: int, q: int, t: float) -> int:
+        torch = self.torch
+        m, n = A.shape
+        o = dict(U=torch.empty((m, k), dtype=self.dtype, device=self.device),
+                 V=torch.empty((n, k), dtype=self.dtype, device=self.device),
+                 S=torch.empty((k,), dtype=torch.float64, device=self.device),
+                 K=torch.empty((1,), dtype=torch.int32, device=self.device),
+                 status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
+        req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), o["U"].data_ptr(),
+                           _ld(o["U"]), o["S"].data_ptr(), o["V"].data_ptr(), _ld(o["V"]),
+                           o["K"].data_ptr(), o["status"].data_ptr())
+        tk = ctypes.c_int64()
+        _check(load_library().rsvd_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)),
+               "rsvd_server_submit")
+        self.results[tk.value] = o
+        return tk.value
+
+    def progress(self):
+        """(finished tickets, queued, running)."""
+        nd, qd, rn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().rsvd_server_progress(self.handle, self._buf, len(self._buf),
+                                                   ctypes.byref(nd), ctypes.byref(qd),
+                                                   ctypes.byref(rn)), "rsvd_server_progress")
+        return list(self._buf[:nd.value]), qd.value, rn.value
+
+    def close(self):
+        if self.handle:
+            _check(load_library().rsvd_server_destroy(self.handle), "rsvd_server_destroy")
             self.handle = None
 
     def __del__(self):

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1208,6 +1209,158 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph) {
   if (graph->exec && hipGraphExecDestroy(graph->exec) != hipSuccess) rc = RSVD_ERR_DEVICE;
   if (graph->graph && hipGraphDestroy(graph->graph) != hipSuccess) rc = RSVD_ERR_DEVICE;
   delete graph;
+  return rc;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: requests queued in arrival order, admitted first come first
+// served onto free slots while their footprints fit the HBM budget, retired
+// by polling each busy slot's completion event.
+struct rsvd_server_s {
+  struct Req {
+    rsvd_instance x;
+    int64_t ticket = 0;
+    int64_t bytes = 0;
+  };
+  rsvd_batch_s* b = nullptr;
+  int64_t budget = 0, in_use = 0, next_ticket = 0;
+  std::deque<Req> queue;
+  std::vector<int64_t> slot_ticket;   // -1: free
+  std::vector<int64_t> slot_bytes;
+  std::deque<int64_t> finished;
+};
+
+namespace {
+
+int64_t request_bytes(const rsvd_server_s* sv, const rsvd_instance& x) {
+  const int64_t es = sv->b->dtype == RSVD_F64 ? 8 : 4;
+  const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+  return x.m * x.lda * es + 2 * x.m * l * es + tn_max_split(x.m, x.n, (int)l) * x.n * l * 8;
+}
+
+// Admit from the head of the queue while a slot is free and the head fits
+// the budget (or nothing runs).
+int32_t server_admit(rsvd_server_s* sv) {
+  rsvd_batch_s* b = sv->b;
+  while (!sv->queue.empty()) {
+    int s = -1;
+    for (int i = 0; i < (int)sv->slot_ticket.size(); ++i)
+      if (sv->slot_ticket[i] < 0) { s = i; break; }
+    if (s < 0) return RSVD_OK;
+    const rsvd_server_s::Req& r = sv->queue.front();
+    if (sv->in_use > 0 && sv->in_use + r.bytes > sv->budget) return RSVD_OK;
+    const rsvd_instance& x = r.x;
+    rsvd_plan_s* p = b->plan[s];
+    const int32_t rc =
+        b->dtype == RSVD_F64
+            ? rsvd_run<double>(p, (const double*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t,
+                               nullptr, (double*)x.U, x.ldu, x.S, (double*)x.V, x.ldv, x.K)
+            : rsvd_run<float>(p, (const float*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr,
+                              (float*)x.U, x.ldu, x.S, (float*)x.V, x.ldv, x.K);
+    if (rc != RSVD_OK) return rc;
+    hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, x.status);
+    RSVD_CHECK(hipGetLastError());
+    RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
+    sv->slot_ticket[s] = r.ticket;
+    sv->slot_bytes[s] = r.bytes;
+    sv->in_use += r.bytes;
+    sv->queue.pop_front();
+  }
+  return RSVD_OK;
+}
+
+// Retire the busy slots whose completion event has fired.
+int32_t server_retire(rsvd_server_s* sv, bool wait) {
+  rsvd_batch_s* b = sv->b;
+  for (int s = 0; s < (int)sv->slot_ticket.size(); ++s) {
+    if (sv->slot_ticket[s] < 0) continue;
+    const hipError_t e = wait ? hipEventSynchronize(b->done[s]) : hipEventQuery(b->done[s]);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return RSVD_ERR_DEVICE;
+    sv->finished.push_back(sv->slot_ticket[s]);
+    sv->in_use -= sv->slot_bytes[s];
+    sv->slot_ticket[s] = -1;
+    sv->slot_bytes[s] = 0;
+  }
+  return RSVD_OK;
+}
+
+int32_t server_running(const rsvd_server_s* sv) {
+  int32_t r = 0;
+  for (int64_t t : sv->slot_ticket) r += t >= 0;
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max, int64_t n_max,
+                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget) {
+  if (!server) return RSVD_ERR_ARG;
+  *server = nullptr;
+  if (hbm_budget < 1) return RSVD_ERR_ARG;
+  rsvd_batch_t b = nullptr;
+  const int32_t rc = rsvd_batch_create(&b, nslots, m_max, n_max, l_max, dtype, seed);
+  if (rc != RSVD_OK) return rc;
+  rsvd_server_s* sv = new (std::nothrow) rsvd_server_s();
+  if (!sv) {
+    batch_free(b);
+    return RSVD_ERR_NOMEM;
+  }
+  sv->b = b;
+  sv->budget = hbm_budget;
+  sv->slot_ticket.assign(nslots, -1);
+  sv->slot_bytes.assign(nslots, 0);
+  *server = sv;
+  return RSVD_OK;
+}
+
+int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64_t* ticket) {
+  if (!server || !req || !ticket) return RSVD_ERR_ARG;
+  const rsvd_instance& x = *req;
+  const int32_t rc = check_rsvd(server->b->plan[0], x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t,
+                                x.U, x.ldu, x.S, x.V, x.ldv, x.K);
+  if (rc != RSVD_OK) return rc;
+  if (!x.status) return RSVD_ERR_ARG;
+  if (hipSetDevice(server->b->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  rsvd_server_s::Req r;
+  r.x = x;
+  r.ticket = server->next_ticket++;
+  r.bytes = request_bytes(server, x);
+  server->queue.push_back(r);
+  *ticket = r.ticket;
+  return server_admit(server);
+}
+
+int32_t rsvd_server_progress(rsvd_server_t server, int64_t* done, int32_t cap, int32_t* ndone,
+                             int32_t* queued, int32_t* running) {
+  if (!server || !ndone || cap < 0 || (cap > 0 && !done)) return RSVD_ERR_ARG;
+  *ndone = 0;
+  if (hipSetDevice(server->b->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  int32_t rc = server_retire(server, false);
+  if (rc == RSVD_OK) rc = server_admit(server);
+  while (*ndone < cap && !server->finished.empty()) {
+    done[(*ndone)++] = server->finished.front();
+    server->finished.pop_front();
+  }
+  if (queued) *queued = (int32_t)server->queue.size();
+  if (running) *running = server_running(server);
+  return rc;
+}
+
+int32_t rsvd_server_destroy(rsvd_server_t server) {
+  if (!server) return RSVD_OK;
+  int32_t rc = RSVD_OK;
+  if (hipSetDevice(server->b->device) != hipSuccess) rc = RSVD_ERR_DEVICE;
+  while (rc == RSVD_OK && (!server->queue.empty() || server_running(server) > 0)) {
+    rc = server_retire(server, true);
+    if (rc == RSVD_OK) rc = server_admit(server);
+  }
+  batch_free(server->b);
+  delete server;
   return rc;
 }
 

@@ -65,6 +65,10 @@ def test_plan_create_validates_before_device_calls(lib):
     assert b(ctypes.byref(h), 0, 1000, 100, 16, 1, 0) == -1               # no slots
     assert b(ctypes.byref(h), 65, 1000, 100, 16, 1, 0) == -1              # too many slots
     assert b(ctypes.byref(h), 2, 1000, 100, 16, 2, 0) == -1               # bf16: not batched
+    sv = lib.rsvd_server_create
+    assert sv(None, 2, 1000, 100, 16, 1, 0, 1 << 30) == -1                # server NULL
+    assert sv(ctypes.byref(h), 2, 1000, 100, 16, 1, 0, 0) == -1           # no budget
+    assert sv(ctypes.byref(h), 0, 1000, 100, 16, 1, 0, 1 << 30) == -1     # no slots
     assert h.value is None
 
 
@@ -87,6 +91,9 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_batch_graph_launch(None, None) == -1
     assert lib.rsvd_batch_destroy(None) == 0
     assert lib.rsvd_batch_graph_destroy(None) == 0
+    assert lib.rsvd_server_submit(None, None, None) == -1
+    assert lib.rsvd_server_progress(None, None, 0, None, None, None) == -1
+    assert lib.rsvd_server_destroy(None) == 0
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -1,0 +1,136 @@
+"""Continuous batching (rsvd_server_*): requests submitted while others run
+are admitted as slots and budget free up; every result must equal, bit for
+bit, the same problem solved alone on a plan of the same sizes and seed, and
+pass the oracle's parity gates (relative sigma error <= 1e-4 for FP32,
+principal angles <= 1e-3 rad, K and status equal)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, dev, host, rounded
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1906_12085_amd as rs  # noqa: E402
+
+SEED = 505
+M_MAX, N_MAX, L_MAX = 20000, 128, 40
+
+
+def requests(dt, count, seed):
+    """m log-uniform in [1000, 20000] (multiples of 64), n in {32, 64, 128},
+    sigma_i = i^-alpha with alpha in [0.5, 2], t in {0.9, 0.95, 0.99}: the
+    serving workload's recipe at test sizes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice([32, 64, 128]))
+        m = max(n, int(np.exp(rng.uniform(np.log(1000), np.log(M_MAX))) // 64 * 64))
+        alpha = rng.uniform(0.5, 2.0)
+        sig = np.arange(1, n + 1, dtype=np.float64) ** -alpha
+        A0 = rounded(synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T, dt)
+        t = float(rng.choice([0.9, 0.95, 0.99]))
+        out.append((dev(A0, dt), min(16, n // 4), 8, 2, t, A0))
+    return out
+
+
+def poll(sv, pending, seen_running):
+    """One progress call: drop the finished tickets from `pending` (the
+    server reports each finished ticket once)."""
+    done, queued, running = sv.progress()
+    seen_running.append(running)
+    for tk in done:
+        pending.discard(tk)
+    return queued, running
+
+
+def drain(sv, pending, seen_running, limit_s=60.0):
+    t0 = time.monotonic()
+    while pending:
+        queued, running = poll(sv, pending, seen_running)
+        assert time.monotonic() - t0 < limit_s, (sorted(pending), queued, running)
+
+
+def test_serve_same_alone_and_in_mix():
+    dt = torch.float32
+    announce("serve: 14 requests arriving in waves on 3 slots")
+    reqs = requests(dt, 14, 3)
+    sv = rs.Server(3, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    tickets, pending, seen = [], set(), []
+    for i, (A, k, p, q, t, _) in enumerate(reqs):
+        tk = sv.submit(A, k, p, q, t)
+        tickets.append(tk)
+        pending.add(tk)
+        poll(sv, pending, seen)
+        if i % 4 == 3:                     # let the first waves finish partly
+            time.sleep(0.002)
+    drain(sv, pending, seen)
+    assert tickets == list(range(len(reqs)))
+    assert max(seen) > 1                   # requests ran side by side
+    alone = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    for tk, (A, k, p, q, t, A0) in zip(tickets, reqs):
+        o = sv.results[tk]
+        ref = alone.solve(A, k, p, q, t)
+        assert torch.equal(o["S"], ref.S) and torch.equal(o["U"], ref.U)
+        assert torch.equal(o["V"], ref.V)
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+        m, n = A.shape
+        G = rounded(synth.gaussian_omega(SEED, n, min(k + p, n)), dt)
+        orc = oracle.rsvd(A0, G, k, p, q, t)
+        assert np.max(np.abs(host(o["S"]) - orc.S) / orc.S) <= 1e-4
+        assert oracle.principal_angle_max(orc.V, host(o["V"])) <= 1e-3
+        assert oracle.principal_angle_max(orc.U, host(o["U"])) <= 1e-3
+        assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
+    alone.close()
+    sv.close()
+
+
+@pytest.mark.parametrize("budget_requests,limit", [(0.5, 1), (2.2, 2)])
+def test_serve_budget_admission(budget_requests, limit):
+    # identical 6000 x 64 requests: the budget holds half of one (each runs
+    # alone) or a bit over two (at most two run at once) of their footprints
+    dt = torch.float32
+    announce(f"serve: budget of {budget_requests} requests, at most {limit} running")
+    m, n, k, p, q = 6000, 64, 8, 8, 2
+    l = k + p
+    rng = np.random.default_rng(9)
+    A0 = rounded(synth.haar(rng, m, n) @ np.diag(np.arange(1, n + 1.0) ** -1.0)
+                 @ synth.haar(rng, n, n).T, dt)
+    A = dev(A0, dt)
+    # footprint as the server counts it: A, two m x l panels, the A^T Q
+    # partials (min(256, ceil(m / 64)) splits of n x l FP64)
+    splits = min(256, (m + 63) // 64)
+    foot = m * n * 4 + 2 * m * l * 4 + splits * n * l * 8
+    sv = rs.Server(4, M_MAX, N_MAX, L_MAX, dt, seed=SEED, hbm_budget=int(budget_requests * foot))
+    pending, seen = set(), []
+    for _ in range(6):
+        pending.add(sv.submit(A, k, p, q, 0.9))
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    assert max(seen) <= limit
+    first = sv.results[0]
+    for tk in range(1, 6):
+        o = sv.results[tk]
+        assert torch.equal(o["S"], first["S"]) and torch.equal(o["V"], first["V"])
+        assert torch.equal(o["U"], first["U"])
+    sv.close()
+
+
+def test_serve_arguments():
+    dt = torch.float32
+    sv = rs.Server(2, 4000, 64, 24, dt, seed=1)
+    A = torch.zeros((1000, 64), dtype=dt, device="cuda")
+    with pytest.raises(rs.RSVDError) as ei:
+        sv.submit(A, 20, 8, 1, 0.9)                    # l = 28 > l_max = 24
+    assert ei.value.code == rs.RSVD_ERR_SHAPE
+    with pytest.raises(rs.RSVDError) as ei:
+        sv.submit(A, 4, 2, 1, 1.5)                     # t outside (0, 1]
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    done, queued, running = sv.progress()
+    assert done == [] and queued == 0 and running == 0
+    assert sv.submit(A, 4, 2, 1, 0.9) == 0             # rejected requests take no ticket
+    sv.close()

@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving leg (Poisson arrivals, continuous batching)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven fp32 instances)")
     ap.add_argument("--no-krylov", action="store_true",
@@ -359,6 +361,68 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
             "graph_replay_equals_eager": same, "status_counts": statuses}
 
 
+def serve_leg(rs, torch, dev, nslots):
+    """The serving workload: Poisson arrivals (200 requests/s for 8 s) of
+    fp32 Randomized PCA requests on a pool of device-resident matrices of
+    uneven shapes, each with its own threshold t, served by one rsvd_server
+    (continuous batching on nslots slots).  Latency is taken on the host from
+    a request's arrival time to the progress() call that reports it done;
+    the outputs of finished requests are released as they are reported."""
+    import synth
+    c = synth.CONFIG5
+    pool = synth.serve_pool(c)
+    mats = [synth.spiked_noisy_torch(c["seed"] * 7919 + i, m, n, synth.power_sigma(n, a), 0.0,
+                                     dev, torch.float32) for i, (m, n, a) in enumerate(pool)]
+    torch.cuda.synchronize()
+    arrivals = synth.serve_arrivals(c)
+    mmax = max(m for m, _, _ in pool)
+    nmax = max(n for _, n, _ in pool)
+    l = c["k"] + c["p"]
+    sv = rs.Server(nslots, mmax, nmax, l, torch.float32, seed=c["seed"], hbm_budget=64 << 30)
+    for A in mats[:2]:                                   # warm-up, not timed
+        sv.submit(A, c["k"], c["p"], c["q"], 0.95)
+    pend = {0, 1}
+    while pend:
+        for tk in sv.progress()[0]:
+            pend.discard(tk)
+            sv.results.pop(tk, None)
+    lat, flops, statuses, max_q, max_r = [], 0.0, {}, 0, 0
+    pending = {}
+    i, nreq = 0, len(arrivals)
+    t0 = time.perf_counter()
+    while i < nreq or pending:
+        now = time.perf_counter() - t0
+        while i < nreq and arrivals[i][0] <= now:
+            at, j, t = arrivals[i]
+            m, n, _ = pool[j]
+            pending[sv.submit(mats[j], c["k"], c["p"], c["q"], t)] = (at, m, n)
+            i += 1
+        done, queued, running = sv.progress()
+        max_q, max_r = max(max_q, queued), max(max_r, running)
+        if done:
+            now = time.perf_counter() - t0
+            for tk in done:
+                at, m, n = pending.pop(tk)
+                lat.append(1e3 * (now - at))
+                o = sv.results.pop(tk)
+                st = rs.STATUS.get(int(o["status"].item()), int(o["status"].item()))
+                statuses[st] = statuses.get(st, 0) + 1
+                f, _, _, _ = algorithmic_counts(m, n, c["k"], min(l, n), c["q"], 4)
+                flops += f
+    wall = time.perf_counter() - t0
+    sv.close()
+    del mats
+    torch.cuda.empty_cache()
+    return {"requests": nreq, "offered_rate_per_s": c["rate"], "slots": nslots,
+            "solves_per_s": round(nreq / wall, 1), "wall_s": round(wall, 2),
+            "latency_ms": {"p50": round(pct(lat, 50), 2), "p99": round(pct(lat, 99), 2),
+                           "max": round(max(lat), 2)},
+            "tflops": round(flops / wall / 1e12, 2), "max_queued": max_q, "max_running": max_r,
+            "pool": {"matrices": len(pool), "m_range": [min(m for m, _, _ in pool), mmax],
+                     "n_set": sorted({n for _, n, _ in pool})},
+            "status_counts": statuses}
+
+
 def pct(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -496,6 +560,11 @@ def main():
         print(f"[bench] batched leg: {synth.CONFIG4['count']} instances, {args.steps} batches "
               "per mode", file=sys.stderr, flush=True)
         legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
+
+    if not args.no_serve:
+        print("[bench] serving leg: Poisson arrivals at 200/s for 8 s", file=sys.stderr,
+              flush=True)
+        legs["serve"] = serve_leg(rs, torch, dev, BATCH_SLOTS)
 
     cpu = None
     if not args.no_cpu_baseline:

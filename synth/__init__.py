@@ -157,6 +157,45 @@ def batch_shapes(c=None):
     return out
 
 
+CONFIG5 = dict(rate=200.0, seconds=8.0, m_lo=1000, m_hi=1_000_000, m_multiple=64,
+               n_choices=(128, 256, 512, 1024), alpha_lo=0.5, alpha_hi=2.0,
+               t_choices=(0.9, 0.95, 0.99), k=32, p=8, q=2, pool=24, seed=5)
+
+
+def serve_pool(c=None):
+    """Matrices the serving workload draws its requests from: (m, n, alpha)
+    with m log-uniform in [m_lo, m_hi] rounded down to a multiple of
+    m_multiple, n uniform in n_choices, alpha uniform in [alpha_lo, alpha_hi]
+    (sigma_i = i^-alpha)."""
+    c = c or CONFIG5
+    rng = np.random.default_rng(c["seed"])
+    out = []
+    for _ in range(c["pool"]):
+        n = int(rng.choice(c["n_choices"]))
+        m = int(np.exp(rng.uniform(np.log(c["m_lo"]), np.log(c["m_hi"]))))
+        m = max(n, m // c["m_multiple"] * c["m_multiple"])
+        out.append((m, n, float(rng.uniform(c["alpha_lo"], c["alpha_hi"]))))
+    return out
+
+
+def serve_arrivals(c=None):
+    """Poisson arrivals at `rate` per second over `seconds`: (time, pool
+    index, t) per request."""
+    c = c or CONFIG5
+    rng = np.random.default_rng(c["seed"] + 1)
+    out, now = [], 0.0
+    while True:
+        now += rng.exponential(1.0 / c["rate"])
+        if now >= c["seconds"]:
+            return out
+        out.append((now, int(rng.integers(0, c["pool"])), float(rng.choice(c["t_choices"]))))
+
+
+def power_sigma(n: int, alpha: float) -> np.ndarray:
+    """sigma_i = i^-alpha, i = 1..n."""
+    return np.arange(1, n + 1, dtype=np.float64) ** -alpha
+
+
 def exp_sigma(n: int, r: float) -> np.ndarray:
     """sigma_i = exp(-r i), i = 1..n."""
     return np.exp(-r * np.arange(1, n + 1, dtype=np.float64))

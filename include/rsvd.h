@@ -304,7 +304,9 @@ typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
 
 /* One problem of a batch: arguments as rsvd_solve (device pointers A, U, S,
  * V, K), plus `status` (1 int32, device) that receives the instance's status
- * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV). */
+ * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV), and
+ * for RSVD_BF16 / RSVD_FP8 batches and servers `col_scale` (n floats, device,
+ * or NULL for unit scales) as in rsvd_solve_bf16; ignored otherwise. */
 typedef struct {
   const void* A;
   int64_t m, n, lda;
@@ -317,12 +319,15 @@ typedef struct {
   int64_t ldv;
   int32_t* K;
   int32_t* status;
+  const float* col_scale;
 } rsvd_instance;
 
-/* Create a batch of nslots (1..64) slots for RSVD_F64 or RSVD_F32 problems
- * up to m_max x n_max with k + p <= l_max (limits as rsvd_plan_create).
- * Each slot's stream is created by the batch (default priority).  Errors as
- * rsvd_plan_create, RSVD_ERR_ARG for nslots out of range or another dtype. */
+/* Create a batch of nslots (1..64) slots for problems of one dtype (any of
+ * rsvd_dtype: A of RSVD_BF16 / RSVD_FP8 problems stored as in
+ * rsvd_solve_bf16 / rsvd_solve_fp8, with U and V float) up to m_max x n_max
+ * with k + p <= l_max (limits as rsvd_plan_create).  Each slot's stream is
+ * created by the batch (default priority).  Errors as rsvd_plan_create,
+ * RSVD_ERR_ARG for nslots out of range. */
 int32_t rsvd_batch_create(rsvd_batch_t* batch, int32_t nslots, int64_t m_max, int64_t n_max,
                           int32_t l_max, int32_t dtype, uint64_t seed);
 
@@ -364,8 +369,8 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
  * its plan and the split partials of its A^T Q products (n l FP64 per split). */
 typedef struct rsvd_server_s* rsvd_server_t;
 
-/* Create a server with nslots slots (1..64) for RSVD_F64 or RSVD_F32
- * requests up to m_max x n_max with k + p <= l_max, admitting while the
+/* Create a server with nslots slots (1..64) for requests of one dtype (as
+ * rsvd_batch_create) up to m_max x n_max with k + p <= l_max, admitting while the
  * running requests' footprints sum to at most hbm_budget bytes (a request
  * larger than the budget runs alone).  Errors as rsvd_batch_create. */
 int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max, int64_t n_max,

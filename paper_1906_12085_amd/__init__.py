@@ -49,7 +49,15 @@ class RsvdInstance(ctypes.Structure):
                 ("lda", ctypes.c_int64), ("k", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_void_p),
                 ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
-                ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+                ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("col_scale", ctypes.c_void_p)]
+
+
+def _dtype_codes(torch):
+    """torch dtype of A -> (rsvd_dtype, dtype of U and V)."""
+    return {torch.float64: (RSVD_F64, torch.float64), torch.float32: (RSVD_F32, torch.float32),
+            torch.bfloat16: (RSVD_BF16, torch.float32),
+            torch.float8_e4m3fn: (RSVD_FP8, torch.float32)}
 
 
 class RSVDError(RuntimeError):
@@ -401,15 +409,15 @@ class Plan:
 
 class Batch:
     """Many Randomized PCA problems of different shapes on `nslots` slots
-    (rsvd_batch_*).  `problems` is a list of (A, k, p, q, t); outputs are
-    allocated per problem.  solve() runs them now; graph() captures the same
-    solves (same A and output tensors) into a replayable HIP graph."""
+    (rsvd_batch_*).  `problems` is a list of (A, k, p, q, t) or, for a
+    bfloat16 / FP8 batch, (A, k, p, q, t, col_scale); outputs are allocated
+    per problem.  solve() runs them now; graph() captures the same solves
+    (same A and output tensors) into a replayable HIP graph."""
 
     def __init__(self, nslots: int, m_max: int, n_max: int, l_max: int, dtype, seed: int = 0):
         import torch
         self.torch = torch
-        self.dtype = dtype
-        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[dtype]
+        code, self.dtype = _dtype_codes(torch)[dtype]
         h = ctypes.c_void_p()
         _check(load_library().rsvd_batch_create(ctypes.byref(h), nslots, m_max, n_max, l_max,
                                                 code, seed), "rsvd_batch_create")
@@ -431,7 +439,9 @@ class Batch:
         """Output tensors and the C instance array for `problems`."""
         torch = self.torch
         outs, arr = [], (RsvdInstance * len(problems))()
-        for i, (A, k, p, q, t) in enumerate(problems):
+        for i, pr in enumerate(problems):
+            A, k, p, q, t = pr[:5]
+            cs = pr[5] if len(pr) > 5 else None
             m, n = A.shape
             o = dict(U=torch.empty((m, k), dtype=self.dtype, device=self.device),
                      V=torch.empty((n, k), dtype=self.dtype, device=self.device),
@@ -441,7 +451,8 @@ class Batch:
             arr[i] = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t),
                                   o["U"].data_ptr(), _ld(o["U"]), o["S"].data_ptr(),
                                   o["V"].data_ptr(), _ld(o["V"]), o["K"].data_ptr(),
-                                  o["status"].data_ptr())
+                                  o["status"].data_ptr(), _ptr(cs))
+            o["col_scale"] = cs
             outs.append(o)
         return outs, arr
 
@@ -492,8 +503,7 @@ class Server:
                  hbm_budget: int = 1 << 40):
         import torch
         self.torch = torch
-        self.dtype = dtype
-        code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[dtype]
+        code, self.dtype = _dtype_codes(torch)[dtype]
         h = ctypes.c_void_p()
         _check(load_library().rsvd_server_create(ctypes.byref(h), nslots, m_max, n_max, l_max,
                                                  code, seed, int(hbm_budget)),
@@ -503,7 +513,7 @@ class Server:
         self.results = {}
         self._buf = (ctypes.c_int64 * 1024)()
 
-    def submit(self, A, k: int, p: int, q: int, t: float) -> int:
+    def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None) -> int:
         torch = self.torch
         m, n = A.shape
         o = dict(U=torch.empty((m, k), dtype=self.dtype, device=self.device),
@@ -513,7 +523,8 @@ class Server:
                  status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
         req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), o["U"].data_ptr(),
                            _ld(o["U"]), o["S"].data_ptr(), o["V"].data_ptr(), _ld(o["V"]),
-                           o["K"].data_ptr(), o["status"].data_ptr())
+                           o["K"].data_ptr(), o["status"].data_ptr(), _ptr(col_scale))
+        o["col_scale"] = col_scale
         tk = ctypes.c_int64()
         _check(load_library().rsvd_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)),
                "rsvd_server_submit")

@@ -1032,6 +1032,39 @@ __global__ void k_status_take(const int32_t* __restrict__ src, int32_t* __restri
   if (threadIdx.x == 0) *dst = *src;
 }
 
+// Validate one instance for a slot plan (as rsvd_solve / rsvd_solve_bf16).
+int32_t check_instance(rsvd_plan_s* p, const rsvd_instance& x) {
+  const int32_t rc = check_rsvd(p, x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, x.U, x.ldu, x.S,
+                                x.V, x.ldv, x.K);
+  if (rc != RSVD_OK) return rc;
+  if (!x.status) return RSVD_ERR_ARG;
+  if (const int es = lowp_es(p->dtype)) {
+    const int l = (int)((x.k + (int64_t)x.p < x.n) ? x.k + x.p : x.n);
+    if (!bf16_pass_applies(x.A, es, x.n, x.lda, l)) return RSVD_ERR_ARG;
+  }
+  return RSVD_OK;
+}
+
+// Enqueue one instance's solve and its status copy on the slot plan's stream.
+int32_t run_instance(rsvd_plan_s* p, const rsvd_instance& x) {
+  int32_t rc;
+  if (p->dtype == RSVD_F64) {
+    rc = rsvd_run<double>(p, (const double*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr,
+                          (double*)x.U, x.ldu, x.S, (double*)x.V, x.ldv, x.K);
+  } else if (const int es = lowp_es(p->dtype)) {
+    const LowpA lp{x.A, x.col_scale, es};
+    rc = rsvd_run<float>(p, nullptr, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr, (float*)x.U,
+                         x.ldu, x.S, (float*)x.V, x.ldv, x.K, &lp);
+  } else {
+    rc = rsvd_run<float>(p, (const float*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr,
+                         (float*)x.U, x.ldu, x.S, (float*)x.V, x.ldv, x.K);
+  }
+  if (rc != RSVD_OK) return rc;
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, x.status);
+  RSVD_CHECK(hipGetLastError());
+  return RSVD_OK;
+}
+
 void batch_free(rsvd_batch_s* b) {
   (void)hipSetDevice(b->device);
   for (rsvd_plan_s* p : b->plan) rsvd_plan_destroy(p);   // synchronises its stream
@@ -1050,10 +1083,8 @@ int32_t batch_schedule(rsvd_batch_s* b, const rsvd_instance* in, int32_t count,
   std::vector<double> work(count);
   for (int i = 0; i < count; ++i) {
     const rsvd_instance& x = in[i];
-    const int32_t rc = check_rsvd(b->plan[0], x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, x.U,
-                                  x.ldu, x.S, x.V, x.ldv, x.K);
+    const int32_t rc = check_instance(b->plan[0], x);
     if (rc != RSVD_OK) return rc;
-    if (!x.status) return RSVD_ERR_ARG;
     const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
     work[i] = (double)x.m * (double)x.n * (double)l;
   }
@@ -1072,7 +1103,6 @@ int32_t batch_schedule(rsvd_batch_s* b, const rsvd_instance* in, int32_t count,
   return RSVD_OK;
 }
 
-template <typename T>
 int32_t batch_launch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hipStream_t st) {
   std::vector<int> order, slot;
   int32_t rc = batch_schedule(b, in, count, order, slot);
@@ -1083,13 +1113,8 @@ int32_t batch_launch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hi
   for (size_t s = 0; s < used.size(); ++s)
     if (used[s]) RSVD_CHECK(hipStreamWaitEvent(b->stream[s], b->fork, 0));
   for (int i : order) {
-    const rsvd_instance& x = in[i];
-    rsvd_plan_s* p = b->plan[slot[i]];
-    rc = rsvd_run<T>(p, (const T*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr, (T*)x.U,
-                     x.ldu, x.S, (T*)x.V, x.ldv, x.K);
+    rc = run_instance(b->plan[slot[i]], in[i]);
     if (rc != RSVD_OK) return rc;
-    hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, x.status);
-    RSVD_CHECK(hipGetLastError());
   }
   for (size_t s = 0; s < used.size(); ++s)
     if (used[s]) {
@@ -1100,8 +1125,7 @@ int32_t batch_launch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hi
 }
 
 int32_t batch_dispatch(rsvd_batch_s* b, const rsvd_instance* in, int32_t count, hipStream_t st) {
-  if (b->dtype == RSVD_F64) return batch_launch<double>(b, in, count, st);
-  return batch_launch<float>(b, in, count, st);
+  return batch_launch(b, in, count, st);
 }
 
 }  // namespace
@@ -1113,7 +1137,7 @@ int32_t rsvd_batch_create(rsvd_batch_t* batch, int32_t nslots, int64_t m_max, in
   if (!batch) return RSVD_ERR_ARG;
   *batch = nullptr;
   if (nslots < 1 || nslots > kMaxSlots) return RSVD_ERR_ARG;
-  if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32 && !lowp_es(dtype)) return RSVD_ERR_ARG;
   rsvd_batch_s* b = new (std::nothrow) rsvd_batch_s();
   if (!b) return RSVD_ERR_NOMEM;
   if (hipGetDevice(&b->device) != hipSuccess) { delete b; return RSVD_ERR_DEVICE; }
@@ -1235,9 +1259,11 @@ struct rsvd_server_s {
 namespace {
 
 int64_t request_bytes(const rsvd_server_s* sv, const rsvd_instance& x) {
-  const int64_t es = sv->b->dtype == RSVD_F64 ? 8 : 4;
+  const int dt = sv->b->dtype;
+  const int64_t ea = dt == RSVD_F64 ? 8 : (lowp_es(dt) ? lowp_es(dt) : 4);   // A's elements
+  const int64_t ep = dt == RSVD_F64 ? 8 : 4;                                  // the panels'
   const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
-  return x.m * x.lda * es + 2 * x.m * l * es + tn_max_split(x.m, x.n, (int)l) * x.n * l * 8;
+  return x.m * x.lda * ea + 2 * x.m * l * ep + tn_max_split(x.m, x.n, (int)l) * x.n * l * 8;
 }
 
 // Admit from the head of the queue while a slot is free and the head fits
@@ -1251,17 +1277,8 @@ int32_t server_admit(rsvd_server_s* sv) {
     if (s < 0) return RSVD_OK;
     const rsvd_server_s::Req& r = sv->queue.front();
     if (sv->in_use > 0 && sv->in_use + r.bytes > sv->budget) return RSVD_OK;
-    const rsvd_instance& x = r.x;
-    rsvd_plan_s* p = b->plan[s];
-    const int32_t rc =
-        b->dtype == RSVD_F64
-            ? rsvd_run<double>(p, (const double*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t,
-                               nullptr, (double*)x.U, x.ldu, x.S, (double*)x.V, x.ldv, x.K)
-            : rsvd_run<float>(p, (const float*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr,
-                              (float*)x.U, x.ldu, x.S, (float*)x.V, x.ldv, x.K);
+    const int32_t rc = run_instance(b->plan[s], r.x);
     if (rc != RSVD_OK) return rc;
-    hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, x.status);
-    RSVD_CHECK(hipGetLastError());
     RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
     sv->slot_ticket[s] = r.ticket;
     sv->slot_bytes[s] = r.bytes;
@@ -1321,10 +1338,8 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
 int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64_t* ticket) {
   if (!server || !req || !ticket) return RSVD_ERR_ARG;
   const rsvd_instance& x = *req;
-  const int32_t rc = check_rsvd(server->b->plan[0], x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t,
-                                x.U, x.ldu, x.S, x.V, x.ldv, x.K);
+  const int32_t rc = check_instance(server->b->plan[0], x);
   if (rc != RSVD_OK) return rc;
-  if (!x.status) return RSVD_ERR_ARG;
   if (hipSetDevice(server->b->device) != hipSuccess) return RSVD_ERR_DEVICE;
   rsvd_server_s::Req r;
   r.x = x;

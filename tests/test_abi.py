@@ -64,7 +64,7 @@ def test_plan_create_validates_before_device_calls(lib):
     assert b(None, 2, 1000, 100, 16, 1, 0) == -1                          # batch NULL
     assert b(ctypes.byref(h), 0, 1000, 100, 16, 1, 0) == -1               # no slots
     assert b(ctypes.byref(h), 65, 1000, 100, 16, 1, 0) == -1              # too many slots
-    assert b(ctypes.byref(h), 2, 1000, 100, 16, 2, 0) == -1               # bf16: not batched
+    assert b(ctypes.byref(h), 2, 1000, 100, 16, 4, 0) == -1               # unknown dtype
     sv = lib.rsvd_server_create
     assert sv(None, 2, 1000, 100, 16, 1, 0, 1 << 30) == -1                # server NULL
     assert sv(ctypes.byref(h), 2, 1000, 100, 16, 1, 0, 0) == -1           # no budget

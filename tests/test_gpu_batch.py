@@ -118,4 +118,4 @@ def test_batch_arguments():
     with pytest.raises(rs.RSVDError):
         rs.Batch(0, 4000, 64, 24, dt)
     with pytest.raises(KeyError):
-        rs.Batch(2, 4000, 64, 24, torch.bfloat16)
+        rs.Batch(2, 4000, 64, 24, torch.int32)

@@ -134,3 +134,44 @@ def test_serve_arguments():
     assert done == [] and queued == 0 and running == 0
     assert sv.submit(A, 4, 2, 1, 0.9) == 0             # rejected requests take no ticket
     sv.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_serve_low_precision_same_alone_and_oracle(fmt):
+    # A stored in bfloat16 / FP8 E4M3 with power-of-two column scales: every
+    # result equals rsvd_solve_bf16 / _fp8 alone on a plan of the same sizes
+    # and seed, and passes the FP32 gates against the oracle on the
+    # dequantised stored matrix
+    storage = torch.bfloat16 if fmt == "bf16" else torch.float8_e4m3fn
+    announce(f"serve: 8 {fmt} requests on 3 slots")
+    reqs = requests(torch.float32, 8, 17)
+    quant = rs.Plan(M_MAX, N_MAX, L_MAX, storage, seed=SEED)
+    stored = []
+    for A, k, p, q, t, _ in reqs:
+        Aq, s = quant.quantize(A)
+        stored.append((Aq, s, k, p, q, t))
+    torch.cuda.synchronize()
+    sv = rs.Server(3, M_MAX, N_MAX, L_MAX, storage, seed=SEED)
+    pending, seen = set(), []
+    tickets = []
+    for Aq, s, k, p, q, t in stored:
+        tickets.append(sv.submit(Aq, k, p, q, t, col_scale=s))
+        pending.add(tickets[-1])
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    for tk, (Aq, s, k, p, q, t) in zip(tickets, stored):
+        o = sv.results[tk]
+        ref = quant.solve(Aq, k, p, q, t, col_scale=s)
+        assert torch.equal(o["S"], ref.S) and torch.equal(o["U"], ref.U)
+        assert torch.equal(o["V"], ref.V)
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+        n = Aq.shape[1]
+        A64 = (Aq.double() * s.double()[None, :]).cpu().numpy()
+        G = rounded(synth.gaussian_omega(SEED, n, min(k + p, n)), torch.float32)
+        orc = oracle.rsvd(A64, G, k, p, q, t)
+        assert np.max(np.abs(host(o["S"]) - orc.S) / orc.S) <= 1e-4
+        assert oracle.principal_angle_max(orc.V, host(o["V"])) <= 1e-3
+        assert oracle.principal_angle_max(orc.U, host(o["U"])) <= 1e-3
+        assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
+    sv.close()
+    quant.close()

@@ -361,33 +361,55 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
             "graph_replay_equals_eager": same, "status_counts": statuses}
 
 
-def serve_leg(rs, torch, dev, nslots):
+def serve_leg(rs, torch, dev, nslots, storage=None):
     """The serving workload: Poisson arrivals (200 requests/s for 8 s) of
-    fp32 Randomized PCA requests on a pool of device-resident matrices of
-    uneven shapes, each with its own threshold t, served by one rsvd_server
-    (continuous batching on nslots slots).  Latency is taken on the host from
-    a request's arrival time to the progress() call that reports it done;
-    the outputs of finished requests are released as they are reported."""
+    Randomized PCA requests on a pool of device-resident matrices of uneven
+    shapes, each with its own threshold t, served by one rsvd_server
+    (continuous batching on nslots slots), with A in fp32 or (storage) in
+    bfloat16 / FP8 E4M3 with power-of-two column scales.  Latency is taken
+    on the host from a request's arrival time to the progress() call that
+    reports it done; the outputs of finished requests are released as they
+    are reported.  Then the same request sequence with arrival times ignored
+    and 32 requests kept outstanding: the server's capacity in solves/s."""
     import synth
     c = synth.CONFIG5
     pool = synth.serve_pool(c)
-    mats = [synth.spiked_noisy_torch(c["seed"] * 7919 + i, m, n, synth.power_sigma(n, a), 0.0,
-                                     dev, torch.float32) for i, (m, n, a) in enumerate(pool)]
-    torch.cuda.synchronize()
-    arrivals = synth.serve_arrivals(c)
     mmax = max(m for m, _, _ in pool)
     nmax = max(n for _, n, _ in pool)
     l = c["k"] + c["p"]
-    sv = rs.Server(nslots, mmax, nmax, l, torch.float32, seed=c["seed"], hbm_budget=64 << 30)
-    for A in mats[:2]:                                   # warm-up, not timed
-        sv.submit(A, c["k"], c["p"], c["q"], 0.95)
+    mats, scales = [], []
+    quant = rs.Plan(mmax, nmax, l, storage, seed=c["seed"]) if storage is not None else None
+    for i, (m, n, a) in enumerate(pool):
+        A = synth.spiked_noisy_torch(c["seed"] * 7919 + i, m, n, synth.power_sigma(n, a), 0.0, dev,
+                                     torch.float32)
+        if quant is not None:
+            Aq, sc = quant.quantize(A)
+            torch.cuda.synchronize()
+            del A
+            mats.append(Aq)
+            scales.append(sc)
+        else:
+            mats.append(A)
+            scales.append(None)
+    if quant is not None:
+        quant.close()
+    torch.cuda.synchronize()
+    arrivals = synth.serve_arrivals(c)
+    sv = rs.Server(nslots, mmax, nmax, l, storage if storage is not None else torch.float32,
+                   seed=c["seed"], hbm_budget=64 << 30)
+
+    def submit(j, t):
+        return sv.submit(mats[j], c["k"], c["p"], c["q"], t, col_scale=scales[j])
+
+    for j in range(2):                                   # warm-up, not timed
+        submit(j, 0.95)
     pend = {0, 1}
     while pend:
         for tk in sv.progress()[0]:
             pend.discard(tk)
             sv.results.pop(tk, None)
     lat, flops, statuses, max_q, max_r = [], 0.0, {}, 0, 0
-    pending = {}
+    pending, Ks = {}, {}
     i, nreq = 0, len(arrivals)
     t0 = time.perf_counter()
     while i < nreq or pending:
@@ -395,32 +417,47 @@ def serve_leg(rs, torch, dev, nslots):
         while i < nreq and arrivals[i][0] <= now:
             at, j, t = arrivals[i]
             m, n, _ = pool[j]
-            pending[sv.submit(mats[j], c["k"], c["p"], c["q"], t)] = (at, m, n)
+            pending[submit(j, t)] = (at, m, n, i)
             i += 1
         done, queued, running = sv.progress()
         max_q, max_r = max(max_q, queued), max(max_r, running)
         if done:
             now = time.perf_counter() - t0
             for tk in done:
-                at, m, n = pending.pop(tk)
+                at, m, n, idx = pending.pop(tk)
                 lat.append(1e3 * (now - at))
                 o = sv.results.pop(tk)
+                Ks[idx] = int(o["K"].item())
                 st = rs.STATUS.get(int(o["status"].item()), int(o["status"].item()))
                 statuses[st] = statuses.get(st, 0) + 1
                 f, _, _, _ = algorithmic_counts(m, n, c["k"], min(l, n), c["q"], 4)
                 flops += f
     wall = time.perf_counter() - t0
+    # capacity: the same requests back to back, 32 outstanding
+    i, outstanding = 0, set()
+    t1 = time.perf_counter()
+    while i < nreq or outstanding:
+        while i < nreq and len(outstanding) < 32:
+            _, j, t = arrivals[i]
+            outstanding.add(submit(j, t))
+            i += 1
+        for tk in sv.progress()[0]:
+            outstanding.discard(tk)
+            sv.results.pop(tk, None)
+    cap_s = time.perf_counter() - t1
     sv.close()
-    del mats
+    del mats, scales
     torch.cuda.empty_cache()
-    return {"requests": nreq, "offered_rate_per_s": c["rate"], "slots": nslots,
+    name = {None: "fp32", torch.bfloat16: "bf16", torch.float8_e4m3fn: "fp8 e4m3"}[storage]
+    return {"storage": name, "requests": nreq, "offered_rate_per_s": c["rate"], "slots": nslots,
             "solves_per_s": round(nreq / wall, 1), "wall_s": round(wall, 2),
             "latency_ms": {"p50": round(pct(lat, 50), 2), "p99": round(pct(lat, 99), 2),
                            "max": round(max(lat), 2)},
+            "capacity_solves_per_s": round(nreq / cap_s, 1),
             "tflops": round(flops / wall / 1e12, 2), "max_queued": max_q, "max_running": max_r,
             "pool": {"matrices": len(pool), "m_range": [min(m for m, _, _ in pool), mmax],
                      "n_set": sorted({n for _, n, _ in pool})},
-            "status_counts": statuses}
+            "status_counts": statuses, "_K": [Ks[i] for i in range(nreq)]}
 
 
 def pct(xs, p):
@@ -562,9 +599,13 @@ def main():
         legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
 
     if not args.no_serve:
-        print("[bench] serving leg: Poisson arrivals at 200/s for 8 s", file=sys.stderr,
-              flush=True)
+        print("[bench] serving legs (fp32, bf16): Poisson arrivals at 200/s for 8 s, then "
+              "capacity", file=sys.stderr, flush=True)
         legs["serve"] = serve_leg(rs, torch, dev, BATCH_SLOTS)
+        legs["serve_bf16"] = serve_leg(rs, torch, dev, BATCH_SLOTS, torch.bfloat16)
+        k32, k16 = legs["serve"].pop("_K"), legs["serve_bf16"].pop("_K")
+        legs["serve_bf16"]["K_equals_fp32_serving"] = round(
+            sum(a == b for a, b in zip(k32, k16)) / max(1, len(k32)), 4)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -99,14 +99,14 @@ KERNEL_INFO = {
 # again.
 TRAFFIC = {
     "eigensolver": (3.2841e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
-    "pass_nn": (2.3910e+09, "gemm.hip", "k_gemm_nt_tall", "5458f34d8ffce76b"),
+    "pass_nn": (2.3911e+09, "gemm.hip", "k_gemm_nt_tall", "5458f34d8ffce76b"),
     "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "03561cb8faeda271"),
-    "syrk": (3.6526e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
-    "nn_wide": (4.4542e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
-    "pass_nn_bf16": (1.5303e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
-    "pass_tn_bf16": (1.4355e+09, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
-    "pass_nn_fp8": (8.4552e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
-    "pass_tn_fp8": (9.1822e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
+    "syrk": (3.6882e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
+    "nn_wide": (4.4559e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
+    "pass_nn_bf16": (1.5380e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "pass_tn_bf16": (1.4354e+09, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
+    "pass_nn_fp8": (8.4523e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "pass_tn_fp8": (9.1849e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 
@@ -493,8 +493,15 @@ def main():
                                  torch.float32)
     torch.cuda.synchronize()
 
-    plan = rs.Plan(m, n, l, torch.float32, want_gram=not args.no_gram, seed=c["omega_seed"],
-                   stream=stream)
+    # the two solves of a step are independent: the rSVD runs on one stream,
+    # the A^T A route (whose eigensolver leaves most of the GPU idle) on
+    # another, each with its own plan; the step forks from and joins into the
+    # current stream
+    s_rs = torch.cuda.Stream(device=dev)
+    s_gr = torch.cuda.Stream(device=dev)
+    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=c["omega_seed"], stream=s_rs)
+    plan_g = (rs.Plan(m, n, l, torch.float32, want_gram=True, seed=c["omega_seed"], stream=s_gr)
+              if not args.no_gram else None)
     U = torch.empty(m, k, dtype=torch.float32, device=dev)
     S = torch.empty(k, dtype=torch.float64, device=dev)
     V = torch.empty(n, k, dtype=torch.float32, device=dev)
@@ -506,39 +513,62 @@ def main():
         Kg = torch.empty(1, dtype=torch.int32, device=dev)
 
     def step(evs=None):
-        if evs:
-            evs[0].record(stream)
-        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
-        if evs:
-            evs[1].record(stream)
+        evs = evs or [torch.cuda.Event(enable_timing=False) for _ in range(6)]
+        evs[0].record(stream)                  # fork
+        s_rs.wait_event(evs[0])
+        s_gr.wait_event(evs[0])
         if not args.no_gram:
-            rs.gram_eig_solve(plan.handle, A, t, n, Ug, Sg, Vg, Kg)
-        if evs:
-            evs[2].record(stream)
+            evs[3].record(s_gr)
+            rs.gram_eig_solve(plan_g.handle, A, t, n, Ug, Sg, Vg, Kg)
+            evs[4].record(s_gr)
+            stream.wait_event(evs[4])
+        evs[1].record(s_rs)
+        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
+        evs[2].record(s_rs)
+        stream.wait_event(evs[2])              # join
+        evs[5].record(stream)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    st = rs.rsvd_plan_status(plan.handle)
+    plans = [plan] + ([plan_g] if plan_g is not None else [])
+    st = [rs.rsvd_plan_status(pl.handle) for pl in plans]
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     # per-kernel launch durations inside the timed steps: HIP events recorded
-    # by the library on the plan's stream around each timed kernel
-    rs.rsvd_plan_kernel_times(plan.handle, True)
+    # by the library on each plan's stream around each timed kernel
+    for pl in plans:
+        rs.rsvd_plan_kernel_times(pl.handle, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ktimes = rs.rsvd_plan_kernel_times(plan.handle, False)
+    kt = [rs.rsvd_plan_kernel_times(pl.handle, False) for pl in plans]
+    ktimes = {kind: max((x[kind] for x in kt), key=lambda v: v[1]) for kind in kt[0]}
     wall = t1 - t0
-    rs_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    gr_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    step_ms = [e[0].elapsed_time(e[2]) for e in evs]
-    status = rs.rsvd_plan_status(plan.handle)
+    rs_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    gr_ms = [e[3].elapsed_time(e[4]) for e in evs] if plan_g is not None else [0.0]
+    step_ms = [e[0].elapsed_time(e[5]) for e in evs]
+    status = [rs.rsvd_plan_status(pl.handle) for pl in plans]
+
+    # the same kernels without the other solve beside them (context for the
+    # per-kernel rooflines; outside the timed region): the two solves of each
+    # step one after the other
+    for pl in plans:
+        rs.rsvd_plan_kernel_times(pl.handle, True)
+    torch.cuda.synchronize()
+    for i in range(args.steps):
+        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
+        torch.cuda.synchronize()
+        if plan_g is not None:
+            rs.gram_eig_solve(plan_g.handle, A, t, n, Ug, Sg, Vg, Kg)
+            torch.cuda.synchronize()
+    kt = [rs.rsvd_plan_kernel_times(pl.handle, False) for pl in plans]
+    ktimes_iso = {kind: max((x[kind] for x in kt), key=lambda v: v[1]) for kind in kt[0]}
 
     if args.pmc_copy:
         # a plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read
@@ -565,6 +595,7 @@ def main():
     # live launch durations of the timed steps and the algorithmic counts
     b = 4
     roof, all_k = kernel_rooflines(ktimes, m, n, l, b, args.steps)
+    _, iso_k = kernel_rooflines(ktimes_iso, m, n, l, b, args.steps)
     rs_f, rs_b, gr_f, gr_b = algorithmic_counts(m, n, k, l, q, b)
     rs_med, gr_med = pct(rs_ms, 50), pct(gr_ms, 50)
     legs = {
@@ -611,7 +642,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, args.cpu_sample_rows, k, p, q, t, c["omega_seed"],
                            with_gram=not args.no_gram)
-    plan.close()
+    for pl in plans:
+        pl.close()
 
     value = args.steps / wall
     out = {
@@ -632,13 +664,15 @@ def main():
         "config": {"workload": f"PCA {m}x{n} fp32, sigma_i=1/i + N(0,1e-3) noise, centred; "
                                f"rSVD k={k} p={p} q={q} t={t} + A^T A route k=n={n}",
                    "m": m, "n": n, "k": k, "p": p, "q": q, "t": t,
-                   "step": "rsvd_solve + gram_eig_solve" if not args.no_gram else "rsvd_solve"},
+                   "step": ("rsvd_solve and gram_eig_solve on two streams, concurrently"
+                            if not args.no_gram else "rsvd_solve")},
         "legs": legs,
         "tflops_step": round((rs_f + (0 if args.no_gram else gr_f)) / (wall / args.steps) / 1e12, 2),
-        "status": rs.STATUS.get(status, status),
-        "status_warmup": rs.STATUS.get(st, st),
+        "status": [rs.STATUS.get(x, x) for x in status],
+        "status_warmup": [rs.STATUS.get(x, x) for x in st],
         "roofline": roof,
         "kernels": all_k,
+        "kernels_isolated": iso_k,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

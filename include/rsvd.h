@@ -306,7 +306,12 @@ typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
  * V, K), plus `status` (1 int32, device) that receives the instance's status
  * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV), and
  * for RSVD_BF16 / RSVD_FP8 batches and servers `col_scale` (n floats, device,
- * or NULL for unit scales) as in rsvd_solve_bf16; ignored otherwise. */
+ * or NULL for unit scales) as in rsvd_solve_bf16; ignored otherwise.
+ * `k_max` (servers only; 0 or <= k = off): adaptive rank -- while a solve
+ * ends with RSVD_WARN_THRESHOLD (the k values capture less than t of
+ * ||A||_F^2, Sec. 2.4) and k < k_max, the request is solved again with
+ * k = min(2k, k_max) ahead of the queue; U, S, V must then hold k_max
+ * columns (ldu, ldv >= k_max) and k_max + p <= the server's l_max. */
 typedef struct {
   const void* A;
   int64_t m, n, lda;
@@ -320,6 +325,7 @@ typedef struct {
   int32_t* K;
   int32_t* status;
   const float* col_scale;
+  int32_t k_max;
 } rsvd_instance;
 
 /* Create a batch of nslots (1..64) slots for problems of one dtype (any of

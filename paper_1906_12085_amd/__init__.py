@@ -50,7 +50,7 @@ class RsvdInstance(ctypes.Structure):
                 ("q", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_void_p),
                 ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
                 ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("col_scale", ctypes.c_void_p)]
+                ("col_scale", ctypes.c_void_p), ("k_max", ctypes.c_int32)]
 
 
 def _dtype_codes(torch):
@@ -451,7 +451,7 @@ class Batch:
             arr[i] = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t),
                                   o["U"].data_ptr(), _ld(o["U"]), o["S"].data_ptr(),
                                   o["V"].data_ptr(), _ld(o["V"]), o["K"].data_ptr(),
-                                  o["status"].data_ptr(), _ptr(cs))
+                                  o["status"].data_ptr(), _ptr(cs), 0)
             o["col_scale"] = cs
             outs.append(o)
         return outs, arr
@@ -513,17 +513,21 @@ class Server:
         self.results = {}
         self._buf = (ctypes.c_int64 * 1024)()
 
-    def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None) -> int:
+    def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None, k_max: int = 0) -> int:
+        """Queue a request; with k_max > k its rank doubles (up to k_max)
+        while t is not reached, and U, S, V hold k_max columns."""
         torch = self.torch
         m, n = A.shape
-        o = dict(U=torch.empty((m, k), dtype=self.dtype, device=self.device),
-                 V=torch.empty((n, k), dtype=self.dtype, device=self.device),
-                 S=torch.empty((k,), dtype=torch.float64, device=self.device),
+        kc = max(k, k_max)
+        o = dict(U=torch.empty((m, kc), dtype=self.dtype, device=self.device),
+                 V=torch.empty((n, kc), dtype=self.dtype, device=self.device),
+                 S=torch.empty((kc,), dtype=torch.float64, device=self.device),
                  K=torch.empty((1,), dtype=torch.int32, device=self.device),
                  status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
         req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), o["U"].data_ptr(),
                            _ld(o["U"]), o["S"].data_ptr(), o["V"].data_ptr(), _ld(o["V"]),
-                           o["K"].data_ptr(), o["status"].data_ptr(), _ptr(col_scale))
+                           o["K"].data_ptr(), o["status"].data_ptr(), _ptr(col_scale),
+                           int(k_max))
         o["col_scale"] = col_scale
         tk = ctypes.c_int64()
         _check(load_library().rsvd_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)),

@@ -1244,7 +1244,7 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph) {
 // by polling each busy slot's completion event.
 struct rsvd_server_s {
   struct Req {
-    rsvd_instance x;
+    rsvd_instance x;   // x.k: the rank of the next (or running) solve
     int64_t ticket = 0;
     int64_t bytes = 0;
   };
@@ -1252,7 +1252,7 @@ struct rsvd_server_s {
   int64_t budget = 0, in_use = 0, next_ticket = 0;
   std::deque<Req> queue;
   std::vector<int64_t> slot_ticket;   // -1: free
-  std::vector<int64_t> slot_bytes;
+  std::vector<Req> slot_req;
   std::deque<int64_t> finished;
 };
 
@@ -1281,14 +1281,16 @@ int32_t server_admit(rsvd_server_s* sv) {
     if (rc != RSVD_OK) return rc;
     RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
     sv->slot_ticket[s] = r.ticket;
-    sv->slot_bytes[s] = r.bytes;
+    sv->slot_req[s] = r;
     sv->in_use += r.bytes;
     sv->queue.pop_front();
   }
   return RSVD_OK;
 }
 
-// Retire the busy slots whose completion event has fired.
+// Retire the busy slots whose completion event has fired; a request with
+// rank to spare whose solve did not reach t goes back to the head of the
+// queue with twice the rank.
 int32_t server_retire(rsvd_server_s* sv, bool wait) {
   rsvd_batch_s* b = sv->b;
   for (int s = 0; s < (int)sv->slot_ticket.size(); ++s) {
@@ -1296,10 +1298,23 @@ int32_t server_retire(rsvd_server_s* sv, bool wait) {
     const hipError_t e = wait ? hipEventSynchronize(b->done[s]) : hipEventQuery(b->done[s]);
     if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) return RSVD_ERR_DEVICE;
-    sv->finished.push_back(sv->slot_ticket[s]);
-    sv->in_use -= sv->slot_bytes[s];
+    rsvd_server_s::Req r = sv->slot_req[s];
+    sv->in_use -= r.bytes;
     sv->slot_ticket[s] = -1;
-    sv->slot_bytes[s] = 0;
+    if (r.x.k_max > r.x.k) {
+      int32_t st = RSVD_OK;   // the slot's stream is idle: this copy returns at once
+      if (hipMemcpyAsync(&st, r.x.status, sizeof(st), hipMemcpyDeviceToHost, b->stream[s]) !=
+              hipSuccess ||
+          hipStreamSynchronize(b->stream[s]) != hipSuccess)
+        return RSVD_ERR_DEVICE;
+      if (st == RSVD_WARN_THRESHOLD) {
+        r.x.k = (r.x.k * 2 < r.x.k_max) ? r.x.k * 2 : r.x.k_max;
+        r.bytes = request_bytes(sv, r.x);
+        sv->queue.push_front(r);
+        continue;
+      }
+    }
+    sv->finished.push_back(r.ticket);
   }
   return RSVD_OK;
 }
@@ -1330,7 +1345,7 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
   sv->b = b;
   sv->budget = hbm_budget;
   sv->slot_ticket.assign(nslots, -1);
-  sv->slot_bytes.assign(nslots, 0);
+  sv->slot_req.assign(nslots, rsvd_server_s::Req());
   *server = sv;
   return RSVD_OK;
 }
@@ -1338,8 +1353,13 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
 int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64_t* ticket) {
   if (!server || !req || !ticket) return RSVD_ERR_ARG;
   const rsvd_instance& x = *req;
-  const int32_t rc = check_instance(server->b->plan[0], x);
+  int32_t rc = check_instance(server->b->plan[0], x);
   if (rc != RSVD_OK) return rc;
+  if (x.k_max > x.k) {   // every rank the request may grow to must fit
+    rsvd_instance y = x;
+    y.k = x.k_max;
+    if ((rc = check_instance(server->b->plan[0], y)) != RSVD_OK) return rc;
+  }
   if (hipSetDevice(server->b->device) != hipSuccess) return RSVD_ERR_DEVICE;
   rsvd_server_s::Req r;
   r.x = x;

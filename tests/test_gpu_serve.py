@@ -175,3 +175,37 @@ def test_serve_low_precision_same_alone_and_oracle(fmt):
         assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
     sv.close()
     quant.close()
+
+
+def test_serve_adaptive_rank():
+    # with k_max the rank doubles while t is not reached: the result equals
+    # the solo solve at the first rank of k, 2k, 4k, ... (capped at k_max)
+    # that reaches t, or at k_max
+    dt = torch.float32
+    announce("serve: adaptive rank, 6 requests, k = 4 growing to at most 32")
+    reqs = requests(dt, 6, 23)
+    sv = rs.Server(3, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    pending, seen, tickets = set(), [], []
+    for A, _, p, q, t, _ in reqs:
+        tickets.append(sv.submit(A, 4, p, q, t, k_max=32))
+        pending.add(tickets[-1])
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    alone = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    grew = 0
+    for tk, (A, _, p, q, t, A0) in zip(tickets, reqs):
+        n = A.shape[1]
+        k = 4
+        while True:
+            ref = alone.solve(A, k, p, q, t)
+            if ref.status != rs.RSVD_WARN_THRESHOLD or k >= 32:
+                break
+            k = min(2 * k, 32)
+        grew += k > 4
+        o = sv.results[tk]
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+        assert torch.equal(o["S"][:k], ref.S) and torch.equal(o["V"][:, :k], ref.V)
+        assert torch.equal(o["U"][:, :k], ref.U)
+    assert grew >= 2                            # the case is exercised
+    alone.close()
+    sv.close()

@@ -376,7 +376,7 @@ def serve_leg(rs, torch, dev, nslots, storage=None):
     pool = synth.serve_pool(c)
     mmax = max(m for m, _, _ in pool)
     nmax = max(n for _, n, _ in pool)
-    l = c["k"] + c["p"]
+    l = c["k_max"] + c["p"]
     mats, scales = [], []
     quant = rs.Plan(mmax, nmax, l, storage, seed=c["seed"]) if storage is not None else None
     for i, (m, n, a) in enumerate(pool):
@@ -399,7 +399,9 @@ def serve_leg(rs, torch, dev, nslots, storage=None):
                    seed=c["seed"], hbm_budget=64 << 30)
 
     def submit(j, t):
-        return sv.submit(mats[j], c["k"], c["p"], c["q"], t, col_scale=scales[j])
+        # adaptive rank: k doubles from k up to k_max while t is not reached
+        return sv.submit(mats[j], c["k"], c["p"], c["q"], t, col_scale=scales[j],
+                         k_max=c["k_max"])
 
     for j in range(2):                                   # warm-up, not timed
         submit(j, 0.95)
@@ -430,7 +432,8 @@ def serve_leg(rs, torch, dev, nslots, storage=None):
                 Ks[idx] = int(o["K"].item())
                 st = rs.STATUS.get(int(o["status"].item()), int(o["status"].item()))
                 statuses[st] = statuses.get(st, 0) + 1
-                f, _, _, _ = algorithmic_counts(m, n, c["k"], min(l, n), c["q"], 4)
+                kk = min(max(c["k"], Ks[idx]), c["k_max"], n)
+                f, _, _, _ = algorithmic_counts(m, n, kk, min(kk + c["p"], n), c["q"], 4)
                 flops += f
     wall = time.perf_counter() - t0
     # capacity: the same requests back to back, 32 outstanding
@@ -454,10 +457,13 @@ def serve_leg(rs, torch, dev, nslots, storage=None):
             "latency_ms": {"p50": round(pct(lat, 50), 2), "p99": round(pct(lat, 99), 2),
                            "max": round(max(lat), 2)},
             "capacity_solves_per_s": round(nreq / cap_s, 1),
-            "tflops": round(flops / wall / 1e12, 2), "max_queued": max_q, "max_running": max_r,
+            "tflops_at_final_rank": round(flops / wall / 1e12, 2), "max_queued": max_q,
+            "max_running": max_r,
             "pool": {"matrices": len(pool), "m_range": [min(m for m, _, _ in pool), mmax],
                      "n_set": sorted({n for _, n, _ in pool})},
-            "status_counts": statuses, "_K": [Ks[i] for i in range(nreq)]}
+            "status_counts": statuses, "K_mean": round(sum(Ks.values()) / max(1, nreq), 2),
+            "rank": {"k_start": c["k"], "k_max": c["k_max"]},
+            "_K": [Ks[i] for i in range(nreq)]}
 
 
 def pct(xs, p):

@@ -159,7 +159,7 @@ def batch_shapes(c=None):
 
 CONFIG5 = dict(rate=200.0, seconds=8.0, m_lo=1000, m_hi=1_000_000, m_multiple=64,
                n_choices=(128, 256, 512, 1024), alpha_lo=0.5, alpha_hi=2.0,
-               t_choices=(0.9, 0.95, 0.99), k=32, p=8, q=2, pool=24, seed=5)
+               t_choices=(0.9, 0.95, 0.99), k=16, k_max=64, p=8, q=2, pool=24, seed=5)
 
 
 def serve_pool(c=None):

@@ -477,7 +477,7 @@ def pct(xs, p):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the row-sharded multi-GPU "
+        print(json.dumps({"error": "only the one-GPU path is implemented; the row-sharded multi-GPU "
                                    "design is documented but not built (use --gpus 1)"}))
         sys.exit(2)
 

@@ -298,7 +298,9 @@ int32_t rsvd_sym_eig(rsvd_plan_t plan, const double* G, int64_t n, double* lam, 
  * join back into the caller's stream, so a batch is ordered like one kernel
  * on that stream, and the whole fork-join can be captured into a HIP graph
  * once and replayed (rsvd_batch_graph_*) for repeated batches of the same
- * shapes and pointers. */
+ * shapes and pointers.  Solves and graph launches of one batch must not
+ * overlap on the device (they share the slots): order them on one stream,
+ * or synchronise in between. */
 typedef struct rsvd_batch_s* rsvd_batch_t;
 typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
 
@@ -372,7 +374,10 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
  * slots are as in a batch (a plan and a stream each, same sizes and seed):
  * a request's results do not depend on what else runs (bit for bit).
  * Footprint of a request: its A (m lda elements), the two m x l panels of
- * its plan and the split partials of its A^T Q products (n l FP64 per split). */
+ * its plan and the split partials of its A^T Q products (n l FP64 per split).
+ * A server is driven from one host thread at a time (its calls must not
+ * overlap).  After RSVD_ERR_DEVICE from any call its state is undefined:
+ * destroy it. */
 typedef struct rsvd_server_s* rsvd_server_t;
 
 /* Create a server with nslots slots (1..64) for requests of one dtype (as

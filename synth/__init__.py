@@ -138,6 +138,15 @@ def config2_sigma(n: int = 512) -> np.ndarray:
     return 1.0 / np.arange(1, n + 1, dtype=np.float64)
 
 
+CONFIG3 = dict(m=262_144, n=1024, k=128, p=32, q=3, t=0.95, seed=3, omega_seed=303,
+               noise_std=1e-4)
+
+
+def config3_sigma(n: int = 1024) -> np.ndarray:
+    """sigma_i = 1/sqrt(i), i = 1..n (slow decay)."""
+    return 1.0 / np.sqrt(np.arange(1, n + 1, dtype=np.float64))
+
+
 CONFIG4 = dict(count=512, m_lo=4096, m_hi=65536, n_choices=(64, 128, 256, 512), r_lo=0.01,
                r_hi=0.2, k_max=32, p=8, q=2, t=0.95, seed=4)
 

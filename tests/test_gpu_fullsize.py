@@ -145,3 +145,39 @@ def test_fullsize_gram_route_vs_oracle(workload):
     d[d == 0] = 1.0
     sel = np.where(sep)[0]
     assert np.max(np.abs(Ug_rows[:, sel] * d[sel] - Uo_rows[:, sel])) <= 1e-4
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_config3_shape_lowp_vs_oracle(fmt):
+    # the mixed-precision workload's matrix (262144 x 1024, sigma_i = 1/sqrt(i)
+    # plus N(0, 1e-4) noise, columns centred) stored in bfloat16 / FP8 E4M3
+    # with power-of-two column scales, q = 3, at the widest sketch the
+    # library holds: k = 64, p = 32 (l = 96; the workload's k = 128, p = 32
+    # would need l = 160).  Oracle on the dequantised stored matrix, same G.
+    c = synth.CONFIG3
+    m, n, q, t = c["m"], c["n"], c["q"], c["t"]
+    k, p = 64, 32
+    l = k + p
+    announce(f"config-3 shape: generating A {m}x{n}, {fmt} storage, k={k} p={p} q={q}")
+    A = synth.spiked_noisy_torch(c["seed"], m, n, synth.config3_sigma(n), c["noise_std"],
+                                 torch.device("cuda", 0), torch.float32)
+    storage = torch.bfloat16 if fmt == "bf16" else torch.float8_e4m3fn
+    plan = rs.Plan(m, n, l, storage, seed=c["omega_seed"])
+    Aq, s = plan.quantize(A)
+    del A
+    res = plan.solve(Aq, k, p, q, t, col_scale=s)
+    plan.close()
+    A64 = (Aq.double() * s.double()[None, :]).cpu().numpy()
+    del Aq
+    G = synth.gaussian_omega(c["omega_seed"], n, l).astype(np.float32).astype(np.float64)
+    announce("config-3 shape: oracle rsvd on the dequantised matrix (tens of seconds)")
+    ref = oracle.rsvd(A64, G, k, p, q, t)
+    S, U, V = host(res.S), host(res.U), host(res.V)
+    sig = float(np.max(np.abs(S - ref.S) / ref.S))
+    av = oracle.principal_angle_max(ref.V, V)
+    au = oracle.principal_angle_max(ref.U, U)
+    announce(f"config-3 shape {fmt}: sigma rel err {sig:.2e}, angle V {av:.2e}, angle U {au:.2e}, "
+             f"K {res.K} (oracle {ref.K})")
+    assert sig <= 1e-4 and av <= 1e-3 and au <= 1e-3
+    assert res.K == ref.K and res.status == ref.status

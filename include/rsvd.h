@@ -365,6 +365,25 @@ int32_t rsvd_batch_graph_launch(rsvd_batch_graph_t graph, void* stream);
 /* Free a captured batch (synchronises nothing; NULL is a no-op). */
 int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
 
+/* Grouped batches: the same solves as rsvd_batch_solve for RSVD_F32
+ * instances, with every step one launch for all instances (instead of one
+ * chain of launches per instance on the slots), which removes the
+ * per-instance launch latency that bounds batches of small problems.
+ * rsvd_batch_grouped_create validates the instances (as rsvd_batch_solve;
+ * further RSVD_ERR_ARG unless A is 16-byte aligned with lda and n multiples
+ * of 4 and l = min(k + p, n) a multiple of 4), allocates one workspace per
+ * instance, sized for it, and records the launches with their arguments
+ * (uploaded once); nothing runs.  rsvd_batch_grouped_launch runs them on
+ * `stream`: results as rsvd_solve on a plan with the batch's seed, bit for
+ * bit.  Instances with equal l, k and q share launches.  One launch of a
+ * grouped batch at a time; rsvd_batch_grouped_destroy synchronises the
+ * device and frees it. */
+typedef struct rsvd_grouped_s* rsvd_grouped_t;
+int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                  rsvd_grouped_t* grouped);
+int32_t rsvd_batch_grouped_launch(rsvd_grouped_t grouped, void* stream);
+int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped);
+
 /* ------------------------------------------------------------- serving --
  * Continuous batching of Randomized PCA requests (Sec. 3.1.2 each): requests
  * are queued in arrival order and admitted, first come first served, as

@@ -40,7 +40,8 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_batch_create", "rsvd_batch_destroy", "rsvd_batch_solve",
            "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_progress",
-           "rsvd_server_destroy"]
+           "rsvd_server_destroy", "rsvd_batch_grouped_create", "rsvd_batch_grouped_launch",
+           "rsvd_batch_grouped_destroy"]
 
 
 class RsvdInstance(ctypes.Structure):
@@ -103,6 +104,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_server_progress": (i32, [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "rsvd_server_destroy": (i32, [vp]),
+        "rsvd_batch_grouped_create": (i32, [vp, ctypes.POINTER(RsvdInstance), i32,
+                                            ctypes.POINTER(vp)]),
+        "rsvd_batch_grouped_launch": (i32, [vp, vp]),
+        "rsvd_batch_grouped_destroy": (i32, [vp]),
         "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
         "rsvd_gaussian_fill": (i32, [u64, i64, i64, vp, vp]),
         "rsvd_gemm_nn": (i32, [vp, vp, i64, i64, i64, vp, i64, i32, vp, i64, vp, vp]),
@@ -462,12 +467,46 @@ class Batch:
                "rsvd_batch_solve")
         return outs
 
+    def grouped(self, problems, prepared=None):
+        """The same solves as a grouped batch (fp32 batches only)."""
+        outs, arr = prepared if prepared is not None else self.prepare(problems)
+        g = ctypes.c_void_p()
+        _check(load_library().rsvd_batch_grouped_create(self.handle, arr, len(arr),
+                                                        ctypes.byref(g)),
+               "rsvd_batch_grouped_create")
+        return BatchGrouped(g.value, outs)
+
     def graph(self, problems, prepared=None):
         outs, arr = prepared if prepared is not None else self.prepare(problems)
         g = ctypes.c_void_p()
         _check(load_library().rsvd_batch_graph_create(self.handle, arr, len(arr), None,
                                                       ctypes.byref(g)), "rsvd_batch_graph_create")
         return BatchGraph(g.value, outs)
+
+
+class BatchGrouped:
+    """A grouped batch (rsvd_batch_grouped_*): every step one launch for all
+    problems; launch() runs it on a stream."""
+
+    def __init__(self, handle, outs):
+        self.handle, self.outs = handle, outs
+
+    def launch(self, stream=None):
+        _check(load_library().rsvd_batch_grouped_launch(self.handle, _stream_ptr(stream)),
+               "rsvd_batch_grouped_launch")
+        return self.outs
+
+    def close(self):
+        if self.handle:
+            _check(load_library().rsvd_batch_grouped_destroy(self.handle),
+                   "rsvd_batch_grouped_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchGraph:

@@ -34,7 +34,13 @@ template <typename T, int NT, int MR, bool VEC>
 __global__ __launch_bounds__(kNNThreads) void k_gemm_nn(
     const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, const T* __restrict__ X,
     int64_t ldx, int c, T* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part,
-    int ncol_tiles) {
+    int ncol_tiles, const GArgNn* __restrict__ grp) {
+  if (grp) {
+    const GArgNn& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = (const T*)a.A; m = a.m; n = a.n; lda = a.lda; X = (const T*)a.X; ldx = a.ldx; c = a.c;
+    Y = (T*)a.Y; ldy = a.ldy; fro2_part = a.fro2; ncol_tiles = a.ncol_tiles;
+  }
   typedef Mfma<T> M;
   typedef typename M::acc_t acc_t;
   typedef typename Vec16<T>::type vec_t;
@@ -515,7 +521,14 @@ constexpr int kTQ = kTK / 4, kTUA = kTM * kTQ / 256;   // k-quads per row, A loa
 template <int NT>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
-    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part) {
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part,
+    const GArgTall* __restrict__ grp) {
+  if (grp) {
+    const GArgTall& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = a.A; m = a.m; n = a.n; lda = a.lda; Xt = a.Xt; ldxt = a.ldxt; c = a.c; Y = a.Y;
+    ldy = a.ldy; fro2_part = a.fro2;
+  }
   constexpr int BC = 16 * NT;
   constexpr int XU = (BC * (kTK / 4) + 255) / 256;   // float4 of the Xt chunk per thread
   __shared__ __attribute__((aligned(16))) float As[2][kTM * kTLD];
@@ -657,7 +670,14 @@ constexpr int kNM = 128;
 template <int NT, int NS>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
-    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy) {
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, const GArgNarrow* __restrict__ grp) {
+  int64_t nbx = gridDim.x;   // blocks of this problem: the stride of the persistent loop
+  if (grp) {
+    const GArgNarrow& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = a.A; m = a.m; n = a.n; lda = a.lda; Xt = a.Xt; ldxt = a.ldxt; c = a.c; Y = a.Y;
+    ldy = a.ldy; nbx = a.nblk;
+  }
   constexpr int BC = 16 * NT, KP = 16 * NS, LD = KP + 4;
   __shared__ __attribute__((aligned(16))) float Bs[BC * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -690,13 +710,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
     *reinterpret_cast<f32x4*>(&Bs[r * LD + 4 * q]) = v;
   }
   __syncthreads();
-  for (; tl < ntile; tl += gridDim.x) {
+  for (; tl < ntile; tl += nbx) {
     f32x4 af[NS][2];
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
       for (int i = 0; i < 2; ++i) af[sl][i] = nxt[sl][i];
-    const int64_t tn = tl + gridDim.x;
+    const int64_t tn = tl + nbx;
     load(tn < ntile ? tn : tl, nxt);          // the last prefetch is a harmless repeat
     __builtin_amdgcn_sched_barrier(0);
     f32x4 acc[2][NT];
@@ -750,7 +770,14 @@ constexpr int kUK = 16, kUA = 512, kUALD = kUA + 16;
 template <int NT>
 __global__ __launch_bounds__(512) void k_gemm_tn_tall(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
-    int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P) {
+    int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P,
+    const GArgTn* __restrict__ grp) {
+  if (grp) {
+    const GArgTn& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = a.A; m = a.m; n = a.n; lda = a.lda; Q = a.Q; ldq = a.ldq; c = a.c; rps = a.rps;
+    ntile = a.ntile; P = a.P;
+  }
   constexpr int BC = 16 * NT;
   constexpr int QLD = BC + ((16 - BC) % 64 + 64) % 64;
   constexpr int QU = BC / 4 * kUK;               // float4 of the Q chunk
@@ -845,17 +872,18 @@ __global__ __launch_bounds__(512) void k_gemm_tn_tall(
 template <typename T, int NT, int MR>
 hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                        int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
-  const int ncol_tiles = (c + 16 * NT - 1) / (16 * NT);
-  const int64_t nrow_blocks = (m + 64 * MR - 1) / (64 * MR);
+  const int ncol_tiles = nn_col_tiles(c, NT);
+  const int64_t nrow_blocks = nn_row_blocks(m);
+  static_assert(MR == 2, "nn_row_blocks assumes two 16-row tiles per wave");
   if (nparts) *nparts = (int)nrow_blocks;
   const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && ((lda * sizeof(T)) % 16 == 0);
   dim3 grid((unsigned)(nrow_blocks * ncol_tiles));
   if (vec)
     hipLaunchKernelGGL((k_gemm_nn<T, NT, MR, true>), grid, dim3(kNNThreads), 0, s, A, m, n, lda,
-                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles);
+                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles, nullptr);
   else
     hipLaunchKernelGGL((k_gemm_nn<T, NT, MR, false>), grid, dim3(kNNThreads), 0, s, A, m, n, lda,
-                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles);
+                       X, ldx, c, Y, ldy, fro2_part, ncol_tiles, nullptr);
   return hipGetLastError();
 }
 
@@ -1003,7 +1031,13 @@ template <typename T, int NT>
 __global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64(const T* __restrict__ Y, int64_t m,
                                                             int c, int64_t ldy,
                                                             double* __restrict__ P,
-                                                            int64_t rows_per_block) {
+                                                            int64_t rows_per_block,
+                                                            const GArgGram* __restrict__ grp) {
+  if (grp) {
+    const GArgGram& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    Y = (const T*)a.Y; m = a.m; c = a.c; ldy = a.ldy; P = a.P; rows_per_block = a.rpb;
+  }
   typedef Mfma<double> M;
   constexpr int NP = NT * (NT + 1) / 2;
   constexpr int U = 2;                       // 4-row groups per register set
@@ -1093,24 +1127,26 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64(const T* __restric
 template <typename T, int NT>
 hipError_t gram_dispatch(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
                          int* nsplit, hipStream_t s) {
-  int64_t blocks = (m + 255) / 256;          // at least 256 rows per block
-  if (blocks > max_split) blocks = max_split;
-  if (blocks < 1) blocks = 1;
-  int64_t rpb = (m + blocks - 1) / blocks;
-  rpb = (rpb + 3) / 4 * 4;
-  blocks = (m + rpb - 1) / rpb;
+  int64_t rpb = 0;
+  const int64_t blocks = gram_blocks(m, max_split, &rpb);
   *nsplit = (int)blocks;
   const size_t shmem = (size_t)c * c * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_gram_f64<T, NT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_gram_f64<T, NT>), dim3((unsigned)blocks), dim3(kGramWaves * 64), shmem, s,
-                     Y, m, c, ldy, P, rpb);
+                     Y, m, c, ldy, P, rpb, nullptr);
   return hipGetLastError();
 }
 
 __global__ void k_reduce_partials(const double* __restrict__ P, int nsplit, int64_t rows,
-                                  int64_t cols, double* __restrict__ Z, int64_t ldz) {
+                                  int64_t cols, double* __restrict__ Z, int64_t ldz,
+                                  const GArgRed* __restrict__ grp) {
+  if (grp) {
+    const GArgRed& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    P = a.P; nsplit = a.nsplit; rows = a.rows; cols = a.cols; Z = a.Z; ldz = a.ldz;
+  }
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = rows * cols;
   if (idx >= total) return;
@@ -1128,7 +1164,12 @@ __global__ void k_reduce_partials(const double* __restrict__ P, int nsplit, int6
   Z[i * ldz + j] = s;
 }
 
-__global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double* out) {
+__global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double* out,
+                                const GArgRedS* __restrict__ grp) {
+  if (grp) {
+    const GArgRedS& a = grp[blockIdx.y];
+    parts = a.parts; n = a.n; out = a.out;
+  }
   // fixed order: 256 strided lanes, then a fixed tree
   __shared__ double sh[256];
   double s = 0.0;
@@ -1152,13 +1193,11 @@ constexpr int kNarrowSlabs = 6;
 template <int NT>
 hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                      int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
-  // persistent: up to two blocks per CU of the 256
-  const int64_t ntile = (m + kNM - 1) / kNM;
-  const dim3 grid((unsigned)(ntile < 512 ? ntile : 512)), block(256);
+  const dim3 grid((unsigned)narrow_blocks(m)), block(256);
 #define RSVD_NT_NARROW(NS)                                                                     \
   case NS:                                                                                     \
     hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, \
-                       Y, ldy);                                                                \
+                       Y, ldy, nullptr);                                                       \
     break;
   switch (ns) {
     RSVD_NT_NARROW(1) RSVD_NT_NARROW(2) RSVD_NT_NARROW(3)
@@ -1195,7 +1234,7 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
                                int64_t ldxt, int c, float* Y, int64_t ldy, double* fro2_part,
                                int* nparts, hipStream_t s) {
   if (!nt_tall_applies(A, n, lda, Xt, ldxt, c)) return hipErrorInvalidValue;
-  const int64_t nblk = (m + kTM - 1) / kTM;
+  const int64_t nblk = tall_blocks(m);
   if (nparts) *nparts = (int)nblk;
   if (m <= 0) return hipSuccess;
   if (!fro2_part && n <= 16 * kNarrowSlabs) return launch_gemm_nt_narrow(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
@@ -1203,7 +1242,7 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
 #define RSVD_NT_TALL(NT)                                                                      \
   case NT:                                                                                    \
     hipLaunchKernelGGL(k_gemm_nt_tall<NT>, grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, Y, ldy, \
-                       fro2_part);                                                            \
+                       fro2_part, nullptr);                                                   \
     break;
   switch ((c + 15) / 16) {
     RSVD_NT_TALL(1) RSVD_NT_TALL(2) RSVD_NT_TALL(3) RSVD_NT_TALL(4)
@@ -1223,15 +1262,9 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
                                int64_t ldq, int c, double* P, int64_t max_split, int* nsplit,
                                hipStream_t s) {
   if (!tn_tall_applies(A, lda, Q, ldq, c) || m <= 0) return hipErrorInvalidValue;
-  const int ntile = (int)((n + kUA - 1) / kUA);
-  // about one block per CU (256), whole 16-row chunks
-  int64_t ns = 256 / ntile;
-  if (ns < 1) ns = 1;
-  if (ns > (m + kUK - 1) / kUK) ns = (m + kUK - 1) / kUK;
-  if (ns > max_split) ns = max_split;
-  int64_t rps = (m + ns - 1) / ns;
-  rps = (rps + kUK - 1) / kUK * kUK;
-  ns = (m + rps - 1) / rps;
+  int ntile = 0;
+  int64_t rps = 0;
+  const int64_t ns = tn_tall_splits(m, n, max_split, &rps, &ntile);
   const int64_t ld = lda > ldq ? lda : ldq;
   if (rps * ld * 4 >= (1LL << 31) || (int64_t)(kUK - 1) * lda * 4 + (int64_t)ntile * kUA * 4 >= (1LL << 31))
     return hipErrorInvalidValue;
@@ -1239,7 +1272,8 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
   const dim3 grid((unsigned)(ns * ntile)), block(512);
 #define RSVD_TN_TALL(NT)                                                                          \
   case NT:                                                                                        \
-    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps, ntile, P); \
+    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps, ntile, P, \
+                       nullptr);                                                               \
     break;
   switch ((c + 15) / 16) {
     RSVD_TN_TALL(1) RSVD_TN_TALL(2) RSVD_TN_TALL(3) RSVD_TN_TALL(4)
@@ -1374,12 +1408,181 @@ hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int
   const int64_t total = rows * cols;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     P, nsplit, rows, cols, Z, ldz);
+                     P, nsplit, rows, cols, Z, ldz, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_scalar(const double* parts, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(256), 0, s, parts, n, out);
+  hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(256), 0, s, parts, n, out, nullptr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry (shared by the ordinary and the grouped launchers).
+int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block) {
+  int64_t blocks = (m + 255) / 256;          // at least 256 rows per block
+  if (blocks > max_split) blocks = max_split;
+  if (blocks < 1) blocks = 1;
+  int64_t rpb = (m + blocks - 1) / blocks;
+  rpb = (rpb + 3) / 4 * 4;
+  *rows_per_block = rpb;
+  return (m + rpb - 1) / rpb;
+}
+
+int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_per_split,
+                       int* ntile_out) {
+  const int ntile = (int)((n + kUA - 1) / kUA);
+  // about one block per CU (256), whole 16-row chunks
+  int64_t ns = 256 / ntile;
+  if (ns < 1) ns = 1;
+  if (ns > (m + kUK - 1) / kUK) ns = (m + kUK - 1) / kUK;
+  if (ns > max_split) ns = max_split;
+  int64_t rps = (m + ns - 1) / ns;
+  rps = (rps + kUK - 1) / kUK * kUK;
+  *rows_per_split = rps;
+  *ntile_out = ntile;
+  return (m + rps - 1) / rps;
+}
+
+// persistent: up to two blocks per CU of the 256
+int64_t narrow_blocks(int64_t m) {
+  const int64_t ntile = (m + kNM - 1) / kNM;
+  return ntile < 512 ? ntile : 512;
+}
+
+int64_t tall_blocks(int64_t m) { return (m + kTM - 1) / kTM; }
+
+int nn_col_tiles(int c, int nt) { return (c + 16 * nt - 1) / (16 * nt); }
+
+int64_t nn_row_blocks(int64_t m) { return (m + 128 - 1) / 128; }
+
+// ---------------------------------------------------------------------------
+// Grouped launchers (one launch, blockIdx.y = problem).
+hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, int count, int maxblk, int nt,
+                                       hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  const dim3 grid((unsigned)maxblk, (unsigned)count), block(256);
+#define RSVD_G(NT)                                                                              \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL(k_gemm_nt_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0,  \
+                       nullptr, 0, nullptr, a);                                                 \
+    break;
+  switch (nt) {
+    RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_G
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t narrow_grouped(const GArgNarrow* a, int count, int maxblk, int ns, hipStream_t s) {
+  const dim3 grid((unsigned)maxblk, (unsigned)count), block(256);
+#define RSVD_G(NS)                                                                              \
+  case NS:                                                                                      \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
+                       0, 0, nullptr, 0, a);                                                    \
+    break;
+  switch (ns) {
+    RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_G
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int maxblk, int nt,
+                                         int ns, hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  switch (nt) {
+    case 1: return narrow_grouped<1>(a, count, maxblk, ns, s);
+    case 2: return narrow_grouped<2>(a, count, maxblk, ns, s);
+    case 3: return narrow_grouped<3>(a, count, maxblk, ns, s);
+    case 4: return narrow_grouped<4>(a, count, maxblk, ns, s);
+    case 5: return narrow_grouped<5>(a, count, maxblk, ns, s);
+    case 6: return narrow_grouped<6>(a, count, maxblk, ns, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt,
+                                       hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  const dim3 grid((unsigned)maxblk, (unsigned)count), block(512);
+#define RSVD_G(NT)                                                                              \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0,  \
+                       0, 1, nullptr, a);                                                       \
+    break;
+  switch (nt) {
+    RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_G
+  return hipGetLastError();
+}
+
+template <typename T, int NT>
+hipError_t gram_grouped(const GArgGram* a, int count, int maxblk, int cmax, hipStream_t s) {
+  const size_t shmem = (size_t)cmax * cmax * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gram_f64<T, NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gram_f64<T, NT>), dim3((unsigned)maxblk, (unsigned)count),
+                     dim3(kGramWaves * 64), shmem, s, nullptr, 0, 0, 0, nullptr, 0, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram_f64_grouped(const GArgGram* a, int count, int maxblk, int nt, int cmax,
+                                   hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  switch (nt) {
+    case 1: return gram_grouped<T, 1>(a, count, maxblk, cmax, s);
+    case 2: return gram_grouped<T, 2>(a, count, maxblk, cmax, s);
+    case 3: return gram_grouped<T, 3>(a, count, maxblk, cmax, s);
+    case 4: return gram_grouped<T, 4>(a, count, maxblk, cmax, s);
+    case 5: return gram_grouped<T, 5>(a, count, maxblk, cmax, s);
+    case 6: return gram_grouped<T, 6>(a, count, maxblk, cmax, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_gram_f64_grouped<float>(const GArgGram*, int, int, int, int,
+                                                   hipStream_t);
+template hipError_t launch_gram_f64_grouped<double>(const GArgGram*, int, int, int, int,
+                                                    hipStream_t);
+
+hipError_t launch_reduce_partials_grouped(const GArgRed* a, int count, int maxblk, hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)maxblk, (unsigned)count), dim3(256), 0, s,
+                     nullptr, 0, 0, 0, nullptr, 0, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_scalar_grouped(const GArgRedS* a, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_scalar, dim3(1, (unsigned)count), dim3(256), 0, s, nullptr, 0,
+                     nullptr, a);
+  return hipGetLastError();
+}
+
+// FP64 Y = A X on the tiles an ordinary launch_gemm_nn<double> picks for c
+// (vectorised loads: every A of a grouped launch is 16-byte aligned with an
+// even leading dimension).
+hipError_t launch_gemm_nn_f64_grouped(const GArgNn* a, int count, int maxblk, int nt,
+                                      hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  const dim3 grid((unsigned)maxblk, (unsigned)count);
+#define RSVD_G(NT)                                                                              \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL((k_gemm_nn<double, NT, 2, true>), grid, dim3(kNNThreads), 0, s, nullptr, \
+                       0, 0, 0, nullptr, 0, 0, nullptr, 0, nullptr, 1, a);                      \
+    break;
+  switch (nt) {
+    RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6) RSVD_G(7) RSVD_G(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_G
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <deque>
+#include <functional>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1397,6 +1398,442 @@ int32_t rsvd_server_destroy(rsvd_server_t server) {
   batch_free(server->b);
   delete server;
   return rc;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Grouped batches: every step of Randomized PCA (Sec. 3.1.2) is one launch
+// for all instances of a batch (blockIdx.y = instance), instead of one chain
+// of launches per instance.  The argument records of all launches are built
+// once, from the instances' shapes and pointers, and uploaded once; a launch
+// of the grouped batch replays the recorded sequence.  Instances with the
+// same sketch width l and rank k share launches (their kernels' template
+// choices are the same); the groups run one after the other.
+struct rsvd_grouped_s {
+  struct Op {
+    int kind = 0;
+    size_t off = 0;
+    int count = 0, maxblk = 0, a0 = 0, a1 = 0;
+  };
+  int device = 0;
+  char* ws = nullptr;          // the instances' workspaces
+  char* args = nullptr;        // all argument records, device
+  std::vector<rsvd_plan_s> plans;
+  std::vector<Op> ops;
+};
+
+namespace {
+
+enum GKind {
+  G_RESET, G_FILL, G_CAST_T, G_TALL, G_NARROW, G_RED_S, G_GRAM_F, G_GRAM_D, G_RED, G_CHOL_F,
+  G_CHOL_D, G_TN, G_SG_F, G_SG_D, G_NN_D, G_JAC, G_JAC_ACC, G_SORT, G_SEL, G_TAKE
+};
+
+__global__ void k_status_grouped(const GArgStat* __restrict__ a) {
+  const GArgStat& g = a[blockIdx.y];
+  if (g.src) {
+    if (threadIdx.x == 0) *g.dst = *g.src;
+  } else {
+    if (threadIdx.x == 0) *g.dst = RSVD_OK;
+    if ((int)threadIdx.x < g.nd) g.diag[threadIdx.x] = 0.0;
+  }
+}
+
+struct GroupedBuilder {
+  std::vector<char> host;
+  std::vector<rsvd_grouped_s::Op> ops;
+  template <typename A>
+  void add(int kind, const std::vector<A>& rec, int a0 = 0, int a1 = 0) {
+    if (rec.empty()) return;
+    rsvd_grouped_s::Op op;
+    op.kind = kind;
+    op.off = (host.size() + 63) / 64 * 64;
+    op.count = (int)rec.size();
+    op.a0 = a0;
+    op.a1 = a1;
+    int mb = 0;
+    for (const A& r : rec) mb = r.nblk > mb ? r.nblk : mb;
+    op.maxblk = mb;
+    host.resize(op.off + rec.size() * sizeof(A));
+    memcpy(host.data() + op.off, rec.data(), rec.size() * sizeof(A));
+    ops.push_back(op);
+  }
+};
+
+int blocks256(int64_t total) { return (int)((total + 255) / 256); }
+
+// Whether the grouped path takes this fp32 instance: the tall kernels'
+// layout conditions for A, and a sketch width that is a multiple of 4.
+bool grouped_applies(const rsvd_instance& x) {
+  const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+  if (l % 4 != 0 || x.n % 4 != 0 || x.lda % 4 != 0) return false;
+  if (reinterpret_cast<uintptr_t>(x.A) % 16 != 0) return false;
+  if ((int64_t)128 * x.lda * 4 >= (1LL << 31)) return false;
+  int ntile = 0;
+  int64_t rps = 0;
+  tn_tall_splits(x.m, x.n, 256, &rps, &ntile);   // the largest split count gives the fewest rows
+  return rps * x.lda * 4 < (1LL << 31) && (int64_t)15 * x.lda * 4 + (int64_t)ntile * 512 * 4 < (1LL << 31);
+}
+
+// Record Randomized PCA (the steps and kernels of rsvd_run<float>) for the
+// instances `ix` (same l and k) on their workspaces `pl`.
+void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<int>& ix,
+                  std::vector<rsvd_plan_s>& pl, int l, int k) {
+  const int ntl = (l + 15) / 16;            // column tiles of l columns
+  const int ntk = (k + 15) / 16;
+  const int nsl = (l + 15) / 16;            // k slabs of an l-long contraction
+  auto P = [&](int i) -> rsvd_plan_s& { return pl[i]; };
+  auto X = [&](int i) -> const rsvd_instance& { return in[i]; };
+  {
+    std::vector<GArgStat> r;
+    for (int i : ix) r.push_back({nullptr, P(i).status, P(i).diag, kDiagWords, 1});
+    B.add(G_RESET, r);
+  }
+  {
+    std::vector<GArgFill> r;
+    for (int i : ix) {
+      const int64_t tot = X(i).n * (int64_t)l;
+      r.push_back({P(i).seed, tot, P(i).omega, blocks256((tot + 1) / 2)});
+    }
+    B.add(G_FILL, r);
+  }
+  // A X (X FP64, n x l) into Y; with fro2 on the first pass
+  auto pass_nn = [&](bool first, bool from_zq) {
+    std::vector<GArgCast> rc;
+    for (int i : ix) {
+      const int64_t n = X(i).n;
+      rc.push_back({from_zq ? P(i).Zq : P(i).omega, n, l, l, P(i).Xs, n, blocks256(n * l)});
+    }
+    B.add(G_CAST_T, rc);
+    std::vector<GArgTall> rt;
+    std::vector<std::vector<GArgNarrow>> rn(7);
+    for (int i : ix) {
+      const rsvd_instance& x = X(i);
+      if (first || x.n > 96) {
+        rt.push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Xs, x.n, l,
+                      (float*)P(i).Y, l, first ? P(i).fro2_part : nullptr, (int)tall_blocks(x.m)});
+      } else {
+        rn[(x.n + 15) / 16].push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Xs,
+                                       x.n, l, (float*)P(i).Y, l, (int)narrow_blocks(x.m)});
+      }
+    }
+    B.add(G_TALL, rt, ntl);
+    for (int ns = 1; ns <= 6; ++ns) B.add(G_NARROW, rn[ns], ntl, ns);
+    if (first) {
+      std::vector<GArgRedS> rs;
+      for (int i : ix) rs.push_back({P(i).fro2_part, (int)tall_blocks(X(i).m), P(i).scal, 1});
+      B.add(G_RED_S, rs);
+    }
+  };
+  // W (c x c) = Y^T Y, FP64 partials then their fixed-order sum
+  auto gram = [&](bool dbl, std::function<const void*(int)> Yp, std::function<int64_t(int)> rows) {
+    std::vector<GArgGram> rg;
+    std::vector<GArgRed> rr;
+    for (int i : ix) {
+      int64_t rpb = 0;
+      const int nb = (int)gram_blocks(rows(i), P(i).max_split, &rpb);
+      rg.push_back({Yp(i), rows(i), l, l, P(i).part, rpb, nb});
+      rr.push_back({P(i).part, nb, l, l, P(i).Wg, l, blocks256((int64_t)l * l)});
+    }
+    B.add(dbl ? G_GRAM_D : G_GRAM_F, rg, ntl, l);
+    B.add(G_RED, rr);
+  };
+  auto chol = [&](bool dbl, std::function<GArgChol(int)> f) {
+    std::vector<GArgChol> r;
+    for (int i : ix) r.push_back(f(i));
+    B.add(dbl ? G_CHOL_D : G_CHOL_F, r);
+  };
+  // CholeskyQR2 of Y (m x l): Q1 = Y R1^-1, R2 = chol(Q1^T Q1), Q = Q1 R2^-1
+  auto cqr2 = [&]() {
+    gram(false, [&](int i) { return (const void*)P(i).Y; }, [&](int i) { return X(i).m; });
+    chol(false, [&](int i) {
+      return GArgChol{P(i).Wg, l, P(i).R1, P(i).R1inv, P(i).RinvT, 1, P(i).status, 1};
+    });
+    std::vector<GArgNarrow> rn;
+    for (int i : ix)
+      rn.push_back({(const float*)P(i).Y, X(i).m, l, l, (const float*)P(i).RinvT, l, l,
+                    (float*)P(i).Q1, l, (int)narrow_blocks(X(i).m)});
+    B.add(G_NARROW, rn, ntl, nsl);
+    gram(false, [&](int i) { return (const void*)P(i).Q1; }, [&](int i) { return X(i).m; });
+    chol(false, [&](int i) {
+      return GArgChol{P(i).Wg, l, P(i).R2, P(i).R2inv, nullptr, 0, P(i).status, 1};
+    });
+  };
+  // Z = A^T Q1 (FP64 n x l) into Zd, then Z2 = Zd R2^-1
+  auto pass_tn = [&]() {
+    std::vector<GArgTn> rt;
+    std::vector<GArgRed> rr;
+    std::vector<GArgSg> rs;
+    for (int i : ix) {
+      const rsvd_instance& x = X(i);
+      int ntile = 0;
+      int64_t rps = 0;
+      const int ns = (int)tn_tall_splits(x.m, x.n, P(i).max_split, &rps, &ntile);
+      rt.push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Q1, l, l, rps, ntile,
+                    P(i).part, ns * ntile});
+      rr.push_back({P(i).part, ns, x.n, l, P(i).Zd, l, blocks256(x.n * (int64_t)l)});
+      rs.push_back({P(i).Zd, P(i).R2inv, x.n, l, l, P(i).Z2, nullptr, 0, blocks256(x.n * (int64_t)l)});
+    }
+    B.add(G_TN, rt, ntl);
+    B.add(G_RED, rr);
+    B.add(G_SG_F, rs);
+  };
+  // orthonormalise the FP64 n x l matrix Z2: Zq (explicit), R2s R1s = R
+  auto cqr2_small = [&]() {
+    auto nn = [&](std::function<const double*(int)> A, std::function<double*(int)> Y) {
+      std::vector<GArgNn> r;
+      const int nt = ntl > 8 ? 8 : ntl;
+      for (int i : ix) {
+        const int ct = nn_col_tiles(l, nt);
+        r.push_back({A(i), X(i).n, l, l, P(i).RinvTs, l, l, Y(i), l, nullptr, ct,
+                     (int)(nn_row_blocks(X(i).n) * ct)});
+      }
+      B.add(G_NN_D, r, nt);
+    };
+    gram(true, [&](int i) { return (const void*)P(i).Z2; }, [&](int i) { return X(i).n; });
+    chol(true, [&](int i) {
+      return GArgChol{P(i).Wg, l, P(i).R1s, P(i).R1invs, P(i).RinvTs, 0, P(i).status, 1};
+    });
+    nn([&](int i) { return (const double*)P(i).Z2; }, [&](int i) { return P(i).Z1; });
+    gram(true, [&](int i) { return (const void*)P(i).Z1; }, [&](int i) { return X(i).n; });
+    chol(true, [&](int i) {
+      return GArgChol{P(i).Wg, l, P(i).R2s, P(i).R2invs, P(i).RinvTs, 0, P(i).status, 1};
+    });
+    nn([&](int i) { return (const double*)P(i).Z1; }, [&](int i) { return P(i).Zq; });
+  };
+  auto sg = [&](bool dbl, std::function<GArgSg(int)> f) {
+    std::vector<GArgSg> r;
+    for (int i : ix) r.push_back(f(i));
+    B.add(dbl ? G_SG_D : G_SG_F, r);
+  };
+
+  // step 2: H = A G (with ||A||_F^2), CholeskyQR2
+  pass_nn(true, false);
+  cqr2();
+  // step 3: power iterations
+  for (int it = 0; it < X(ix[0]).q; ++it) {
+    pass_tn();
+    cqr2_small();
+    pass_nn(false, true);
+    cqr2();
+  }
+  // step 5: T = A^T Q
+  pass_tn();
+  // step 6: T = V~ S~ W^T (J formed from Uo S^-1; repeated with J accumulated
+  // when the values span more than six decades)
+  cqr2_small();
+  sg(true, [&](int i) {
+    return GArgSg{P(i).R2s, P(i).R1s, l, l, l, P(i).Rt, nullptr, 0, blocks256((int64_t)l * l)};
+  });
+  {
+    std::vector<GArgJac> r;
+    for (int i : ix)
+      r.push_back({P(i).Rt, l, 1, P(i).Uo, P(i).Su, P(i).Mk, P(i).diag, P(i).status,
+                   P(i).diag + 5, 1});
+    B.add(G_JAC, r, l);
+  }
+  sg(true, [&](int i) {
+    return GArgSg{P(i).Rt, P(i).Mk, l, l, l, P(i).Jm, nullptr, 0, blocks256((int64_t)l * l)};
+  });
+  {
+    std::vector<GArgJac> r;
+    for (int i : ix)
+      r.push_back({P(i).Rt, l, 1, P(i).Uo, P(i).Su, P(i).Jm, P(i).diag, P(i).status,
+                   P(i).diag + 5, 1});
+    B.add(G_JAC_ACC, r, l);
+  }
+  sg(true, [&](int i) {
+    return GArgSg{P(i).Zq, P(i).Jm, X(i).n, l, l, P(i).Vt, nullptr, 0,
+                  blocks256(X(i).n * (int64_t)l)};
+  });
+  {
+    std::vector<GArgSort> r;
+    for (int i : ix) {
+      const rsvd_instance& x = X(i);
+      r.push_back({P(i).Su, l, P(i).Vt, x.n, l, 1, P(i).Uo, k, x.S, x.V, x.ldv, nullptr, P(i).Wk,
+                   (k + 15) / 16});
+    }
+    B.add(G_SORT, r, l);
+  }
+  // step 7: U~ = Q1 (R2^-1 W), first k columns
+  sg(false, [&](int i) {
+    return GArgSg{P(i).R2inv, P(i).Wk, l, l, k, nullptr, P(i).MkT, 1, blocks256((int64_t)l * k)};
+  });
+  {
+    std::vector<GArgNarrow> r;
+    for (int i : ix)
+      r.push_back({(const float*)P(i).Q1, X(i).m, l, l, (const float*)P(i).MkT, l, k,
+                   (float*)X(i).U, X(i).ldu, (int)narrow_blocks(X(i).m)});
+    B.add(G_NARROW, r, ntk, nsl);
+  }
+  {
+    std::vector<GArgSel> r;
+    for (int i : ix)
+      r.push_back({X(i).S, k, P(i).scal, X(i).t, X(i).K, P(i).diag, P(i).status, 1});
+    B.add(G_SEL, r, k);
+  }
+  {
+    std::vector<GArgStat> r;
+    for (int i : ix) r.push_back({P(i).status, X(i).status, nullptr, 0, 1});
+    B.add(G_TAKE, r);
+  }
+}
+
+hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (const rsvd_grouped_s::Op& op : g->ops) {
+    const void* a = g->args + op.off;
+    switch (op.kind) {
+      case G_RESET:
+      case G_TAKE:
+        hipLaunchKernelGGL(k_status_grouped, dim3(1, (unsigned)op.count), dim3(64), 0, s,
+                           (const GArgStat*)a);
+        e = hipGetLastError();
+        break;
+      case G_FILL: e = launch_gaussian_fill_grouped((const GArgFill*)a, op.count, op.maxblk, s); break;
+      case G_CAST_T:
+        e = launch_cast_t_from_f64_grouped<float>((const GArgCast*)a, op.count, op.maxblk, s);
+        break;
+      case G_TALL:
+        e = launch_gemm_nt_tall_grouped((const GArgTall*)a, op.count, op.maxblk, op.a0, s);
+        break;
+      case G_NARROW:
+        e = launch_gemm_nt_narrow_grouped((const GArgNarrow*)a, op.count, op.maxblk, op.a0, op.a1,
+                                          s);
+        break;
+      case G_RED_S: e = launch_reduce_scalar_grouped((const GArgRedS*)a, op.count, s); break;
+      case G_GRAM_F:
+        e = launch_gram_f64_grouped<float>((const GArgGram*)a, op.count, op.maxblk, op.a0, op.a1, s);
+        break;
+      case G_GRAM_D:
+        e = launch_gram_f64_grouped<double>((const GArgGram*)a, op.count, op.maxblk, op.a0, op.a1,
+                                            s);
+        break;
+      case G_RED: e = launch_reduce_partials_grouped((const GArgRed*)a, op.count, op.maxblk, s); break;
+      case G_CHOL_F: e = launch_chol_inv_grouped<float>((const GArgChol*)a, op.count, s); break;
+      case G_CHOL_D: e = launch_chol_inv_grouped<double>((const GArgChol*)a, op.count, s); break;
+      case G_TN:
+        e = launch_gemm_tn_tall_grouped((const GArgTn*)a, op.count, op.maxblk, op.a0, s);
+        break;
+      case G_SG_F: e = launch_small_gemm_grouped<float>((const GArgSg*)a, op.count, op.maxblk, s); break;
+      case G_SG_D: e = launch_small_gemm_grouped<double>((const GArgSg*)a, op.count, op.maxblk, s); break;
+      case G_NN_D:
+        e = launch_gemm_nn_f64_grouped((const GArgNn*)a, op.count, op.maxblk, op.a0, s);
+        break;
+      case G_JAC:
+        e = launch_jacobi_svd_small_grouped((const GArgJac*)a, op.count, op.a0, 0, s);
+        break;
+      case G_JAC_ACC:
+        e = launch_jacobi_svd_small_grouped((const GArgJac*)a, op.count, op.a0, 1, s);
+        break;
+      case G_SORT:
+        e = launch_sort_sign_scatter_grouped<float>((const GArgSort*)a, op.count, op.maxblk, op.a0,
+                                                    s);
+        break;
+      case G_SEL: e = launch_select_k_grouped((const GArgSel*)a, op.count, op.a0, s); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void grouped_free(rsvd_grouped_s* g) {
+  (void)hipSetDevice(g->device);
+  if (g->ws) (void)hipFree(g->ws);
+  if (g->args) (void)hipFree(g->args);
+  delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                  rsvd_grouped_t* grouped) {
+  if (!batch || !grouped || count < 0 || (count > 0 && !inst)) return RSVD_ERR_ARG;
+  *grouped = nullptr;
+  if (batch->dtype != RSVD_F32) return RSVD_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    const int32_t rc = check_instance(batch->plan[0], inst[i]);
+    if (rc != RSVD_OK) return rc;
+    if (!grouped_applies(inst[i])) return RSVD_ERR_ARG;
+  }
+  if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  rsvd_grouped_s* g = new (std::nothrow) rsvd_grouped_s();
+  if (!g) return RSVD_ERR_NOMEM;
+  g->device = batch->device;
+  // one workspace per instance, sized for it, carved from one allocation
+  g->plans.resize(count);
+  std::vector<size_t> off(count);
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    rsvd_plan_s& p = g->plans[i];
+    const rsvd_instance& x = inst[i];
+    p.device = batch->device;
+    p.dtype = RSVD_F32;
+    p.m_max = x.m;
+    p.n_max = x.n;
+    p.l_max = (int)((x.k + (int64_t)x.p < x.n) ? x.k + x.p : x.n);
+    p.gram = false;
+    p.seed = batch->plan[0]->seed;
+    // the batch's split limit: the same row splits, so the same sums, as its slots
+    p.max_split = batch->plan[0]->max_split;
+    off[i] = total;
+    total += carve(&p, nullptr);
+  }
+  if (total > 0 && hipMalloc(&g->ws, total) != hipSuccess) {
+    (void)hipGetLastError();
+    grouped_free(g);
+    return RSVD_ERR_NOMEM;
+  }
+  for (int i = 0; i < count; ++i) carve(&g->plans[i], g->ws + off[i]);
+  if (total > 0 && (hipMemset(g->ws, 0, total) != hipSuccess)) {
+    grouped_free(g);
+    return RSVD_ERR_DEVICE;
+  }
+  // groups of equal (l, k), in order of first appearance
+  GroupedBuilder B;
+  std::vector<char> done(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (done[i]) continue;
+    const int l = g->plans[i].l_max, k = inst[i].k, q = inst[i].q;
+    std::vector<int> ix;
+    for (int j = i; j < count; ++j)
+      if (!done[j] && g->plans[j].l_max == l && inst[j].k == k && inst[j].q == q) {
+        ix.push_back(j);
+        done[j] = 1;
+      }
+    record_group(B, inst, ix, g->plans, l, k);
+  }
+  g->ops = B.ops;
+  if (!B.host.empty()) {
+    if (hipMalloc(&g->args, B.host.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      grouped_free(g);
+      return RSVD_ERR_NOMEM;
+    }
+    if (hipMemcpy(g->args, B.host.data(), B.host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      grouped_free(g);
+      return RSVD_ERR_DEVICE;
+    }
+  }
+  *grouped = g;
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_grouped_launch(rsvd_grouped_t grouped, void* stream) {
+  if (!grouped) return RSVD_ERR_ARG;
+  if (hipSetDevice(grouped->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  return grouped_launch(grouped, (hipStream_t)stream) == hipSuccess ? RSVD_OK : RSVD_ERR_DEVICE;
+}
+
+int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped) {
+  if (!grouped) return RSVD_OK;
+  if (hipSetDevice(grouped->device) == hipSuccess) (void)hipDeviceSynchronize();
+  grouped_free(grouped);
+  return RSVD_OK;
 }
 
 }  // extern "C"

@@ -241,4 +241,107 @@ int jacobi_eig_flag_words();
 // Largest n the Jacobi eigensolver supports (every workgroup resident).
 int64_t jacobi_eig_max_n();
 
+
+// ---------------------------------------------------------------------------
+// Grouped launches: one launch runs one kernel for many problems.  Each
+// kernel below takes, as its last argument, an optional array of per-problem
+// arguments (nullptr for an ordinary launch); in a grouped launch blockIdx.y
+// selects the problem, whose arguments replace the kernel's own, and blocks
+// with blockIdx.x >= nblk (that problem's own grid) leave at once, so every
+// problem runs exactly the blocks an ordinary launch would give it.
+struct GArgTall {   // k_gemm_nt_tall
+  const float* A; int64_t m, n, lda; const float* Xt; int64_t ldxt; int c;
+  float* Y; int64_t ldy; double* fro2; int nblk;
+};
+struct GArgNarrow {   // k_gemm_nt_narrow (nblk also strides the persistent loop)
+  const float* A; int64_t m, n, lda; const float* Xt; int64_t ldxt; int c;
+  float* Y; int64_t ldy; int nblk;
+};
+struct GArgTn {   // k_gemm_tn_tall
+  const float* A; int64_t m, n, lda; const float* Q; int64_t ldq; int c; int64_t rps;
+  int ntile; double* P; int nblk;
+};
+struct GArgGram {   // k_gram_f64
+  const void* Y; int64_t m; int c; int64_t ldy; double* P; int64_t rpb; int nblk;
+};
+struct GArgRed {   // k_reduce_partials
+  const double* P; int nsplit; int64_t rows, cols; double* Z; int64_t ldz; int nblk;
+};
+struct GArgRedS {   // k_reduce_scalar
+  const double* parts; int n; double* out; int nblk;
+};
+struct GArgNn {   // k_gemm_nn
+  const void* A; int64_t m, n, lda; const void* X; int64_t ldx; int c; void* Y; int64_t ldy;
+  double* fro2; int ncol_tiles; int nblk;
+};
+struct GArgFill {   // k_gaussian_fill
+  uint64_t seed; int64_t total; double* G; int nblk;
+};
+struct GArgCast {   // k_cast_t
+  const double* src; int64_t rows, cols, lds; void* dst; int64_t ldd; int nblk;
+};
+struct GArgChol {   // k_chol_inv
+  const double* W; int c; double* R; double* Rinv; void* RinvT; int trans; int32_t* status;
+  int nblk;
+};
+struct GArgSg {   // k_small_gemm
+  const double* A; const double* B; int64_t r; int c1, c2; double* C; void* CT; int trans;
+  int nblk;
+};
+struct GArgJac {   // k_jacobi_svd_small
+  const double* M; int c; int transpose; double* Uo; double* S; double* J; double* diag;
+  int32_t* status; double* redo; int nblk;
+};
+struct GArgSort {   // k_sort_sign_scatter
+  const double* S; int c; const double* Vsrc; int64_t r, vrs, vcs; const double* Wsrc; int kout;
+  double* S_out; void* Vout; int64_t ldv; double* Vd_out; double* Wout; int nblk;
+};
+struct GArgSel {   // k_select_k
+  const double* S; int k; const double* fro2; double t; int32_t* K; double* diag;
+  int32_t* status; int nblk;
+};
+struct GArgStat {   // k_reset (src = nullptr: status = RSVD_OK, diag zeroed) and k_status_take
+  const int32_t* src; int32_t* dst; double* diag; int nd; int nblk;
+};
+
+// Launch geometry shared by the ordinary and the grouped launchers.
+int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block);
+int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_per_split,
+                       int* ntile);
+int64_t narrow_blocks(int64_t m);
+int64_t tall_blocks(int64_t m);
+int nn_col_tiles(int c, int nt);
+int64_t nn_row_blocks(int64_t m);
+
+// Grouped launchers: `a` is a device array of `count` argument records,
+// `maxblk` the largest nblk among them; the template choices (column tiles
+// nt, k slabs ns, element type) are the same for every problem of a launch.
+hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, int count, int maxblk, int nt,
+                                       hipStream_t s);
+hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int maxblk, int nt,
+                                         int ns, hipStream_t s);
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt,
+                                       hipStream_t s);
+template <typename T>
+hipError_t launch_gram_f64_grouped(const GArgGram* a, int count, int maxblk, int nt, int cmax,
+                                   hipStream_t s);
+hipError_t launch_reduce_partials_grouped(const GArgRed* a, int count, int maxblk, hipStream_t s);
+hipError_t launch_reduce_scalar_grouped(const GArgRedS* a, int count, hipStream_t s);
+hipError_t launch_gemm_nn_f64_grouped(const GArgNn* a, int count, int maxblk, int nt,
+                                      hipStream_t s);
+hipError_t launch_gaussian_fill_grouped(const GArgFill* a, int count, int maxblk, hipStream_t s);
+template <typename T>
+hipError_t launch_cast_t_from_f64_grouped(const GArgCast* a, int count, int maxblk,
+                                          hipStream_t s);
+template <typename T>
+hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, hipStream_t s);
+template <typename T>
+hipError_t launch_small_gemm_grouped(const GArgSg* a, int count, int maxblk, hipStream_t s);
+hipError_t launch_jacobi_svd_small_grouped(const GArgJac* a, int count, int cmax, int acc_j,
+                                           hipStream_t s);
+template <typename T>
+hipError_t launch_sort_sign_scatter_grouped(const GArgSort* a, int count, int maxblk, int cmax,
+                                            hipStream_t s);
+hipError_t launch_select_k_grouped(const GArgSel* a, int count, int kmax, hipStream_t s);
+
 }  // namespace rsvd

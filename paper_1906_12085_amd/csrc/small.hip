@@ -31,7 +31,13 @@ __device__ __forceinline__ double uniform53(uint32_t hi, uint32_t lo) {
 }
 
 // The standard normal sketch matrix G of Sec. 3.1.2 step 1 (Box-Muller).
-__global__ void k_gaussian_fill(uint64_t seed, int64_t total, double* __restrict__ G) {
+__global__ void k_gaussian_fill(uint64_t seed, int64_t total, double* __restrict__ G,
+                                const GArgFill* __restrict__ grp) {
+  if (grp) {
+    const GArgFill& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    seed = a.seed; total = a.total; G = a.G;
+  }
   const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (2 * pair >= total) return;
   uint32_t c[4] = {(uint32_t)(pair & 0xFFFFFFFFu), (uint32_t)((uint64_t)pair >> 32), 0u, 0u};
@@ -56,7 +62,13 @@ __global__ void k_cast(const S* __restrict__ src, int64_t rows, int64_t cols, in
 // dst (cols x rows) = src^T, consecutive threads writing consecutive dst.
 template <typename S, typename D>
 __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
-                         D* __restrict__ dst, int64_t ldd) {
+                         D* __restrict__ dst, int64_t ldd, const GArgCast* __restrict__ grp) {
+  if (grp) {
+    const GArgCast& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    src = (const S*)a.src; rows = a.rows; cols = a.cols; lds = a.lds; dst = (D*)a.dst;
+    ldd = a.ldd;
+  }
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t j = idx / rows, i = idx - j * rows;
@@ -141,7 +153,13 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv,
                                                    T* __restrict__ RinvT, int trans,
-                                                   int32_t* __restrict__ status) {
+                                                   int32_t* __restrict__ status,
+                                                   const GArgChol* __restrict__ grp) {
+  if (grp) {
+    const GArgChol& a = grp[blockIdx.y];
+    W = a.W; c = a.c; R = a.R; Rinv = a.Rinv; RinvT = (T*)a.RinvT; trans = a.trans;
+    status = a.status;
+  }
   __shared__ double rowR[2][96];
   __shared__ double rowB[2][96];
   __shared__ int bad;
@@ -199,7 +217,12 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
 template <typename T>
 __global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
                              int64_t r, int c1, int c2, double* __restrict__ C, T* __restrict__ CT,
-                             int trans) {
+                             int trans, const GArgSg* __restrict__ grp) {
+  if (grp) {
+    const GArgSg& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = a.A; B = a.B; r = a.r; c1 = a.c1; c2 = a.c2; C = a.C; CT = (T*)a.CT; trans = a.trans;
+  }
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= r * c2) return;
   const int64_t i = idx / c2;
@@ -236,7 +259,12 @@ template <bool AccJ>
 __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     const double* __restrict__ Min, int c, int transpose, double* __restrict__ Uo,
     double* __restrict__ S, double* __restrict__ Jout, double* __restrict__ diag,
-    int32_t* __restrict__ status, double* __restrict__ redo) {
+    int32_t* __restrict__ status, double* __restrict__ redo, const GArgJac* __restrict__ garg) {
+  if (garg) {
+    const GArgJac& a = garg[blockIdx.y];
+    Min = a.M; c = a.c; transpose = a.transpose; Uo = a.Uo; S = a.S; Jout = a.J; diag = a.diag;
+    status = a.status; redo = a.redo;
+  }
   if (AccJ && redo && *redo == 0.0) return;  // uniform: the first pass needed no J
   extern __shared__ double sm[];
   double* Mc = sm;                   // column j at Mc + j*c
@@ -373,7 +401,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sort_sign_scatter(
     const double* __restrict__ S, int c, const double* __restrict__ Vsrc, int64_t r, int64_t vrs,
     int64_t vcs, const double* __restrict__ Wsrc, int kout, double* __restrict__ S_out,
-    T* __restrict__ Vout, int64_t ldv, double* __restrict__ Vd_out, double* __restrict__ Wout) {
+    T* __restrict__ Vout, int64_t ldv, double* __restrict__ Vd_out, double* __restrict__ Wout,
+    const GArgSort* __restrict__ grp) {
+  if (grp) {
+    const GArgSort& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    S = a.S; c = a.c; Vsrc = a.Vsrc; r = a.r; vrs = a.vrs; vcs = a.vcs; Wsrc = a.Wsrc;
+    kout = a.kout; S_out = a.S_out; Vout = (T*)a.Vout; ldv = a.ldv; Vd_out = a.Vd_out;
+    Wout = a.Wout;
+  }
   extern __shared__ double Sl[];              // c keys, then c ints
   int* perm = reinterpret_cast<int*>(Sl + c);
   __shared__ int src_l[kSsCols];
@@ -436,7 +472,11 @@ __global__ __launch_bounds__(256) void k_sort_sign_scatter(
 // sum_{i<=K} s_i^2 >= t * ||A||_F^2 (Eq. sumeigen gives the denominator).
 __global__ void k_select_k(const double* __restrict__ S, int k, const double* __restrict__ fro2,
                            double t, int32_t* __restrict__ K, double* __restrict__ diag,
-                           int32_t* __restrict__ status) {
+                           int32_t* __restrict__ status, const GArgSel* __restrict__ grp) {
+  if (grp) {
+    const GArgSel& a = grp[blockIdx.y];
+    S = a.S; k = a.k; fro2 = a.fro2; t = a.t; K = a.K; diag = a.diag; status = a.status;
+  }
   extern __shared__ double Sl[];
   stage_to_lds(Sl, S, k);
   __syncthreads();
@@ -540,7 +580,7 @@ hipError_t launch_gaussian_fill(uint64_t seed, int64_t rows, int64_t cols, doubl
   const int64_t total = rows * cols;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gaussian_fill, dim3(blocks_for((total + 1) / 2, 256)), dim3(256), 0, s,
-                     seed, total, G);
+                     seed, total, G, nullptr);
   return hipGetLastError();
 }
 
@@ -558,7 +598,7 @@ hipError_t launch_cast_t_from_f64(const double* src, int64_t rows, int64_t cols,
                                   int64_t ldd, hipStream_t s) {
   if (rows * cols <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_cast_t<double, T>), dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, src,
-                     rows, cols, lds, dst, ldd);
+                     rows, cols, lds, dst, ldd, nullptr);
   return hipGetLastError();
 }
 
@@ -576,7 +616,7 @@ hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* R
                            int32_t* status, hipStream_t s, int trans) {
   if (c < 1 || c > 16 * kCiU) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), 0, s, W, c, R, Rinv, RinvT, trans,
-                     status);
+                     status, nullptr);
   return hipGetLastError();
 }
 
@@ -585,7 +625,7 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
                              T* CT, hipStream_t s, int trans) {
   if (r * c2 <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_small_gemm<T>), dim3(blocks_for(r * c2, 256)), dim3(256), 0, s, A, B, r,
-                     c1, c2, C, CT, trans);
+                     c1, c2, C, CT, trans, nullptr);
   return hipGetLastError();
 }
 
@@ -602,10 +642,10 @@ hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double
   if (e != hipSuccess) return e;
   if (acc_j)
     hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status, redo);
+                       transpose, Uo, S, J, diag, status, redo, nullptr);
   else
     hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status, redo);
+                       transpose, Uo, S, J, diag, status, redo, nullptr);
   return hipGetLastError();
 }
 
@@ -618,14 +658,14 @@ hipError_t launch_sort_sign_scatter(const double* S, int c, const double* Vsrc, 
   if (kout <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3((kout + kSsCols - 1) / kSsCols), dim3(256),
                      (size_t)c * (sizeof(double) + sizeof(int)), s, S,
-                     c, Vsrc, r, vrs, vcs, Wsrc, kout, S_out, Vout, ldv, Vd_out, Wout);
+                     c, Vsrc, r, vrs, vcs, Wsrc, kout, S_out, Vout, ldv, Vd_out, Wout, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_select_k(const double* S, int k, const double* fro2, double t, int32_t* K,
                            double* diag, int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_select_k, dim3(1), dim3(256), (size_t)k * sizeof(double), s, S, k, fro2, t,
-                     K, diag, status);
+                     K, diag, status, nullptr);
   return hipGetLastError();
 }
 
@@ -663,6 +703,87 @@ hipError_t launch_sqrt_clamp(const double* lam, int n, double* S, hipStream_t s)
   hipLaunchKernelGGL(k_sqrt_clamp, dim3(blocks_for(n, 256)), dim3(256), 0, s, lam, n, S);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Grouped launchers (one launch, blockIdx.y = problem).
+hipError_t launch_gaussian_fill_grouped(const GArgFill* a, int count, int maxblk, hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gaussian_fill, dim3((unsigned)maxblk, (unsigned)count), dim3(256), 0, s,
+                     0, 0, nullptr, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cast_t_from_f64_grouped(const GArgCast* a, int count, int maxblk,
+                                          hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cast_t<double, T>), dim3((unsigned)maxblk, (unsigned)count), dim3(256), 0,
+                     s, nullptr, 0, 0, 0, nullptr, 0, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1, (unsigned)count), dim3(kCiT), 0, s, nullptr, 0,
+                     nullptr, nullptr, nullptr, 0, nullptr, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_small_gemm_grouped(const GArgSg* a, int count, int maxblk, hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_small_gemm<T>), dim3((unsigned)maxblk, (unsigned)count), dim3(256), 0, s,
+                     nullptr, nullptr, 0, 0, 0, nullptr, nullptr, 0, a);
+  return hipGetLastError();
+}
+
+// every problem of the launch has c = cmax (the thread count and the LDS
+// size follow c)
+hipError_t launch_jacobi_svd_small_grouped(const GArgJac* a, int count, int cmax, int acc_j,
+                                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (cmax < 1 || cmax > kJsG * kJsRows) return hipErrorInvalidValue;
+  const int npad = cmax + (cmax & 1);
+  const size_t shmem = (acc_j ? 2 : 1) * (size_t)cmax * cmax * sizeof(double);
+  const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
+  const void* fn = acc_j ? (const void*)k_jacobi_svd_small<true>
+                         : (const void*)k_jacobi_svd_small<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  if (acc_j)
+    hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1, (unsigned)count), dim3(threads), shmem, s,
+                       nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, a);
+  else
+    hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1, (unsigned)count), dim3(threads), shmem,
+                       s, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sort_sign_scatter_grouped(const GArgSort* a, int count, int maxblk, int cmax,
+                                            hipStream_t s) {
+  if (count <= 0 || maxblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sort_sign_scatter<T>), dim3((unsigned)maxblk, (unsigned)count), dim3(256),
+                     (size_t)cmax * (sizeof(double) + sizeof(int)), s, nullptr, 0, nullptr, 0, 0,
+                     0, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_k_grouped(const GArgSel* a, int count, int kmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select_k, dim3(1, (unsigned)count), dim3(256), (size_t)kmax * sizeof(double),
+                     s, nullptr, 0, nullptr, 0.0, nullptr, nullptr, nullptr, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cast_t_from_f64_grouped<float>(const GArgCast*, int, int, hipStream_t);
+template hipError_t launch_chol_inv_grouped<float>(const GArgChol*, int, hipStream_t);
+template hipError_t launch_chol_inv_grouped<double>(const GArgChol*, int, hipStream_t);
+template hipError_t launch_small_gemm_grouped<float>(const GArgSg*, int, int, hipStream_t);
+template hipError_t launch_small_gemm_grouped<double>(const GArgSg*, int, int, hipStream_t);
+template hipError_t launch_sort_sign_scatter_grouped<float>(const GArgSort*, int, int, int,
+                                                            hipStream_t);
 
 #define RSVD_INST(T)                                                                               \
   template hipError_t launch_cast_t_from_f64<T>(const double*, int64_t, int64_t, int64_t, T*,      \

@@ -119,3 +119,56 @@ def test_batch_arguments():
         rs.Batch(0, 4000, 64, 24, dt)
     with pytest.raises(KeyError):
         rs.Batch(2, 4000, 64, 24, torch.int32)
+
+
+def test_batch_grouped_equals_alone():
+    # every step one launch for all instances: each result must equal the
+    # solo solve bit for bit; two rank groups (k = 8 and 16), replayed twice
+    dt = torch.float32
+    announce("grouped batch: 12 uneven instances, two (l, k) groups, two launches")
+    probs = problems(dt, 12, 31)
+    probs = [(A, 8 if i % 2 else 16, p, q, t, A0) if A.shape[1] >= 64 else (A, k, p, q, t, A0)
+             for i, (A, k, p, q, t, A0) in enumerate(probs)]
+    b = rs.Batch(2, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    g = b.grouped([pr[:5] for pr in probs])
+    alone = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED)
+    for rep in range(2):
+        for o in g.outs:
+            for key in ("U", "S", "V"):
+                o[key].fill_(float("nan"))
+            o["K"].fill_(-9)
+            o["status"].fill_(-99)
+        g.launch()
+        torch.cuda.synchronize()
+        for (A, k, p, q, t, A0), o in zip(probs, g.outs):
+            ref = alone.solve(A, k, p, q, t)
+            assert torch.equal(o["S"], ref.S) and torch.equal(o["U"], ref.U), (rep, A.shape, k)
+            assert torch.equal(o["V"], ref.V)
+            assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+    # and against the oracle on the first instances
+    for (A, k, p, q, t, A0), o in list(zip(probs, g.outs))[:4]:
+        n = A.shape[1]
+        G = rounded(synth.gaussian_omega(SEED, n, min(k + p, n)), dt)
+        orc = oracle.rsvd(A0, G, k, p, q, t)
+        assert np.max(np.abs(host(o["S"]) - orc.S) / orc.S) <= 1e-4
+        assert oracle.principal_angle_max(orc.V, host(o["V"])) <= 1e-3
+    g.close()
+    alone.close()
+    b.close()
+
+
+def test_batch_grouped_arguments():
+    b = rs.Batch(2, 4000, 64, 24, torch.float32, seed=1)
+    A = torch.zeros((1000, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(rs.RSVDError) as ei:
+        b.grouped([(A, 6, 4, 1, 0.9)])                  # l = 10: not a multiple of 4
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    with pytest.raises(rs.RSVDError) as ei:
+        b.grouped([(A[:, :62], 8, 8, 1, 0.9)])          # n = 62, lda = 64
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    b.close()
+    b64 = rs.Batch(2, 4000, 64, 24, torch.float64, seed=1)
+    with pytest.raises(rs.RSVDError) as ei:
+        b64.grouped([(A.double(), 8, 8, 1, 0.9)])       # fp32 batches only
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    b64.close()

@@ -98,15 +98,15 @@ KERNEL_INFO = {
 # the kernel that was measured: a changed kernel reports null until measured
 # again.
 TRAFFIC = {
-    "eigensolver": (3.2841e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
-    "pass_nn": (2.3911e+09, "gemm.hip", "k_gemm_nt_tall", "5458f34d8ffce76b"),
-    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "03561cb8faeda271"),
-    "syrk": (3.6882e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
-    "nn_wide": (4.4559e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
-    "pass_nn_bf16": (1.5380e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "eigensolver": (3.2842e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
+    "pass_nn": (2.3911e+09, "gemm.hip", "k_gemm_nt_tall", "de061d75de085870"),
+    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "e06f144a6ab9e4c9"),
+    "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
+    "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
+    "pass_nn_bf16": (1.5362e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
     "pass_tn_bf16": (1.4354e+09, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
-    "pass_nn_fp8": (8.4523e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
-    "pass_tn_fp8": (9.1849e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
+    "pass_nn_fp8": (8.4586e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
+    "pass_tn_fp8": (9.1820e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 

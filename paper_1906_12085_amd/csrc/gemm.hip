@@ -869,6 +869,149 @@ __global__ __launch_bounds__(512) void k_gemm_tn_tall(
     }
 }
 
+// Z partials of A^T Q for n <= 64 CW columns (CW = 1, 2 or 4): the same
+// contraction and partial layout as k_gemm_tn_tall, whose 512-column tile
+// would spend most of its matrix-core steps on columns past n.  The block's
+// 4 CW x NT output tiles (16 x 16) are dealt to its 8 waves -- CW = 4: two
+// row tiles and all NT column tiles per wave; CW = 2: one row tile, all
+// column tiles; CW = 1: one row tile and every second column tile (waves w
+// and w + 4, which share a SIMD, split them) -- and every wave contracts over
+// all rows of a chunk, so no cross-wave sum is needed.  Chunks of R rows
+// (32; 16 for CW = 4) of the 64 CW columns of A and of Q's BC columns are
+// staged row-major in LDS (row strides 16 mod 64 floats), double-buffered.
+// With one column tile (n <= 256) a block is one row split.
+template <int CW>
+struct TnNarrow {
+  static constexpr int R = CW == 4 ? 16 : 32;          // rows per chunk
+  static constexpr int COLS = 64 * CW;
+  static constexpr int ALD = COLS + 16;
+  static constexpr int RT = 4 * CW;                     // row tiles of the block's Z
+  static constexpr int IPW = RT > 8 ? RT / 8 : 1;       // row tiles per wave
+  static constexpr int JS = RT < 8 ? 8 / RT : 1;        // column-tile stride
+  static constexpr int UA = R * COLS / 4 / 512;         // float4 of A per thread
+  static_assert(UA * 512 * 4 == R * COLS, "A chunk must be whole float4 per thread");
+};
+
+template <int NT, int CW>
+__global__ __launch_bounds__(512) void k_gemm_tn_narrow(
+    const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
+    int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P,
+    const GArgTn* __restrict__ grp) {
+  using G = TnNarrow<CW>;
+  if (grp) {
+    const GArgTn& a = grp[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;
+    A = a.A; m = a.m; n = a.n; lda = a.lda; Q = a.Q; ldq = a.ldq; c = a.c; rps = a.rps;
+    ntile = a.ntile; P = a.P;
+  }
+  constexpr int BC = 16 * NT;
+  constexpr int QLD = BC + ((16 - BC) % 64 + 64) % 64;
+  constexpr int QU = G::R * BC / 4;                     // float4 of the Q chunk
+  constexpr int UQ = (QU + 511) / 512;
+  constexpr int JPW = (NT + G::JS - 1) / G::JS;
+  __shared__ __attribute__((aligned(16))) float As[2][G::R * G::ALD];
+  __shared__ __attribute__((aligned(16))) float Qs[2][G::R * QLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  const int64_t sp = blockIdx.x / ntile;
+  const int64_t row0 = sp * rps;
+  const int64_t rows = m - row0 < rps ? m - row0 : rps;
+  const int nch = (int)((rows + G::R - 1) / G::R);
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), 0, (int)(rows * lda * 4), kBufDword3);
+  const __amdgpu_buffer_rsrc_t qr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(Q + row0 * ldq), 0, (int)(rows * ldq * 4), kBufDword3);
+  int voa[G::UA], voq[UQ];
+#pragma unroll
+  for (int u = 0; u < G::UA; ++u) {
+    const int idx = tid + u * 512, r = idx / (G::COLS / 4), q4 = idx % (G::COLS / 4);
+    voa[u] = (int)((r * lda + 4 * q4) * 4);
+  }
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) {
+    const int idx = tid + u * 512, r = idx / (BC / 4), q4 = idx % (BC / 4);
+    voq[u] = (int)((r * ldq + 4 * q4) * 4);
+  }
+  f32x4 ra[G::UA], rq[UQ];
+  auto load = [&](int ch) {
+    const int sa = (int)((int64_t)ch * G::R * lda * 4), sq = (int)((int64_t)ch * G::R * ldq * 4);
+#pragma unroll
+    for (int u = 0; u < G::UA; ++u)
+      ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[u], sa, 0));
+#pragma unroll
+    for (int u = 0; u < UQ; ++u)
+      if (tid + u * 512 < QU)
+        rq[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq[u], sq, 0));
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < G::UA; ++u) {
+      const int idx = tid + u * 512, r = idx / (G::COLS / 4), q4 = idx % (G::COLS / 4);
+      *reinterpret_cast<f32x4*>(&As[buf][r * G::ALD + 4 * q4]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UQ; ++u) {
+      const int idx = tid + u * 512, r = idx / (BC / 4), q4 = idx % (BC / 4);
+      if (idx < QU) *reinterpret_cast<f32x4*>(&Qs[buf][r * QLD + 4 * q4]) = rq[u];
+    }
+  };
+  // this wave's tiles: row tile i0 + 8 ii, column tile j0 + JS jj (if < NT)
+  const int i0 = G::RT < 8 ? wave % G::RT : wave;
+  const int j0 = G::RT < 8 ? wave / G::RT : 0;
+  f32x4 acc[G::IPW][JPW];
+#pragma unroll
+  for (int ii = 0; ii < G::IPW; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < JPW; ++jj) acc[ii][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto steps = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < G::R / 4; ++t) {
+      const float* arow = &As[buf][(4 * t + g) * G::ALD + lr];
+      const float* qrow = &Qs[buf][(4 * t + g) * QLD + lr];
+      float af[G::IPW], bf[JPW];
+#pragma unroll
+      for (int ii = 0; ii < G::IPW; ++ii) af[ii] = arow[16 * (i0 + 8 * ii)];
+#pragma unroll
+      for (int jj = 0; jj < JPW; ++jj) {
+        const int j = j0 + G::JS * jj;
+        bf[jj] = j < NT ? qrow[16 * j] : 0.f;
+      }
+#pragma unroll
+      for (int ii = 0; ii < G::IPW; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < JPW; ++jj)
+          if (j0 + G::JS * jj < NT) acc[ii][jj] = Mfma<float>::run(af[ii], bf[jj], acc[ii][jj]);
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    load(more ? ch + 1 : ch);
+    __builtin_amdgcn_sched_barrier(0);
+    steps(buf);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = P + sp * n * (int64_t)c;
+#pragma unroll
+  for (int ii = 0; ii < G::IPW; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < JPW; ++jj) {
+      const int j = j0 + G::JS * jj;
+      if (j >= NT) continue;
+      const int col = 16 * j + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = 16 * (i0 + 8 * ii) + Mfma<float>::row(lane, e);
+        if (row < n && col < c) out[row * c + col] = (double)acc[ii][jj][e];
+      }
+    }
+}
+
 template <typename T, int NT, int MR>
 hipError_t nn_dispatch(const T* A, int64_t m, int64_t n, int64_t lda, const T* X, int64_t ldx,
                        int c, T* Y, int64_t ldy, double* fro2_part, int* nparts, hipStream_t s) {
@@ -1266,14 +1409,27 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
   int64_t rps = 0;
   const int64_t ns = tn_tall_splits(m, n, max_split, &rps, &ntile);
   const int64_t ld = lda > ldq ? lda : ldq;
-  if (rps * ld * 4 >= (1LL << 31) || (int64_t)(kUK - 1) * lda * 4 + (int64_t)ntile * kUA * 4 >= (1LL << 31))
+  // 32-bit buffer offsets: the split's rows, and a chunk's offsets (at most
+  // 32 rows, the narrow kernel's) within a row split
+  if (rps * ld * 4 >= (1LL << 31) || (int64_t)31 * ld * 4 + (int64_t)ntile * kUA * 4 >= (1LL << 31))
     return hipErrorInvalidValue;
   *nsplit = (int)ns;
   const dim3 grid((unsigned)(ns * ntile)), block(512);
+  const int cw = tn_col_waves(n);
 #define RSVD_TN_TALL(NT)                                                                          \
   case NT:                                                                                        \
-    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps, ntile, P, \
-                       nullptr);                                                               \
+    if (cw == 1)                                                                                  \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 1>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
+                         rps, ntile, P, nullptr);                                                 \
+    else if (cw == 2)                                                                             \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 2>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
+                         rps, ntile, P, nullptr);                                                 \
+    else if (cw == 4)                                                                             \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 4>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
+                         rps, ntile, P, nullptr);                                                 \
+    else                                                                                          \
+      hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps,     \
+                         ntile, P, nullptr);                                                      \
     break;
   switch ((c + 15) / 16) {
     RSVD_TN_TALL(1) RSVD_TN_TALL(2) RSVD_TN_TALL(3) RSVD_TN_TALL(4)
@@ -1445,6 +1601,10 @@ int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_pe
 }
 
 // persistent: up to two blocks per CU of the 256
+// column waves of the A^T Q kernel for n columns: 1, 2 or 4 (narrow kernel,
+// 64 columns per wave group) or 8 (the 512-column tile)
+int tn_col_waves(int64_t n) { return n <= 64 ? 1 : (n <= 128 ? 2 : (n <= 256 ? 4 : 8)); }
+
 int64_t narrow_blocks(int64_t m) {
   const int64_t ntile = (m + kNM - 1) / kNM;
   return ntile < 512 ? ntile : 512;
@@ -1505,14 +1665,24 @@ hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int max
   }
 }
 
-hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt,
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt, int cw,
                                        hipStream_t s) {
   if (count <= 0 || maxblk <= 0) return hipSuccess;
   const dim3 grid((unsigned)maxblk, (unsigned)count), block(512);
 #define RSVD_G(NT)                                                                              \
   case NT:                                                                                      \
-    hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0,  \
-                       0, 1, nullptr, a);                                                       \
+    if (cw == 1)                                                                                \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 1>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
+                         0, 0, 0, 1, nullptr, a);                                               \
+    else if (cw == 2)                                                                           \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 2>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
+                         0, 0, 0, 1, nullptr, a);                                               \
+    else if (cw == 4)                                                                           \
+      hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 4>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
+                         0, 0, 0, 1, nullptr, a);                                               \
+    else                                                                                        \
+      hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0, \
+                         0, 1, nullptr, a);                                                     \
     break;
   switch (nt) {
     RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)

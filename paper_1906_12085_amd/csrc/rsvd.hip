@@ -1575,7 +1575,13 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
       rr.push_back({P(i).part, ns, x.n, l, P(i).Zd, l, blocks256(x.n * (int64_t)l)});
       rs.push_back({P(i).Zd, P(i).R2inv, x.n, l, l, P(i).Z2, nullptr, 0, blocks256(x.n * (int64_t)l)});
     }
-    B.add(G_TN, rt, ntl);
+    // one launch per A^T Q kernel (column waves 1, 2, 4, 8 by n)
+    for (int cw : {1, 2, 4, 8}) {
+      std::vector<GArgTn> rc;
+      for (const GArgTn& r : rt)
+        if (tn_col_waves(r.n) == cw) rc.push_back(r);
+      B.add(G_TN, rc, ntl, cw);
+    }
     B.add(G_RED, rr);
     B.add(G_SG_F, rs);
   };
@@ -1714,7 +1720,7 @@ hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
       case G_CHOL_F: e = launch_chol_inv_grouped<float>((const GArgChol*)a, op.count, s); break;
       case G_CHOL_D: e = launch_chol_inv_grouped<double>((const GArgChol*)a, op.count, s); break;
       case G_TN:
-        e = launch_gemm_tn_tall_grouped((const GArgTn*)a, op.count, op.maxblk, op.a0, s);
+        e = launch_gemm_tn_tall_grouped((const GArgTn*)a, op.count, op.maxblk, op.a0, op.a1, s);
         break;
       case G_SG_F: e = launch_small_gemm_grouped<float>((const GArgSg*)a, op.count, op.maxblk, s); break;
       case G_SG_D: e = launch_small_gemm_grouped<double>((const GArgSg*)a, op.count, op.maxblk, s); break;

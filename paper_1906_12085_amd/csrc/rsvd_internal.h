@@ -308,6 +308,7 @@ struct GArgStat {   // k_reset (src = nullptr: status = RSVD_OK, diag zeroed) an
 int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block);
 int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_per_split,
                        int* ntile);
+int tn_col_waves(int64_t n);
 int64_t narrow_blocks(int64_t m);
 int64_t tall_blocks(int64_t m);
 int nn_col_tiles(int c, int nt);
@@ -320,7 +321,7 @@ hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, int count, int maxblk,
                                        hipStream_t s);
 hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int maxblk, int nt,
                                          int ns, hipStream_t s);
-hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt,
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt, int cw,
                                        hipStream_t s);
 template <typename T>
 hipError_t launch_gram_f64_grouped(const GArgGram* a, int count, int maxblk, int nt, int cmax,

@@ -162,7 +162,11 @@ def big_plans(name):
 
 
 TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100, 97, 96),
-            (4099, 512, 80), (1000, 600, 128), (70, 64, 3), (2000, 36, 48)]
+            (4099, 512, 80), (1000, 600, 128), (70, 64, 3), (2000, 36, 48),
+            # the fp32 narrow kernel, n <= 64 / 128 / 256: every column-tile
+            # count's extremes, ragged m, splits shorter than a chunk
+            (5003, 64, 128), (4097, 60, 20), (16, 64, 8), (3001, 128, 40), (777, 100, 96),
+            (2050, 144, 24), (65, 256, 4), (5999, 192, 96)]
 
 
 @pytest.mark.parametrize("name", DTYPES)

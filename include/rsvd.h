@@ -374,8 +374,14 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
  * of 4 and l = min(k + p, n) a multiple of 4), allocates one workspace per
  * instance, sized for it, and records the launches with their arguments
  * (uploaded once); nothing runs.  rsvd_batch_grouped_launch runs them on
- * `stream`: results as rsvd_solve on a plan with the batch's seed, bit for
- * bit.  Instances with equal l, k and q share launches.  One launch of a
+ * `stream`: the steps of rsvd_solve on a plan with the batch's seed (the
+ * same G), with longer row splits for the FP64 partial sums (A^T Q and the
+ * m-row Gram matrices: at least 1024 rows each, where a solve alone on the
+ * GPU splits its rows over every CU), since the instances fill the GPU
+ * together; the sums are rounded in another order, so results agree with
+ * rsvd_solve to FP32 rounding, not bit for bit, and every launch of one
+ * grouped batch gives the same bits.  Instances with equal l, k and q share
+ * launches.  One launch of a
  * grouped batch at a time; rsvd_batch_grouped_destroy synchronises the
  * device and frees it. */
 typedef struct rsvd_grouped_s* rsvd_grouped_t;

@@ -1575,8 +1575,14 @@ hipError_t launch_reduce_scalar(const double* parts, int n, double* out, hipStre
 
 // ---------------------------------------------------------------------------
 // Launch geometry (shared by the ordinary and the grouped launchers).
-int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block) {
-  int64_t blocks = (m + 255) / 256;          // at least 256 rows per block
+// Row splits of the partial-sum kernels: at most one block per CU (256) and at
+// least min_rows rows per split.  A solve that has the GPU to itself takes
+// many short splits (parallelism); a grouped batch, whose instances fill the
+// GPU together, takes long ones, so that the FP64 partials (c x c or n x c
+// per split, written and read back by the reduction) stay small beside the
+// panel itself (2c / min_rows of its bytes).
+int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block, int64_t min_rows) {
+  int64_t blocks = (m + min_rows - 1) / min_rows;
   if (blocks > max_split) blocks = max_split;
   if (blocks < 1) blocks = 1;
   int64_t rpb = (m + blocks - 1) / blocks;
@@ -1586,12 +1592,12 @@ int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block) {
 }
 
 int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_per_split,
-                       int* ntile_out) {
+                       int* ntile_out, int64_t min_rows) {
   const int ntile = (int)((n + kUA - 1) / kUA);
   // about one block per CU (256), whole 16-row chunks
   int64_t ns = 256 / ntile;
   if (ns < 1) ns = 1;
-  if (ns > (m + kUK - 1) / kUK) ns = (m + kUK - 1) / kUK;
+  if (ns > (m + min_rows - 1) / min_rows) ns = (m + min_rows - 1) / min_rows;
   if (ns > max_split) ns = max_split;
   int64_t rps = (m + ns - 1) / ns;
   rps = (rps + kUK - 1) / kUK * kUK;

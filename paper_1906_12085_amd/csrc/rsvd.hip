@@ -1473,7 +1473,7 @@ bool grouped_applies(const rsvd_instance& x) {
   int ntile = 0;
   int64_t rps = 0;
   tn_tall_splits(x.m, x.n, 256, &rps, &ntile);   // the largest split count gives the fewest rows
-  return rps * x.lda * 4 < (1LL << 31) && (int64_t)15 * x.lda * 4 + (int64_t)ntile * 512 * 4 < (1LL << 31);
+  return rps * x.lda * 4 < (1LL << 31) && (int64_t)31 * x.lda * 4 + (int64_t)ntile * 512 * 4 < (1LL << 31);
 }
 
 // Record Randomized PCA (the steps and kernels of rsvd_run<float>) for the
@@ -1532,7 +1532,7 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
     std::vector<GArgRed> rr;
     for (int i : ix) {
       int64_t rpb = 0;
-      const int nb = (int)gram_blocks(rows(i), P(i).max_split, &rpb);
+      const int nb = (int)gram_blocks(rows(i), P(i).max_split, &rpb, kGroupedSplitRows);
       rg.push_back({Yp(i), rows(i), l, l, P(i).part, rpb, nb});
       rr.push_back({P(i).part, nb, l, l, P(i).Wg, l, blocks256((int64_t)l * l)});
     }
@@ -1569,7 +1569,7 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
       const rsvd_instance& x = X(i);
       int ntile = 0;
       int64_t rps = 0;
-      const int ns = (int)tn_tall_splits(x.m, x.n, P(i).max_split, &rps, &ntile);
+      const int ns = (int)tn_tall_splits(x.m, x.n, P(i).max_split, &rps, &ntile, kGroupedSplitRows);
       rt.push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Q1, l, l, rps, ntile,
                     P(i).part, ns * ntile});
       rr.push_back({P(i).part, ns, x.n, l, P(i).Zd, l, blocks256(x.n * (int64_t)l)});
@@ -1784,7 +1784,8 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
     p.l_max = (int)((x.k + (int64_t)x.p < x.n) ? x.k + x.p : x.n);
     p.gram = false;
     p.seed = batch->plan[0]->seed;
-    // the batch's split limit: the same row splits, so the same sums, as its slots
+    // the batch's split limit bounds the partials (the grouped splits are
+    // longer than a slot's: kGroupedSplitRows rows at least)
     p.max_split = batch->plan[0]->max_split;
     off[i] = total;
     total += carve(&p, nullptr);

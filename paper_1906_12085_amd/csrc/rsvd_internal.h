@@ -305,9 +305,13 @@ struct GArgStat {   // k_reset (src = nullptr: status = RSVD_OK, diag zeroed) an
 };
 
 // Launch geometry shared by the ordinary and the grouped launchers.
-int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block);
+// Row splits of the Gram and A^T Q partial sums: min_rows is the shortest
+// split (the defaults suit a solve alone on the GPU; grouped batches take
+// kGroupedSplitRows).
+constexpr int64_t kGroupedSplitRows = 1024;
+int64_t gram_blocks(int64_t m, int64_t max_split, int64_t* rows_per_block, int64_t min_rows = 256);
 int64_t tn_tall_splits(int64_t m, int64_t n, int64_t max_split, int64_t* rows_per_split,
-                       int* ntile);
+                       int* ntile, int64_t min_rows = 16);
 int tn_col_waves(int64_t n);
 int64_t narrow_blocks(int64_t m);
 int64_t tall_blocks(int64_t m);

@@ -1465,14 +1465,15 @@ int blocks256(int64_t total) { return (int)((total + 255) / 256); }
 
 // Whether the grouped path takes this fp32 instance: the tall kernels'
 // layout conditions for A, and a sketch width that is a multiple of 4.
-bool grouped_applies(const rsvd_instance& x) {
+bool grouped_applies(const rsvd_instance& x, int64_t max_split) {
   const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
   if (l % 4 != 0 || x.n % 4 != 0 || x.lda % 4 != 0) return false;
   if (reinterpret_cast<uintptr_t>(x.A) % 16 != 0) return false;
   if ((int64_t)128 * x.lda * 4 >= (1LL << 31)) return false;
   int ntile = 0;
   int64_t rps = 0;
-  tn_tall_splits(x.m, x.n, 256, &rps, &ntile);   // the largest split count gives the fewest rows
+  // the A^T Q splits record_group takes (32-bit buffer offsets within one)
+  tn_tall_splits(x.m, x.n, max_split, &rps, &ntile, kGroupedSplitRows);
   return rps * x.lda * 4 < (1LL << 31) && (int64_t)31 * x.lda * 4 + (int64_t)ntile * 512 * 4 < (1LL << 31);
 }
 
@@ -1764,7 +1765,7 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(batch->plan[0], inst[i]);
     if (rc != RSVD_OK) return rc;
-    if (!grouped_applies(inst[i])) return RSVD_ERR_ARG;
+    if (!grouped_applies(inst[i], batch->plan[0]->max_split)) return RSVD_ERR_ARG;
   }
   if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
   rsvd_grouped_s* g = new (std::nothrow) rsvd_grouped_s();

@@ -187,6 +187,28 @@ def test_gemm_tn_parity(plans, name, m, n, c):
     assert np.all(np.abs(host(Z) - Zref) <= bound)
 
 
+@pytest.mark.parametrize("m,n,pad,c", [(3000, 60, 4, 40), (2500, 120, 8, 24), (1800, 200, 4, 96),
+                                         (777, 300, 4, 48)])
+def test_gemm_tn_padded_rows(plans, m, n, pad, c):
+    # A as a view with row stride lda = n + pad (a multiple of 4): the fp32
+    # kernels read whole 64-column slabs from each row start, so the padding
+    # and the next row's leading entries are read and must not reach Z
+    dt = torch.float32
+    announce(f"gemm_tn padded rows m={m} n={n} lda={n + pad} c={c}")
+    rng = np.random.default_rng(m + n + pad + c)
+    A0 = rounded(rng.standard_normal((m, n)), dt)
+    Q0 = rounded(rng.standard_normal((m, c)), dt)
+    Abig = torch.full((m, n + pad), float("nan"), dtype=dt, device="cuda")
+    Abig[:, :n] = dev(A0, dt)
+    Z = torch.empty(n, c, dtype=torch.float64, device="cuda")
+    rs.rsvd_gemm_tn(plans["f32"].handle, Abig[:, :n], dev(Q0, dt), Z)
+    torch.cuda.synchronize()
+    Zref = oracle.gemm_tn(A0, Q0)
+    bound = 2.0 * m * unit(dt) * (np.abs(A0).T @ np.abs(Q0)) + 1e-300
+    assert np.all(np.isfinite(host(Z)))
+    assert np.all(np.abs(host(Z) - Zref) <= bound)
+
+
 @pytest.mark.parametrize("name", DTYPES)
 @pytest.mark.parametrize("m,c,kappa", [(2000, 30, 1e2), (5000, 80, 1e3), (333, 17, 10.0),
                                            (3000, 96, 1e2), (4000, 44, 1e3)])

@@ -171,6 +171,49 @@ def test_batch_grouped_replays_and_oracle():
     b.close()
 
 
+def test_batch_grouped_wide_columns():
+    # the wider A^T Q kernels in grouped launches (n = 192 and 256: 256-column
+    # slabs; n = 512: the 512-column tile), m below and above the grouped
+    # split length (1024 rows), two rank groups; replays bit for bit, results
+    # against the oracle and the solo solve
+    dt = torch.float32
+    announce("grouped batch: n in {192, 256, 512}, m 900..5000, two launches")
+    shapes = [(900, 512, 16), (5000, 512, 32), (1500, 192, 32), (3000, 256, 16), (1100, 256, 32),
+              (4000, 192, 16)]
+    rng = np.random.default_rng(77)
+    probs = []
+    for m, n, k in shapes:
+        sig = np.exp(-rng.uniform(0.01, 0.05) * np.arange(1, n + 1))
+        A0 = rounded(synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T, dt)
+        probs.append((dev(A0, dt), k, 8, 2, 0.9, A0))
+    b = rs.Batch(2, 5000, 512, 40, dt, seed=SEED)
+    g = b.grouped([pr[:5] for pr in probs])
+    g.launch()
+    torch.cuda.synchronize()
+    first = [{key: o[key].clone() for key in ("U", "S", "V", "K", "status")} for o in g.outs]
+    g.launch()
+    torch.cuda.synchronize()
+    for o, f in zip(g.outs, first):
+        for key in f:
+            assert torch.equal(o[key], f[key]), key
+    alone = rs.Plan(5000, 512, 40, dt, seed=SEED)
+    for (A, k, p, q, t, A0), o in zip(probs, g.outs):
+        ref = alone.solve(A, k, p, q, t)
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+        assert np.max(np.abs(host(o["S"]) - host(ref.S)) / host(ref.S)) <= 1e-5
+        n = A.shape[1]
+        G = rounded(synth.gaussian_omega(SEED, n, k + p), dt)
+        orc = oracle.rsvd(A0, G, k, p, q, t)
+        S, U, V = host(o["S"]), host(o["U"]), host(o["V"])
+        assert np.max(np.abs(S - orc.S) / orc.S) <= 1e-4, A.shape
+        assert oracle.principal_angle_max(orc.V, V) <= 1e-3
+        assert oracle.principal_angle_max(orc.U, U) <= 1e-3
+        assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
+    g.close()
+    alone.close()
+    b.close()
+
+
 def test_batch_grouped_arguments():
     b = rs.Batch(2, 4000, 64, 24, torch.float32, seed=1)
     A = torch.zeros((1000, 64), dtype=torch.float32, device="cuda")

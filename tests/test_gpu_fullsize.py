@@ -181,3 +181,31 @@ def test_config3_shape_lowp_vs_oracle(fmt):
              f"K {res.K} (oracle {ref.K})")
     assert sig <= 1e-4 and av <= 1e-3 and au <= 1e-3
     assert res.K == ref.K and res.status == ref.status
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_tall_narrow_rsvd_vs_oracle(n):
+    # the largest serving shapes' row count with a narrow A (the A^T Q
+    # passes on the narrow kernel, 256 splits of ~1,950 rows each, 61-122
+    # chunks per block): 500,000 x n FP32, sigma_i = i^-1 plus N(0, 1e-5)
+    # noise (the noise's singular values, ~7e-3, stay below sigma_16, so the
+    # top-16 subspace has a 6% gap), k = 16, p = 8, q = 2; oracle on the same
+    # stored A and sketch
+    m, k, p, q, t = 500_000, 16, 8, 2, 0.9
+    l = k + p
+    announce(f"tall narrow: {m}x{n} rsvd_solve vs oracle")
+    A = synth.spiked_noisy_torch(50 + n, m, n, synth.config2_sigma(n), 1e-5,
+                                 torch.device("cuda", 0), torch.float32)
+    torch.cuda.synchronize()
+    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=606)
+    res = plan.solve(A, k, p, q, t)
+    plan.close()
+    A64 = A.double().cpu().numpy()
+    G = synth.gaussian_omega(606, n, l).astype(np.float32).astype(np.float64)
+    ref = oracle.rsvd(A64, G, k, p, q, t)
+    S, U, V = host(res.S), host(res.U), host(res.V)
+    assert np.max(np.abs(S - ref.S) / ref.S) <= 1e-4
+    assert oracle.principal_angle_max(ref.V, V) <= 1e-3
+    assert oracle.principal_angle_max(ref.U, U) <= 1e-3
+    assert res.K == ref.K and res.status == ref.status

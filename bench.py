@@ -1,18 +1,22 @@
-"""Benchmark: one step = one pass of the whole hot path on the 1,000,000 x 512
-FP32 PCA workload -- a Randomized PCA solve (k=64, p=16, q=2, Gaussian
-sketch, t=0.95) followed by the all-eigenpairs A^T A-route solve (k=n=512)
-on the same device-resident A.
+"""Benchmark of the Randomized PCA hot path on one MI355X.
 
-Prints ONE JSON line (rank 0): whole-job throughput in solves/s (one solve =
-one step), per-leg latencies (p50/p99) and TFLOP/s, the roofline of the
-dominant kernel timed live with HIP events on the plan's stream, and the CPU
-oracle timed on a bounded row sample of the same A.
+Headline (the metric): Randomized PCA solves/s on the 1,000,000 x 512 FP32
+workload (sigma_i = 1/i plus N(0, 1e-3) noise, centred; k=64, p=16, q=2,
+t=0.95; Gaussian sketch from the plan's seed), one solve per step on one
+stream with A resident in HBM; p50/p99 per solve; the roofline of the
+solve's dominant kernel from HIP events the library records around it on the
+plan's stream.  Legs: the whole hot path (the solve and the all-eigenpairs
+A^T A route on the same A, concurrently), the A^T A route alone, the FP64
+2000 x 200 latency case (eager and graph-replayed, kernels per solve), bf16
+and FP8 storage, the Krylov method, the 512-instance batch and the serving
+stream.  cpu_baseline: the FP64 oracle's Randomized PCA on the full matrix.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -36,15 +40,19 @@ BATCH_SLOTS = 8
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM counters)")
-    ap.add_argument("--cpu-sample-rows", type=int, default=62_500)
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="rows of A the CPU oracle solves (0 = all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-gram", action="store_true", help="time the Randomized PCA leg only")
+    ap.add_argument("--no-gram", action="store_true",
+                    help="skip the A^T A-route legs (alone and in the whole-path step)")
+    ap.add_argument("--no-config1", action="store_true",
+                    help="skip the FP64 2000 x 200 latency leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving leg (Poisson arrivals, continuous batching)")
     ap.add_argument("--no-batch", action="store_true",
@@ -129,7 +137,9 @@ def kernel_source_digest(path, names):
 
 
 def traffic_bytes(kind, m, n, l):
-    if kind not in TRAFFIC or (m, n, l) != TRAFFIC_SHAPE:
+    # the A^T A-route kernels do not depend on the sketch width
+    shape = (m, n) if kind in ("eigensolver", "syrk", "nn_wide") else (m, n, l)
+    if kind not in TRAFFIC or shape != TRAFFIC_SHAPE[:len(shape)]:
         return None
     nbytes, path, name, digest = TRAFFIC[kind]
     if nbytes is None or kernel_source_digest(path, name) != digest:
@@ -488,6 +498,249 @@ def pct(xs, p):
     return xs[i]
 
 
+class HipGraph:
+    """Stream capture of library calls into a HIP graph through the HIP
+    runtime's C API (ctypes): begin/end capture on a stream, count the
+    graph's nodes, instantiate, launch."""
+
+    def __init__(self):
+        lib = None
+        for name in ("libamdhip64.so", "libamdhip64.so.7", "libamdhip64.so.6"):
+            try:
+                lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        if lib is None:
+            raise OSError("libamdhip64 not found")
+        vp = ctypes.c_void_p
+        lib.hipStreamBeginCapture.argtypes = [vp, ctypes.c_int]
+        lib.hipStreamEndCapture.argtypes = [vp, ctypes.POINTER(vp)]
+        lib.hipGraphGetNodes.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.hipGraphInstantiate.argtypes = [ctypes.POINTER(vp), vp, vp, vp, ctypes.c_size_t]
+        lib.hipGraphLaunch.argtypes = [vp, vp]
+        lib.hipGraphExecDestroy.argtypes = [vp]
+        lib.hipGraphDestroy.argtypes = [vp]
+        self.lib, self.graph, self.exec = lib, vp(), vp()
+
+    def capture(self, stream, fn):
+        """Capture fn()'s launches on `stream` (relaxed mode); returns the
+        number of nodes of the captured graph."""
+        sp = ctypes.c_void_p(int(stream.cuda_stream))
+        assert self.lib.hipStreamBeginCapture(sp, 2) == 0
+        fn()
+        assert self.lib.hipStreamEndCapture(sp, ctypes.byref(self.graph)) == 0
+        cnt = ctypes.c_size_t(0)
+        assert self.lib.hipGraphGetNodes(self.graph, None, ctypes.byref(cnt)) == 0
+        assert self.lib.hipGraphInstantiate(ctypes.byref(self.exec), self.graph, None, None, 0) == 0
+        return int(cnt.value)
+
+    def launch(self, stream):
+        assert self.lib.hipGraphLaunch(self.exec, ctypes.c_void_p(int(stream.cuda_stream))) == 0
+
+    def close(self):
+        if self.exec:
+            self.lib.hipGraphExecDestroy(self.exec)
+            self.exec = ctypes.c_void_p()
+        if self.graph:
+            self.lib.hipGraphDestroy(self.graph)
+            self.graph = ctypes.c_void_p()
+
+
+def timed_events(torch, stream, fn, reps):
+    """fn() `reps` times on `stream`, each between two events; returns the
+    per-call GPU times (ms) and the host wall time of the whole loop (s)."""
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(reps):
+        evs[i][0].record(stream)
+        fn()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [e[0].elapsed_time(e[1]) for e in evs], wall
+
+
+def config1_leg(rs, torch, dev, reps):
+    """The FP64 2000 x 200 workload (U Haar in the complement of the ones
+    vector, V Haar, sigma_i = 10 * 0.85^(i-1); k=20, p=10, q=2, t=0.95): a
+    latency case (A is 3.2 MB and stays in cache), reported as microseconds
+    per solve and kernels per solve, eager and as a replayed HIP graph, for
+    the Randomized PCA solve and the all-eigenpairs A^T A route."""
+    import synth
+    c = synth.CONFIG1
+    A0 = synth.config1(c["seed"])
+    m, n = A0.shape
+    k, p, q, t = c["k"], c["p"], c["q"], c["t"]
+    l = k + p
+    A = torch.from_numpy(A0).to(dev)
+    s = torch.cuda.Stream(device=dev)
+    plan = rs.Plan(m, n, l, torch.float64, want_gram=True, seed=c["omega_seed"], stream=s)
+    U = torch.empty(m, k, dtype=torch.float64, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(n, k, dtype=torch.float64, device=dev)
+    K = torch.empty(1, dtype=torch.int32, device=dev)
+    Ug = torch.empty(m, n, dtype=torch.float64, device=dev)
+    Sg = torch.empty(n, dtype=torch.float64, device=dev)
+    Vg = torch.empty(n, n, dtype=torch.float64, device=dev)
+    Kg = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def solve():
+        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
+
+    def gram():
+        rs.gram_eig_solve(plan.handle, A, t, n, Ug, Sg, Vg, Kg)
+
+    for _ in range(3):
+        solve()
+        gram()
+    torch.cuda.synchronize()
+    rs_ms, rs_wall = timed_events(torch, s, solve, reps)
+    st_rs = rs.rsvd_plan_status(plan.handle)
+    S_eager = S.clone()
+    gr_ms, gr_wall = timed_events(torch, s, gram, reps)
+    st_gr = rs.rsvd_plan_status(plan.handle)
+    out = {"workload": "PCA 2000x200 fp64, U Haar (centred), V Haar, sigma_i=10*0.85^(i-1); "
+                       f"rSVD k={k} p={p} q={q} t={t}; A^T A route with all {n} eigenpairs",
+           "rsvd": {"us_p50": round(1e3 * pct(rs_ms, 50), 1), "us_p99": round(1e3 * pct(rs_ms, 99), 1),
+                    "solves_per_s": round(reps / rs_wall, 1), "K": int(K.item()),
+                    "status": rs.STATUS.get(st_rs, st_rs)},
+           "gram_eig": {"us_p50": round(1e3 * pct(gr_ms, 50), 1),
+                        "us_p99": round(1e3 * pct(gr_ms, 99), 1),
+                        "solves_per_s": round(reps / gr_wall, 1), "K": int(Kg.item()),
+                        "status": rs.STATUS.get(st_gr, st_gr)}}
+    # the same solve captured once into a HIP graph and replayed: the number
+    # of graph nodes is the number of kernels a solve launches
+    try:
+        g = HipGraph()
+        nodes = g.capture(s, solve)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.launch(s)
+        torch.cuda.synchronize()
+        gms, gwall = timed_events(torch, s, lambda: g.launch(s), reps)
+        same = bool(torch.equal(S, S_eager))
+        g.close()
+        out["rsvd"].update({"kernels_per_solve": nodes,
+                            "graph_us_p50": round(1e3 * pct(gms, 50), 1),
+                            "graph_us_p99": round(1e3 * pct(gms, 99), 1),
+                            "graph_solves_per_s": round(reps / gwall, 1),
+                            "graph_replay_equals_eager": same})
+    except (OSError, AssertionError) as e:
+        out["rsvd"]["graph"] = f"not captured: {e!r}"
+    plan.close()
+    return out
+
+
+def gram_leg(rs, torch, A, t, steps, warmup, seed):
+    """The all-eigenpairs A^T A route (k = n) alone on the same A: p50/p99
+    and the rooflines of its kernels (symmetric A^T A, the eigensolver, the
+    wide product U = A V S^-1)."""
+    m, n = A.shape
+    dev = A.device
+    stream = torch.cuda.current_stream()
+    plan = rs.Plan(m, n, 16, torch.float32, want_gram=True, seed=seed, stream=stream)
+    Ug = torch.empty(m, n, dtype=torch.float32, device=dev)
+    Sg = torch.empty(n, dtype=torch.float64, device=dev)
+    Vg = torch.empty(n, n, dtype=torch.float32, device=dev)
+    Kg = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def gram():
+        rs.gram_eig_solve(plan.handle, A, t, n, Ug, Sg, Vg, Kg)
+
+    for _ in range(warmup):
+        gram()
+    torch.cuda.synchronize()
+    rs.rsvd_plan_kernel_times(plan.handle, True)
+    ms, wall = timed_events(torch, stream, gram, steps)
+    kt = rs.rsvd_plan_kernel_times(plan.handle, False)
+    st = rs.rsvd_plan_status(plan.handle)
+    diag = plan.diag()
+    plan.close()
+    del Ug
+    torch.cuda.empty_cache()
+    _, _, gr_f, gr_b = algorithmic_counts(m, n, 1, 1, 0, 4)
+    _, rows = kernel_rooflines(kt, m, n, 16, 4, steps)
+    med = pct(ms, 50)
+    return {"p50_ms": round(med, 3), "p99_ms": round(pct(ms, 99), 3),
+            "solves_per_s": round(steps / wall, 2), "tflops": round(gr_f / (med / 1e3) / 1e12, 2),
+            "gbs": round(gr_b / (med / 1e3) / 1e9, 1), "K": int(Kg.item()),
+            "status": rs.STATUS.get(st, st), "eigensolver_sweeps": int(diag[2]),
+            "kernels": rows}
+
+
+def hot_path_leg(rs, torch, A, k, p, q, t, steps, warmup, seed):
+    """One pass of the whole hot path: the Randomized PCA solve and the
+    all-eigenpairs A^T A route on the same A.  The two are independent, so
+    they run concurrently, each with its own plan on its own stream, forked
+    from and joined into the current stream (the eigensolver occupies 64
+    workgroups and is bound by its dependent steps; the solve's passes fill
+    the rest of the GPU)."""
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    stream = torch.cuda.current_stream()
+    s_rs = torch.cuda.Stream(device=dev)
+    s_gr = torch.cuda.Stream(device=dev)
+    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=seed, stream=s_rs)
+    plan_g = rs.Plan(m, n, l, torch.float32, want_gram=True, seed=seed, stream=s_gr)
+    U = torch.empty(m, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(n, k, dtype=torch.float32, device=dev)
+    K = torch.empty(1, dtype=torch.int32, device=dev)
+    Ug = torch.empty(m, n, dtype=torch.float32, device=dev)
+    Sg = torch.empty(n, dtype=torch.float64, device=dev)
+    Vg = torch.empty(n, n, dtype=torch.float32, device=dev)
+    Kg = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def step(evs):
+        evs[0].record(stream)                  # fork
+        s_rs.wait_event(evs[0])
+        s_gr.wait_event(evs[0])
+        evs[3].record(s_gr)
+        rs.gram_eig_solve(plan_g.handle, A, t, n, Ug, Sg, Vg, Kg)
+        evs[4].record(s_gr)
+        stream.wait_event(evs[4])
+        evs[1].record(s_rs)
+        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
+        evs[2].record(s_rs)
+        stream.wait_event(evs[2])              # join
+        evs[5].record(stream)
+
+    for _ in range(warmup):
+        step([torch.cuda.Event() for _ in range(6)])
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    for pl in (plan, plan_g):
+        rs.rsvd_plan_kernel_times(pl.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = [rs.rsvd_plan_kernel_times(pl.handle, False) for pl in (plan, plan_g)]
+    ktimes = {kind: max((x[kind] for x in kt), key=lambda v: v[1]) for kind in kt[0]}
+    status = [rs.STATUS.get(x, x) for x in (rs.rsvd_plan_status(plan.handle),
+                                             rs.rsvd_plan_status(plan_g.handle))]
+    rs_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    gr_ms = [e[3].elapsed_time(e[4]) for e in evs]
+    step_ms = [e[0].elapsed_time(e[5]) for e in evs]
+    plan.close()
+    plan_g.close()
+    del Ug
+    torch.cuda.empty_cache()
+    rs_f, _, gr_f, _ = algorithmic_counts(m, n, k, l, q, 4)
+    _, rows = kernel_rooflines(ktimes, m, n, l, 4, steps)
+    return {"step": "rsvd_solve and gram_eig_solve on two streams, concurrently",
+            "steps_per_s": round(steps / wall, 3), "ms_per_step": round(1e3 * wall / steps, 3),
+            "p50_ms": round(pct(step_ms, 50), 3), "p99_ms": round(pct(step_ms, 99), 3),
+            "rsvd_p50_ms": round(pct(rs_ms, 50), 3), "gram_p50_ms": round(pct(gr_ms, 50), 3),
+            "tflops": round((rs_f + gr_f) / (wall / steps) / 1e12, 2), "status": status,
+            "kernels_shared_gpu": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -513,82 +766,29 @@ def main():
                                  torch.float32)
     torch.cuda.synchronize()
 
-    # the two solves of a step are independent: the rSVD runs on one stream,
-    # the A^T A route (whose eigensolver leaves most of the GPU idle) on
-    # another, each with its own plan; the step forks from and joins into the
-    # current stream
-    s_rs = torch.cuda.Stream(device=dev)
-    s_gr = torch.cuda.Stream(device=dev)
-    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=c["omega_seed"], stream=s_rs)
-    plan_g = (rs.Plan(m, n, l, torch.float32, want_gram=True, seed=c["omega_seed"], stream=s_gr)
-              if not args.no_gram else None)
+    # the headline: one Randomized PCA solve per step on the current stream
+    plan = rs.Plan(m, n, l, torch.float32, want_gram=False, seed=c["omega_seed"], stream=stream)
     U = torch.empty(m, k, dtype=torch.float32, device=dev)
     S = torch.empty(k, dtype=torch.float64, device=dev)
     V = torch.empty(n, k, dtype=torch.float32, device=dev)
     K = torch.empty(1, dtype=torch.int32, device=dev)
-    if not args.no_gram:
-        Ug = torch.empty(m, n, dtype=torch.float32, device=dev)
-        Sg = torch.empty(n, dtype=torch.float64, device=dev)
-        Vg = torch.empty(n, n, dtype=torch.float32, device=dev)
-        Kg = torch.empty(1, dtype=torch.int32, device=dev)
 
-    def step(evs=None):
-        evs = evs or [torch.cuda.Event(enable_timing=False) for _ in range(6)]
-        evs[0].record(stream)                  # fork
-        s_rs.wait_event(evs[0])
-        s_gr.wait_event(evs[0])
-        if not args.no_gram:
-            evs[3].record(s_gr)
-            rs.gram_eig_solve(plan_g.handle, A, t, n, Ug, Sg, Vg, Kg)
-            evs[4].record(s_gr)
-            stream.wait_event(evs[4])
-        evs[1].record(s_rs)
+    def solve():
         rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
-        evs[2].record(s_rs)
-        stream.wait_event(evs[2])              # join
-        evs[5].record(stream)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        step()
+        solve()
     torch.cuda.synchronize()
-    plans = [plan] + ([plan_g] if plan_g is not None else [])
-    st = [rs.rsvd_plan_status(pl.handle) for pl in plans]
+    st_warm = rs.rsvd_plan_status(plan.handle)
 
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} solves", file=sys.stderr, flush=True)
     # per-kernel launch durations inside the timed steps: HIP events recorded
-    # by the library on each plan's stream around each timed kernel
-    for pl in plans:
-        rs.rsvd_plan_kernel_times(pl.handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = [rs.rsvd_plan_kernel_times(pl.handle, False) for pl in plans]
-    ktimes = {kind: max((x[kind] for x in kt), key=lambda v: v[1]) for kind in kt[0]}
-    wall = t1 - t0
-    rs_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    gr_ms = [e[3].elapsed_time(e[4]) for e in evs] if plan_g is not None else [0.0]
-    step_ms = [e[0].elapsed_time(e[5]) for e in evs]
-    status = [rs.rsvd_plan_status(pl.handle) for pl in plans]
-
-    # the same kernels without the other solve beside them (context for the
-    # per-kernel rooflines; outside the timed region): the two solves of each
-    # step one after the other
-    for pl in plans:
-        rs.rsvd_plan_kernel_times(pl.handle, True)
-    torch.cuda.synchronize()
-    for i in range(args.steps):
-        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
-        torch.cuda.synchronize()
-        if plan_g is not None:
-            rs.gram_eig_solve(plan_g.handle, A, t, n, Ug, Sg, Vg, Kg)
-            torch.cuda.synchronize()
-    kt = [rs.rsvd_plan_kernel_times(pl.handle, False) for pl in plans]
-    ktimes_iso = {kind: max((x[kind] for x in kt), key=lambda v: v[1]) for kind in kt[0]}
+    # by the library on the plan's stream around each timed kernel
+    rs.rsvd_plan_kernel_times(plan.handle, True)
+    step_ms, wall = timed_events(torch, stream, solve, args.steps)
+    ktimes = rs.rsvd_plan_kernel_times(plan.handle, False)
+    status = rs.rsvd_plan_status(plan.handle)
 
     if args.pmc_copy:
         # a plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read
@@ -600,36 +800,36 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # accuracy of this run's rSVD: FP32 path vs the FP64 path of the same
+    # accuracy of this run's solve: FP32 path vs the FP64 path of the same
     # library on the same stored A and sketch (the oracle comparison at this
-    # size is in tests/test_gpu_fullsize.py)
+    # size is in the full-size GPU tests)
     A64 = A.double()
     plan64 = rs.Plan(m, n, l, torch.float64, want_gram=False, seed=c["omega_seed"], stream=stream)
     r64 = plan64.solve(A64, k, p, q, t)
     sig_err = float(torch.max(torch.abs(S - r64.S) / r64.S).item())
+    same_k = int(K.item()) == r64.K
     plan64.close()
-    del A64
+    del A64, r64
     torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel (largest time per step), from the
-    # live launch durations of the timed steps and the algorithmic counts
     b = 4
     roof, all_k = kernel_rooflines(ktimes, m, n, l, b, args.steps)
-    _, iso_k = kernel_rooflines(ktimes_iso, m, n, l, b, args.steps)
-    rs_f, rs_b, gr_f, gr_b = algorithmic_counts(m, n, k, l, q, b)
-    rs_med, gr_med = pct(rs_ms, 50), pct(gr_ms, 50)
-    legs = {
-        "rsvd": {"p50_ms": round(rs_med, 3), "p99_ms": round(pct(rs_ms, 99), 3),
-                 "solves_per_s": round(1000.0 / rs_med, 2),
-                 "tflops": round(rs_f / (rs_med / 1e3) / 1e12, 2),
-                 "gbs": round(rs_b / (rs_med / 1e3) / 1e9, 1),
-                 "K": int(K.item()), "sigma_rel_err_vs_fp64_path": sig_err},
-    }
+    rs_f, rs_b, _, _ = algorithmic_counts(m, n, k, l, q, b)
+    med = pct(step_ms, 50)
+    passes_ms = sum(r["ms_per_step"] for kk, r in all_k.items() if kk in ("pass_nn", "pass_tn"))
+    legs = {}
+
     if not args.no_gram:
-        legs["gram_eig"] = {"p50_ms": round(gr_med, 3), "p99_ms": round(pct(gr_ms, 99), 3),
-                            "solves_per_s": round(1000.0 / gr_med, 2),
-                            "tflops": round(gr_f / (gr_med / 1e3) / 1e12, 2),
-                            "K": int(Kg.item())}
+        print(f"[bench] whole hot path (rSVD + A^T A route, concurrent): {args.steps} steps",
+              file=sys.stderr, flush=True)
+        legs["hot_path_step"] = hot_path_leg(rs, torch, A, k, p, q, t, args.steps, args.warmup,
+                                             c["omega_seed"])
+        print(f"[bench] A^T A route alone: {args.steps} solves", file=sys.stderr, flush=True)
+        legs["gram_eig"] = gram_leg(rs, torch, A, t, args.steps, args.warmup, c["omega_seed"])
+
+    if not args.no_config1:
+        print("[bench] fp64 2000x200 latency leg", file=sys.stderr, flush=True)
+        legs["config1_fp64"] = config1_leg(rs, torch, dev, max(50, 5 * args.steps))
 
     if not args.no_bf16:
         for key, fmt in (("rsvd_bf16", torch.bfloat16), ("rsvd_fp8", torch.float8_e4m3fn)):
@@ -645,8 +845,8 @@ def main():
                                     args.steps, args.warmup, stream)
 
     if not args.no_batch:
-        print(f"[bench] batched leg: {synth.CONFIG4['count']} instances, {args.steps} batches "
-              "per mode", file=sys.stderr, flush=True)
+        print(f"[bench] batched leg: {synth.CONFIG4['count']} instances", file=sys.stderr,
+              flush=True)
         legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
 
     if not args.no_serve:
@@ -658,12 +858,12 @@ def main():
         legs["serve_bf16"]["K_equals_fp32_serving"] = round(
             sum(a == b for a, b in zip(k32, k16)) / max(1, len(k32)), 4)
 
+    plan.close()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, args.cpu_sample_rows, k, p, q, t, c["omega_seed"],
-                           with_gram=not args.no_gram)
-    for pl in plans:
-        pl.close()
+        print("[bench] cpu baseline: the FP64 oracle's Randomized PCA", file=sys.stderr,
+              flush=True)
+        cpu = cpu_baseline(A, args.cpu_sample_rows, k, p, q, t, c["omega_seed"])
 
     value = args.steps / wall
     out = {
@@ -674,71 +874,65 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(1000.0 * wall / args.steps, 3),
-        "p50_ms": round(pct(step_ms, 50), 3),
+        "p50_ms": round(med, 3),
         "p99_ms": round(pct(step_ms, 99), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"PCA {m}x{n} fp32, sigma_i=1/i + N(0,1e-3) noise, centred; "
-                               f"rSVD k={k} p={p} q={q} t={t} + A^T A route k=n={n}",
+        "config": {"workload": f"Randomized PCA of a {m}x{n} fp32 matrix, sigma_i=1/i + N(0,1e-3) "
+                               f"noise, centred; k={k} p={p} q={q} t={t}, Gaussian sketch",
                    "m": m, "n": n, "k": k, "p": p, "q": q, "t": t,
-                   "step": ("rsvd_solve and gram_eig_solve on two streams, concurrently"
-                            if not args.no_gram else "rsvd_solve")},
-        "legs": legs,
-        "tflops_step": round((rs_f + (0 if args.no_gram else gr_f)) / (wall / args.steps) / 1e12, 2),
-        "status": [rs.STATUS.get(x, x) for x in status],
-        "status_warmup": [rs.STATUS.get(x, x) for x in st],
+                   "step": "one rsvd_solve on one stream, A resident in HBM"},
+        "tflops": round(rs_f / (wall / args.steps) / 1e12, 2),
+        "gbs": round(rs_b / (wall / args.steps) / 1e9, 1),
+        "K": int(K.item()),
+        "K_equals_fp64_path": same_k,
+        "sigma_rel_err_vs_fp64_path": sig_err,
+        "status": rs.STATUS.get(status, status),
+        "status_warmup": rs.STATUS.get(st_warm, st_warm),
+        "passes_ms_per_solve": round(passes_ms, 3),
         "roofline": roof,
         "kernels": all_k,
-        "kernels_isolated": iso_k,
+        "legs": legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(A, rows, k, p, q, t, omega_seed, with_gram=True):
-    """The FP64 oracle, as it stands, on the first `rows` rows of the same A:
-    one step (rSVD + A^T A route).  Its m-proportional time is scaled to the
-    full m; the n x n eigensolve, whose cost does not depend on m, is timed
-    on its own and counted once."""
+def cpu_baseline(A, rows, k, p, q, t, omega_seed):
+    """The FP64 oracle, as it stands, timed on this host: its Randomized PCA
+    (the same steps and sketch) on the same stored matrix read back to FP64
+    -- all of it by default, or its first `rows` rows with the time scaled
+    to the full row count (every step of the solve but the n x l small SVD
+    is proportional to m)."""
     import numpy as np
 
     import oracle
     import synth
 
     m, n = A.shape
-    rows = min(rows, m)
-    A0 = A[:rows].double().cpu().numpy()
+    rows = m if rows <= 0 else min(rows, m)
+    A0 = A[:rows].cpu().numpy().astype(np.float64)
     l = min(k + p, n)
     G = synth.gaussian_omega(omega_seed, n, l).astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
     oracle.rsvd(A0, G, k, p, q, t)
-    t1 = time.perf_counter()
-    t_rs = t1 - t0
-    t_gr = t_eig = 0.0
-    if with_gram:
-        # the A^T A route as the oracle computes it (orc_gram_eig's steps),
-        # timed step by step so the m-independent eigensolve is known
-        t0 = time.perf_counter()
-        Gm = oracle.gemm_tn(A0, A0)
-        t1 = time.perf_counter()
-        lam, Vo, _ = oracle.eig_sym(Gm)
-        t2 = time.perf_counter()
-        s = np.sqrt(np.maximum(lam, 0.0))
-        oracle.gemm_nn(A0, Vo / np.where(s > 0, s, 1.0))
-        t3 = time.perf_counter()
-        t_eig = t2 - t1
-        t_gr = t3 - t0
+    sec = time.perf_counter() - t0
+    del A0
+    if rows == m:
+        return {"value": round(1.0 / sec, 6), "unit": "solves/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"one Randomized PCA solve of the full {m}x{n} matrix (FP64 oracle, "
+                          f"k={k} p={p} q={q}): {sec:.1f} s",
+                "sample_seconds": round(sec, 2)}
     scale = m / rows
-    t_full = (t_rs + t_gr - t_eig) * scale + t_eig
-    return {"value": round(1.0 / t_full, 6), "unit": "solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {rows} of {m} rows; one step (rSVD + A^T A route) took "
-                      f"{t_rs + t_gr:.1f} s ({t_eig:.1f} s of it the m-independent n x n "
-                      f"eigensolve); m-proportional part scaled by {scale:.0f}",
-            "sample_seconds": round(t_rs + t_gr, 2)}
+    return {"value": round(1.0 / (sec * scale), 6), "unit": "solves/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"extrapolated: one solve of the first {rows} of {m} rows took {sec:.1f} s, "
+                      f"scaled by {scale:.1f}",
+            "sample_seconds": round(sec, 2)}
 
 
 if __name__ == "__main__":

@@ -90,7 +90,7 @@ const char* rsvd_status_string(int32_t status);
  *             Box-Muller, see rsvd_gaussian_fill)
  *   stream    hipStream_t to order all work on; NULL = the null stream
  * Limits: l_max <= 96 (the l x l factors live in one workgroup's LDS); with
- * want_gram, n_max <= 1120 (the eigensolver keeps column blocks in LDS).
+ * want_gram, n_max <= 1024 (every workgroup of the eigensolver is resident).
  * Errors: RSVD_ERR_ARG (plan NULL, bad dtype, l_max < 1), RSVD_ERR_SHAPE
  * (m_max < n_max, n_max < 1, or a limit above exceeded), RSVD_ERR_NOMEM,
  * RSVD_ERR_DEVICE. */
@@ -136,24 +136,34 @@ int32_t rsvd_plan_kernel_times(rsvd_plan_t plan, int32_t enable, double* ms, int
  * each product with A or A^T is followed by an orthonormalisation
  * (CholeskyQR2 for the m x l basis), and K is chosen by threshold t in (0, 1]
  * over the k computed values (Sec. 2.4).
+ *   A          element type of the plan: double (RSVD_F64), float
+ *              (RSVD_F32), bfloat16 (RSVD_BF16) or FP8 E4M3 bytes
+ *              (RSVD_FP8); for the last two the matrix is
+ *              A diag(col_scale), as in rsvd_solve_bf16 / rsvd_solve_fp8
+ *   col_scale  (n floats, device) column scales of bfloat16 / FP8 storage,
+ *              NULL = all ones; must be NULL on RSVD_F64 / RSVD_F32 plans
  *   U  (m x k, ldu >= k)  left singular vectors U~ = Q W (first k columns)
  *   S  (k, double)        singular values, descending
  *   V  (n x k, ldv >= k)  right singular vectors (the principal axes)
  *   K  (1 int32, device)  number of components meeting t (K <= k)
  * The sketch G is drawn from the plan's seed: repeated calls on one plan use
  * the same G.  Errors (synchronous): RSVD_ERR_ARG (a NULL pointer, k < 1,
- * k > n, p < 0, q < 0, t outside (0, 1], lda < n, ldu < k, ldv < k),
- * RSVD_ERR_SHAPE (m < n, or m, n, l above the plan's maxima). */
+ * k > n, p < 0, q < 0, t outside (0, 1], lda < n, ldu < k, ldv < k,
+ * col_scale given on an RSVD_F64 / RSVD_F32 plan, the storage conditions of
+ * rsvd_solve_bf16 / rsvd_solve_fp8 on a low-precision plan), RSVD_ERR_SHAPE
+ * (m < n, or m, n, l above the plan's maxima). */
 int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
-                   int32_t k, int32_t p, int32_t q, double t,
+                   const float* col_scale, int32_t k, int32_t p, int32_t q, double t,
                    void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
 
 /* Same as rsvd_solve with the sketch G supplied: `omega` is a device FP64
  * row-major n x l matrix, l = min(k + p, n) (it is rounded to the plan's
- * dtype before use).  For parity tests and for callers with their own G. */
+ * dtype before use), or NULL for the plan's seeded sketch.  For parity tests
+ * and for callers with their own G. */
 int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
-                         int32_t k, int32_t p, int32_t q, double t, const double* omega,
-                         void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
+                         const float* col_scale, int32_t k, int32_t p, int32_t q, double t,
+                         const double* omega, void* U, int64_t ldu, double* S, void* V,
+                         int64_t ldv, int32_t* K);
 
 /* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
  * min(k + p, n)), blocks H(0) = A G and H(j) = A (A^T H(j-1)) for j = 1..i,
@@ -170,7 +180,7 @@ int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n,
                           int32_t k, int32_t p, int32_t i, double t, const double* omega,
                           void* U, int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K);
 
-/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the
+/* rsvd_solve_bf16: Randomized PCA (Sec. 3.1.2, steps as rsvd_solve) of the
  * matrix Aq diag(col_scale), Aq bfloat16 m x n (device, row-major, lda),
  * col_scale n FP32 values (device; NULL = all ones).  The plan must be
  * RSVD_BF16.  H = A G and the power-iteration products run on BF16 matrix
@@ -181,8 +191,8 @@ int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n,
  * as for RSVD_F32.  omega: as rsvd_solve_omega, or NULL for the plan's seeded
  * sketch.  U (m x k, ldu), V (n x k, ldv) float; S, K as rsvd_solve.
  * Requires n % 8 == 0, lda % 8 == 0 and a 16-byte aligned A (else
- * RSVD_ERR_ARG).  rsvd_solve / rsvd_solve_omega on an RSVD_BF16 plan take A
- * as bfloat16 with unit scales. */
+ * RSVD_ERR_ARG).  rsvd_solve / rsvd_solve_omega on an RSVD_BF16 plan are
+ * this call (with the plan's seeded sketch for rsvd_solve). */
 int32_t rsvd_solve_bf16(rsvd_plan_t plan, const void* A, const float* col_scale, int64_t m,
                         int64_t n, int64_t lda, int32_t k, int32_t p, int32_t q, double t,
                         const double* omega, float* U, int64_t ldu, double* S, float* V,
@@ -413,7 +423,10 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
                            int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget);
 
 /* Queue one request (arguments and status word as a batch instance; the
- * buffers must stay valid until it is reported done).  Validated at once
+ * buffers must stay valid until it is reported done).  A (and col_scale)
+ * must be complete on the device when this is called: the request runs on
+ * the server's own slot streams, which are not ordered after any stream of
+ * the caller (synchronise the stream that wrote A first).  Validated at once
  * (RSVD_ERR_ARG / RSVD_ERR_SHAPE as rsvd_solve, nothing queued); *ticket
  * receives its number (0, 1, 2, ... in submission order).  Admits at once
  * when it can. */

@@ -87,8 +87,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_plan_destroy": (i32, [vp]),
         "rsvd_plan_status": (i32, [vp]),
         "rsvd_plan_diag": (i32, [vp, vp, i32]),
-        "rsvd_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp]),
-        "rsvd_solve_omega": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
+        "rsvd_solve": (i32, [vp, vp, i64, i64, i64, vp, i32, i32, i32, dbl, vp, i64, vp, vp, i64,
+                             vp]),
+        "rsvd_solve_omega": (i32, [vp, vp, i64, i64, i64, vp, i32, i32, i32, dbl, vp,
                                    vp, i64, vp, vp, i64, vp]),
         "rsvd_solve_krylov": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                     vp, i64, vp, vp, i64, vp]),
@@ -196,19 +197,23 @@ def rsvd_plan_kernel_times(plan: int, enable: bool):
     return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(nc)}
 
 
-def rsvd_solve(plan: int, A, k: int, p: int, q: int, t: float, U, S, V, K) -> int:
+def rsvd_solve(plan: int, A, k: int, p: int, q: int, t: float, U, S, V, K,
+               col_scale=None) -> int:
     m, n = A.shape
-    return _check(load_library().rsvd_solve(plan, _ptr(A), m, n, _ld(A), k, p, q, float(t),
-                                            _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V), _ptr(K)),
-                  "rsvd_solve")
+    return _check(load_library().rsvd_solve(plan, _ptr(A), m, n, _ld(A), _ptr(col_scale), k, p,
+                                            q, float(t), _ptr(U), _ld(U), _ptr(S), _ptr(V),
+                                            _ld(V), _ptr(K)), "rsvd_solve")
 
 
-def rsvd_solve_omega(plan: int, A, k: int, p: int, q: int, t: float, omega, U, S, V, K) -> int:
+def rsvd_solve_omega(plan: int, A, k: int, p: int, q: int, t: float, omega, U, S, V, K,
+                     col_scale=None) -> int:
     m, n = A.shape
-    assert omega.is_contiguous() and omega.dtype.is_floating_point and omega.element_size() == 8
-    return _check(load_library().rsvd_solve_omega(plan, _ptr(A), m, n, _ld(A), k, p, q, float(t),
-                                                  _ptr(omega), _ptr(U), _ld(U), _ptr(S), _ptr(V),
-                                                  _ld(V), _ptr(K)), "rsvd_solve_omega")
+    if omega is not None:
+        assert omega.is_contiguous() and omega.dtype.is_floating_point and omega.element_size() == 8
+    return _check(load_library().rsvd_solve_omega(plan, _ptr(A), m, n, _ld(A), _ptr(col_scale), k,
+                                                  p, q, float(t), _ptr(omega), _ptr(U), _ld(U),
+                                                  _ptr(S), _ptr(V), _ld(V), _ptr(K)),
+                  "rsvd_solve_omega")
 
 
 def rsvd_solve_krylov(plan: int, A, k: int, p: int, i: int, t: float, omega, U, S, V,
@@ -360,14 +365,10 @@ class Plan:
         torch = self.torch
         U = self._out((m, k)); V = self._out((n, k))
         S = self._out((k,), torch.float64); K = self._out((1,), torch.int32)
-        if self.storage == torch.bfloat16:
-            rsvd_solve_bf16(self.handle, A, col_scale, k, p, q, t, omega, U, S, V, K)
-        elif self.storage == torch.float8_e4m3fn:
-            rsvd_solve_fp8(self.handle, A, col_scale, k, p, q, t, omega, U, S, V, K)
-        elif omega is None:
-            rsvd_solve(self.handle, A, k, p, q, t, U, S, V, K)
+        if omega is None:
+            rsvd_solve(self.handle, A, k, p, q, t, U, S, V, K, col_scale=col_scale)
         else:
-            rsvd_solve_omega(self.handle, A, k, p, q, t, omega, U, S, V, K)
+            rsvd_solve_omega(self.handle, A, k, p, q, t, omega, U, S, V, K, col_scale=col_scale)
         if not sync:
             return Result(U, S, V, K, 0)
         st = self.status()

@@ -743,20 +743,22 @@ int32_t rsvd_plan_kernel_times(rsvd_plan_t plan, int32_t enable, double* ms, int
 }
 
 int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
-                         int32_t k, int32_t p, int32_t q, double t, const double* omega, void* U,
-                         int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K) {
+                         const float* col_scale, int32_t k, int32_t p, int32_t q, double t,
+                         const double* omega, void* U, int64_t ldu, double* S, void* V,
+                         int64_t ldv, int32_t* K) {
   int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
   if (rc != RSVD_OK) return rc;
+  if (plan->dtype == RSVD_BF16)
+    return rsvd_solve_bf16(plan, A, col_scale, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
+                           (float*)V, ldv, K);
+  if (plan->dtype == RSVD_FP8)
+    return rsvd_solve_fp8(plan, A, col_scale, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
+                          (float*)V, ldv, K);
+  if (col_scale) return RSVD_ERR_ARG;   // column scales belong to bf16 / FP8 storage
   if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
   if (plan->dtype == RSVD_F64)
     return rsvd_run<double>(plan, (const double*)A, m, n, lda, k, p, q, t, omega, (double*)U, ldu,
                             S, (double*)V, ldv, K);
-  if (plan->dtype == RSVD_BF16)
-    return rsvd_solve_bf16(plan, A, nullptr, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
-                           (float*)V, ldv, K);
-  if (plan->dtype == RSVD_FP8)
-    return rsvd_solve_fp8(plan, A, nullptr, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
-                          (float*)V, ldv, K);
   return rsvd_run<float>(plan, (const float*)A, m, n, lda, k, p, q, t, omega, (float*)U, ldu, S,
                          (float*)V, ldv, K);
 }
@@ -840,10 +842,11 @@ int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n,
                            S, (float*)V, ldv, K);
 }
 
-int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda, int32_t k,
-                   int32_t p, int32_t q, double t, void* U, int64_t ldu, double* S, void* V,
-                   int64_t ldv, int32_t* K) {
-  return rsvd_solve_omega(plan, A, m, n, lda, k, p, q, t, nullptr, U, ldu, S, V, ldv, K);
+int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                   const float* col_scale, int32_t k, int32_t p, int32_t q, double t, void* U,
+                   int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K) {
+  return rsvd_solve_omega(plan, A, m, n, lda, col_scale, k, p, q, t, nullptr, U, ldu, S, V, ldv,
+                          K);
 }
 
 int32_t gram_eig_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
@@ -1845,3 +1848,4 @@ int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped) {
 }
 
 }  // extern "C"
+

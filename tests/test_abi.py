@@ -74,7 +74,9 @@ def test_plan_create_validates_before_device_calls(lib):
 
 def test_solvers_reject_null_plan(lib):
     a = ctypes.c_void_p(16)
-    assert lib.rsvd_solve(None, a, 100, 10, 10, 2, 2, 1, 0.9, a, 2, a, a, 2, a) == -1
+    assert lib.rsvd_solve(None, a, 100, 10, 10, None, 2, 2, 1, 0.9, a, 2, a, a, 2, a) == -1
+    assert lib.rsvd_solve_omega(None, a, 100, 10, 10, None, 2, 2, 1, 0.9, None, a, 2, a, a, 2,
+                                a) == -1
     assert lib.gram_eig_solve(None, a, 100, 10, 10, 0.9, 0, None, 0, a, a, 10, a) == -1
     assert lib.rsvd_gemm_nn(None, a, 10, 10, 10, a, 4, 4, a, 4, None, None) == -1
     assert lib.rsvd_plan_status(None) == -1

@@ -444,6 +444,35 @@ int32_t rsvd_server_progress(rsvd_server_t server, int64_t* done, int32_t cap, i
 /* Wait for every queued and running request, then free the server. */
 int32_t rsvd_server_destroy(rsvd_server_t server);
 
+/* ------------------------------------------------------ allocation-free --
+ * rsvd_solve_noalloc: rsvd_solve (Randomized PCA, same steps, same kernels,
+ * same results bit for bit as rsvd_solve on a plan with this seed) without a
+ * plan and without allocating anything: for callers that cannot call
+ * hipMalloc (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid device allocation).  The workspace is a file-scope device
+ * array of RSVD_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds from the library's loading until the process ends; the call makes
+ * no hipMalloc / hipFree and creates no streams or events.
+ *   A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K   as rsvd_solve
+ *   dtype   RSVD_F64 or RSVD_F32 (element type of A, U, V)
+ *   seed    seeds the Gaussian sketch G as rsvd_plan_create's seed does
+ *   status  (1 int32, device) receives the solve's status word (RSVD_OK,
+ *           RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV)
+ *   stream  hipStream_t to order the work on (NULL = the null stream)
+ * Workspace: about (2 m l + n l) elements of dtype plus (s + 6) n l + 16 l^2
+ * doubles, l = min(k + p, n), s = min(256, ceil(m / 64)) row splits.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (on different streams or threads) race and must not be issued; calls
+ * ordered on one stream are safe.  Errors (synchronous, nothing launched):
+ * RSVD_ERR_ARG (bad dtype, NULL A / status, the argument errors of
+ * rsvd_solve), RSVD_ERR_SHAPE (m < n, l > 96, or a workspace larger than
+ * RSVD_NOALLOC_SCRATCH_BYTES), RSVD_ERR_DEVICE. */
+#define RSVD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t rsvd_solve_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype,
+                           int32_t k, int32_t p, int32_t q, double t, uint64_t seed, void* U,
+                           int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K,
+                           int32_t* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,7 +41,7 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_progress",
            "rsvd_server_destroy", "rsvd_batch_grouped_create", "rsvd_batch_grouped_launch",
-           "rsvd_batch_grouped_destroy"]
+           "rsvd_batch_grouped_destroy", "rsvd_solve_noalloc"]
 
 
 class RsvdInstance(ctypes.Structure):
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rsvd_solve_fp8": (i32, [vp, vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                  vp, i64, vp, vp, i64, vp]),
         "rsvd_quantize_fp8": (i32, [vp, vp, i64, i64, i64, vp, i64, vp]),
+        "rsvd_solve_noalloc": (i32, [vp, i64, i64, i64, i32, i32, i32, i32, dbl, u64, vp, i64,
+                                     vp, vp, i64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -214,6 +216,21 @@ def rsvd_solve_omega(plan: int, A, k: int, p: int, q: int, t: float, omega, U, S
                                                   p, q, float(t), _ptr(omega), _ptr(U), _ld(U),
                                                   _ptr(S), _ptr(V), _ld(V), _ptr(K)),
                   "rsvd_solve_omega")
+
+
+def rsvd_solve_noalloc(A, k: int, p: int, q: int, t: float, seed: int, U, S, V, K, status,
+                       stream=None) -> int:
+    """rsvd_solve without a plan: the workspace is the library's static device
+    array (nothing is allocated); status (1 int32, device) receives the
+    status word."""
+    import torch
+    m, n = A.shape
+    code = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}[A.dtype]
+    return _check(load_library().rsvd_solve_noalloc(_ptr(A), m, n, _ld(A), code, k, p, q,
+                                                    float(t), seed, _ptr(U), _ld(U), _ptr(S),
+                                                    _ptr(V), _ld(V), _ptr(K), _ptr(status),
+                                                    _stream_ptr(stream)),
+                  "rsvd_solve_noalloc")
 
 
 def rsvd_solve_krylov(plan: int, A, k: int, p: int, i: int, t: float, omega, U, S, V,

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <deque>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1849,3 +1850,85 @@ int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped) {
 
 }  // extern "C"
 
+// ===========================================================================
+// Allocation-free Randomized PCA: the solve of rsvd_solve with its workspace
+// carved, exactly as a plan's, from a file-scope device array instead of a
+// plan's allocation, for callers that must not allocate device memory.
+// Each GPU the library runs on holds its own copy of the array (module
+// global memory) until the process ends; every call on one GPU uses that
+// GPU's copy, so calls that overlap on one GPU race.
+
+static __device__ __align__(256) char scratch[RSVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current).  In host code the array's name is
+// only a host-side stand-in, so kernels are given this address, never it.
+int32_t scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return RSVD_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return RSVD_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsvd_solve_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype,
+                           int32_t k, int32_t p, int32_t q, double t, uint64_t seed, void* U,
+                           int64_t ldu, double* S, void* V, int64_t ldv, int32_t* K,
+                           int32_t* status, void* stream) {
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
+  if (!A || !status) return RSVD_ERR_ARG;
+  if (n < 1 || m < n) return RSVD_ERR_SHAPE;
+  if (k < 1 || k > n || p < 0) return RSVD_ERR_ARG;
+  const int64_t l = (k + (int64_t)p < n) ? k + (int64_t)p : n;
+  if (l > kMaxL) return RSVD_ERR_SHAPE;
+  // a plan sized for exactly this problem, its workspace in `scratch`: the
+  // same buffers, row splits and kernels as rsvd_solve on a plan with this
+  // seed (so the same results, bit for bit)
+  rsvd_plan_s pl;
+  pl.dtype = dtype;
+  pl.m_max = m;
+  pl.n_max = n;
+  pl.l_max = (int)l;
+  pl.gram = false;
+  pl.seed = seed;
+  pl.stream = (hipStream_t)stream;
+  pl.max_split = tn_max_split(m, n, (int)l);
+  int32_t rc = check_rsvd(&pl, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (carve(&pl, nullptr) > (size_t)RSVD_NOALLOC_SCRATCH_BYTES) return RSVD_ERR_SHAPE;
+  if (hipGetDevice(&pl.device) != hipSuccess) return RSVD_ERR_DEVICE;
+  char* base = nullptr;
+  if ((rc = scratch_address(pl.device, &base)) != RSVD_OK) return rc;
+  carve(&pl, base);
+  // the status word and diagnostics are cleared by the solve's first kernel;
+  // every other buffer is written before it is read
+  if (dtype == RSVD_F64)
+    rc = rsvd_run<double>(&pl, (const double*)A, m, n, lda, k, p, q, t, nullptr, (double*)U, ldu,
+                          S, (double*)V, ldv, K);
+  else
+    rc = rsvd_run<float>(&pl, (const float*)A, m, n, lda, k, p, q, t, nullptr, (float*)U, ldu, S,
+                         (float*)V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, pl.stream, pl.status, status);
+  RSVD_CHECK(hipGetLastError());
+  return RSVD_OK;
+}
+
+}  // extern "C"

@@ -89,8 +89,11 @@ const char* rsvd_status_string(int32_t status);
  *   seed      seeds the Gaussian sketch G of rsvd_solve (Philox4x32-10 +
  *             Box-Muller, see rsvd_gaussian_fill)
  *   stream    hipStream_t to order all work on; NULL = the null stream
- * Limits: l_max <= 96 (the l x l factors live in one workgroup's LDS); with
- * want_gram, n_max <= 1024 (every workgroup of the eigensolver is resident).
+ * Limits: l_max <= 192 (the l x l Cholesky factor and its inverse share one
+ * workgroup's registers); with want_gram, n_max <= 1024 (every workgroup of
+ * the eigensolver is resident).  Sketches wider than 96 columns take their
+ * small SVD on the cooperative block-Jacobi solver (one cooperative launch
+ * per solve).
  * Errors: RSVD_ERR_ARG (plan NULL, bad dtype, l_max < 1), RSVD_ERR_SHAPE
  * (m_max < n_max, n_max < 1, or a limit above exceeded), RSVD_ERR_NOMEM,
  * RSVD_ERR_DEVICE. */
@@ -465,7 +468,7 @@ int32_t rsvd_server_destroy(rsvd_server_t server);
  * GPU (on different streams or threads) race and must not be issued; calls
  * ordered on one stream are safe.  Errors (synchronous, nothing launched):
  * RSVD_ERR_ARG (bad dtype, NULL A / status, the argument errors of
- * rsvd_solve), RSVD_ERR_SHAPE (m < n, l > 96, or a workspace larger than
+ * rsvd_solve), RSVD_ERR_SHAPE (m < n, l > 192, or a workspace larger than
  * RSVD_NOALLOC_SCRATCH_BYTES), RSVD_ERR_DEVICE. */
 #define RSVD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 int32_t rsvd_solve_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype,

@@ -88,7 +88,8 @@ template <int RPT>
 __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
     double* __restrict__ X, double* __restrict__ J, int n, int nbp, int P, int inner_max,
     double* __restrict__ Mpart, double* __restrict__ fro_part, double* __restrict__ lam,
-    double* __restrict__ diag, int32_t* __restrict__ flags, int32_t* __restrict__ status) {
+    double* __restrict__ diag, int32_t* __restrict__ flags, int32_t* __restrict__ status,
+    int svd) {
   constexpr int RS = 16 * RPT;                 // rows per slice
   constexpr int LDX = RS + 1;
   extern __shared__ double sm[];
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
   double fro2 = 0.0;
   for (int i = 0; i < nwg; ++i) fro2 += ld_agent(fro_part + i);
   const double tol = kEps * (double)n, tol2 = tol * tol;
-  const double floor = kEps * kEps * fro2;
+  const double floor = svd ? 0.0 : kEps * kEps * fro2;
 
   // Stage this slice of the pair's kW columns of a matrix (X or J) into LDS,
   // all loads issued before the first store.
@@ -354,7 +355,8 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
     if (g == 0 && tid == 0) set_error(status, RSVD_ERR_DEVICE);
     return;
   }
-  // lambda_j = |x_j| signed by the Rayleigh quotient j_j^T x_j; a wave per column
+  // lambda_j = |x_j| signed by the Rayleigh quotient j_j^T x_j (unsigned for
+  // the SVD); a wave per column
   for (int j = g * 4 + wave; j < n; j += nwg * 4) {
     double s2 = 0.0, rq = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
     }
     s2 = group_sum<64>(s2);
     rq = group_sum<64>(rq);
-    if (lane == 0) lam[j] = rq < 0.0 ? -sqrt(s2) : sqrt(s2);
+    if (lane == 0) lam[j] = (rq < 0.0 && !svd) ? -sqrt(s2) : sqrt(s2);
   }
   if (g == 0 && tid == 0) {
     diag[2] = (double)sweep;
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
 template <int RPT>
 hipError_t eig_launch(double* X, double* J, int n, const Geom& G, int inner, double* lam,
                       double* diag, int32_t* flags, double* scratch, int32_t* status,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int svd) {
   const size_t shmem = ((size_t)2 * kW * (16 * RPT + 1) + (size_t)3 * kW * kLdM) * sizeof(double);
   const void* fn = (const void*)k_jacobi_eig<RPT>;
   int dev = 0;
@@ -395,8 +397,9 @@ hipError_t eig_launch(double* X, double* J, int n, const Geom& G, int inner, dou
   if (e != hipSuccess) return e;
   double* Mpart = scratch;
   double* fro_part = scratch + (size_t)2 * G.nwg * kW * kW;
-  int nn = n, nbp = G.nbp, P = G.P, inn = inner;
-  void* args[] = {&X, &J, &nn, &nbp, &P, &inn, &Mpart, &fro_part, &lam, &diag, &flags, &status};
+  int nn = n, nbp = G.nbp, P = G.P, inn = inner, sv = svd;
+  void* args[] = {&X,    &J,   &nn,   &nbp,    &P,      &inn, &Mpart,
+                  &fro_part, &lam, &diag, &flags, &status, &sv};
   if (ev0) (void)hipEventRecord(ev0, s);
   e = hipLaunchCooperativeKernel(fn, dim3(G.nwg), dim3(kThreads), args, shmem, s);
   if (ev1) (void)hipEventRecord(ev1, s);
@@ -407,17 +410,17 @@ hipError_t eig_launch(double* X, double* J, int n, const Geom& G, int inner, dou
 
 hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
                              int32_t* flags, double* scratch, int32_t* status, hipStream_t s,
-                             int inner_sweeps, hipEvent_t ev0, hipEvent_t ev1) {
+                             int inner_sweeps, hipEvent_t ev0, hipEvent_t ev1, int svd) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   const Geom G = geom((int)n);
   const int inner = inner_sweeps < 0 ? kDefaultInner : (inner_sweeps < 1 ? 1 : inner_sweeps);
   switch (G.rpt) {
     case 2: return eig_launch<2>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
-                                     ev0, ev1);
+                                     ev0, ev1, svd);
     case 4: return eig_launch<4>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
-                                     ev0, ev1);
+                                     ev0, ev1, svd);
     default: return eig_launch<8>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
-                                     ev0, ev1);
+                                     ev0, ev1, svd);
   }
 }
 

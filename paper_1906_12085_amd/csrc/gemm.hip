@@ -1555,7 +1555,10 @@ hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P,
     case 4: return gram_dispatch<T, 4>(Y, m, c, ldy, P, max_split, nsplit, s);
     case 5: return gram_dispatch<T, 5>(Y, m, c, ldy, P, max_split, nsplit, s);
     case 6: return gram_dispatch<T, 6>(Y, m, c, ldy, P, max_split, nsplit, s);
-    default: return hipErrorInvalidValue;   // c <= 96 (the plan's l limit)
+    default:
+      // wider panels: the general split-m product Y^T Y on the FP64 matrix
+      // cores (exact products of fp32 data, the same c x c partial layout)
+      return launch_gemm_tn_partial<T, double>(Y, m, c, ldy, Y, ldy, c, P, max_split, nsplit, s);
   }
 }
 

@@ -393,29 +393,46 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
 
 // ---------------------------------------------------------------------------
 // Z partials (FP64, one n x c slab per row split) of Aq^T Q: block = one row
-// split x 512 columns of A (column tile blockIdx.y), 8 waves of 64 columns
-// (4 x NT tiles of 16 x 16).  Chunks of 32 rows (one 32-deep matrix-core
-// step): lane l = 16 g + 8 h + o loads row 8 g + o of the chunk, columns
-// 16 i + 8 h .. +7 of its wave's tiles, and the octet transpose turns that
-// into the operand the matrix core takes (column 8 h + o = l % 16, rows
-// 8 g .. 8 g + 7).  Q's chunk is split into hi + lo bfloat16 and transposed
-// the same way by waves 0..NT-1 (one column tile each) into LDS, where every
-// wave reads it.  Rows past the split read zeros (buffer range); columns of A
-// past n and of Q past c only reach outputs that are not stored.  Requires
-// 16-byte rows of A and Q (lda % 8 == 0, ldq % 8 == 0), n % 8 == 0, and
-// round_up(c, 8) readable columns in every row of Q (ldq >= that).
-constexpr int kTA = 512, kTR = 32;
+// split x 512 / QS columns of A, 8 waves; wave w takes the 64 A columns of
+// group w % (8 / QS) (4 x NTW tiles of 16 x 16, NTW = ceil(NT / QS)) against
+// the Q column tiles [NTW (w / (8 / QS)), +NTW).  QS = 2 for NT > 8: two
+// waves then share each 64-column group of A and split Q's tiles, so a
+// wave's accumulators stay within two waves per SIMD.  Chunks of 32 rows
+// (one 32-deep matrix-core step): lane l = 16 g + 8 h + o loads row 8 g + o
+// of the chunk, columns 16 i + 8 h .. +7 of its wave's group, and the octet
+// transpose turns that into the operand the matrix core takes (column
+// 8 h + o = l % 16, rows 8 g .. 8 g + 7).  Q's chunk is split into hi + lo
+// bfloat16 and transposed the same way (tile j by wave j mod 8) into LDS,
+// where every wave reads it.  Rows past the split read zeros (buffer range);
+// columns of A past n and of Q past c only reach outputs that are not
+// stored.  Block order: workgroup b runs on XCD b mod 8, and the column
+// tiles of one row split are given consecutive workgroups of one XCD, so
+// the Q rows that every tile of the split reads come from that XCD's L2
+// after the first.  Requires 16-byte rows of A and Q (lda % 8 == 0,
+// ldq % 8 == 0), n % 8 == 0, and round_up(c, 8) readable columns in every
+// row of Q (ldq >= that).
+constexpr int kTR = 32;
+template <int NT> constexpr int tn_bf16_qs() { return NT > 8 ? 2 : 1; }
 
-template <int NT, int ES>
+template <int NT, int ES, int QS>
 __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     const unsigned char* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
-    int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split) {
+    int64_t ldq, int c, double* __restrict__ P, int64_t rows_per_split, int nsplit, int ntile) {
+  constexpr int GW = 8 / QS;                  // 64-column groups of A per block
+  constexpr int TA = 64 * GW;                 // A columns per block
+  constexpr int NTW = (NT + QS - 1) / QS;     // Q tiles per wave
+  constexpr int QPW = (NT + 7) / 8;           // Q tiles staged per wave
   __shared__ __attribute__((aligned(16))) u32x4 Bq[2][NT][2][64];   // [buf][j][hi/lo][lane]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int o = lane & 7, h = (lane >> 3) & 1, g = lane >> 4;
-  const int64_t rs = (int64_t)blockIdx.x * rows_per_split;
+  const int xcd = blockIdx.x & 7, rr = blockIdx.x >> 3;
+  const int tile = rr % ntile;
+  const int64_t split = (int64_t)(rr / ntile) * 8 + xcd;
+  if (split >= nsplit) return;                // padding of the XCD order (whole block)
+  const int ag = wave % GW, j0 = (wave / GW) * NTW;
+  const int64_t rs = split * rows_per_split;
   const int64_t re = rs + rows_per_split < m ? rs + rows_per_split : m;
-  const int64_t col0 = (int64_t)blockIdx.y * kTA + wave * 64;
+  const int64_t col0 = (int64_t)tile * TA + ag * 64;
   const int nchunk = (int)((re - rs + kTR - 1) / kTR);
   const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<unsigned char*>(A + rs * lda * ES), 0, (int)(((re - rs - 1) * lda + n) * ES),
@@ -433,44 +450,58 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     if (cc > n - 8) cc = n - 8;
     voa[i] = (int)(((int64_t)(8 * g + o) * lda + cc) * ES);
   }
-  // Q (waves 0..NT-1): row 8 g + o, columns 16 wave + 8 h .. +7, clamped to
-  // the readable width (the columns past c only reach dropped outputs)
-  const int qc = 16 * wave + 8 * h < cpad - 8 ? 16 * wave + 8 * h : cpad - 8;
-  const int voq = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
-  const bool qwave = wave < NT;
+  // Q tile wave + 8 t (t < QPW, below NT): row 8 g + o, columns 16 j + 8 h
+  // .. +7, clamped to the readable width (the columns past c only reach
+  // dropped outputs)
+  int voq[QPW];
+  bool qon[QPW];
+#pragma unroll
+  for (int t = 0; t < QPW; ++t) {
+    const int jq = wave + 8 * t;
+    qon[t] = jq < NT;
+    const int qc = 16 * jq + 8 * h < cpad - 8 ? 16 * jq + 8 * h : cpad - 8;
+    voq[t] = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
+  }
   // two register sets, chunk ch in set ch & 1, loaded two chunks ahead
   typedef typename Frag<ES>::raw raw_t;
   raw_t ra[2][4];
-  f32x4 rq[2][2];
-  auto load = [&](int ch, raw_t (&da)[4], f32x4 (&dq)[2]) {
+  f32x4 rq[2][QPW][2];
+  auto load = [&](int ch, raw_t (&da)[4], f32x4 (&dq)[QPW][2]) {
     const int soa = ch * kTR * (int)lda * ES;
 #pragma unroll
     for (int i = 0; i < 4; ++i) da[i] = Frag<ES>::load(ar, voa[i], soa);
-    if (qwave) {
-      const int soq = ch * kTR * (int)ldq * 4;
-      dq[0] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, soq, 0));
-      dq[1] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq + 16, soq, 0));
-    }
-  };
-  auto store_q = [&](int buf, const f32x4 (&q)[2]) {
-    if (!qwave) return;
-    bf16x8 hi, lo;
+    const int soq = ch * kTR * (int)ldq * 4;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      __bf16 a, b;
-      split_hilo(q[0][e], &a, &b);
-      hi[e] = a; lo[e] = b;
-      split_hilo(q[1][e], &a, &b);
-      hi[4 + e] = a; lo[4 + e] = b;
+    for (int t = 0; t < QPW; ++t) {
+      if (qon[t]) {
+        dq[t][0] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq[t], soq, 0));
+        dq[t][1] =
+            __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq[t] + 16, soq, 0));
+      }
     }
-    Bq[buf][wave][0][lane] = octet_transpose(as_u32x4(hi), o);
-    Bq[buf][wave][1][lane] = octet_transpose(as_u32x4(lo), o);
   };
-  f32x4 acc[4][NT];
+  auto store_q = [&](int buf, const f32x4 (&q)[QPW][2]) {
+#pragma unroll
+    for (int t = 0; t < QPW; ++t) {
+      if (!qon[t]) continue;
+      bf16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        __bf16 a, b;
+        split_hilo(q[t][0][e], &a, &b);
+        hi[e] = a; lo[e] = b;
+        split_hilo(q[t][1][e], &a, &b);
+        hi[4 + e] = a; lo[4 + e] = b;
+      }
+      Bq[buf][wave + 8 * t][0][lane] = octet_transpose(as_u32x4(hi), o);
+      Bq[buf][wave + 8 * t][1][lane] = octet_transpose(as_u32x4(lo), o);
+    }
+  };
+  f32x4 acc[4][NTW];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NTW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   load(0, ra[0], rq[0]);
   load(1 < nchunk ? 1 : 0, ra[1], rq[1]);
   store_q(0, rq[0]);
@@ -488,13 +519,15 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     load(ch2, ra[set], rq[set]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
+    for (int jj = 0; jj < NTW; ++jj) {
+      const int j = j0 + jj;
+      if (NT % QS != 0 && j >= NT) continue;  // uniform per wave
       const bf16x8 bh = as_bf16x8(Bq[set][j][0][lane]);
       const bf16x8 bl = as_bf16x8(Bq[set][j][1][lane]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh, acc[i][j]);
-        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl, acc[i][j]);
+        acc[i][jj] = mfma_bf16(as_bf16x8(a[i]), bh, acc[i][jj]);
+        acc[i][jj] = mfma_bf16(as_bf16x8(a[i]), bl, acc[i][jj]);
       }
     }
     if (ch + 1 < nchunk) store_q(nxt, rq[nxt]);
@@ -504,17 +537,17 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     chunk(ch, std::integral_constant<int, 0>());
     if (ch + 1 < nchunk) chunk(ch + 1, std::integral_constant<int, 1>());
   }
-  // acc[i][j][e]: A column col0 + 16 i + 4 g + e, Q column 16 j + (lane % 16)
-  double* Pb = P + (int64_t)blockIdx.x * n * c;
+  // acc[i][jj][e]: A column col0 + 16 i + 4 g + e, Q column 16 (j0 + jj) + (lane % 16)
+  double* Pb = P + split * n * c;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int qcol = 16 * j + (lane & 15);
+    for (int jj = 0; jj < NTW; ++jj) {
+      const int qcol = 16 * (j0 + jj) + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t acol = col0 + 16 * i + 4 * g + e;
-        if (acol < n && qcol < c) Pb[acol * c + qcol] = (double)acc[i][j][e];
+        if (acol < n && qcol < c) Pb[acol * c + qcol] = (double)acc[i][jj][e];
       }
     }
 }
@@ -551,7 +584,7 @@ hipError_t launch_scale_rows(double* Z, int64_t n, int c, const float* scale, hi
 }
 
 bool bf16_pass_applies(const void* A, int es, int64_t n, int64_t lda, int c) {
-  return (es == 1 || es == 2) && c >= 1 && c <= 128 && n % 8 == 0 && lda % 8 == 0 &&
+  return (es == 1 || es == 2) && c >= 1 && c <= 192 && n % 8 == 0 && lda % 8 == 0 &&
          (reinterpret_cast<uintptr_t>(A) % (8 * es)) == 0 && (int64_t)512 * lda * es < (1LL << 31);
 }
 
@@ -572,6 +605,7 @@ hipError_t nt_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const __bf1
   switch ((c + 15) / 16) {
     RSVD_NT_BF16(1) RSVD_NT_BF16(2) RSVD_NT_BF16(3) RSVD_NT_BF16(4)
     RSVD_NT_BF16(5) RSVD_NT_BF16(6) RSVD_NT_BF16(7) RSVD_NT_BF16(8)
+    RSVD_NT_BF16(9) RSVD_NT_BF16(10) RSVD_NT_BF16(11) RSVD_NT_BF16(12)
     default: return hipErrorInvalidValue;
   }
 #undef RSVD_NT_BF16
@@ -594,17 +628,19 @@ hipError_t launch_gemm_nt_bf16(const void* A, int es, int64_t m, int64_t n, int6
 
 template <int ES>
 hipError_t tn_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const float* Q, int64_t ldq,
-                   int c, double* P, int64_t rps, dim3 grid, hipStream_t s) {
+                   int c, double* P, int64_t rps, int ns, int ntile, hipStream_t s) {
   const unsigned char* Ab = static_cast<const unsigned char*>(A);
-  const dim3 block(512);
+  const int nsp = (ns + 7) / 8 * 8;           // splits padded to the 8 XCDs
+  const dim3 grid((unsigned)(nsp * ntile)), block(512);
 #define RSVD_TN_BF16(NT)                                                                        \
   case NT:                                                                                      \
-    hipLaunchKernelGGL((k_gemm_tn_bf16<NT, ES>), grid, block, 0, s, Ab, m, n, lda, Q, ldq, c,   \
-                       P, rps);                                                                 \
+    hipLaunchKernelGGL((k_gemm_tn_bf16<NT, ES, tn_bf16_qs<NT>()>), grid, block, 0, s, Ab, m, n, \
+                       lda, Q, ldq, c, P, rps, ns, ntile);                                      \
     break;
   switch ((c + 15) / 16) {
     RSVD_TN_BF16(1) RSVD_TN_BF16(2) RSVD_TN_BF16(3) RSVD_TN_BF16(4)
     RSVD_TN_BF16(5) RSVD_TN_BF16(6) RSVD_TN_BF16(7) RSVD_TN_BF16(8)
+    RSVD_TN_BF16(9) RSVD_TN_BF16(10) RSVD_TN_BF16(11) RSVD_TN_BF16(12)
     default: return hipErrorInvalidValue;
   }
 #undef RSVD_TN_BF16
@@ -617,7 +653,8 @@ hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int6
   if (!bf16_pass_applies(A, es, n, lda, c) || ldq % 8 != 0 || ldq < ((c + 7) & ~7) ||
       (reinterpret_cast<uintptr_t>(Q) % 16) != 0 || m <= 0)
     return hipErrorInvalidValue;
-  const int ntile = (int)((n + kTA - 1) / kTA);
+  const int ta = (c + 15) / 16 > 8 ? 256 : 512;   // A columns per block (QS = 2 / 1)
+  const int ntile = (int)((n + ta - 1) / ta);
   int64_t ns = 256 / ntile;
   if (ns < 1) ns = 1;
   if (ns > (m + kTR - 1) / kTR) ns = (m + kTR - 1) / kTR;
@@ -628,9 +665,8 @@ hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int6
   const int64_t ld = lda * es > ldq * 4 ? lda * es : ldq * 4;
   if ((rps + kTR) * ld >= (1LL << 31)) return hipErrorInvalidValue;
   *nsplit = (int)ns;
-  const dim3 grid((unsigned)ns, (unsigned)ntile);
-  return es == 1 ? tn_lowp<1>(A, m, n, lda, Q, ldq, c, P, rps, grid, s)
-                 : tn_lowp<2>(A, m, n, lda, Q, ldq, c, P, rps, grid, s);
+  return es == 1 ? tn_lowp<1>(A, m, n, lda, Q, ldq, c, P, rps, (int)ns, ntile, s)
+                 : tn_lowp<2>(A, m, n, lda, Q, ldq, c, P, rps, (int)ns, ntile, s);
 }
 
 hipError_t launch_quantize_fp8(const float* A, int64_t m, int64_t n, int64_t lda, void* Aq,

@@ -20,9 +20,13 @@ using namespace rsvd;
 
 namespace {
 
-// Largest sketch width l supported: the l x l Cholesky / inverse and the
-// one-sided Jacobi SVD keep two l x l FP64 matrices in one block's LDS.
-constexpr int kMaxL = 96;
+// Largest sketch width l supported: the l x l Cholesky factor and its
+// inverse share one workgroup's registers (192 columns at most).  Up to
+// kSmallSvdMaxC columns the small SVD runs in one workgroup's LDS; wider
+// factors go to the cooperative block-Jacobi solver, which is kept out of
+// grouped batches and of captured batch graphs (both take l <= kSmallSvdMaxC).
+constexpr int kMaxL = 192;
+constexpr int kSmallSvdMaxC = 96;
 constexpr int kDiagWords = 8;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -69,6 +73,7 @@ struct rsvd_plan_s {
   double *Rt = nullptr, *Uo = nullptr, *Jm = nullptr, *Su = nullptr, *Vt = nullptr;
   double *Wk = nullptr, *Mk = nullptr;
   void* MkT = nullptr;       // l x l (T)
+  double* EsS = nullptr;     // block-Jacobi scratch of the small SVD (l > kSmallSvdMaxC)
   int32_t* status = nullptr;
   double* diag = nullptr;
   int32_t* flags = nullptr;
@@ -168,6 +173,7 @@ size_t carve(rsvd_plan_s* p, char* base) {
   p->Wk = (double*)take(l * l * 8);
   p->Mk = (double*)take(l * l * 8);
   p->MkT = take(l * l * es);
+  if (l > kSmallSvdMaxC) p->EsS = (double*)take(jacobi_eig_scratch_doubles(l) * 8);
   p->status = (int32_t*)take(64);
   p->diag = (double*)take(kDiagWords * 8);
   p->flags = (int32_t*)take(jacobi_eig_flag_words() * 4);
@@ -199,6 +205,27 @@ __global__ void k_trace(const double* G, int64_t n, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// J = I (c x c).
+__global__ void k_eye(double* J, int c) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  J[idx] = (idx / c == idx % c) ? 1.0 : 0.0;
+}
+
+// From the block-Jacobi SVD of N (c x c; X = N J with orthogonal columns,
+// column j at X + j c, and J column-major likewise): Uo (row-major) = the
+// columns of X over S_j (a zero column where S_j = 0), Jm = J row-major.
+__global__ void k_svd_finish(const double* __restrict__ X, const double* __restrict__ J,
+                             const double* __restrict__ S, int c, double* __restrict__ Uo,
+                             double* __restrict__ Jm) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx / c, j = idx - i * c;
+  const double s = S[j];
+  Uo[idx] = s > 0.0 ? X[j * c + i] / s : 0.0;
+  Jm[idx] = J[j * c + i];
 }
 
 // X = G (a symmetric matrix is its own column-major copy), J = I.
@@ -350,6 +377,21 @@ hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c
   if ((e = cqr2_small(p, Tm, r, c, p->Zq)) != hipSuccess) return e;
   if ((e = launch_small_gemm<double>(p->R2s, p->R1s, c, c, c, p->Rt, nullptr, p->stream)) != hipSuccess)
     return e;
+  if (c > kSmallSvdMaxC) {
+    // the same one-sided Jacobi on R^T, as blocks of columns shared out over
+    // workgroups (the column j of R^T is row j of Rt, so Rt is R^T stored
+    // column by column); J accumulated, every column exact
+    const unsigned nb = (unsigned)((c * c + 255) / 256);
+    hipLaunchKernelGGL(k_eye, dim3(nb), dim3(256), 0, p->stream, p->Mk, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_jacobi_eig(p->Rt, p->Mk, c, p->Su, p->diag, p->flags, p->EsS, p->status,
+                               p->stream, -1, nullptr, nullptr, 1)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_svd_finish, dim3(nb), dim3(256), 0, p->stream, p->Rt, p->Mk, p->Su, c,
+                       p->Uo, p->Jm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_small_gemm<double>(p->Zq, p->Jm, r, c, c, p->Vt, nullptr, p->stream);
+  }
   if (all_columns) {
     if ((e = launch_jacobi_svd_small(p->Rt, c, 1, p->Uo, p->Su, p->Jm, 1, p->diag, p->status,
                                      nullptr, p->stream)) != hipSuccess)
@@ -1200,6 +1242,11 @@ int32_t rsvd_batch_graph_create(rsvd_batch_t batch, const rsvd_instance* inst, i
     std::vector<int> order, slot;
     const int32_t rc = batch_schedule(batch, inst, count, order, slot);
     if (rc != RSVD_OK) return rc;
+    // sketches past kSmallSvdMaxC columns take a cooperative launch, which
+    // is not put into a graph
+    for (int i = 0; i < count; ++i)
+      if (inst[i].k + (int64_t)inst[i].p > kSmallSvdMaxC && inst[i].n > kSmallSvdMaxC)
+        return RSVD_ERR_SHAPE;
   }
   if (hipStreamBeginCapture(batch->cap, hipStreamCaptureModeRelaxed) != hipSuccess)
     return RSVD_ERR_DEVICE;
@@ -1471,6 +1518,7 @@ int blocks256(int64_t total) { return (int)((total + 255) / 256); }
 // layout conditions for A, and a sketch width that is a multiple of 4.
 bool grouped_applies(const rsvd_instance& x, int64_t max_split) {
   const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+  if (l > kSmallSvdMaxC) return false;       // the grouped small kernels hold l <= 96
   if (l % 4 != 0 || x.n % 4 != 0 || x.lda % 4 != 0) return false;
   if (reinterpret_cast<uintptr_t>(x.A) % 16 != 0) return false;
   if ((int64_t)128 * x.lda * 4 >= (1LL << 31)) return false;

@@ -95,7 +95,8 @@ hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda,
                                   hipStream_t s);
 
 // Symmetric partial Gram matrices P[s] (c x c, FP64) of a tall m x c panel Y,
-// accumulated in FP64 from exact products (c <= 96).
+// accumulated in FP64 from exact products (upper tile pairs for c <= 96, the
+// general split-m product above that).
 template <typename T>
 hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
                            int* nsplit, hipStream_t s);
@@ -124,14 +125,16 @@ template <typename T>
 hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t lds,
                               double* dst, int64_t ldd, hipStream_t s);
 
-// Cholesky of the symmetric c x c matrix W (ld = c): R upper with W = R^T R,
-// Rinv = R^-1 (upper), both ld = c.  Rinv also written, rounded, to RinvT
+// Cholesky of the symmetric c x c matrix W (ld = c, c <= chol_inv_max_c()):
+// R upper with W = R^T R, Rinv = R^-1 (upper), both ld = c.  Rinv also written, rounded, to RinvT
 // (type T, ld = c) when RinvT != nullptr, transposed when trans != 0.
 // Non-positive pivot -> status word = RSVD_ERR_BREAKDOWN, R = 0 and
 // Rinv = identity (so later kernels stay finite).
 template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
                            int32_t* status, hipStream_t s, int trans = 0);
+// Largest c launch_chol_inv takes (the grouped launcher: at most 96).
+int chol_inv_max_c();
 
 // C (r x c2) = A (r x c1) B (c1 x c2), FP64, all ld = their column counts.
 // Optional rounded copy CT (type T): C itself (ld = c2), or C^T (ld = r)
@@ -162,10 +165,14 @@ hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double
 // int32 words and `scratch` jacobi_eig_scratch_doubles(n) doubles; sweeps
 // used go to diag[2].  inner_sweeps < 0 selects the default; ev0/ev1, when
 // given, are recorded around the solver kernel itself.
+// svd != 0: the same iteration as a one-sided Jacobi SVD of any square X
+// (X J = Uo diag(lam) with lam_j = ||x_j||, unsigned): pairs are rotated on
+// the cosine test alone (no absolute floor, so small singular values keep
+// their relative accuracy).
 hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, double* diag,
                              int32_t* flags, double* scratch, int32_t* status, hipStream_t s,
                              int inner_sweeps = -1, hipEvent_t ev0 = nullptr,
-                             hipEvent_t ev1 = nullptr);
+                             hipEvent_t ev1 = nullptr, int svd = 0);
 // Doubles of scratch launch_jacobi_eig needs for matrices up to n.
 int64_t jacobi_eig_scratch_doubles(int64_t n);
 
@@ -214,7 +221,7 @@ hipError_t launch_quantize_fp8(const float* A, int64_t m, int64_t n, int64_t lda
                                int64_t ldq, float* scale, unsigned* cmax, hipStream_t s);
 // Whether the low-precision passes take A of es bytes per element (2:
 // bfloat16, 1: FP8 E4M3): n % 8 == 0, lda % 8 == 0, rows aligned to 8 es
-// bytes, c <= 128.
+// bytes, c <= 192.
 bool bf16_pass_applies(const void* A, int es, int64_t n, int64_t lda, int c);
 // Y (m x c, fp32) = Aq (Xhi + Xlo)^T on the bf16 matrix cores (FP8 widened to
 // bf16 in registers); per-block FP64 sums of the squared dequantised entries

@@ -214,6 +214,130 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same factorisation for 96 < c <= 192, one workgroup of 1024 threads.
+// W and B cannot both sit in registers at this width, but they never
+// overlap: the symmetric elimination only ever needs W on and right of the
+// diagonal (its trailing part is kept as an upper triangle), and row i of
+// B = L^-1 has nonzeros only in columns k <= i.  So one c x c array P holds
+// W (then R) in k >= i and B in k < i; B's diagonal, 1/sqrt(d_i), is kept
+// apart in LDS.  Thread (ti, tk) = (tid / 32, tid % 32) keeps the elements
+// (ti + 32u, tk + 32v), u, v < U; the 32 owners of a row are one half of a
+// wave.  Step j: the owners of row j take d = p_jj, scale the row by
+// r = 1/sqrt(d) (R right of the diagonal, B left of it), set p_jj = sqrt(d)
+// and publish x = the row with r in the diagonal slot; every row i > j then
+// subtracts r_ji x_k from its columns k >= i (the trailing triangle of W)
+// and k <= j (its row of B), and leaves j < k < i at zero.  One barrier per
+// step (the published rows alternate between two LDS buffers).
+constexpr int kCwT = 1024;
+constexpr int kCwMax = 192;                   // 32 * 6
+
+template <int U, int JU>
+__device__ __forceinline__ void chol_wide_block(double (&a)[U][U], int c, int ti, int tk, int lane,
+                                                int wv, double (*xrow)[kCwMax], double* rdiag,
+                                                int* bad) {
+  for (int jj = 0; jj < 32; ++jj) {
+    const int j = 32 * JU + jj;
+    if (j >= c) return;
+    const int p = j & 1;
+    if (ti == jj) {
+      const double d = __shfl(a[JU][JU], (lane & 32) + jj);
+      if (!(d > 0.0)) *bad = 1;
+      const double r = rsq_newton(d);
+      const double sd = d * r;
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const int k = tk + 32 * v;
+        const double nv = (k == j) ? sd : a[JU][v] * r;
+        if (k < c) a[JU][v] = nv;
+        xrow[p][k] = (k < c) ? ((k == j) ? r : nv) : 0.0;
+      }
+      if (tk == 0) rdiag[j] = r;
+    }
+    __syncthreads();
+    double xv[U];
+#pragma unroll
+    for (int v = 0; v < U; ++v) xv[v] = xrow[p][tk + 32 * v];
+#pragma unroll
+    for (int u = JU; u < U; ++u) {
+      if (32 * u + 2 * wv + 1 <= j) continue;   // no row of this wave is below j
+      const int i = ti + 32 * u;
+      const double rji = (i > j && i < c) ? xrow[p][i] : 0.0;
+#pragma unroll
+      for (int v = 0; v < U; ++v) {
+        const int k = tk + 32 * v;
+        const double coef = (k >= i || k <= j) ? xv[v] : 0.0;
+        a[u][v] = fma(-rji, coef, a[u][v]);
+      }
+    }
+  }
+}
+
+template <int U, int JU>
+__device__ __forceinline__ void chol_wide_all(double (&a)[U][U], int c, int ti, int tk, int lane,
+                                              int wv, double (*xrow)[kCwMax], double* rdiag,
+                                              int* bad) {
+  if constexpr (JU < U) {
+    chol_wide_block<U, JU>(a, c, ti, tk, lane, wv, xrow, rdiag, bad);
+    chol_wide_all<U, JU + 1>(a, c, ti, tk, lane, wv, xrow, rdiag, bad);
+  }
+}
+
+template <typename T, int U>
+__global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict__ W, int c,
+                                                        double* __restrict__ R,
+                                                        double* __restrict__ Rinv,
+                                                        T* __restrict__ RinvT, int trans,
+                                                        int32_t* __restrict__ status,
+                                                        const GArgChol* __restrict__ grp) {
+  if (grp) {
+    const GArgChol& a = grp[blockIdx.y];
+    W = a.W; c = a.c; R = a.R; Rinv = a.Rinv; RinvT = (T*)a.RinvT; trans = a.trans;
+    status = a.status;
+  }
+  __shared__ double xrow[2][kCwMax];
+  __shared__ double rdiag[kCwMax];
+  __shared__ int bad;
+  const int tid = threadIdx.x, ti = tid >> 5, tk = tid & 31, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double a[U][U];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int v = 0; v < U; ++v) {
+      const int i = ti + 32 * u, k = tk + 32 * v;
+      a[u][v] = (i < c && k < c && k >= i) ? 0.5 * (W[i * c + k] + W[k * c + i]) : 0.0;
+    }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  chol_wide_all<U, 0>(a, c, ti, tk, lane, wv, xrow, rdiag, &bad);
+  __syncthreads();
+  if (bad) {
+    for (int idx = tid; idx < c * c; idx += kCwT) {
+      const int i = idx / c, j = idx - i * c;
+      const double v = (i == j) ? 1.0 : 0.0;
+      R[idx] = 0.0;
+      Rinv[idx] = v;
+      if (RinvT) RinvT[idx] = (T)v;
+    }
+    if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
+    return;
+  }
+  // P(i, k): R for k >= i; (L^-1)_ik = (R^-1)_ki for k < i, 1/r_ii on the diagonal
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int v = 0; v < U; ++v) {
+      const int i = ti + 32 * u, k = tk + 32 * v;
+      if (i < c && k < c) {
+        R[i * c + k] = k >= i ? a[u][v] : 0.0;
+        const double x = k < i ? a[u][v] : (k == i ? rdiag[i] : 0.0);
+        Rinv[k * c + i] = x;
+        if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
+      }
+    }
+}
+
 template <typename T>
 __global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
                              int64_t r, int c1, int c2, double* __restrict__ C, T* __restrict__ CT,
@@ -614,11 +738,26 @@ hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t 
 template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
                            int32_t* status, hipStream_t s, int trans) {
-  if (c < 1 || c > 16 * kCiU) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), 0, s, W, c, R, Rinv, RinvT, trans,
-                     status, nullptr);
+  if (c < 1 || c > kCwMax) return hipErrorInvalidValue;
+  if (c <= 16 * kCiU) {
+    hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), 0, s, W, c, R, Rinv, RinvT, trans,
+                       status, nullptr);
+    return hipGetLastError();
+  }
+#define RSVD_CHOL_WIDE(U)                                                                        \
+  case U:                                                                                        \
+    hipLaunchKernelGGL((k_chol_inv_wide<T, U>), dim3(1), dim3(kCwT), 0, s, W, c, R, Rinv, RinvT, \
+                       trans, status, nullptr);                                                  \
+    break;
+  switch ((c + 31) / 32) {
+    RSVD_CHOL_WIDE(4) RSVD_CHOL_WIDE(5) RSVD_CHOL_WIDE(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef RSVD_CHOL_WIDE
   return hipGetLastError();
 }
+
+int chol_inv_max_c() { return kCwMax; }
 
 template <typename T>
 hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1, int c2, double* C,

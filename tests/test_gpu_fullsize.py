@@ -150,14 +150,13 @@ def test_fullsize_gram_route_vs_oracle(workload):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 def test_config3_shape_lowp_vs_oracle(fmt):
-    # the mixed-precision workload's matrix (262144 x 1024, sigma_i = 1/sqrt(i)
-    # plus N(0, 1e-4) noise, columns centred) stored in bfloat16 / FP8 E4M3
-    # with power-of-two column scales, q = 3, at the widest sketch the
-    # library holds: k = 64, p = 32 (l = 96; the workload's k = 128, p = 32
-    # would need l = 160).  Oracle on the dequantised stored matrix, same G.
+    # the mixed-precision workload as stated: 262144 x 1024, sigma_i =
+    # 1/sqrt(i) plus N(0, 1e-4) noise, columns centred, stored in bfloat16 /
+    # FP8 E4M3 with power-of-two column scales, k = 128, p = 32 (l = 160),
+    # q = 3.  Oracle on the dequantised stored matrix, same G.
     c = synth.CONFIG3
     m, n, q, t = c["m"], c["n"], c["q"], c["t"]
-    k, p = 64, 32
+    k, p = c["k"], c["p"]
     l = k + p
     announce(f"config-3 shape: generating A {m}x{n}, {fmt} storage, k={k} p={p} q={q}")
     A = synth.spiked_noisy_torch(c["seed"], m, n, synth.config3_sigma(n), c["noise_std"],

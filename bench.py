@@ -8,8 +8,9 @@ solve's dominant kernel from HIP events the library records around it on the
 plan's stream.  Legs: the whole hot path (the solve and the all-eigenpairs
 A^T A route on the same A, concurrently), the A^T A route alone, the FP64
 2000 x 200 latency case (eager and graph-replayed, kernels per solve), bf16
-and FP8 storage, the Krylov method, the 512-instance batch and the serving
-stream.  cpu_baseline: the FP64 oracle's Randomized PCA on the full matrix.
+and FP8 storage of the same A, the mixed-precision 262144 x 1024 workload
+(fp32, bf16 and FP8 storage at k=128, p=32, q=3), the Krylov method, the
+512-instance batch and the serving stream.  cpu_baseline: the FP64 oracle's Randomized PCA on the full matrix.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -31,8 +32,9 @@ METRIC = "rSVD solves/s + TFLOP/s (% roofline) at ≤1e-4 σ rel err; p50/p99 la
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
-# Krylov-method leg: k, p and the block count minus one (L = (i+1)(k+p) = 96)
-KRYLOV = (32, 16, 1)
+# Krylov-method leg: k, p and the block count minus one (the 1e6 x 512
+# workload's rank: L = (i+1)(k+p) = 160)
+KRYLOV = (64, 16, 1)
 # slots of the batched leg
 BATCH_SLOTS = 8
 
@@ -57,8 +59,10 @@ def parse():
                     help="skip the serving leg (Poisson arrivals, continuous batching)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven fp32 instances)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the 262144 x 1024 mixed-precision workload legs")
     ap.add_argument("--no-krylov", action="store_true",
-                    help="skip the Krylov-method leg (k=32, p=16, two blocks: L = 96)")
+                    help="skip the Krylov-method leg (k=64, p=16, two blocks: L = 160)")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the legs on bfloat16 and FP8 storage of the same A")
     return ap.parse_args()
@@ -209,7 +213,7 @@ def lowp_rooflines(ktimes, m, n, l, steps, es, tag):
     return rows
 
 
-def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt):
+def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt, plan64=None):
     """Randomized PCA of the same A stored in bfloat16 or FP8 E4M3 with
     power-of-two column scales (quantised outside the timed region), timed
     like the fp32 leg; accuracy against the FP64 path on the dequantised
@@ -241,11 +245,14 @@ def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt):
     status = rs.rsvd_plan_status(plan.handle)
     ms = [e[0].elapsed_time(e[1]) for e in evs]
     A64 = Aq.double() * sc.double()[None, :]
-    plan64 = rs.Plan(m, n, l, torch.float64, want_gram=False, seed=seed, stream=stream)
+    own64 = plan64 is None
+    if own64:
+        plan64 = rs.Plan(m, n, l, torch.float64, want_gram=False, seed=seed, stream=stream)
     r64 = plan64.solve(A64, k, p, q, t)
     sig_err = float(torch.max(torch.abs(S - r64.S) / r64.S).item())
     same_k = int(K.item()) == r64.K
-    plan64.close()
+    if own64:
+        plan64.close()
     plan.close()
     del A64, Aq
     torch.cuda.empty_cache()
@@ -258,7 +265,85 @@ def lowp_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream, fmt):
             "gbs_passes": round(nbytes / (med / 1e3) / 1e9, 1), "K": int(K.item()),
             "K_equals_fp64_path": same_k, "status": rs.STATUS.get(status, status),
             "sigma_rel_err_vs_fp64_path_on_stored_matrix": sig_err,
-            "kernels": lowp_rooflines(ktimes, m, n, l, steps, es, "_bf16" if es == 2 else "_fp8")}
+            "kernels": lowp_rooflines(ktimes, m, n, l, steps, es, "_bf16" if es == 2 else "_fp8"),
+            "_S": S.clone()}
+
+
+def solve_bytes(m, n, k, l, q, b_a, b_y=4):
+    """Algorithmic HBM bytes of one Randomized PCA solve: 2q + 2 passes over
+    A (each also moving an m x l panel), the (q + 1) CholeskyQR2 panel
+    traffic and the U product."""
+    return (2 * q + 2) * (m * n * b_a + m * l * b_y) + (q + 1) * 4 * m * l * b_y + (m * l + m * k) * b_y
+
+
+def mixed_precision_leg(rs, torch, dev, steps, warmup, stream):
+    """The mixed-precision workload: 262144 x 1024, sigma_i = 1/sqrt(i) plus
+    N(0, 1e-4) noise, centred, stored in bfloat16 and in FP8 E4M3 with
+    power-of-two column scales (and, for comparison, in fp32); Randomized
+    PCA with k = 128, p = 32 (l = 160), q = 3.  Each storage is timed like
+    the headline; accuracy against the FP64 path of the library on the
+    dequantised stored matrix (the gate of the tests) and, reported only,
+    on the fp32 matrix before quantisation."""
+    import synth
+    c = synth.CONFIG3
+    m, n, k, p, q, t = c["m"], c["n"], c["k"], c["p"], c["q"], c["t"]
+    l = k + p
+    A = synth.spiked_noisy_torch(c["seed"], m, n, synth.config3_sigma(n), c["noise_std"], dev,
+                                 torch.float32)
+    torch.cuda.synchronize()
+    out = {"workload": f"{m}x{n}, sigma_i=1/sqrt(i) + N(0,1e-4) noise, centred; k={k} p={p} "
+                       f"q={q} t={t}"}
+    # FP64 path on the fp32 matrix: the reference for the report-only error
+    A64 = A.double()
+    plan64 = rs.Plan(m, n, l, torch.float64, seed=c["omega_seed"], stream=stream)
+    r_orig = plan64.solve(A64, k, p, q, t)
+    del A64
+    torch.cuda.empty_cache()
+    for key, fmt, es in (("fp32", torch.float32, 4), ("bf16", torch.bfloat16, 2),
+                         ("fp8", torch.float8_e4m3fn, 1)):
+        if es == 4:
+            leg = fp32_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"], steps, warmup, stream)
+        else:
+            leg = lowp_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"], steps, warmup, stream,
+                           fmt, plan64=plan64)
+        nb = solve_bytes(m, n, k, l, q, es)
+        leg["hbm_bound_ms"] = round(nb / PEAK_HBM_GBS / 1e6, 3)
+        leg["frac_of_hbm_bound"] = round(leg["hbm_bound_ms"] / leg["p50_ms"], 4)
+        S = leg.pop("_S")
+        leg["sigma_rel_err_vs_fp64_path_on_fp32_matrix"] = float(
+            torch.max(torch.abs(S - r_orig.S) / r_orig.S).item())
+        leg["K_equals_fp64_path_on_fp32_matrix"] = leg["K"] == r_orig.K
+        out[key] = leg
+    plan64.close()
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
+def fp32_leg(rs, torch, A, m, n, k, p, q, t, seed, steps, warmup, stream):
+    """Randomized PCA of an fp32 matrix, timed like the headline (per-solve
+    events on the current stream)."""
+    l = k + p
+    dev = A.device
+    plan = rs.Plan(m, n, l, torch.float32, seed=seed, stream=stream)
+    U = torch.empty(m, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(n, k, dtype=torch.float32, device=dev)
+    K = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def solve():
+        rs.rsvd_solve(plan.handle, A, k, p, q, t, U, S, V, K)
+
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    ms, wall = timed_events(torch, stream, solve, steps)
+    status = rs.rsvd_plan_status(plan.handle)
+    plan.close()
+    med = pct(ms, 50)
+    return {"storage": "fp32", "p50_ms": round(med, 3), "p99_ms": round(pct(ms, 99), 3),
+            "solves_per_s": round(1000.0 / med, 2), "wall_solves_per_s": round(steps / wall, 2),
+            "K": int(K.item()), "status": rs.STATUS.get(status, status), "_S": S.clone()}
 
 
 def krylov_leg(rs, torch, A, m, n, k, p, i, t, seed, steps, warmup, stream):
@@ -836,6 +921,13 @@ def main():
             print(f"[bench] {key} storage leg: {args.steps} solves", file=sys.stderr, flush=True)
             legs[key] = lowp_leg(rs, torch, A, m, n, k, p, q, t, c["omega_seed"], args.steps,
                                  args.warmup, stream, fmt)
+            legs[key].pop("_S")
+
+    if not args.no_mixed:
+        print("[bench] mixed-precision workload 262144x1024 (fp32, bf16, fp8), k=128 p=32 q=3",
+              file=sys.stderr, flush=True)
+        legs["mixed_precision"] = mixed_precision_leg(rs, torch, dev, args.steps, args.warmup,
+                                                      stream)
 
     if not args.no_krylov:
         kk, kp, ki = KRYLOV

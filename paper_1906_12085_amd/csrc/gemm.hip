@@ -1267,6 +1267,145 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64(const T* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same FP64 Gram W = Y^T Y for panels wider than 96 columns (c <= 192):
+// the columns are cut into segments of kGsW 16-column tiles, and one block
+// computes the tile pairs of one segment pair (sa <= sb; the upper tile
+// pairs only when sa == sb) over one row split, so a wave keeps at most
+// kGsW^2 accumulator tiles.  The segment pairs of a row split are given to
+// consecutive workgroups of one XCD (workgroup b runs on XCD b mod 8), so
+// they read the split's rows of Y from that XCD's L2 after the first.
+// Rows, the wave split, the fixed-order LDS reduction and the exact FP64
+// products are those of k_gram_f64; each block writes its tiles of the
+// split's symmetric partial P[split] (c x c), mirrored below the diagonal
+// tiles.  Tiles past c (the last segment of a c that is not a multiple of
+// 64) are skipped.
+constexpr int kGsW = 4;
+
+template <typename T>
+__global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64_seg(const T* __restrict__ Y, int64_t m,
+                                                                int c, int64_t ldy,
+                                                                double* __restrict__ P,
+                                                                int64_t rows_per_block,
+                                                                int64_t nsplit, int nseg,
+                                                                int64_t per_xcd) {
+  typedef Mfma<double> M;
+  constexpr int U = 2;                       // 4-row groups per register set
+  constexpr int64_t STEP = (int64_t)4 * kGramWaves * U;
+  __shared__ double red[kGsW * kGsW][256];
+  const int npair = nseg * (nseg + 1) / 2;
+  const int64_t L = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= nsplit * npair) return;
+  const int64_t split = L / npair;
+  int sa = 0, rem = (int)(L - split * npair);
+  while (rem >= nseg - sa) { rem -= nseg - sa; ++sa; }
+  const int sb = sa + rem;
+  const bool sym = sa == sb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t rs = split * rows_per_block;
+  const int64_t re = (rs + rows_per_block < m) ? rs + rows_per_block : m;
+  const int ca = 16 * kGsW * sa, cb = 16 * kGsW * sb;
+  f64x4 acc[kGsW][kGsW];
+#pragma unroll
+  for (int I = 0; I < kGsW; ++I)
+#pragma unroll
+    for (int J = 0; J < kGsW; ++J) acc[I][J] = f64x4{0, 0, 0, 0};
+  bool oka[kGsW], okb[kGsW];
+#pragma unroll
+  for (int J = 0; J < kGsW; ++J) {
+    oka[J] = (ca + 16 * J + x) < c;
+    okb[J] = (cb + 16 * J + x) < c;
+  }
+  auto load = [&](int64_t r0, T(&ya)[U][kGsW], T(&yb)[U][kGsW]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = r0 + (int64_t)4 * kGramWaves * u + g;
+      const bool rok = row < re;
+#pragma unroll
+      for (int J = 0; J < kGsW; ++J) {
+        ya[u][J] = (rok && oka[J]) ? Y[row * ldy + ca + 16 * J + x] : T(0);
+        yb[u][J] = (rok && okb[J]) ? Y[row * ldy + cb + 16 * J + x] : T(0);
+      }
+    }
+  };
+  auto compute = [&](const T(&ya)[U][kGsW], const T(&yb)[U][kGsW]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double da[kGsW], db[kGsW];
+#pragma unroll
+      for (int J = 0; J < kGsW; ++J) {
+        da[J] = (double)ya[u][J];
+        db[J] = (double)yb[u][J];
+      }
+#pragma unroll
+      for (int I = 0; I < kGsW; ++I)
+#pragma unroll
+        for (int J = 0; J < kGsW; ++J)
+          if ((!sym || I <= J) && ca + 16 * I < c && cb + 16 * J < c)   // uniform per block
+            acc[I][J] = M::run(da[I], db[J], acc[I][J]);
+    }
+  };
+  T a0[U][kGsW], b0[U][kGsW], a1[U][kGsW], b1[U][kGsW];
+  int64_t r = rs + 4 * wave;
+  load(r, a0, b0);
+  while (r < re) {
+    const bool has1 = r + STEP < re;
+    if (has1) load(r + STEP, a1, b1);
+    compute(a0, b0);
+    if (!has1) break;
+    const bool has2 = r + 2 * STEP < re;
+    if (has2) load(r + 2 * STEP, a0, b0);
+    compute(a1, b1);
+    if (!has2) break;
+    r += 2 * STEP;
+  }
+  // fixed-order reduction of the waves' tiles in LDS
+  for (int w = 0; w < kGramWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int I = 0; I < kGsW; ++I)
+#pragma unroll
+        for (int J = 0; J < kGsW; ++J) {
+          if (sym && I > J) continue;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int t = M::row(lane, e) * 16 + x;
+            red[I * kGsW + J][t] = (w == 0) ? acc[I][J][e] : red[I * kGsW + J][t] + acc[I][J][e];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double* Pb = P + split * (int64_t)c * c;
+  for (int idx = threadIdx.x; idx < kGsW * kGsW * 256; idx += kGramWaves * 64) {
+    const int tp = idx >> 8, t = idx & 255;
+    const int I = tp / kGsW, J = tp - I * kGsW;
+    if (sym && I > J) continue;
+    const int i = ca + 16 * I + (t >> 4), j = cb + 16 * J + (t & 15);
+    if (i >= c || j >= c) continue;
+    const double v = red[tp][t];
+    Pb[(int64_t)i * c + j] = v;
+    if (!(sym && I == J)) Pb[(int64_t)j * c + i] = v;
+  }
+}
+
+template <typename T>
+hipError_t gram_seg_dispatch(const T* Y, int64_t m, int c, int64_t ldy, double* P,
+                             int64_t max_split, int* nsplit, hipStream_t s) {
+  const int nseg = (c + 16 * kGsW - 1) / (16 * kGsW);
+  const int npair = nseg * (nseg + 1) / 2;
+  // about two blocks per CU in all, splits of at least 1024 rows
+  int64_t rpb = 0;
+  const int64_t blocks = gram_blocks(m, max_split < 512 / npair ? max_split : 512 / npair, &rpb,
+                                     1024);
+  *nsplit = (int)blocks;
+  const int64_t per_xcd = (blocks * npair + 7) / 8;
+  hipLaunchKernelGGL((k_gram_f64_seg<T>), dim3((unsigned)(8 * per_xcd)), dim3(kGramWaves * 64), 0,
+                     s, Y, m, c, ldy, P, rpb, blocks, nseg, per_xcd);
+  return hipGetLastError();
+}
+
 template <typename T, int NT>
 hipError_t gram_dispatch(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
                          int* nsplit, hipStream_t s) {
@@ -1368,7 +1507,7 @@ hipError_t launch_gemm_nt_narrow(const float* A, int64_t m, int64_t n, int64_t l
 }
 
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c) {
-  return c >= 1 && c <= 128 && n % 4 == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
+  return c >= 1 && c <= 192 && n % 4 == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
          (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Xt) % 16) == 0 && (ldxt % 4) == 0 &&
          (int64_t)kTM * lda * 4 < (1LL << 31) && (int64_t)c * ldxt * 4 < (1LL << 31);
 }
@@ -1380,7 +1519,8 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
   const int64_t nblk = tall_blocks(m);
   if (nparts) *nparts = (int)nblk;
   if (m <= 0) return hipSuccess;
-  if (!fro2_part && n <= 16 * kNarrowSlabs) return launch_gemm_nt_narrow(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+  if (!fro2_part && n <= 16 * kNarrowSlabs && c <= 128)
+    return launch_gemm_nt_narrow(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
   const dim3 grid((unsigned)nblk), block(256);
 #define RSVD_NT_TALL(NT)                                                                      \
   case NT:                                                                                    \
@@ -1390,6 +1530,7 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
   switch ((c + 15) / 16) {
     RSVD_NT_TALL(1) RSVD_NT_TALL(2) RSVD_NT_TALL(3) RSVD_NT_TALL(4)
     RSVD_NT_TALL(5) RSVD_NT_TALL(6) RSVD_NT_TALL(7) RSVD_NT_TALL(8)
+    RSVD_NT_TALL(9) RSVD_NT_TALL(10) RSVD_NT_TALL(11) RSVD_NT_TALL(12)
     default: return hipErrorInvalidValue;
   }
 #undef RSVD_NT_TALL
@@ -1556,9 +1697,8 @@ hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P,
     case 5: return gram_dispatch<T, 5>(Y, m, c, ldy, P, max_split, nsplit, s);
     case 6: return gram_dispatch<T, 6>(Y, m, c, ldy, P, max_split, nsplit, s);
     default:
-      // wider panels: the general split-m product Y^T Y on the FP64 matrix
-      // cores (exact products of fp32 data, the same c x c partial layout)
-      return launch_gemm_tn_partial<T, double>(Y, m, c, ldy, Y, ldy, c, P, max_split, nsplit, s);
+      if (c > 16 * kGsW * 3) return hipErrorInvalidValue;   // c <= 192
+      return gram_seg_dispatch<T>(Y, m, c, ldy, P, max_split, nsplit, s);
   }
 }
 

@@ -64,7 +64,7 @@ hipError_t launch_gemm_nn(const T* A, int64_t m, int64_t n, int64_t lda, const T
 hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s);
 
-// Y (m x c) = A Xt^T for fp32 with c <= 128 (Xt is c x n), optional per-block
+// Y (m x c) = A Xt^T for fp32 with c <= 192 (Xt is c x n), optional per-block
 // FP64 partial sums of a_ij^2 (*nparts of them); requires nt_tall_applies.
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c);
 hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,

@@ -289,3 +289,49 @@ def test_sym_eig_parity(plans, n):
     assert np.abs(align_columns(Vg, Vo) - Vo).max() <= 100 * n * EPS64 / gap
     assert sign_rule_holds(Vg)
     assert np.abs(Vg.T @ Vg - np.eye(n)).max() <= 50 * n * EPS64
+
+
+def test_sym_eig_repeated_and_clustered():
+    # n = 512 (four row slices per block pair) with exactly repeated
+    # eigenvalues (multiplicities 6, 10, 15 and a zero of multiplicity 3), a
+    # cluster of 20 eigenvalues 1e-12 apart (relative), a separated leading
+    # one, and 457 distinct values.  Eigenvectors inside a cluster are
+    # determined only as a subspace, so the checks are: eigenvalues within
+    # c n eps lambda_1, the residual ||G V - V Lambda||_F within c n eps ||G||_F,
+    # orthonormal V, and for every cluster (split where the relative gap
+    # exceeds 1e-9) the largest principal angle against the construction's
+    # subspace within c n eps lambda_1 / delta (Davis-Kahan, delta = the
+    # cluster's distance to the rest of the spectrum).
+    n = 512
+    announce(f"sym_eig repeated/clustered n={n}")
+    lam = np.concatenate([[9.0], [7.0] * 6, 5.0 * (1.0 + 1e-12 * np.arange(20)), [3.0] * 10,
+                          [2.5] * 15, np.linspace(2.0, 0.1, n - 55), [0.0] * 3])
+    order = np.argsort(-lam, kind="stable")
+    lam = lam[order]
+    rng = np.random.default_rng(512)
+    Qh = synth.haar(rng, n, n)
+    G0 = (Qh * lam) @ Qh.T
+    G0 = 0.5 * (G0 + G0.T)
+    lg_t = torch.empty(n, dtype=torch.float64, device="cuda")
+    V_t = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    p = rs.Plan(n, n, 8, torch.float64, want_gram=True, seed=1)
+    try:
+        rs.rsvd_sym_eig(p.handle, dev(G0, torch.float64), lg_t, V_t)
+        assert p.status() == rs.RSVD_OK
+    finally:
+        p.close()
+    lg, Vg = host(lg_t), host(V_t)
+    tol = 50 * n * EPS64
+    assert np.all(np.diff(lg) <= 0)
+    assert np.abs(lg - lam).max() <= tol * lam[0]
+    assert np.linalg.norm(G0 @ Vg - Vg * lg) <= tol * np.linalg.norm(G0)
+    assert np.abs(Vg.T @ Vg - np.eye(n)).max() <= tol
+    assert sign_rule_holds(Vg)
+    cut = np.where(-np.diff(lam) > 1e-9 * lam[0])[0] + 1
+    groups = np.split(np.arange(n), cut)
+    assert max(len(g) for g in groups) == 20 and len(groups) == n - 19 - 5 - 9 - 14 - 2
+    for idx in groups:
+        rest = np.setdiff1d(np.arange(n), idx)
+        delta = np.min(np.abs(lam[idx][:, None] - lam[rest][None, :]))
+        ang = oracle.principal_angle_max(Qh[:, idx], Vg[:, idx])
+        assert ang <= 2 * tol * lam[0] / delta + 1e-14, (idx[0], len(idx), ang, delta)

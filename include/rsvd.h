@@ -94,6 +94,7 @@ const char* rsvd_status_string(int32_t status);
  * the eigensolver is resident).  Sketches wider than 96 columns take their
  * small SVD on the cooperative block-Jacobi solver (one cooperative launch
  * per solve).
+ * Also m_max <= 2^40 and n_max <= 2^20 (sizes stay within 64-bit arithmetic).
  * Errors: RSVD_ERR_ARG (plan NULL, bad dtype, l_max < 1), RSVD_ERR_SHAPE
  * (m_max < n_max, n_max < 1, or a limit above exceeded), RSVD_ERR_NOMEM,
  * RSVD_ERR_DEVICE. */
@@ -468,7 +469,7 @@ int32_t rsvd_server_destroy(rsvd_server_t server);
  * GPU (on different streams or threads) race and must not be issued; calls
  * ordered on one stream are safe.  Errors (synchronous, nothing launched):
  * RSVD_ERR_ARG (bad dtype, NULL A / status, the argument errors of
- * rsvd_solve), RSVD_ERR_SHAPE (m < n, l > 192, or a workspace larger than
+ * rsvd_solve), RSVD_ERR_SHAPE (m < n, m > 2^40, n > 2^20, l > 192, or a workspace larger than
  * RSVD_NOALLOC_SCRATCH_BYTES), RSVD_ERR_DEVICE. */
 #define RSVD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 int32_t rsvd_solve_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype,

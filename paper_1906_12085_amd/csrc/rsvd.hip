@@ -27,6 +27,10 @@ namespace {
 // grouped batches and of captured batch graphs (both take l <= kSmallSvdMaxC).
 constexpr int kMaxL = 192;
 constexpr int kSmallSvdMaxC = 96;
+// Dimension limits checked before any size arithmetic: with m <= 2^40 rows
+// and n <= 2^20 columns every workspace size below stays far inside int64_t.
+constexpr int64_t kMaxRows = (int64_t)1 << 40;
+constexpr int64_t kMaxCols = (int64_t)1 << 20;
 constexpr int kDiagWords = 8;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -683,7 +687,7 @@ int32_t rsvd_plan_create(rsvd_plan_t* plan, int64_t m_max, int64_t n_max, int32_
     return RSVD_ERR_ARG;
   if (lowp_es(dtype) && want_gram) return RSVD_ERR_ARG;   // the A^T A route is fp32/fp64
   if (l_max < 1) return RSVD_ERR_ARG;
-  if (n_max < 1 || m_max < n_max) return RSVD_ERR_SHAPE;
+  if (n_max < 1 || m_max < n_max || m_max > kMaxRows || n_max > kMaxCols) return RSVD_ERR_SHAPE;
   if (l_max > kMaxL) return RSVD_ERR_SHAPE;
   if (want_gram && n_max > jacobi_eig_max_n()) return RSVD_ERR_SHAPE;
   rsvd_plan_s* p = new (std::nothrow) rsvd_plan_s();
@@ -1837,9 +1841,11 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
     p.l_max = (int)((x.k + (int64_t)x.p < x.n) ? x.k + x.p : x.n);
     p.gram = false;
     p.seed = batch->plan[0]->seed;
-    // the batch's split limit bounds the partials (the grouped splits are
-    // longer than a slot's: kGroupedSplitRows rows at least)
-    p.max_split = batch->plan[0]->max_split;
+    // partials for the grouped row splits only: at least kGroupedSplitRows
+    // rows each, so at most ceil(m / kGroupedSplitRows) of them (within the
+    // batch's split limit; the grouped launchers cap at the same count)
+    const int64_t gsplit = (x.m + kGroupedSplitRows - 1) / kGroupedSplitRows;
+    p.max_split = gsplit < batch->plan[0]->max_split ? gsplit : batch->plan[0]->max_split;
     off[i] = total;
     total += carve(&p, nullptr);
   }
@@ -1942,7 +1948,7 @@ int32_t rsvd_solve_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int
                            int32_t* status, void* stream) {
   if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_ARG;
   if (!A || !status) return RSVD_ERR_ARG;
-  if (n < 1 || m < n) return RSVD_ERR_SHAPE;
+  if (n < 1 || m < n || m > kMaxRows || n > kMaxCols) return RSVD_ERR_SHAPE;
   if (k < 1 || k > n || p < 0) return RSVD_ERR_ARG;
   const int64_t l = (k + (int64_t)p < n) ? k + (int64_t)p : n;
   if (l > kMaxL) return RSVD_ERR_SHAPE;

@@ -55,7 +55,7 @@ def test_plan_create_validates_before_device_calls(lib):
     assert f(ctypes.byref(h), 100, 10, 0, 0, 0, 0, None) == -1            # l_max < 1
     assert f(ctypes.byref(h), 5, 10, 8, 0, 0, 0, None) == -2              # m_max < n_max
     assert f(ctypes.byref(h), 100, 0, 8, 0, 0, 0, None) == -2             # n_max < 1
-    assert f(ctypes.byref(h), 1000, 200, 97, 1, 0, 0, None) == -2         # l_max above 96
+    assert f(ctypes.byref(h), 1000, 200, 193, 1, 0, 0, None) == -2        # l_max above 192
     assert f(ctypes.byref(h), 5000, 2000, 32, 1, 1, 0, None) == -2        # A^T A route n_max above 1024
     assert f(ctypes.byref(h), 5000, 200, 32, 2, 1, 0, None) == -1         # bf16 plan: no A^T A route
     assert f(ctypes.byref(h), 5000, 200, 32, 3, 1, 0, None) == -1         # fp8 plan: no A^T A route

@@ -34,8 +34,9 @@ def test_noalloc_rejects_before_any_device_call():
     # workspace beyond the static array: 2 m l fp32 elements alone exceed it
     assert f(a, 2_000_000, 512, 512, rs.RSVD_F32, 64, 16, 2, 0.9, 1, a, 64, a, a, 64, a, a,
              None) == -2
-    # l above 96
-    assert f(a, 5000, 512, 512, rs.RSVD_F32, 90, 16, 2, 0.9, 1, a, 90, a, a, 90, a, a, None) == -2
+    # l above 192
+    assert f(a, 5000, 512, 512, rs.RSVD_F32, 190, 16, 2, 0.9, 1, a, 190, a, a, 190, a, a,
+             None) == -2
     # argument errors of rsvd_solve
     assert f(a, 1000, 64, 32, rs.RSVD_F32, 8, 4, 1, 0.9, 1, a, 8, a, a, 8, a, a, None) == -1
     assert f(a, 1000, 64, 64, rs.RSVD_F32, 8, 4, -1, 0.9, 1, a, 8, a, a, 8, a, a, None) == -1

@@ -40,6 +40,10 @@ PINS = {
     "rsvd": "tests/test_oracle_rsvd.py (exact recovery at rank l, interlacing, "
             "Halko et al. error bound, convergence in q)",
     "gram_eig": "tests/test_oracle_rsvd.py (equals exact SVD on well-separated spectra)",
+    "rsvd_blocked": "tests/test_oracle_blocked.py (one block equals Randomized PCA, exact "
+                    "recovery when rank(A) is a multiple of the block, energy = sum of the "
+                    "captured s^2 and monotone up to ||A||_F^2, the stopping block is the first "
+                    "to reach t, orthonormal factors, interlacing, K equals the exact K)",
     "krylov": "tests/test_oracle_krylov.py (exact recovery at rank (i+1) l where Randomized "
               "PCA with q = i is not exact, Ritz values between those of Randomized PCA and "
               "the exact ones, U^T A V = diag(s), i = 0 equals q = 0)",
@@ -94,6 +98,10 @@ def _load():
         lib.orc_gram_eig.argtypes = [i64, i64, p, i64, dbl, i64, p, i64, p, p, i64,
                                      ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         lib.orc_gram_eig.restype = ctypes.c_int
+        lib.orc_rsvd_blocked.argtypes = [i64, i64, p, i64, p, i64, i64, i64, dbl, i64, i64,
+                                         p, i64, p, p, i64, ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64), p, ctypes.POINTER(dbl)]
+        lib.orc_rsvd_blocked.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -269,6 +277,41 @@ def gram_eig(A, t: float, ucols: int | None = None) -> RSVDResult:
     if rc < 0:
         raise RuntimeError(f"orc_gram_eig failed: {rc}")
     return RSVDResult(U[:, :uc], S, V, int(K.value), float(f2.value), int(rc))
+
+
+class BlockedResult(NamedTuple):
+    U: np.ndarray
+    S: np.ndarray
+    V: np.ndarray
+    K: int
+    fro2: float
+    status: int
+    L: int
+    energy: np.ndarray
+
+
+def rsvd_blocked(A, G, b: int, q: int, t: float, lmax: int, kcap: int) -> BlockedResult:
+    """Randomized PCA with the rank grown in blocks of b columns until the
+    criterion of Sec. 2.4 can be met (Martinsson & Voronin 2016, blocked
+    range finder with power steps); G (n x nb*b) holds the blocks' sketches
+    side by side.  Returns the first min(kcap, L) triplets, K (capped at
+    kcap), the columns used L and the captured energy after each block."""
+    A, G = _f64(A), _f64(G)
+    m, n = A.shape
+    assert G.shape[0] == n and (b < 1 or G.shape[1] % b == 0)
+    kcap_ = max(int(kcap), 1)
+    U = np.zeros((m, kcap_)); S = np.zeros(kcap_); V = np.zeros((n, kcap_))
+    energy = np.zeros(max(1, G.shape[1] // max(b, 1)))
+    K = ctypes.c_int64(0); L = ctypes.c_int64(0); f2 = ctypes.c_double(0.0)
+    rc = _load().orc_rsvd_blocked(m, n, _ptr(A), n, _ptr(G), G.shape[1], b, q, float(t), lmax,
+                                  kcap, _ptr(U), kcap_, _ptr(S), _ptr(V), kcap_, ctypes.byref(K),
+                                  ctypes.byref(L), _ptr(energy), ctypes.byref(f2))
+    if rc < 0:
+        raise RuntimeError(f"orc_rsvd_blocked failed: {rc}")
+    Lv = int(L.value)
+    kc = min(kcap, Lv)
+    return BlockedResult(U[:, :kc], S[:kc], V[:, :kc], int(K.value), float(f2.value), int(rc),
+                         Lv, energy[:Lv // b])
 
 
 def principal_angle_max(X, Y) -> float:

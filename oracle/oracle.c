@@ -32,6 +32,10 @@
  *                               orthonormal (same Krylov space)
  *   orc_gram_eig                truncated SVD through A^T A (Sec. 2.3,
  *                               Sec. 3.1.3)
+ *   orc_rsvd_blocked            Randomized PCA with the rank grown in blocks
+ *                               until the criterion of Sec. 2.4 can be met
+ *                               (Martinsson & Voronin 2016, blocked range
+ *                               finder with power steps)
  *
  * Reductions are split into a fixed number of row chunks whose partial
  * results are added in chunk order, so results do not depend on the number
@@ -634,5 +638,134 @@ int orc_gram_eig(int64_t m, int64_t n, const double* A, int64_t lda, double t,
   rc = orc_select_k(n, S, *fro2, t, K);
 done:
   free(Gm); free(lam);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Randomized PCA with the rank grown in blocks of b columns until the
+ * criterion of Sec. 2.4 can be met: the blocked randomized range finder with
+ * power steps of Martinsson & Voronin (SIAM J. Sci. Comput. 38(5), 2016,
+ * randQB_b with power iterations), with B = Q^T A kept as T = B^T = A^T Q.
+ *   for j = 0, 1, ... (block j of G: columns j b .. j b + b - 1):
+ *     Y = A G_j - Q (T^T G_j)          the part of A G_j outside span(Q)
+ *     Q_j = qr(Y)
+ *     q times:  Z = qr(A^T Q_j);  Y = A Z - Q (T^T Z);  Q_j = qr(Y)
+ *     Q_j = qr(Q_j - Q (Q^T Q_j))      re-orthogonalisation against Q
+ *     T_j = A^T Q_j;  Q = [Q Q_j];  T = [T T_j];  L = L + b
+ *     energy[j] = ||T||_F^2 = ||Q^T A||_F^2, the part of ||A||_F^2 (Eq.
+ *     sumeigen) that span(Q) holds; stop when energy[j] >= t ||A||_F^2 or
+ *     when another block would pass min(lmax, n) columns
+ *   SVD T = V~ S~ W^T;  U~ = Q W;  K by Sec. 2.4 over all L values.
+ * The first min(kcap, L) triplets are returned (sign rule applied); K is
+ * capped at kcap, with ORC_WARN_THRESHOLD when capped or not reached.
+ * Reading: Martinsson & Voronin also subtract B^T (Q^T Q_j) before the A^T
+ * product of a power step; Q_j was projected off span(Q) just before, so
+ * that term is rounding only, and the re-orthogonalisation that ends the
+ * block restores Q_j's orthogonality to Q; it is left out. */
+int orc_rsvd_blocked(int64_t m, int64_t n, const double* A, int64_t lda,
+                     const double* G, int64_t ldg, int64_t b, int64_t q, double t,
+                     int64_t lmax, int64_t kcap, double* U, int64_t ldu, double* S,
+                     double* V, int64_t ldv, int64_t* K, int64_t* Lout, double* energy,
+                     double* fro2) {
+  const int64_t Lcap = (lmax < n) ? lmax : n;
+  if (m < n || n < 1 || b < 1 || b > Lcap || q < 0 || kcap < 1 || kcap > n ||
+      ldg < b || !(t > 0.0 && t <= 1.0))
+    return ORC_ERR_ARG;
+  double* Q = (double*)calloc((size_t)(m * Lcap), sizeof(double));
+  double* T = (double*)calloc((size_t)(n * Lcap), sizeof(double));
+  double* Y = (double*)malloc((size_t)(m * b) * sizeof(double));
+  double* Qj = (double*)malloc((size_t)(m * b) * sizeof(double));
+  double* Gj = (double*)malloc((size_t)(n * b) * sizeof(double));
+  double* Z = (double*)malloc((size_t)(n * b) * sizeof(double));
+  double* Zq = (double*)malloc((size_t)(n * b) * sizeof(double));
+  double* C = (double*)malloc((size_t)(Lcap * b) * sizeof(double));
+  double* Rb = (double*)malloc((size_t)(b * b) * sizeof(double));
+  double* Tc = (double*)malloc((size_t)(n * Lcap) * sizeof(double));
+  double* Vt = (double*)malloc((size_t)(n * Lcap) * sizeof(double));
+  double* St = (double*)malloc((size_t)Lcap * sizeof(double));
+  double* W = (double*)malloc((size_t)(Lcap * Lcap) * sizeof(double));
+  int rc = ORC_OK;
+  int64_t L = 0;
+  if (!Q || !T || !Y || !Qj || !Gj || !Z || !Zq || !C || !Rb || !Tc || !Vt || !St || !W) {
+    rc = ORC_ERR_NOMEM;
+    goto done;
+  }
+  *fro2 = orc_fro2(m, n, A, lda);                               /* Eq. sumeigen */
+  /* Y -= Q C (C = L x b) */
+#define ORC_SUB_QC(Ymat)                                                      \
+  do {                                                                        \
+    _Pragma("omp parallel for schedule(static)")                              \
+    for (int64_t r = 0; r < m; ++r)                                           \
+      for (int64_t c = 0; c < b; ++c) {                                       \
+        double s = 0.0;                                                       \
+        for (int64_t e = 0; e < L; ++e) s += Q[r * Lcap + e] * C[e * b + c];  \
+        (Ymat)[r * b + c] -= s;                                               \
+      }                                                                       \
+  } while (0)
+  for (int64_t j = 0;; ++j) {
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t c = 0; c < b; ++c) Gj[r * b + c] = G[r * ldg + j * b + c];
+    orc_gemm_nn(m, n, b, A, lda, Gj, b, Y, b);                 /* Y = A G_j */
+    if (L > 0) {                                                /* - Q (T^T G_j) */
+      if ((rc = orc_gemm_tn(n, L, b, T, Lcap, Gj, b, C, b)) != ORC_OK) goto done;
+      ORC_SUB_QC(Y);
+    }
+    if ((rc = orc_qr_householder(m, b, Y, b, Qj, b, Rb, b)) != ORC_OK) goto done;
+    for (int64_t it = 0; it < q; ++it) {
+      if ((rc = orc_gemm_tn(m, n, b, A, lda, Qj, b, Z, b)) != ORC_OK) goto done;
+      if ((rc = orc_qr_householder(n, b, Z, b, Zq, b, Rb, b)) != ORC_OK) goto done;
+      orc_gemm_nn(m, n, b, A, lda, Zq, b, Y, b);               /* Y = A Z */
+      if (L > 0) {                                              /* - Q (T^T Z) */
+        if ((rc = orc_gemm_tn(n, L, b, T, Lcap, Zq, b, C, b)) != ORC_OK) goto done;
+        ORC_SUB_QC(Y);
+      }
+      if ((rc = orc_qr_householder(m, b, Y, b, Qj, b, Rb, b)) != ORC_OK) goto done;
+    }
+    if (L > 0) {                                                /* Q_j - Q (Q^T Q_j) */
+      if ((rc = orc_gemm_tn(m, L, b, Q, Lcap, Qj, b, C, b)) != ORC_OK) goto done;
+      ORC_SUB_QC(Qj);
+      memcpy(Y, Qj, (size_t)(m * b) * sizeof(double));
+      if ((rc = orc_qr_householder(m, b, Y, b, Qj, b, Rb, b)) != ORC_OK) goto done;
+    }
+    if ((rc = orc_gemm_tn(m, n, b, A, lda, Qj, b, Z, b)) != ORC_OK) goto done;   /* T_j */
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t c = 0; c < b; ++c) Q[r * Lcap + L + c] = Qj[r * b + c];
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t c = 0; c < b; ++c) T[r * Lcap + L + c] = Z[r * b + c];
+    L += b;
+    double e2 = 0.0;                                            /* ||T||_F^2 */
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t c = 0; c < L; ++c) e2 += T[r * Lcap + c] * T[r * Lcap + c];
+    energy[j] = e2;
+    if (!(e2 < t * *fro2) || L + b > Lcap) break;
+  }
+#undef ORC_SUB_QC
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t c = 0; c < L; ++c) Tc[r * L + c] = T[r * Lcap + c];
+  rc = orc_svd_exact(n, L, Tc, L, Vt, L, St, W, L);             /* T = V~ S~ W^T */
+  if (rc < 0) goto done;
+  {
+    const int64_t kc = kcap < L ? kcap : L;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < m; ++r)                             /* U~ = Q W */
+      for (int64_t c = 0; c < kc; ++c) {
+        double s = 0.0;
+        for (int64_t e = 0; e < L; ++e) s += Q[r * Lcap + e] * W[e * L + c];
+        U[r * ldu + c] = s;
+      }
+    for (int64_t c = 0; c < kc; ++c) S[c] = St[c];
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t c = 0; c < kc; ++c) V[r * ldv + c] = Vt[r * L + c];
+    orc_sign_convention(m, n, kc, U, ldu, V, ldv);
+    rc = orc_select_k(L, St, *fro2, t, K);
+    if (rc >= 0 && *K > kcap) {
+      *K = kcap;
+      rc = ORC_WARN_THRESHOLD;
+    }
+  }
+done:
+  *Lout = L;
+  free(Q); free(T); free(Y); free(Qj); free(Gj); free(Z); free(Zq); free(C); free(Rb);
+  free(Tc); free(Vt); free(St); free(W);
   return rc;
 }

@@ -169,7 +169,33 @@ int32_t rsvd_solve_omega(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, 
                          const double* omega, void* U, int64_t ldu, double* S, void* V,
                          int64_t ldv, int32_t* K);
 
-/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
+/* rsvd_solve_adaptive: Randomized PCA (Sec. 3.1.2) whose rank is grown in
+ * blocks until the criterion of Sec. 2.4 can be met -- the blocked randomized
+ * range finder with power steps of Martinsson & Voronin (SIAM J. Sci.
+ * Comput. 38(5), 2016).  Blocks of b = min(k + p, n) columns: block j draws
+ * its sketch G_j (n x b) from the plan's seed plus j * 0x9E3779B97F4A7C15
+ * (block 0 is rsvd_solve's sketch), takes the part of A G_j outside the
+ * basis Q built so far, runs q power steps with that projection, is
+ * re-orthogonalised against Q (CholeskyQR2 throughout) and appended to Q,
+ * and T = A^T Q grows by A^T Q_j; the energy ||Q^T A||_F^2 = ||T||_F^2 is
+ * accumulated on the device.  After each block the host reads it and
+ * grows again while it is below t ||A||_F^2 (Eq. sumeigen) and another
+ * block fits (L + b <= l_max and <= n): so the call synchronises the plan's
+ * stream once per block.  Then SVD T = V~ S~ W^T, U~ = Q W, and K by Sec.
+ * 2.4 over all L values, capped at k_max (RSVD_WARN_THRESHOLD when capped
+ * or not reached).  U (m x k_max, ldu), S (k_max), V (n x k_max, ldv):
+ * the first min(k_max, L) triplets are written (columns past L are left
+ * untouched); rsvd_plan_diag reports L in diag[6] and the captured fraction
+ * ||T||_F^2 / ||A||_F^2 in diag[7].  Any plan dtype (col_scale as
+ * rsvd_solve).  Requires k <= k_max <= n, ldu and ldv >= k_max, and two
+ * row-padded blocks within the plan's sketch width (2 * round_up(b, 8) <=
+ * l_max, else RSVD_ERR_SHAPE); other errors as rsvd_solve. */
+int32_t rsvd_solve_adaptive(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                            const float* col_scale, int32_t k, int32_t p, int32_t q, double t,
+                            int32_t k_max, void* U, int64_t ldu, double* S, void* V, int64_t ldv,
+                            int32_t* K);
+
+/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1)/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
  * min(k + p, n)), blocks H(0) = A G and H(j) = A (A^T H(j-1)) for j = 1..i,
  * QR of their concatenation H (m x (i+1) l), T = A^T Q, SVD T = V~ S~ W^T,
  * U~ = Q W -- returning the first k triplets and K by the threshold t

@@ -41,7 +41,7 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_progress",
            "rsvd_server_destroy", "rsvd_batch_grouped_create", "rsvd_batch_grouped_launch",
-           "rsvd_batch_grouped_destroy", "rsvd_solve_noalloc"]
+           "rsvd_batch_grouped_destroy", "rsvd_solve_noalloc", "rsvd_solve_adaptive"]
 
 
 class RsvdInstance(ctypes.Structure):
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    vp, i64, vp, vp, i64, vp]),
         "rsvd_solve_krylov": (i32, [vp, vp, i64, i64, i64, i32, i32, i32, dbl, vp,
                                     vp, i64, vp, vp, i64, vp]),
+        "rsvd_solve_adaptive": (i32, [vp, vp, i64, i64, i64, vp, i32, i32, i32, dbl, i32,
+                                      vp, i64, vp, vp, i64, vp]),
         "rsvd_batch_create": (i32, [ctypes.POINTER(vp), i32, i64, i64, i32, i32, u64]),
         "rsvd_batch_destroy": (i32, [vp]),
         "rsvd_batch_solve": (i32, [vp, ctypes.POINTER(RsvdInstance), i32, vp]),
@@ -244,6 +246,16 @@ def rsvd_solve_krylov(plan: int, A, k: int, p: int, i: int, t: float, omega, U, 
                   "rsvd_solve_krylov")
 
 
+def rsvd_solve_adaptive(plan: int, A, k: int, p: int, q: int, t: float, k_max: int, U, S, V, K,
+                        col_scale=None) -> int:
+    m, n = A.shape
+    return _check(load_library().rsvd_solve_adaptive(plan, _ptr(A), m, n, _ld(A),
+                                                     _ptr(col_scale), k, p, q, float(t),
+                                                     int(k_max), _ptr(U), _ld(U), _ptr(S),
+                                                     _ptr(V), _ld(V), _ptr(K)),
+                  "rsvd_solve_adaptive")
+
+
 def rsvd_solve_bf16(plan: int, A, col_scale, k: int, p: int, q: int, t: float, omega, U, S, V,
                     K) -> int:
     m, n = A.shape
@@ -388,6 +400,19 @@ class Plan:
             rsvd_solve_omega(self.handle, A, k, p, q, t, omega, U, S, V, K, col_scale=col_scale)
         if not sync:
             return Result(U, S, V, K, 0)
+        st = self.status()
+        return Result(U, S, V, int(K.item()), st)
+
+    def solve_adaptive(self, A, k: int, p: int, q: int, t: float, k_max: int, col_scale=None):
+        """Randomized PCA with the rank grown in blocks of min(k + p, n)
+        columns until the threshold t can be met (rsvd_solve_adaptive); U, S,
+        V hold k_max columns (the first min(k_max, L) written), L = the
+        basis size, from the plan's diagnostics."""
+        m, n = A.shape
+        torch = self.torch
+        U = self._out((m, k_max)); V = self._out((n, k_max))
+        S = self._out((k_max,), torch.float64); K = self._out((1,), torch.int32)
+        rsvd_solve_adaptive(self.handle, A, k, p, q, t, k_max, U, S, V, K, col_scale=col_scale)
         st = self.status()
         return Result(U, S, V, int(K.item()), st)
 

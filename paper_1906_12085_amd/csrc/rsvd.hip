@@ -78,6 +78,7 @@ struct rsvd_plan_s {
   double *Wk = nullptr, *Mk = nullptr;
   void* MkT = nullptr;       // l x l (T)
   double* EsS = nullptr;     // block-Jacobi scratch of the small SVD (l > kSmallSvdMaxC)
+  double* Tp = nullptr;      // n x l_max (ld l_max) A^T Q of a basis grown in blocks
   int32_t* status = nullptr;
   double* diag = nullptr;
   int32_t* flags = nullptr;
@@ -178,6 +179,7 @@ size_t carve(rsvd_plan_s* p, char* base) {
   p->Mk = (double*)take(l * l * 8);
   p->MkT = take(l * l * es);
   if (l > kSmallSvdMaxC) p->EsS = (double*)take(jacobi_eig_scratch_doubles(l) * 8);
+  p->Tp = (double*)take(n * l * 8);
   p->status = (int32_t*)take(64);
   p->diag = (double*)take(kDiagWords * 8);
   p->flags = (int32_t*)take(jacobi_eig_flag_words() * 4);
@@ -585,6 +587,296 @@ int32_t krylov_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda
   return RSVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Randomized PCA with the rank grown in blocks of b columns until the
+// criterion of Sec. 2.4 can be met: the blocked randomized range finder with
+// power steps of Martinsson & Voronin (SIAM J. Sci. Comput. 2016, randQB_b
+// with power iterations).  The basis Q is kept explicit in the plan's Q1
+// buffer (m x L, row stride ldq1_of(l_max)), B = Q^T A as T = A^T Q in Tp
+// (n x L, FP64, row stride l_max); block j:
+//   Y = A G_j - Q (T^T G_j);  Q_j = orth(Y)
+//   q times:  Z = orth(A^T Q_j);  Y = A Z - Q (T^T Z);  Q_j = orth(Y)
+//   Q_j = orth(Q_j - Q (Q^T Q_j))            (re-orthogonalisation)
+//   T_j = A^T Q_j;  Q = [Q Q_j];  T = [T T_j];  L += b
+// with orth = CholeskyQR2 and its explicit factor, and scal[1] += ||T_j||_F^2,
+// the energy ||Q^T A||_F^2 that span(Q) holds (scal[0] = ||A||_F^2, Eq.
+// sumeigen, from block 0's first pass).  Block j's sketch G_j is drawn from
+// seed + j * 0x9E3779B97F4A7C15 (block 0: the plan's own sketch).  The
+// caller decides between blocks (on the host) whether to grow; then the
+// finish step: SVD T = V~ S~ W^T, U~ = Q W, K over all L values.
+struct GrowJob {
+  const void* A = nullptr;
+  int64_t m = 0, n = 0, lda = 0;
+  LowpA lp{nullptr, nullptr, 0};
+  int b = 0, q = 0, kcap = 0;
+  double t = 0.0;
+  int L = 0, j = 0;
+  void* U = nullptr;
+  int64_t ldu = 0;
+  double* S = nullptr;
+  void* V = nullptr;
+  int64_t ldv = 0;
+  int32_t* K = nullptr;
+};
+
+constexpr uint64_t kBlockSeedStep = 0x9E3779B97F4A7C15ull;
+
+// Y (rows x cols, ld) -= W (same layout).
+template <typename T>
+__global__ void k_sub(T* __restrict__ Y, const T* __restrict__ W, int64_t rows, int cols,
+                      int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx / cols;
+  const int j = (int)(idx - i * cols);
+  Y[i * ld + j] -= W[i * ld + j];
+}
+
+// dst (rows x cols, ldd) = src (rows x cols, lds).
+template <typename T>
+__global__ void k_copy2d(const T* __restrict__ src, int64_t lds, T* __restrict__ dst, int64_t ldd,
+                         int64_t rows, int cols) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx / cols;
+  const int j = (int)(idx - i * cols);
+  dst[i * ldd + j] = src[i * lds + j];
+}
+
+// scal[1] += ||Z||_F^2 (Z rows x cols, ld cols; one block, fixed order);
+// diag[6] = L, diag[7] = scal[1] / scal[0].
+__global__ void k_energy(const double* __restrict__ Z, int64_t rows, int cols, double* scal,
+                         double* diag, int L) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < rows * cols; e += 256) s += Z[e] * Z[e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double e = scal[1] + sh[0];
+    scal[1] = e;
+    diag[6] = (double)L;
+    diag[7] = scal[0] > 0.0 ? e / scal[0] : 0.0;
+  }
+}
+
+// K <= kcap: a larger K is capped, with RSVD_WARN_THRESHOLD.
+__global__ void k_cap_k(int32_t* K, int kcap, int32_t* status, double* diag) {
+  if (threadIdx.x == 0 && *K > kcap) {
+    *K = kcap;
+    diag[4] = (double)kcap;
+    atomicCAS(status, (int32_t)RSVD_OK, (int32_t)RSVD_WARN_THRESHOLD);   // errors stay
+  }
+}
+
+inline unsigned grid_for(int64_t total) { return (unsigned)((total + 255) / 256); }
+
+template <typename T>
+struct Grow {
+  rsvd_plan_s* p;
+  GrowJob& g;
+  hipStream_t s;
+  Path<T> P;
+  int64_t ldp, ldb;
+  T* Qp;
+  T* Yb;
+  T* Wb;
+  Grow(rsvd_plan_s* plan, GrowJob& job)
+      : p(plan), g(job), s(plan->stream), P(plan), ldp(ldq1_of(plan->l_max)),
+        ldb(ldq1_of(job.b)), Qp((T*)plan->Q1), Yb((T*)plan->Y), Wb((T*)plan->Y + job.m * ldb) {}
+
+  bool low() const { return g.lp.es != 0; }
+
+  // Y (m x b, ldb) = A X, X n x b FP64 (ld b)
+  hipError_t pass_nn(const double* X64, double* fro2_part, int* np) {
+    hipError_t e;
+    const int b = g.b;
+    const int64_t m = g.m, n = g.n;
+    if (low()) {
+      __bf16* Xhi = reinterpret_cast<__bf16*>(p->Xs);
+      __bf16* Xlo = Xhi + (int64_t)b * n;
+      if ((e = launch_cast_hilo_t(X64, n, b, g.lp.scale, Xhi, Xlo, n, s)) != hipSuccess) return e;
+      return launch_gemm_nt_bf16(g.lp.A, g.lp.es, m, n, g.lda, Xhi, Xlo, n, b, g.lp.scale,
+                                 reinterpret_cast<float*>(Yb), ldb, fro2_part, np, s);
+    }
+    const T* A = (const T*)g.A;
+    T* Xs = (T*)p->Xs;
+    if (std::is_same<T, float>::value &&
+        nt_tall_applies(reinterpret_cast<const float*>(A), n, g.lda,
+                        reinterpret_cast<const float*>(Xs), n, b)) {
+      if ((e = launch_cast_t_from_f64<T>(X64, n, b, b, Xs, n, s)) != hipSuccess) return e;
+      return launch_gemm_nt_tall(reinterpret_cast<const float*>(A), m, n, g.lda,
+                                 reinterpret_cast<const float*>(Xs), n, b,
+                                 reinterpret_cast<float*>(Yb), ldb, fro2_part, np, s);
+    }
+    if ((e = launch_cast_from_f64<T>(X64, n, b, b, Xs, b, s)) != hipSuccess) return e;
+    return launch_gemm_nn<T>(A, m, n, g.lda, Xs, b, b, Yb, ldb, fro2_part, np, s);
+  }
+
+  // Z (n x b, FP64) = A^T Q, Q m x b (ld ldq)
+  hipError_t pass_tn(const T* Q, int64_t ldq, double* Z) {
+    if (low())
+      return P.tn_bf16(g.lp, g.m, g.n, g.lda, reinterpret_cast<const float*>(Q), ldq, g.b, Z);
+    return P.tn((const T*)g.A, g.m, g.n, g.lda, Q, ldq, g.b, Z);
+  }
+
+  // Yb -= Qp C, C (L x b, FP64, ld b) in p->Mk
+  hipError_t sub_qc() {
+    hipError_t e;
+    const int L = g.L, b = g.b;
+    T* CT = (T*)p->MkT;
+    if (std::is_same<T, float>::value &&
+        nt_tall_applies(reinterpret_cast<const float*>(Qp), L, ldp,
+                        reinterpret_cast<const float*>(CT), L, b)) {
+      if ((e = launch_cast_t_from_f64<T>(p->Mk, L, b, b, CT, L, s)) != hipSuccess) return e;
+      e = launch_gemm_nt_tall(reinterpret_cast<const float*>(Qp), g.m, L, ldp,
+                              reinterpret_cast<const float*>(CT), L, b,
+                              reinterpret_cast<float*>(Wb), ldb, nullptr, nullptr, s);
+    } else {
+      if ((e = launch_cast_from_f64<T>(p->Mk, L, b, b, CT, b, s)) != hipSuccess) return e;
+      e = launch_gemm_nn<T>(Qp, g.m, L, ldp, CT, b, b, Wb, ldb, nullptr, nullptr, s);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sub<T>), dim3(grid_for(g.m * b)), dim3(256), 0, s, Yb, Wb, g.m, b, ldb);
+    return hipGetLastError();
+  }
+
+  // Yb -= Qp (T^T X), X n x b FP64 (ld b): the part outside span(Q)
+  hipError_t project(const double* X64) {
+    if (g.L == 0) return hipSuccess;
+    hipError_t e = Path<double>(p).tn(p->Tp, g.n, g.L, p->l_max, X64, g.b, g.b, p->Mk);
+    if (e != hipSuccess) return e;
+    return sub_qc();
+  }
+
+  // Yb <- an orthonormal basis of its columns (CholeskyQR2, explicit)
+  hipError_t orth() {
+    hipError_t e;
+    const bool tb = P.times_rinv_tall(Wb, g.b, ldb, (const T*)p->RinvT);
+    if ((e = P.cqr2(Yb, g.m, g.b, ldb, Wb, ldb, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT,
+                    tb)) != hipSuccess)
+      return e;
+    return P.times_rinv(Wb, g.m, g.b, ldb, (const T*)p->RinvT, tb, Yb, ldb);
+  }
+
+  hipError_t block() {
+    hipError_t e;
+    const int b = g.b;
+    const int64_t m = g.m, n = g.n;
+    if (g.j == 0) {
+      if ((e = launch_fill_scal(p)) != hipSuccess) return e;
+    }
+    if ((e = launch_gaussian_fill(p->seed + kBlockSeedStep * (uint64_t)g.j, n, b, p->omega, s)) !=
+        hipSuccess)
+      return e;
+    int np = 0;
+    if ((e = pass_nn(p->omega, g.j == 0 ? p->fro2_part : nullptr, &np)) != hipSuccess) return e;
+    if (g.j == 0 && (e = launch_reduce_scalar(p->fro2_part, np, p->scal, s)) != hipSuccess)
+      return e;
+    if ((e = project(p->omega)) != hipSuccess) return e;
+    if ((e = orth()) != hipSuccess) return e;
+    for (int it = 0; it < g.q; ++it) {
+      if ((e = pass_tn(Yb, ldb, p->Zd)) != hipSuccess) return e;
+      if ((e = cqr2_small(p, p->Zd, n, b, p->Zq)) != hipSuccess) return e;
+      if ((e = pass_nn(p->Zq, nullptr, nullptr)) != hipSuccess) return e;
+      if ((e = project(p->Zq)) != hipSuccess) return e;
+      if ((e = orth()) != hipSuccess) return e;
+    }
+    if (g.L > 0) {   // Q_j - Q (Q^T Q_j), then orthonormalised again
+      if ((e = P.tn(Qp, m, g.L, ldp, Yb, ldb, b, p->Mk)) != hipSuccess) return e;
+      if ((e = sub_qc()) != hipSuccess) return e;
+      if ((e = orth()) != hipSuccess) return e;
+    }
+    // append Q_j, T_j = A^T Q_j
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(grid_for(m * b)), dim3(256), 0, s, Yb, ldb,
+                       Qp + g.L, ldp, m, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = pass_tn(Yb, ldb, p->Zd)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_copy2d<double>), dim3(grid_for(n * b)), dim3(256), 0, s, p->Zd,
+                       (int64_t)b, p->Tp + g.L, (int64_t)p->l_max, n, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    g.L += b;
+    ++g.j;
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, s, p->Zd, n, b, p->scal, p->diag, g.L);
+    return hipGetLastError();
+  }
+
+  static hipError_t launch_fill_scal(rsvd_plan_s* pl) {
+    // scal[1] (the captured energy) starts at zero
+    return launch_fill_i32(reinterpret_cast<int32_t*>(pl->scal + 1), 2, 0, pl->stream);
+  }
+
+  hipError_t finish() {
+    hipError_t e;
+    const int L = g.L;
+    const int64_t m = g.m, n = g.n;
+    const int kc = g.kcap < L ? g.kcap : L;
+    hipLaunchKernelGGL((k_copy2d<double>), dim3(grid_for(n * L)), dim3(256), 0, s, p->Tp,
+                       (int64_t)p->l_max, p->Z2, (int64_t)L, n, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = small_svd_unsorted(p, p->Z2, n, L)) != hipSuccess) return e;
+    // the first kc triplets; all L values (sorted) for the criterion
+    if ((e = launch_sort_sign_scatter<T>(p->Su, L, p->Vt, n, L, 1, p->Uo, kc, g.S, (T*)g.V, g.ldv,
+                                         nullptr, p->Wk, s)) != hipSuccess)
+      return e;
+    if ((e = launch_sort_sign_scatter<T>(p->Su, L, p->Vt, n, L, 1, nullptr, L, p->Zq, nullptr, 0,
+                                         nullptr, nullptr, s)) != hipSuccess)
+      return e;
+    // U~ = Q W (first kc columns)
+    T* WT = (T*)p->MkT;
+    if (std::is_same<T, float>::value &&
+        nt_tall_applies(reinterpret_cast<const float*>(Qp), L, ldp,
+                        reinterpret_cast<const float*>(WT), L, kc)) {
+      if ((e = launch_cast_t_from_f64<T>(p->Wk, L, kc, kc, WT, L, s)) != hipSuccess) return e;
+      e = launch_gemm_nt_tall(reinterpret_cast<const float*>(Qp), m, L, ldp,
+                              reinterpret_cast<const float*>(WT), L, kc,
+                              reinterpret_cast<float*>(g.U), g.ldu, nullptr, nullptr, s);
+    } else {
+      if ((e = launch_cast_from_f64<T>(p->Wk, L, kc, kc, WT, kc, s)) != hipSuccess) return e;
+      e = launch_gemm_nn<T>(Qp, m, L, ldp, WT, kc, kc, (T*)g.U, g.ldu, nullptr, nullptr, s);
+    }
+    if (e != hipSuccess) return e;
+    if ((e = launch_select_k(p->Zq, L, p->scal, g.t, g.K, p->diag, p->status, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_cap_k, dim3(1), dim3(64), 0, s, g.K, g.kcap, p->status, p->diag);
+    return hipGetLastError();
+  }
+};
+
+// Whether another block fits: L + b columns within the sketch limit and n.
+bool grow_fits(const rsvd_plan_s* p, const GrowJob& g) {
+  return g.L + g.b <= p->l_max && g.L + g.b <= g.n;
+}
+
+// Enqueue the next block (the first one resets the status word).
+int32_t grow_block(rsvd_plan_s* p, GrowJob& g) {
+  if (g.j == 0) RSVD_CHECK(reset(p));
+  if (p->dtype == RSVD_F64) RSVD_CHECK(Grow<double>(p, g).block());
+  else RSVD_CHECK(Grow<float>(p, g).block());
+  return RSVD_OK;
+}
+
+int32_t grow_finish(rsvd_plan_s* p, GrowJob& g) {
+  if (p->dtype == RSVD_F64) RSVD_CHECK(Grow<double>(p, g).finish());
+  else RSVD_CHECK(Grow<float>(p, g).finish());
+  return RSVD_OK;
+}
+
+// ||A||_F^2 and the captured energy after the blocks so far (waits for the
+// plan's stream).
+int32_t grow_read(rsvd_plan_s* p, double* fro2, double* energy) {
+  double h[2] = {0.0, 0.0};
+  RSVD_CHECK(hipMemcpyAsync(h, p->scal, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  RSVD_CHECK(hipStreamSynchronize(p->stream));
+  *fro2 = h[0];
+  *energy = h[1];
+  return RSVD_OK;
+}
+
 template <typename T>
 int32_t gram_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, double t,
                  int ucols, T* U, int64_t ldu, double* S, T* V, int64_t ldv, int32_t* K) {
@@ -887,6 +1179,34 @@ int32_t rsvd_solve_krylov(rsvd_plan_t plan, const void* A, int64_t m, int64_t n,
                               ldu, S, (double*)V, ldv, K);
   return krylov_run<float>(plan, (const float*)A, m, n, lda, k, p, i, t, omega, (float*)U, ldu,
                            S, (float*)V, ldv, K);
+}
+
+int32_t rsvd_solve_adaptive(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,
+                            const float* col_scale, int32_t k, int32_t p, int32_t q, double t,
+                            int32_t k_max, void* U, int64_t ldu, double* S, void* V, int64_t ldv,
+                            int32_t* K) {
+  int32_t rc = check_rsvd(plan, A, m, n, lda, k, p, q, t, U, ldu, S, V, ldv, K);
+  if (rc != RSVD_OK) return rc;
+  if (k_max < k || k_max > n || ldu < k_max || ldv < k_max) return RSVD_ERR_ARG;
+  const int64_t b = (k + (int64_t)p < n) ? k + (int64_t)p : n;
+  if (2 * ldq1_of(b) > plan->l_max) return RSVD_ERR_SHAPE;
+  const int es = lowp_es(plan->dtype);
+  if (!es && col_scale) return RSVD_ERR_ARG;
+  if (es && !bf16_pass_applies(A, es, n, lda, (int)b)) return RSVD_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  GrowJob g;
+  g.A = A; g.m = m; g.n = n; g.lda = lda;
+  g.lp = LowpA{es ? A : nullptr, col_scale, es};
+  g.b = (int)b; g.q = q; g.kcap = k_max; g.t = t;
+  g.U = U; g.ldu = ldu; g.S = S; g.V = V; g.ldv = ldv; g.K = K;
+  if ((rc = grow_block(plan, g)) != RSVD_OK) return rc;
+  while (grow_fits(plan, g)) {
+    double f2 = 0.0, e = 0.0;
+    if ((rc = grow_read(plan, &f2, &e)) != RSVD_OK) return rc;
+    if (!(e < t * f2)) break;        // reached (a NaN stops the growth as well)
+    if ((rc = grow_block(plan, g)) != RSVD_OK) return rc;
+  }
+  return grow_finish(plan, g);
 }
 
 int32_t rsvd_solve(rsvd_plan_t plan, const void* A, int64_t m, int64_t n, int64_t lda,

@@ -349,11 +349,21 @@ typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
  * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV), and
  * for RSVD_BF16 / RSVD_FP8 batches and servers `col_scale` (n floats, device,
  * or NULL for unit scales) as in rsvd_solve_bf16; ignored otherwise.
- * `k_max` (servers only; 0 or <= k = off): adaptive rank -- while a solve
- * ends with RSVD_WARN_THRESHOLD (the k values capture less than t of
- * ||A||_F^2, Sec. 2.4) and k < k_max, the request is solved again with
- * k = min(2k, k_max) ahead of the queue; U, S, V must then hold k_max
- * columns (ldu, ldv >= k_max) and k_max + p <= the server's l_max. */
+ * `k_max` (servers only; 0 or <= k = off): adaptive rank -- the request is
+ * solved as rsvd_solve_adaptive (the rank grown in blocks of b = min(k + p,
+ * n) columns, reusing the basis, until the threshold t can be met or the
+ * plan's l_max is full; 2 round_up(b, 8) <= l_max), with K capped at k_max;
+ * U, S, V then hold k_max <= n columns (ldu, ldv >= k_max), the first
+ * min(k_max, columns found) written.  A server created with
+ * RSVD_SERVER_GRAM_FALLBACK sends such a request to the A^T A route
+ * instead when its K is predicted past n / 2 (the paper's conclusion that
+ * the A^T A route is faster when most eigenpairs are needed, Sec. 3.3 and 5)
+ * or past what the sketch can hold; see rsvd_server_create.
+ * `dtype` (0 = the batch's or server's own dtype): the storage of this
+ * instance's A -- RSVD_F32, RSVD_BF16 or RSVD_FP8 (A as in rsvd_solve_bf16 /
+ * rsvd_solve_fp8, with col_scale) on a batch or server of any of those three
+ * dtypes (U and V are float for all of them), RSVD_F64 on an RSVD_F64 one;
+ * grouped batches take RSVD_F32 only. */
 typedef struct {
   const void* A;
   int64_t m, n, lda;
@@ -368,6 +378,7 @@ typedef struct {
   int32_t* status;
   const float* col_scale;
   int32_t k_max;
+  int32_t dtype;
 } rsvd_instance;
 
 /* Create a batch of nslots (1..64) slots for problems of one dtype (any of
@@ -446,11 +457,25 @@ int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped);
 typedef struct rsvd_server_s* rsvd_server_t;
 
 /* Create a server with nslots slots (1..64) for requests of one dtype (as
- * rsvd_batch_create) up to m_max x n_max with k + p <= l_max, admitting while the
- * running requests' footprints sum to at most hbm_budget bytes (a request
- * larger than the budget runs alone).  Errors as rsvd_batch_create. */
+ * rsvd_batch_create; an RSVD_F32, RSVD_BF16 or RSVD_FP8 server also takes
+ * requests whose own `dtype` is another of those three) up to m_max x n_max
+ * with k + p <= l_max, admitting while the running requests' footprints sum
+ * to at most hbm_budget bytes (a request larger than the budget runs alone).
+ * flags: RSVD_SERVER_GRAM_FALLBACK adds one A^T A-route slot (a plan sized
+ * m_max x n_max for gram_eig_solve, n_max <= 1024, its own stream, and for
+ * non-FP64 servers an m_max x n_max fp32 buffer into which a bfloat16 /
+ * FP8 request's A is dequantised): a request with k_max > k whose growth
+ * predicts K > n / 2 (from the energy its last block captured per column,
+ * a lower estimate on a decaying spectrum) or finds the sketch full below t
+ * is moved there, first come first served, and solved with all n
+ * eigenpairs: K by Sec. 2.4 over all n values (capped at k_max), and U,
+ * S, V receive the route's first k_max sorted triplets.  Errors as
+ * rsvd_batch_create, and RSVD_ERR_SHAPE for the fallback with
+ * n_max > 1024. */
+#define RSVD_SERVER_GRAM_FALLBACK 1
 int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max, int64_t n_max,
-                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget);
+                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget,
+                           int32_t flags);
 
 /* Queue one request (arguments and status word as a batch instance; the
  * buffers must stay valid until it is reported done).  A (and col_scale)

@@ -31,6 +31,7 @@ STATUS = {
 RSVD_OK, RSVD_WARN_THRESHOLD, RSVD_WARN_ZERO_MATRIX = 0, 1, 2
 RSVD_ERR_ARG, RSVD_ERR_SHAPE, RSVD_ERR_NOMEM, RSVD_ERR_DEVICE = -1, -2, -3, -4
 RSVD_ERR_BREAKDOWN, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = -5, -6, -7
+RSVD_SERVER_GRAM_FALLBACK = 1
 
 EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_plan_status",
            "rsvd_plan_diag", "rsvd_solve", "rsvd_solve_omega", "gram_eig_solve",
@@ -51,7 +52,8 @@ class RsvdInstance(ctypes.Structure):
                 ("q", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_void_p),
                 ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
                 ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("col_scale", ctypes.c_void_p), ("k_max", ctypes.c_int32)]
+                ("col_scale", ctypes.c_void_p), ("k_max", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
 
 
 def _dtype_codes(torch):
@@ -102,7 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                           ctypes.POINTER(vp)]),
         "rsvd_batch_graph_launch": (i32, [vp, vp]),
         "rsvd_batch_graph_destroy": (i32, [vp]),
-        "rsvd_server_create": (i32, [ctypes.POINTER(vp), i32, i64, i64, i32, i32, u64, i64]),
+        "rsvd_server_create": (i32, [ctypes.POINTER(vp), i32, i64, i64, i32, i32, u64, i64,
+                                     i32]),
         "rsvd_server_submit": (i32, [vp, ctypes.POINTER(RsvdInstance), ctypes.POINTER(i64)]),
         "rsvd_server_progress": (i32, [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -499,7 +502,8 @@ class Batch:
             arr[i] = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t),
                                   o["U"].data_ptr(), _ld(o["U"]), o["S"].data_ptr(),
                                   o["V"].data_ptr(), _ld(o["V"]), o["K"].data_ptr(),
-                                  o["status"].data_ptr(), _ptr(cs), 0)
+                                  o["status"].data_ptr(), _ptr(cs), 0,
+                                  _dtype_codes(torch)[A.dtype][0])
             o["col_scale"] = cs
             outs.append(o)
         return outs, arr
@@ -579,16 +583,19 @@ class Server:
     """Continuous batching of Randomized PCA requests (rsvd_server_*): submit()
     queues a request and returns its ticket; progress() never blocks and
     returns the tickets that finished since the last call (their outputs,
-    kept in `results[ticket]`, are then complete)."""
+    kept in `results[ticket]`, are then complete).  Requests may store A in
+    fp32, bfloat16 or FP8 on one server (other than FP64); gram_fallback adds
+    the A^T A-route slot for requests whose K is predicted past n / 2."""
 
     def __init__(self, nslots: int, m_max: int, n_max: int, l_max: int, dtype, seed: int = 0,
-                 hbm_budget: int = 1 << 40):
+                 hbm_budget: int = 1 << 40, gram_fallback: bool = False):
         import torch
         self.torch = torch
         code, self.dtype = _dtype_codes(torch)[dtype]
         h = ctypes.c_void_p()
+        flags = RSVD_SERVER_GRAM_FALLBACK if gram_fallback else 0
         _check(load_library().rsvd_server_create(ctypes.byref(h), nslots, m_max, n_max, l_max,
-                                                 code, seed, int(hbm_budget)),
+                                                 code, seed, int(hbm_budget), flags),
                "rsvd_server_create")
         self.handle = h.value
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -596,11 +603,14 @@ class Server:
         self._buf = (ctypes.c_int64 * 1024)()
 
     def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None, k_max: int = 0) -> int:
-        """Queue a request; with k_max > k its rank doubles (up to k_max)
-        while t is not reached, and U, S, V hold k_max columns."""
+        """Queue a request (A in fp32, bfloat16 or FP8 E4M3 with col_scale, or
+        fp64 on an fp64 server); with k_max > k its rank grows in blocks of
+        k + p columns until t can be met (or the A^T A route takes it), K is
+        capped at k_max, and U, S, V hold k_max columns."""
         torch = self.torch
         m, n = A.shape
         kc = max(k, k_max)
+        code = _dtype_codes(torch)[A.dtype][0]
         o = dict(U=torch.empty((m, kc), dtype=self.dtype, device=self.device),
                  V=torch.empty((n, kc), dtype=self.dtype, device=self.device),
                  S=torch.empty((kc,), dtype=torch.float64, device=self.device),
@@ -609,7 +619,7 @@ class Server:
         req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), o["U"].data_ptr(),
                            _ld(o["U"]), o["S"].data_ptr(), o["V"].data_ptr(), _ld(o["V"]),
                            o["K"].data_ptr(), o["status"].data_ptr(), _ptr(col_scale),
-                           int(k_max))
+                           int(k_max), code)
         o["col_scale"] = col_scale
         tk = ctypes.c_int64()
         _check(load_library().rsvd_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)),

@@ -683,4 +683,46 @@ hipError_t launch_quantize_fp8(const float* A, int64_t m, int64_t n, int64_t lda
   return hipGetLastError();
 }
 
+// A32 (m x n, ld lda32) = Aq diag(scale) (Aq bfloat16 or FP8 E4M3, one
+// thread per 8 consecutive elements of a row, widened as in the passes).
+template <int ES>
+__global__ void k_dequantize(const unsigned char* __restrict__ Aq, int64_t m, int64_t n,
+                             int64_t lda, const float* __restrict__ scale, float* __restrict__ A32,
+                             int64_t lda32) {
+  const int64_t g8 = (n + 7) / 8;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * g8) return;
+  const int64_t i = idx / g8, j0 = 8 * (idx - i * g8);
+  const unsigned char* row = Aq + i * lda * ES;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t j = j0 + e;
+    if (j >= n) break;
+    float v;
+    if (ES == 2) {
+      v = (float)reinterpret_cast<const __bf16*>(row)[j];
+    } else {
+      const int byte = row[j];
+      v = __builtin_amdgcn_cvt_pk_f32_fp8(byte, false)[0];
+    }
+    A32[i * lda32 + j] = scale ? v * scale[j] : v;
+  }
+}
+
+hipError_t launch_dequantize(const void* Aq, int es, int64_t m, int64_t n, int64_t lda,
+                             const float* scale, float* A32, int64_t lda32, hipStream_t s) {
+  if (m < 1 || n < 1) return hipSuccess;
+  const int64_t total = m * ((n + 7) / 8);
+  const unsigned char* Ab = static_cast<const unsigned char*>(Aq);
+  if (es == 2)
+    hipLaunchKernelGGL((k_dequantize<2>), dim3(nblocks(total, 256)), dim3(256), 0, s, Ab, m, n,
+                       lda, scale, A32, lda32);
+  else if (es == 1)
+    hipLaunchKernelGGL((k_dequantize<1>), dim3(nblocks(total, 256)), dim3(256), 0, s, Ab, m, n,
+                       lda, scale, A32, lda32);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace rsvd

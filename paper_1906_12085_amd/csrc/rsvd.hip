@@ -1403,13 +1403,21 @@ __global__ void k_status_take(const int32_t* __restrict__ src, int32_t* __restri
   if (threadIdx.x == 0) *dst = *src;
 }
 
+// The storage dtype of an instance's A on a slot plan: its own, or the plan's.
+int instance_dtype(const rsvd_plan_s* p, const rsvd_instance& x) {
+  return x.dtype ? x.dtype : p->dtype;
+}
+
 // Validate one instance for a slot plan (as rsvd_solve / rsvd_solve_bf16).
 int32_t check_instance(rsvd_plan_s* p, const rsvd_instance& x) {
   const int32_t rc = check_rsvd(p, x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, x.U, x.ldu, x.S,
                                 x.V, x.ldv, x.K);
   if (rc != RSVD_OK) return rc;
   if (!x.status) return RSVD_ERR_ARG;
-  if (const int es = lowp_es(p->dtype)) {
+  const int dt = instance_dtype(p, x);
+  if ((p->dtype == RSVD_F64) != (dt == RSVD_F64)) return RSVD_ERR_ARG;
+  if (dt != RSVD_F64 && dt != RSVD_F32 && !lowp_es(dt)) return RSVD_ERR_ARG;
+  if (const int es = lowp_es(dt)) {
     const int l = (int)((x.k + (int64_t)x.p < x.n) ? x.k + x.p : x.n);
     if (!bf16_pass_applies(x.A, es, x.n, x.lda, l)) return RSVD_ERR_ARG;
   }
@@ -1422,7 +1430,7 @@ int32_t run_instance(rsvd_plan_s* p, const rsvd_instance& x) {
   if (p->dtype == RSVD_F64) {
     rc = rsvd_run<double>(p, (const double*)x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr,
                           (double*)x.U, x.ldu, x.S, (double*)x.V, x.ldv, x.K);
-  } else if (const int es = lowp_es(p->dtype)) {
+  } else if (const int es = lowp_es(instance_dtype(p, x))) {
     const LowpA lp{x.A, x.col_scale, es};
     rc = rsvd_run<float>(p, nullptr, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, nullptr, (float*)x.U,
                          x.ldu, x.S, (float*)x.V, x.ldv, x.K, &lp);
@@ -1617,29 +1625,138 @@ int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph) {
 // ===========================================================================
 // Serving: requests queued in arrival order, admitted first come first
 // served onto free slots while their footprints fit the HBM budget, retired
-// by polling each busy slot's completion event.
+// by polling each busy slot's completion event.  A request with k_max > k
+// grows its basis block by block on its slot (the steps of
+// rsvd_solve_adaptive; after each block the captured energy decides: finish,
+// grow again, or, with the fallback, move to the A^T A-route slot).
 struct rsvd_server_s {
+  enum Phase { kIdle = 0, kPlain, kGrow, kFinish };
   struct Req {
-    rsvd_instance x;   // x.k: the rank of the next (or running) solve
+    rsvd_instance x;
     int64_t ticket = 0;
     int64_t bytes = 0;
+    GrowJob g;
+    double e_prev = 0.0;   // energy after the previous block
   };
   rsvd_batch_s* b = nullptr;
   int64_t budget = 0, in_use = 0, next_ticket = 0;
   std::deque<Req> queue;
   std::vector<int64_t> slot_ticket;   // -1: free
+  std::vector<int> slot_phase;
   std::vector<Req> slot_req;
   std::deque<int64_t> finished;
+  // A^T A-route slot (RSVD_SERVER_GRAM_FALLBACK)
+  rsvd_plan_s* gplan = nullptr;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gdone = nullptr;
+  float* gbuf = nullptr;   // fp32 copy of a bfloat16 / FP8 request's A
+  std::deque<Req> gqueue;
+  bool gbusy = false;
+  Req greq;
 };
 
 namespace {
 
 int64_t request_bytes(const rsvd_server_s* sv, const rsvd_instance& x) {
-  const int dt = sv->b->dtype;
+  const int dt = instance_dtype(sv->b->plan[0], x);
   const int64_t ea = dt == RSVD_F64 ? 8 : (lowp_es(dt) ? lowp_es(dt) : 4);   // A's elements
   const int64_t ep = dt == RSVD_F64 ? 8 : 4;                                  // the panels'
-  const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+  const int64_t l = (x.k_max > x.k) ? sv->b->plan[0]->l_max
+                                    : ((x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n);
   return x.m * x.lda * ea + 2 * x.m * l * ep + tn_max_split(x.m, x.n, (int)l) * x.n * l * 8;
+}
+
+bool grows(const rsvd_instance& x) { return x.k_max > x.k; }
+
+GrowJob grow_job(const rsvd_plan_s* p, const rsvd_instance& x) {
+  GrowJob g;
+  const int es = lowp_es(instance_dtype(p, x));
+  g.A = x.A; g.m = x.m; g.n = x.n; g.lda = x.lda;
+  g.lp = LowpA{es ? x.A : nullptr, x.col_scale, es};
+  g.b = (int)((x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n);
+  g.q = x.q; g.kcap = x.k_max; g.t = x.t;
+  g.U = x.U; g.ldu = x.ldu; g.S = x.S; g.V = x.V; g.ldv = x.ldv; g.K = x.K;
+  return g;
+}
+
+// The A^T A route for one request on the fallback slot: all n eigenpairs
+// (gram_run's steps), K over all n values capped at k_max, the first k_max
+// sorted triplets written to the request's U, S, V.
+template <typename T>
+int32_t gram_run_capped(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, double t,
+                        int kcap, T* U, int64_t ldu, double* S, T* V, int64_t ldv, int32_t* K) {
+  hipStream_t s = p->stream;
+  Path<T> P(p);
+  RSVD_CHECK(reset(p));
+  if (std::is_same<T, float>::value &&
+      syrk_f32_applies(reinterpret_cast<const float*>(A), n, lda)) {
+    RSVD_CHECK(launch_syrk_f32(reinterpret_cast<const float*>(A), m, n, lda, p->part,
+                               p->max_split * p->n_max * p_cmax(p), p->Gd, s));
+  } else {
+    RSVD_CHECK(P.tn(A, m, n, lda, A, lda, (int)n, p->Gd));
+  }
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, p->Gd, n, p->scal);
+  RSVD_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_init_eig, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, p->Gd, n,
+                     p->Xe, p->Je);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(launch_jacobi_eig(p->Xe, p->Je, n, p->lam, p->diag, p->flags, p->Es, p->status, s));
+  RSVD_CHECK(launch_sqrt_clamp(p->lam, (int)n, p->Se, s));
+  // all n values sorted (into Es, free after the eigensolver) and V in FP64
+  RSVD_CHECK(launch_sort_sign_scatter<T>(p->Se, (int)n, p->Je, n, 1, n, nullptr, (int)n, p->Es,
+                                         nullptr, 0, p->Vd, nullptr, s));
+  const int kc = (int)(kcap < n ? kcap : n);
+  hipLaunchKernelGGL((k_copy2d<double>), dim3(grid_for(kc)), dim3(256), 0, s, p->Es, (int64_t)kc,
+                     S, (int64_t)kc, (int64_t)1, kc);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(launch_cast_from_f64<T>(p->Vd, n, kc, n, V, ldv, s));
+  // u_i = A v_i / s_i for the first kc columns
+  const double floor_rel = (double)(m > n ? m : n) * 2.220446049250313e-16;
+  if (std::is_same<T, float>::value && kc > 128) {
+    RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, kc, n, p->Es, floor_rel, (T*)p->Xs, n, 1, s));
+    RSVD_CHECK(launch_gemm_nt_wide(reinterpret_cast<const float*>(A), m, n, lda,
+                                   reinterpret_cast<const float*>(p->Xs), n, kc,
+                                   reinterpret_cast<float*>(U), ldu, s));
+  } else {
+    RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, kc, n, p->Es, floor_rel, (T*)p->Xs, kc, 0, s));
+    RSVD_CHECK(launch_gemm_nn<T>(A, m, n, lda, (const T*)p->Xs, kc, kc, U, ldu, nullptr, nullptr,
+                                 s));
+  }
+  RSVD_CHECK(launch_select_k(p->Es, (int)n, p->scal, t, K, p->diag, p->status, s));
+  hipLaunchKernelGGL(k_cap_k, dim3(1), dim3(64), 0, s, K, kcap, p->status, p->diag);
+  RSVD_CHECK(hipGetLastError());
+  return RSVD_OK;
+}
+
+int32_t gram_admit(rsvd_server_s* sv) {
+  if (sv->gbusy || sv->gqueue.empty()) return RSVD_OK;
+  rsvd_server_s::Req r = sv->gqueue.front();
+  sv->gqueue.pop_front();
+  rsvd_plan_s* p = sv->gplan;
+  const rsvd_instance& x = r.x;
+  int32_t rc;
+  if (p->dtype == RSVD_F64) {
+    rc = gram_run_capped<double>(p, (const double*)x.A, x.m, x.n, x.lda, x.t, x.k_max,
+                                 (double*)x.U, x.ldu, x.S, (double*)x.V, x.ldv, x.K);
+  } else {
+    const float* A32 = (const float*)x.A;
+    int64_t lda = x.lda;
+    if (const int es = lowp_es(instance_dtype(sv->b->plan[0], x))) {
+      RSVD_CHECK(launch_dequantize(x.A, es, x.m, x.n, x.lda, x.col_scale, sv->gbuf, x.n,
+                                   sv->gstream));
+      A32 = sv->gbuf;
+      lda = x.n;
+    }
+    rc = gram_run_capped<float>(p, A32, x.m, x.n, lda, x.t, x.k_max, (float*)x.U, x.ldu, x.S,
+                                (float*)x.V, x.ldv, x.K);
+  }
+  if (rc != RSVD_OK) return rc;
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, sv->gstream, p->status, x.status);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(hipEventRecord(sv->gdone, sv->gstream));
+  sv->gbusy = true;
+  sv->greq = r;
+  return RSVD_OK;
 }
 
 // Admit from the head of the queue while a slot is free and the head fits
@@ -1650,10 +1767,19 @@ int32_t server_admit(rsvd_server_s* sv) {
     int s = -1;
     for (int i = 0; i < (int)sv->slot_ticket.size(); ++i)
       if (sv->slot_ticket[i] < 0) { s = i; break; }
-    if (s < 0) return RSVD_OK;
-    const rsvd_server_s::Req& r = sv->queue.front();
-    if (sv->in_use > 0 && sv->in_use + r.bytes > sv->budget) return RSVD_OK;
-    const int32_t rc = run_instance(b->plan[s], r.x);
+    if (s < 0) break;
+    rsvd_server_s::Req& r = sv->queue.front();
+    if (sv->in_use > 0 && sv->in_use + r.bytes > sv->budget) break;
+    int32_t rc;
+    if (grows(r.x)) {
+      r.g = grow_job(b->plan[s], r.x);
+      r.e_prev = 0.0;
+      rc = grow_block(b->plan[s], r.g);
+      sv->slot_phase[s] = rsvd_server_s::kGrow;
+    } else {
+      rc = run_instance(b->plan[s], r.x);
+      sv->slot_phase[s] = rsvd_server_s::kPlain;
+    }
     if (rc != RSVD_OK) return rc;
     RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
     sv->slot_ticket[s] = r.ticket;
@@ -1661,12 +1787,48 @@ int32_t server_admit(rsvd_server_s* sv) {
     sv->in_use += r.bytes;
     sv->queue.pop_front();
   }
+  return gram_admit(sv);
+}
+
+// After a block of a growing request on slot s: finish it, grow again, or
+// move it to the A^T A-route slot.
+int32_t grow_next(rsvd_server_s* sv, int s) {
+  rsvd_batch_s* b = sv->b;
+  rsvd_plan_s* p = b->plan[s];
+  rsvd_server_s::Req& r = sv->slot_req[s];
+  double f2 = 0.0, e = 0.0;
+  int32_t rc = grow_read(p, &f2, &e);   // the slot's stream is idle: returns at once
+  if (rc != RSVD_OK) return rc;
+  const double need = r.x.t * f2;
+  const bool fits = grow_fits(p, r.g);
+  if (e < need) {
+    // K predicted from the energy per column of the last block (a lower
+    // estimate: later columns capture less on a decaying spectrum)
+    const double per_col = (e - r.e_prev) / r.g.b;
+    const double kpred = per_col > 0.0 ? r.g.L + (need - e) / per_col : 1e300;
+    if (sv->gplan && r.x.n <= sv->gplan->n_max && (kpred > 0.5 * r.x.n || !fits)) {
+      sv->slot_ticket[s] = -1;
+      sv->slot_phase[s] = rsvd_server_s::kIdle;
+      sv->gqueue.push_back(r);   // its bytes stay counted until it is done
+      return RSVD_OK;
+    }
+    if (fits) {
+      r.e_prev = e;
+      if ((rc = grow_block(p, r.g)) != RSVD_OK) return rc;
+      RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
+      return RSVD_OK;
+    }
+  }
+  if ((rc = grow_finish(p, r.g)) != RSVD_OK) return rc;
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, p->stream, p->status, r.x.status);
+  RSVD_CHECK(hipGetLastError());
+  RSVD_CHECK(hipEventRecord(b->done[s], b->stream[s]));
+  sv->slot_phase[s] = rsvd_server_s::kFinish;
   return RSVD_OK;
 }
 
-// Retire the busy slots whose completion event has fired; a request with
-// rank to spare whose solve did not reach t goes back to the head of the
-// queue with twice the rank.
+// Retire the busy slots whose completion event has fired (a growing
+// request takes its next step instead), and the A^T A-route slot.
 int32_t server_retire(rsvd_server_s* sv, bool wait) {
   rsvd_batch_s* b = sv->b;
   for (int s = 0; s < (int)sv->slot_ticket.size(); ++s) {
@@ -1674,23 +1836,26 @@ int32_t server_retire(rsvd_server_s* sv, bool wait) {
     const hipError_t e = wait ? hipEventSynchronize(b->done[s]) : hipEventQuery(b->done[s]);
     if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) return RSVD_ERR_DEVICE;
-    rsvd_server_s::Req r = sv->slot_req[s];
+    if (sv->slot_phase[s] == rsvd_server_s::kGrow) {
+      const int32_t rc = grow_next(sv, s);
+      if (rc != RSVD_OK) return rc;
+      continue;
+    }
+    const rsvd_server_s::Req& r = sv->slot_req[s];
     sv->in_use -= r.bytes;
     sv->slot_ticket[s] = -1;
-    if (r.x.k_max > r.x.k) {
-      int32_t st = RSVD_OK;   // the slot's stream is idle: this copy returns at once
-      if (hipMemcpyAsync(&st, r.x.status, sizeof(st), hipMemcpyDeviceToHost, b->stream[s]) !=
-              hipSuccess ||
-          hipStreamSynchronize(b->stream[s]) != hipSuccess)
-        return RSVD_ERR_DEVICE;
-      if (st == RSVD_WARN_THRESHOLD) {
-        r.x.k = (r.x.k * 2 < r.x.k_max) ? r.x.k * 2 : r.x.k_max;
-        r.bytes = request_bytes(sv, r.x);
-        sv->queue.push_front(r);
-        continue;
-      }
-    }
+    sv->slot_phase[s] = rsvd_server_s::kIdle;
     sv->finished.push_back(r.ticket);
+  }
+  if (sv->gbusy) {
+    const hipError_t e = wait ? hipEventSynchronize(sv->gdone) : hipEventQuery(sv->gdone);
+    if (e == hipSuccess) {
+      sv->gbusy = false;
+      sv->in_use -= sv->greq.bytes;
+      sv->finished.push_back(sv->greq.ticket);
+    } else if (e != hipErrorNotReady) {
+      return RSVD_ERR_DEVICE;
+    }
   }
   return RSVD_OK;
 }
@@ -1698,7 +1863,16 @@ int32_t server_retire(rsvd_server_s* sv, bool wait) {
 int32_t server_running(const rsvd_server_s* sv) {
   int32_t r = 0;
   for (int64_t t : sv->slot_ticket) r += t >= 0;
-  return r;
+  return r + (sv->gbusy ? 1 : 0);
+}
+
+void server_free(rsvd_server_s* sv) {
+  if (sv->b) batch_free(sv->b);
+  if (sv->gplan) rsvd_plan_destroy(sv->gplan);
+  if (sv->gbuf) (void)hipFree(sv->gbuf);
+  if (sv->gdone) (void)hipEventDestroy(sv->gdone);
+  if (sv->gstream) (void)hipStreamDestroy(sv->gstream);
+  delete sv;
 }
 
 }  // namespace
@@ -1706,12 +1880,15 @@ int32_t server_running(const rsvd_server_s* sv) {
 extern "C" {
 
 int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max, int64_t n_max,
-                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget) {
+                           int32_t l_max, int32_t dtype, uint64_t seed, int64_t hbm_budget,
+                           int32_t flags) {
   if (!server) return RSVD_ERR_ARG;
   *server = nullptr;
-  if (hbm_budget < 1) return RSVD_ERR_ARG;
+  if (hbm_budget < 1 || (flags & ~RSVD_SERVER_GRAM_FALLBACK)) return RSVD_ERR_ARG;
+  const bool fallback = (flags & RSVD_SERVER_GRAM_FALLBACK) != 0;
+  if (fallback && n_max > jacobi_eig_max_n()) return RSVD_ERR_SHAPE;
   rsvd_batch_t b = nullptr;
-  const int32_t rc = rsvd_batch_create(&b, nslots, m_max, n_max, l_max, dtype, seed);
+  int32_t rc = rsvd_batch_create(&b, nslots, m_max, n_max, l_max, dtype, seed);
   if (rc != RSVD_OK) return rc;
   rsvd_server_s* sv = new (std::nothrow) rsvd_server_s();
   if (!sv) {
@@ -1721,7 +1898,30 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
   sv->b = b;
   sv->budget = hbm_budget;
   sv->slot_ticket.assign(nslots, -1);
+  sv->slot_phase.assign(nslots, rsvd_server_s::kIdle);
   sv->slot_req.assign(nslots, rsvd_server_s::Req());
+  if (fallback) {
+    if (hipStreamCreateWithFlags(&sv->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->gdone, hipEventDisableTiming) != hipSuccess) {
+      server_free(sv);
+      return RSVD_ERR_DEVICE;
+    }
+    const int gdt = dtype == RSVD_F64 ? RSVD_F64 : RSVD_F32;
+    const int32_t gl = (int32_t)(n_max < 8 ? n_max : 8);
+    if ((rc = rsvd_plan_create(&sv->gplan, m_max, n_max, gl, gdt, 1, seed, sv->gstream)) !=
+        RSVD_OK) {
+      sv->gplan = nullptr;
+      server_free(sv);
+      return rc;
+    }
+    if (gdt == RSVD_F32 &&
+        hipMalloc(&sv->gbuf, (size_t)m_max * (size_t)n_max * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      sv->gbuf = nullptr;
+      server_free(sv);
+      return RSVD_ERR_NOMEM;
+    }
+  }
   *server = sv;
   return RSVD_OK;
 }
@@ -1729,12 +1929,13 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
 int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64_t* ticket) {
   if (!server || !req || !ticket) return RSVD_ERR_ARG;
   const rsvd_instance& x = *req;
-  int32_t rc = check_instance(server->b->plan[0], x);
+  rsvd_plan_s* p0 = server->b->plan[0];
+  int32_t rc = check_instance(p0, x);
   if (rc != RSVD_OK) return rc;
-  if (x.k_max > x.k) {   // every rank the request may grow to must fit
-    rsvd_instance y = x;
-    y.k = x.k_max;
-    if ((rc = check_instance(server->b->plan[0], y)) != RSVD_OK) return rc;
+  if (grows(x)) {   // outputs for k_max columns; two row-padded blocks within l_max
+    if (x.k_max > x.n || x.ldu < x.k_max || x.ldv < x.k_max) return RSVD_ERR_ARG;
+    const int64_t bw = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+    if (2 * ldq1_of(bw) > p0->l_max) return RSVD_ERR_SHAPE;
   }
   if (hipSetDevice(server->b->device) != hipSuccess) return RSVD_ERR_DEVICE;
   rsvd_server_s::Req r;
@@ -1757,7 +1958,7 @@ int32_t rsvd_server_progress(rsvd_server_t server, int64_t* done, int32_t cap, i
     done[(*ndone)++] = server->finished.front();
     server->finished.pop_front();
   }
-  if (queued) *queued = (int32_t)server->queue.size();
+  if (queued) *queued = (int32_t)(server->queue.size() + server->gqueue.size());
   if (running) *running = server_running(server);
   return rc;
 }
@@ -1766,12 +1967,12 @@ int32_t rsvd_server_destroy(rsvd_server_t server) {
   if (!server) return RSVD_OK;
   int32_t rc = RSVD_OK;
   if (hipSetDevice(server->b->device) != hipSuccess) rc = RSVD_ERR_DEVICE;
-  while (rc == RSVD_OK && (!server->queue.empty() || server_running(server) > 0)) {
+  while (rc == RSVD_OK && (!server->queue.empty() || !server->gqueue.empty() ||
+                           server_running(server) > 0)) {
     rc = server_retire(server, true);
     if (rc == RSVD_OK) rc = server_admit(server);
   }
-  batch_free(server->b);
-  delete server;
+  server_free(server);
   return rc;
 }
 
@@ -2141,6 +2342,7 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(batch->plan[0], inst[i]);
     if (rc != RSVD_OK) return rc;
+    if (instance_dtype(batch->plan[0], inst[i]) != RSVD_F32) return RSVD_ERR_ARG;
     if (!grouped_applies(inst[i], batch->plan[0]->max_split)) return RSVD_ERR_ARG;
   }
   if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;

@@ -236,6 +236,11 @@ hipError_t launch_gemm_tn_bf16(const void* A, int es, int64_t m, int64_t n, int6
                                const float* Q, int64_t ldq, int c, double* P, int64_t max_split,
                                int* nsplit, hipStream_t s);
 
+// A32 (m x n, ld lda32, fp32) = Aq diag(scale) for A stored in bfloat16
+// (es = 2) or FP8 E4M3 (es = 1); scale may be null (ones).
+hipError_t launch_dequantize(const void* Aq, int es, int64_t m, int64_t n, int64_t lda,
+                             const float* scale, float* A32, int64_t lda32, hipStream_t s);
+
 // Shifted CholeskyQR's diagonal shift on the c x c Gram W of an m x c matrix:
 // W += 11 (m c + c (c+1)) 2^-53 trace(W) I (one block).
 hipError_t launch_shift_diag(double* W, int c, int64_t m, hipStream_t s);

@@ -59,8 +59,13 @@ int main() {
   EXPECT(rsvd_batch_create(&b, 65, 1000, 100, 16, RSVD_F32, 0) == RSVD_ERR_ARG);
   EXPECT(rsvd_batch_solve(nullptr, nullptr, 0, nullptr) == RSVD_ERR_ARG);
   rsvd_server_t sv = nullptr;
-  EXPECT(rsvd_server_create(nullptr, 2, 1000, 100, 16, RSVD_F32, 0, 1 << 30) == RSVD_ERR_ARG);
-  EXPECT(rsvd_server_create(&sv, 2, 1000, 100, 16, RSVD_F32, 0, 0) == RSVD_ERR_ARG);
+  EXPECT(rsvd_server_create(nullptr, 2, 1000, 100, 16, RSVD_F32, 0, 1 << 30, 0) == RSVD_ERR_ARG);
+  EXPECT(rsvd_server_create(&sv, 2, 1000, 100, 16, RSVD_F32, 0, 0, 0) == RSVD_ERR_ARG);
+  EXPECT(rsvd_server_create(&sv, 2, 1000, 100, 16, RSVD_F32, 0, 1 << 30, 6) == RSVD_ERR_ARG);
+  EXPECT(rsvd_server_create(&sv, 2, 5000, 2000, 16, RSVD_F32, 0, 1 << 30,
+                            RSVD_SERVER_GRAM_FALLBACK) == RSVD_ERR_SHAPE);
+  EXPECT(rsvd_solve_adaptive(nullptr, a, 100, 10, 10, nullptr, 2, 2, 1, 0.9, 4, a, 4, d, a, 4,
+                             k32) == RSVD_ERR_ARG);
   EXPECT(rsvd_server_submit(nullptr, nullptr, nullptr) == RSVD_ERR_ARG);
   EXPECT(rsvd_server_destroy(nullptr) == RSVD_OK);
   EXPECT(rsvd_batch_destroy(nullptr) == RSVD_OK);

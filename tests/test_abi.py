@@ -66,9 +66,11 @@ def test_plan_create_validates_before_device_calls(lib):
     assert b(ctypes.byref(h), 65, 1000, 100, 16, 1, 0) == -1              # too many slots
     assert b(ctypes.byref(h), 2, 1000, 100, 16, 4, 0) == -1               # unknown dtype
     sv = lib.rsvd_server_create
-    assert sv(None, 2, 1000, 100, 16, 1, 0, 1 << 30) == -1                # server NULL
-    assert sv(ctypes.byref(h), 2, 1000, 100, 16, 1, 0, 0) == -1           # no budget
-    assert sv(ctypes.byref(h), 0, 1000, 100, 16, 1, 0, 1 << 30) == -1     # no slots
+    assert sv(None, 2, 1000, 100, 16, 1, 0, 1 << 30, 0) == -1             # server NULL
+    assert sv(ctypes.byref(h), 2, 1000, 100, 16, 1, 0, 0, 0) == -1        # no budget
+    assert sv(ctypes.byref(h), 0, 1000, 100, 16, 1, 0, 1 << 30, 0) == -1  # no slots
+    assert sv(ctypes.byref(h), 2, 1000, 100, 16, 1, 0, 1 << 30, 4) == -1  # unknown flag
+    assert sv(ctypes.byref(h), 2, 5000, 2000, 16, 1, 0, 1 << 30, 1) == -2  # fallback n_max > 1024
     assert h.value is None
 
 
@@ -88,6 +90,8 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_solve_fp8(None, a, None, 100, 16, 16, 4, 2, 1, 0.9, None, a, 4, a, a, 4, a) == -1
     assert lib.rsvd_quantize_fp8(None, a, 100, 16, 16, a, 16, a) == -1
     assert lib.rsvd_solve_krylov(None, a, 100, 10, 10, 2, 2, 1, 0.9, None, a, 2, a, a, 2, a) == -1
+    assert lib.rsvd_solve_adaptive(None, a, 100, 10, 10, None, 2, 2, 1, 0.9, 4, a, 4, a, a, 4,
+                                   a) == -1
     assert lib.rsvd_batch_solve(None, None, 0, None) == -1
     assert lib.rsvd_batch_graph_create(None, None, 0, None, None) == -1
     assert lib.rsvd_batch_graph_launch(None, None) == -1

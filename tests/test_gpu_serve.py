@@ -178,11 +178,12 @@ def test_serve_low_precision_same_alone_and_oracle(fmt):
 
 
 def test_serve_adaptive_rank():
-    # with k_max the rank doubles while t is not reached: the result equals
-    # the solo solve at the first rank of k, 2k, 4k, ... (capped at k_max)
-    # that reaches t, or at k_max
+    # with k_max the rank grows in blocks of k + p columns while t is not
+    # reached: each result equals rsvd_solve_adaptive alone on a plan of the
+    # same sizes and seed (bit for bit) and the oracle's blocked routine on
+    # the same block sketches
     dt = torch.float32
-    announce("serve: adaptive rank, 6 requests, k = 4 growing to at most 32")
+    announce("serve: adaptive rank, 6 requests, blocks of 12 growing up to k_max = 32")
     reqs = requests(dt, 6, 23)
     sv = rs.Server(3, M_MAX, N_MAX, L_MAX, dt, seed=SEED)
     pending, seen, tickets = set(), [], []
@@ -193,19 +194,110 @@ def test_serve_adaptive_rank():
     drain(sv, pending, seen)
     alone = rs.Plan(M_MAX, N_MAX, L_MAX, dt, seed=SEED)
     grew = 0
+    step = 0x9E3779B97F4A7C15
     for tk, (A, _, p, q, t, A0) in zip(tickets, reqs):
         n = A.shape[1]
-        k = 4
-        while True:
-            ref = alone.solve(A, k, p, q, t)
-            if ref.status != rs.RSVD_WARN_THRESHOLD or k >= 32:
-                break
-            k = min(2 * k, 32)
-        grew += k > 4
+        ref = alone.solve_adaptive(A, 4, p, q, t, 32)
+        L = int(alone.diag()[6])
+        grew += L > 4 + p
         o = sv.results[tk]
+        kc = min(32, L)
         assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
-        assert torch.equal(o["S"][:k], ref.S) and torch.equal(o["V"][:, :k], ref.V)
-        assert torch.equal(o["U"][:, :k], ref.U)
+        assert torch.equal(o["S"][:kc], ref.S[:kc]) and torch.equal(o["V"][:, :kc], ref.V[:, :kc])
+        assert torch.equal(o["U"][:, :kc], ref.U[:, :kc])
+        b = min(4 + p, n)
+        G = np.concatenate([synth.gaussian_omega((SEED + j * step) % (1 << 64), n, b)
+                            for j in range(L_MAX // b)], axis=1)
+        orc = oracle.rsvd_blocked(A0, rounded(G, dt), b, q, t, L_MAX, 32)
+        assert orc.L == L
+        assert np.max(np.abs(host(o["S"])[:kc] - orc.S) / orc.S) <= 1e-4
+        assert oracle.principal_angle_max(orc.V, host(o["V"])[:, :kc]) <= 1e-3
+        assert int(o["K"].item()) == orc.K and int(o["status"].item()) == orc.status
     assert grew >= 2                            # the case is exercised
     alone.close()
+    sv.close()
+
+
+def test_serve_mixed_storage():
+    # one fp32 server, requests alternating fp32 and bfloat16 / FP8 storage:
+    # every result equals the solve alone on a plan of that storage with the
+    # same sizes and seed, bit for bit
+    announce("serve: 9 requests, fp32 / bf16 / fp8 storage on one server")
+    reqs = requests(torch.float32, 9, 41)
+    plans = {fmt: rs.Plan(M_MAX, N_MAX, L_MAX, fmt, seed=SEED)
+             for fmt in (torch.float32, torch.bfloat16, torch.float8_e4m3fn)}
+    sv = rs.Server(3, M_MAX, N_MAX, L_MAX, torch.float32, seed=SEED)
+    pending, seen, sub = set(), [], []
+    fmts = [torch.float32, torch.bfloat16, torch.float8_e4m3fn]
+    for i, (A, k, p, q, t, _) in enumerate(reqs):
+        fmt = fmts[i % 3]
+        if fmt == torch.float32:
+            Aq, s = A, None
+        else:
+            Aq, s = plans[fmt].quantize(A)
+            torch.cuda.synchronize()
+        tk = sv.submit(Aq, k, p, q, t, col_scale=s)
+        sub.append((tk, fmt, Aq, s, k, p, q, t))
+        pending.add(tk)
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    assert max(seen) > 1
+    for tk, fmt, Aq, s, k, p, q, t in sub:
+        o = sv.results[tk]
+        ref = plans[fmt].solve(Aq, k, p, q, t, col_scale=s)
+        assert torch.equal(o["S"], ref.S) and torch.equal(o["U"], ref.U)
+        assert torch.equal(o["V"], ref.V)
+        assert int(o["K"].item()) == ref.K and int(o["status"].item()) == ref.status
+    for pl in plans.values():
+        pl.close()
+    sv.close()
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_serve_gram_fallback(fmt):
+    # slow decay (sigma_i = i^-0.5) at t = 0.99 needs K ~ 0.9 n: the growth
+    # predicts K past n / 2 (or fills the 40-column sketch) and the request
+    # moves to the A^T A-route slot, whose result equals gram_eig_solve alone
+    # (the first k_max = n triplets; a bfloat16 A dequantised); fast decay
+    # (i^-2, t = 0.9) finishes on its slot.  No request ends short of t.
+    announce(f"serve: A^T A fallback, {fmt} storage")
+    rng = np.random.default_rng(61)
+    sv = rs.Server(2, M_MAX, N_MAX, L_MAX, torch.float32, seed=SEED, gram_fallback=True)
+    quant = rs.Plan(M_MAX, N_MAX, L_MAX, torch.bfloat16, seed=SEED)
+    gram = rs.Plan(M_MAX, N_MAX, 8, torch.float32, want_gram=True, seed=SEED)
+    alone = rs.Plan(M_MAX, N_MAX, L_MAX, torch.float32, seed=SEED)
+    pending, seen, sub = set(), [], []
+    for i, (alpha, t) in enumerate([(0.5, 0.99), (2.0, 0.9), (0.5, 0.99), (1.5, 0.95)]):
+        m, n = 4096 + 1024 * i, 128
+        sig = np.arange(1, n + 1, dtype=np.float64) ** -alpha
+        A0 = synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T
+        A = dev(A0.astype(np.float32), torch.float32)
+        if fmt == "bf16":
+            Aq, s = quant.quantize(A)
+            torch.cuda.synchronize()
+            A32 = (Aq.float() * s[None, :]).contiguous()
+        else:
+            Aq, s, A32 = A, None, A
+        tk = sv.submit(Aq, 4, 8, 2, t, col_scale=s, k_max=n)
+        sub.append((tk, alpha, t, Aq, s, A32))
+        pending.add(tk)
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    for tk, alpha, t, Aq, s, A32 in sub:
+        o = sv.results[tk]
+        n = Aq.shape[1]
+        assert int(o["status"].item()) == rs.RSVD_OK
+        if alpha == 0.5:
+            ref = gram.gram_eig(A32, t, ucols=n)
+            assert int(o["K"].item()) == ref.K > n // 2
+            assert torch.equal(o["S"], ref.S[:n]) and torch.equal(o["V"], ref.V[:, :n])
+            assert torch.equal(o["U"], ref.U)
+        else:
+            ref = alone.solve_adaptive(Aq, 4, 8, 2, t, n) if s is None else None
+            if ref is not None:
+                L = int(alone.diag()[6])
+                assert int(o["K"].item()) == ref.K <= L
+                assert torch.equal(o["S"][:L], ref.S[:L]) and torch.equal(o["V"][:, :L], ref.V[:, :L])
+    for pl in (quant, gram, alone):
+        pl.close()
     sv.close()

@@ -37,6 +37,8 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 KRYLOV = (64, 16, 1)
 # slots of the batched leg
 BATCH_SLOTS = 8
+# requests a serving client keeps in the server at once
+MAX_OUTSTANDING = 256
 
 
 def parse():
@@ -57,6 +59,8 @@ def parse():
                     help="skip the FP64 2000 x 200 latency leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving leg (Poisson arrivals, continuous batching)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving leg's Poisson stream (the workload's 60 s)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven fp32 instances)")
     ap.add_argument("--no-mixed", action="store_true",
@@ -470,109 +474,128 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
             "status_counts": statuses}
 
 
-def serve_leg(rs, torch, dev, nslots, storage=None):
-    """The serving workload: Poisson arrivals (200 requests/s for 8 s) of
-    Randomized PCA requests on a pool of device-resident matrices of uneven
-    shapes, each with its own threshold t, served by one rsvd_server
-    (continuous batching on nslots slots), with A in fp32 or (storage) in
-    bfloat16 / FP8 E4M3 with power-of-two column scales.  Latency is taken
-    on the host from a request's arrival time to the progress() call that
-    reports it done; the outputs of finished requests are released as they
-    are reported.  Then the same request sequence with arrival times ignored
-    and 32 requests kept outstanding: the server's capacity in solves/s."""
+def serve_leg(rs, torch, dev, nslots, seconds):
+    """The serving workload: Poisson arrivals (200 requests/s for `seconds`)
+    of PCA requests on a pool of device-resident matrices of uneven shapes,
+    each request with its own threshold t and its own storage (fp32 or
+    bfloat16 with power-of-two column scales, 50/50), all served by one
+    rsvd_server (continuous batching on nslots slots, HBM-budget admission)
+    with adaptive rank: the basis grows in blocks of k + p columns until t
+    can be met, and a request whose K is predicted past n / 2 (or past the
+    sketch) goes to the server's A^T A-route slot; every request holds
+    k_max = n output columns, so none needs to stop short of t.  Latency is
+    taken on the host from a request's arrival time to the progress() call
+    that reports it done; outputs are released as they are reported.  Then
+    capacity: the first 2000 requests back to back with 32 outstanding, as
+    they are (mixed), all in fp32 and all in bfloat16, and the agreement of K
+    between the fp32 and bfloat16 runs."""
     import synth
-    c = synth.CONFIG5
+    c = dict(synth.CONFIG5)
+    c["seconds"] = seconds
     pool = synth.serve_pool(c)
     mmax = max(m for m, _, _ in pool)
     nmax = max(n for _, n, _ in pool)
-    l = c["k_max"] + c["p"]
-    mats, scales = [], []
-    quant = rs.Plan(mmax, nmax, l, storage, seed=c["seed"]) if storage is not None else None
+    mats = {"fp32": [], "bf16": []}
+    quant = rs.Plan(mmax, nmax, 8, torch.bfloat16, seed=c["seed"])
     for i, (m, n, a) in enumerate(pool):
         A = synth.spiked_noisy_torch(c["seed"] * 7919 + i, m, n, synth.power_sigma(n, a), 0.0, dev,
                                      torch.float32)
-        if quant is not None:
-            Aq, sc = quant.quantize(A)
-            torch.cuda.synchronize()
-            del A
-            mats.append(Aq)
-            scales.append(sc)
-        else:
-            mats.append(A)
-            scales.append(None)
-    if quant is not None:
-        quant.close()
+        Aq, sc = quant.quantize(A)
+        torch.cuda.synchronize()
+        mats["fp32"].append((A, None))
+        mats["bf16"].append((Aq, sc))
+    quant.close()
     torch.cuda.synchronize()
     arrivals = synth.serve_arrivals(c)
-    sv = rs.Server(nslots, mmax, nmax, l, storage if storage is not None else torch.float32,
-                   seed=c["seed"], hbm_budget=64 << 30)
+    sv = rs.Server(nslots, mmax, nmax, c["l_max"], torch.float32, seed=c["seed"],
+                   hbm_budget=64 << 30, gram_fallback=True)
 
-    def submit(j, t):
-        # adaptive rank: k doubles from k up to k_max while t is not reached
-        return sv.submit(mats[j], c["k"], c["p"], c["q"], t, col_scale=scales[j],
-                         k_max=c["k_max"])
+    def submit(j, t, storage):
+        # a request asks for the principal directions V, their singular
+        # values and K (no scores U), for every component it may need
+        A, sc = mats[storage][j]
+        return sv.submit(A, c["k"], c["p"], c["q"], t, col_scale=sc, k_max=pool[j][1],
+                         want_u=False)
+
+    def drain_all(outstanding, keep_k=None):
+        done, _, _ = sv.progress()
+        for tk in done:
+            outstanding.discard(tk)
+            o = sv.results.pop(tk)
+            if keep_k is not None:
+                keep_k[tk] = int(o["K"].item())
 
     for j in range(2):                                   # warm-up, not timed
-        submit(j, 0.95)
+        submit(j, 0.95, "fp32")
     pend = {0, 1}
     while pend:
-        for tk in sv.progress()[0]:
-            pend.discard(tk)
-            sv.results.pop(tk, None)
-    lat, flops, statuses, max_q, max_r = [], 0.0, {}, 0, 0
-    pending, Ks = {}, {}
+        drain_all(pend)
+    lat, statuses, max_q, max_r = [], {}, 0, 0
+    pending, Ks, big = {}, {}, 0
     i, nreq = 0, len(arrivals)
     t0 = time.perf_counter()
     while i < nreq or pending:
         now = time.perf_counter() - t0
-        while i < nreq and arrivals[i][0] <= now:
-            at, j, t = arrivals[i]
-            m, n, _ = pool[j]
-            pending[submit(j, t)] = (at, m, n, i)
+        # at most MAX_OUTSTANDING requests in the server: later arrivals wait
+        # at the client (their latency still counts from their arrival)
+        while i < nreq and arrivals[i][0] <= now and len(pending) < MAX_OUTSTANDING:
+            at, j, t, storage = arrivals[i]
+            pending[submit(j, t, storage)] = (at, j, i)
             i += 1
         done, queued, running = sv.progress()
         max_q, max_r = max(max_q, queued), max(max_r, running)
         if done:
             now = time.perf_counter() - t0
             for tk in done:
-                at, m, n, idx = pending.pop(tk)
+                at, j, idx = pending.pop(tk)
                 lat.append(1e3 * (now - at))
                 o = sv.results.pop(tk)
                 Ks[idx] = int(o["K"].item())
+                big += Ks[idx] > pool[j][1] // 2
                 st = rs.STATUS.get(int(o["status"].item()), int(o["status"].item()))
                 statuses[st] = statuses.get(st, 0) + 1
-                kk = min(max(c["k"], Ks[idx]), c["k_max"], n)
-                f, _, _, _ = algorithmic_counts(m, n, kk, min(kk + c["p"], n), c["q"], 4)
-                flops += f
     wall = time.perf_counter() - t0
-    # capacity: the same requests back to back, 32 outstanding
-    i, outstanding = 0, set()
-    t1 = time.perf_counter()
-    while i < nreq or outstanding:
-        while i < nreq and len(outstanding) < 32:
-            _, j, t = arrivals[i]
-            outstanding.add(submit(j, t))
-            i += 1
-        for tk in sv.progress()[0]:
-            outstanding.discard(tk)
-            sv.results.pop(tk, None)
-    cap_s = time.perf_counter() - t1
+
+    def capacity(reqs, storage=None):
+        k_of, out, nxt, order = {}, set(), 0, {}
+        t1 = time.perf_counter()
+        while nxt < len(reqs) or out:
+            while nxt < len(reqs) and len(out) < 32:
+                _, j, t, st = reqs[nxt]
+                tk = submit(j, t, storage or st)
+                out.add(tk)
+                order[tk] = nxt
+                nxt += 1
+            drain_all(out, k_of)
+        sec = time.perf_counter() - t1
+        return len(reqs) / sec, {order[tk]: K for tk, K in k_of.items()}
+
+    sub = arrivals[:2000]
+    cap_mixed, _ = capacity(sub)
+    cap32, k32 = capacity(sub, "fp32")
+    cap16, k16 = capacity(sub, "bf16")
     sv.close()
-    del mats, scales
+    del mats
     torch.cuda.empty_cache()
-    name = {None: "fp32", torch.bfloat16: "bf16", torch.float8_e4m3fn: "fp8 e4m3"}[storage]
-    return {"storage": name, "requests": nreq, "offered_rate_per_s": c["rate"], "slots": nslots,
+    agree = sum(k32[i] == k16[i] for i in k32) / max(1, len(k32))
+    return {"storage": "fp32 and bf16 requests (50/50) on one server", "requests": nreq,
+            "seconds": seconds, "offered_rate_per_s": c["rate"], "slots": nslots,
             "solves_per_s": round(nreq / wall, 1), "wall_s": round(wall, 2),
             "latency_ms": {"p50": round(pct(lat, 50), 2), "p99": round(pct(lat, 99), 2),
                            "max": round(max(lat), 2)},
-            "capacity_solves_per_s": round(nreq / cap_s, 1),
-            "tflops_at_final_rank": round(flops / wall / 1e12, 2), "max_queued": max_q,
-            "max_running": max_r,
+            "capacity_solves_per_s": {"mixed": round(cap_mixed, 1), "fp32": round(cap32, 1),
+                                      "bf16": round(cap16, 1), "requests": len(sub),
+                                      "outstanding": 32},
+            "client_max_outstanding": MAX_OUTSTANDING,
+            "bf16_over_fp32_capacity": round(cap16 / cap32, 3),
+            "K_bf16_equals_fp32": round(agree, 4),
+            "max_queued": max_q, "max_running": max_r,
             "pool": {"matrices": len(pool), "m_range": [min(m for m, _, _ in pool), mmax],
                      "n_set": sorted({n for _, n, _ in pool})},
             "status_counts": statuses, "K_mean": round(sum(Ks.values()) / max(1, nreq), 2),
-            "rank": {"k_start": c["k"], "k_max": c["k_max"]},
-            "_K": [Ks[i] for i in range(nreq)]}
+            "K_past_half_n": big,
+            "rank": {"k_start": c["k"], "block": c["k"] + c["p"], "sketch_max": c["l_max"],
+                     "k_max": "n", "fallback": "A^T A route when K is predicted past n/2"}}
 
 
 def pct(xs, p):
@@ -942,13 +965,9 @@ def main():
         legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
 
     if not args.no_serve:
-        print("[bench] serving legs (fp32, bf16): Poisson arrivals at 200/s for 8 s, then "
-              "capacity", file=sys.stderr, flush=True)
-        legs["serve"] = serve_leg(rs, torch, dev, BATCH_SLOTS)
-        legs["serve_bf16"] = serve_leg(rs, torch, dev, BATCH_SLOTS, torch.bfloat16)
-        k32, k16 = legs["serve"].pop("_K"), legs["serve_bf16"].pop("_K")
-        legs["serve_bf16"]["K_equals_fp32_serving"] = round(
-            sum(a == b for a, b in zip(k32, k16)) / max(1, len(k32)), 4)
+        print(f"[bench] serving leg: Poisson arrivals at 200/s for {args.serve_seconds:g} s "
+              "(fp32 and bf16 requests), then capacity", file=sys.stderr, flush=True)
+        legs["serve"] = serve_leg(rs, torch, dev, BATCH_SLOTS, args.serve_seconds)
 
     plan.close()
     cpu = None

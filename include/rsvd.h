@@ -345,7 +345,9 @@ typedef struct rsvd_batch_s* rsvd_batch_t;
 typedef struct rsvd_batch_graph_s* rsvd_batch_graph_t;
 
 /* One problem of a batch: arguments as rsvd_solve (device pointers A, U, S,
- * V, K), plus `status` (1 int32, device) that receives the instance's status
+ * V, K; U may be NULL for a problem that needs only S, V and K -- the
+ * principal directions and their variances -- and then costs no U product;
+ * grouped batches need U), plus `status` (1 int32, device) that receives the instance's status
  * word (RSVD_OK, RSVD_WARN_*, RSVD_ERR_BREAKDOWN / _NONFINITE / _NOCONV), and
  * for RSVD_BF16 / RSVD_FP8 batches and servers `col_scale` (n floats, device,
  * or NULL for unit scales) as in rsvd_solve_bf16; ignored otherwise.
@@ -461,9 +463,9 @@ typedef struct rsvd_server_s* rsvd_server_t;
  * requests whose own `dtype` is another of those three) up to m_max x n_max
  * with k + p <= l_max, admitting while the running requests' footprints sum
  * to at most hbm_budget bytes (a request larger than the budget runs alone).
- * flags: RSVD_SERVER_GRAM_FALLBACK adds one A^T A-route slot (a plan sized
- * m_max x n_max for gram_eig_solve, n_max <= 1024, its own stream, and for
- * non-FP64 servers an m_max x n_max fp32 buffer into which a bfloat16 /
+ * flags: RSVD_SERVER_GRAM_FALLBACK adds two A^T A-route slots (each a plan
+ * sized m_max x n_max for gram_eig_solve, n_max <= 1024, its own stream, and
+ * for non-FP64 servers an m_max x n_max fp32 buffer into which a bfloat16 /
  * FP8 request's A is dequantised): a request with k_max > k whose growth
  * predicts K > n / 2 (from the energy its last block captured per column,
  * a lower estimate on a decaying spectrum) or finds the sketch full below t

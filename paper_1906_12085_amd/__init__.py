@@ -602,22 +602,25 @@ class Server:
         self.results = {}
         self._buf = (ctypes.c_int64 * 1024)()
 
-    def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None, k_max: int = 0) -> int:
+    def submit(self, A, k: int, p: int, q: int, t: float, col_scale=None, k_max: int = 0,
+               want_u: bool = True) -> int:
         """Queue a request (A in fp32, bfloat16 or FP8 E4M3 with col_scale, or
         fp64 on an fp64 server); with k_max > k its rank grows in blocks of
         k + p columns until t can be met (or the A^T A route takes it), K is
-        capped at k_max, and U, S, V hold k_max columns."""
+        capped at k_max, and U, S, V hold k_max columns (no U with
+        want_u=False)."""
         torch = self.torch
         m, n = A.shape
         kc = max(k, k_max)
         code = _dtype_codes(torch)[A.dtype][0]
-        o = dict(U=torch.empty((m, kc), dtype=self.dtype, device=self.device),
+        o = dict(U=torch.empty((m, kc), dtype=self.dtype, device=self.device) if want_u else None,
                  V=torch.empty((n, kc), dtype=self.dtype, device=self.device),
                  S=torch.empty((kc,), dtype=torch.float64, device=self.device),
                  K=torch.empty((1,), dtype=torch.int32, device=self.device),
                  status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
-        req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), o["U"].data_ptr(),
-                           _ld(o["U"]), o["S"].data_ptr(), o["V"].data_ptr(), _ld(o["V"]),
+        req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), _ptr(o["U"]),
+                           _ld(o["U"]) if want_u else 0, o["S"].data_ptr(), o["V"].data_ptr(),
+                           _ld(o["V"]),
                            o["K"].data_ptr(), o["status"].data_ptr(), _ptr(col_scale),
                            int(k_max), code)
         o["col_scale"] = col_scale

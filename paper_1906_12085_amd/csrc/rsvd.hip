@@ -489,13 +489,16 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   const bool tall_u = std::is_same<T, float>::value &&
                       nt_tall_applies(reinterpret_cast<const float*>(Q1), l, lq,
                                       reinterpret_cast<const float*>(p->MkT), l, k);
-  RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s, tall_u));
-  if (tall_u)
-    RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, l, lq,
-                                   reinterpret_cast<const float*>(p->MkT), l, k,
-                                   reinterpret_cast<float*>(U), ldu, nullptr, nullptr, s));
-  else
-    RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, lq, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr, s));
+  if (U) {   // (batch instances and server requests may ask for S, V and K only)
+    RSVD_CHECK(launch_small_gemm<T>(p->R2inv, p->Wk, l, l, k, nullptr, (T*)p->MkT, s, tall_u));
+    if (tall_u)
+      RSVD_CHECK(launch_gemm_nt_tall(reinterpret_cast<const float*>(Q1), m, l, lq,
+                                     reinterpret_cast<const float*>(p->MkT), l, k,
+                                     reinterpret_cast<float*>(U), ldu, nullptr, nullptr, s));
+    else
+      RSVD_CHECK(launch_gemm_nn<T>(Q1, m, l, lq, (const T*)p->MkT, k, k, U, ldu, nullptr, nullptr,
+                                   s));
+  }
   // K by the explained-variance criterion (Sec. 2.4)
   RSVD_CHECK(launch_select_k(S, k, p->scal, t, K, p->diag, p->status, s));
   return RSVD_OK;
@@ -826,9 +829,11 @@ struct Grow {
     if ((e = launch_sort_sign_scatter<T>(p->Su, L, p->Vt, n, L, 1, nullptr, L, p->Zq, nullptr, 0,
                                          nullptr, nullptr, s)) != hipSuccess)
       return e;
-    // U~ = Q W (first kc columns)
+    // U~ = Q W (first kc columns; none when U is not wanted)
     T* WT = (T*)p->MkT;
-    if (std::is_same<T, float>::value &&
+    if (!g.U) {
+      e = hipSuccess;
+    } else if (std::is_same<T, float>::value &&
         nt_tall_applies(reinterpret_cast<const float*>(Qp), L, ldp,
                         reinterpret_cast<const float*>(WT), L, kc)) {
       if ((e = launch_cast_t_from_f64<T>(p->Wk, L, kc, kc, WT, L, s)) != hipSuccess) return e;
@@ -1410,7 +1415,10 @@ int instance_dtype(const rsvd_plan_s* p, const rsvd_instance& x) {
 
 // Validate one instance for a slot plan (as rsvd_solve / rsvd_solve_bf16).
 int32_t check_instance(rsvd_plan_s* p, const rsvd_instance& x) {
-  const int32_t rc = check_rsvd(p, x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, x.U, x.ldu, x.S,
+  // U may be NULL (S, V and K only); its leading dimension is then unused
+  const void* u = x.U ? x.U : x.A;
+  const int64_t ldu = x.U ? x.ldu : (int64_t)(x.k_max > x.k ? x.k_max : x.k);
+  const int32_t rc = check_rsvd(p, x.A, x.m, x.n, x.lda, x.k, x.p, x.q, x.t, u, ldu, x.S,
                                 x.V, x.ldv, x.K);
   if (rc != RSVD_OK) return rc;
   if (!x.status) return RSVD_ERR_ARG;
@@ -1645,15 +1653,21 @@ struct rsvd_server_s {
   std::vector<int> slot_phase;
   std::vector<Req> slot_req;
   std::deque<int64_t> finished;
-  // A^T A-route slot (RSVD_SERVER_GRAM_FALLBACK)
-  rsvd_plan_s* gplan = nullptr;
-  hipStream_t gstream = nullptr;
-  hipEvent_t gdone = nullptr;
-  float* gbuf = nullptr;   // fp32 copy of a bfloat16 / FP8 request's A
+  // A^T A-route slots (RSVD_SERVER_GRAM_FALLBACK)
+  struct GramSlot {
+    rsvd_plan_s* plan = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    float* buf = nullptr;   // fp32 copy of a bfloat16 / FP8 request's A
+    bool busy = false;
+    Req req;
+  };
+  std::vector<GramSlot> gslot;
   std::deque<Req> gqueue;
-  bool gbusy = false;
-  Req greq;
 };
+
+// A^T A-route slots of a server created with RSVD_SERVER_GRAM_FALLBACK.
+constexpr int kGramSlots = 2;
 
 namespace {
 
@@ -1712,7 +1726,9 @@ int32_t gram_run_capped(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_
   RSVD_CHECK(launch_cast_from_f64<T>(p->Vd, n, kc, n, V, ldv, s));
   // u_i = A v_i / s_i for the first kc columns
   const double floor_rel = (double)(m > n ? m : n) * 2.220446049250313e-16;
-  if (std::is_same<T, float>::value && kc > 128) {
+  if (!U) {
+    // S, V and K only
+  } else if (std::is_same<T, float>::value && kc > 128) {
     RSVD_CHECK(launch_scale_cols_inv<T>(p->Vd, n, kc, n, p->Es, floor_rel, (T*)p->Xs, n, 1, s));
     RSVD_CHECK(launch_gemm_nt_wide(reinterpret_cast<const float*>(A), m, n, lda,
                                    reinterpret_cast<const float*>(p->Xs), n, kc,
@@ -1728,11 +1744,10 @@ int32_t gram_run_capped(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_
   return RSVD_OK;
 }
 
-int32_t gram_admit(rsvd_server_s* sv) {
-  if (sv->gbusy || sv->gqueue.empty()) return RSVD_OK;
+int32_t gram_admit_one(rsvd_server_s* sv, rsvd_server_s::GramSlot& gs) {
   rsvd_server_s::Req r = sv->gqueue.front();
   sv->gqueue.pop_front();
-  rsvd_plan_s* p = sv->gplan;
+  rsvd_plan_s* p = gs.plan;
   const rsvd_instance& x = r.x;
   int32_t rc;
   if (p->dtype == RSVD_F64) {
@@ -1742,20 +1757,30 @@ int32_t gram_admit(rsvd_server_s* sv) {
     const float* A32 = (const float*)x.A;
     int64_t lda = x.lda;
     if (const int es = lowp_es(instance_dtype(sv->b->plan[0], x))) {
-      RSVD_CHECK(launch_dequantize(x.A, es, x.m, x.n, x.lda, x.col_scale, sv->gbuf, x.n,
-                                   sv->gstream));
-      A32 = sv->gbuf;
+      RSVD_CHECK(launch_dequantize(x.A, es, x.m, x.n, x.lda, x.col_scale, gs.buf, x.n,
+                                   gs.stream));
+      A32 = gs.buf;
       lda = x.n;
     }
     rc = gram_run_capped<float>(p, A32, x.m, x.n, lda, x.t, x.k_max, (float*)x.U, x.ldu, x.S,
                                 (float*)x.V, x.ldv, x.K);
   }
   if (rc != RSVD_OK) return rc;
-  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, sv->gstream, p->status, x.status);
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, gs.stream, p->status, x.status);
   RSVD_CHECK(hipGetLastError());
-  RSVD_CHECK(hipEventRecord(sv->gdone, sv->gstream));
-  sv->gbusy = true;
-  sv->greq = r;
+  RSVD_CHECK(hipEventRecord(gs.done, gs.stream));
+  gs.busy = true;
+  gs.req = r;
+  return RSVD_OK;
+}
+
+int32_t gram_admit(rsvd_server_s* sv) {
+  for (auto& gs : sv->gslot) {
+    if (sv->gqueue.empty()) break;
+    if (gs.busy) continue;
+    const int32_t rc = gram_admit_one(sv, gs);
+    if (rc != RSVD_OK) return rc;
+  }
   return RSVD_OK;
 }
 
@@ -1806,7 +1831,7 @@ int32_t grow_next(rsvd_server_s* sv, int s) {
     // estimate: later columns capture less on a decaying spectrum)
     const double per_col = (e - r.e_prev) / r.g.b;
     const double kpred = per_col > 0.0 ? r.g.L + (need - e) / per_col : 1e300;
-    if (sv->gplan && r.x.n <= sv->gplan->n_max && (kpred > 0.5 * r.x.n || !fits)) {
+    if (!sv->gslot.empty() && (kpred > 0.5 * r.x.n || !fits)) {
       sv->slot_ticket[s] = -1;
       sv->slot_phase[s] = rsvd_server_s::kIdle;
       sv->gqueue.push_back(r);   // its bytes stay counted until it is done
@@ -1847,12 +1872,13 @@ int32_t server_retire(rsvd_server_s* sv, bool wait) {
     sv->slot_phase[s] = rsvd_server_s::kIdle;
     sv->finished.push_back(r.ticket);
   }
-  if (sv->gbusy) {
-    const hipError_t e = wait ? hipEventSynchronize(sv->gdone) : hipEventQuery(sv->gdone);
+  for (auto& gs : sv->gslot) {
+    if (!gs.busy) continue;
+    const hipError_t e = wait ? hipEventSynchronize(gs.done) : hipEventQuery(gs.done);
     if (e == hipSuccess) {
-      sv->gbusy = false;
-      sv->in_use -= sv->greq.bytes;
-      sv->finished.push_back(sv->greq.ticket);
+      gs.busy = false;
+      sv->in_use -= gs.req.bytes;
+      sv->finished.push_back(gs.req.ticket);
     } else if (e != hipErrorNotReady) {
       return RSVD_ERR_DEVICE;
     }
@@ -1863,15 +1889,18 @@ int32_t server_retire(rsvd_server_s* sv, bool wait) {
 int32_t server_running(const rsvd_server_s* sv) {
   int32_t r = 0;
   for (int64_t t : sv->slot_ticket) r += t >= 0;
-  return r + (sv->gbusy ? 1 : 0);
+  for (const auto& gs : sv->gslot) r += gs.busy ? 1 : 0;
+  return r;
 }
 
 void server_free(rsvd_server_s* sv) {
   if (sv->b) batch_free(sv->b);
-  if (sv->gplan) rsvd_plan_destroy(sv->gplan);
-  if (sv->gbuf) (void)hipFree(sv->gbuf);
-  if (sv->gdone) (void)hipEventDestroy(sv->gdone);
-  if (sv->gstream) (void)hipStreamDestroy(sv->gstream);
+  for (auto& gs : sv->gslot) {
+    if (gs.plan) rsvd_plan_destroy(gs.plan);
+    if (gs.buf) (void)hipFree(gs.buf);
+    if (gs.done) (void)hipEventDestroy(gs.done);
+    if (gs.stream) (void)hipStreamDestroy(gs.stream);
+  }
   delete sv;
 }
 
@@ -1901,25 +1930,28 @@ int32_t rsvd_server_create(rsvd_server_t* server, int32_t nslots, int64_t m_max,
   sv->slot_phase.assign(nslots, rsvd_server_s::kIdle);
   sv->slot_req.assign(nslots, rsvd_server_s::Req());
   if (fallback) {
-    if (hipStreamCreateWithFlags(&sv->gstream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sv->gdone, hipEventDisableTiming) != hipSuccess) {
-      server_free(sv);
-      return RSVD_ERR_DEVICE;
-    }
+    sv->gslot.resize(kGramSlots);
     const int gdt = dtype == RSVD_F64 ? RSVD_F64 : RSVD_F32;
     const int32_t gl = (int32_t)(n_max < 8 ? n_max : 8);
-    if ((rc = rsvd_plan_create(&sv->gplan, m_max, n_max, gl, gdt, 1, seed, sv->gstream)) !=
-        RSVD_OK) {
-      sv->gplan = nullptr;
-      server_free(sv);
-      return rc;
-    }
-    if (gdt == RSVD_F32 &&
-        hipMalloc(&sv->gbuf, (size_t)m_max * (size_t)n_max * sizeof(float)) != hipSuccess) {
-      (void)hipGetLastError();
-      sv->gbuf = nullptr;
-      server_free(sv);
-      return RSVD_ERR_NOMEM;
+    for (auto& gs : sv->gslot) {
+      if (hipStreamCreateWithFlags(&gs.stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&gs.done, hipEventDisableTiming) != hipSuccess) {
+        server_free(sv);
+        return RSVD_ERR_DEVICE;
+      }
+      if ((rc = rsvd_plan_create(&gs.plan, m_max, n_max, gl, gdt, 1, seed, gs.stream)) !=
+          RSVD_OK) {
+        gs.plan = nullptr;
+        server_free(sv);
+        return rc;
+      }
+      if (gdt == RSVD_F32 &&
+          hipMalloc(&gs.buf, (size_t)m_max * (size_t)n_max * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        gs.buf = nullptr;
+        server_free(sv);
+        return RSVD_ERR_NOMEM;
+      }
     }
   }
   *server = sv;
@@ -1933,7 +1965,7 @@ int32_t rsvd_server_submit(rsvd_server_t server, const rsvd_instance* req, int64
   int32_t rc = check_instance(p0, x);
   if (rc != RSVD_OK) return rc;
   if (grows(x)) {   // outputs for k_max columns; two row-padded blocks within l_max
-    if (x.k_max > x.n || x.ldu < x.k_max || x.ldv < x.k_max) return RSVD_ERR_ARG;
+    if (x.k_max > x.n || (x.U && x.ldu < x.k_max) || x.ldv < x.k_max) return RSVD_ERR_ARG;
     const int64_t bw = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
     if (2 * ldq1_of(bw) > p0->l_max) return RSVD_ERR_SHAPE;
   }
@@ -2342,7 +2374,7 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(batch->plan[0], inst[i]);
     if (rc != RSVD_OK) return rc;
-    if (instance_dtype(batch->plan[0], inst[i]) != RSVD_F32) return RSVD_ERR_ARG;
+    if (instance_dtype(batch->plan[0], inst[i]) != RSVD_F32 || !inst[i].U) return RSVD_ERR_ARG;
     if (!grouped_applies(inst[i], batch->plan[0]->max_split)) return RSVD_ERR_ARG;
   }
   if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;

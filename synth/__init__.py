@@ -166,9 +166,10 @@ def batch_shapes(c=None):
     return out
 
 
-CONFIG5 = dict(rate=200.0, seconds=8.0, m_lo=1000, m_hi=1_000_000, m_multiple=64,
+CONFIG5 = dict(rate=200.0, seconds=60.0, m_lo=1000, m_hi=1_000_000, m_multiple=64,
                n_choices=(128, 256, 512, 1024), alpha_lo=0.5, alpha_hi=2.0,
-               t_choices=(0.9, 0.95, 0.99), k=16, k_max=64, p=8, q=2, pool=24, seed=5)
+               t_choices=(0.9, 0.95, 0.99), storage_choices=("fp32", "bf16"), k=16, p=8, q=2,
+               l_max=192, pool=24, seed=5)
 
 
 def serve_pool(c=None):
@@ -189,7 +190,8 @@ def serve_pool(c=None):
 
 def serve_arrivals(c=None):
     """Poisson arrivals at `rate` per second over `seconds`: (time, pool
-    index, t) per request."""
+    index, t, storage) per request, storage drawn uniformly from
+    storage_choices."""
     c = c or CONFIG5
     rng = np.random.default_rng(c["seed"] + 1)
     out, now = [], 0.0
@@ -197,7 +199,9 @@ def serve_arrivals(c=None):
         now += rng.exponential(1.0 / c["rate"])
         if now >= c["seconds"]:
             return out
-        out.append((now, int(rng.integers(0, c["pool"])), float(rng.choice(c["t_choices"]))))
+        j = int(rng.integers(0, c["pool"]))
+        t = float(rng.choice(c["t_choices"]))
+        out.append((now, j, t, str(rng.choice(c["storage_choices"]))))
 
 
 def power_sigma(n: int, alpha: float) -> np.ndarray:

@@ -301,3 +301,27 @@ def test_serve_gram_fallback(fmt):
     for pl in (quant, gram, alone):
         pl.close()
     sv.close()
+
+
+def test_serve_without_u():
+    # requests that ask for S, V and K only: the same values as with U, bit
+    # for bit, through all three routes (fixed rank, growth, A^T A fallback)
+    announce("serve: requests without U")
+    reqs = requests(torch.float32, 6, 71)
+    sv = rs.Server(3, M_MAX, N_MAX, L_MAX, torch.float32, seed=SEED, gram_fallback=True)
+    pending, seen, pairs = set(), [], []
+    for i, (A, k, p, q, t, _) in enumerate(reqs):
+        k_max = 0 if i % 2 == 0 else A.shape[1]
+        kk = 4 if k_max else k
+        a = sv.submit(A, kk, p, q, t, k_max=k_max)
+        b = sv.submit(A, kk, p, q, t, k_max=k_max, want_u=False)
+        pairs.append((a, b))
+        pending.update((a, b))
+        poll(sv, pending, seen)
+    drain(sv, pending, seen)
+    for a, b in pairs:
+        oa, ob = sv.results[a], sv.results[b]
+        assert ob["U"] is None
+        assert torch.equal(oa["S"], ob["S"]) and torch.equal(oa["V"], ob["V"])
+        assert torch.equal(oa["K"], ob["K"]) and torch.equal(oa["status"], ob["status"])
+    sv.close()

@@ -608,14 +608,15 @@ class Server:
         fp64 on an fp64 server); with k_max > k its rank grows in blocks of
         k + p columns until t can be met (or the A^T A route takes it), K is
         capped at k_max, and U, S, V hold k_max columns (no U with
-        want_u=False)."""
+        want_u=False), of which the first min(k_max, columns found) are
+        written; S starts at zero, so its unwritten tail reads 0."""
         torch = self.torch
         m, n = A.shape
         kc = max(k, k_max)
         code = _dtype_codes(torch)[A.dtype][0]
         o = dict(U=torch.empty((m, kc), dtype=self.dtype, device=self.device) if want_u else None,
                  V=torch.empty((n, kc), dtype=self.dtype, device=self.device),
-                 S=torch.empty((kc,), dtype=torch.float64, device=self.device),
+                 S=torch.zeros((kc,), dtype=torch.float64, device=self.device),
                  K=torch.empty((1,), dtype=torch.int32, device=self.device),
                  status=torch.empty((1,), dtype=torch.int32, device=self.device), A=A)
         req = RsvdInstance(A.data_ptr(), m, n, _ld(A), k, p, q, float(t), _ptr(o["U"]),

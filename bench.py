@@ -410,11 +410,9 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
     mmax = max(s[0] for s in shapes)
     nmax = max(s[1] for s in shapes)
     lmax = max(min(s[3] + c["p"], s[1]) for s in shapes)
-    probs, flops, nbytes = [], 0.0, 0.0
-    for i, (m, n, r, k) in enumerate(shapes):
-        A = synth.spiked_noisy_torch(c["seed"] * 100003 + i, m, n, synth.exp_sigma(n, r), 0.0,
-                                     dev, torch.float32)
-        probs.append((A, k, c["p"], c["q"], c["t"]))
+    probs = synth.batch_problems(torch, dev, c)
+    flops, nbytes = 0.0, 0.0
+    for m, n, r, k in shapes:
         l = min(k + c["p"], n)
         f, b_, _, _ = algorithmic_counts(m, n, k, l, c["q"], 4)
         flops += f
@@ -440,14 +438,24 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
     graph_s = timed(g.launch)
     same = all(torch.equal(o["S"], e) for o, e in zip(prepared[0], keep))
     g.close()
-    # every step one launch for all instances
-    gg = b.grouped(None, prepared=prepared)
+    # every step one launch for all instances: default tile parameters, then
+    # the committed autotuner cache, eagerly and as a captured graph
+    gd = b.grouped(None, prepared=prepared)
+    grouped_default_s = timed(gd.launch)
+    gd.close()
+    tune = rs.load_tune_cache()
+    gg = b.grouped(None, prepared=prepared, tune=tune)
     grouped_s = timed(gg.launch)
     # the grouped partial sums use longer row splits than a slot's, so they
     # are rounded in another order: singular values agree to FP32 rounding
     grouped_rel = max(float(((o["S"].double() - e.double()).abs() / e.double()).max())
                       for o, e in zip(prepared[0], keep))
     grouped_k = all(int(o["K"].item()) == kk for o, kk in zip(prepared[0], keep_k))
+    gkeep = [o["S"].clone() for o in prepared[0]]
+    gr = gg.graph()
+    grouped_graph_s = timed(gr.launch)
+    grouped_graph_same = all(torch.equal(o["S"], e) for o, e in zip(prepared[0], gkeep))
+    gr.close()
     gg.close()
     statuses = {}
     for o in prepared[0]:
@@ -459,13 +467,21 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
     b.close()
     del probs, prepared
     torch.cuda.empty_cache()
-    best = min(eager_s, graph_s, grouped_s)
+    best = min(eager_s, graph_s, grouped_s, grouped_graph_s)
+    a_bytes = sum(m * n * 4 for m, n, _, _ in shapes)
     return {"instances": len(shapes), "slots": nslots,
             "m_range": [min(s[0] for s in shapes), mmax], "n_set": sorted({s[1] for s in shapes}),
             "ms_per_batch": {"sequential_one_stream": round(1e3 * seq_s, 2),
                              "batch_eager": round(1e3 * eager_s, 2),
                              "batch_graph": round(1e3 * graph_s, 2),
-                             "batch_grouped": round(1e3 * grouped_s, 2)},
+                             "batch_grouped_default_tiles": round(1e3 * grouped_default_s, 2),
+                             "batch_grouped": round(1e3 * grouped_s, 2),
+                             "batch_grouped_graph": round(1e3 * grouped_graph_s, 2)},
+            "tuning": {"cache": os.path.basename(rs.TUNE_CACHE) if tune else None,
+                       "entries": [list(e) for e in tune]},
+            "hbm_bound_ms": round(1e3 * 6 * a_bytes / 8e12, 2),
+            "frac_of_hbm_bound": round(6 * a_bytes / 8e12 / best, 3),
+            "grouped_graph_replay_equals_eager": grouped_graph_same,
             "instances_per_s": round(len(shapes) / best, 1),
             "speedup_vs_sequential": round(seq_s / best, 2),
             "tflops": round(flops / best / 1e12, 2), "gbs": round(nbytes / best / 1e9, 1),

@@ -419,29 +419,67 @@ int32_t rsvd_batch_graph_launch(rsvd_batch_graph_t graph, void* stream);
 int32_t rsvd_batch_graph_destroy(rsvd_batch_graph_t graph);
 
 /* Grouped batches: the same solves as rsvd_batch_solve for RSVD_F32
- * instances, with every step one launch for all instances (instead of one
- * chain of launches per instance on the slots), which removes the
- * per-instance launch latency that bounds batches of small problems.
+ * instances (Sec. 3.1.2 each), with every step one launch for all
+ * instances (instead of one chain of launches per instance on the slots),
+ * which removes the per-instance launch latency that bounds batches of small
+ * problems.  The passes over the tall matrices run over a work list of
+ * (instance, row panel) items, largest instances first, one workgroup per
+ * item: the A X product and the Y R^-1 product of CholeskyQR2 also take the
+ * panel's FP64 Gram matrix from their output registers (the m-row Gram
+ * matrices of CholeskyQR2, l <= 64), and the first pass its sum of squares;
+ * A^T Q writes one FP64 partial per row split.  Each instance's partials are
+ * summed in a fixed order.
+ *
  * rsvd_batch_grouped_create validates the instances (as rsvd_batch_solve;
  * further RSVD_ERR_ARG unless A is 16-byte aligned with lda and n multiples
- * of 4 and l = min(k + p, n) a multiple of 4), allocates one workspace per
- * instance, sized for it, and records the launches with their arguments
- * (uploaded once); nothing runs.  rsvd_batch_grouped_launch runs them on
- * `stream`: the steps of rsvd_solve on a plan with the batch's seed (the
- * same G), with longer row splits for the FP64 partial sums (A^T Q and the
- * m-row Gram matrices: at least 1024 rows each, where a solve alone on the
- * GPU splits its rows over every CU), since the instances fill the GPU
- * together; the sums are rounded in another order, so results agree with
- * rsvd_solve to FP32 rounding, not bit for bit, and every launch of one
- * grouped batch gives the same bits.  Instances with equal l, k and q share
- * launches.  One launch of a
- * grouped batch at a time; rsvd_batch_grouped_destroy synchronises the
+ * of 4, l = min(k + p, n) a multiple of 4 and at most 96, and U given),
+ * allocates one workspace per instance, sized for it, and records the
+ * launches with their arguments and work lists (uploaded once); nothing
+ * runs.  `tune` (host, `ntune` entries, may be NULL) sets the tile
+ * parameters per (n, l): rows per work item of the A X and Y R^-1 products
+ * and the shortest A^T Q row split (rsvd_tune_entry; instances with no
+ * entry take 1024 and 1024; RSVD_ERR_ARG for an entry outside the limits
+ * below).  rsvd_batch_grouped_launch runs the batch on `stream`: the steps
+ * of rsvd_solve on a plan with the batch's seed (the same G), with longer
+ * row splits for the FP64 partial sums (at least 1024 rows each, where a
+ * solve alone on the GPU splits its rows over every CU), since the
+ * instances fill the GPU together; the sums are rounded in another order,
+ * so results agree with rsvd_solve to FP32 rounding, not bit for bit, and
+ * every launch of one grouped batch gives the same bits (also with another
+ * tuning).  Instances with equal l, k and q share launches.  One launch of
+ * a grouped batch at a time; rsvd_batch_grouped_destroy synchronises the
  * device and frees it. */
+typedef struct rsvd_tune_entry {
+  int32_t n, l;          /* the bucket: instances with this n and l = min(k + p, n) */
+  int32_t panel_rows;    /* rows per work item of A X and Y R^-1: a multiple of 128, 1024..2^20 */
+  int32_t split_rows;    /* shortest A^T Q row split: a multiple of 16, 1024..2^20 */
+} rsvd_tune_entry;
 typedef struct rsvd_grouped_s* rsvd_grouped_t;
 int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                  const rsvd_tune_entry* tune, int32_t ntune,
                                   rsvd_grouped_t* grouped);
 int32_t rsvd_batch_grouped_launch(rsvd_grouped_t grouped, void* stream);
 int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped);
+
+/* Capture one launch of a grouped batch into a HIP graph (nothing runs);
+ * launch it with rsvd_batch_graph_launch on any stream (each launch repeats
+ * the same solves on the same buffers, bit for bit those of
+ * rsvd_batch_grouped_launch) and free it with rsvd_batch_graph_destroy.  The
+ * grouped batch must outlive the graph; one launch of either at a time.
+ * RSVD_ERR_DEVICE if the capture fails. */
+int32_t rsvd_batch_grouped_graph_create(rsvd_grouped_t grouped, rsvd_batch_graph_t* graph);
+
+/* Autotuner of the grouped tile parameters: for each (n, l) bucket of the
+ * instances (in order of first appearance; at most `cap`, else
+ * RSVD_ERR_ARG) it times grouped launches of that bucket's instances alone
+ * on `stream` (one untimed launch, then the mean of three) for rows per
+ * work item in {1024, 2048, 4096, 8192} at the default split, then the
+ * split in the same set at the best rows, and writes the fastest pair to
+ * out[b] (host); *nout = the number of buckets.  It runs the instances
+ * (their outputs are written) and synchronises the device; the entries are
+ * for rsvd_batch_grouped_create.  Errors as rsvd_batch_grouped_create. */
+int32_t rsvd_batch_grouped_tune(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                rsvd_tune_entry* out, int32_t cap, int32_t* nout, void* stream);
 
 /* ------------------------------------------------------------- serving --
  * Continuous batching of Randomized PCA requests (Sec. 3.1.2 each): requests

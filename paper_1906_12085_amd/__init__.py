@@ -42,7 +42,12 @@ EXPORTS = ["rsvd_status_string", "rsvd_plan_create", "rsvd_plan_destroy", "rsvd_
            "rsvd_batch_graph_create", "rsvd_batch_graph_launch", "rsvd_batch_graph_destroy",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_progress",
            "rsvd_server_destroy", "rsvd_batch_grouped_create", "rsvd_batch_grouped_launch",
-           "rsvd_batch_grouped_destroy", "rsvd_solve_noalloc", "rsvd_solve_adaptive"]
+           "rsvd_batch_grouped_destroy", "rsvd_solve_noalloc", "rsvd_solve_adaptive",
+           "rsvd_batch_grouped_tune", "rsvd_batch_grouped_graph_create"]
+
+# The committed tile parameters of grouped batches on gfx950 (written by
+# tune_grouped.py from the autotuner's measurements).
+TUNE_CACHE = os.path.join(HERE, "tune_grouped_gfx950.json")
 
 
 class RsvdInstance(ctypes.Structure):
@@ -54,6 +59,33 @@ class RsvdInstance(ctypes.Structure):
                 ("ldv", ctypes.c_int64), ("K", ctypes.c_void_p), ("status", ctypes.c_void_p),
                 ("col_scale", ctypes.c_void_p), ("k_max", ctypes.c_int32),
                 ("dtype", ctypes.c_int32)]
+
+
+class RsvdTuneEntry(ctypes.Structure):
+    """Tile parameters of a grouped batch for one (n, l) (rsvd_tune_entry)."""
+    _fields_ = [("n", ctypes.c_int32), ("l", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
+                ("split_rows", ctypes.c_int32)]
+
+
+def load_tune_cache(path: str = TUNE_CACHE):
+    """The entries of a tuning cache file (JSON list of {n, l, panel_rows,
+    split_rows}); [] if there is none."""
+    import json
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        data = json.load(f)
+    return [(int(e["n"]), int(e["l"]), int(e["panel_rows"]), int(e["split_rows"]))
+            for e in data["entries"]]
+
+
+def _tune_array(entries):
+    if not entries:
+        return None, 0
+    arr = (RsvdTuneEntry * len(entries))()
+    for i, e in enumerate(entries):
+        arr[i] = RsvdTuneEntry(*[int(v) for v in e])
+    return arr, len(entries)
 
 
 def _dtype_codes(torch):
@@ -111,7 +143,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "rsvd_server_destroy": (i32, [vp]),
         "rsvd_batch_grouped_create": (i32, [vp, ctypes.POINTER(RsvdInstance), i32,
+                                            ctypes.POINTER(RsvdTuneEntry), i32,
                                             ctypes.POINTER(vp)]),
+        "rsvd_batch_grouped_tune": (i32, [vp, ctypes.POINTER(RsvdInstance), i32,
+                                          ctypes.POINTER(RsvdTuneEntry), i32,
+                                          ctypes.POINTER(i32), vp]),
+        "rsvd_batch_grouped_graph_create": (i32, [vp, ctypes.POINTER(vp)]),
         "rsvd_batch_grouped_launch": (i32, [vp, vp]),
         "rsvd_batch_grouped_destroy": (i32, [vp]),
         "gram_eig_solve": (i32, [vp, vp, i64, i64, i64, dbl, i32, vp, i64, vp, vp, i64, vp]),
@@ -514,14 +551,27 @@ class Batch:
                "rsvd_batch_solve")
         return outs
 
-    def grouped(self, problems, prepared=None):
-        """The same solves as a grouped batch (fp32 batches only)."""
+    def grouped(self, problems, prepared=None, tune=None):
+        """The same solves as a grouped batch (fp32 batches only); `tune` is
+        a list of (n, l, panel_rows, split_rows) tile parameters."""
         outs, arr = prepared if prepared is not None else self.prepare(problems)
         g = ctypes.c_void_p()
-        _check(load_library().rsvd_batch_grouped_create(self.handle, arr, len(arr),
+        tarr, nt = _tune_array(tune)
+        _check(load_library().rsvd_batch_grouped_create(self.handle, arr, len(arr), tarr, nt,
                                                         ctypes.byref(g)),
                "rsvd_batch_grouped_create")
         return BatchGrouped(g.value, outs)
+
+    def tune_grouped(self, problems, prepared=None, stream=None, cap: int = 64):
+        """Autotune the grouped tile parameters on these problems (runs
+        them): [(n, l, panel_rows, split_rows)] per (n, l) bucket."""
+        outs, arr = prepared if prepared is not None else self.prepare(problems)
+        out = (RsvdTuneEntry * cap)()
+        nout = ctypes.c_int32()
+        _check(load_library().rsvd_batch_grouped_tune(self.handle, arr, len(arr), out, cap,
+                                                      ctypes.byref(nout), _stream_ptr(stream)),
+               "rsvd_batch_grouped_tune")
+        return [(e.n, e.l, e.panel_rows, e.split_rows) for e in out[:nout.value]]
 
     def graph(self, problems, prepared=None):
         outs, arr = prepared if prepared is not None else self.prepare(problems)
@@ -543,6 +593,14 @@ class BatchGrouped:
                "rsvd_batch_grouped_launch")
         return self.outs
 
+    def graph(self):
+        """One launch of this grouped batch captured into a HIP graph (which
+        keeps this object alive)."""
+        g = ctypes.c_void_p()
+        _check(load_library().rsvd_batch_grouped_graph_create(self.handle, ctypes.byref(g)),
+               "rsvd_batch_grouped_graph_create")
+        return BatchGraph(g.value, self.outs, owner=self)
+
     def close(self):
         if self.handle:
             _check(load_library().rsvd_batch_grouped_destroy(self.handle),
@@ -559,8 +617,8 @@ class BatchGrouped:
 class BatchGraph:
     """A captured batch; launch() replays it on a stream."""
 
-    def __init__(self, handle, outs):
-        self.handle, self.outs = handle, outs
+    def __init__(self, handle, outs, owner=None):
+        self.handle, self.outs, self.owner = handle, outs, owner
 
     def launch(self, stream=None):
         _check(load_library().rsvd_batch_graph_launch(self.handle, _stream_ptr(stream)),

@@ -518,16 +518,80 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 constexpr int kTM = 128, kTK = 32, kTLD = kTK + 4;
 constexpr int kTQ = kTK / 4, kTUA = kTM * kTQ / 256;   // k-quads per row, A loads per thread
 
-template <int NT>
+// Work-list epilogue of the NT products (see GWork): a wave's FP32 output
+// tiles acc[i][J] (16 rows x 16 columns each, value e of lane l at row
+// 4 (l / 16) + e, column l % 16) are, for each e, exactly the operands the
+// FP64 16x16x4 matrix core takes for Y_I^T Y_J over the four rows
+// 4 k + e (a = column l % 16 of tile I, b = of tile J, k = l / 16), so the
+// Gram matrix of the stored (FP32) outputs is summed from the registers with
+// exact products.  Columns past c and rows past m hold zeros there.
+template <int NT, int RT>
+__device__ __forceinline__ void gram_from_acc(const f32x4 (&acc)[RT][NT],
+                                              f64x4 (&g)[NT * (NT + 1) / 2]) {
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double y[NT];
+#pragma unroll
+      for (int J = 0; J < NT; ++J) y[J] = (double)acc[i][J][e];
+      int q = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+          g[q] = Mfma<double>::run(y[I], y[J], g[q]);
+          ++q;
+        }
+    }
+}
+
+// The waves' Gram tiles added in wave order in LDS (red: c x c doubles) and
+// written as the symmetric c x c partial Pb (the upper tile pairs mirrored).
+template <int NT, int WAVES>
+__device__ __forceinline__ void gram_store(const f64x4 (&g)[NT * (NT + 1) / 2], int c,
+                                           double* red, double* __restrict__ Pb) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int w = 0; w < WAVES; ++w) {
+    if (wave == w) {
+      int q = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = 16 * I + Mfma<double>::row(lane, e), j = 16 * J + (lane & 15);
+            if (i < c && j < c) red[i * c + j] = (w == 0) ? g[q][e] : red[i * c + j] + g[q][e];
+          }
+          ++q;
+        }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < c * c; idx += WAVES * 64) {
+    const int i = idx / c, j = idx - i * c;
+    Pb[idx] = ((i >> 4) <= (j >> 4)) ? red[i * c + j] : red[j * c + i];
+  }
+}
+
+template <int NT, bool GR>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
     int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ fro2_part,
-    const GArgTall* __restrict__ grp) {
+    const GArgTall* __restrict__ grp, const GWork* __restrict__ wl) {
+  // tiles [t0, t1) of 128 rows; partial slot of the sum of squares / Gram
+  int64_t t0 = blockIdx.x, t1 = (int64_t)blockIdx.x + 1, slot = blockIdx.x;
+  double* gram = nullptr;
   if (grp) {
-    const GArgTall& a = grp[blockIdx.y];
-    if ((int)blockIdx.x >= a.nblk) return;
+    const GWork w = wl[blockIdx.x];
+    const GArgTall& a = grp[w.inst];
     A = a.A; m = a.m; n = a.n; lda = a.lda; Xt = a.Xt; ldxt = a.ldxt; c = a.c; Y = a.Y;
-    ldy = a.ldy; fro2_part = a.fro2;
+    ldy = a.ldy; fro2_part = a.fro2; gram = a.gram;
+    slot = w.item;
+    t0 = (int64_t)w.item * a.tpp;
+    const int64_t nt_all = (m + kTM - 1) / kTM;
+    t1 = t0 + a.tpp < nt_all ? t0 + a.tpp : nt_all;
   }
   constexpr int BC = 16 * NT;
   constexpr int XU = (BC * (kTK / 4) + 255) / 256;   // float4 of the Xt chunk per thread
@@ -536,15 +600,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kTM;
-  const int64_t rows = m - row0 < kTM ? m - row0 : kTM;
   const int nch = (int)((n + kTK - 1) / kTK);
   const bool do_ss = fro2_part != nullptr;
-  // both ranges end at the last element of their last row
-  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(A + row0 * lda), 0, (int)(((rows - 1) * lda + n) * 4), kBufDword3);
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(Xt), 0, (int)(((int64_t)(c - 1) * ldxt + n) * 4), kBufDword3);
+  __amdgpu_buffer_rsrc_t ar = xr;   // the tile's rows, set per tile
   int voa[kTUA], vox[XU];
 #pragma unroll
   for (int u = 0; u < kTUA; ++u) {
@@ -601,11 +661,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
     }
   };
   constexpr int RT = kTM / 64;                 // 16-row tiles per wave
+  constexpr int NP = GR ? NT * (NT + 1) / 2 : 1;
+  f64x4 gacc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) gacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
   f32x4 acc[RT][NT];
-#pragma unroll
-  for (int i = 0; i < RT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // slab of 16 k: lane (lr, g) reads k = 16 s + 4 g .. +3 with one 16-byte
   // load; step t contracts over k = 16 s + 4 g + t on both operands
   auto slab = [&](int buf, int s) {
@@ -623,37 +683,55 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[i][t], bf[j][t], acc[i][j]);
   };
-  load(0);
-  store(0, 0);
-  __syncthreads();
   static_assert(kTK == 32, "two slabs per chunk");
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    const bool more = ch + 1 < nch;
-    load(more ? ch + 1 : ch);                  // the last prefetch is a harmless repeat
-    __builtin_amdgcn_sched_barrier(0);
-    slab(buf, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    slab(buf, 1);
-    if (more) store(buf ^ 1, ch + 1);
+  for (int64_t tl = t0; tl < t1; ++tl) {
+    const int64_t row0 = tl * kTM;
+    const int64_t rows = m - row0 < kTM ? m - row0 : kTM;
+    // the range ends at the last element of the tile's last row
+    ar = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A + row0 * lda), 0,
+                                           (int)(((rows - 1) * lda + n) * 4), kBufDword3);
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    store(0, 0);
     __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < RT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int col = 16 * j + lr;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + wave * 16 * RT + 16 * i + Mfma<float>::row(lane, e);
-        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
-      }
+    for (int ch = 0; ch < nch; ++ch) {
+      const int buf = ch & 1;
+      const bool more = ch + 1 < nch;
+      load(more ? ch + 1 : ch);                  // the last prefetch is a harmless repeat
+      __builtin_amdgcn_sched_barrier(0);
+      slab(buf, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      slab(buf, 1);
+      if (more) store(buf ^ 1, ch + 1);
+      __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int col = 16 * j + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = row0 + wave * 16 * RT + 16 * i + Mfma<float>::row(lane, e);
+          if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+        }
+      }
+    if constexpr (GR) gram_from_acc<NT, RT>(acc, gacc);
+  }
   if (do_ss) {
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) fro2_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) fro2_part[slot] = red[0] + red[1] + red[2] + red[3];
+  }
+  if constexpr (GR) {
+    // As is free (the last chunk ended with a barrier): c <= 64 fits
+    static_assert(16 * NT * 16 * NT * sizeof(double) <= sizeof(As), "Gram tile fits in As");
+    if (gram) gram_store<NT, 4>(gacc, c, reinterpret_cast<double*>(&As[0][0]),
+                                gram + slot * (int64_t)c * c);
   }
 }
 
@@ -667,22 +745,30 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
 // (n % 4 == 0, 16-byte rows).
 constexpr int kNM = 128;
 
-template <int NT, int NS>
+template <int NT, int NS, bool GR>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
-    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, const GArgNarrow* __restrict__ grp) {
-  int64_t nbx = gridDim.x;   // blocks of this problem: the stride of the persistent loop
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, const GArgNarrow* __restrict__ grp,
+    const GWork* __restrict__ wl) {
+  // tiles t0, t0 + step, ... below t1
+  int64_t t0 = blockIdx.x, step = gridDim.x, t1 = (m + kNM - 1) / kNM, slot = 0;
+  double* gram = nullptr;
   if (grp) {
-    const GArgNarrow& a = grp[blockIdx.y];
-    if ((int)blockIdx.x >= a.nblk) return;
+    const GWork w = wl[blockIdx.x];
+    const GArgNarrow& a = grp[w.inst];
     A = a.A; m = a.m; n = a.n; lda = a.lda; Xt = a.Xt; ldxt = a.ldxt; c = a.c; Y = a.Y;
-    ldy = a.ldy; nbx = a.nblk;
+    ldy = a.ldy; gram = a.gram;
+    slot = w.item;
+    step = 1;
+    t0 = (int64_t)w.item * a.tpp;
+    const int64_t nt_all = (m + kNM - 1) / kNM;
+    t1 = t0 + a.tpp < nt_all ? t0 + a.tpp : nt_all;
   }
   constexpr int BC = 16 * NT, KP = 16 * NS, LD = KP + 4;
   __shared__ __attribute__((aligned(16))) float Bs[BC * LD];
+  __shared__ double gred[GR ? BC * BC : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int64_t ntile = (m + kNM - 1) / kNM;
   int vo[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) vo[i] = (int)(((int64_t)(wave * 32 + 16 * i + lr) * lda + 4 * g) * 4);
@@ -699,9 +785,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
       for (int sl = 0; sl < NS; ++sl)
         dst[sl][i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, vo[i], 64 * sl, 0));
   };
+  constexpr int NP = GR ? NT * (NT + 1) / 2 : 1;
+  f64x4 gacc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) gacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
   f32x4 nxt[NS][2];
-  int64_t tl = blockIdx.x;
-  if (tl < ntile) load(tl, nxt);
+  int64_t tl = t0;
+  if (tl < t1) load(tl, nxt);
   // Xt into LDS, zero beyond c rows and n columns, while A is in flight
   for (int e = tid; e < BC * (KP / 4); e += 256) {
     const int r = e / (KP / 4), q = e - r * (KP / 4);
@@ -710,14 +800,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
     *reinterpret_cast<f32x4*>(&Bs[r * LD + 4 * q]) = v;
   }
   __syncthreads();
-  for (; tl < ntile; tl += nbx) {
+  for (; tl < t1; tl += step) {
     f32x4 af[NS][2];
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
       for (int i = 0; i < 2; ++i) af[sl][i] = nxt[sl][i];
-    const int64_t tn = tl + nbx;
-    load(tn < ntile ? tn : tl, nxt);          // the last prefetch is a harmless repeat
+    const int64_t tn = tl + step;
+    load(tn < t1 ? tn : tl, nxt);             // the last prefetch is a harmless repeat
     __builtin_amdgcn_sched_barrier(0);
     f32x4 acc[2][NT];
 #pragma unroll
@@ -754,6 +844,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
           if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
         }
       }
+    if constexpr (GR) gram_from_acc<NT, 2>(acc, gacc);
+  }
+  if constexpr (GR) {
+    if (gram) gram_store<NT, 4>(gacc, c, gred, gram + slot * (int64_t)c * c);
   }
 }
 
@@ -771,12 +865,14 @@ template <int NT>
 __global__ __launch_bounds__(512) void k_gemm_tn_tall(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
     int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P,
-    const GArgTn* __restrict__ grp) {
+    const GArgTn* __restrict__ grp, const GWork* __restrict__ wl) {
+  int bx = blockIdx.x;
   if (grp) {
-    const GArgTn& a = grp[blockIdx.y];
-    if ((int)blockIdx.x >= a.nblk) return;
+    const GWork w = wl[blockIdx.x];
+    const GArgTn& a = grp[w.inst];
     A = a.A; m = a.m; n = a.n; lda = a.lda; Q = a.Q; ldq = a.ldq; c = a.c; rps = a.rps;
     ntile = a.ntile; P = a.P;
+    bx = w.item;
   }
   constexpr int BC = 16 * NT;
   constexpr int QLD = BC + ((16 - BC) % 64 + 64) % 64;
@@ -785,8 +881,8 @@ __global__ __launch_bounds__(512) void k_gemm_tn_tall(
   __shared__ __attribute__((aligned(16))) float Qs[2][kUK * QLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int ta = blockIdx.x % ntile;
-  const int64_t sp = blockIdx.x / ntile;
+  const int ta = bx % ntile;
+  const int64_t sp = bx / ntile;
   const int64_t row0 = sp * rps;
   const int64_t rows = m - row0 < rps ? m - row0 : rps;
   const int nch = (int)((rows + kUK - 1) / kUK);
@@ -896,13 +992,15 @@ template <int NT, int CW>
 __global__ __launch_bounds__(512) void k_gemm_tn_narrow(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Q,
     int64_t ldq, int c, int64_t rps, int ntile, double* __restrict__ P,
-    const GArgTn* __restrict__ grp) {
+    const GArgTn* __restrict__ grp, const GWork* __restrict__ wl) {
   using G = TnNarrow<CW>;
+  int bx = blockIdx.x;
   if (grp) {
-    const GArgTn& a = grp[blockIdx.y];
-    if ((int)blockIdx.x >= a.nblk) return;
+    const GWork w = wl[blockIdx.x];
+    const GArgTn& a = grp[w.inst];
     A = a.A; m = a.m; n = a.n; lda = a.lda; Q = a.Q; ldq = a.ldq; c = a.c; rps = a.rps;
     ntile = a.ntile; P = a.P;
+    bx = w.item;
   }
   constexpr int BC = 16 * NT;
   constexpr int QLD = BC + ((16 - BC) % 64 + 64) % 64;
@@ -913,7 +1011,7 @@ __global__ __launch_bounds__(512) void k_gemm_tn_narrow(
   __shared__ __attribute__((aligned(16))) float Qs[2][G::R * QLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int64_t sp = blockIdx.x / ntile;
+  const int64_t sp = bx / ntile;
   const int64_t row0 = sp * rps;
   const int64_t rows = m - row0 < rps ? m - row0 : rps;
   const int nch = (int)((rows + G::R - 1) / G::R);
@@ -1478,8 +1576,8 @@ hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, 
   const dim3 grid((unsigned)narrow_blocks(m)), block(256);
 #define RSVD_NT_NARROW(NS)                                                                     \
   case NS:                                                                                     \
-    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, \
-                       Y, ldy, nullptr);                                                       \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, false>), grid, block, 0, s, A, m, n, lda, Xt, \
+                       ldxt, c, Y, ldy, nullptr, nullptr);                                     \
     break;
   switch (ns) {
     RSVD_NT_NARROW(1) RSVD_NT_NARROW(2) RSVD_NT_NARROW(3)
@@ -1524,8 +1622,8 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
   const dim3 grid((unsigned)nblk), block(256);
 #define RSVD_NT_TALL(NT)                                                                      \
   case NT:                                                                                    \
-    hipLaunchKernelGGL(k_gemm_nt_tall<NT>, grid, block, 0, s, A, m, n, lda, Xt, ldxt, c, Y, ldy, \
-                       fro2_part, nullptr);                                                   \
+    hipLaunchKernelGGL((k_gemm_nt_tall<NT, false>), grid, block, 0, s, A, m, n, lda, Xt, ldxt, \
+                       c, Y, ldy, fro2_part, nullptr, nullptr);                               \
     break;
   switch ((c + 15) / 16) {
     RSVD_NT_TALL(1) RSVD_NT_TALL(2) RSVD_NT_TALL(3) RSVD_NT_TALL(4)
@@ -1561,16 +1659,16 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
   case NT:                                                                                        \
     if (cw == 1)                                                                                  \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 1>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
-                         rps, ntile, P, nullptr);                                                 \
+                         rps, ntile, P, nullptr, nullptr);                                             \
     else if (cw == 2)                                                                             \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 2>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
-                         rps, ntile, P, nullptr);                                                 \
+                         rps, ntile, P, nullptr, nullptr);                                             \
     else if (cw == 4)                                                                             \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 4>), grid, block, 0, s, A, m, n, lda, Q, ldq, c,   \
-                         rps, ntile, P, nullptr);                                                 \
+                         rps, ntile, P, nullptr, nullptr);                                             \
     else                                                                                          \
       hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, A, m, n, lda, Q, ldq, c, rps,     \
-                         ntile, P, nullptr);                                                      \
+                         ntile, P, nullptr, nullptr);                                             \
     break;
   switch ((c + 15) / 16) {
     RSVD_TN_TALL(1) RSVD_TN_TALL(2) RSVD_TN_TALL(3) RSVD_TN_TALL(4)
@@ -1766,31 +1864,38 @@ int nn_col_tiles(int c, int nt) { return (c + 16 * nt - 1) / (16 * nt); }
 int64_t nn_row_blocks(int64_t m) { return (m + 128 - 1) / 128; }
 
 // ---------------------------------------------------------------------------
-// Grouped launchers (one launch, blockIdx.y = problem).
-hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, int count, int maxblk, int nt,
-                                       hipStream_t s) {
-  if (count <= 0 || maxblk <= 0) return hipSuccess;
-  const dim3 grid((unsigned)maxblk, (unsigned)count), block(256);
-#define RSVD_G(NT)                                                                              \
-  case NT:                                                                                      \
-    hipLaunchKernelGGL(k_gemm_nt_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0,  \
-                       nullptr, 0, nullptr, a);                                                 \
-    break;
-  switch (nt) {
-    RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
-    default: return hipErrorInvalidValue;
-  }
-#undef RSVD_G
+// Grouped launchers.  The three tall passes run over a work list (one
+// block per item); the other steps take one launch with blockIdx.y =
+// problem.
+template <int NT, bool GR>
+hipError_t tall_grouped(const GArgTall* a, const GWork* wl, int nwork, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_nt_tall<NT, GR>), dim3((unsigned)nwork), dim3(256), 0, s, nullptr, 0,
+                     0, 0, nullptr, 0, 0, nullptr, 0, nullptr, a, wl);
   return hipGetLastError();
 }
 
-template <int NT>
-hipError_t narrow_grouped(const GArgNarrow* a, int count, int maxblk, int ns, hipStream_t s) {
-  const dim3 grid((unsigned)maxblk, (unsigned)count), block(256);
+hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, const GWork* wl, int nwork, int nt,
+                                       bool gram, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (gram && nt > kGramFuseMaxNt) return hipErrorInvalidValue;
+  switch (nt) {
+    case 1: return gram ? tall_grouped<1, true>(a, wl, nwork, s) : tall_grouped<1, false>(a, wl, nwork, s);
+    case 2: return gram ? tall_grouped<2, true>(a, wl, nwork, s) : tall_grouped<2, false>(a, wl, nwork, s);
+    case 3: return gram ? tall_grouped<3, true>(a, wl, nwork, s) : tall_grouped<3, false>(a, wl, nwork, s);
+    case 4: return gram ? tall_grouped<4, true>(a, wl, nwork, s) : tall_grouped<4, false>(a, wl, nwork, s);
+    case 5: return tall_grouped<5, false>(a, wl, nwork, s);
+    case 6: return tall_grouped<6, false>(a, wl, nwork, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NT, bool GR>
+hipError_t narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int ns, hipStream_t s) {
+  const dim3 grid((unsigned)nwork), block(256);
 #define RSVD_G(NS)                                                                              \
   case NS:                                                                                      \
-    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
-                       0, 0, nullptr, 0, a);                                                    \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, GR>), grid, block, 0, s, nullptr, 0, 0, 0,     \
+                       nullptr, 0, 0, nullptr, 0, a, wl);                                       \
     break;
   switch (ns) {
     RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
@@ -1800,38 +1905,39 @@ hipError_t narrow_grouped(const GArgNarrow* a, int count, int maxblk, int ns, hi
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int maxblk, int nt,
-                                         int ns, hipStream_t s) {
-  if (count <= 0 || maxblk <= 0) return hipSuccess;
+hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int nt,
+                                         int ns, bool gram, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (gram && nt > kGramFuseMaxNt) return hipErrorInvalidValue;
   switch (nt) {
-    case 1: return narrow_grouped<1>(a, count, maxblk, ns, s);
-    case 2: return narrow_grouped<2>(a, count, maxblk, ns, s);
-    case 3: return narrow_grouped<3>(a, count, maxblk, ns, s);
-    case 4: return narrow_grouped<4>(a, count, maxblk, ns, s);
-    case 5: return narrow_grouped<5>(a, count, maxblk, ns, s);
-    case 6: return narrow_grouped<6>(a, count, maxblk, ns, s);
+    case 1: return gram ? narrow_grouped<1, true>(a, wl, nwork, ns, s) : narrow_grouped<1, false>(a, wl, nwork, ns, s);
+    case 2: return gram ? narrow_grouped<2, true>(a, wl, nwork, ns, s) : narrow_grouped<2, false>(a, wl, nwork, ns, s);
+    case 3: return gram ? narrow_grouped<3, true>(a, wl, nwork, ns, s) : narrow_grouped<3, false>(a, wl, nwork, ns, s);
+    case 4: return gram ? narrow_grouped<4, true>(a, wl, nwork, ns, s) : narrow_grouped<4, false>(a, wl, nwork, ns, s);
+    case 5: return narrow_grouped<5, false>(a, wl, nwork, ns, s);
+    case 6: return narrow_grouped<6, false>(a, wl, nwork, ns, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt, int cw,
-                                       hipStream_t s) {
-  if (count <= 0 || maxblk <= 0) return hipSuccess;
-  const dim3 grid((unsigned)maxblk, (unsigned)count), block(512);
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, const GWork* wl, int nwork, int nt,
+                                       int cw, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nwork), block(512);
 #define RSVD_G(NT)                                                                              \
   case NT:                                                                                      \
     if (cw == 1)                                                                                \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 1>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
-                         0, 0, 0, 1, nullptr, a);                                               \
+                         0, 0, 0, 1, nullptr, a, wl);                                           \
     else if (cw == 2)                                                                           \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 2>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
-                         0, 0, 0, 1, nullptr, a);                                               \
+                         0, 0, 0, 1, nullptr, a, wl);                                           \
     else if (cw == 4)                                                                           \
       hipLaunchKernelGGL((k_gemm_tn_narrow<NT, 4>), grid, block, 0, s, nullptr, 0, 0, 0, nullptr, \
-                         0, 0, 0, 1, nullptr, a);                                               \
+                         0, 0, 0, 1, nullptr, a, wl);                                           \
     else                                                                                        \
       hipLaunchKernelGGL(k_gemm_tn_tall<NT>, grid, block, 0, s, nullptr, 0, 0, 0, nullptr, 0, 0, \
-                         0, 1, nullptr, a);                                                     \
+                         0, 1, nullptr, a, wl);                                                 \
     break;
   switch (nt) {
     RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)

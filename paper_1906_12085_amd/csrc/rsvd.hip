@@ -2023,6 +2023,9 @@ struct rsvd_grouped_s {
     int kind = 0;
     size_t off = 0;
     int count = 0, maxblk = 0, a0 = 0, a1 = 0;
+    size_t wl_off = 0;   // work list (GWork items) of the tall passes
+    int nwork = 0;
+    bool fuse = false;   // the fused-Gram kernels
   };
   int device = 0;
   char* ws = nullptr;          // the instances' workspaces
@@ -2067,13 +2070,73 @@ struct GroupedBuilder {
     memcpy(host.data() + op.off, rec.data(), rec.size() * sizeof(A));
     ops.push_back(op);
   }
+  // a tall pass: records plus its work list, whose items are ordered by
+  // their records' cost (largest first; the items of one record in order)
+  template <typename A>
+  void add_wl(int kind, const std::vector<A>& rec, const std::vector<int>& items_per_rec,
+              const std::vector<double>& cost, int a0, int a1, bool fuse) {
+    if (rec.empty()) return;
+    rsvd_grouped_s::Op op;
+    op.kind = kind;
+    op.off = (host.size() + 63) / 64 * 64;
+    op.count = (int)rec.size();
+    op.a0 = a0;
+    op.a1 = a1;
+    host.resize(op.off + rec.size() * sizeof(A));
+    memcpy(host.data() + op.off, rec.data(), rec.size() * sizeof(A));
+    std::vector<int> order(rec.size());
+    for (size_t r = 0; r < rec.size(); ++r) order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<GWork> wl;
+    for (int r : order)
+      for (int it = 0; it < items_per_rec[r]; ++it) wl.push_back(GWork{r, it});
+    op.wl_off = (host.size() + 63) / 64 * 64;
+    op.nwork = (int)wl.size();
+    op.fuse = fuse;
+    host.resize(op.wl_off + wl.size() * sizeof(GWork));
+    memcpy(host.data() + op.wl_off, wl.data(), wl.size() * sizeof(GWork));
+    ops.push_back(op);
+  }
 };
+
+// Tile parameters of one instance's tall passes: 128-row tiles per work
+// item of the A X and Y R^-1 products, and the shortest row split of the
+// A^T Q partial sums.
+struct GTune {
+  int tpp = (int)(kGroupedSplitRows / 128);
+  int64_t split_rows = kGroupedSplitRows;
+};
+
+constexpr int64_t kTnTileCols = 512;   // columns of A per A^T Q block
 
 int blocks256(int64_t total) { return (int)((total + 255) / 256); }
 
 // Whether the grouped path takes this fp32 instance: the tall kernels'
 // layout conditions for A, and a sketch width that is a multiple of 4.
-bool grouped_applies(const rsvd_instance& x, int64_t max_split) {
+// A tuning entry: rows per item a whole number of 128-row tiles and
+// kGroupedSplitRows <= rows <= 2^20 for both (the per-instance partials are
+// sized for splits of kGroupedSplitRows rows).
+bool tune_entry_valid(const rsvd_tune_entry& t) {
+  const int64_t lo = kGroupedSplitRows, hi = (int64_t)1 << 20;
+  return t.n > 0 && t.l > 0 && t.panel_rows >= lo && t.panel_rows <= hi &&
+         t.panel_rows % 128 == 0 && t.split_rows >= lo && t.split_rows <= hi &&
+         t.split_rows % 16 == 0;
+}
+
+// The entry for an instance's (n, l), else the defaults.
+GTune tune_for(const rsvd_instance& x, const rsvd_tune_entry* tune, int ntune) {
+  GTune g;
+  const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
+  for (int t = 0; t < ntune; ++t)
+    if (tune[t].n == x.n && tune[t].l == l) {
+      g.tpp = tune[t].panel_rows / 128;
+      g.split_rows = tune[t].split_rows;
+      break;
+    }
+  return g;
+}
+
+bool grouped_applies(const rsvd_instance& x, int64_t max_split, const GTune& tu) {
   const int64_t l = (x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n;
   if (l > kSmallSvdMaxC) return false;       // the grouped small kernels hold l <= 96
   if (l % 4 != 0 || x.n % 4 != 0 || x.lda % 4 != 0) return false;
@@ -2082,19 +2145,32 @@ bool grouped_applies(const rsvd_instance& x, int64_t max_split) {
   int ntile = 0;
   int64_t rps = 0;
   // the A^T Q splits record_group takes (32-bit buffer offsets within one)
-  tn_tall_splits(x.m, x.n, max_split, &rps, &ntile, kGroupedSplitRows);
+  tn_tall_splits(x.m, x.n, max_split, &rps, &ntile, tu.split_rows);
   return rps * x.lda * 4 < (1LL << 31) && (int64_t)31 * x.lda * 4 + (int64_t)ntile * 512 * 4 < (1LL << 31);
 }
 
 // Record Randomized PCA (the steps and kernels of rsvd_run<float>) for the
 // instances `ix` (same l and k) on their workspaces `pl`.
 void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<int>& ix,
-                  std::vector<rsvd_plan_s>& pl, int l, int k) {
+                  std::vector<rsvd_plan_s>& pl, const std::vector<GTune>& tune, int l, int k) {
   const int ntl = (l + 15) / 16;            // column tiles of l columns
   const int ntk = (k + 15) / 16;
   const int nsl = (l + 15) / 16;            // k slabs of an l-long contraction
   auto P = [&](int i) -> rsvd_plan_s& { return pl[i]; };
   auto X = [&](int i) -> const rsvd_instance& { return in[i]; };
+  // the m-row Gram matrices come from the products that write Y and Q1
+  // (fused epilogue) when l fits the fused kernels
+  const bool fuse = ntl <= kGramFuseMaxNt;
+  auto panels = [&](int i) {
+    const int64_t nt = (X(i).m + 127) / 128;
+    return (int)((nt + tune[i].tpp - 1) / tune[i].tpp);
+  };
+  auto gram_red = [&]() {   // the fused partials' fixed-order sum into Wg
+    std::vector<GArgRed> rr;
+    for (int i : ix)
+      rr.push_back({P(i).part, panels(i), l, l, P(i).Wg, l, blocks256((int64_t)l * l)});
+    B.add(G_RED, rr);
+  };
   {
     std::vector<GArgStat> r;
     for (int i : ix) r.push_back({nullptr, P(i).status, P(i).diag, kDiagWords, 1});
@@ -2108,7 +2184,8 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
     }
     B.add(G_FILL, r);
   }
-  // A X (X FP64, n x l) into Y; with fro2 on the first pass
+  // A X (X FP64, n x l) into Y; with fro2 on the first pass, and the Gram
+  // matrix Y^T Y when fused
   auto pass_nn = [&](bool first, bool from_zq) {
     std::vector<GArgCast> rc;
     for (int i : ix) {
@@ -2117,24 +2194,35 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
     }
     B.add(G_CAST_T, rc);
     std::vector<GArgTall> rt;
+    std::vector<int> it;
+    std::vector<double> ct;
     std::vector<std::vector<GArgNarrow>> rn(7);
+    std::vector<std::vector<int>> itn(7);
+    std::vector<std::vector<double>> cn(7);
     for (int i : ix) {
       const rsvd_instance& x = X(i);
+      double* gm = fuse ? P(i).part : nullptr;
       if (first || x.n > 96) {
         rt.push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Xs, x.n, l,
-                      (float*)P(i).Y, l, first ? P(i).fro2_part : nullptr, (int)tall_blocks(x.m)});
+                      (float*)P(i).Y, l, first ? P(i).fro2_part : nullptr, gm, tune[i].tpp});
+        it.push_back(panels(i));
+        ct.push_back((double)x.n);
       } else {
-        rn[(x.n + 15) / 16].push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Xs,
-                                       x.n, l, (float*)P(i).Y, l, (int)narrow_blocks(x.m)});
+        const int ns = (int)((x.n + 15) / 16);
+        rn[ns].push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Xs, x.n, l,
+                          (float*)P(i).Y, l, gm, tune[i].tpp});
+        itn[ns].push_back(panels(i));
+        cn[ns].push_back((double)x.n);
       }
     }
-    B.add(G_TALL, rt, ntl);
-    for (int ns = 1; ns <= 6; ++ns) B.add(G_NARROW, rn[ns], ntl, ns);
+    B.add_wl(G_TALL, rt, it, ct, ntl, 0, fuse);
+    for (int ns = 1; ns <= 6; ++ns) B.add_wl(G_NARROW, rn[ns], itn[ns], cn[ns], ntl, ns, fuse);
     if (first) {
       std::vector<GArgRedS> rs;
-      for (int i : ix) rs.push_back({P(i).fro2_part, (int)tall_blocks(X(i).m), P(i).scal, 1});
+      for (int i : ix) rs.push_back({P(i).fro2_part, panels(i), P(i).scal, 1});
       B.add(G_RED_S, rs);
     }
+    if (fuse) gram_red();
   };
   // W (c x c) = Y^T Y, FP64 partials then their fixed-order sum
   auto gram = [&](bool dbl, std::function<const void*(int)> Yp, std::function<int64_t(int)> rows) {
@@ -2155,17 +2243,26 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
     B.add(dbl ? G_CHOL_D : G_CHOL_F, r);
   };
   // CholeskyQR2 of Y (m x l): Q1 = Y R1^-1, R2 = chol(Q1^T Q1), Q = Q1 R2^-1
+  // (fused: Y^T Y came with the pass that wrote Y, Q1^T Q1 comes with Q1)
   auto cqr2 = [&]() {
-    gram(false, [&](int i) { return (const void*)P(i).Y; }, [&](int i) { return X(i).m; });
+    if (!fuse) gram(false, [&](int i) { return (const void*)P(i).Y; }, [&](int i) { return X(i).m; });
     chol(false, [&](int i) {
       return GArgChol{P(i).Wg, l, P(i).R1, P(i).R1inv, P(i).RinvT, 1, P(i).status, 1};
     });
     std::vector<GArgNarrow> rn;
-    for (int i : ix)
+    std::vector<int> it;
+    std::vector<double> ct;
+    for (int i : ix) {
       rn.push_back({(const float*)P(i).Y, X(i).m, l, l, (const float*)P(i).RinvT, l, l,
-                    (float*)P(i).Q1, l, (int)narrow_blocks(X(i).m)});
-    B.add(G_NARROW, rn, ntl, nsl);
-    gram(false, [&](int i) { return (const void*)P(i).Q1; }, [&](int i) { return X(i).m; });
+                    (float*)P(i).Q1, l, fuse ? P(i).part : nullptr, tune[i].tpp});
+      it.push_back(panels(i));
+      ct.push_back((double)l);
+    }
+    B.add_wl(G_NARROW, rn, it, ct, ntl, nsl, fuse);
+    if (fuse)
+      gram_red();
+    else
+      gram(false, [&](int i) { return (const void*)P(i).Q1; }, [&](int i) { return X(i).m; });
     chol(false, [&](int i) {
       return GArgChol{P(i).Wg, l, P(i).R2, P(i).R2inv, nullptr, 0, P(i).status, 1};
     });
@@ -2173,24 +2270,33 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
   // Z = A^T Q1 (FP64 n x l) into Zd, then Z2 = Zd R2^-1
   auto pass_tn = [&]() {
     std::vector<GArgTn> rt;
+    std::vector<int> blocks;
     std::vector<GArgRed> rr;
     std::vector<GArgSg> rs;
     for (int i : ix) {
       const rsvd_instance& x = X(i);
       int ntile = 0;
       int64_t rps = 0;
-      const int ns = (int)tn_tall_splits(x.m, x.n, P(i).max_split, &rps, &ntile, kGroupedSplitRows);
+      const int ns = (int)tn_tall_splits(x.m, x.n, P(i).max_split, &rps, &ntile, tune[i].split_rows);
       rt.push_back({(const float*)x.A, x.m, x.n, x.lda, (const float*)P(i).Q1, l, l, rps, ntile,
-                    P(i).part, ns * ntile});
+                    P(i).part});
+      blocks.push_back(ns * ntile);
       rr.push_back({P(i).part, ns, x.n, l, P(i).Zd, l, blocks256(x.n * (int64_t)l)});
       rs.push_back({P(i).Zd, P(i).R2inv, x.n, l, l, P(i).Z2, nullptr, 0, blocks256(x.n * (int64_t)l)});
     }
-    // one launch per A^T Q kernel (column waves 1, 2, 4, 8 by n)
+    // one launch per A^T Q kernel (column waves 1, 2, 4, 8 by n); a block
+    // costs about its split's rows times n
     for (int cw : {1, 2, 4, 8}) {
       std::vector<GArgTn> rc;
-      for (const GArgTn& r : rt)
-        if (tn_col_waves(r.n) == cw) rc.push_back(r);
-      B.add(G_TN, rc, ntl, cw);
+      std::vector<int> it;
+      std::vector<double> ct;
+      for (size_t r = 0; r < rt.size(); ++r)
+        if (tn_col_waves(rt[r].n) == cw) {
+          rc.push_back(rt[r]);
+          it.push_back(blocks[r]);
+          ct.push_back((double)rt[r].rps * (double)(rt[r].n < kTnTileCols ? rt[r].n : kTnTileCols));
+        }
+      B.add_wl(G_TN, rc, it, ct, ntl, cw, false);
     }
     B.add(G_RED, rr);
     B.add(G_SG_F, rs);
@@ -2278,10 +2384,15 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
   });
   {
     std::vector<GArgNarrow> r;
-    for (int i : ix)
+    std::vector<int> it;
+    std::vector<double> ct;
+    for (int i : ix) {
       r.push_back({(const float*)P(i).Q1, X(i).m, l, l, (const float*)P(i).MkT, l, k,
-                   (float*)X(i).U, X(i).ldu, (int)narrow_blocks(X(i).m)});
-    B.add(G_NARROW, r, ntk, nsl);
+                   (float*)X(i).U, X(i).ldu, nullptr, tune[i].tpp});
+      it.push_back(panels(i));
+      ct.push_back((double)k);
+    }
+    B.add_wl(G_NARROW, r, it, ct, ntk, nsl, false);
   }
   {
     std::vector<GArgSel> r;
@@ -2312,11 +2423,13 @@ hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
         e = launch_cast_t_from_f64_grouped<float>((const GArgCast*)a, op.count, op.maxblk, s);
         break;
       case G_TALL:
-        e = launch_gemm_nt_tall_grouped((const GArgTall*)a, op.count, op.maxblk, op.a0, s);
+        e = launch_gemm_nt_tall_grouped((const GArgTall*)a, (const GWork*)(g->args + op.wl_off),
+                                        op.nwork, op.a0, op.fuse, s);
         break;
       case G_NARROW:
-        e = launch_gemm_nt_narrow_grouped((const GArgNarrow*)a, op.count, op.maxblk, op.a0, op.a1,
-                                          s);
+        e = launch_gemm_nt_narrow_grouped((const GArgNarrow*)a,
+                                          (const GWork*)(g->args + op.wl_off), op.nwork, op.a0,
+                                          op.a1, op.fuse, s);
         break;
       case G_RED_S: e = launch_reduce_scalar_grouped((const GArgRedS*)a, op.count, s); break;
       case G_GRAM_F:
@@ -2330,7 +2443,8 @@ hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
       case G_CHOL_F: e = launch_chol_inv_grouped<float>((const GArgChol*)a, op.count, s); break;
       case G_CHOL_D: e = launch_chol_inv_grouped<double>((const GArgChol*)a, op.count, s); break;
       case G_TN:
-        e = launch_gemm_tn_tall_grouped((const GArgTn*)a, op.count, op.maxblk, op.a0, op.a1, s);
+        e = launch_gemm_tn_tall_grouped((const GArgTn*)a, (const GWork*)(g->args + op.wl_off),
+                                        op.nwork, op.a0, op.a1, s);
         break;
       case G_SG_F: e = launch_small_gemm_grouped<float>((const GArgSg*)a, op.count, op.maxblk, s); break;
       case G_SG_D: e = launch_small_gemm_grouped<double>((const GArgSg*)a, op.count, op.maxblk, s); break;
@@ -2367,15 +2481,21 @@ void grouped_free(rsvd_grouped_s* g) {
 extern "C" {
 
 int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                  const rsvd_tune_entry* tune, int32_t ntune,
                                   rsvd_grouped_t* grouped) {
   if (!batch || !grouped || count < 0 || (count > 0 && !inst)) return RSVD_ERR_ARG;
+  if (ntune < 0 || (ntune > 0 && !tune)) return RSVD_ERR_ARG;
   *grouped = nullptr;
   if (batch->dtype != RSVD_F32) return RSVD_ERR_ARG;
+  for (int t = 0; t < ntune; ++t)
+    if (!tune_entry_valid(tune[t])) return RSVD_ERR_ARG;
+  std::vector<GTune> tu(count);
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(batch->plan[0], inst[i]);
     if (rc != RSVD_OK) return rc;
     if (instance_dtype(batch->plan[0], inst[i]) != RSVD_F32 || !inst[i].U) return RSVD_ERR_ARG;
-    if (!grouped_applies(inst[i], batch->plan[0]->max_split)) return RSVD_ERR_ARG;
+    tu[i] = tune_for(inst[i], tune, ntune);
+    if (!grouped_applies(inst[i], batch->plan[0]->max_split, tu[i])) return RSVD_ERR_ARG;
   }
   if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
   rsvd_grouped_s* g = new (std::nothrow) rsvd_grouped_s();
@@ -2400,6 +2520,11 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
     // batch's split limit; the grouped launchers cap at the same count)
     const int64_t gsplit = (x.m + kGroupedSplitRows - 1) / kGroupedSplitRows;
     p.max_split = gsplit < batch->plan[0]->max_split ? gsplit : batch->plan[0]->max_split;
+    // the panels of the NT products write one partial each: at most
+    // max_split of them
+    const int64_t ntiles = (x.m + 127) / 128;
+    const int64_t tpp_min = (ntiles + p.max_split - 1) / p.max_split;
+    if (tu[i].tpp < tpp_min) tu[i].tpp = (int)tpp_min;
     off[i] = total;
     total += carve(&p, nullptr);
   }
@@ -2425,7 +2550,7 @@ int32_t rsvd_batch_grouped_create(rsvd_batch_t batch, const rsvd_instance* inst,
         ix.push_back(j);
         done[j] = 1;
       }
-    record_group(B, inst, ix, g->plans, l, k);
+    record_group(B, inst, ix, g->plans, tu, l, k);
   }
   g->ops = B.ops;
   if (!B.host.empty()) {
@@ -2453,6 +2578,116 @@ int32_t rsvd_batch_grouped_destroy(rsvd_grouped_t grouped) {
   if (!grouped) return RSVD_OK;
   if (hipSetDevice(grouped->device) == hipSuccess) (void)hipDeviceSynchronize();
   grouped_free(grouped);
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_grouped_tune(rsvd_batch_t batch, const rsvd_instance* inst, int32_t count,
+                                rsvd_tune_entry* out, int32_t cap, int32_t* nout, void* stream) {
+  if (!batch || !out || !nout || cap < 0 || count < 0 || (count > 0 && !inst)) return RSVD_ERR_ARG;
+  *nout = 0;
+  // buckets of equal (n, l), in order of first appearance
+  std::vector<rsvd_tune_entry> key;
+  std::vector<std::vector<rsvd_instance>> members;
+  for (int i = 0; i < count; ++i) {
+    const rsvd_instance& x = inst[i];
+    const int32_t l = (int32_t)((x.k + (int64_t)x.p < x.n) ? x.k + (int64_t)x.p : x.n);
+    size_t b = 0;
+    while (b < key.size() && !(key[b].n == x.n && key[b].l == l)) ++b;
+    if (b == key.size()) {
+      key.push_back(rsvd_tune_entry{(int32_t)x.n, l, (int32_t)kGroupedSplitRows,
+                                    (int32_t)kGroupedSplitRows});
+      members.emplace_back();
+    }
+    members[b].push_back(x);
+  }
+  if ((int32_t)key.size() > cap) return RSVD_ERR_ARG;
+  if (hipSetDevice(batch->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return RSVD_ERR_DEVICE;
+  }
+  // mean time of a launch of the bucket's grouped batch under one entry
+  // (one untimed launch first)
+  auto timed = [&](const std::vector<rsvd_instance>& xs, const rsvd_tune_entry& t,
+                   float* ms) -> int32_t {
+    rsvd_grouped_t g = nullptr;
+    int32_t rc = rsvd_batch_grouped_create(batch, xs.data(), (int32_t)xs.size(), &t, 1, &g);
+    if (rc != RSVD_OK) return rc;
+    constexpr int kReps = 3;
+    rc = grouped_launch(g, s) == hipSuccess ? RSVD_OK : RSVD_ERR_DEVICE;
+    if (rc == RSVD_OK && hipEventRecord(e0, s) != hipSuccess) rc = RSVD_ERR_DEVICE;
+    for (int r = 0; r < kReps && rc == RSVD_OK; ++r)
+      if (grouped_launch(g, s) != hipSuccess) rc = RSVD_ERR_DEVICE;
+    if (rc == RSVD_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                          hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+      rc = RSVD_ERR_DEVICE;
+    *ms /= kReps;
+    (void)rsvd_batch_grouped_destroy(g);
+    return rc;
+  };
+  static const int32_t kRows[] = {1024, 2048, 4096, 8192};
+  int32_t rc = RSVD_OK;
+  for (size_t b = 0; b < key.size() && rc == RSVD_OK; ++b) {
+    rsvd_tune_entry best = key[b];
+    float tbest = 0.f;
+    rc = timed(members[b], best, &tbest);
+    // rows per work item of the A X and Y R^-1 products, then the A^T Q
+    // split length with the best of those
+    for (int pass = 0; pass < 2 && rc == RSVD_OK; ++pass)
+      for (int32_t r : kRows) {
+        rsvd_tune_entry t = best;
+        (pass == 0 ? t.panel_rows : t.split_rows) = r;
+        if (t.panel_rows == best.panel_rows && t.split_rows == best.split_rows) continue;
+        float ms = 0.f;
+        if ((rc = timed(members[b], t, &ms)) != RSVD_OK) break;
+        if (ms < tbest) {
+          tbest = ms;
+          best = t;
+        }
+      }
+    out[b] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != RSVD_OK) return rc;
+  *nout = (int32_t)key.size();
+  return RSVD_OK;
+}
+
+int32_t rsvd_batch_grouped_graph_create(rsvd_grouped_t grouped, rsvd_batch_graph_t* graph) {
+  if (!grouped || !graph) return RSVD_ERR_ARG;
+  *graph = nullptr;
+  if (hipSetDevice(grouped->device) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return RSVD_ERR_DEVICE;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t el = grouped_launch(grouped, cap);
+    e = hipStreamEndCapture(cap, &gr);
+    if (el != hipSuccess) e = el;
+  }
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess || !gr) {
+    if (gr) (void)hipGraphDestroy(gr);
+    (void)hipGetLastError();
+    return RSVD_ERR_DEVICE;
+  }
+  rsvd_batch_graph_s* h = new (std::nothrow) rsvd_batch_graph_s();
+  if (!h) {
+    (void)hipGraphDestroy(gr);
+    return RSVD_ERR_NOMEM;
+  }
+  h->graph = gr;
+  if (hipGraphInstantiate(&h->exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    delete h;
+    return RSVD_ERR_DEVICE;
+  }
+  *graph = h;
   return RSVD_OK;
 }
 

@@ -261,17 +261,30 @@ int64_t jacobi_eig_max_n();
 // selects the problem, whose arguments replace the kernel's own, and blocks
 // with blockIdx.x >= nblk (that problem's own grid) leave at once, so every
 // problem runs exactly the blocks an ordinary launch would give it.
+//
+// The passes over tall matrices (the A X and Y R^-1 products, A^T Q) take a
+// work list instead: a 1-D grid with one block per item {problem, item},
+// ordered on the host (largest problems first).  For the two NT products an
+// item is a row panel of `tpp` 128-row tiles that the block walks one tile
+// after the other, writing one FP64 partial per panel: the sum of squares
+// of A (fro2 != nullptr) and, with gram != nullptr, the Gram matrix Y^T Y of
+// the panel's output rows, taken on the FP64 matrix cores straight from the
+// FP32 accumulator registers (c x c, symmetric, at gram + item c^2).  For
+// A^T Q an item is one block of the problem's ordinary grid.
+struct GWork {
+  int32_t inst, item;
+};
 struct GArgTall {   // k_gemm_nt_tall
   const float* A; int64_t m, n, lda; const float* Xt; int64_t ldxt; int c;
-  float* Y; int64_t ldy; double* fro2; int nblk;
+  float* Y; int64_t ldy; double* fro2; double* gram; int tpp;
 };
-struct GArgNarrow {   // k_gemm_nt_narrow (nblk also strides the persistent loop)
+struct GArgNarrow {   // k_gemm_nt_narrow
   const float* A; int64_t m, n, lda; const float* Xt; int64_t ldxt; int c;
-  float* Y; int64_t ldy; int nblk;
+  float* Y; int64_t ldy; double* gram; int tpp;
 };
-struct GArgTn {   // k_gemm_tn_tall
+struct GArgTn {   // k_gemm_tn_tall, k_gemm_tn_narrow
   const float* A; int64_t m, n, lda; const float* Q; int64_t ldq; int c; int64_t rps;
-  int ntile; double* P; int nblk;
+  int ntile; double* P;
 };
 struct GArgGram {   // k_gram_f64
   const void* Y; int64_t m; int c; int64_t ldy; double* P; int64_t rpb; int nblk;
@@ -333,12 +346,15 @@ int64_t nn_row_blocks(int64_t m);
 // Grouped launchers: `a` is a device array of `count` argument records,
 // `maxblk` the largest nblk among them; the template choices (column tiles
 // nt, k slabs ns, element type) are the same for every problem of a launch.
-hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, int count, int maxblk, int nt,
-                                       hipStream_t s);
-hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, int count, int maxblk, int nt,
-                                         int ns, hipStream_t s);
-hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, int count, int maxblk, int nt, int cw,
-                                       hipStream_t s);
+// The three work-list launchers take the item list `wl` (nwork items) and
+// the records it indexes; gram selects the fused-Gram kernels (nt <= 4).
+constexpr int kGramFuseMaxNt = 4;
+hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, const GWork* wl, int nwork, int nt,
+                                       bool gram, hipStream_t s);
+hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int nt,
+                                         int ns, bool gram, hipStream_t s);
+hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, const GWork* wl, int nwork, int nt,
+                                       int cw, hipStream_t s);
 template <typename T>
 hipError_t launch_gram_f64_grouped(const GArgGram* a, int count, int maxblk, int nt, int cmax,
                                    hipStream_t s);

@@ -166,6 +166,18 @@ def batch_shapes(c=None):
     return out
 
 
+def batch_problems(torch, dev, c=None):
+    """The batched workload's matrices on the device (no noise), as
+    (A, k, p, q, t) per instance, by the device recipe of spiked_noisy_torch."""
+    c = c or CONFIG4
+    out = []
+    for i, (m, n, r, k) in enumerate(batch_shapes(c)):
+        A = spiked_noisy_torch(c["seed"] * 100003 + i, m, n, exp_sigma(n, r), 0.0, dev,
+                               torch.float32)
+        out.append((A, k, c["p"], c["q"], c["t"]))
+    return out
+
+
 CONFIG5 = dict(rate=200.0, seconds=60.0, m_lo=1000, m_hi=1_000_000, m_multiple=64,
                n_choices=(128, 256, 512, 1024), alpha_lo=0.5, alpha_hi=2.0,
                t_choices=(0.9, 0.95, 0.99), storage_choices=("fp32", "bf16"), k=16, p=8, q=2,

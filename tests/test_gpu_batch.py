@@ -229,3 +229,71 @@ def test_batch_grouped_arguments():
         b64.grouped([(A.double(), 8, 8, 1, 0.9)])       # fp32 batches only
     assert ei.value.code == rs.RSVD_ERR_ARG
     b64.close()
+
+
+def test_batch_grouped_tuned_graph_unfused():
+    # the work-list passes under non-default tile parameters (rows per item
+    # and A^T Q split length from a tuning table) give the same K and status
+    # as the defaults and sigma to FP32 rounding; sketches wider than 64
+    # columns take the separate m-row Gram kernels (no fused epilogue); a
+    # captured grouped batch replays bit for bit the eager launch, with
+    # eager work between replays; the autotuner returns one valid entry per
+    # (n, l); an entry outside the limits is an argument error
+    dt = torch.float32
+    announce("grouped batch: tuning table, l = 72 (unfused Gram), graph replays, autotuner")
+    rng = np.random.default_rng(91)
+    shapes = [(9000, 128, 64), (3000, 128, 64), (6000, 256, 16), (2500, 64, 16), (12000, 256, 64),
+              (700, 64, 8)]
+    probs = []
+    for m, n, k in shapes:
+        sig = np.exp(-rng.uniform(0.01, 0.2) * np.arange(1, n + 1))
+        A0 = rounded(synth.haar(rng, m, n) @ np.diag(sig) @ synth.haar(rng, n, n).T, dt)
+        probs.append((dev(A0, dt), k, 8, 2, 0.95, A0))
+    b = rs.Batch(2, 12000, 256, 72, dt, seed=SEED)
+    g1 = b.grouped([pr[:5] for pr in probs])
+    g1.launch()
+    torch.cuda.synchronize()
+    buckets = sorted({(A.shape[1], min(k + p, A.shape[1])) for A, k, p, *_ in probs})
+    tune = [(n, l, 2048, 4096) for n, l in buckets]
+    g2 = b.grouped([pr[:5] for pr in probs], tune=tune)
+    g2.launch()
+    torch.cuda.synchronize()
+    eager = [{key: o[key].clone() for key in ("U", "S", "V", "K", "status")} for o in g2.outs]
+    for (A, k, p, q, t, A0), o1, o2 in zip(probs, g1.outs, g2.outs):
+        assert torch.equal(o1["K"], o2["K"]) and torch.equal(o1["status"], o2["status"])
+        # other row splits and panels round the FP32 sums in another order:
+        # the values differ by about u sigma_1 (not relative to each sigma_i)
+        s1 = host(o1["S"])
+        assert np.max(np.abs(s1 - host(o2["S"]))) <= 1e-6 * s1[0]
+        n = A.shape[1]
+        G = rounded(synth.gaussian_omega(SEED, n, min(k + p, n)), dt)
+        orc = oracle.rsvd(A0, G, k, p, q, t)
+        S, U, V = host(o2["S"]), host(o2["U"]), host(o2["V"])
+        assert np.max(np.abs(S - orc.S) / orc.S) <= 1e-4, A.shape
+        assert oracle.principal_angle_max(orc.V, V) <= 1e-3
+        assert oracle.principal_angle_max(orc.U, U) <= 1e-3
+        assert int(o2["K"].item()) == orc.K and int(o2["status"].item()) == orc.status
+    gr = g2.graph()
+    for rep in range(3):
+        for o in g2.outs:
+            for key in ("U", "S", "V"):
+                o[key].fill_(float("nan"))
+            o["K"].fill_(-9)
+            o["status"].fill_(-99)
+        torch.cuda.synchronize()
+        gr.launch()
+        torch.cuda.synchronize()
+        for o, e in zip(g2.outs, eager):
+            for key in e:
+                assert torch.equal(o[key], e[key]), (rep, key)
+    gr.close()
+    entries = b.tune_grouped([pr[:5] for pr in probs])
+    assert sorted((n, l) for n, l, _, _ in entries) == buckets
+    for _, _, pr_, sr in entries:
+        assert pr_ in (1024, 2048, 4096, 8192) and sr in (1024, 2048, 4096, 8192)
+    with pytest.raises(rs.RSVDError) as ei:
+        b.grouped([pr[:5] for pr in probs], tune=[(128, 72, 1000, 1024)])
+    assert ei.value.code == rs.RSVD_ERR_ARG
+    g1.close()
+    g2.close()
+    b.close()

@@ -63,6 +63,9 @@ def parse():
                     help="length of the serving leg's Poisson stream (the workload's 60 s)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven fp32 instances)")
+    ap.add_argument("--batch-grouped-only", action="store_true",
+                    help="in the batched leg, time only the grouped batch (tuned tiles; for "
+                         "profiling it alone)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the 262144 x 1024 mixed-precision workload legs")
     ap.add_argument("--no-krylov", action="store_true",
@@ -115,8 +118,8 @@ KERNEL_INFO = {
 # again.
 TRAFFIC = {
     "eigensolver": (3.2842e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
-    "pass_nn": (2.3911e+09, "gemm.hip", "k_gemm_nt_tall", "de061d75de085870"),
-    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "e06f144a6ab9e4c9"),
+    "pass_nn": (2.3905e+09, "gemm.hip", "k_gemm_nt_tall", "b17a75a2a07e1bbd"),
+    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "f6ccc62099be49a2"),
     "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
     "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
     "pass_nn_bf16": (1.5362e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
@@ -396,7 +399,7 @@ def krylov_leg(rs, torch, A, m, n, k, p, i, t, seed, steps, warmup, stream):
             "sigma_rel_err_vs_fp64_path": sig_err}
 
 
-def batch_leg(rs, torch, dev, steps, warmup, nslots):
+def batch_leg(rs, torch, dev, steps, warmup, nslots, grouped_only=False):
     """The batched workload (512 fp32 instances of uneven shapes, each
     Randomized PCA with k = min(32, n/4), p = 8, q = 2) solved three ways on
     the same device-resident inputs: one plan solving them one after another
@@ -431,6 +434,16 @@ def batch_leg(rs, torch, dev, steps, warmup, nslots):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    if grouped_only:
+        gg = b.grouped(None, prepared=prepared, tune=rs.load_tune_cache())
+        grouped_s = timed(gg.launch)
+        gg.close()
+        b.close()
+        del probs, prepared
+        torch.cuda.empty_cache()
+        a_bytes = sum(m * n * 4 for m, n, _, _ in shapes)
+        return {"instances": len(shapes), "ms_per_batch": {"batch_grouped": round(1e3 * grouped_s, 2)},
+                "frac_of_hbm_bound": round(6 * a_bytes / 8e12 / grouped_s, 3)}
     eager_s = timed(lambda: b.solve(None, prepared=prepared))
     keep = [o["S"].clone() for o in prepared[0]]
     keep_k = [int(o["K"].item()) for o in prepared[0]]
@@ -978,7 +991,8 @@ def main():
     if not args.no_batch:
         print(f"[bench] batched leg: {synth.CONFIG4['count']} instances", file=sys.stderr,
               flush=True)
-        legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS)
+        legs["batch"] = batch_leg(rs, torch, dev, max(2, min(args.steps, 5)), 1, BATCH_SLOTS,
+                                  args.batch_grouped_only)
 
     if not args.no_serve:
         print(f"[bench] serving leg: Poisson arrivals at 200/s for {args.serve_seconds:g} s "

@@ -2240,7 +2240,7 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
   auto chol = [&](bool dbl, std::function<GArgChol(int)> f) {
     std::vector<GArgChol> r;
     for (int i : ix) r.push_back(f(i));
-    B.add(dbl ? G_CHOL_D : G_CHOL_F, r);
+    B.add(dbl ? G_CHOL_D : G_CHOL_F, r, l);   // every factor of the group is l x l
   };
   // CholeskyQR2 of Y (m x l): Q1 = Y R1^-1, R2 = chol(Q1^T Q1), Q = Q1 R2^-1
   // (fused: Y^T Y came with the pass that wrote Y, Q1^T Q1 comes with Q1)
@@ -2440,8 +2440,8 @@ hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
                                             s);
         break;
       case G_RED: e = launch_reduce_partials_grouped((const GArgRed*)a, op.count, op.maxblk, s); break;
-      case G_CHOL_F: e = launch_chol_inv_grouped<float>((const GArgChol*)a, op.count, s); break;
-      case G_CHOL_D: e = launch_chol_inv_grouped<double>((const GArgChol*)a, op.count, s); break;
+      case G_CHOL_F: e = launch_chol_inv_grouped<float>((const GArgChol*)a, op.count, op.a0, s); break;
+      case G_CHOL_D: e = launch_chol_inv_grouped<double>((const GArgChol*)a, op.count, op.a0, s); break;
       case G_TN:
         e = launch_gemm_tn_tall_grouped((const GArgTn*)a, (const GWork*)(g->args + op.wl_off),
                                         op.nwork, op.a0, op.a1, s);

@@ -367,7 +367,7 @@ template <typename T>
 hipError_t launch_cast_t_from_f64_grouped(const GArgCast* a, int count, int maxblk,
                                           hipStream_t s);
 template <typename T>
-hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, hipStream_t s);
+hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, int cmax, hipStream_t s);
 template <typename T>
 hipError_t launch_small_gemm_grouped(const GArgSg* a, int count, int maxblk, hipStream_t s);
 hipError_t launch_jacobi_svd_small_grouped(const GArgJac* a, int count, int cmax, int acc_j,

@@ -77,21 +77,23 @@ __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, 
 
 // ---------------------------------------------------------------------------
 // Cholesky factor R (upper, W = R^T R) and its inverse of a c x c SPD matrix
-// (c <= 96), one workgroup of 256 threads, in one pass over the columns:
-// the symmetric elimination that turns W into R is applied at the same time
-// to an identity matrix B beside it (as in Gauss-Jordan elimination on
-// [W | I]), which turns B into L^-1 = R^-T (L = R^T); R^-1 is B transposed.
-// Thread (ti, tk) = (tid / 16, tid % 16) keeps the elements (ti + 16u,
-// tk + 16v), u, v < 6, of W and of B in registers; the 16 owners of a row are
-// one 16-lane group of one wave.  Step j: the owners of row j take
-// d = w_jj from the lane that holds it (cross-lane read), scale their part of
-// row j of W and of B by 1/sqrt(d) (row j of R, row j of L^-1) and publish
-// both in LDS; after one barrier every thread subtracts r_ji times row j from
-// its rows i > j, in W and in B.  The LDS rows alternate between steps, so
-// one barrier per step suffices.  The block index of the step (j / 16) is
-// unrolled so that register subscripts are compile-time constants.
+// (c <= 96), one workgroup of 256 threads, blocked in 16 x 16 blocks.  The
+// matrix, padded to cp = 16 ceil(c / 16) with the identity, sits in LDS as
+// its lower triangle A (turned into L = R^T in place), beside B (the identity,
+// turned into L^-1 = R^-T).  For each block column k:
+//   1. one wave factors the diagonal block, A_kk = L_kk L_kk^T, and inverts
+//      it, X_kk = L_kk^-1, by the symmetric elimination applied to [A_kk | I]
+//      (each step: 1/sqrt of the pivot, the pivot column and the scaled pivot
+//      row of X shared by cross-lane reads; no workgroup barrier);
+//   2. L_ik = A_ik X_kk^T below it, and the block row k of B, B_kj <- X_kk B_kj
+//      (j < k), B_kk = X_kk;
+//   3. the trailing update A_ij -= L_ik L_jk^T (k < j <= i) and the rows below
+//      in B, B_ij -= L_ik B_kj (i > k, j <= k).
+// Steps 2 and 3 are 16 x 16 x 16 products on the FP64 matrix cores, spread
+// over the four waves; three barriers per block column.  This is the block
+// form of the elimination on [W | I] (Gauss-Jordan with the symmetric pivot).
 constexpr int kCiT = 256;
-constexpr int kCiU = 6;                       // 16 * 6 = 96 rows and columns
+constexpr int kCiMax = 96;
 
 // 1/sqrt(x): hardware estimate plus two Newton steps.
 __device__ __forceinline__ double rsq_newton(double x) {
@@ -101,51 +103,34 @@ __device__ __forceinline__ double rsq_newton(double x) {
   return fma(y, fma(-h * y, y, 0.5), y);
 }
 
-// Updates are branch-free: an element outside the active rows gets an exact
-// zero subtracted (the LDS rows start at zero and only ever hold finite
-// values), so no lane diverges inside a step.
-// A pivot <= 0 (not positive definite to working precision) is recorded in
-// *bad and checked once after the factorisation; meanwhile it only produces
-// non-finite values.
-template <int UB>
-__device__ __forceinline__ void chol_block(double (&a)[kCiU][kCiU], double (&b)[kCiU][kCiU], int c,
-                                           int ti, int tk, int lane, int wv, double (*rowR)[96],
-                                           double (*rowB)[96], int* bad) {
-  for (int jj = 0; jj < 16; ++jj) {
-    const int j = 16 * UB + jj;
-    if (j >= c) return;
-    const int p = j & 1;
-    if (ti == jj) {
-      const double d = __shfl(a[UB][UB], (lane & 48) + jj);
-      if (!(d > 0.0)) *bad = 1;
-      const double rs = rsq_newton(d);
+// acc += sgn P Q for 16 x 16 blocks P, Q in LDS (row stride ld); QT: Q is
+// read as the transpose of the block at Q.  FP64 16x16x4 operands: lane
+// (x, y) = (l % 16, l / 16) supplies P[x][4s + y] and Q[4s + y][x].
+template <bool QT>
+__device__ __forceinline__ f64x4 mm16(const double* P, const double* Q, int ld, double sgn,
+                                      f64x4 acc) {
+  const int lane = threadIdx.x & 63, x = lane & 15, y = lane >> 4;
 #pragma unroll
-      for (int v = 0; v < kCiU; ++v) {
-        const int k = tk + 16 * v;
-        const bool on = k >= j && k < c;
-        a[UB][v] = on ? a[UB][v] * rs : a[UB][v];
-        rowR[p][k] = on ? a[UB][v] : 0.0;
-        // row j of B is zero right of the diagonal
-        b[UB][v] = b[UB][v] * rs;
-        rowB[p][k] = k < c ? b[UB][v] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = UB; u < kCiU; ++u) {
-      if (16 * u + 4 * wv + 3 <= j) continue;   // no row of this wave is below j
-      const int i = ti + 16 * u;
-      const double rji = (i > j && i < c) ? rowR[p][i] : 0.0;
-      // W: the whole trailing square (its lower half stays the mirror image
-      // and is never read); columns left of j read a zero from rowR.
-      // B: columns right of j read a zero from rowB.
-#pragma unroll
-      for (int v = 0; v < kCiU; ++v) {
-        a[u][v] = fma(-rji, rowR[p][tk + 16 * v], a[u][v]);
-        b[u][v] = fma(-rji, rowB[p][tk + 16 * v], b[u][v]);
-      }
-    }
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const double av = sgn * P[x * ld + 4 * s4 + y];
+    const double bv = QT ? Q[x * ld + 4 * s4 + y] : Q[(4 * s4 + y) * ld + x];
+    acc = Mfma<double>::run(av, bv, acc);
   }
+  return acc;
+}
+// a 16 x 16 block in the matrix-core output layout (value e of lane l at row
+// l / 16 + 4 e, column l % 16)
+__device__ __forceinline__ f64x4 ld16(const double* C, int ld) {
+  const int lane = threadIdx.x & 63;
+  f64x4 v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = C[Mfma<double>::row(lane, e) * ld + (lane & 15)];
+  return v;
+}
+__device__ __forceinline__ void st16(double* C, int ld, f64x4 v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) C[Mfma<double>::row(lane, e) * ld + (lane & 15)] = v[e];
 }
 
 template <typename T>
@@ -160,33 +145,129 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     W = a.W; c = a.c; R = a.R; Rinv = a.Rinv; RinvT = (T*)a.RinvT; trans = a.trans;
     status = a.status;
   }
-  __shared__ double rowR[2][96];
-  __shared__ double rowB[2][96];
+  extern __shared__ double csm[];
+  const int nb = (c + 15) >> 4, cp = 16 * nb, ld = cp + 1;
+  double* Ls = csm;                  // A, then L (lower blocks)
+  double* Bs = csm + cp * ld;        // I, then L^-1 (lower blocks)
   __shared__ int bad;
-  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double a[kCiU][kCiU], b[kCiU][kCiU];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // W into LDS with every load in flight at once (one memory latency), the
+  // identity past c; then the lower triangle takes (w_ij + w_ji) / 2
+  {
+    constexpr int PER = (kCiMax * kCiMax + kCiT - 1) / kCiT;
+    double v[PER];
 #pragma unroll
-  for (int u = 0; u < kCiU; ++u)
-#pragma unroll
-    for (int v = 0; v < kCiU; ++v) {
-      const int i = ti + 16 * u, k = tk + 16 * v;
-      a[u][v] = (i < c && k < c) ? 0.5 * (W[i * c + k] + W[k * c + i]) : 0.0;
-      b[u][v] = (i == k && i < c) ? 1.0 : 0.0;
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kCiT;
+      v[u] = e < c * c ? W[e] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kCiT;
+      if (e < c * c) {
+        const int i = e / c, j = e - i * c;
+        Ls[i * ld + j] = v[u];
+      }
+    }
+  }
+  for (int e = tid; e < cp * cp; e += kCiT) {
+    const int i = e / cp, j = e - i * cp;
+    if (i >= c || j >= c) Ls[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    Bs[i * ld + j] = (i == j) ? 1.0 : 0.0;
+  }
   if (tid == 0) bad = 0;
-  for (int e = tid; e < 2 * 96; e += kCiT) {
-    rowR[e / 96][e % 96] = 0.0;
-    rowB[e / 96][e % 96] = 0.0;
+  __syncthreads();
+  // each lower element is written by the one thread that reads its mirror
+  for (int e = tid; e < c * c; e += kCiT) {
+    const int i = e / c, j = e - i * c;
+    if (i > j) Ls[i * ld + j] = 0.5 * (Ls[i * ld + j] + Ls[j * ld + i]);
   }
   __syncthreads();
-  chol_block<0>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  chol_block<1>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  chol_block<2>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  chol_block<3>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  chol_block<4>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  chol_block<5>(a, b, c, ti, tk, lane, wv, rowR, rowB, &bad);
-  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const int k0 = 16 * k;
+    if (wave == 0) {
+      // 1. lane (r, g) holds columns 4 g .. 4 g + 3 of row r of the block
+      const int r = lane & 15, g = lane >> 4;
+      double d[4], xb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[q] = Ls[(k0 + r) * ld + k0 + 4 * g + q];
+        xb[q] = (r == 4 * g + q) ? 1.0 : 0.0;
+      }
+      int badl = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int gj = j >> 2, qj = j & 3;
+        const double dj = __shfl(d[qj], j + 16 * gj);               // pivot a_jj
+        badl |= (dj > 0.0) ? 0 : 1;
+        const double rs = rsq_newton(dj);
+        const double lr = __shfl(d[qj], r + 16 * gj) * rs;          // l_rj
+        double lc[4], bj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          lc[q] = __shfl(d[qj], 4 * g + q + 16 * gj) * rs;          // l_(4g+q) j
+          bj[q] = __shfl(xb[q], j + 16 * g) * rs;                   // scaled row j of X
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = 4 * g + q;
+          if (r == j) {
+            xb[q] = bj[q];
+            d[q] = (col == j) ? dj * rs : d[q];
+          } else if (r > j) {
+            d[q] = (col == j) ? lr : ((col > j) ? fma(-lr, lc[q], d[q]) : d[q]);
+            xb[q] = fma(-lr, bj[q], xb[q]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = 4 * g + q;
+        Ls[(k0 + r) * ld + k0 + col] = (col <= r) ? d[q] : 0.0;
+        Bs[(k0 + r) * ld + k0 + col] = (col <= r) ? xb[q] : 0.0;
+      }
+      if (badl && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    // 2. panel and block row k of B
+    const int m1 = nb - k - 1;
+    for (int t = wave; t < m1 + k; t += 4) {
+      if (t < m1) {
+        const int i0 = 16 * (k + 1 + t);
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm16<true>(Ls + i0 * ld + k0, Bs + k0 * ld + k0, ld, 1.0, acc);   // A_ik X_kk^T
+        st16(Ls + i0 * ld + k0, ld, acc);
+      } else {
+        const int j0 = 16 * (t - m1);
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm16<false>(Bs + k0 * ld + k0, Bs + k0 * ld + j0, ld, 1.0, acc);  // X_kk B_kj
+        st16(Bs + k0 * ld + j0, ld, acc);
+      }
+    }
+    __syncthreads();
+    // 3. trailing update of A and the rows of B below block row k
+    const int nA = m1 * (m1 + 1) / 2, nBt = m1 * (k + 1);
+    for (int t = wave; t < nA + nBt; t += 4) {
+      if (t < nA) {
+        int ii = 0, rem = t;
+        while (rem > ii) {
+          rem -= ii + 1;
+          ++ii;
+        }
+        const int i0 = 16 * (k + 1 + ii), j0 = 16 * (k + 1 + rem);
+        f64x4 acc = ld16(Ls + i0 * ld + j0, ld);
+        acc = mm16<true>(Ls + i0 * ld + k0, Ls + j0 * ld + k0, ld, -1.0, acc);  // -L_ik L_jk^T
+        st16(Ls + i0 * ld + j0, ld, acc);
+      } else {
+        const int u = t - nA, ii = u / (k + 1), jj = u - ii * (k + 1);
+        const int i0 = 16 * (k + 1 + ii), j0 = 16 * jj;
+        f64x4 acc = ld16(Bs + i0 * ld + j0, ld);
+        acc = mm16<false>(Ls + i0 * ld + k0, Bs + k0 * ld + j0, ld, -1.0, acc); // -L_ik B_kj
+        st16(Bs + i0 * ld + j0, ld, acc);
+      }
+    }
+    __syncthreads();
+  }
   if (bad) {
     // R = 0 (no factor), Rinv = I keeps the later products finite
     for (int idx = tid; idx < c * c; idx += kCiT) {
@@ -199,19 +280,20 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
   }
-  // b[u][v] = (L^-1)_ik = (R^-1)_ki, i = ti + 16u, k = tk + 16v (lower: k <= i)
-#pragma unroll
-  for (int u = 0; u < kCiU; ++u)
-#pragma unroll
-    for (int v = 0; v < kCiU; ++v) {
-      const int i = ti + 16 * u, k = tk + 16 * v;
-      if (i < c && k < c) {
-        R[i * c + k] = k >= i ? a[u][v] : 0.0;
-        const double x = k <= i ? b[u][v] : 0.0;
-        Rinv[k * c + i] = x;
-        if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
-      }
-    }
+  // R = L^T; (L^-1)_ik = (R^-1)_ki (zero above the diagonal)
+  for (int e = tid; e < c * c; e += kCiT) {
+    const int i = e / c, k = e - i * c;
+    R[e] = (k >= i) ? Ls[k * ld + i] : 0.0;
+    const double x = Bs[i * ld + k];
+    Rinv[k * c + i] = x;
+    if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
+  }
+}
+
+// LDS bytes of k_chol_inv for c columns
+size_t chol_inv_lds(int c) {
+  const size_t cp = 16 * (size_t)((c + 15) / 16);
+  return 2 * cp * (cp + 1) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,9 +821,13 @@ template <typename T>
 hipError_t launch_chol_inv(const double* W, int c, double* R, double* Rinv, T* RinvT,
                            int32_t* status, hipStream_t s, int trans) {
   if (c < 1 || c > kCwMax) return hipErrorInvalidValue;
-  if (c <= 16 * kCiU) {
-    hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), 0, s, W, c, R, Rinv, RinvT, trans,
-                       status, nullptr);
+  if (c <= kCiMax) {
+    const size_t shmem = chol_inv_lds(c);
+    const hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv<T>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_chol_inv<T>), dim3(1), dim3(kCiT), shmem, s, W, c, R, Rinv, RinvT,
+                       trans, status, nullptr);
     return hipGetLastError();
   }
 #define RSVD_CHOL_WIDE(U)                                                                        \
@@ -862,9 +948,14 @@ hipError_t launch_cast_t_from_f64_grouped(const GArgCast* a, int count, int maxb
 }
 
 template <typename T>
-hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, hipStream_t s) {
+hipError_t launch_chol_inv_grouped(const GArgChol* a, int count, int cmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1, (unsigned)count), dim3(kCiT), 0, s, nullptr, 0,
+  if (cmax < 1 || cmax > kCiMax) return hipErrorInvalidValue;
+  const size_t shmem = chol_inv_lds(cmax);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_chol_inv<T>), dim3(1, (unsigned)count), dim3(kCiT), shmem, s, nullptr, 0,
                      nullptr, nullptr, nullptr, 0, nullptr, a);
   return hipGetLastError();
 }
@@ -917,8 +1008,8 @@ hipError_t launch_select_k_grouped(const GArgSel* a, int count, int kmax, hipStr
 }
 
 template hipError_t launch_cast_t_from_f64_grouped<float>(const GArgCast*, int, int, hipStream_t);
-template hipError_t launch_chol_inv_grouped<float>(const GArgChol*, int, hipStream_t);
-template hipError_t launch_chol_inv_grouped<double>(const GArgChol*, int, hipStream_t);
+template hipError_t launch_chol_inv_grouped<float>(const GArgChol*, int, int, hipStream_t);
+template hipError_t launch_chol_inv_grouped<double>(const GArgChol*, int, int, hipStream_t);
 template hipError_t launch_small_gemm_grouped<float>(const GArgSg*, int, int, hipStream_t);
 template hipError_t launch_small_gemm_grouped<double>(const GArgSg*, int, int, hipStream_t);
 template hipError_t launch_sort_sign_scatter_grouped<float>(const GArgSort*, int, int, int,

@@ -58,14 +58,15 @@ template <> struct Frag<1> {
   static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
     return __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
-  static __device__ __forceinline__ unsigned pair(f32x2 f) {
-    return __builtin_bit_cast(unsigned, bf16x2{(__bf16)f[0], (__bf16)f[1]});
+  // two E4M3 codes (low or high half of w) to two bfloat16 in one packed
+  // convert (unit scale); every E4M3 value is exact in bfloat16, and this
+  // gives the same bits as widening through FP32 for all 2^16 code pairs
+  template <bool HI>
+  static __device__ __forceinline__ unsigned pair(unsigned w) {
+    return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, 1.0f, HI));
   }
   static __device__ __forceinline__ u32x4 bf(raw v) {
-    return u32x4{pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[0], false)),
-                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[0], true)),
-                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[1], false)),
-                 pair(__builtin_amdgcn_cvt_pk_f32_fp8((int)v[1], true))};
+    return u32x4{pair<false>(v[0]), pair<true>(v[0]), pair<false>(v[1]), pair<true>(v[1])};
   }
 };
 
@@ -223,7 +224,11 @@ __global__ void k_scale_rows(double* __restrict__ Z, int64_t n, int c,
 // squared dequantised entries (Eq. sumeigen) per block.  Requires n % 8 == 0
 // and 16-byte rows of A, Xhi, Xlo.
 constexpr int kBK = 64, kBLD = kBK + 8;
-template <int NT> constexpr int nt_bf16_threads() { return NT <= 5 ? 512 : 256; }
+template <int NT> constexpr int nt_bf16_threads() { return 512; }
+// 16-row tiles per wave: 4, or 2 for panels wider than 80 columns (their
+// FP32 accumulators then stay within two waves per SIMD)
+template <int NT> constexpr int nt_bf16_tiles() { return NT <= 5 ? 4 : 2; }
+template <int NT> constexpr int nt_bf16_rows() { return nt_bf16_threads<NT>() / 64 * 16 * nt_bf16_tiles<NT>(); }
 
 template <int NT, int ES>
 __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
@@ -232,7 +237,8 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
     const float* __restrict__ scale, float* __restrict__ Y, int64_t ldy,
     double* __restrict__ fro2_part) {
   constexpr int BC = 16 * NT;
-  constexpr int kBT = nt_bf16_threads<NT>(), kBM = kBT;     // threads, rows per block
+  constexpr int kBT = nt_bf16_threads<NT>(), RT = nt_bf16_tiles<NT>();
+  constexpr int kBM = nt_bf16_rows<NT>();                  // rows per block: RT 16-row tiles per wave
   constexpr int XP = (2 * BC * (kBK / 8) + kBT - 1) / kBT;  // 16-byte X pieces per thread
   __shared__ __attribute__((aligned(16))) __bf16 Xs[2][2][BC * kBLD];
   __shared__ double s2l[2][kBK];
@@ -251,9 +257,10 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xhi), 0, xrange, 0x00020000);
   const __amdgpu_buffer_rsrc_t lrs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xlo), 0, xrange, 0x00020000);
-  int voa[4];
+  int voa[RT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) voa[i] = (int)(((int64_t)(wave * 64 + 16 * i + lr) * lda + 8 * g) * ES);
+  for (int i = 0; i < RT; ++i)
+    voa[i] = (int)(((int64_t)(wave * 16 * RT + 16 * i + lr) * lda + 8 * g) * ES);
   // X piece p of this thread: hi/lo h, row xr, 8-column group q of the chunk
   int vox[XP];
   bool xon[XP];
@@ -269,11 +276,11 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   // (set t & 1 holds step t); X pieces of the next chunk loaded at its first
   // step and stored to LDS after its second
   typedef typename Frag<ES>::raw raw_t;
-  raw_t ra[2][4];
+  raw_t ra[2][RT];
   u32x4 rx[XP];
-  auto load_a = [&](int t, raw_t (&dst)[4]) {
+  auto load_a = [&](int t, raw_t (&dst)[RT]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) dst[i] = Frag<ES>::load(ar, voa[i], t * 32 * ES);
+    for (int i = 0; i < RT; ++i) dst[i] = Frag<ES>::load(ar, voa[i], t * 32 * ES);
   };
   auto load_x = [&](int ch) {
 #pragma unroll
@@ -303,9 +310,9 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
       s2l[buf][tid] = s * s;
     }
   };
-  f32x4 acc[4][NT];
+  f32x4 acc[RT][NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   double ss = 0.0;
@@ -319,9 +326,9 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   auto step = [&](int t, auto stc) {
     constexpr int st = decltype(stc)::value;
     const int ch = t >> 1, buf = ch & 1;
-    u32x4 a[4];
+    u32x4 a[RT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = Frag<ES>::bf(ra[st][i]);
+    for (int i = 0; i < RT; ++i) a[i] = Frag<ES>::bf(ra[st][i]);
     const bool more_x = st == 0 && ch + 1 < nch;
     if (more_x) load_x(ch + 1);
     // refill this set with step t + 2 (the last prefetches are harmless repeats)
@@ -330,28 +337,42 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
     // a step that runs past n holds the next row's values there
     if (32 * t + 8 * g >= n) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = u32x4{0u, 0u, 0u, 0u};
+      for (int i = 0; i < RT; ++i) a[i] = u32x4{0u, 0u, 0u, 0u};
     }
-    bf16x8 bh[NT], bl[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      bh[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][0][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
-      bl[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][1][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
+    if constexpr (NT <= 5) {
+      bf16x8 bh[NT], bl[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh[j], acc[i][j]);
-        acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl[j], acc[i][j]);
+        bh[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][0][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
+        bl[j] = *reinterpret_cast<const bf16x8*>(&Xs[buf][1][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
       }
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh[j], acc[i][j]);
+          acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl[j], acc[i][j]);
+        }
+    } else {
+      // wide panels: one column tile's hi and lo fragments live at a time
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Xs[buf][0][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Xs[buf][1][(16 * j + lr) * kBLD + 32 * st + 8 * g]);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bh, acc[i][j]);
+          acc[i][j] = mfma_bf16(as_bf16x8(a[i]), bl, acc[i][j]);
+        }
+      }
+    }
     if (do_ss) {
       // column 32 st + 8 g + e of the chunk, four rows per value
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         float v2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RT; ++i) {
           const float v = (float)as_bf16x8(a[i])[e];
           v2 = fmaf(v, v, v2);
         }
@@ -369,13 +390,13 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
     if (t + 1 < nst) step(t + 1, std::integral_constant<int, 1>());
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const int col = 16 * j + lr;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + wave * 64 + 16 * i + 4 * g + e;
+        const int64_t row = row0 + wave * 16 * RT + 16 * i + 4 * g + e;
         if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
       }
     }
@@ -595,8 +616,8 @@ hipError_t nt_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const __bf1
   const unsigned char* Ab = static_cast<const unsigned char*>(A);
 #define RSVD_NT_BF16(NT)                                                                        \
   case NT: {                                                                                    \
-    constexpr int bt = nt_bf16_threads<NT>();                                                   \
-    const int64_t nblk = (m + bt - 1) / bt;                                                     \
+    constexpr int bt = nt_bf16_threads<NT>(), br = nt_bf16_rows<NT>();                          \
+    const int64_t nblk = (m + br - 1) / br;                                                     \
     if (nparts) *nparts = (int)nblk;                                                            \
     hipLaunchKernelGGL((k_gemm_nt_bf16<NT, ES>), dim3((unsigned)nblk), dim3(bt), 0, s, Ab, m,   \
                        n, lda, Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part);                     \

@@ -117,15 +117,15 @@ KERNEL_INFO = {
 # the kernel that was measured: a changed kernel reports null until measured
 # again.
 TRAFFIC = {
-    "eigensolver": (3.2842e+09, "eig.hip", "k_jacobi_eig", "da89077235080b21"),
+    "eigensolver": (3.2839e+09, "eig.hip", "k_jacobi_eig", "1b800c71708d35cd"),
     "pass_nn": (2.3905e+09, "gemm.hip", "k_gemm_nt_tall", "b17a75a2a07e1bbd"),
     "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "f6ccc62099be49a2"),
     "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
     "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
-    "pass_nn_bf16": (1.5362e+09, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
-    "pass_tn_bf16": (1.4354e+09, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
-    "pass_nn_fp8": (8.4586e+08, "lowp.hip", "k_gemm_nt_bf16", "2ea7cf83425a15e1"),
-    "pass_tn_fp8": (9.1820e+08, "lowp.hip", "k_gemm_tn_bf16", "2b53b47ebf8fa640"),
+    "pass_nn_bf16": (1.3808e+09, "lowp.hip", "k_gemm_nt_bf16", "0f74e48fee48d8c8"),
+    "pass_tn_bf16": (1.4355e+09, "lowp.hip", "k_gemm_tn_bf16", "582c4bcb81bfa79d"),
+    "pass_nn_fp8": (8.4490e+08, "lowp.hip", "k_gemm_nt_bf16", "0f74e48fee48d8c8"),
+    "pass_tn_fp8": (9.1830e+08, "lowp.hip", "k_gemm_tn_bf16", "582c4bcb81bfa79d"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 

@@ -100,6 +100,22 @@ def test_solvers_reject_null_plan(lib):
     assert lib.rsvd_server_submit(None, None, None) == -1
     assert lib.rsvd_server_progress(None, None, 0, None, None, None) == -1
     assert lib.rsvd_server_destroy(None) == 0
+    # grouped batches: null handles, negative counts and tables are argument
+    # errors before any device call
+    g = ctypes.c_void_p()
+    assert lib.rsvd_batch_grouped_create(None, None, 0, None, 0, ctypes.byref(g)) == -1
+    assert lib.rsvd_batch_grouped_create(a, None, 0, None, -1, ctypes.byref(g)) == -1
+    assert lib.rsvd_batch_grouped_create(a, None, 0, None, 2, ctypes.byref(g)) == -1
+    assert lib.rsvd_batch_grouped_launch(None, None) == -1
+    assert lib.rsvd_batch_grouped_destroy(None) == 0
+    assert lib.rsvd_batch_grouped_graph_create(None, ctypes.byref(g)) == -1
+    nout = ctypes.c_int32()
+    assert lib.rsvd_batch_grouped_tune(None, None, 0, None, 0, ctypes.byref(nout), None) == -1
+    import paper_1906_12085_amd as pk
+    tab = (pk.RsvdTuneEntry * 4)()
+    assert lib.rsvd_batch_grouped_tune(a, None, -1, tab, 4, ctypes.byref(nout), None) == -1
+    assert lib.rsvd_batch_grouped_tune(a, None, 0, tab, -1, ctypes.byref(nout), None) == -1
+    assert lib.rsvd_batch_grouped_tune(a, None, 0, None, 4, ctypes.byref(nout), None) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -59,7 +59,9 @@ Geom geom(int n) {
   Geom g;
   const int nb = (n + kB - 1) / kB;
   g.nbp = nb + (nb & 1) < 2 ? 2 : nb + (nb & 1);
-  g.rpt = n <= 128 ? 2 : (n <= 256 ? 4 : 8);       // at most 4 slices up to n = 512
+  // at most 4 slices up to n = 512; 256-row slices past it (4 at n = 1024:
+  // fewer partial Gram matrices per pair, half the CUs)
+  g.rpt = n <= 128 ? 2 : (n <= 256 ? 4 : (n <= 512 ? 8 : 16));
   const int rs = 16 * g.rpt;
   g.P = (n + rs - 1) / rs;
   g.nwg = (g.nbp / 2) * g.P;
@@ -419,6 +421,8 @@ hipError_t launch_jacobi_eig(double* X, double* J, int64_t n, double* lam, doubl
                                      ev0, ev1, svd);
     case 4: return eig_launch<4>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
                                      ev0, ev1, svd);
+    case 16: return eig_launch<16>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
+                                   ev0, ev1, svd);
     default: return eig_launch<8>(X, J, (int)n, G, inner, lam, diag, flags, scratch, status, s,
                                      ev0, ev1, svd);
   }

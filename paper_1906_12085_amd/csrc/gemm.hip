@@ -898,16 +898,27 @@ __global__ __launch_bounds__(512) void k_gemm_tn_tall(
     const int idx = tid + u * 512;
     voa[u] = (int)(((idx >> 7) * lda + col0 + 4 * (idx & 127)) * 4);
   }
-  const int qr_row = tid / (BC / 4), qr_q = tid % (BC / 4);
-  const int voq = (int)((qr_row * ldq + 4 * qr_q) * 4);
-  const bool has_q = tid < QU;
-  f32x4 ra[4], rq;
+  // Q chunk: float4 piece tid + 512 u of the chunk (two per thread past 128 columns)
+  constexpr int QP = (QU + 511) / 512;
+  int voq[QP], qoff[QP];
+  bool has_q[QP];
+#pragma unroll
+  for (int u = 0; u < QP; ++u) {
+    const int idx = tid + 512 * u, qr_row = idx / (BC / 4), qr_q = idx % (BC / 4);
+    has_q[u] = idx < QU;
+    voq[u] = (int)((qr_row * ldq + 4 * qr_q) * 4);
+    qoff[u] = qr_row * QLD + 4 * qr_q;
+  }
+  f32x4 ra[4], rq[QP];
   auto load = [&](int ch) {
     const int sa = (int)((int64_t)ch * kUK * lda * 4), sq = (int)((int64_t)ch * kUK * ldq * 4);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       ra[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ar, voa[u], sa, 0));
-    if (has_q) rq = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq, sq, 0));
+#pragma unroll
+    for (int u = 0; u < QP; ++u)
+      if (has_q[u])
+        rq[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(qr, voq[u], sq, 0));
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -915,7 +926,9 @@ __global__ __launch_bounds__(512) void k_gemm_tn_tall(
       const int idx = tid + u * 512;
       *reinterpret_cast<f32x4*>(&As[buf][(idx >> 7) * kUALD + 4 * (idx & 127)]) = ra[u];
     }
-    if (has_q) *reinterpret_cast<f32x4*>(&Qs[buf][qr_row * QLD + 4 * qr_q]) = rq;
+#pragma unroll
+    for (int u = 0; u < QP; ++u)
+      if (has_q[u]) *reinterpret_cast<f32x4*>(&Qs[buf][qoff[u]]) = rq[u];
   };
   f32x4 acc[4][NT];
 #pragma unroll
@@ -1636,7 +1649,7 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
 }
 
 bool tn_tall_applies(const float* A, int64_t lda, const float* Q, int64_t ldq, int c) {
-  return c >= 1 && c <= 128 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (lda % 4) == 0 &&
+  return c >= 1 && c <= 160 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (lda % 4) == 0 &&
          (reinterpret_cast<uintptr_t>(Q) % 16) == 0 && (ldq % 4) == 0;
 }
 
@@ -1673,6 +1686,7 @@ hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda
   switch ((c + 15) / 16) {
     RSVD_TN_TALL(1) RSVD_TN_TALL(2) RSVD_TN_TALL(3) RSVD_TN_TALL(4)
     RSVD_TN_TALL(5) RSVD_TN_TALL(6) RSVD_TN_TALL(7) RSVD_TN_TALL(8)
+    RSVD_TN_TALL(9) RSVD_TN_TALL(10)
     default: return hipErrorInvalidValue;
   }
 #undef RSVD_TN_TALL

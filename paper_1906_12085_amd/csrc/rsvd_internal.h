@@ -70,7 +70,7 @@ bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, in
 hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, double* fro2_part,
                                int* nparts, hipStream_t s);
-// Partials P[s] (n x c, FP64) of A^T Q for fp32 with c <= 128 (16-byte rows);
+// Partials P[s] (n x c, FP64) of A^T Q for fp32 with c <= 160 (16-byte rows);
 // *nsplit returns their number.
 bool tn_tall_applies(const float* A, int64_t lda, const float* Q, int64_t ldq, int c);
 hipError_t launch_gemm_tn_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,

@@ -240,10 +240,11 @@ def test_batch_grouped_tuned_graph_unfused():
     # eager work between replays; the autotuner returns one valid entry per
     # (n, l); an entry outside the limits is an argument error
     dt = torch.float32
-    announce("grouped batch: tuning table, l = 72 (unfused Gram), graph replays, autotuner")
+    announce("grouped batch: tuning table, l = 72 (unfused Gram) and 56, graph replays, autotuner")
     rng = np.random.default_rng(91)
+    # l = 72 (unfused), 56 (the fused kernels' widest, four column tiles), 24 and 16
     shapes = [(9000, 128, 64), (3000, 128, 64), (6000, 256, 16), (2500, 64, 16), (12000, 256, 64),
-              (700, 64, 8)]
+              (700, 64, 8), (7000, 128, 48), (1500, 96, 48)]
     probs = []
     for m, n, k in shapes:
         sig = np.exp(-rng.uniform(0.01, 0.2) * np.arange(1, n + 1))

@@ -166,7 +166,12 @@ TN_CASES = [(1037, 203, 30), (5000, 256, 80), (129, 300, 200), (3, 10, 5), (4100
             # the fp32 narrow kernel, n <= 64 / 128 / 256: every column-tile
             # count's extremes, ragged m, splits shorter than a chunk
             (5003, 64, 128), (4097, 60, 20), (16, 64, 8), (3001, 128, 40), (777, 100, 96),
-            (2050, 144, 24), (65, 256, 4), (5999, 192, 96)]
+            (2050, 144, 24), (65, 256, 4), (5999, 192, 96),
+            # 129 to 160 columns (nine and ten column tiles): the narrow
+            # kernel of every width and the 512-column tile, two of them at
+            # n = 640
+            (1500, 64, 136), (2600, 120, 160), (3001, 256, 152), (4100, 512, 160),
+            (2333, 640, 144)]
 
 
 @pytest.mark.parametrize("name", DTYPES)

@@ -105,7 +105,7 @@ def algorithmic_counts(m, n, k, l, q, b):
 KERNEL_INFO = {
     "eigensolver": ("k_jacobi_eig", "alu"),
     "pass_nn": ("k_gemm_nt_tall", "fp32"),
-    "pass_tn": ("k_gemm_tn_tall", "fp32"),
+    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "8e9c23250fe70cc1"),
     "syrk": ("k_syrk_f32", "fp32"),
     "nn_wide": ("k_gemm_nt_wide", "fp32"),
 }

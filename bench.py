@@ -105,7 +105,7 @@ def algorithmic_counts(m, n, k, l, q, b):
 KERNEL_INFO = {
     "eigensolver": ("k_jacobi_eig", "alu"),
     "pass_nn": ("k_gemm_nt_tall", "fp32"),
-    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "8e9c23250fe70cc1"),
+    "pass_tn": ("k_gemm_tn_tall", "fp32"),
     "syrk": ("k_syrk_f32", "fp32"),
     "nn_wide": ("k_gemm_nt_wide", "fp32"),
 }
@@ -119,7 +119,7 @@ KERNEL_INFO = {
 TRAFFIC = {
     "eigensolver": (3.2839e+09, "eig.hip", "k_jacobi_eig", "1b800c71708d35cd"),
     "pass_nn": (2.3905e+09, "gemm.hip", "k_gemm_nt_tall", "b17a75a2a07e1bbd"),
-    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "f6ccc62099be49a2"),
+    "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "8e9c23250fe70cc1"),
     "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
     "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
     "pass_nn_bf16": (1.3808e+09, "lowp.hip", "k_gemm_nt_bf16", "0f74e48fee48d8c8"),

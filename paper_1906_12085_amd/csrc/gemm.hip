@@ -745,14 +745,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
 // (n % 4 == 0, 16-byte rows).
 constexpr int kNM = 128;
 
+// With GR the Gram partial of a solo launch is per block (slot = blockIdx.x,
+// at gram_part); 5 or 6 column tiles of FP64 Gram accumulators fit only at
+// one wave per SIMD.
 template <int NT, int NS, bool GR>
-__global__ __launch_bounds__(256, 2) void k_gemm_nt_narrow(
+__global__ __launch_bounds__(256, (GR && NT > kGramFuseMaxNt) ? 1 : 2) void k_gemm_nt_narrow(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
-    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, const GArgNarrow* __restrict__ grp,
-    const GWork* __restrict__ wl) {
+    int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ gram_part,
+    const GArgNarrow* __restrict__ grp, const GWork* __restrict__ wl) {
   // tiles t0, t0 + step, ... below t1
-  int64_t t0 = blockIdx.x, step = gridDim.x, t1 = (m + kNM - 1) / kNM, slot = 0;
-  double* gram = nullptr;
+  int64_t t0 = blockIdx.x, step = gridDim.x, t1 = (m + kNM - 1) / kNM, slot = blockIdx.x;
+  double* gram = gram_part;
   if (grp) {
     const GWork w = wl[blockIdx.x];
     const GArgNarrow& a = grp[w.inst];
@@ -1590,7 +1593,7 @@ hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, 
 #define RSVD_NT_NARROW(NS)                                                                     \
   case NS:                                                                                     \
     hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, false>), grid, block, 0, s, A, m, n, lda, Xt, \
-                       ldxt, c, Y, ldy, nullptr, nullptr);                                     \
+                       ldxt, c, Y, ldy, nullptr, nullptr, nullptr);                            \
     break;
   switch (ns) {
     RSVD_NT_NARROW(1) RSVD_NT_NARROW(2) RSVD_NT_NARROW(3)
@@ -1613,6 +1616,58 @@ hipError_t launch_gemm_nt_narrow(const float* A, int64_t m, int64_t n, int64_t l
     case 6: return narrow_nt<6>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
     case 7: return narrow_nt<7>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
     case 8: return narrow_nt<8>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The narrow product with the FP64 Gram matrix of its output: one c x c
+// partial per block at gram_part (persistent blocks, at most max_parts).
+template <int NT, int NS>
+hipError_t narrow_gram_launch(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                              int64_t ldxt, int c, float* Y, int64_t ldy, double* gram_part,
+                              int nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, true>), dim3((unsigned)nblk), dim3(256), 0, s, A,
+                     m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t narrow_gram_ns(int ns, const float* A, int64_t m, int64_t n, int64_t lda,
+                          const float* Xt, int64_t ldxt, int c, float* Y, int64_t ldy,
+                          double* gram_part, int nblk, hipStream_t s) {
+  switch (ns) {
+    case 1: return narrow_gram_launch<NT, 1>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    case 2: return narrow_gram_launch<NT, 2>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    case 3: return narrow_gram_launch<NT, 3>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    case 4: return narrow_gram_launch<NT, 4>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    case 5: return narrow_gram_launch<NT, 5>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    case 6: return narrow_gram_launch<NT, 6>(A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nblk, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool nt_narrow_gram_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt,
+                            int c) {
+  return nt_tall_applies(A, n, lda, Xt, ldxt, c) && n <= 16 * kNarrowSlabs && c <= 96;
+}
+
+hipError_t launch_gemm_nt_narrow_gram(const float* A, int64_t m, int64_t n, int64_t lda,
+                                      const float* Xt, int64_t ldxt, int c, float* Y, int64_t ldy,
+                                      double* gram_part, int64_t max_parts, int* nparts,
+                                      hipStream_t s) {
+  if (!nt_narrow_gram_applies(A, n, lda, Xt, ldxt, c) || max_parts < 1) return hipErrorInvalidValue;
+  int64_t nb = narrow_blocks(m);
+  if (nb > max_parts) nb = max_parts;
+  *nparts = m > 0 ? (int)nb : 0;
+  if (m <= 0) return hipSuccess;
+  const int ns = (int)((n + 15) / 16);
+  switch ((c + 15) / 16) {
+    case 1: return narrow_gram_ns<1>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
+    case 2: return narrow_gram_ns<2>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
+    case 3: return narrow_gram_ns<3>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
+    case 4: return narrow_gram_ns<4>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
+    case 5: return narrow_gram_ns<5>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
+    case 6: return narrow_gram_ns<6>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, (int)nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1909,7 +1964,7 @@ hipError_t narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int n
 #define RSVD_G(NS)                                                                              \
   case NS:                                                                                      \
     hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, GR>), grid, block, 0, s, nullptr, 0, 0, 0,     \
-                       nullptr, 0, 0, nullptr, 0, a, wl);                                       \
+                       nullptr, 0, 0, nullptr, 0, nullptr, a, wl);                              \
     break;
   switch (ns) {
     RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)

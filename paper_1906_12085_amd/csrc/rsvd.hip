@@ -334,8 +334,21 @@ struct Path {
     if ((e = gram(Y, m, c, ldy, p->Wg)) != hipSuccess) return e;
     if ((e = launch_chol_inv<T>(p->Wg, c, R1, R1inv, RinvT, p->status, s, tall)) != hipSuccess)
       return e;
-    if ((e = times_rinv(Y, m, c, ldy, RinvT, tall, Q1, ldq)) != hipSuccess) return e;
-    if ((e = gram(Q1, m, c, ldq, p->Wg)) != hipSuccess) return e;
+    if (tall && nt_narrow_gram_applies(reinterpret_cast<const float*>(Y), c, ldy,
+                                       reinterpret_cast<const float*>(RinvT), c, c)) {
+      // Q1 = Y R1^-1 with Q1^T Q1 summed from the product's accumulators
+      int np = 0;
+      const int64_t cap = p->max_split * p->n_max * p_cmax(p) / ((int64_t)c * c);
+      if ((e = launch_gemm_nt_narrow_gram(reinterpret_cast<const float*>(Y), m, c, ldy,
+                                          reinterpret_cast<const float*>(RinvT), c, c,
+                                          reinterpret_cast<float*>(Q1), ldq, p->part, cap, &np,
+                                          s)) != hipSuccess)
+        return e;
+      if ((e = launch_reduce_partials(p->part, np, c, c, p->Wg, c, s)) != hipSuccess) return e;
+    } else {
+      if ((e = times_rinv(Y, m, c, ldy, RinvT, tall, Q1, ldq)) != hipSuccess) return e;
+      if ((e = gram(Q1, m, c, ldq, p->Wg)) != hipSuccess) return e;
+    }
     return launch_chol_inv<T>(p->Wg, c, R2, R2inv, trans2 >= 0 ? RinvT : nullptr, p->status, s,
                               trans2 > 0);
   }

@@ -67,6 +67,16 @@ hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda
 // Y (m x c) = A Xt^T for fp32 with c <= 192 (Xt is c x n), optional per-block
 // FP64 partial sums of a_ij^2 (*nparts of them); requires nt_tall_applies.
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c);
+// Y (m x c) = A Xt^T on the narrow kernel (n <= 96, c <= 96) with the FP64
+// Gram matrix Y^T Y of the stored output as per-block c x c partials at
+// gram_part (*nparts of them, at most max_parts), summed by
+// launch_reduce_partials.
+bool nt_narrow_gram_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt,
+                            int c);
+hipError_t launch_gemm_nt_narrow_gram(const float* A, int64_t m, int64_t n, int64_t lda,
+                                      const float* Xt, int64_t ldxt, int c, float* Y, int64_t ldy,
+                                      double* gram_part, int64_t max_parts, int* nparts,
+                                      hipStream_t s);
 hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                                int64_t ldxt, int c, float* Y, int64_t ldy, double* fro2_part,
                                int* nparts, hipStream_t s);

@@ -195,7 +195,7 @@ int32_t rsvd_solve_adaptive(rsvd_plan_t plan, const void* A, int64_t m, int64_t 
                             int32_t k_max, void* U, int64_t ldu, double* S, void* V, int64_t ldv,
                             int32_t* K);
 
-/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1)/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
+/* rsvd_solve_krylov: the Krylov method (Sec. 3.1.1) -- G (n x l, l =
  * min(k + p, n)), blocks H(0) = A G and H(j) = A (A^T H(j-1)) for j = 1..i,
  * QR of their concatenation H (m x (i+1) l), T = A^T Q, SVD T = V~ S~ W^T,
  * U~ = Q W -- returning the first k triplets and K by the threshold t

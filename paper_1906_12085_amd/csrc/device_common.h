@@ -39,10 +39,16 @@ __device__ __forceinline__ void stage_to_lds(double* dst, const double* __restri
 // npad-1 steps meet every pair exactly once, and the pairs of one step are
 // disjoint, so their rotations commute.
 __device__ __forceinline__ void rr_pair(int s, int k, int npad, int* p, int* q) {
+  // s < h and k <= h / 2, so one conditional step reduces each index mod h
   int a, b;
   const int h = npad - 1;
   if (k == 0) { a = h; b = s; }
-  else { a = (s + k) % h; b = (s - k + h) % h; }
+  else {
+    a = s + k;
+    a = a >= h ? a - h : a;
+    b = s - k;
+    b = b < 0 ? b + h : b;
+  }
   *p = a < b ? a : b;
   *q = a < b ? b : a;
 }
@@ -92,11 +98,14 @@ __device__ __forceinline__ void rot_cst(double al, double be, double ga, bool ne
   *t = need ? sg * ti : 0.0;
 }
 
-// Sum over the G consecutive lanes of this lane's group (G = 16, 32 or 64,
-// groups aligned to G).  Within a 16-lane row: quad_perm swaps (lanes l^1,
-// l^2) and row rotations by 4 and 8 (DPP), then every lane takes lane
+// Sum over the G consecutive lanes of this lane's group (G = 8, 16, 32 or
+// 64, groups aligned to G).  Within a 16-lane row: quad_perm swaps (lanes
+// l^1, l^2) and row rotations by 4 and 8 (DPP), then every lane takes lane
 // (l & 16)'s value (ds_swizzle) so all lanes of the row hold the same bits;
-// larger groups add the partner row / half-wave symmetrically.
+// larger groups add the partner row / half-wave symmetrically.  G = 8: the
+// two quad sums of the half-row are exchanged by row_half_mirror (lane i
+// reads lane 7 - i), and since x + y == y + x exactly, every lane of the
+// group holds the same bits without a broadcast.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
@@ -111,9 +120,10 @@ __device__ __forceinline__ double swizzle(double v) {
 }
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(G == 16 || G == 32 || G == 64, "group of 16, 32 or 64 lanes");
+  static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group of 8, 16, 32 or 64 lanes");
   v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
   v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1): quad sum
+  if (G == 8) return v + dpp_mov<0x141>(v);   // row_half_mirror
   v += dpp_mov<0x124>(v);   // row_ror:4
   v += dpp_mov<0x128>(v);   // row_ror:8: row sum (association differs by quad)
   v = swizzle<0x0010>(v);   // broadcast lane (l & 16): identical bits in the row

@@ -440,54 +440,84 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
 }
 
 // One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: the
-// columns of M held column-major in LDS.  Each group of 16 lanes owns one
-// column pair per step (round-robin ordering), keeps the pair's entries in
-// registers (6 rows per lane), reduces the three inner products with
-// group_sum, rotates and writes back.  With transpose != 0 the kernel works
-// on M^T (the rows of Min are its columns).  AccJ: the rotations are
-// accumulated in a second LDS matrix J and written out.  Otherwise they are
-// not: at convergence N J = Uo S with N = M or M^T, so J = N^-1 Uo S and, for
-// N = R^T, J = R Uo S^-1 -- the kernel writes Uo S^-1 (zero columns for zero
-// values) in J's place and the caller forms the columns of J it needs with
-// one small product.  Keeping J out of the rounds removes a third of their
-// loads, stores and FP64 operations; J's column j then carries an error of
-// order eps S_1 / S_j, so this form serves callers that use the leading
-// columns only, and it sets *redo when the values span more than
-// 1 / kJsRedoRatio (or one is zero): a second launch with AccJ and the same
-// redo word then repeats the decomposition with J accumulated (and returns
-// at once when *redo is 0).
-constexpr int kJsG = 16;
-constexpr int kJsRows = 6;                   // c <= kJsG * kJsRows
+// columns of M held column-major in LDS, padded with zero rows to cs = 16 RU2
+// (RU2 = ceil(c / 16), a template parameter).  Each group of 8 lanes owns one
+// column pair per step (round-robin ordering); lane g of the group keeps rows
+// 2 g + 16 u and 2 g + 1 + 16 u (u < RU2) of both columns in registers, read
+// and written as 16-byte pairs, so each load or store of a group is one
+// contiguous 128-byte line (bank-conflict free whatever the columns; with
+// 8-byte accesses two groups of a half-wave met in the same banks whenever
+// their columns were a multiple of 128 bytes apart).  The squared column
+// norms sit in LDS: computed exactly at the start of each sweep and, after a
+// rotation by tangent t, updated as alpha - t gamma and beta + t gamma (the
+// norms of the rotated columns), so a step reduces only gamma = x_p . x_q
+// across the group.  A round reads and writes the whole matrix in LDS and
+// that traffic, not the arithmetic, bounds it.  Whether a group rotated, and
+// the largest cosine it rotated, stay in registers until the sweep ends.
+// With transpose != 0 the kernel works on M^T (the rows of Min are its
+// columns).  AccJ: the rotations are accumulated in a second LDS matrix J
+// and written out.  Otherwise they are not: at convergence N J = Uo S with
+// N = M or M^T, so J = N^-1 Uo S and, for N = R^T, J = R Uo S^-1 -- the
+// kernel writes Uo S^-1 (zero columns for zero values) in J's place and the
+// caller forms the columns of J it needs with one small product.  Keeping J
+// out of the rounds removes a third of their loads, stores and FP64
+// operations; J's column j then carries an error of order eps S_1 / S_j, so
+// this form serves callers that use the leading columns only, and it sets
+// *redo when the values span more than 1 / kJsRedoRatio (or one is zero): a
+// second launch with AccJ and the same redo word then repeats the
+// decomposition with J accumulated (and returns at once when *redo is 0).
+constexpr int kJsG = 8;
+constexpr int kJsMaxRu2 = 6;                 // c <= 16 * kJsMaxRu2
+constexpr int kJsMaxC = 16 * kJsMaxRu2;
 constexpr int kJsMaxSweeps = 60;
 constexpr double kJsRedoRatio = 1e-6;
 
-template <bool AccJ>
-__global__ __launch_bounds__(768) void k_jacobi_svd_small(
+template <bool AccJ, int RU2>
+__global__ __launch_bounds__(kJsMaxC / 2 * kJsG) void k_jacobi_svd_small(
     const double* __restrict__ Min, int c, int transpose, double* __restrict__ Uo,
     double* __restrict__ S, double* __restrict__ Jout, double* __restrict__ diag,
     int32_t* __restrict__ status, double* __restrict__ redo, const GArgJac* __restrict__ garg) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
   if (garg) {
     const GArgJac& a = garg[blockIdx.y];
     Min = a.M; c = a.c; transpose = a.transpose; Uo = a.Uo; S = a.S; Jout = a.J; diag = a.diag;
     status = a.status; redo = a.redo;
   }
   if (AccJ && redo && *redo == 0.0) return;  // uniform: the first pass needed no J
-  extern __shared__ double sm[];
-  double* Mc = sm;                   // column j at Mc + j*c
-  double* Jc = sm + (size_t)c * c;   // AccJ only
+  constexpr int cs = 16 * RU2;               // LDS rows per column
+  extern __shared__ __attribute__((aligned(16))) double sm[];
+  double* Mc = sm;                           // column j at Mc + j*cs
+  double* Jc = sm + (size_t)cs * c;          // AccJ only
   __shared__ int rotated;
   __shared__ double offmax;
-  __shared__ double snrm[kJsG * kJsRows];
+  __shared__ double nrm2[kJsMaxC];           // squared column norms
+  __shared__ double snrm[kJsMaxC];
   const int npad = c + (c & 1);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int idx = tid; idx < c * c; idx += nthr) {
-    const int i = idx / c, j = idx - i * c;   // Min row-major (i, j)
-    const double v = Min[idx];
-    if (transpose) Mc[i * c + j] = v;        // column i of M^T is row i of Min
-    else Mc[j * c + i] = v;
-    if (AccJ) Jc[j * c + i] = (i == j) ? 1.0 : 0.0;
+  // Min read in its row-major order, four loads in flight per thread
+  for (int idx0 = tid; idx0 < c * c; idx0 += 4 * nthr) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = idx0 + u * nthr;
+      v[u] = idx < c * c ? Min[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = idx0 + u * nthr;
+      if (idx < c * c) {
+        const int i = idx / c, j = idx - i * c;   // Min row-major (i, j)
+        if (transpose) Mc[i * cs + j] = v[u];    // column i of M^T is row i of Min
+        else Mc[j * cs + i] = v[u];
+      }
+    }
   }
-  const int npairs = npad / 2;
+  for (int idx = tid; idx < cs * c; idx += nthr) {
+    const int j = idx / cs, i = idx - j * cs;
+    if (i >= c) Mc[idx] = 0.0;                   // the padding rows
+    if (AccJ) Jc[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  const int npairs = npad / 2, ngroups = nthr / kJsG;
   const int grp = tid / kJsG, gl = tid % kJsG;
   const double tol = kEps * (double)c, tol2 = tol * tol;
   int sweep = 0;
@@ -496,63 +526,78 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
   __syncthreads();
   while (sweep < kJsMaxSweeps) {
     if (tid == 0) { rotated = 0; offmax = 0.0; }
+    for (int j = grp; j < c; j += ngroups) {   // exact squared norms
+      const d2* x = reinterpret_cast<const d2*>(Mc + (size_t)j * cs) + gl;
+      double s2 = 0.0;
+#pragma unroll
+      for (int u = 0; u < RU2; ++u) {
+        const d2 v = x[kJsG * u];
+        s2 = fma(v.x, v.x, s2);
+        s2 = fma(v.y, v.y, s2);
+      }
+      s2 = group_sum<kJsG>(s2);
+      if (gl == 0) nrm2[j] = s2;
+    }
     __syncthreads();
+    bool my_rot = false;
+    double my_off = 0.0;                     // squared cosine, approximate (diagnostic only)
     for (int s = 0; s < npad - 1; ++s) {
       int p = 0, q = c;
       if (grp < npairs) rr_pair(s, grp, npad, &p, &q);
-      if (grp < npairs && q < c) {           // uniform within the 16-lane group
-        double* xp = Mc + (size_t)p * c;
-        double* xq = Mc + (size_t)q * c;
-        double* jp = Jc + (size_t)p * c;
-        double* jq = Jc + (size_t)q * c;
+      if (grp < npairs && q < c) {           // uniform within the 8-lane group
+        d2* xp = reinterpret_cast<d2*>(Mc + (size_t)p * cs) + gl;
+        d2* xq = reinterpret_cast<d2*>(Mc + (size_t)q * cs) + gl;
+        d2* jp = reinterpret_cast<d2*>(Jc + (size_t)p * cs) + gl;
+        d2* jq = reinterpret_cast<d2*>(Jc + (size_t)q * cs) + gl;
+        const double al = nrm2[p], be = nrm2[q];
         // all reads of the two columns (and their J columns) before any write
-        double a[kJsRows], b[kJsRows], ja[kJsRows], jb[kJsRows];
-        double al = 0.0, be = 0.0, ga = 0.0;
+        d2 a[RU2], b[RU2], ja[RU2], jb[RU2];
 #pragma unroll
-        for (int u = 0; u < kJsRows; ++u) {
-          const int i = gl + kJsG * u;
-          a[u] = (i < c) ? xp[i] : 0.0;
-          b[u] = (i < c) ? xq[i] : 0.0;
+        for (int u = 0; u < RU2; ++u) {
+          a[u] = xp[kJsG * u];
+          b[u] = xq[kJsG * u];
           if (AccJ) {
-            ja[u] = (i < c) ? jp[i] : 0.0;
-            jb[u] = (i < c) ? jq[i] : 0.0;
+            ja[u] = jp[kJsG * u];
+            jb[u] = jq[kJsG * u];
           }
         }
+        double ga = 0.0;
 #pragma unroll
-        for (int u = 0; u < kJsRows; ++u) {
-          al = fma(a[u], a[u], al);
-          be = fma(b[u], b[u], be);
-          ga = fma(a[u], b[u], ga);
+        for (int u = 0; u < RU2; ++u) {
+          ga = fma(a[u].x, b[u].x, ga);
+          ga = fma(a[u].y, b[u].y, ga);
         }
-        al = group_sum<kJsG>(al);
-        be = group_sum<kJsG>(be);
         ga = group_sum<kJsG>(ga);
         // rotate when the cosine of the pair's angle exceeds tol
         if (rot_needed(al, be, ga, tol2, 0.0)) {
-          double cs, sn, tt;
-          rot_cst(al, be, ga, true, &cs, &sn, &tt);
+          double cs_, sn, tt;
+          rot_cst(al, be, ga, true, &cs_, &sn, &tt);
 #pragma unroll
-          for (int u = 0; u < kJsRows; ++u) {
-            const int i = gl + kJsG * u;
-            if (i < c) {
-              xp[i] = cs * a[u] - sn * b[u];
-              xq[i] = sn * a[u] + cs * b[u];
-              if (AccJ) {
-                jp[i] = cs * ja[u] - sn * jb[u];
-                jq[i] = sn * ja[u] + cs * jb[u];
-              }
+          for (int u = 0; u < RU2; ++u) {
+            xp[kJsG * u] = cs_ * a[u] - sn * b[u];
+            xq[kJsG * u] = sn * a[u] + cs_ * b[u];
+            if (AccJ) {
+              jp[kJsG * u] = cs_ * ja[u] - sn * jb[u];
+              jq[kJsG * u] = sn * ja[u] + cs_ * jb[u];
             }
           }
           if (gl == 0) {
-            rotated = 1;
-            // squared cosine, approximate (diagnostic only; benign race)
-            const double rel2 = ga * ga * __builtin_amdgcn_rcp(al * be);
-            if (rel2 > offmax) offmax = rel2;
+            nrm2[p] = fma(-tt, ga, al);
+            nrm2[q] = fma(tt, ga, be);
           }
+          my_rot = true;
+          my_off = fmax(my_off, ga * ga * __builtin_amdgcn_rcp(al * be));
         }
       }
       __syncthreads();
     }
+    // the groups' flags (the last round's barrier orders these writes after
+    // the reset; the racing maximum is a diagnostic only)
+    if (my_rot && gl == 0) {
+      rotated = 1;
+      if (my_off > offmax) offmax = my_off;
+    }
+    __syncthreads();
     ++sweep;
     last_off = sqrt(offmax);
     const bool done = (rotated == 0);
@@ -563,7 +608,7 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
   for (int j = tid / 64; j < c; j += nthr / 64) {
     const int lane = tid & 63;
     double s2 = 0.0;
-    for (int i = lane; i < c; i += 64) s2 += Mc[(size_t)j * c + i] * Mc[(size_t)j * c + i];
+    for (int i = lane; i < c; i += 64) s2 += Mc[(size_t)j * cs + i] * Mc[(size_t)j * cs + i];
     s2 = group_sum<64>(s2);
     const double nrm = sqrt(s2);
     if (lane == 0) {
@@ -572,9 +617,9 @@ __global__ __launch_bounds__(768) void k_jacobi_svd_small(
     }
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     for (int i = lane; i < c; i += 64) {
-      const double u = Mc[(size_t)j * c + i] * inv;
+      const double u = Mc[(size_t)j * cs + i] * inv;
       Uo[(size_t)i * c + j] = u;
-      Jout[(size_t)i * c + j] = AccJ ? Jc[(size_t)j * c + i] : u * inv;
+      Jout[(size_t)i * c + j] = AccJ ? Jc[(size_t)j * cs + i] : u * inv;
     }
   }
   __syncthreads();
@@ -854,24 +899,44 @@ hipError_t launch_small_gemm(const double* A, const double* B, int64_t r, int c1
   return hipGetLastError();
 }
 
+// the kernel for c columns (RU2 = ceil(c / 16) row pairs per lane)
+template <bool AccJ>
+const void* jacobi_small_fn(int ru2) {
+  switch (ru2) {
+    case 1: return (const void*)k_jacobi_svd_small<AccJ, 1>;
+    case 2: return (const void*)k_jacobi_svd_small<AccJ, 2>;
+    case 3: return (const void*)k_jacobi_svd_small<AccJ, 3>;
+    case 4: return (const void*)k_jacobi_svd_small<AccJ, 4>;
+    case 5: return (const void*)k_jacobi_svd_small<AccJ, 5>;
+    case 6: return (const void*)k_jacobi_svd_small<AccJ, 6>;
+    default: return nullptr;
+  }
+}
+
+// one launch of k_jacobi_svd_small for c columns: grid (1, count), LDS for
+// M (and J) padded to 16 ceil(c / 16) rows
+hipError_t launch_jacobi_small(const double* M, int c, int transpose, double* Uo, double* S,
+                               double* J, int acc_j, double* diag, int32_t* status, double* redo,
+                               const GArgJac* garg, int count, hipStream_t s) {
+  if (c < 1 || c > kJsMaxC) return hipErrorInvalidValue;
+  const int ru2 = (c + 15) / 16;
+  const int npad = c + (c & 1);
+  const size_t shmem = (acc_j ? 2 : 1) * (size_t)(16 * ru2) * c * sizeof(double);
+  const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
+  const void* fn = acc_j ? jacobi_small_fn<true>(ru2) : jacobi_small_fn<false>(ru2);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&M, (void*)&c, (void*)&transpose, (void*)&Uo, (void*)&S, (void*)&J,
+                  (void*)&diag, (void*)&status, (void*)&redo, (void*)&garg};
+  e = hipLaunchKernel(fn, dim3(1, (unsigned)count), dim3(threads), args, shmem, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi_svd_small(const double* M, int c, int transpose, double* Uo, double* S,
                                    double* J, int acc_j, double* diag, int32_t* status,
                                    double* redo, hipStream_t s) {
-  if (c < 1 || c > kJsG * kJsRows) return hipErrorInvalidValue;
-  const int npad = c + (c & 1);
-  const size_t shmem = (acc_j ? 2 : 1) * (size_t)c * c * sizeof(double);
-  const void* fn = acc_j ? (const void*)k_jacobi_svd_small<true>
-                         : (const void*)k_jacobi_svd_small<false>;
-  const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  if (acc_j)
-    hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status, redo, nullptr);
-  else
-    hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1), dim3(threads), shmem, s, M, c,
-                       transpose, Uo, S, J, diag, status, redo, nullptr);
-  return hipGetLastError();
+  return launch_jacobi_small(M, c, transpose, Uo, S, J, acc_j, diag, status, redo, nullptr, 1, s);
 }
 
 
@@ -973,21 +1038,8 @@ hipError_t launch_small_gemm_grouped(const GArgSg* a, int count, int maxblk, hip
 hipError_t launch_jacobi_svd_small_grouped(const GArgJac* a, int count, int cmax, int acc_j,
                                            hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (cmax < 1 || cmax > kJsG * kJsRows) return hipErrorInvalidValue;
-  const int npad = cmax + (cmax & 1);
-  const size_t shmem = (acc_j ? 2 : 1) * (size_t)cmax * cmax * sizeof(double);
-  const int threads = ((npad / 2) * kJsG + 63) / 64 * 64;
-  const void* fn = acc_j ? (const void*)k_jacobi_svd_small<true>
-                         : (const void*)k_jacobi_svd_small<false>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  if (acc_j)
-    hipLaunchKernelGGL(k_jacobi_svd_small<true>, dim3(1, (unsigned)count), dim3(threads), shmem, s,
-                       nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, a);
-  else
-    hipLaunchKernelGGL(k_jacobi_svd_small<false>, dim3(1, (unsigned)count), dim3(threads), shmem,
-                       s, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, a);
-  return hipGetLastError();
+  return launch_jacobi_small(nullptr, cmax, 0, nullptr, nullptr, nullptr, acc_j, nullptr, nullptr,
+                             nullptr, a, count, s);
 }
 
 template <typename T>

@@ -240,11 +240,20 @@ def test_cholqr2_parity(plans, name, m, c, kappa):
     assert np.abs(Qg - Qo).max() <= 50 * c * u * kappa
 
 
-@pytest.mark.parametrize("r,c", [(300, 40), (200, 31), (96, 96), (250, 1)])
-def test_small_svd_parity(plans, r, c):
-    announce(f"small_svd r={r} c={c}")
+# c covers every rows-per-lane count of the kernel (ceil(c / 8) = 1 .. 12);
+# the wide spectrum (sigma down to 1e-6) takes the second, J-accumulating
+# launch, the clustered one (sigma in [1, 1.4], the headline's shape) does not
+@pytest.mark.parametrize("r,c,spec", [
+    (300, 40, "wide"), (200, 31, "wide"), (96, 96, "wide"), (250, 1, "wide"), (100, 2, "wide"),
+    (150, 17, "wide"), (300, 80, "wide"), (300, 89, "wide"), (64, 63, "clustered"),
+    (290, 80, "clustered"), (300, 96, "clustered"), (120, 8, "clustered"), (200, 9, "clustered"),
+    (220, 24, "clustered"), (260, 33, "clustered"), (300, 47, "clustered"), (280, 56, "clustered"),
+    (296, 72, "clustered")])
+def test_small_svd_parity(plans, r, c, spec):
+    announce(f"small_svd r={r} c={c} {spec}")
     rng = np.random.default_rng(r * c)
-    T0 = synth.haar(rng, r, c) @ np.diag(np.logspace(0, -6, c)) @ synth.haar(rng, c, c).T
+    sig = np.logspace(0, -6, c) if spec == "wide" else np.linspace(1.4, 1.0, c)
+    T0 = synth.haar(rng, r, c) @ np.diag(sig) @ synth.haar(rng, c, c).T
     Vt = torch.empty(r, c, dtype=torch.float64, device="cuda")
     S = torch.empty(c, dtype=torch.float64, device="cuda")
     W = torch.empty(c, c, dtype=torch.float64, device="cuda")

@@ -83,8 +83,12 @@ __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, 
 // turned into L^-1 = R^-T).  For each block column k:
 //   1. one wave factors the diagonal block, A_kk = L_kk L_kk^T, and inverts
 //      it, X_kk = L_kk^-1, by the symmetric elimination applied to [A_kk | I]
-//      (each step: 1/sqrt of the pivot, the pivot column and the scaled pivot
-//      row of X shared by cross-lane reads; no workgroup barrier);
+//      with row r of both halves in the registers of lane r: at step j the
+//      pivot, the pivot column (entry j of each row below) and the old row j
+//      of X are read into scalar registers (readlane from fixed lanes), and
+//      each row below subtracts its multiple (one FMA per entry); no
+//      workgroup barrier.  Exchanging the pivot data through cross-lane
+//      permutes instead (four entries per lane) took ~800 cycles a step;
 //   2. L_ik = A_ik X_kk^T below it, and the block row k of B, B_kj <- X_kk B_kj
 //      (j < k), B_kk = X_kk;
 //   3. the trailing update A_ij -= L_ik L_jk^T (k < j <= i) and the rows below
@@ -92,6 +96,8 @@ __global__ void k_cast_t(const S* __restrict__ src, int64_t rows, int64_t cols, 
 // Steps 2 and 3 are 16 x 16 x 16 products on the FP64 matrix cores, spread
 // over the four waves; three barriers per block column.  This is the block
 // form of the elimination on [W | I] (Gauss-Jordan with the symmetric pivot).
+// The element loops before and after run over rows and lanes (no index
+// division), every global store coalesced.
 constexpr int kCiT = 256;
 constexpr int kCiMax = 96;
 
@@ -133,6 +139,13 @@ __device__ __forceinline__ void st16(double* C, int ld, f64x4 v) {
   for (int e = 0; e < 4; ++e) C[Mfma<double>::row(lane, e) * ld + (lane & 15)] = v[e];
 }
 
+// a double broadcast from lane `src` (a constant) of the wave
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W, int c,
                                                    double* __restrict__ R,
@@ -151,80 +164,79 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
   double* Bs = csm + cp * ld;        // I, then L^-1 (lower blocks)
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // W into LDS with every load in flight at once (one memory latency), the
-  // identity past c; then the lower triangle takes (w_ij + w_ji) / 2
+  constexpr int kWaves = kCiT / 64, kRows = kCiMax / kWaves, kCols = (kCiMax + 63) / 64;
+  // global memory through address-space-1 pointers: generic (flat) accesses
+  // may alias LDS, and the compiler then orders them against every LDS access
+  const gmem<double>* Wg = to_global(W);
+  // thread (u, h) covers element (i, j) = (w + 4 u, l + 64 h) of the padded
+  // matrix (wave w, lane l), clamped into it: a clamped copy computes and
+  // writes the same value as the element's owner, so no access is predicated
+  double v[kRows][kCols];
   {
-    constexpr int PER = (kCiMax * kCiMax + kCiT - 1) / kCiT;
-    double v[PER];
+    double wt[kRows][kCols];
+    // every load of a thread in flight at once (one memory latency): w_ij
+    // and w_ji (indices clamped into W)
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * kCiT;
-      v[u] = e < c * c ? W[e] : 0.0;
-    }
+    for (int u = 0; u < kRows; ++u)
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * kCiT;
-      if (e < c * c) {
-        const int i = e / c, j = e - i * c;
-        Ls[i * ld + j] = v[u];
+      for (int h = 0; h < kCols; ++h) {
+        const int i = min(wave + kWaves * u, c - 1), j = min(lane + 64 * h, c - 1);
+        v[u][h] = Wg[(size_t)i * c + j];
+        wt[u][h] = Wg[(size_t)j * c + i];
       }
-    }
-  }
-  for (int e = tid; e < cp * cp; e += kCiT) {
-    const int i = e / cp, j = e - i * cp;
-    if (i >= c || j >= c) Ls[i * ld + j] = (i == j) ? 1.0 : 0.0;
-    Bs[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    // A: the lower triangle (w_ij + w_ji) / 2, the rest w_ij; the identity
+    // past c in A, and in B throughout
+#pragma unroll
+    for (int u = 0; u < kRows; ++u)
+#pragma unroll
+      for (int h = 0; h < kCols; ++h) {
+        const int i = min(wave + kWaves * u, cp - 1), j = min(lane + 64 * h, cp - 1);
+        const double a0 = (i > j) ? 0.5 * (v[u][h] + wt[u][h]) : v[u][h];
+        Ls[i * ld + j] = (i < c && j < c) ? a0 : ((i == j) ? 1.0 : 0.0);
+        Bs[i * ld + j] = (i == j) ? 1.0 : 0.0;
+      }
   }
   if (tid == 0) bad = 0;
-  __syncthreads();
-  // each lower element is written by the one thread that reads its mirror
-  for (int e = tid; e < c * c; e += kCiT) {
-    const int i = e / c, j = e - i * c;
-    if (i > j) Ls[i * ld + j] = 0.5 * (Ls[i * ld + j] + Ls[j * ld + i]);
-  }
   __syncthreads();
   for (int k = 0; k < nb; ++k) {
     const int k0 = 16 * k;
     if (wave == 0) {
-      // 1. lane (r, g) holds columns 4 g .. 4 g + 3 of row r of the block
-      const int r = lane & 15, g = lane >> 4;
-      double d[4], xb[4];
+      // 1. lane r (and its copies r + 16, r + 32, r + 48) holds row r of the
+      // block in a and of X in x
+      const int r = lane & 15;
+      double a[16], x[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[q] = Ls[(k0 + r) * ld + k0 + 4 * g + q];
-        xb[q] = (r == 4 * g + q) ? 1.0 : 0.0;
+      for (int q = 0; q < 16; ++q) {
+        a[q] = Ls[(k0 + r) * ld + k0 + q];
+        x[q] = (q == r) ? 1.0 : 0.0;
       }
-      int badl = 0;
+      bool badl = false;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int gj = j >> 2, qj = j & 3;
-        const double dj = __shfl(d[qj], j + 16 * gj);               // pivot a_jj
-        badl |= (dj > 0.0) ? 0 : 1;
-        const double rs = rsq_newton(dj);
-        const double lr = __shfl(d[qj], r + 16 * gj) * rs;          // l_rj
-        double lc[4], bj[4];
+        const double p = readlane_d(a[j], j);                     // pivot a_jj
+        badl |= !(p > 0.0);
+        double sc[16], tx[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          lc[q] = __shfl(d[qj], 4 * g + q + 16 * gj) * rs;          // l_(4g+q) j
-          bj[q] = __shfl(xb[q], j + 16 * g) * rs;                   // scaled row j of X
-        }
+        for (int q = j + 1; q < 16; ++q) sc[q] = readlane_d(a[j], q);   // a_qj, q > j
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int col = 4 * g + q;
-          if (r == j) {
-            xb[q] = bj[q];
-            d[q] = (col == j) ? dj * rs : d[q];
-          } else if (r > j) {
-            d[q] = (col == j) ? lr : ((col > j) ? fma(-lr, lc[q], d[q]) : d[q]);
-            xb[q] = fma(-lr, bj[q], xb[q]);
-          }
-        }
+        for (int q = 0; q <= j; ++q) tx[q] = readlane_d(x[q], j);       // old row j of X
+        const double rs = rsq_newton(p);
+        // branch-free: rows above and at the pivot take multiple 0 (an
+        // exact no-op of the FMAs), rows other than the pivot's scale 1
+        const double f = (r > j) ? a[j] * (rs * rs) : 0.0;           // l_rj / l_jj
+        const double g = (r == j) ? rs : 1.0;
+#pragma unroll
+        for (int q = j + 1; q < 16; ++q) a[q] = fma(-f, sc[q], a[q]);
+#pragma unroll
+        for (int q = 0; q <= j; ++q) x[q] = fma(-f, tx[q], x[q]) * g;
+        a[j] *= (r >= j) ? rs : 1.0;                                 // l_rj (l_jj at r = j)
       }
+      if (lane < 16) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col = 4 * g + q;
-        Ls[(k0 + r) * ld + k0 + col] = (col <= r) ? d[q] : 0.0;
-        Bs[(k0 + r) * ld + k0 + col] = (col <= r) ? xb[q] : 0.0;
+        for (int q = 0; q < 16; ++q) {
+          Ls[(k0 + r) * ld + k0 + q] = (q <= r) ? a[q] : 0.0;
+          Bs[(k0 + r) * ld + k0 + q] = (q <= r) ? x[q] : 0.0;
+        }
       }
       if (badl && lane == 0) bad = 1;
     }
@@ -268,25 +280,49 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     }
     __syncthreads();
   }
+  gmem<double>* Rg = to_global(R);
+  gmem<double>* Rig = to_global(Rinv);
+  gmem<T>* RTg = to_global(RinvT);
   if (bad) {
     // R = 0 (no factor), Rinv = I keeps the later products finite
-    for (int idx = tid; idx < c * c; idx += kCiT) {
-      const int i = idx / c, j = idx - i * c;
-      const double v = (i == j) ? 1.0 : 0.0;
-      R[idx] = 0.0;
-      Rinv[idx] = v;
-      if (RinvT) RinvT[idx] = (T)v;
-    }
+    for (int i = wave; i < c; i += kWaves)
+      for (int j = lane; j < c; j += 64) {
+        const double v1 = (i == j) ? 1.0 : 0.0;
+        Rg[i * c + j] = 0.0;
+        Rig[i * c + j] = v1;
+        if (RinvT) RTg[i * c + j] = (T)v1;
+      }
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
   }
-  // R = L^T; (L^-1)_ik = (R^-1)_ki (zero above the diagonal)
-  for (int e = tid; e < c * c; e += kCiT) {
-    const int i = e / c, k = e - i * c;
-    R[e] = (k >= i) ? Ls[k * ld + i] : 0.0;
-    const double x = Bs[i * ld + k];
-    Rinv[k * c + i] = x;
-    if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
+  // R = L^T: R_ij = L_ji; R^-1 = (L^-1)^T: (R^-1)_ij = B_ji, row i of both
+  // from column i in LDS (stride ld odd: no bank conflicts); RinvT is R^-1
+  // or, with trans, its transpose B.  Indices clamped into c x c as above;
+  // four rows per batch: the LDS reads of a batch in flight together, then
+  // its coalesced stores.
+  constexpr int kBatch = 4;
+  static_assert(kRows % kBatch == 0, "whole batches of rows");
+#pragma unroll
+  for (int u0 = 0; u0 < kRows; u0 += kBatch) {
+    double rv[kBatch][kCols], xv[kBatch][kCols], bv[kBatch][kCols];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int h = 0; h < kCols; ++h) {
+        const int i = min(wave + kWaves * (u0 + u), c - 1), j = min(lane + 64 * h, c - 1);
+        rv[u][h] = (j >= i) ? Ls[j * ld + i] : 0.0;
+        xv[u][h] = Bs[j * ld + i];
+        bv[u][h] = Bs[i * ld + j];
+      }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int h = 0; h < kCols; ++h) {
+        const int i = min(wave + kWaves * (u0 + u), c - 1), j = min(lane + 64 * h, c - 1);
+        Rg[i * c + j] = rv[u][h];
+        Rig[i * c + j] = xv[u][h];
+        if (RinvT) RTg[i * c + j] = (T)(trans ? bv[u][h] : xv[u][h]);
+      }
   }
 }
 

@@ -747,8 +747,12 @@ constexpr int kNM = 128;
 
 // With GR the Gram partial of a solo launch is per block (slot = blockIdx.x,
 // at gram_part); 5 or 6 column tiles of FP64 Gram accumulators fit only at
-// one wave per SIMD.
-template <int NT, int NS, bool GR>
+// one wave per SIMD.  TRI: Xt is lower triangular (Xt[j][k] = 0 for k > j,
+// the transposed inverse Cholesky factor R^-1 of CholeskyQR, whose zero
+// blocks are exact), so k slab s only meets output tiles j >= s and the
+// products of the zero blocks are skipped: NT (NT + 1) / 2 of NT^2 tile
+// products at n = c.
+template <int NT, int NS, bool GR, bool TRI>
 __global__ __launch_bounds__(256, (GR && NT > kGramFuseMaxNt) ? 1 : 2) void k_gemm_nt_narrow(
     const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const float* __restrict__ Xt,
     int64_t ldxt, int c, float* __restrict__ Y, int64_t ldy, double* __restrict__ gram_part,
@@ -827,13 +831,15 @@ __global__ __launch_bounds__(256, (GR && NT > kGramFuseMaxNt) ? 1 : 2) void k_ge
       f32x4 bf[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j)
-        bf[j] = *reinterpret_cast<const f32x4*>(&Bs[(16 * j + lr) * LD + 16 * sl + 4 * g]);
+        if (!TRI || j >= sl)
+          bf[j] = *reinterpret_cast<const f32x4*>(&Bs[(16 * j + lr) * LD + 16 * sl + 4 * g]);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<float>::run(af[sl][i][t], bf[j][t], acc[i][j]);
+          for (int j = 0; j < NT; ++j)
+            if (!TRI || j >= sl) acc[i][j] = Mfma<float>::run(af[sl][i][t], bf[j][t], acc[i][j]);
     }
     const int64_t row0 = tl * kNM + wave * 32;
 #pragma unroll
@@ -1586,14 +1592,14 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
 // tiles, k slabs).
 constexpr int kNarrowSlabs = 6;
 
-template <int NT>
+template <int NT, bool TRI>
 hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                      int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
   const dim3 grid((unsigned)narrow_blocks(m)), block(256);
-#define RSVD_NT_NARROW(NS)                                                                     \
-  case NS:                                                                                     \
-    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, false>), grid, block, 0, s, A, m, n, lda, Xt, \
-                       ldxt, c, Y, ldy, nullptr, nullptr, nullptr);                            \
+#define RSVD_NT_NARROW(NS)                                                                          \
+  case NS:                                                                                          \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, false, TRI>), grid, block, 0, s, A, m, n, lda, Xt, \
+                       ldxt, c, Y, ldy, nullptr, nullptr, nullptr);                                 \
     break;
   switch (ns) {
     RSVD_NT_NARROW(1) RSVD_NT_NARROW(2) RSVD_NT_NARROW(3)
@@ -1604,30 +1610,37 @@ hipError_t narrow_nt(int ns, const float* A, int64_t m, int64_t n, int64_t lda, 
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_nt_narrow(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
-                                 int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+template <bool TRI>
+hipError_t launch_narrow(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                         int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
   const int ns = (int)((n + 15) / 16);
   switch ((c + 15) / 16) {
-    case 1: return narrow_nt<1>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 2: return narrow_nt<2>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 3: return narrow_nt<3>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 4: return narrow_nt<4>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 5: return narrow_nt<5>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 6: return narrow_nt<6>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 7: return narrow_nt<7>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
-    case 8: return narrow_nt<8>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 1: return narrow_nt<1, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 2: return narrow_nt<2, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 3: return narrow_nt<3, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 4: return narrow_nt<4, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 5: return narrow_nt<5, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 6: return narrow_nt<6, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 7: return narrow_nt<7, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+    case 8: return narrow_nt<8, TRI>(ns, A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-// The narrow product with the FP64 Gram matrix of its output: one c x c
-// partial per block at gram_part (persistent blocks, at most max_parts).
+hipError_t launch_gemm_nt_narrow(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                                 int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+  return launch_narrow<false>(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+}
+
+// The narrow product Y = A Xt^T with a lower-triangular Xt (A R^-1 of
+// CholeskyQR) and the FP64 Gram matrix of its output: one c x c partial per
+// block at gram_part (persistent blocks, at most max_parts).
 template <int NT, int NS>
 hipError_t narrow_gram_launch(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
                               int64_t ldxt, int c, float* Y, int64_t ldy, double* gram_part,
                               int nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, true>), dim3((unsigned)nblk), dim3(256), 0, s, A,
-                     m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nullptr, nullptr);
+  hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, true, true>), dim3((unsigned)nblk), dim3(256), 0, s,
+                     A, m, n, lda, Xt, ldxt, c, Y, ldy, gram_part, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1701,6 +1714,15 @@ hipError_t launch_gemm_nt_tall(const float* A, int64_t m, int64_t n, int64_t lda
   }
 #undef RSVD_NT_TALL
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt_tri(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                              int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s) {
+  if (!nt_tall_applies(A, n, lda, Xt, ldxt, c)) return hipErrorInvalidValue;
+  if (m <= 0) return hipSuccess;
+  if (n <= 16 * kNarrowSlabs && c <= 128)
+    return launch_narrow<true>(A, m, n, lda, Xt, ldxt, c, Y, ldy, s);
+  return launch_gemm_nt_tall(A, m, n, lda, Xt, ldxt, c, Y, ldy, nullptr, nullptr, s);
 }
 
 bool tn_tall_applies(const float* A, int64_t lda, const float* Q, int64_t ldq, int c) {
@@ -1958,13 +1980,13 @@ hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, const GWork* wl, int n
   }
 }
 
-template <int NT, bool GR>
+template <int NT, bool GR, bool TRI>
 hipError_t narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int ns, hipStream_t s) {
   const dim3 grid((unsigned)nwork), block(256);
-#define RSVD_G(NS)                                                                              \
-  case NS:                                                                                      \
-    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, GR>), grid, block, 0, s, nullptr, 0, 0, 0,     \
-                       nullptr, 0, 0, nullptr, 0, nullptr, a, wl);                              \
+#define RSVD_G(NS)                                                                                \
+  case NS:                                                                                        \
+    hipLaunchKernelGGL((k_gemm_nt_narrow<NT, NS, GR, TRI>), grid, block, 0, s, nullptr, 0, 0, 0,  \
+                       nullptr, 0, 0, nullptr, 0, nullptr, a, wl);                                \
     break;
   switch (ns) {
     RSVD_G(1) RSVD_G(2) RSVD_G(3) RSVD_G(4) RSVD_G(5) RSVD_G(6)
@@ -1974,19 +1996,26 @@ hipError_t narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int n
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int nt,
-                                         int ns, bool gram, hipStream_t s) {
-  if (nwork <= 0) return hipSuccess;
-  if (gram && nt > kGramFuseMaxNt) return hipErrorInvalidValue;
+template <bool TRI>
+hipError_t narrow_grouped_nt(const GArgNarrow* a, const GWork* wl, int nwork, int nt, int ns,
+                             bool gram, hipStream_t s) {
   switch (nt) {
-    case 1: return gram ? narrow_grouped<1, true>(a, wl, nwork, ns, s) : narrow_grouped<1, false>(a, wl, nwork, ns, s);
-    case 2: return gram ? narrow_grouped<2, true>(a, wl, nwork, ns, s) : narrow_grouped<2, false>(a, wl, nwork, ns, s);
-    case 3: return gram ? narrow_grouped<3, true>(a, wl, nwork, ns, s) : narrow_grouped<3, false>(a, wl, nwork, ns, s);
-    case 4: return gram ? narrow_grouped<4, true>(a, wl, nwork, ns, s) : narrow_grouped<4, false>(a, wl, nwork, ns, s);
-    case 5: return narrow_grouped<5, false>(a, wl, nwork, ns, s);
-    case 6: return narrow_grouped<6, false>(a, wl, nwork, ns, s);
+    case 1: return gram ? narrow_grouped<1, true, TRI>(a, wl, nwork, ns, s) : narrow_grouped<1, false, TRI>(a, wl, nwork, ns, s);
+    case 2: return gram ? narrow_grouped<2, true, TRI>(a, wl, nwork, ns, s) : narrow_grouped<2, false, TRI>(a, wl, nwork, ns, s);
+    case 3: return gram ? narrow_grouped<3, true, TRI>(a, wl, nwork, ns, s) : narrow_grouped<3, false, TRI>(a, wl, nwork, ns, s);
+    case 4: return gram ? narrow_grouped<4, true, TRI>(a, wl, nwork, ns, s) : narrow_grouped<4, false, TRI>(a, wl, nwork, ns, s);
+    case 5: return narrow_grouped<5, false, TRI>(a, wl, nwork, ns, s);
+    case 6: return narrow_grouped<6, false, TRI>(a, wl, nwork, ns, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int nt,
+                                         int ns, bool gram, bool tri, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (gram && nt > kGramFuseMaxNt) return hipErrorInvalidValue;
+  return tri ? narrow_grouped_nt<true>(a, wl, nwork, nt, ns, gram, s)
+             : narrow_grouped_nt<false>(a, wl, nwork, nt, ns, gram, s);
 }
 
 hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, const GWork* wl, int nwork, int nt,

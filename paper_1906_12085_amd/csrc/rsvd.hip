@@ -307,8 +307,10 @@ struct Path {
     return launch_reduce_partials(p->part, ns, n, c, Z, c, s);
   }
 
-  // Y Rinv (m x c, type T) with Rinv held in RinvT (c x c); fp32 with a
-  // narrow right factor takes it transposed (row j = column j of Rinv).
+  // Y Rinv (m x c, type T) with Rinv held in RinvT (c x c; an inverse
+  // Cholesky factor, upper triangular with exact zeros below its diagonal);
+  // fp32 with a narrow right factor takes it transposed (row j = column j of
+  // Rinv) and skips the products of its zero blocks.
   static bool times_rinv_tall(const T* Y, int c, int64_t ldy, const T* RinvT) {
     return std::is_same<T, float>::value &&
            nt_tall_applies(reinterpret_cast<const float*>(Y), c, ldy,
@@ -317,9 +319,9 @@ struct Path {
   hipError_t times_rinv(const T* Y, int64_t m, int c, int64_t ldy, const T* RinvT, bool tall,
                         T* Out, int64_t ldo) {
     if (tall)
-      return launch_gemm_nt_tall(reinterpret_cast<const float*>(Y), m, c, ldy,
-                                 reinterpret_cast<const float*>(RinvT), c, c,
-                                 reinterpret_cast<float*>(Out), ldo, nullptr, nullptr, s);
+      return launch_gemm_nt_tri(reinterpret_cast<const float*>(Y), m, c, ldy,
+                                reinterpret_cast<const float*>(RinvT), c, c,
+                                reinterpret_cast<float*>(Out), ldo, s);
     return launch_gemm_nn<T>(Y, m, c, ldy, RinvT, c, c, Out, ldo, nullptr, nullptr, s);
   }
 
@@ -2050,8 +2052,8 @@ struct rsvd_grouped_s {
 namespace {
 
 enum GKind {
-  G_RESET, G_FILL, G_CAST_T, G_TALL, G_NARROW, G_RED_S, G_GRAM_F, G_GRAM_D, G_RED, G_CHOL_F,
-  G_CHOL_D, G_TN, G_SG_F, G_SG_D, G_NN_D, G_JAC, G_JAC_ACC, G_SORT, G_SEL, G_TAKE
+  G_RESET, G_FILL, G_CAST_T, G_TALL, G_NARROW, G_NARROW_TRI, G_RED_S, G_GRAM_F, G_GRAM_D, G_RED,
+  G_CHOL_F, G_CHOL_D, G_TN, G_SG_F, G_SG_D, G_NN_D, G_JAC, G_JAC_ACC, G_SORT, G_SEL, G_TAKE
 };
 
 __global__ void k_status_grouped(const GArgStat* __restrict__ a) {
@@ -2271,7 +2273,7 @@ void record_group(GroupedBuilder& B, const rsvd_instance* in, const std::vector<
       it.push_back(panels(i));
       ct.push_back((double)l);
     }
-    B.add_wl(G_NARROW, rn, it, ct, ntl, nsl, fuse);
+    B.add_wl(G_NARROW_TRI, rn, it, ct, ntl, nsl, fuse);   // Y R1^-1: triangular factor
     if (fuse)
       gram_red();
     else
@@ -2440,9 +2442,10 @@ hipError_t grouped_launch(const rsvd_grouped_s* g, hipStream_t s) {
                                         op.nwork, op.a0, op.fuse, s);
         break;
       case G_NARROW:
+      case G_NARROW_TRI:
         e = launch_gemm_nt_narrow_grouped((const GArgNarrow*)a,
                                           (const GWork*)(g->args + op.wl_off), op.nwork, op.a0,
-                                          op.a1, op.fuse, s);
+                                          op.a1, op.fuse, op.kind == G_NARROW_TRI, s);
         break;
       case G_RED_S: e = launch_reduce_scalar_grouped((const GArgRedS*)a, op.count, s); break;
       case G_GRAM_F:

@@ -67,10 +67,16 @@ hipError_t launch_gemm_nt_wide(const float* A, int64_t m, int64_t n, int64_t lda
 // Y (m x c) = A Xt^T for fp32 with c <= 192 (Xt is c x n), optional per-block
 // FP64 partial sums of a_ij^2 (*nparts of them); requires nt_tall_applies.
 bool nt_tall_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt, int c);
-// Y (m x c) = A Xt^T on the narrow kernel (n <= 96, c <= 96) with the FP64
-// Gram matrix Y^T Y of the stored output as per-block c x c partials at
-// gram_part (*nparts of them, at most max_parts), summed by
-// launch_reduce_partials.
+// Y (m x c) = A Xt^T for a lower-triangular Xt with exact zeros above its
+// diagonal (the transposed inverse Cholesky factor of CholeskyQR): the
+// products of its zero blocks are skipped.  Same requirements as
+// launch_gemm_nt_tall.
+hipError_t launch_gemm_nt_tri(const float* A, int64_t m, int64_t n, int64_t lda, const float* Xt,
+                              int64_t ldxt, int c, float* Y, int64_t ldy, hipStream_t s);
+// Y (m x c) = A Xt^T on the narrow kernel (n <= 96, c <= 96) for a lower-
+// triangular Xt (as launch_gemm_nt_tri) with the FP64 Gram matrix Y^T Y of
+// the stored output as per-block c x c partials at gram_part (*nparts of
+// them, at most max_parts), summed by launch_reduce_partials.
 bool nt_narrow_gram_applies(const float* A, int64_t n, int64_t lda, const float* Xt, int64_t ldxt,
                             int c);
 hipError_t launch_gemm_nt_narrow_gram(const float* A, int64_t m, int64_t n, int64_t lda,
@@ -357,12 +363,14 @@ int64_t nn_row_blocks(int64_t m);
 // `maxblk` the largest nblk among them; the template choices (column tiles
 // nt, k slabs ns, element type) are the same for every problem of a launch.
 // The three work-list launchers take the item list `wl` (nwork items) and
-// the records it indexes; gram selects the fused-Gram kernels (nt <= 4).
+// the records it indexes; gram selects the fused-Gram kernels (nt <= 4);
+// tri: every Xt of the launch is lower triangular with exact zeros (an
+// inverse Cholesky factor), and the products of its zero blocks are skipped.
 constexpr int kGramFuseMaxNt = 4;
 hipError_t launch_gemm_nt_tall_grouped(const GArgTall* a, const GWork* wl, int nwork, int nt,
                                        bool gram, hipStream_t s);
 hipError_t launch_gemm_nt_narrow_grouped(const GArgNarrow* a, const GWork* wl, int nwork, int nt,
-                                         int ns, bool gram, hipStream_t s);
+                                         int ns, bool gram, bool tri, hipStream_t s);
 hipError_t launch_gemm_tn_tall_grouped(const GArgTn* a, const GWork* wl, int nwork, int nt,
                                        int cw, hipStream_t s);
 template <typename T>

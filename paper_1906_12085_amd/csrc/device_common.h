@@ -12,22 +12,6 @@ namespace {
 
 constexpr double kEps = 2.220446049250313e-16;
 
-// Device memory through address-space-1 (global) pointers.  A pointer that
-// reaches a kernel through an argument record is generic, and generic (flat)
-// accesses may alias LDS: the compiler then orders them against the kernel's
-// LDS accesses (a wait on both counters after each).  Only for pointers to
-// device memory.
-template <typename T>
-using gmem = __attribute__((address_space(1))) T;
-template <typename T>
-__device__ __forceinline__ gmem<T>* to_global(T* p) {
-  return (gmem<T>*)p;
-}
-template <typename T>
-__device__ __forceinline__ const gmem<T>* to_global(const T* p) {
-  return (const gmem<T>*)p;
-}
-
 // Errors win over warnings; among errors the most negative code wins.
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code) { atomicMin(status, code); }
 __device__ __forceinline__ void set_warning(int32_t* status, int32_t code) { atomicCAS(status, 0, code); }

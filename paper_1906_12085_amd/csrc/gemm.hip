@@ -1566,6 +1566,46 @@ __global__ void k_reduce_partials(const double* __restrict__ P, int nsplit, int6
   Z[i * ldz + j] = s;
 }
 
+// The same sum for many partials: a workgroup of kRsWaves waves covers 64
+// consecutive elements (lane = element), wave w sums the w-th contiguous run
+// of the partials in order (eight loads in flight), and the runs' sums are
+// added in wave order: a fixed order, with each thread's chain of dependent
+// loads kRsWaves times shorter.
+constexpr int kRsWaves = 8;
+
+__global__ __launch_bounds__(kRsWaves * 64) void k_reduce_partials_split(
+    const double* __restrict__ P, int nsplit, int64_t rows, int64_t cols, double* __restrict__ Z,
+    int64_t ldz) {
+  __shared__ double sh[kRsWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t total = rows * cols;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const int run = (nsplit + kRsWaves - 1) / kRsWaves;
+  const int k0 = wave * run, k1 = min(nsplit, k0 + run);
+  double s = 0.0;
+  if (idx < total) {
+    const gmem<double>* p = to_global(P) + idx;
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * total];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < k1; ++k) s += p[(int64_t)k * total];
+  }
+  sh[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && idx < total) {
+    double t = sh[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRsWaves; ++w) t += sh[w][lane];
+    const int64_t i = idx / cols, j = idx - i * cols;
+    to_global(Z)[i * ldz + j] = t;
+  }
+}
+
 __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double* out,
                                 const GArgRedS* __restrict__ grp) {
   if (grp) {
@@ -1583,6 +1623,71 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// W (c x c, FP64) = Y^T Y for a short panel (m <= kGramShortRows): one
+// workgroup per upper 16 x 16 tile pair (I, J), I <= J, and the waves of the
+// workgroup split the rows (wave w takes the 4-row steps w, w + 8, ...;
+// kGsUnroll steps' loads in flight per lane before their products); the
+// waves' tiles are added in wave order in LDS and the tile and its mirror are
+// written to W directly.  Against the row-split kernel plus the sum of its
+// partials (two launches, and for m = 512 only two workgroups) a single
+// short launch.  Same FP64 products of the stored values (exact for fp32).
+constexpr int kGsWaves = 8, kGsUnroll = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kGsWaves * 64) void k_gram_short(const T* __restrict__ Y, int64_t m,
+                                                              int c, int64_t ldy,
+                                                              double* __restrict__ W,
+                                                              int64_t ldw) {
+  typedef Mfma<double> M;
+  // tile pair of this workgroup: the upper pairs in row order
+  const int nt = (c + 15) >> 4;
+  int I = 0, rem = (int)blockIdx.x;
+  while (rem >= nt - I) {
+    rem -= nt - I;
+    ++I;
+  }
+  const int J = I + rem;
+  __shared__ double red[kGsWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int ci = 16 * I + x, cj = 16 * J + x;
+  const bool oki = ci < c, okj = cj < c;
+  const T* yi = Y + (oki ? ci : 0);
+  const T* yj = Y + (okj ? cj : 0);
+  const int64_t nks = (m + 3) / 4;                      // 4-row steps
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = wave; k0 < nks; k0 += (int64_t)kGsWaves * kGsUnroll) {
+    double a[kGsUnroll], b[kGsUnroll];
+#pragma unroll
+    for (int u = 0; u < kGsUnroll; ++u) {
+      const int64_t row = 4 * (k0 + (int64_t)kGsWaves * u) + g;
+      const bool rok = row < m;
+      a[u] = (rok && oki) ? (double)yi[row * ldy] : 0.0;
+      b[u] = (rok && okj) ? (double)yj[row * ldy] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGsUnroll; ++u) acc = M::run(a[u], b[u], acc);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[wave][e * 64 + lane] = acc[e];
+  __syncthreads();
+  if (wave == 0) {
+    f64x4 t = acc;
+#pragma unroll
+    for (int w = 1; w < kGsWaves; ++w)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[e] += red[w][e * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * I + M::row(lane, e), j = 16 * J + x;
+      if (i < c && j < c) {
+        W[i * ldw + j] = t[e];
+        if (I != J) W[j * ldw + i] = t[e];
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -1669,7 +1774,11 @@ hipError_t launch_gemm_nt_narrow_gram(const float* A, int64_t m, int64_t n, int6
                                       double* gram_part, int64_t max_parts, int* nparts,
                                       hipStream_t s) {
   if (!nt_narrow_gram_applies(A, n, lda, Xt, ldxt, c) || max_parts < 1) return hipErrorInvalidValue;
+  // past kGramFuseMaxNt column tiles the kernel holds one workgroup per CU:
+  // one persistent workgroup per CU (half the partials to sum, no second
+  // round of workgroups)
   int64_t nb = narrow_blocks(m);
+  if ((c + 15) / 16 > kGramFuseMaxNt && nb > 256) nb = 256;
   if (nb > max_parts) nb = max_parts;
   *nparts = m > 0 ? (int)nb : 0;
   if (m <= 0) return hipSuccess;
@@ -1891,12 +2000,26 @@ hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P,
   }
 }
 
+template <typename T>
+hipError_t launch_gram_short(const T* Y, int64_t m, int c, int64_t ldy, double* W, int64_t ldw,
+                             hipStream_t s) {
+  if (m <= 0 || c <= 0 || m > kGramShortRows) return hipErrorInvalidValue;
+  const int nt = (c + 15) / 16;
+  hipLaunchKernelGGL(k_gram_short<T>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kGsWaves * 64), 0,
+                     s, Y, m, c, ldy, W, ldw);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,
                                   double* Z, int64_t ldz, hipStream_t s) {
   const int64_t total = rows * cols;
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     P, nsplit, rows, cols, Z, ldz, nullptr);
+  if (nsplit >= 4 * kRsWaves)
+    hipLaunchKernelGGL(k_reduce_partials_split, dim3((unsigned)((total + 63) / 64)),
+                       dim3(kRsWaves * 64), 0, s, P, nsplit, rows, cols, Z, ldz);
+  else
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       P, nsplit, rows, cols, Z, ldz, nullptr);
   return hipGetLastError();
 }
 
@@ -2119,6 +2242,10 @@ template hipError_t launch_gram_f64<float>(const float*, int64_t, int, int64_t, 
                                            int*, hipStream_t);
 template hipError_t launch_gram_f64<double>(const double*, int64_t, int, int64_t, double*, int64_t,
                                             int*, hipStream_t);
+template hipError_t launch_gram_short<float>(const float*, int64_t, int, int64_t, double*, int64_t,
+                                             hipStream_t);
+template hipError_t launch_gram_short<double>(const double*, int64_t, int, int64_t, double*,
+                                              int64_t, hipStream_t);
 template hipError_t launch_gemm_tn_partial<float, float>(const float*, int64_t, int64_t, int64_t,
                                                          const float*, int64_t, int, double*,
                                                          int64_t, int*, hipStream_t);

@@ -281,6 +281,7 @@ struct Path {
 
   // Wout (c x c) = Y^T Y with exact FP64 products, fixed-order reduction.
   hipError_t gram(const T* Y, int64_t m, int c, int64_t ldy, double* Wout) {
+    if (m <= kGramShortRows) return launch_gram_short<T>(Y, m, c, ldy, Wout, c, s);
     int ns = 0;
     hipError_t e = launch_gram_f64<T>(Y, m, c, ldy, p->part, p->max_split, &ns, s);
     if (e != hipSuccess) return e;
@@ -322,6 +323,10 @@ struct Path {
       return launch_gemm_nt_tri(reinterpret_cast<const float*>(Y), m, c, ldy,
                                 reinterpret_cast<const float*>(RinvT), c, c,
                                 reinterpret_cast<float*>(Out), ldo, s);
+    if (std::is_same<T, double>::value && m <= kGramShortRows && ldy == c && ldo == c)
+      return launch_small_gemm<double>(reinterpret_cast<const double*>(Y),
+                                       reinterpret_cast<const double*>(RinvT), m, c, c,
+                                       reinterpret_cast<double*>(Out), nullptr, s, 0);
     return launch_gemm_nn<T>(Y, m, c, ldy, RinvT, c, c, Out, ldo, nullptr, nullptr, s);
   }
 
@@ -376,6 +381,9 @@ hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, doubl
   hipError_t e = d.cqr2(Zin, n, c, c, p->Z1, c, p->R1s, p->R1invs, p->R2s, p->R2invs,
                         (double*)p->RinvTs, 0);
   if (e != hipSuccess) return e;
+  if (n <= kGramShortRows)   // a short panel: the one-thread-per-output product
+    return launch_small_gemm<double>(p->Z1, (const double*)p->RinvTs, n, c, c, Zout, nullptr,
+                                     p->stream, 0);
   return launch_gemm_nn<double>(p->Z1, n, c, c, (const double*)p->RinvTs, c, c, Zout, c, nullptr,
                                 nullptr, p->stream);
 }

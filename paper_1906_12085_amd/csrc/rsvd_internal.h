@@ -9,6 +9,22 @@
 
 namespace rsvd {
 
+// Device memory through address-space-1 (global) pointers.  A pointer that
+// reaches a kernel through an argument record is generic, and generic (flat)
+// accesses may alias LDS: the compiler then orders them against the kernel's
+// LDS accesses (a wait on both counters after each).  Only for pointers to
+// device memory.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* to_global(T* p) {
+  return (gmem<T>*)p;
+}
+template <typename T>
+__device__ __forceinline__ const gmem<T>* to_global(const T* p) {
+  return (const gmem<T>*)p;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -116,6 +132,13 @@ hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda,
 template <typename T>
 hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
                            int* nsplit, hipStream_t s);
+
+// W (c x c, FP64, ldw) = Y^T Y for a short panel (m <= kGramShortRows) in one
+// launch: one workgroup per 16 x 16 tile pair, no partials.
+constexpr int64_t kGramShortRows = 8192;
+template <typename T>
+hipError_t launch_gram_short(const T* Y, int64_t m, int c, int64_t ldy, double* W, int64_t ldw,
+                             hipStream_t s);
 
 // Z (rows x cols) = sum over s < nsplit of P[s] (each rows x cols), fixed order.
 hipError_t launch_reduce_partials(const double* P, int nsplit, int64_t rows, int64_t cols,

@@ -456,6 +456,9 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
     }
 }
 
+// C (r x c2) = A (r x c1) B (c1 x c2), FP64, all row-major and contiguous,
+// one thread per output; optionally also CT = C cast to T (transposed with
+// trans).  For the small products between the passes (c1, c2 <= 192).
 template <typename T>
 __global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
                              int64_t r, int c1, int c2, double* __restrict__ C, T* __restrict__ CT,
@@ -469,10 +472,26 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   if (idx >= r * c2) return;
   const int64_t i = idx / c2;
   const int j = (int)(idx - i * c2);
+  const gmem<double>* a = to_global(A) + i * c1;
+  const gmem<double>* b = to_global(B) + j;
+  // the sum in k order (one FMA chain); the loads of 16 steps in flight at
+  // once, not one step's at a time
+  constexpr int KU = 16;
   double s = 0.0;
-  for (int k = 0; k < c1; ++k) s += A[i * c1 + k] * B[(int64_t)k * c2 + j];
-  if (C) C[idx] = s;
-  if (CT) CT[trans ? (int64_t)j * r + i : idx] = (T)s;
+  int k = 0;
+  for (; k + KU <= c1; k += KU) {
+    double av[KU], bv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      av[u] = a[k + u];
+      bv[u] = b[(int64_t)(k + u) * c2];
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) s = fma(av[u], bv[u], s);
+  }
+  for (; k < c1; ++k) s = fma(a[k], b[(int64_t)k * c2], s);
+  if (C) to_global(C)[idx] = s;
+  if (CT) to_global(CT)[trans ? (int64_t)j * r + i : idx] = (T)s;
 }
 
 // One-sided Jacobi SVD of a c x c matrix M (c <= 96) in one block: the

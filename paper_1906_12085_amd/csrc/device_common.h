@@ -62,11 +62,15 @@ __device__ __forceinline__ double rsq_step(double x, double y) {
 
 // A pair of columns with alpha = |x_p|^2, beta = |x_q|^2, gamma = x_p.x_q is
 // rotated when the cosine of their angle exceeds tol (gamma^2 > tol^2 alpha
-// beta) and |gamma| exceeds floor (a level below which the columns' inner
-// product is rounding noise of the input).
+// beta) and gamma^2 exceeds floor2 max(alpha, beta).  With floor2 =
+// (eps |G|_F)^2 the second test leaves alone a coupling at the rounding level
+// of the input G (entries carry errors of order eps |G|_F, so the inner
+// product of a column of norm |x| with any other carries eps |G|_F |x|); in
+// particular two columns both below that noise level are never rotated
+// against each other.  floor2 = 0: every nonzero coupling past tol.
 __device__ __forceinline__ bool rot_needed(double al, double be, double ga, double tol2,
-                                           double floor) {
-  return fabs(ga) > floor && ga * ga > tol2 * (al * be);
+                                           double floor2) {
+  return ga * ga > floor2 * fmax(al, be) && ga * ga > tol2 * (al * be);
 }
 
 // The rotation (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) that makes the

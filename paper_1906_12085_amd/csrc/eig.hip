@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
   double fro2 = 0.0;
   for (int i = 0; i < nwg; ++i) fro2 += ld_agent(fro_part + i);
   const double tol = kEps * (double)n, tol2 = tol * tol;
-  const double floor = svd ? 0.0 : kEps * kEps * fro2;
+  const double floor2 = svd ? 0.0 : kEps * kEps * fro2;   // (eps |G|_F)^2
 
   // Stage this slice of the pair's kW columns of a matrix (X or J) into LDS,
   // all loads issued before the first store.
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
       int need = 0;
       for (int e = tid; e < kW * kW; e += kThreads) {
         const int i = e / kW, j = e - i * kW;
-        if (i < j) need |= rot_needed(Mb[i * kLdM + i], Mb[j * kLdM + j], Mb[i * kLdM + j], tol2, floor) ? 1 : 0;
+        if (i < j) need |= rot_needed(Mb[i * kLdM + i], Mb[j * kLdM + j], Mb[i * kLdM + j], tol2, floor2) ? 1 : 0;
       }
       const int nneed = __syncthreads_count(need);
       if (nneed > 0) {
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(kThreads) void k_jacobi_eig(
             double* r0 = Rl + (2 * a) * kLdM;
             double* r1 = r0 + kLdM;
             const double x0 = r0[pb], x1 = r0[qb], y0 = r1[pb], y1 = r1[qb];
-            const bool ra = rot_needed(aal, abe, aga, tol2, floor);
-            const bool rb = rot_needed(bal, bbe, bga, tol2, floor);
+            const bool ra = rot_needed(aal, abe, aga, tol2, floor2);
+            const bool rb = rot_needed(bal, bbe, bga, tol2, floor2);
             double ta, ca, sa, tb, cb, sb;
             rot_cst(aal, abe, aga, ra, &ca, &sa, &ta);
             rot_cst(bal, bbe, bga, rb, &cb, &sb, &tb);

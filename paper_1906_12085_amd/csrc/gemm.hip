@@ -1388,142 +1388,106 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64(const T* __restric
 }
 
 // ---------------------------------------------------------------------------
-// The same FP64 Gram W = Y^T Y for panels wider than 96 columns (c <= 192):
-// the columns are cut into segments of kGsW 16-column tiles, and one block
-// computes the tile pairs of one segment pair (sa <= sb; the upper tile
-// pairs only when sa == sb) over one row split, so a wave keeps at most
-// kGsW^2 accumulator tiles.  The segment pairs of a row split are given to
-// consecutive workgroups of one XCD (workgroup b runs on XCD b mod 8), so
-// they read the split's rows of Y from that XCD's L2 after the first.
-// Rows, the wave split, the fixed-order LDS reduction and the exact FP64
-// products are those of k_gram_f64; each block writes its tiles of the
-// split's symmetric partial P[split] (c x c), mirrored below the diagonal
-// tiles.  Tiles past c (the last segment of a c that is not a multiple of
-// 64) are skipped.
-constexpr int kGsW = 4;
+// W partials (c x c, FP64) of Y^T Y for wide panels (96 < c <= 192): one
+// workgroup per row split stages 32-row chunks of all c columns in LDS (two
+// buffers, the next chunk's loads in flight while the current one is
+// multiplied), and its eight waves take disjoint sets of the upper 16 x 16
+// tile pairs (pair p to wave p mod 8, at most kGlMaxPairs each), so every row
+// of Y is read from memory once and the waves need no sum across them; each
+// wave writes its tiles (and their mirrors) to the split's partial.  The LDS
+// row stride is 16 (mod 32) words, so the four 4-row groups of a read fall in
+// alternate halves of the banks.
+constexpr int kGlWaves = 8, kGlRows = 32;
 
-template <typename T>
-__global__ __launch_bounds__(kGramWaves * 64) void k_gram_f64_seg(const T* __restrict__ Y, int64_t m,
-                                                                int c, int64_t ldy,
-                                                                double* __restrict__ P,
-                                                                int64_t rows_per_block,
-                                                                int64_t nsplit, int nseg,
-                                                                int64_t per_xcd) {
+template <typename T, int NT>
+__global__ __launch_bounds__(kGlWaves * 64) void k_gram_lds(const T* __restrict__ Y, int64_t m,
+                                                            int c, int64_t ldy,
+                                                            double* __restrict__ P,
+                                                            int64_t rows_per_block) {
   typedef Mfma<double> M;
-  constexpr int U = 2;                       // 4-row groups per register set
-  constexpr int64_t STEP = (int64_t)4 * kGramWaves * U;
-  __shared__ double red[kGsW * kGsW][256];
-  const int npair = nseg * (nseg + 1) / 2;
-  const int64_t L = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (L >= nsplit * npair) return;
-  const int64_t split = L / npair;
-  int sa = 0, rem = (int)(L - split * npair);
-  while (rem >= nseg - sa) { rem -= nseg - sa; ++sa; }
-  const int sb = sa + rem;
-  const bool sym = sa == sb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NPAIR = NT * (NT + 1) / 2, MAXP = (NPAIR + kGlWaves - 1) / kGlWaves;
+  constexpr int LD = (NT % 2) ? 16 * NT : 16 * NT + 16;
+  constexpr int NTH = kGlWaves * 64;
+  constexpr int EPT = (kGlRows * 16 * NT + NTH - 1) / NTH;   // staged elements per thread
+  __shared__ T Ys[2][kGlRows * LD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int x = lane & 15, g = lane >> 4;
-  const int64_t rs = split * rows_per_block;
-  const int64_t re = (rs + rows_per_block < m) ? rs + rows_per_block : m;
-  const int ca = 16 * kGsW * sa, cb = 16 * kGsW * sb;
-  f64x4 acc[kGsW][kGsW];
+  const int64_t rs = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = rs + rows_per_block < m ? rs + rows_per_block : m;
+  // this wave's tile pairs (upper pairs in row order, every eighth)
+  int pI[MAXP], pJ[MAXP];
+  const int np = (NPAIR - wave + kGlWaves - 1) / kGlWaves;
 #pragma unroll
-  for (int I = 0; I < kGsW; ++I)
-#pragma unroll
-    for (int J = 0; J < kGsW; ++J) acc[I][J] = f64x4{0, 0, 0, 0};
-  bool oka[kGsW], okb[kGsW];
-#pragma unroll
-  for (int J = 0; J < kGsW; ++J) {
-    oka[J] = (ca + 16 * J + x) < c;
-    okb[J] = (cb + 16 * J + x) < c;
+  for (int q = 0; q < MAXP; ++q) {
+    int I = 0, rem = q < np ? wave + kGlWaves * q : 0;
+    while (rem >= NT - I) {
+      rem -= NT - I;
+      ++I;
+    }
+    pI[q] = I;
+    pJ[q] = I + rem;
   }
-  auto load = [&](int64_t r0, T(&ya)[U][kGsW], T(&yb)[U][kGsW]) {
+  f64x4 acc[MAXP];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t row = r0 + (int64_t)4 * kGramWaves * u + g;
-      const bool rok = row < re;
+  for (int q = 0; q < MAXP; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // both buffers zeroed once: columns past c stay zero
+  for (int e = tid; e < 2 * kGlRows * LD; e += NTH) (&Ys[0][0])[e] = T(0);
+  // the chunk elements this thread stages (row er, column ec), fixed per chunk
+  int er[EPT], ec[EPT];
 #pragma unroll
-      for (int J = 0; J < kGsW; ++J) {
-        ya[u][J] = (rok && oka[J]) ? Y[row * ldy + ca + 16 * J + x] : T(0);
-        yb[u][J] = (rok && okb[J]) ? Y[row * ldy + cb + 16 * J + x] : T(0);
-      }
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + NTH * u;
+    er[u] = e / c;
+    ec[u] = e - er[u] * c;
+  }
+  const gmem<T>* Yg = to_global(Y);
+  T v[EPT];
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int64_t row = r0 + er[u];
+      v[u] = (er[u] < kGlRows && row < re) ? Yg[row * ldy + ec[u]] : T(0);
     }
   };
-  auto compute = [&](const T(&ya)[U][kGsW], const T(&yb)[U][kGsW]) {
+  auto store = [&](int b) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      double da[kGsW], db[kGsW];
-#pragma unroll
-      for (int J = 0; J < kGsW; ++J) {
-        da[J] = (double)ya[u][J];
-        db[J] = (double)yb[u][J];
-      }
-#pragma unroll
-      for (int I = 0; I < kGsW; ++I)
-#pragma unroll
-        for (int J = 0; J < kGsW; ++J)
-          if ((!sym || I <= J) && ca + 16 * I < c && cb + 16 * J < c)   // uniform per block
-            acc[I][J] = M::run(da[I], db[J], acc[I][J]);
-    }
+    for (int u = 0; u < EPT; ++u)
+      if (er[u] < kGlRows) Ys[b][er[u] * LD + ec[u]] = v[u];
   };
-  T a0[U][kGsW], b0[U][kGsW], a1[U][kGsW], b1[U][kGsW];
-  int64_t r = rs + 4 * wave;
-  load(r, a0, b0);
-  while (r < re) {
-    const bool has1 = r + STEP < re;
-    if (has1) load(r + STEP, a1, b1);
-    compute(a0, b0);
-    if (!has1) break;
-    const bool has2 = r + 2 * STEP < re;
-    if (has2) load(r + 2 * STEP, a0, b0);
-    compute(a1, b1);
-    if (!has2) break;
-    r += 2 * STEP;
+  __syncthreads();
+  int b = 0;
+  if (rs < re) {
+    load(rs);
+    store(0);
   }
-  // fixed-order reduction of the waves' tiles in LDS
-  for (int w = 0; w < kGramWaves; ++w) {
-    if (wave == w) {
+  __syncthreads();
+  for (int64_t r0 = rs; r0 < re; r0 += kGlRows, b ^= 1) {
+    const bool more = r0 + kGlRows < re;
+    if (more) load(r0 + kGlRows);
 #pragma unroll
-      for (int I = 0; I < kGsW; ++I)
+    for (int sk = 0; sk < kGlRows / 4; ++sk) {
+      const T* row = &Ys[b][(4 * sk + g) * LD + x];
 #pragma unroll
-        for (int J = 0; J < kGsW; ++J) {
-          if (sym && I > J) continue;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int t = M::row(lane, e) * 16 + x;
-            red[I * kGsW + J][t] = (w == 0) ? acc[I][J][e] : red[I * kGsW + J][t] + acc[I][J][e];
-          }
-        }
+      for (int q = 0; q < MAXP; ++q)
+        if (q < np) acc[q] = M::run((double)row[16 * pI[q]], (double)row[16 * pJ[q]], acc[q]);
     }
+    if (more) store(b ^ 1);
     __syncthreads();
   }
-  double* Pb = P + split * (int64_t)c * c;
-  for (int idx = threadIdx.x; idx < kGsW * kGsW * 256; idx += kGramWaves * 64) {
-    const int tp = idx >> 8, t = idx & 255;
-    const int I = tp / kGsW, J = tp - I * kGsW;
-    if (sym && I > J) continue;
-    const int i = ca + 16 * I + (t >> 4), j = cb + 16 * J + (t & 15);
-    if (i >= c || j >= c) continue;
-    const double v = red[tp][t];
-    Pb[(int64_t)i * c + j] = v;
-    if (!(sym && I == J)) Pb[(int64_t)j * c + i] = v;
-  }
-}
-
-template <typename T>
-hipError_t gram_seg_dispatch(const T* Y, int64_t m, int c, int64_t ldy, double* P,
-                             int64_t max_split, int* nsplit, hipStream_t s) {
-  const int nseg = (c + 16 * kGsW - 1) / (16 * kGsW);
-  const int npair = nseg * (nseg + 1) / 2;
-  // about two blocks per CU in all, splits of at least 1024 rows
-  int64_t rpb = 0;
-  const int64_t blocks = gram_blocks(m, max_split < 512 / npair ? max_split : 512 / npair, &rpb,
-                                     1024);
-  *nsplit = (int)blocks;
-  const int64_t per_xcd = (blocks * npair + 7) / 8;
-  hipLaunchKernelGGL((k_gram_f64_seg<T>), dim3((unsigned)(8 * per_xcd)), dim3(kGramWaves * 64), 0,
-                     s, Y, m, c, ldy, P, rpb, blocks, nseg, per_xcd);
-  return hipGetLastError();
+  double* Pb = P + (int64_t)blockIdx.x * c * c;
+#pragma unroll
+  for (int q = 0; q < MAXP; ++q)
+    if (q < np) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * pI[q] + M::row(lane, e), j = 16 * pJ[q] + x;
+        if (i < c && j < c) {
+          Pb[(int64_t)i * c + j] = acc[q][e];
+          if (pI[q] != pJ[q]) Pb[(int64_t)j * c + i] = acc[q][e];
+        }
+      }
+    }
 }
 
 template <typename T, int NT>
@@ -1994,9 +1958,25 @@ hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P,
     case 4: return gram_dispatch<T, 4>(Y, m, c, ldy, P, max_split, nsplit, s);
     case 5: return gram_dispatch<T, 5>(Y, m, c, ldy, P, max_split, nsplit, s);
     case 6: return gram_dispatch<T, 6>(Y, m, c, ldy, P, max_split, nsplit, s);
-    default:
-      if (c > 16 * kGsW * 3) return hipErrorInvalidValue;   // c <= 192
-      return gram_seg_dispatch<T>(Y, m, c, ldy, P, max_split, nsplit, s);
+    default: {
+      if (c > 192) return hipErrorInvalidValue;
+      // one workgroup per split of at least 1024 rows, at most one per CU
+      int64_t rpb = 0;
+      const int64_t blocks = gram_blocks(m, max_split < 256 ? max_split : 256, &rpb, 1024);
+      *nsplit = (int)blocks;
+      const dim3 grid((unsigned)blocks), block(kGlWaves * 64);
+      // c <= 112 takes the 8-tile kernel (its last tile column all zeros):
+      // the 7-tile build needs every register and spills
+      switch ((c + 15) / 16) {
+        case 7:
+        case 8: hipLaunchKernelGGL((k_gram_lds<T, 8>), grid, block, 0, s, Y, m, c, ldy, P, rpb); break;
+        case 9: hipLaunchKernelGGL((k_gram_lds<T, 9>), grid, block, 0, s, Y, m, c, ldy, P, rpb); break;
+        case 10: hipLaunchKernelGGL((k_gram_lds<T, 10>), grid, block, 0, s, Y, m, c, ldy, P, rpb); break;
+        case 11: hipLaunchKernelGGL((k_gram_lds<T, 11>), grid, block, 0, s, Y, m, c, ldy, P, rpb); break;
+        default: hipLaunchKernelGGL((k_gram_lds<T, 12>), grid, block, 0, s, Y, m, c, ldy, P, rpb); break;
+      }
+      return hipGetLastError();
+    }
   }
 }
 

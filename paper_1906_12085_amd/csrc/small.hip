@@ -418,13 +418,19 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
   __shared__ int bad;
   const int tid = threadIdx.x, ti = tid >> 5, tk = tid & 31, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // device memory through global pointers (generic ones would order every
+  // access against the LDS traffic of the elimination)
+  const gmem<double>* Wg = to_global(W);
+  gmem<double>* Rg = to_global(R);
+  gmem<double>* Rig = to_global(Rinv);
+  gmem<T>* RTg = to_global(RinvT);
   double a[U][U];
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int v = 0; v < U; ++v) {
       const int i = ti + 32 * u, k = tk + 32 * v;
-      a[u][v] = (i < c && k < c && k >= i) ? 0.5 * (W[i * c + k] + W[k * c + i]) : 0.0;
+      a[u][v] = (i < c && k < c && k >= i) ? 0.5 * (Wg[i * c + k] + Wg[k * c + i]) : 0.0;
     }
   if (tid == 0) bad = 0;
   __syncthreads();
@@ -434,9 +440,9 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
     for (int idx = tid; idx < c * c; idx += kCwT) {
       const int i = idx / c, j = idx - i * c;
       const double v = (i == j) ? 1.0 : 0.0;
-      R[idx] = 0.0;
-      Rinv[idx] = v;
-      if (RinvT) RinvT[idx] = (T)v;
+      Rg[idx] = 0.0;
+      Rig[idx] = v;
+      if (RinvT) RTg[idx] = (T)v;
     }
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
     return;
@@ -448,10 +454,10 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
     for (int v = 0; v < U; ++v) {
       const int i = ti + 32 * u, k = tk + 32 * v;
       if (i < c && k < c) {
-        R[i * c + k] = k >= i ? a[u][v] : 0.0;
+        Rg[i * c + k] = k >= i ? a[u][v] : 0.0;
         const double x = k < i ? a[u][v] : (k == i ? rdiag[i] : 0.0);
-        Rinv[k * c + i] = x;
-        if (RinvT) RinvT[trans ? i * c + k : k * c + i] = (T)x;
+        Rig[k * c + i] = x;
+        if (RinvT) RTg[trans ? i * c + k : k * c + i] = (T)x;
       }
     }
 }

@@ -127,8 +127,9 @@ hipError_t launch_gemm_tn_partial(const T* A, int64_t m, int64_t n, int64_t lda,
                                   hipStream_t s);
 
 // Symmetric partial Gram matrices P[s] (c x c, FP64) of a tall m x c panel Y,
-// accumulated in FP64 from exact products (upper tile pairs for c <= 96, the
-// general split-m product above that).
+// one per row split, accumulated in FP64 from exact products (every wave of
+// a split holds all upper tile pairs for c <= 96; above that, up to 192, the
+// split's rows are staged in LDS and its waves share out the tile pairs).
 template <typename T>
 hipError_t launch_gram_f64(const T* Y, int64_t m, int c, int64_t ldy, double* P, int64_t max_split,
                            int* nsplit, hipStream_t s);

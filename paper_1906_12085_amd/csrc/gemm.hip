@@ -1576,10 +1576,19 @@ __global__ void k_reduce_scalar(const double* __restrict__ parts, int n, double*
     const GArgRedS& a = grp[blockIdx.y];
     parts = a.parts; n = a.n; out = a.out;
   }
-  // fixed order: 256 strided lanes, then a fixed tree
+  // fixed order: 256 strided lanes (each adding its entries in index order,
+  // eight loads in flight), then a fixed tree
   __shared__ double sh[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += parts[i];
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = parts[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; i < n; i += 256) s += parts[i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

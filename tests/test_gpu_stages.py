@@ -217,7 +217,7 @@ def test_gemm_tn_padded_rows(plans, m, n, pad, c):
 @pytest.mark.parametrize("name", DTYPES)
 @pytest.mark.parametrize("m,c,kappa", [(2000, 30, 1e2), (5000, 80, 1e3), (333, 17, 10.0),
                                            (3000, 96, 1e2), (4000, 44, 1e3), (500, 1, 1.0),
-                                           (1200, 16, 10.0), (2500, 65, 1e2)])
+                                           (1200, 16, 10.0), (2500, 65, 1e2), (6000, 33, 1e2)])
 def test_cholqr2_parity(plans, name, m, c, kappa):
     dt = DTYPES[name]
     announce(f"cholqr2 {name} m={m} c={c} kappa={kappa}")

@@ -54,8 +54,11 @@ def test_wide_plan_limits():
 
 
 @pytest.mark.parametrize("name", DTYPES)
+# m <= 8192 takes the one-launch short Gram; longer panels the LDS-staged
+# row-split kernel (c <= 112 on its 8-tile build), at 8193 just past the switch
 @pytest.mark.parametrize("m,c,kappa", [(3000, 97, 1e2), (5000, 128, 1e3), (4001, 160, 1e3),
-                                       (2500, 192, 10.0), (3000, 113, 1e4)])
+                                       (2500, 192, 10.0), (3000, 113, 1e4), (8193, 100, 1e2),
+                                       (12001, 112, 1e3), (20000, 150, 1e2), (9500, 192, 1e3)])
 def test_wide_cholqr2_parity(plans, name, m, c, kappa):
     dt = DTYPES[name]
     announce(f"wide cholqr2 {name} m={m} c={c} kappa={kappa}")

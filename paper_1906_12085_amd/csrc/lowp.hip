@@ -229,6 +229,9 @@ template <int NT> constexpr int nt_bf16_threads() { return 512; }
 // FP32 accumulators then stay within two waves per SIMD)
 template <int NT> constexpr int nt_bf16_tiles() { return NT <= 5 ? 4 : 2; }
 template <int NT> constexpr int nt_bf16_rows() { return nt_bf16_threads<NT>() / 64 * 16 * nt_bf16_tiles<NT>(); }
+// persistent workgroups of the NT pass: as many per CU as fit (the
+// occupancy of the instantiation), on the 256 CUs
+constexpr int64_t kLowpCus = 256;
 
 template <int NT, int ES>
 __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
@@ -245,13 +248,21 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   __shared__ double red[kBT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kBM;
-  const int64_t rows = m - row0 < kBM ? m - row0 : kBM;
   const int nch = (int)((n + kBK - 1) / kBK);
   const bool do_ss = fro2_part != nullptr;
-  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<unsigned char*>(A + row0 * lda * ES), 0, (int)(((rows - 1) * lda + n) * ES),
-      0x00020000);
+  // persistent workgroups: this one takes the kBM-row tiles blockIdx.x,
+  // blockIdx.x + gridDim.x, ... as one stream of 32-deep steps, so the loads
+  // run ahead across tile boundaries (no drain and refill per tile)
+  const int64_t ntile = (m + kBM - 1) / kBM;
+  const int nlt = (int)((ntile - blockIdx.x + gridDim.x - 1) / gridDim.x);
+  auto tile_row0 = [&](int lt) { return ((int64_t)blockIdx.x + (int64_t)lt * gridDim.x) * kBM; };
+  // the tile's rows; the range ends at the last element of its last row
+  auto tile_rsrc = [&](int lt) {
+    const int64_t r0 = tile_row0(lt);
+    const int64_t rows = m - r0 < kBM ? m - r0 : kBM;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(A + r0 * lda * ES), 0,
+                                             (int)(((rows - 1) * lda + n) * ES), 0x00020000);
+  };
   const int xrange = (int)(((int64_t)(c - 1) * ldx + n) * 2);
   const __amdgpu_buffer_rsrc_t hr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Xhi), 0, xrange, 0x00020000);
@@ -278,7 +289,7 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
   typedef typename Frag<ES>::raw raw_t;
   raw_t ra[2][RT];
   u32x4 rx[XP];
-  auto load_a = [&](int t, raw_t (&dst)[RT]) {
+  auto load_a = [&](__amdgpu_buffer_rsrc_t ar, int t, raw_t (&dst)[RT]) {
 #pragma unroll
     for (int i = 0; i < RT; ++i) dst[i] = Frag<ES>::load(ar, voa[i], t * 32 * ES);
   };
@@ -316,23 +327,35 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   double ss = 0.0;
-  const int nst = (int)((n + 31) / 32);        // 32-deep steps
+  // 32-deep steps per tile, rounded up to whole chunks (two steps each): a
+  // step past n multiplies zeros (its A fragments are zeroed below, its X
+  // columns are zero in LDS), so the register set of global step gs is gs & 1
+  // and the LDS buffer of global chunk gs >> 1 is its parity
+  const int nst = 2 * nch;
+  const int nsteps = nlt * nst;
   load_x(0);
-  load_a(0, ra[0]);
-  load_a(1 < nst ? 1 : 0, ra[1]);
+  load_a(tile_rsrc(0), 0, ra[0]);
+  load_a(tile_rsrc(0), 1, ra[1]);
   store_x(0, 0);
   __syncthreads();
-  // step t with register set ST = t & 1 (a compile-time index)
-  auto step = [&](int t, auto stc) {
+  // global step gs with register set ST = gs & 1 (a compile-time index)
+  auto step = [&](int gs, auto stc) {
     constexpr int st = decltype(stc)::value;
-    const int ch = t >> 1, buf = ch & 1;
+    const int lt = gs / nst, t = gs - lt * nst;
+    const int ch = t >> 1, buf = (gs >> 1) & 1;
+    const bool more_x = (gs >> 1) + 1 < nsteps / 2;   // a next chunk (maybe the next tile's)
+    const int nxt_ch = ch + 1 < nch ? ch + 1 : 0;
     u32x4 a[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) a[i] = Frag<ES>::bf(ra[st][i]);
-    const bool more_x = st == 0 && ch + 1 < nch;
-    if (more_x) load_x(ch + 1);
-    // refill this set with step t + 2 (the last prefetches are harmless repeats)
-    load_a(t + 2 < nst ? t + 2 : t, ra[st]);
+    if (st == 0 && more_x) load_x(nxt_ch);
+    // refill this set with global step gs + 2, which may open the next tile
+    // (the last prefetches are harmless repeats)
+    {
+      const int g2 = gs + 2 < nsteps ? gs + 2 : gs;
+      const int lt2 = g2 / nst;
+      load_a(tile_rsrc(lt2), g2 - lt2 * nst, ra[st]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     // a step that runs past n holds the next row's values there
     if (32 * t + 8 * g >= n) {
@@ -379,27 +402,32 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
         ss = fma((double)v2, s2l[buf][32 * st + 8 * g + e], ss);
       }
     }
-    if (st == 1 || t + 1 == nst) {
-      // end of chunk ch: the next chunk's X goes to the other buffer
-      if (ch + 1 < nch) store_x(buf ^ 1, ch + 1);
+    if (st == 1) {
+      // end of the chunk: the next one's X goes to the other buffer
+      if (more_x) store_x(buf ^ 1, nxt_ch);
       __syncthreads();
-    }
-  };
-  for (int t = 0; t < nst; t += 2) {
-    step(t, std::integral_constant<int, 0>());
-    if (t + 1 < nst) step(t + 1, std::integral_constant<int, 1>());
-  }
+      if (t == nst - 1) {
+        // end of the tile: its outputs, and fresh accumulators
+        const int64_t row0 = tile_row0(lt);
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int col = 16 * j + lr;
+          for (int j = 0; j < NT; ++j) {
+            const int col = 16 * j + lr;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + wave * 16 * RT + 16 * i + 4 * g + e;
-        if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+            for (int e = 0; e < 4; ++e) {
+              const int64_t row = row0 + wave * 16 * RT + 16 * i + 4 * g + e;
+              if (row < m && col < c) Y[row * ldy + col] = acc[i][j][e];
+            }
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
       }
     }
+  };
+  for (int gs = 0; gs < nsteps; gs += 2) {
+    step(gs, std::integral_constant<int, 0>());
+    step(gs + 1, std::integral_constant<int, 1>());
+  }
   if (do_ss) {
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if (lane == 0) red[wave] = ss;
@@ -609,6 +637,14 @@ bool bf16_pass_applies(const void* A, int es, int64_t n, int64_t lda, int c) {
          (reinterpret_cast<uintptr_t>(A) % (8 * es)) == 0 && (int64_t)512 * lda * es < (1LL << 31);
 }
 
+// resident workgroups per CU of a kernel (at least one)
+int lowp_blocks_per_cu(const void* fn, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
 template <int ES>
 hipError_t nt_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const __bf16* Xhi,
                    const __bf16* Xlo, int64_t ldx, int c, const float* scale, float* Y,
@@ -617,7 +653,9 @@ hipError_t nt_lowp(const void* A, int64_t m, int64_t n, int64_t lda, const __bf1
 #define RSVD_NT_BF16(NT)                                                                        \
   case NT: {                                                                                    \
     constexpr int bt = nt_bf16_threads<NT>(), br = nt_bf16_rows<NT>();                          \
-    const int64_t nblk = (m + br - 1) / br;                                                     \
+    static const int per_cu = lowp_blocks_per_cu((const void*)k_gemm_nt_bf16<NT, ES>, bt);     \
+    const int64_t ntl = (m + br - 1) / br;                                                      \
+    const int64_t nblk = ntl < kLowpCus * per_cu ? ntl : kLowpCus * per_cu;                     \
     if (nparts) *nparts = (int)nblk;                                                            \
     hipLaunchKernelGGL((k_gemm_nt_bf16<NT, ES>), dim3((unsigned)nblk), dim3(bt), 0, s, Ab, m,   \
                        n, lda, Xhi, Xlo, ldx, c, scale, Y, ldy, fro2_part);                     \

@@ -123,9 +123,9 @@ TRAFFIC = {
     "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
     "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),
     "pass_nn_bf16": (1.3614e+09, "lowp.hip", "k_gemm_nt_bf16", "702daeb6565ffc5e"),
-    "pass_tn_bf16": (1.4355e+09, "lowp.hip", "k_gemm_tn_bf16", "582c4bcb81bfa79d"),
+    "pass_tn_bf16": (1.4504e+09, "lowp.hip", "k_gemm_tn_bf16", "c7b96c5f42a457b8"),
     "pass_nn_fp8": (9.4270e+08, "lowp.hip", "k_gemm_nt_bf16", "702daeb6565ffc5e"),
-    "pass_tn_fp8": (9.1830e+08, "lowp.hip", "k_gemm_tn_bf16", "582c4bcb81bfa79d"),
+    "pass_tn_fp8": (9.2139e+08, "lowp.hip", "k_gemm_tn_bf16", "c7b96c5f42a457b8"),
 }
 TRAFFIC_SHAPE = (1_000_000, 512, 80)
 

@@ -462,6 +462,9 @@ __global__ __launch_bounds__(nt_bf16_threads<NT>()) void k_gemm_nt_bf16(
 // row of Q (ldq >= that).
 constexpr int kTR = 32;
 template <int NT> constexpr int tn_bf16_qs() { return NT > 8 ? 2 : 1; }
+// chunks in flight (register sets, and LDS buffers of Q): three where the
+// accumulators leave room for a third set within two waves per SIMD
+template <int NT, int QS> constexpr int tn_bf16_depth() { return (NT <= 6 || QS == 2) ? 3 : 2; }
 
 template <int NT, int ES, int QS>
 __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
@@ -471,7 +474,8 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   constexpr int TA = 64 * GW;                 // A columns per block
   constexpr int NTW = (NT + QS - 1) / QS;     // Q tiles per wave
   constexpr int QPW = (NT + 7) / 8;           // Q tiles staged per wave
-  __shared__ __attribute__((aligned(16))) u32x4 Bq[2][NT][2][64];   // [buf][j][hi/lo][lane]
+  constexpr int D = tn_bf16_depth<NT, QS>();
+  __shared__ __attribute__((aligned(16))) u32x4 Bq[D][NT][2][64];   // [buf][j][hi/lo][lane]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int o = lane & 7, h = (lane >> 3) & 1, g = lane >> 4;
   const int xcd = blockIdx.x & 7, rr = blockIdx.x >> 3;
@@ -511,10 +515,10 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     const int qc = 16 * jq + 8 * h < cpad - 8 ? 16 * jq + 8 * h : cpad - 8;
     voq[t] = (int)(((int64_t)(8 * g + o) * ldq + qc) * 4);
   }
-  // two register sets, chunk ch in set ch & 1, loaded two chunks ahead
+  // D register sets, chunk ch in set ch % D, loaded D chunks ahead
   typedef typename Frag<ES>::raw raw_t;
-  raw_t ra[2][4];
-  f32x4 rq[2][QPW][2];
+  raw_t ra[D][4];
+  f32x4 rq[D][QPW][2];
   auto load = [&](int ch, raw_t (&da)[4], f32x4 (&dq)[QPW][2]) {
     const int soa = ch * kTR * (int)lda * ES;
 #pragma unroll
@@ -551,21 +555,21 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  load(0, ra[0], rq[0]);
-  load(1 < nchunk ? 1 : 0, ra[1], rq[1]);
+#pragma unroll
+  for (int d = 0; d < D; ++d) load(d < nchunk ? d : 0, ra[d], rq[d]);
   store_q(0, rq[0]);
   __syncthreads();
-  // chunk ch with register set SET = ch & 1 (a compile-time index); its Q
-  // fragments are in LDS buffer ch & 1, the next chunk's go to the other
+  // chunk ch with register set SET = ch % D (a compile-time index); its Q
+  // fragments are in LDS buffer SET, the next chunk's go to the next buffer
   auto chunk = [&](int ch, auto setc) {
     constexpr int set = decltype(setc)::value;
-    constexpr int nxt = set ^ 1;
+    constexpr int nxt = (set + 1) % D;
     u32x4 a[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] = octet_transpose(Frag<ES>::bf(ra[set][i]), o);
-    // refill this set with chunk ch + 2 (the last prefetches are harmless repeats)
-    const int ch2 = ch + 2 < nchunk ? ch + 2 : ch;
-    load(ch2, ra[set], rq[set]);
+    // refill this set with chunk ch + D (the last prefetches are harmless repeats)
+    const int chd = ch + D < nchunk ? ch + D : ch;
+    load(chd, ra[set], rq[set]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int jj = 0; jj < NTW; ++jj) {
@@ -582,9 +586,11 @@ __global__ __launch_bounds__(512) void k_gemm_tn_bf16(
     if (ch + 1 < nchunk) store_q(nxt, rq[nxt]);
     __syncthreads();
   };
-  for (int ch = 0; ch < nchunk; ch += 2) {
+  for (int ch = 0; ch < nchunk; ch += D) {
     chunk(ch, std::integral_constant<int, 0>());
     if (ch + 1 < nchunk) chunk(ch + 1, std::integral_constant<int, 1>());
+    if constexpr (D > 2)
+      if (ch + 2 < nchunk) chunk(ch + 2, std::integral_constant<int, 2 % D>());
   }
   // acc[i][jj][e]: A column col0 + 16 i + 4 g + e, Q column 16 (j0 + jj) + (lane % 16)
   double* Pb = P + split * n * c;

@@ -99,6 +99,8 @@ TN_CASES = [
     (70, 16, 1),
     (1000, 96, 96),
     (33, 8, 9),            # one partial row chunk
+    (40000, 512, 80),      # 5 chunks per row split (prefetch sets past a whole round)
+    (30000, 136, 20),      # 4 chunks per split, a 136-column A in a 512-column tile
 ]
 
 

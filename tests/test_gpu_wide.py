@@ -211,7 +211,8 @@ def test_wide_lowp_gemm_nn_parity(lowp_plan, m, n, c):
 
 
 @pytest.mark.parametrize("m,n,c", [(1037, 1024, 160), (4099, 520, 144), (33, 64, 192),
-                                   (2000, 256, 176), (5000, 1032, 160)])
+                                   (2000, 256, 176), (5000, 1032, 160),
+                                   (26000, 1024, 160)])   # 13 chunks per row split
 def test_wide_lowp_gemm_tn_parity(lowp_plan, m, n, c):
     announce(f"{lowp_plan.storage} wide gemm_tn m={m} n={n} c={c}")
     rng = np.random.default_rng(3 * m + n + 7 * c)

@@ -118,7 +118,7 @@ KERNEL_INFO = {
 # again.
 TRAFFIC = {
     "eigensolver": (3.2840e+09, "eig.hip", "k_jacobi_eig", "3a89242cd902cc4b"),
-    "pass_nn": (2.3905e+09, "gemm.hip", "k_gemm_nt_tall", "b17a75a2a07e1bbd"),
+    "pass_nn": (2.3922e+09, "gemm.hip", "k_gemm_nt_tall", "a0cdaf64bd48123c"),
     "pass_tn": (2.4520e+09, "gemm.hip", "k_gemm_tn_tall", "8e9c23250fe70cc1"),
     "syrk": (3.6498e+09, "gemm.hip", "k_syrk_f32", "4d7743b804316718"),
     "nn_wide": (4.4520e+09, "gemm.hip", "nt_wide_body k_gemm_nt_wide", "4d3b0820e755a8d5"),

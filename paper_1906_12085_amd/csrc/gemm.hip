@@ -506,7 +506,10 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 //
 // Y = A Xt^T (Xt is c x n): block = 128 rows of A x all c columns, 4 waves of
 // 32 rows (2 x NT tiles); chunks of kTK = 32 along k of both operands staged
-// row-major in LDS (two buffers, small enough for two blocks per CU).  A
+// row-major in LDS (two buffers; at l <= 80 small enough for three blocks per
+// CU: rows unpadded, the 16-byte k-quad q of row r stored at quad q ^ (r % 8),
+// so the eight rows a read or write touches at one quad fall in distinct
+// banks).  A
 // chunk is a whole 128-byte segment of each row: with 16-k chunks each row's
 // cache line was consumed in two halves a chunk apart, and at n = 512 (rows
 // 2 KB apart) the half left for the next chunk was often evicted and fetched
@@ -515,8 +518,10 @@ __global__ void k_syrk_reduce(const double* __restrict__ P, int64_t nsplit, int 
 // FP64 sum of squares of A (Eq. sumeigen) taken from the loaded chunk.
 // Requires n % 4 == 0 and 16-byte rows (the descriptor ends at the last
 // valid row; a last chunk that ends past n is zeroed there on its way to LDS).
-constexpr int kTM = 128, kTK = 32, kTLD = kTK + 4;
+constexpr int kTM = 128, kTK = 32, kTLD = kTK;
 constexpr int kTQ = kTK / 4, kTUA = kTM * kTQ / 256;   // k-quads per row, A loads per thread
+// float offset of k-quad q of row r in an LDS chunk
+__device__ __forceinline__ int tq_off(int r, int q) { return r * kTLD + 4 * (q ^ (r & 7)); }
 
 // Work-list epilogue of the NT products (see GWork): a wave's FP32 output
 // tiles acc[i][J] (16 rows x 16 columns each, value e of lane l at row
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
 #pragma unroll
         for (int i = 0; i < 4; ++i) v[i] = 4 * (idx % kTQ) + i < kend ? v[i] : 0.f;
       }
-      *reinterpret_cast<f32x4*>(&As[buf][(idx / kTQ) * kTLD + 4 * (idx % kTQ)]) = v;
+      *reinterpret_cast<f32x4*>(&As[buf][tq_off(idx / kTQ, idx % kTQ)]) = v;
       if (do_ss) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ss = fma((double)v[i], (double)v[i], ss);
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
 #pragma unroll
           for (int i = 0; i < 4; ++i) v[i] = 4 * (idx % kTQ) + i < kend ? v[i] : 0.f;
         }
-        *reinterpret_cast<f32x4*>(&Bs[buf][(idx / kTQ) * kTLD + 4 * (idx % kTQ)]) = v;
+        *reinterpret_cast<f32x4*>(&Bs[buf][tq_off(idx / kTQ, idx % kTQ)]) = v;
       }
     }
   };
@@ -672,10 +677,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_tall(
     f32x4 af[RT], bf[NT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
-      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][(wave * 16 * RT + 16 * i + lr) * kTLD + 16 * s + 4 * g]);
+      af[i] = *reinterpret_cast<const f32x4*>(&As[buf][tq_off(wave * 16 * RT + 16 * i + lr, 4 * s + g)]);
 #pragma unroll
     for (int j = 0; j < NT; ++j)
-      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][(16 * j + lr) * kTLD + 16 * s + 4 * g]);
+      bf[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][tq_off(16 * j + lr, 4 * s + g)]);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll

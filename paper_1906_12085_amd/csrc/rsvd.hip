@@ -375,11 +375,13 @@ struct Path {
   }
 };
 
-// Orthonormalise an FP64 n x c matrix Zin: Zout = Q (explicit), R2s R1s = R.
-hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, double* Zout) {
+// Orthonormalise an FP64 n x c matrix Zin: Zout = Q (explicit), and with
+// keep_r R2s R1s = R (otherwise the factors are not stored).
+hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, double* Zout,
+                      bool keep_r = false) {
   Path<double> d(p);
-  hipError_t e = d.cqr2(Zin, n, c, c, p->Z1, c, p->R1s, p->R1invs, p->R2s, p->R2invs,
-                        (double*)p->RinvTs, 0);
+  hipError_t e = d.cqr2(Zin, n, c, c, p->Z1, c, keep_r ? p->R1s : nullptr, nullptr,
+                        keep_r ? p->R2s : nullptr, nullptr, (double*)p->RinvTs, 0);
   if (e != hipSuccess) return e;
   if (n <= kGramShortRows)   // a short panel: the one-thread-per-output product
     return launch_small_gemm<double>(p->Z1, (const double*)p->RinvTs, n, c, c, Zout, nullptr,
@@ -403,7 +405,7 @@ hipError_t cqr2_small(rsvd_plan_s* p, const double* Zin, int64_t n, int c, doubl
 hipError_t small_svd_unsorted(rsvd_plan_s* p, const double* Tm, int64_t r, int c,
                               bool all_columns = false) {
   hipError_t e;
-  if ((e = cqr2_small(p, Tm, r, c, p->Zq)) != hipSuccess) return e;
+  if ((e = cqr2_small(p, Tm, r, c, p->Zq, true)) != hipSuccess) return e;
   if ((e = launch_small_gemm<double>(p->R2s, p->R1s, c, c, c, p->Rt, nullptr, p->stream)) != hipSuccess)
     return e;
   if (c > kSmallSvdMaxC) {
@@ -487,7 +489,8 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
   int np = 0;
   RSVD_CHECK(pass_nn(omega, p->fro2_part, &np));
   RSVD_CHECK(launch_reduce_scalar(p->fro2_part, np, p->scal, s));
-  RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  // only R2^-1 (and R1^-1 through RinvT) of the CholeskyQR2 factors is used
+  RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, nullptr, nullptr, nullptr, p->R2inv, (T*)p->RinvT));
   auto pass_tn = [&](double* Z) -> hipError_t {
     if (lp) return P.tn_bf16(*lp, m, n, lda, reinterpret_cast<const float*>(Q1), lq, l, Z);
     return P.tn(A, m, n, lda, Q1, lq, l, Z);
@@ -498,7 +501,7 @@ int32_t rsvd_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda, 
     RSVD_CHECK(launch_small_gemm<T>(p->Zd, p->R2inv, n, l, l, p->Z2, nullptr, s));  // A^T Q
     RSVD_CHECK(cqr2_small(p, p->Z2, n, l, p->Zq));
     RSVD_CHECK(pass_nn(p->Zq, nullptr, nullptr));
-    RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+    RSVD_CHECK(P.cqr2(Y, m, l, l, Q1, lq, nullptr, nullptr, nullptr, p->R2inv, (T*)p->RinvT));
   }
   // step 5: T = A^T Q
   RSVD_CHECK(pass_tn(p->Zd));
@@ -581,15 +584,15 @@ int32_t krylov_run(rsvd_plan_s* p, const T* A, int64_t m, int64_t n, int64_t lda
     }
     T* Yj = H + (int64_t)j * l;
     const bool tb = P.times_rinv_tall(Q1, l, l, (const T*)p->RinvT);
-    RSVD_CHECK(P.cqr2(Yj, m, l, L, Q1, l, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT, tb));
+    RSVD_CHECK(P.cqr2(Yj, m, l, L, Q1, l, nullptr, nullptr, nullptr, p->R2inv, (T*)p->RinvT, tb));
     RSVD_CHECK(P.times_rinv(Q1, m, l, l, (const T*)p->RinvT, tb, Yj, L));   // Q(j) = Q1 R2^-1
   }
   // step 5: QR of the panel.  Its blocks overlap more as the Krylov space
   // converges (condition numbers of 1e4 .. 1e11 on decaying spectra), so a
   // shifted CholeskyQR pass (H -> Q1) precedes CholeskyQR2 (Q1 -> the panel's
   // own storage, no longer needed): Q = H R2^-1, kept implicit.
-  RSVD_CHECK(P.cqr_shifted(H, m, L, L, Q1, L, p->R1, p->R1inv, (T*)p->RinvT));
-  RSVD_CHECK(P.cqr2(Q1, m, L, L, H, L, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT));
+  RSVD_CHECK(P.cqr_shifted(H, m, L, L, Q1, L, nullptr, nullptr, (T*)p->RinvT));
+  RSVD_CHECK(P.cqr2(Q1, m, L, L, H, L, nullptr, nullptr, nullptr, p->R2inv, (T*)p->RinvT));
   Q1 = H;
   // step 6: T = A^T Q = (A^T Q1) R2^-1
   RSVD_CHECK(P.tn(A, m, n, lda, Q1, L, L, p->Zd));
@@ -783,7 +786,7 @@ struct Grow {
   hipError_t orth() {
     hipError_t e;
     const bool tb = P.times_rinv_tall(Wb, g.b, ldb, (const T*)p->RinvT);
-    if ((e = P.cqr2(Yb, g.m, g.b, ldb, Wb, ldb, p->R1, p->R1inv, p->R2, p->R2inv, (T*)p->RinvT,
+    if ((e = P.cqr2(Yb, g.m, g.b, ldb, Wb, ldb, nullptr, nullptr, nullptr, p->R2inv, (T*)p->RinvT,
                     tb)) != hipSuccess)
       return e;
     return P.times_rinv(Wb, g.m, g.b, ldb, (const T*)p->RinvT, tb, Yb, ldb);

@@ -166,7 +166,8 @@ hipError_t launch_cast_to_f64(const T* src, int64_t rows, int64_t cols, int64_t 
                               double* dst, int64_t ldd, hipStream_t s);
 
 // Cholesky of the symmetric c x c matrix W (ld = c, c <= chol_inv_max_c()):
-// R upper with W = R^T R, Rinv = R^-1 (upper), both ld = c.  Rinv also written, rounded, to RinvT
+// R upper with W = R^T R, Rinv = R^-1 (upper), both ld = c, each written
+// only when not null.  Rinv also written, rounded, to RinvT
 // (type T, ld = c) when RinvT != nullptr, transposed when trans != 0.
 // Non-positive pivot -> status word = RSVD_ERR_BREAKDOWN, R = 0 and
 // Rinv = identity (so later kernels stay finite).

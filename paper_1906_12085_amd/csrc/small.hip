@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
     for (int i = wave; i < c; i += kWaves)
       for (int j = lane; j < c; j += 64) {
         const double v1 = (i == j) ? 1.0 : 0.0;
-        Rg[i * c + j] = 0.0;
-        Rig[i * c + j] = v1;
+        if (R) Rg[i * c + j] = 0.0;
+        if (Rinv) Rig[i * c + j] = v1;
         if (RinvT) RTg[i * c + j] = (T)v1;
       }
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
   // from column i in LDS (stride ld odd: no bank conflicts); RinvT is R^-1
   // or, with trans, its transpose B.  Indices clamped into c x c as above;
   // four rows per batch: the LDS reads of a batch in flight together, then
-  // its coalesced stores.
+  // its coalesced stores.  A null R or Rinv is not written.
   constexpr int kBatch = 4;
   static_assert(kRows % kBatch == 0, "whole batches of rows");
 #pragma unroll
@@ -319,8 +319,8 @@ __global__ __launch_bounds__(kCiT) void k_chol_inv(const double* __restrict__ W,
 #pragma unroll
       for (int h = 0; h < kCols; ++h) {
         const int i = min(wave + kWaves * (u0 + u), c - 1), j = min(lane + 64 * h, c - 1);
-        Rg[i * c + j] = rv[u][h];
-        Rig[i * c + j] = xv[u][h];
+        if (R) Rg[i * c + j] = rv[u][h];
+        if (Rinv) Rig[i * c + j] = xv[u][h];
         if (RinvT) RTg[i * c + j] = (T)(trans ? bv[u][h] : xv[u][h]);
       }
   }
@@ -440,8 +440,8 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
     for (int idx = tid; idx < c * c; idx += kCwT) {
       const int i = idx / c, j = idx - i * c;
       const double v = (i == j) ? 1.0 : 0.0;
-      Rg[idx] = 0.0;
-      Rig[idx] = v;
+      if (R) Rg[idx] = 0.0;
+      if (Rinv) Rig[idx] = v;
       if (RinvT) RTg[idx] = (T)v;
     }
     if (tid == 0) set_error(status, RSVD_ERR_BREAKDOWN);
@@ -454,9 +454,9 @@ __global__ __launch_bounds__(kCwT) void k_chol_inv_wide(const double* __restrict
     for (int v = 0; v < U; ++v) {
       const int i = ti + 32 * u, k = tk + 32 * v;
       if (i < c && k < c) {
-        Rg[i * c + k] = k >= i ? a[u][v] : 0.0;
+        if (R) Rg[i * c + k] = k >= i ? a[u][v] : 0.0;
         const double x = k < i ? a[u][v] : (k == i ? rdiag[i] : 0.0);
-        Rig[k * c + i] = x;
+        if (Rinv) Rig[k * c + i] = x;
         if (RinvT) RTg[trans ? i * c + k : k * c + i] = (T)x;
       }
     }

@@ -708,6 +708,8 @@ __global__ __launch_bounds__(kJsMaxC / 2 * kJsG) void k_jacobi_svd_small(
 // cheap next to the scatter), a wave per column finds the sign, and the
 // scatter writes 16 consecutive outputs of a row together.
 constexpr int kSsCols = 16;
+constexpr int kSsReg = 8;     // rows per lane held in registers by the sign scan
+constexpr int kSsUnroll = 8;  // scatter rows per thread with their loads in flight
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_sign_scatter(
@@ -742,24 +744,61 @@ __global__ __launch_bounds__(256) void k_sort_sign_scatter(
     if (rank < c) perm[rank] = i;
   }
   __syncthreads();
-  // sign rule: the first entry within 0.999 of the largest magnitude is positive
-  for (int q = wave; q < ncol; q += 4) {
-    const int kk = kk0 + q;
-    int src = perm[kk];
-    if (src < 0 || src >= c) src = kk;
+  // sign rule: the first entry within 0.999 of the largest magnitude is positive.
+  // Wave w takes the block's columns w, w + 4, w + 8, w + 12; the first
+  // 64 kSsReg rows of all of them are read into registers at once (every
+  // load in flight together), rows past those (r > 64 kSsReg) in the loops
+  // after, and the sign of the chosen entry comes from the lane that holds it.
+  constexpr int kQ = kSsCols / 4;
+  double av[kQ][kSsReg];
+  int srcq[kQ];
+#pragma unroll
+  for (int jq = 0; jq < kQ; ++jq) {
+    const int q = wave + 4 * jq;
+    int src = q < ncol ? perm[kk0 + q] : 0;
+    if (src < 0 || src >= c) src = q < ncol ? kk0 + q : 0;
+    srcq[jq] = src;
+    const double* col = Vsrc + (int64_t)src * vcs;
+#pragma unroll
+    for (int t = 0; t < kSsReg; ++t) {
+      const int64_t i = lane + 64 * t;
+      av[jq][t] = (q < ncol && i < r) ? col[i * vrs] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int jq = 0; jq < kQ; ++jq) {
+    const int q = wave + 4 * jq;
+    if (q >= ncol) continue;                  // uniform per wave
+    const int kk = kk0 + q, src = srcq[jq];
+    const double* col = Vsrc + (int64_t)src * vcs;
     double vmax = 0.0;
-    for (int64_t i = lane; i < r; i += 64) vmax = fmax(vmax, fabs(Vsrc[i * vrs + src * vcs]));
+#pragma unroll
+    for (int t = 0; t < kSsReg; ++t) vmax = fmax(vmax, fabs(av[jq][t]));
+    for (int64_t i = lane + 64 * kSsReg; i < r; i += 64) vmax = fmax(vmax, fabs(col[i * vrs]));
     for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
     int64_t first = r;
-    for (int64_t i = lane; i < r; i += 64)
-      if (fabs(Vsrc[i * vrs + src * vcs]) >= 0.999 * vmax) { first = i; break; }
+#pragma unroll
+    for (int t = kSsReg - 1; t >= 0; --t) {
+      const int64_t i = lane + 64 * t;
+      if (i < r && fabs(av[jq][t]) >= 0.999 * vmax) first = i;
+    }
+    if (first == r)
+      for (int64_t i = lane + 64 * kSsReg; i < r; i += 64)
+        if (fabs(col[i * vrs]) >= 0.999 * vmax) { first = i; break; }
     for (int off = 32; off > 0; off >>= 1) {
       const int64_t o = __shfl_xor(first, off);
       first = o < first ? o : first;
     }
+    // the chosen entry (first is the same in every lane)
+    double fv = 0.0;
+#pragma unroll
+    for (int t = 0; t < kSsReg; ++t)
+      if (lane + 64 * t == first) fv = av[jq][t];
+    if (first < 64 * kSsReg) fv = __shfl(fv, (int)(first & 63));
+    else if (first < r) fv = col[first * vrs];
     if (lane == 0) {
       src_l[q] = src;
-      sg_l[q] = (first < r && Vsrc[first * vrs + src * vcs] < 0.0) ? -1.0 : 1.0;
+      sg_l[q] = (first < r && fv < 0.0) ? -1.0 : 1.0;
       S_out[kk] = Sl[src];
     }
   }
@@ -770,10 +809,23 @@ __global__ __launch_bounds__(256) void k_sort_sign_scatter(
     const int src = src_l[cj];
     const double sg = sg_l[cj];
     const int kk = kk0 + cj;
-    for (int64_t i = ri; i < r; i += 256 / kSsCols) {
-      const double v = sg * Vsrc[i * vrs + src * vcs];
-      if (Vout) Vout[i * ldv + kk] = (T)v;
-      if (Vd_out) Vd_out[i * kout + kk] = v;
+    const double* col = Vsrc + (int64_t)src * vcs;
+    constexpr int RS = 256 / kSsCols;           // rows between a thread's rows
+    for (int64_t i0 = ri; i0 < r; i0 += RS * kSsUnroll) {
+      double v[kSsUnroll];
+#pragma unroll
+      for (int u = 0; u < kSsUnroll; ++u) {
+        const int64_t i = i0 + RS * u;
+        v[u] = i < r ? sg * col[i * vrs] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kSsUnroll; ++u) {
+        const int64_t i = i0 + RS * u;
+        if (i < r) {
+          if (Vout) Vout[i * ldv + kk] = (T)v[u];
+          if (Vd_out) Vd_out[i * kout + kk] = v[u];
+        }
+      }
     }
     if (Wsrc && Wout)
       for (int i = ri; i < c; i += 256 / kSsCols) Wout[(int64_t)i * kout + kk] = sg * Wsrc[(int64_t)i * c + src];
